@@ -1,0 +1,207 @@
+/*
+ * mctrg.h - C ABI of the MI355X (gfx950) Monte Carlo TRG library.
+ *
+ * Problem (Huggins, Freeman, Stoudenmire, Tubman, Whaley, "Monte Carlo
+ * Tensor Network Renormalization", Sections II-III): the trace of a square
+ * tensor network is Z.  Each sample coarse-grains the network with TRG
+ * (Levin-Nave) where every SVD keeps a random subset of k singular values,
+ * drawn with probability p(e) proportional to the product of the squared
+ * kept values (Section II, w(e) and p(e)), and divides each kept value by
+ * its inclusion rate r(S_ii) (Section II), so that every truncated tensor
+ * averages to the exact one (Eqs. Tsum, Ssum) and the mean of the sample
+ * traces estimates Z without bias (Section III, Eqs. infiniteSum and
+ * infiniteEnsemble).  The error of the mean falls as 1/sqrt(samples)
+ * (Section V, Eq. shrunkDev).
+ *
+ * Conventions shared by every call
+ *   - Every function returns an int status: MCTRG_OK (0) or a negative
+ *     MCTRG_E* code.  No C++ exception crosses the ABI.
+ *   - Argument errors are detected before any work is enqueued; the call
+ *     then returns MCTRG_EINVAL and leaves every output untouched.
+ *   - "device" pointers are HIP device allocations (for example from
+ *     torch tensors on cuda:0); "host" pointers are ordinary host memory.
+ *     The caller owns every pointer it passes; the library owns its tensor
+ *     sets and their workspace.
+ *   - hip_stream is a hipStream_t (NULL = default stream).  Calls block
+ *     until their results are written unless a flag says otherwise.
+ *   - Tensors are FP64, row-major with legs ordered [l][u][r][d].
+ *   - Decompositions, sampling probabilities, inclusion rates and the
+ *     running log-normalisation are always FP64; only the large coarse-
+ *     graining GEMM takes the contraction dtype.
+ *   - A tensor set is not thread-safe; use one per host thread / stream.
+ */
+#ifndef MCTRG_H
+#define MCTRG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum mctrg_status {
+  MCTRG_OK = 0,
+  MCTRG_EINVAL = -1,       /* invalid argument; nothing was enqueued          */
+  MCTRG_ENOMEM = -2,       /* device workspace could not be allocated         */
+  MCTRG_EDEVICE = -3,      /* HIP runtime or kernel launch error              */
+  MCTRG_ENUMERIC = -4,     /* some samples failed numerically (see outputs)   */
+  MCTRG_EUNSUPPORTED = -5  /* valid but not implemented combination           */
+};
+
+/* Initial tensor constructions (all with legs l,u,r,d and bond dimension 2,
+ * leg index 0 <-> spin +1 where a leg carries a spin):
+ *   MCTRG_ISING_SITE      one tensor per spin of the square-lattice Ising
+ *                         model (Section IV, Eq. ising_model): every bond
+ *                         weight exp(beta s s') is split symmetrically into
+ *                         two half-bonds W = [[sqrt cosh b, sqrt sinh b],
+ *                         [sqrt cosh b, -sqrt sinh b]], and the field factor
+ *                         exp(beta h s) sits on the spin.  An L x L torus of
+ *                         these tensors traces to Z of the L x L Ising torus.
+ *   MCTRG_ISING_PLAQUETTE spins on the network bonds; every tensor holds the
+ *                         four interactions between cyclically adjacent leg
+ *                         spins (Section III, Fig. 1), field split in half.
+ *   MCTRG_USER            caller-provided tensors.                           */
+enum mctrg_model { MCTRG_ISING_SITE = 0, MCTRG_ISING_PLAQUETTE = 1, MCTRG_USER = 2 };
+
+/* Estimator forms:
+ *   MCTRG_SHARED       one random tensor per level per sample: every tensor
+ *                      of a level equals the same sampled tensor (a
+ *                      translation-invariant chain whose cost is logarithmic
+ *                      in the number of sites).  Biased for Z in general,
+ *                      because the paper requires independent samples per
+ *                      tensor (Section III, the paragraph after
+ *                      Eq. infiniteEnsemble); provided because it is the
+ *                      only form feasible on 2^20..2^30 sites.
+ *   MCTRG_INDEPENDENT  the paper's estimator: every tensor of every level on
+ *                      an L x L torus (L = 2^(n_steps/2)) gets its own
+ *                      independent truncation; unbiased.
+ *   MCTRG_TOPK         deterministic TRG keeping the k largest singular
+ *                      values (Section II, Eq. approxSVD), shared form.      */
+enum mctrg_mode { MCTRG_SHARED = 0, MCTRG_INDEPENDENT = 1, MCTRG_TOPK = 2 };
+
+/* dtype of the coarse-graining GEMM (FP32 accumulation for the narrow ones,
+ * with one power-of-two scale per operand tensor and sample). */
+enum mctrg_dtype { MCTRG_F64 = 0, MCTRG_F32 = 1, MCTRG_BF16 = 2, MCTRG_FP8_E4M3 = 3 };
+
+/* flags */
+#define MCTRG_RECORD 1u   /* write per-step selection records to record_buf   */
+#define MCTRG_ASYNC  2u   /* return without synchronising hip_stream          */
+
+typedef struct mctrg_tensor_set mctrg_tensor_set;  /* opaque, library-owned */
+
+/* Build the initial tensors of n_groups (beta, h) groups on the current HIP
+ * device.  beta, h: host arrays of n_groups values (beta >= 0).
+ * For MCTRG_USER, d_user is the bond dimension (2..4) and user_T a host
+ * array of n_groups * d_user^4 FP64 values (row-major [g][l][u][r][d]),
+ * copied; beta and h may then be NULL.  *out receives the new set.
+ * Errors: EINVAL (bad model, n_groups < 1, beta < 0 or non-finite, missing
+ * arrays), ENOMEM, EDEVICE. */
+int mctrg_init_tensor(int model, int32_t n_groups, const double* beta, const double* h,
+                      int32_t d_user, const double* user_T, mctrg_tensor_set** out);
+
+/* Number of groups and bond dimension of a set; 0 on success. */
+int mctrg_tensor_set_info(const mctrg_tensor_set* ts, int32_t* n_groups, int32_t* d0);
+
+typedef struct {
+  uint64_t seed;           /* Philox4x64-10 key word 0                               */
+  int64_t sample_offset;   /* global sample id of output i = sample_offset + i        */
+  int32_t n_steps;         /* N = 2^n_steps sites, 1..40; independent mode: even, <= 12 */
+  int32_t k;               /* kept count per decomposition, 1..64                     */
+  int32_t mode;            /* enum mctrg_mode                                         */
+  int32_t contract_dtype;  /* enum mctrg_dtype                                        */
+  double tau_null;         /* singular values <= tau_null * s_1 count as zero (1e-11) */
+  uint32_t flags;          /* MCTRG_RECORD | MCTRG_ASYNC                              */
+  int32_t* record_buf;     /* device, n_samples * n_steps * (4 + 2k) int32, or NULL:  */
+                           /*   per step: cA, cB (candidates), kA, kB (kept),        */
+                           /*   selA[k], selB[k] (kept indices into the descending    */
+                           /*   spectrum, -1 padded).  Shared and top-k modes only.   */
+  double* out_tensor;      /* device or NULL: final normalised tensor of every sample */
+                           /*   (shared/top-k), n_samples * Dc^4 with Dc the capacity */
+                           /*   bond dimension after n_steps (mctrg_capacity_dim)     */
+} mctrg_run_config;
+
+/* Fill *cfg with the defaults (seed 0, offset 0, tau_null 1e-11, F64, shared). */
+void mctrg_default_config(mctrg_run_config* cfg);
+
+/* Bond dimension of the stored tensors after n_steps steps at kept count k,
+ * starting from bond dimension d0: D_0 = d0, D_{s+1} = min(k, D_s^2).
+ * Kept counts below the capacity are zero-padded. */
+int32_t mctrg_capacity_dim(int32_t d0, int32_t k, int32_t n_steps);
+
+/* Run n_samples independent Monte Carlo samples (Section III).
+ *   group_of_sample: host, n_samples group indices, or NULL (all group 0)
+ *   k_of_sample:     host, n_samples kept counts, or NULL (all cfg->k);
+ *                    samples are bucketed by k internally
+ *   out_sign:        device int8, n_samples: sign of Z~ (0 = failed sample)
+ *   out_ln_abs_Z:    device FP64, n_samples: ln|Z~| (NaN for failed)
+ *   out_ln_c:        device FP64 or NULL, n_samples * n_steps: per-step
+ *                    ln of the normalisation (shared: max|T'| of the one
+ *                    tensor; independent: sum over the level's tensors)
+ * Per-sample results depend only on (seed, global sample id, group, k,
+ * n_steps, mode, dtype, tau_null) - not on batch size or order.
+ * Returns ENUMERIC if any sample failed (its sign is 0); other samples are
+ * valid.  Errors: EINVAL, ENOMEM, EDEVICE, EUNSUPPORTED. */
+int mctrg_run_samples(mctrg_tensor_set* ts, const mctrg_run_config* cfg, int64_t n_samples,
+                      const int32_t* group_of_sample, const int32_t* k_of_sample,
+                      int8_t* out_sign, double* out_ln_abs_Z, double* out_ln_c,
+                      void* hip_stream);
+
+typedef struct {
+  double ln_meanZ_per_site;  /* ln(mean of signed Z~) / n_sites (NaN if mean <= 0)   */
+  double rel_stderr_Z;       /* stderr of the mean of Z~ over |mean|                 */
+  double mean_lnZ_per_site;  /* mean of ln|Z~| / n_sites                             */
+  double stderr_mean_lnZ;    /* its standard error                                   */
+  int64_t n_used, n_negative, n_failed;
+} mctrg_estimate;
+
+/* Monte Carlo estimate from per-sample results (Section III
+ * Eq. infiniteEnsemble; error bars per Section V Eq. shrunkDev), computed on
+ * the device with a signed log-sum-exp.  sign, ln_abs_Z: device arrays of
+ * n_samples (samples with sign 0 or non-finite ln are excluded and
+ * counted as failed).  *out is written on the host.  Blocks on hip_stream. */
+int mctrg_estimate_lnZ(int64_t n_samples, const int8_t* sign, const double* ln_abs_Z,
+                       double n_sites, mctrg_estimate* out, void* hip_stream);
+
+void mctrg_destroy(mctrg_tensor_set* ts);
+const char* mctrg_status_string(int status);
+
+/* ---- Step-level entry points (the individual steps of one TRG step) ---- */
+
+/* Decomposition step (Section II, Eq. exactSVD): FP64 SVD of n_mats square
+ * n x n matrices (device, row-major, n_mats * n * n), n = d1 * d2 with the
+ * column index j = i1 * d2 + i2.  sigma_out: device, n_mats * n, descending.
+ * V_out: device or NULL, n_mats * n * n, row i = i-th right singular vector,
+ * signed so that sum_j V[i][j] / (1 + i1 + phi*i2) > 0 (phi = golden ratio).
+ * sweeps_out: device or NULL, n_mats int32 Jacobi sweeps used (-1 = no
+ * convergence).  Blocks on hip_stream. */
+int mctrg_svd_batched(int64_t n_mats, int32_t d1, int32_t d2, const double* M,
+                      double* sigma_out, double* V_out, int32_t* sweeps_out, void* hip_stream);
+
+/* Sampling and reweighting step (Section II): for each of n_jobs descending
+ * spectra sigma (device, n_jobs * n) choose the kept subset: mode
+ * MCTRG_TOPK keeps the first min(k, c); otherwise a subset drawn from
+ * p(e) ~ prod s^2 when c > k (c = #{s > tau_null * s_1}), else all c.
+ * rng: device, n_jobs * 3 uint64 (sample id, position id, step) naming the
+ * Philox counters; split: device int32 per job (0 = A, 1 = B).
+ * Outputs (device): kept[n_jobs], cand[n_jobs], sel[n_jobs*k] (ascending
+ * indices, -1 padded), log_r[n_jobs*k] (ln inclusion rate), weight
+ * [n_jobs*k] (sqrt(s/r)).  Blocks on hip_stream. */
+int mctrg_sample_batched(int64_t n_jobs, int32_t n, int32_t k, int32_t mode, uint64_t seed,
+                         double tau_null, const double* sigma, const uint64_t* rng,
+                         const int32_t* split, int32_t* kept, int32_t* cand, int32_t* sel,
+                         double* log_r, double* weight, void* hip_stream);
+
+/* Contraction step (Section III, Levin-Nave TRG): for each job,
+ *   T'[a,b,c,e] = sum_{p,q,s,t} GA[a,p,t] GB[b,q,p] FA[s,q,c] FB[t,s,e]
+ * with GA, GB: kk x D x D, FA, FB: D x D x kk (device, FP64, per job
+ * contiguous).  T_out: device FP64, n_jobs * kk^4.  dtype selects the
+ * precision of the kk^2 x kk^2 x D^2 GEMM.  Blocks on hip_stream. */
+int mctrg_contract_batched(int64_t n_jobs, int32_t D, int32_t kk, int32_t dtype,
+                           const double* GA, const double* GB, const double* FA,
+                           const double* FB, double* T_out, void* hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MCTRG_H */

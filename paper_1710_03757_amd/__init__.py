@@ -1,0 +1,305 @@
+"""Python binding of the MI355X Monte Carlo TRG library (libmctrg.so).
+
+Argument marshalling only: every step of the method runs in the HIP
+kernels behind the C ABI declared in include/mctrg.h.  PyTorch supplies
+device buffers (``tensor.data_ptr()``) and the current HIP stream.  There
+is no CPU fallback: importing this package without the built library, or
+calling it without a GPU, raises.
+
+Functions keep the C names without the ``mctrg_`` prefix:
+  init_tensor, run_samples, estimate_lnZ, capacity_dim, default_config,
+  svd_batched, sample_batched, contract_batched.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmctrg.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1710_03757_amd.build` "
+                      "(the HIP library is the only implementation; there is no fallback)")
+_lib = ctypes.CDLL(LIB_PATH)
+
+# ---- constants (include/mctrg.h) ------------------------------------------------
+OK, EINVAL, ENOMEM, EDEVICE, ENUMERIC, EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+ISING_SITE, ISING_PLAQUETTE, USER = 0, 1, 2
+SHARED, INDEPENDENT, TOPK = 0, 1, 2
+F64, F32, BF16, FP8_E4M3 = 0, 1, 2, 3
+RECORD, ASYNC = 1, 2
+
+MODES = {"shared": SHARED, "independent": INDEPENDENT, "topk": TOPK}
+DTYPES = {"f64": F64, "f32": F32, "bf16": BF16, "fp8": FP8_E4M3}
+MODELS = {"site": ISING_SITE, "vertex": ISING_SITE, "plaquette": ISING_PLAQUETTE, "user": USER}
+
+EXPORTED = ("mctrg_init_tensor", "mctrg_tensor_set_info", "mctrg_default_config", "mctrg_capacity_dim",
+            "mctrg_run_samples", "mctrg_estimate_lnZ", "mctrg_destroy", "mctrg_status_string",
+            "mctrg_svd_batched", "mctrg_sample_batched", "mctrg_contract_batched")
+
+
+class RunConfig(ctypes.Structure):
+    _fields_ = [("seed", ctypes.c_uint64), ("sample_offset", ctypes.c_int64), ("n_steps", ctypes.c_int32),
+                ("k", ctypes.c_int32), ("mode", ctypes.c_int32), ("contract_dtype", ctypes.c_int32),
+                ("tau_null", ctypes.c_double), ("flags", ctypes.c_uint32),
+                ("record_buf", ctypes.c_void_p), ("out_tensor", ctypes.c_void_p)]
+
+
+class Estimate(ctypes.Structure):
+    _fields_ = [("ln_meanZ_per_site", ctypes.c_double), ("rel_stderr_Z", ctypes.c_double),
+                ("mean_lnZ_per_site", ctypes.c_double), ("stderr_mean_lnZ", ctypes.c_double),
+                ("n_used", ctypes.c_int64), ("n_negative", ctypes.c_int64), ("n_failed", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+_vp, _i32, _i64, _u64, _f64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_double
+_lib.mctrg_init_tensor.argtypes = [ctypes.c_int, _i32, _vp, _vp, _i32, _vp, ctypes.POINTER(_vp)]
+_lib.mctrg_init_tensor.restype = ctypes.c_int
+_lib.mctrg_tensor_set_info.argtypes = [_vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32)]
+_lib.mctrg_default_config.argtypes = [ctypes.POINTER(RunConfig)]
+_lib.mctrg_default_config.restype = None
+_lib.mctrg_capacity_dim.argtypes = [_i32, _i32, _i32]
+_lib.mctrg_capacity_dim.restype = _i32
+_lib.mctrg_run_samples.argtypes = [_vp, ctypes.POINTER(RunConfig), _i64, _vp, _vp, _vp, _vp, _vp, _vp]
+_lib.mctrg_run_samples.restype = ctypes.c_int
+_lib.mctrg_estimate_lnZ.argtypes = [_i64, _vp, _vp, _f64, ctypes.POINTER(Estimate), _vp]
+_lib.mctrg_estimate_lnZ.restype = ctypes.c_int
+_lib.mctrg_destroy.argtypes = [_vp]
+_lib.mctrg_destroy.restype = None
+_lib.mctrg_status_string.argtypes = [ctypes.c_int]
+_lib.mctrg_status_string.restype = ctypes.c_char_p
+_lib.mctrg_svd_batched.argtypes = [_i64, _i32, _i32, _vp, _vp, _vp, _vp, _vp]
+_lib.mctrg_svd_batched.restype = ctypes.c_int
+_lib.mctrg_sample_batched.argtypes = [_i64, _i32, _i32, _i32, _u64, _f64, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+                                      _vp, _vp]
+_lib.mctrg_sample_batched.restype = ctypes.c_int
+_lib.mctrg_contract_batched.argtypes = [_i64, _i32, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp]
+_lib.mctrg_contract_batched.restype = ctypes.c_int
+
+
+class MctrgError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__(f"{where}: {status_string(status)} ({status})")
+
+
+def status_string(status: int) -> str:
+    return _lib.mctrg_status_string(status).decode()
+
+
+def _check(status: int, where: str, allow=(OK,)):
+    if status not in allow:
+        raise MctrgError(status, where)
+    return status
+
+
+def library():
+    """The loaded ctypes library (for ABI checks)."""
+    return _lib
+
+
+# ---- torch helpers ------------------------------------------------------------------
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("paper_1710_03757_amd needs a ROCm GPU (cuda:0); none is visible")
+    return torch
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream(torch):
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev(torch, t, dtype, name):
+    if not (t.is_cuda and t.dtype == dtype and t.is_contiguous()):
+        raise ValueError(f"{name} must be a contiguous {dtype} tensor on the GPU")
+    return t
+
+
+# ---- API ------------------------------------------------------------------------------
+class TensorSet:
+    """Owner of the library's initial tensors (mctrg_tensor_set)."""
+
+    def __init__(self, handle: int, n_groups: int, d0: int):
+        self._h = ctypes.c_void_p(handle)
+        self.n_groups = n_groups
+        self.d0 = d0
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if self._h and self._h.value:
+            _lib.mctrg_destroy(self._h)
+            self._h = ctypes.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def init_tensor(model="site", betas: Sequence[float] = (), hs: Optional[Sequence[float]] = None,
+                user_T=None) -> TensorSet:
+    import numpy as np
+    _torch()
+    m = MODELS[model] if isinstance(model, str) else int(model)
+    out = ctypes.c_void_p()
+    if m == USER:
+        arr = np.ascontiguousarray(user_T, dtype=np.float64)
+        if arr.ndim == 4:
+            arr = arr[None]
+        n_groups, d = arr.shape[0], arr.shape[1]
+        st = _lib.mctrg_init_tensor(m, n_groups, None, None, d, arr.ctypes.data_as(ctypes.c_void_p),
+                                    ctypes.byref(out))
+    else:
+        b = np.ascontiguousarray(betas, dtype=np.float64).reshape(-1)
+        h = np.zeros_like(b) if hs is None else np.ascontiguousarray(hs, dtype=np.float64).reshape(-1)
+        if h.size != b.size:
+            raise ValueError("betas and hs must have the same length")
+        n_groups = b.size
+        st = _lib.mctrg_init_tensor(m, n_groups, b.ctypes.data_as(ctypes.c_void_p),
+                                    h.ctypes.data_as(ctypes.c_void_p), 0, None, ctypes.byref(out))
+    _check(st, "mctrg_init_tensor")
+    ng, d0 = _i32(), _i32()
+    _check(_lib.mctrg_tensor_set_info(out, ctypes.byref(ng), ctypes.byref(d0)), "mctrg_tensor_set_info")
+    return TensorSet(out.value, ng.value, d0.value)
+
+
+def default_config() -> RunConfig:
+    cfg = RunConfig()
+    _lib.mctrg_default_config(ctypes.byref(cfg))
+    return cfg
+
+
+def capacity_dim(d0: int, k: int, n_steps: int) -> int:
+    return int(_lib.mctrg_capacity_dim(d0, k, n_steps))
+
+
+@dataclass
+class SampleResult:
+    sign: "object"           # torch int8, device
+    ln_abs_Z: "object"       # torch float64, device
+    ln_c: "object"           # torch float64 (n_samples, n_steps) or None
+    status: int
+    record: "object" = None
+    tensor: "object" = None
+
+
+def run_samples(ts: TensorSet, n_samples: int, *, n_steps: int, k: int, mode="shared", dtype="f64",
+                seed: int = 0, sample_offset: int = 0, tau_null: float = 1e-11, groups=None,
+                ks=None, want_ln_c: bool = False, record: bool = False, want_tensor: bool = False,
+                async_: bool = False, out_sign=None, out_ln_abs_Z=None) -> SampleResult:
+    """mctrg_run_samples.  ``groups`` / ``ks``: host sequences (one per sample)."""
+    import numpy as np
+    torch = _torch()
+    cfg = default_config()
+    cfg.seed = seed
+    cfg.sample_offset = sample_offset
+    cfg.n_steps = n_steps
+    cfg.k = k
+    cfg.mode = MODES[mode] if isinstance(mode, str) else int(mode)
+    cfg.contract_dtype = DTYPES[dtype] if isinstance(dtype, str) else int(dtype)
+    cfg.tau_null = tau_null
+    dev = torch.device("cuda", torch.cuda.current_device())
+    sign = out_sign if out_sign is not None else torch.empty(n_samples, dtype=torch.int8, device=dev)
+    ln = out_ln_abs_Z if out_ln_abs_Z is not None else torch.empty(n_samples, dtype=torch.float64, device=dev)
+    _dev(torch, sign, torch.int8, "out_sign")
+    _dev(torch, ln, torch.float64, "out_ln_abs_Z")
+    lnc = torch.empty((n_samples, n_steps), dtype=torch.float64, device=dev) if want_ln_c else None
+    rec = None
+    if record:
+        rec = torch.full((n_samples, n_steps, 4 + 2 * k), -7, dtype=torch.int32, device=dev)
+        cfg.flags |= RECORD
+        cfg.record_buf = rec.data_ptr()
+    ten = None
+    if want_tensor:
+        Dc = capacity_dim(ts.d0, k, n_steps)
+        ten = torch.empty((n_samples, Dc, Dc, Dc, Dc), dtype=torch.float64, device=dev)
+        cfg.out_tensor = ten.data_ptr()
+    if async_:
+        cfg.flags |= ASYNC
+    g = None if groups is None else np.ascontiguousarray(groups, dtype=np.int32)
+    kk = None if ks is None else np.ascontiguousarray(ks, dtype=np.int32)
+    for arr, nm in ((g, "groups"), (kk, "ks")):
+        if arr is not None and arr.size != n_samples:
+            raise ValueError(f"{nm} must have one entry per sample")
+    st = _lib.mctrg_run_samples(ts.handle, ctypes.byref(cfg), n_samples,
+                                None if g is None else g.ctypes.data_as(ctypes.c_void_p),
+                                None if kk is None else kk.ctypes.data_as(ctypes.c_void_p),
+                                _ptr(sign), _ptr(ln), _ptr(lnc), _stream(torch))
+    _check(st, "mctrg_run_samples", allow=(OK, ENUMERIC))
+    return SampleResult(sign, ln, lnc, st, rec, ten)
+
+
+def estimate_lnZ(sign, ln_abs_Z, n_sites: float) -> dict:
+    torch = _torch()
+    _dev(torch, sign, torch.int8, "sign")
+    _dev(torch, ln_abs_Z, torch.float64, "ln_abs_Z")
+    est = Estimate()
+    _check(_lib.mctrg_estimate_lnZ(sign.numel(), _ptr(sign), _ptr(ln_abs_Z), float(n_sites), ctypes.byref(est),
+                                   _stream(torch)), "mctrg_estimate_lnZ")
+    return est.as_dict()
+
+
+def svd_batched(M, d1: int, d2: int, want_V: bool = True):
+    """mctrg_svd_batched on a (n_mats, n, n) float64 device tensor.
+    Returns (sigma, V or None, sweeps)."""
+    torch = _torch()
+    _dev(torch, M, torch.float64, "M")
+    nm, n = M.shape[0], d1 * d2
+    if tuple(M.shape[1:]) != (n, n):
+        raise ValueError("M must be (n_mats, d1*d2, d1*d2)")
+    sig = torch.empty((nm, n), dtype=torch.float64, device=M.device)
+    V = torch.empty((nm, n, n), dtype=torch.float64, device=M.device) if want_V else None
+    sw = torch.empty(nm, dtype=torch.int32, device=M.device)
+    _check(_lib.mctrg_svd_batched(nm, d1, d2, _ptr(M), _ptr(sig), _ptr(V), _ptr(sw), _stream(torch)),
+           "mctrg_svd_batched")
+    return sig, V, sw
+
+
+def sample_batched(sigma, rng, split, k: int, mode="shared", seed: int = 0, tau_null: float = 1e-11):
+    """mctrg_sample_batched.  sigma (n_jobs, n) float64, rng (n_jobs, 3)
+    int64 (sample id, position id, step), split (n_jobs,) int32 - all on the
+    device.  Returns dict of kept, cand, sel, log_r, weight."""
+    torch = _torch()
+    _dev(torch, sigma, torch.float64, "sigma")
+    _dev(torch, rng, torch.int64, "rng")
+    _dev(torch, split, torch.int32, "split")
+    nj, n = sigma.shape
+    d = sigma.device
+    kept = torch.empty(nj, dtype=torch.int32, device=d)
+    cand = torch.empty(nj, dtype=torch.int32, device=d)
+    sel = torch.empty((nj, k), dtype=torch.int32, device=d)
+    lr = torch.empty((nj, k), dtype=torch.float64, device=d)
+    w = torch.empty((nj, k), dtype=torch.float64, device=d)
+    m = MODES[mode] if isinstance(mode, str) else int(mode)
+    _check(_lib.mctrg_sample_batched(nj, n, k, m, seed, tau_null, _ptr(sigma), _ptr(rng), _ptr(split),
+                                     _ptr(kept), _ptr(cand), _ptr(sel), _ptr(lr), _ptr(w), _stream(torch)),
+           "mctrg_sample_batched")
+    return {"kept": kept, "cand": cand, "sel": sel, "log_r": lr, "weight": w}
+
+
+def contract_batched(GA, GB, FA, FB, dtype="f64"):
+    """mctrg_contract_batched: GA, GB (n, kk, D, D); FA, FB (n, D, D, kk)
+    float64 device tensors -> T' (n, kk, kk, kk, kk) float64."""
+    torch = _torch()
+    for t, nm in ((GA, "GA"), (GB, "GB"), (FA, "FA"), (FB, "FB")):
+        _dev(torch, t, torch.float64, nm)
+    nj, kk, D = GA.shape[0], GA.shape[1], GA.shape[2]
+    out = torch.empty((nj, kk, kk, kk, kk), dtype=torch.float64, device=GA.device)
+    dt = DTYPES[dtype] if isinstance(dtype, str) else int(dtype)
+    _check(_lib.mctrg_contract_batched(nj, D, kk, dt, _ptr(GA), _ptr(GB), _ptr(FA), _ptr(FB), _ptr(out),
+                                       _stream(torch)), "mctrg_contract_batched")
+    return out

@@ -1,0 +1,772 @@
+// Host runtime and C ABI of the MI355X Monte Carlo TRG library.
+//
+// run_samples buckets samples by kept count k, splits every bucket into
+// waves that fit the device memory, and runs each wave as a chain: the
+// starting tensors are gathered per sample, n_steps TRG steps are applied
+// (unfold -> Jacobi SVD -> sample/reweight -> factors -> contraction ->
+// normalisation), and the last tensor is traced (paper Section III).
+// In independent mode the batch is (sample x lattice position) and the
+// contraction gathers its four halves from the plaquette's four positions.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/mctrg.h"
+#include "mctrg_internal.h"
+
+using namespace mctrg;
+
+struct mctrg_tensor_set {
+  int ngroups;
+  int d0;
+  int device;
+  double* T0;   // device, ngroups * d0^4
+};
+
+namespace {
+
+constexpr int kMaxSweeps = 60;
+
+// ---------------------------------------------------------------------------
+// Independent-mode lattice (TRG geometry on a torus).
+// Legs (l,u,r,d) = 0..3; leg r of a site joins leg l of its right neighbour,
+// leg d joins leg u of the site below.  One new tensor per A site p0, from
+// G_A(p0), G_B(q0 = r of p0), F_A(p1 = d of q0), F_B(q1 = d of p0); its new
+// l' leg joins r' of the tensor of (l of (u of p0)) and its u' leg joins d'
+// of the tensor of (u of (r of p0)).  New ids are ranks of the A-site ids;
+// new sublattices come from a 2-colouring started at position 0.
+// ---------------------------------------------------------------------------
+struct Level {
+  int n = 0;
+  std::vector<int> nbr;     // 4 per position
+  std::vector<char> is_a;
+};
+
+Level square_torus(int L) {
+  Level v;
+  v.n = L * L;
+  v.nbr.resize(4 * v.n);
+  v.is_a.resize(v.n);
+  for (int y = 0; y < L; ++y)
+    for (int x = 0; x < L; ++x) {
+      const int i = x + L * y;
+      v.nbr[4 * i + 0] = (x + L - 1) % L + L * y;
+      v.nbr[4 * i + 1] = x + L * ((y + L - 1) % L);
+      v.nbr[4 * i + 2] = (x + 1) % L + L * y;
+      v.nbr[4 * i + 3] = x + L * ((y + 1) % L);
+      v.is_a[i] = ((x + y) % 2) == 0;
+    }
+  return v;
+}
+
+bool coarsen(const Level& lev, std::vector<int>& plaq, Level& nxt) {
+  std::vector<int> newid(lev.n, -1);
+  int m = 0;
+  for (int p = 0; p < lev.n; ++p)
+    if (lev.is_a[p]) newid[p] = m++;
+  plaq.assign(4 * m, 0);
+  nxt.n = m;
+  nxt.nbr.assign(4 * m, -1);
+  nxt.is_a.assign(m, 0);
+  auto nb = [&](int p, int d) { return lev.nbr[4 * p + d]; };
+  for (int p0 = 0; p0 < lev.n; ++p0) {
+    if (!lev.is_a[p0]) continue;
+    const int P = newid[p0];
+    const int q0 = nb(p0, 2), p1 = nb(q0, 3), q1 = nb(p0, 3);
+    if (nb(q1, 2) != p1 || lev.is_a[q0] || lev.is_a[q1] || !lev.is_a[p1]) return false;
+    plaq[4 * P + 0] = p0; plaq[4 * P + 1] = q0; plaq[4 * P + 2] = p1; plaq[4 * P + 3] = q1;
+  }
+  for (int p0 = 0; p0 < lev.n; ++p0) {
+    if (!lev.is_a[p0]) continue;
+    const int P = newid[p0];
+    const int Ql = newid[nb(nb(p0, 1), 0)], Qu = newid[nb(nb(p0, 2), 1)];
+    if (Ql < 0 || Qu < 0) return false;
+    if (nxt.nbr[4 * P + 0] >= 0 || nxt.nbr[4 * Ql + 2] >= 0) return false;
+    nxt.nbr[4 * P + 0] = Ql; nxt.nbr[4 * Ql + 2] = P;
+    if (nxt.nbr[4 * P + 1] >= 0 || nxt.nbr[4 * Qu + 3] >= 0) return false;
+    nxt.nbr[4 * P + 1] = Qu; nxt.nbr[4 * Qu + 3] = P;
+  }
+  for (int v : nxt.nbr)
+    if (v < 0) return false;
+  // 2-colouring
+  std::vector<int> col(m, -1), queue;
+  col[0] = 0;
+  queue.push_back(0);
+  for (size_t h = 0; h < queue.size(); ++h) {
+    const int p = queue[h];
+    for (int d = 0; d < 4; ++d) {
+      const int q = nxt.nbr[4 * p + d];
+      if (col[q] < 0) { col[q] = 1 - col[p]; queue.push_back(q); }
+      else if (m > 1 && col[q] == col[p]) return false;
+    }
+  }
+  for (int p = 0; p < m; ++p) {
+    if (col[p] < 0) return false;
+    nxt.is_a[p] = col[p] == 0;
+  }
+  return true;
+}
+
+// ---------------------------------------------------------------------------
+// Device arena: one allocation carved into 256-byte aligned pieces.
+// ---------------------------------------------------------------------------
+struct Arena {
+  char* base = nullptr;
+  size_t cap = 0, off = 0;
+  bool counting = true;
+  template <typename T>
+  T* take(size_t count) {
+    const size_t bytes = ((count * sizeof(T) + 255) / 256) * 256 + 256;
+    T* p = counting ? nullptr : reinterpret_cast<T*>(base + off);
+    off += bytes;
+    return p;
+  }
+};
+
+struct HostPinned {
+  void* p = nullptr;
+  ~HostPinned() { if (p) (void)hipHostFree(p); }
+};
+
+int32_t capacity_next(int32_t D, int32_t k) {
+  const int64_t sq = (int64_t)D * D;
+  return (int32_t)std::min<int64_t>(k, sq);
+}
+
+struct StepShape {
+  int D, kc, n, n_pad, P, jps, ops;
+};
+
+struct Chain {
+  hipStream_t st = nullptr;
+  int mode = 0, dtype = 0, k = 0, n_steps = 0, kmax_rec = 0;
+  double tau = 1e-11;
+  uint64_t seed = 0;
+  int64_t nsamp = 0;
+  int step = 0;
+  uint32_t flags = 0;
+  int32_t* record = nullptr;
+  std::vector<int> Dsched;
+  std::vector<Level> levels;
+  std::vector<std::vector<int>> plaqs;
+  std::vector<int64_t> sids;
+  // device
+  char* mem = nullptr;
+  double *Ta = nullptr, *Tb = nullptr, *Tn = nullptr, *W = nullptr, *sigma = nullptr, *logr = nullptr,
+         *weight = nullptr, *sscr = nullptr, *G = nullptr, *F = nullptr, *X = nullptr, *Y = nullptr,
+         *scales = nullptr, *cbuf = nullptr, *lnc = nullptr, *lnc_steps = nullptr, *lnabs = nullptr;
+  void *Xlp = nullptr, *Ylp = nullptr;
+  int32_t *order = nullptr, *kept = nullptr, *cand = nullptr, *sel = nullptr, *src = nullptr, *split = nullptr,
+          *cjobs = nullptr;
+  uint64_t* rng = nullptr;
+  int64_t* idx = nullptr;
+  int* failed = nullptr;
+  int8_t* sign = nullptr;
+  JacobiWork jw{};
+  // host staging (pinned)
+  HostPinned pin;
+  int32_t *h_src = nullptr, *h_split = nullptr, *h_cjobs = nullptr;
+  uint64_t* h_rng = nullptr;
+  int64_t max_jobs = 0, max_out = 0;
+
+  ~Chain() {
+    if (mem) (void)hipFree(mem);
+  }
+
+  StepShape shape(int s) const {
+    StepShape sh;
+    sh.D = Dsched[s];
+    sh.kc = Dsched[s + 1];
+    sh.n = sh.D * sh.D;
+    sh.n_pad = std::max(32, round_up32(sh.n));
+    if (mode == MCTRG_INDEPENDENT) {
+      sh.P = levels[s].n;
+      sh.jps = sh.P;
+      sh.ops = sh.P / 2;
+    } else {
+      sh.P = 1;
+      sh.jps = 2;
+      sh.ops = 1;
+    }
+    return sh;
+  }
+
+  double* Tcur() { return Ta; }
+};
+
+// Lays out (or, when counting, sizes) every device buffer of a chain.
+void layout(Chain& c, Arena& ar) {
+  size_t tmax = 0, wmax = 0, nmax = 0, selmax = 0, sscr = 0, gmax = 0, xmax = 0, tnmax = 0;
+  int64_t jmax = 0, omax = 0;
+  for (int s = 0; s < c.n_steps; ++s) {
+    const StepShape sh = c.shape(s);
+    const int64_t nj = c.nsamp * sh.jps, no = c.nsamp * sh.ops;
+    const size_t D4 = (size_t)sh.D * sh.D * sh.D * sh.D, K4 = (size_t)sh.kc * sh.kc * sh.kc * sh.kc;
+    tmax = std::max(tmax, (size_t)c.nsamp * sh.P * D4);
+    tmax = std::max(tmax, (size_t)no * K4);
+    wmax = std::max(wmax, (size_t)nj * sh.n_pad * sh.n_pad);
+    nmax = std::max(nmax, (size_t)nj * sh.n);
+    selmax = std::max(selmax, (size_t)nj * sh.kc);
+    sscr = std::max(sscr, sample_scratch_doubles(nj, sh.n, sh.kc));
+    gmax = std::max(gmax, (size_t)nj * sh.kc * sh.n);
+    xmax = std::max(xmax, (size_t)no * sh.kc * sh.kc * sh.n);
+    tnmax = std::max(tnmax, (size_t)no * K4);
+    jmax = std::max(jmax, nj);
+    omax = std::max(omax, no);
+  }
+  c.max_jobs = jmax;
+  c.max_out = omax;
+  c.Ta = ar.take<double>(tmax);
+  c.Tb = ar.take<double>(tmax);
+  c.Tn = ar.take<double>(tnmax);
+  c.W = ar.take<double>(wmax);
+  c.sigma = ar.take<double>(nmax);
+  c.order = ar.take<int32_t>(nmax);
+  c.kept = ar.take<int32_t>(jmax);
+  c.cand = ar.take<int32_t>(jmax);
+  c.sel = ar.take<int32_t>(selmax);
+  c.logr = ar.take<double>(selmax);
+  c.weight = ar.take<double>(selmax);
+  c.sscr = ar.take<double>(sscr);
+  c.G = ar.take<double>(gmax);
+  c.F = ar.take<double>(gmax);
+  c.X = ar.take<double>(xmax);
+  c.Y = ar.take<double>(xmax);
+  if (c.dtype != MCTRG_F64) {
+    c.Xlp = ar.take<float>(xmax);
+    c.Ylp = ar.take<float>(xmax);
+  }
+  c.scales = ar.take<double>(2 * omax);
+  c.cbuf = ar.take<double>(omax);
+  c.lnc = ar.take<double>(omax);
+  c.src = ar.take<int32_t>(jmax);
+  c.split = ar.take<int32_t>(jmax);
+  c.rng = ar.take<uint64_t>(3 * jmax);
+  c.cjobs = ar.take<int32_t>(4 * omax);
+  c.idx = ar.take<int64_t>(c.nsamp);
+  c.lnc_steps = ar.take<double>((size_t)c.nsamp * c.n_steps);
+  c.failed = ar.take<int>(c.nsamp);
+  c.sign = ar.take<int8_t>(c.nsamp);
+  c.lnabs = ar.take<double>(c.nsamp);
+  c.jw.active = ar.take<int>(jmax);
+  c.jw.rotated = ar.take<int>(jmax);
+  c.jw.sweeps = ar.take<int>(jmax);
+  c.jw.counter = ar.take<int>(1);
+}
+
+std::vector<int> schedule(int d0, int k, int n_steps) {
+  std::vector<int> D(n_steps + 1);
+  D[0] = d0;
+  for (int s = 0; s < n_steps; ++s) D[s + 1] = capacity_next(D[s], k);
+  return D;
+}
+
+int build_levels(Chain& c) {
+  const int L = 1 << (c.n_steps / 2);
+  Level lev = square_torus(L);
+  for (int s = 0; s < c.n_steps; ++s) {
+    std::vector<int> plaq;
+    Level nxt;
+    if (!coarsen(lev, plaq, nxt)) return MCTRG_EINVAL;
+    c.levels.push_back(lev);
+    c.plaqs.push_back(plaq);
+    lev = nxt;
+  }
+  if (lev.n != 1) return MCTRG_EINVAL;
+  return MCTRG_OK;
+}
+
+size_t chain_bytes(Chain& c) {
+  Arena ar;
+  layout(c, ar);
+  return ar.off;
+}
+
+#define CKH(x)                                  \
+  do {                                          \
+    hipError_t e_ = (x);                        \
+    if (e_ != hipSuccess) return MCTRG_EDEVICE; \
+  } while (0)
+
+// Allocates the chain's memory and gathers its starting tensors.
+int chain_start(Chain& c, const mctrg_tensor_set* ts, const std::vector<int32_t>& groups,
+                const std::vector<int64_t>& out_index) {
+  Arena ar;
+  layout(c, ar);
+  const size_t bytes = ar.off;
+  if (hipMalloc(&c.mem, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    c.mem = nullptr;
+    return MCTRG_ENOMEM;
+  }
+  ar.base = c.mem;
+  ar.off = 0;
+  ar.counting = false;
+  layout(c, ar);
+  const int64_t J = c.max_jobs, O = c.max_out;
+  const size_t hb = sizeof(int32_t) * (2 * J + 4 * O) + sizeof(uint64_t) * 3 * J + sizeof(int) + 64;
+  if (hipHostMalloc(&c.pin.p, hb, hipHostMallocDefault) != hipSuccess) return MCTRG_ENOMEM;
+  char* hp = reinterpret_cast<char*>(c.pin.p);
+  c.h_rng = reinterpret_cast<uint64_t*>(hp);
+  hp += sizeof(uint64_t) * 3 * J;
+  c.h_src = reinterpret_cast<int32_t*>(hp);
+  hp += sizeof(int32_t) * J;
+  c.h_split = reinterpret_cast<int32_t*>(hp);
+  hp += sizeof(int32_t) * J;
+  c.h_cjobs = reinterpret_cast<int32_t*>(hp);
+  hp += sizeof(int32_t) * 4 * O;
+  c.jw.counter_host = reinterpret_cast<int*>(hp);
+
+  // groups -> device (staged through the cjobs area, int32 per sample)
+  int32_t* dgroups = c.cjobs;  // reused before the first step
+  std::vector<int32_t> g = groups;
+  if ((int64_t)g.size() > 4 * O) return MCTRG_EINVAL;
+  CKH(hipMemcpyAsync(dgroups, g.data(), g.size() * sizeof(int32_t), hipMemcpyHostToDevice, c.st));
+  CKH(hipMemcpyAsync(c.idx, out_index.data(), out_index.size() * sizeof(int64_t), hipMemcpyHostToDevice, c.st));
+  // every position of a sample starts from the sample's group tensor
+  const int P0 = (c.mode == MCTRG_INDEPENDENT) ? c.levels[0].n : 1;
+  if (P0 == 1) {
+    CKH(launch_gather_tensors(c.nsamp, ts->d0, ts->T0, dgroups, c.Ta, c.st));
+  } else {
+    // expand groups to (sample, position)
+    std::vector<int32_t> gp((size_t)c.nsamp * P0);
+    for (int64_t s = 0; s < c.nsamp; ++s)
+      for (int p = 0; p < P0; ++p) gp[(size_t)s * P0 + p] = groups[s];
+    int32_t* dg2 = c.src;   // J >= nsamp * P0 at step 0
+    CKH(hipMemcpyAsync(dg2, gp.data(), gp.size() * sizeof(int32_t), hipMemcpyHostToDevice, c.st));
+    CKH(launch_gather_tensors(c.nsamp * P0, ts->d0, ts->T0, dg2, c.Ta, c.st));
+  }
+  CKH(launch_izero(c.nsamp, c.failed, c.st));
+  CKH(hipStreamSynchronize(c.st));
+  return MCTRG_OK;
+}
+
+int chain_step(Chain& c) {
+  const int s = c.step;
+  const StepShape sh = c.shape(s);
+  const int64_t nj = c.nsamp * sh.jps, no = c.nsamp * sh.ops;
+  // job descriptors
+  if (c.mode == MCTRG_INDEPENDENT) {
+    const Level& lev = c.levels[s];
+    const std::vector<int>& pl = c.plaqs[s];
+    for (int64_t i = 0; i < c.nsamp; ++i) {
+      for (int p = 0; p < sh.P; ++p) {
+        const int64_t j = i * sh.P + p;
+        c.h_src[j] = (int32_t)j;
+        c.h_split[j] = lev.is_a[p] ? 0 : 1;
+        c.h_rng[3 * j + 0] = (uint64_t)c.sids[i];
+        c.h_rng[3 * j + 1] = (uint64_t)p;
+        c.h_rng[3 * j + 2] = (uint64_t)s;
+      }
+      for (int P = 0; P < sh.ops; ++P) {
+        const int64_t o = i * sh.ops + P;
+        for (int t = 0; t < 4; ++t) c.h_cjobs[4 * o + t] = (int32_t)(i * sh.P + pl[4 * P + t]);
+      }
+    }
+  } else {
+    for (int64_t i = 0; i < c.nsamp; ++i) {
+      for (int sp = 0; sp < 2; ++sp) {
+        const int64_t j = 2 * i + sp;
+        c.h_src[j] = (int32_t)i;
+        c.h_split[j] = sp;
+        c.h_rng[3 * j + 0] = (uint64_t)c.sids[i];
+        c.h_rng[3 * j + 1] = 0;
+        c.h_rng[3 * j + 2] = (uint64_t)s;
+      }
+      c.h_cjobs[4 * i + 0] = (int32_t)(2 * i);
+      c.h_cjobs[4 * i + 1] = (int32_t)(2 * i + 1);
+      c.h_cjobs[4 * i + 2] = (int32_t)(2 * i);
+      c.h_cjobs[4 * i + 3] = (int32_t)(2 * i + 1);
+    }
+  }
+  CKH(hipMemcpyAsync(c.src, c.h_src, nj * sizeof(int32_t), hipMemcpyHostToDevice, c.st));
+  CKH(hipMemcpyAsync(c.split, c.h_split, nj * sizeof(int32_t), hipMemcpyHostToDevice, c.st));
+  CKH(hipMemcpyAsync(c.rng, c.h_rng, 3 * nj * sizeof(uint64_t), hipMemcpyHostToDevice, c.st));
+  CKH(hipMemcpyAsync(c.cjobs, c.h_cjobs, 4 * no * sizeof(int32_t), hipMemcpyHostToDevice, c.st));
+
+  CKH(launch_unfold(nj, sh.D, sh.n_pad, c.Ta, c.src, c.split, c.W, c.st));
+  CKH(run_jacobi(nj, sh.n_pad, c.W, c.jw, kMaxSweeps, c.st));
+  CKH(launch_jacobi_fail(nj, sh.jps, c.jw.sweeps, c.failed, c.st));
+  CKH(launch_jacobi_finalize(nj, sh.n, sh.n_pad, c.W, c.sigma, c.order, c.st));
+  SampleArgs sa{};
+  sa.njobs = nj; sa.n = sh.n; sa.k = sh.kc; sa.mode = c.mode; sa.seed = c.seed; sa.tau = c.tau;
+  sa.sigma = c.sigma; sa.rng = c.rng; sa.split = c.split; sa.kept = c.kept; sa.cand = c.cand;
+  sa.sel = c.sel; sa.log_r = c.logr; sa.weight = c.weight; sa.scratch = c.sscr;
+  CKH(launch_sample(sa, c.st));
+  if ((c.flags & MCTRG_RECORD) && c.record)
+    CKH(launch_record(c.nsamp, s, c.n_steps, c.kmax_rec, sh.kc, c.idx, c.cand, c.kept, c.sel, c.record, c.st));
+  CKH(launch_factor_G(nj, sh.D, sh.n_pad, sh.kc, c.W, c.sigma, c.order, c.kept, c.sel, c.weight, c.G, c.st));
+  CKH(launch_factor_F(nj, sh.D, sh.kc, c.Ta, c.src, c.split, c.sigma, c.kept, c.sel, c.G, c.F, c.st));
+  ContractArgs ca{};
+  ca.nout = no; ca.D = sh.D; ca.kk = sh.kc; ca.dtype = c.dtype;
+  ca.GA = c.G; ca.GB = c.G; ca.FA = c.F; ca.FB = c.F;
+  ca.g_stride = (int64_t)sh.kc * sh.n; ca.f_stride = (int64_t)sh.n * sh.kc;
+  ca.jobs = c.cjobs; ca.X = c.X; ca.Y = c.Y; ca.Xlp = c.Xlp; ca.Ylp = c.Ylp; ca.scales = c.scales; ca.Tout = c.Tn;
+  CKH(launch_contract(ca, c.st));
+  const int64_t K4 = (int64_t)sh.kc * sh.kc * sh.kc * sh.kc;
+  CKH(launch_normalize(no, K4, c.dtype != MCTRG_F64, c.Tn, c.scales, c.cbuf, c.Tb, c.lnc, c.st));
+  CKH(launch_lnc_accum(c.nsamp, sh.ops, s, c.n_steps, c.lnc, c.lnc_steps, c.failed, c.st));
+  std::swap(c.Ta, c.Tb);
+  c.step++;
+  return MCTRG_OK;
+}
+
+int chain_finish(Chain& c, int8_t* out_sign, double* out_ln, double* out_lnc, double* out_tensor) {
+  const int Df = c.Dsched[c.n_steps];
+  CKH(launch_trace(c.nsamp, Df, c.Ta, c.lnc_steps, c.n_steps, c.mode != MCTRG_INDEPENDENT, c.failed, c.sign,
+                   c.lnabs, c.st));
+  CKH(launch_scatter(c.nsamp, c.n_steps, c.idx, c.sign, c.lnabs, c.lnc_steps, out_sign, out_ln, out_lnc, c.st));
+  if (out_tensor) {
+    const size_t per = (size_t)Df * Df * Df * Df;
+    std::vector<int64_t> idx(c.nsamp);
+    CKH(hipMemcpyAsync(idx.data(), c.idx, c.nsamp * sizeof(int64_t), hipMemcpyDeviceToHost, c.st));
+    CKH(hipStreamSynchronize(c.st));
+    for (int64_t s = 0; s < c.nsamp; ++s)
+      CKH(hipMemcpyAsync(out_tensor + (size_t)idx[s] * per, c.Ta + (size_t)s * per, per * sizeof(double),
+                         hipMemcpyDeviceToDevice, c.st));
+  }
+  return MCTRG_OK;
+}
+
+bool is_fin(double x) { return std::isfinite(x); }
+
+int validate_config(const mctrg_run_config* cfg) {
+  if (!cfg) return MCTRG_EINVAL;
+  if (cfg->n_steps < 1 || cfg->n_steps > 40) return MCTRG_EINVAL;
+  if (cfg->k < 1 || cfg->k > 64) return MCTRG_EINVAL;
+  if (cfg->mode < MCTRG_SHARED || cfg->mode > MCTRG_TOPK) return MCTRG_EINVAL;
+  if (cfg->contract_dtype < MCTRG_F64 || cfg->contract_dtype > MCTRG_FP8_E4M3) return MCTRG_EINVAL;
+  if (!is_fin(cfg->tau_null) || cfg->tau_null < 0.0 || cfg->tau_null >= 1.0) return MCTRG_EINVAL;
+  if (cfg->sample_offset < 0) return MCTRG_EINVAL;
+  if (cfg->mode == MCTRG_INDEPENDENT) {
+    if ((cfg->n_steps % 2) != 0 || cfg->n_steps > 12) return MCTRG_EINVAL;
+  }
+  return MCTRG_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+const char* mctrg_status_string(int status) {
+  switch (status) {
+    case MCTRG_OK: return "ok";
+    case MCTRG_EINVAL: return "invalid argument";
+    case MCTRG_ENOMEM: return "out of device memory";
+    case MCTRG_EDEVICE: return "HIP device error";
+    case MCTRG_ENUMERIC: return "numerical failure in some samples";
+    case MCTRG_EUNSUPPORTED: return "unsupported combination";
+    default: return "unknown status";
+  }
+}
+
+void mctrg_default_config(mctrg_run_config* cfg) {
+  if (!cfg) return;
+  std::memset(cfg, 0, sizeof(*cfg));
+  cfg->n_steps = 8;
+  cfg->k = 8;
+  cfg->mode = MCTRG_SHARED;
+  cfg->contract_dtype = MCTRG_F64;
+  cfg->tau_null = 1e-11;
+}
+
+int32_t mctrg_capacity_dim(int32_t d0, int32_t k, int32_t n_steps) {
+  if (d0 < 1 || k < 1 || n_steps < 0) return -1;
+  int32_t D = d0;
+  for (int s = 0; s < n_steps; ++s) D = capacity_next(D, k);
+  return D;
+}
+
+int mctrg_init_tensor(int model, int32_t n_groups, const double* beta, const double* h, int32_t d_user,
+                      const double* user_T, mctrg_tensor_set** out) {
+  if (!out || n_groups < 1 || n_groups > (1 << 20)) return MCTRG_EINVAL;
+  if (model != MCTRG_ISING_SITE && model != MCTRG_ISING_PLAQUETTE && model != MCTRG_USER) return MCTRG_EINVAL;
+  int d0 = 2;
+  if (model == MCTRG_USER) {
+    if (!user_T || d_user < 2 || d_user > 4) return MCTRG_EINVAL;
+    d0 = d_user;
+    const size_t per = (size_t)d0 * d0 * d0 * d0;
+    for (size_t i = 0; i < per * n_groups; ++i)
+      if (!is_fin(user_T[i])) return MCTRG_EINVAL;
+  } else {
+    if (!beta || !h) return MCTRG_EINVAL;
+    for (int g = 0; g < n_groups; ++g)
+      if (!is_fin(beta[g]) || beta[g] < 0.0 || beta[g] > 50.0 || !is_fin(h[g]) || std::fabs(h[g]) > 50.0)
+        return MCTRG_EINVAL;
+  }
+  mctrg_tensor_set* ts = new (std::nothrow) mctrg_tensor_set();
+  if (!ts) return MCTRG_ENOMEM;
+  ts->ngroups = n_groups;
+  ts->d0 = d0;
+  if (hipGetDevice(&ts->device) != hipSuccess) { delete ts; return MCTRG_EDEVICE; }
+  const size_t per = (size_t)d0 * d0 * d0 * d0;
+  if (hipMalloc(&ts->T0, per * n_groups * sizeof(double)) != hipSuccess) {
+    (void)hipGetLastError();
+    delete ts;
+    return MCTRG_ENOMEM;
+  }
+  int rc = MCTRG_OK;
+  if (model == MCTRG_USER) {
+    if (hipMemcpy(ts->T0, user_T, per * n_groups * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
+      rc = MCTRG_EDEVICE;
+  } else {
+    double* dbh = nullptr;
+    if (hipMalloc(&dbh, 2 * n_groups * sizeof(double)) != hipSuccess) {
+      rc = MCTRG_ENOMEM;
+    } else {
+      if (hipMemcpy(dbh, beta, n_groups * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
+          hipMemcpy(dbh + n_groups, h, n_groups * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
+          launch_init_tensors(model, n_groups, dbh, dbh + n_groups, ts->T0, nullptr) != hipSuccess ||
+          hipDeviceSynchronize() != hipSuccess)
+        rc = MCTRG_EDEVICE;
+      (void)hipFree(dbh);
+    }
+  }
+  if (rc != MCTRG_OK) {
+    (void)hipFree(ts->T0);
+    delete ts;
+    return rc;
+  }
+  *out = ts;
+  return MCTRG_OK;
+}
+
+int mctrg_tensor_set_info(const mctrg_tensor_set* ts, int32_t* n_groups, int32_t* d0) {
+  if (!ts) return MCTRG_EINVAL;
+  if (n_groups) *n_groups = ts->ngroups;
+  if (d0) *d0 = ts->d0;
+  return MCTRG_OK;
+}
+
+void mctrg_destroy(mctrg_tensor_set* ts) {
+  if (!ts) return;
+  (void)hipFree(ts->T0);
+  delete ts;
+}
+
+int mctrg_run_samples(mctrg_tensor_set* ts, const mctrg_run_config* cfg, int64_t n_samples,
+                      const int32_t* group_of_sample, const int32_t* k_of_sample, int8_t* out_sign,
+                      double* out_ln_abs_Z, double* out_ln_c, void* hip_stream) {
+  if (!ts) return MCTRG_EINVAL;
+  int rc = validate_config(cfg);
+  if (rc != MCTRG_OK) return rc;
+  if (n_samples < 0 || n_samples > (int64_t)1 << 31) return MCTRG_EINVAL;
+  if (n_samples == 0) return MCTRG_OK;
+  if (!out_sign || !out_ln_abs_Z) return MCTRG_EINVAL;
+  if (group_of_sample)
+    for (int64_t i = 0; i < n_samples; ++i)
+      if (group_of_sample[i] < 0 || group_of_sample[i] >= ts->ngroups) return MCTRG_EINVAL;
+  if (k_of_sample)
+    for (int64_t i = 0; i < n_samples; ++i)
+      if (k_of_sample[i] < 1 || k_of_sample[i] > 64) return MCTRG_EINVAL;
+  const bool record = (cfg->flags & MCTRG_RECORD) != 0;
+  if (record) {
+    if (cfg->mode == MCTRG_INDEPENDENT) return MCTRG_EUNSUPPORTED;
+    if (!cfg->record_buf) return MCTRG_EINVAL;
+    if (k_of_sample)
+      for (int64_t i = 0; i < n_samples; ++i)
+        if (k_of_sample[i] > cfg->k) return MCTRG_EINVAL;
+  }
+  if (cfg->out_tensor) {
+    if (cfg->mode == MCTRG_INDEPENDENT) return MCTRG_EUNSUPPORTED;
+    if (k_of_sample)
+      for (int64_t i = 0; i < n_samples; ++i)
+        if (k_of_sample[i] != cfg->k) return MCTRG_EINVAL;
+  }
+  hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev != ts->device) return MCTRG_EINVAL;
+
+  // bucket samples by k
+  std::vector<int> ks;
+  if (k_of_sample) {
+    for (int64_t i = 0; i < n_samples; ++i) ks.push_back(k_of_sample[i]);
+    std::sort(ks.begin(), ks.end());
+    ks.erase(std::unique(ks.begin(), ks.end()), ks.end());
+  } else {
+    ks.push_back(cfg->k);
+  }
+  bool any_fail = false;
+  for (int kb : ks) {
+    std::vector<int64_t> members;
+    for (int64_t i = 0; i < n_samples; ++i)
+      if ((k_of_sample ? k_of_sample[i] : cfg->k) == kb) members.push_back(i);
+    // wave size from free device memory
+    Chain probe;
+    probe.mode = cfg->mode; probe.dtype = cfg->contract_dtype; probe.k = kb; probe.n_steps = cfg->n_steps;
+    probe.Dsched = schedule(ts->d0, kb, cfg->n_steps);
+    if (cfg->mode == MCTRG_INDEPENDENT && build_levels(probe) != MCTRG_OK) return MCTRG_EINVAL;
+    probe.nsamp = 1;
+    const size_t per1 = chain_bytes(probe);
+    probe.nsamp = 2;
+    const size_t per_sample = std::max<size_t>(1, chain_bytes(probe) - per1);
+    size_t freeb = 0, totalb = 0;
+    if (hipMemGetInfo(&freeb, &totalb) != hipSuccess) return MCTRG_EDEVICE;
+    const double budget = 0.70 * (double)freeb;
+    int64_t wave = (int64_t)std::max(1.0, std::floor((budget - (double)per1) / (double)per_sample) + 1);
+    if ((double)per1 > budget) return MCTRG_ENOMEM;
+    wave = std::min<int64_t>(wave, (int64_t)members.size());
+    for (size_t w0 = 0; w0 < members.size(); w0 += (size_t)wave) {
+      const size_t w1 = std::min(members.size(), w0 + (size_t)wave);
+      Chain c;
+      c.st = st; c.mode = cfg->mode; c.dtype = cfg->contract_dtype; c.k = kb; c.n_steps = cfg->n_steps;
+      c.tau = cfg->tau_null; c.seed = cfg->seed; c.flags = cfg->flags; c.record = cfg->record_buf;
+      c.kmax_rec = cfg->k;
+      c.Dsched = probe.Dsched;
+      c.levels = probe.levels;
+      c.plaqs = probe.plaqs;
+      c.nsamp = (int64_t)(w1 - w0);
+      std::vector<int32_t> groups(c.nsamp);
+      std::vector<int64_t> out_index(c.nsamp);
+      for (int64_t s = 0; s < c.nsamp; ++s) {
+        const int64_t i = members[w0 + s];
+        groups[s] = group_of_sample ? group_of_sample[i] : 0;
+        out_index[s] = i;
+        c.sids.push_back(cfg->sample_offset + i);
+      }
+      rc = chain_start(c, ts, groups, out_index);
+      if (rc != MCTRG_OK) return rc;
+      for (int s = 0; s < cfg->n_steps; ++s) {
+        rc = chain_step(c);
+        if (rc != MCTRG_OK) return rc;
+      }
+      rc = chain_finish(c, out_sign, out_ln_abs_Z, out_ln_c, cfg->out_tensor);
+      if (rc != MCTRG_OK) return rc;
+      if (hipStreamSynchronize(st) != hipSuccess) return MCTRG_EDEVICE;
+      std::vector<int8_t> sg(c.nsamp);
+      if (hipMemcpy(sg.data(), c.sign, c.nsamp, hipMemcpyDeviceToHost) != hipSuccess) return MCTRG_EDEVICE;
+      for (int8_t v : sg)
+        if (v == 0) any_fail = true;
+    }
+  }
+  return any_fail ? MCTRG_ENUMERIC : MCTRG_OK;
+}
+
+int mctrg_estimate_lnZ(int64_t n_samples, const int8_t* sign, const double* ln_abs_Z, double n_sites,
+                       mctrg_estimate* out, void* hip_stream) {
+  if (n_samples < 1 || !sign || !ln_abs_Z || !out || !(n_sites > 0.0) || !is_fin(n_sites)) return MCTRG_EINVAL;
+  hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+  double* d = nullptr;
+  if (hipMalloc(&d, 8 * sizeof(double)) != hipSuccess) return MCTRG_ENOMEM;
+  double h[8];
+  int rc = MCTRG_OK;
+  if (launch_estimate(n_samples, sign, ln_abs_Z, n_sites, d, st) != hipSuccess ||
+      hipMemcpyAsync(h, d, 8 * sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    rc = MCTRG_EDEVICE;
+  (void)hipFree(d);
+  if (rc != MCTRG_OK) return rc;
+  out->ln_meanZ_per_site = h[0];
+  out->rel_stderr_Z = h[1];
+  out->mean_lnZ_per_site = h[2];
+  out->stderr_mean_lnZ = h[3];
+  out->n_used = (int64_t)h[4];
+  out->n_negative = (int64_t)h[5];
+  out->n_failed = (int64_t)h[6];
+  return MCTRG_OK;
+}
+
+// ---- step-level entry points ----------------------------------------------
+
+int mctrg_svd_batched(int64_t n_mats, int32_t d1, int32_t d2, const double* M, double* sigma_out, double* V_out,
+                      int32_t* sweeps_out, void* hip_stream) {
+  if (n_mats < 0 || d1 < 1 || d2 < 1 || (int64_t)d1 * d2 > 4096 || !M || !sigma_out) return MCTRG_EINVAL;
+  if (n_mats == 0) return MCTRG_OK;
+  hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+  const int n = d1 * d2, n_pad = std::max(32, round_up32(n));
+  Arena ar;
+  double* W = ar.take<double>((size_t)n_mats * n_pad * n_pad);
+  int32_t* order = ar.take<int32_t>((size_t)n_mats * n);
+  int* jws = ar.take<int>(3 * n_mats + 1);
+  char* mem = nullptr;
+  if (hipMalloc(&mem, ar.off) != hipSuccess) { (void)hipGetLastError(); return MCTRG_ENOMEM; }
+  HostPinned pin;
+  if (hipHostMalloc(&pin.p, 64, hipHostMallocDefault) != hipSuccess) { (void)hipFree(mem); return MCTRG_ENOMEM; }
+  Arena a2;
+  a2.base = mem; a2.counting = false;
+  W = a2.take<double>((size_t)n_mats * n_pad * n_pad);
+  order = a2.take<int32_t>((size_t)n_mats * n);
+  jws = a2.take<int>(3 * n_mats + 1);
+  JacobiWork wk{jws, jws + n_mats, jws + 2 * n_mats, jws + 3 * n_mats, reinterpret_cast<int*>(pin.p)};
+  int rc = MCTRG_OK;
+  if (launch_pad_copy(n_mats, n, n_pad, M, W, st) != hipSuccess ||
+      run_jacobi(n_mats, n_pad, W, wk, kMaxSweeps, st) != hipSuccess ||
+      launch_jacobi_finalize(n_mats, n, n_pad, W, sigma_out, order, st) != hipSuccess)
+    rc = MCTRG_EDEVICE;
+  if (rc == MCTRG_OK && V_out && launch_extract_V(n_mats, n, n_pad, d2, W, sigma_out, order, V_out, st) != hipSuccess)
+    rc = MCTRG_EDEVICE;
+  if (rc == MCTRG_OK && sweeps_out &&
+      hipMemcpyAsync(sweeps_out, wk.sweeps, n_mats * sizeof(int32_t), hipMemcpyDeviceToDevice, st) != hipSuccess)
+    rc = MCTRG_EDEVICE;
+  if (hipStreamSynchronize(st) != hipSuccess) rc = MCTRG_EDEVICE;
+  (void)hipFree(mem);
+  return rc;
+}
+
+int mctrg_sample_batched(int64_t n_jobs, int32_t n, int32_t k, int32_t mode, uint64_t seed, double tau_null,
+                         const double* sigma, const uint64_t* rng, const int32_t* split, int32_t* kept,
+                         int32_t* cand, int32_t* sel, double* log_r, double* weight, void* hip_stream) {
+  if (n_jobs < 0 || n < 1 || n > 4096 || k < 1 || k > 64 || mode < 0 || mode > MCTRG_TOPK) return MCTRG_EINVAL;
+  if (!is_fin(tau_null) || tau_null < 0 || tau_null >= 1) return MCTRG_EINVAL;
+  if (n_jobs == 0) return MCTRG_OK;
+  if (!sigma || !rng || !split || !kept || !cand || !sel || !log_r || !weight) return MCTRG_EINVAL;
+  hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+  double* scr = nullptr;
+  if (hipMalloc(&scr, sample_scratch_doubles(n_jobs, n, k) * sizeof(double)) != hipSuccess) {
+    (void)hipGetLastError();
+    return MCTRG_ENOMEM;
+  }
+  SampleArgs sa{};
+  sa.njobs = n_jobs; sa.n = n; sa.k = k; sa.mode = mode; sa.seed = seed; sa.tau = tau_null; sa.sigma = sigma;
+  sa.rng = rng; sa.split = split; sa.kept = kept; sa.cand = cand; sa.sel = sel; sa.log_r = log_r;
+  sa.weight = weight; sa.scratch = scr;
+  int rc = MCTRG_OK;
+  if (launch_sample(sa, st) != hipSuccess || hipStreamSynchronize(st) != hipSuccess) rc = MCTRG_EDEVICE;
+  (void)hipFree(scr);
+  return rc;
+}
+
+int mctrg_contract_batched(int64_t n_jobs, int32_t D, int32_t kk, int32_t dtype, const double* GA,
+                           const double* GB, const double* FA, const double* FB, double* T_out, void* hip_stream) {
+  if (n_jobs < 0 || D < 1 || D > 64 || kk < 1 || kk > 64 || dtype < MCTRG_F64 || dtype > MCTRG_FP8_E4M3)
+    return MCTRG_EINVAL;
+  if (n_jobs == 0) return MCTRG_OK;
+  if (!GA || !GB || !FA || !FB || !T_out) return MCTRG_EINVAL;
+  hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+  const size_t xe = (size_t)n_jobs * kk * kk * D * D, te = (size_t)n_jobs * kk * kk * kk * kk;
+  Arena ar;
+  ar.take<double>(xe); ar.take<double>(xe); ar.take<float>(xe); ar.take<float>(xe);
+  ar.take<double>(2 * n_jobs); ar.take<double>(te); ar.take<int32_t>(4 * n_jobs);
+  char* mem = nullptr;
+  if (hipMalloc(&mem, ar.off) != hipSuccess) { (void)hipGetLastError(); return MCTRG_ENOMEM; }
+  Arena a2;
+  a2.base = mem; a2.counting = false;
+  ContractArgs ca{};
+  ca.X = a2.take<double>(xe); ca.Y = a2.take<double>(xe); ca.Xlp = a2.take<float>(xe); ca.Ylp = a2.take<float>(xe);
+  ca.scales = a2.take<double>(2 * n_jobs);
+  double* C = a2.take<double>(te);
+  int32_t* jobs = a2.take<int32_t>(4 * n_jobs);
+  std::vector<int32_t> hj(4 * n_jobs);
+  for (int64_t o = 0; o < n_jobs; ++o)
+    for (int t = 0; t < 4; ++t) hj[4 * o + t] = (int32_t)o;
+  ca.nout = n_jobs; ca.D = D; ca.kk = kk; ca.dtype = dtype;
+  ca.GA = GA; ca.GB = GB; ca.FA = FA; ca.FB = FB;
+  ca.g_stride = (int64_t)kk * D * D; ca.f_stride = (int64_t)D * D * kk;
+  ca.jobs = jobs; ca.Tout = C;
+  int rc = MCTRG_OK;
+  if (hipMemcpyAsync(jobs, hj.data(), hj.size() * sizeof(int32_t), hipMemcpyHostToDevice, st) != hipSuccess ||
+      launch_contract(ca, st) != hipSuccess ||
+      launch_unscale(n_jobs, (int64_t)kk * kk * kk * kk, dtype != MCTRG_F64, C, ca.scales, T_out, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    rc = MCTRG_EDEVICE;
+  (void)hipFree(mem);
+  return rc;
+}
+
+}  // extern "C"

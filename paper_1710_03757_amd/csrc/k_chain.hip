@@ -1,0 +1,129 @@
+// Per-chain bookkeeping kernels: selection records, per-sample sums of the
+// normalisation logs, failure flags and scatter of results to the caller's
+// sample order.
+#include "mctrg_internal.h"
+
+namespace mctrg {
+
+// record[(idx[s] * n_steps + step) * (4 + 2*kmax) + ...] = cA, cB, kA, kB, selA[kmax], selB[kmax]
+__global__ void record_kernel(int64_t nsamp, int step, int n_steps, int kmax, int kcap,
+                              const int64_t* __restrict__ idx, const int32_t* __restrict__ cand,
+                              const int32_t* __restrict__ kept, const int32_t* __restrict__ sel,
+                              int32_t* __restrict__ rec) {
+  const int64_t s = blockIdx.x;
+  const int stride = 4 + 2 * kmax;
+  int32_t* r = rec + ((size_t)idx[s] * n_steps + step) * stride;
+  const int64_t jA = 2 * s, jB = 2 * s + 1;
+  for (int t = threadIdx.x; t < stride; t += blockDim.x) {
+    int32_t v;
+    if (t == 0) v = cand[jA];
+    else if (t == 1) v = cand[jB];
+    else if (t == 2) v = kept[jA];
+    else if (t == 3) v = kept[jB];
+    else {
+      const int q = t - 4;
+      const int64_t j = q < kmax ? jA : jB;
+      const int a = q < kmax ? q : q - kmax;
+      v = a < kcap ? sel[j * kcap + a] : -1;
+    }
+    r[t] = v;
+  }
+}
+
+hipError_t launch_record(int64_t nsamp, int step, int n_steps, int kmax, int kcap, const int64_t* idx,
+                         const int32_t* cand, const int32_t* kept, const int32_t* sel, int32_t* rec,
+                         hipStream_t stream) {
+  if (nsamp == 0) return hipSuccess;
+  hipLaunchKernelGGL(record_kernel, dim3((unsigned)nsamp), dim3(64), 0, stream, nsamp, step, n_steps, kmax, kcap,
+                     idx, cand, kept, sel, rec);
+  return hipGetLastError();
+}
+
+// lnc_steps[s * n_steps + step] = sum over the sample's outputs (fixed order);
+// failed[s] |= any non-finite.
+__global__ void lnc_accum_kernel(int64_t nsamp, int out_per_sample, int step, int n_steps,
+                                 const double* __restrict__ lnc, double* __restrict__ lnc_steps,
+                                 int* __restrict__ failed) {
+  const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (s >= nsamp) return;
+  double acc = 0.0;
+  for (int P = 0; P < out_per_sample; ++P) acc += lnc[s * out_per_sample + P];
+  lnc_steps[s * n_steps + step] = acc;
+  if (!isfinite(acc)) failed[s] = 1;
+}
+
+hipError_t launch_lnc_accum(int64_t nsamp, int out_per_sample, int step, int n_steps, const double* lnc,
+                            double* lnc_steps, int* failed, hipStream_t stream) {
+  if (nsamp == 0) return hipSuccess;
+  hipLaunchKernelGGL(lnc_accum_kernel, dim3(ceil_div(nsamp, 128)), dim3(128), 0, stream, nsamp, out_per_sample,
+                     step, n_steps, lnc, lnc_steps, failed);
+  return hipGetLastError();
+}
+
+__global__ void jacobi_fail_kernel(int64_t njobs, int jobs_per_sample, const int* __restrict__ sweeps,
+                                   int* __restrict__ failed) {
+  const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (j < njobs && sweeps[j] < 0) failed[j / jobs_per_sample] = 1;
+}
+
+hipError_t launch_jacobi_fail(int64_t njobs, int jobs_per_sample, const int* sweeps, int* failed,
+                              hipStream_t stream) {
+  if (njobs == 0) return hipSuccess;
+  hipLaunchKernelGGL(jacobi_fail_kernel, dim3(ceil_div(njobs, 256)), dim3(256), 0, stream, njobs, jobs_per_sample,
+                     sweeps, failed);
+  return hipGetLastError();
+}
+
+__global__ void izero_kernel(int64_t n, int* p) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+
+hipError_t launch_izero(int64_t n, int* p, hipStream_t stream) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(izero_kernel, dim3(ceil_div(n, 256)), dim3(256), 0, stream, n, p);
+  return hipGetLastError();
+}
+
+__global__ void scatter_kernel(int64_t nsamp, int n_steps, const int64_t* __restrict__ idx,
+                               const int8_t* __restrict__ sign, const double* __restrict__ ln,
+                               const double* __restrict__ lnc_steps, int8_t* __restrict__ out_sign,
+                               double* __restrict__ out_ln, double* __restrict__ out_lnc) {
+  const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (s >= nsamp) return;
+  const int64_t d = idx[s];
+  out_sign[d] = sign[s];
+  out_ln[d] = ln[s];
+  if (out_lnc)
+    for (int t = 0; t < n_steps; ++t) out_lnc[d * n_steps + t] = lnc_steps[s * n_steps + t];
+}
+
+hipError_t launch_scatter(int64_t nsamp, int n_steps, const int64_t* idx, const int8_t* sign, const double* ln,
+                          const double* lnc_steps, int8_t* out_sign, double* out_ln, double* out_lnc,
+                          hipStream_t stream) {
+  if (nsamp == 0) return hipSuccess;
+  hipLaunchKernelGGL(scatter_kernel, dim3(ceil_div(nsamp, 128)), dim3(128), 0, stream, nsamp, n_steps, idx, sign,
+                     ln, lnc_steps, out_sign, out_ln, out_lnc);
+  return hipGetLastError();
+}
+
+// Square n x n matrices into zero-padded n_pad x n_pad workspaces.
+__global__ void pad_copy_kernel(int n, int n_pad, const double* __restrict__ M, double* __restrict__ W) {
+  const int64_t m = blockIdx.y;
+  const size_t per = (size_t)n_pad * n_pad;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < per; e += (size_t)gridDim.x * blockDim.x) {
+    const int r = (int)(e / n_pad), c = (int)(e % n_pad);
+    W[m * per + e] = (r < n && c < n) ? M[(size_t)m * n * n + (size_t)r * n + c] : 0.0;
+  }
+}
+
+hipError_t launch_pad_copy(int64_t nmats, int n, int n_pad, const double* M, double* W, hipStream_t stream) {
+  if (nmats == 0) return hipSuccess;
+  const size_t per = (size_t)n_pad * n_pad;
+  int gx = (int)((per + 255) / 256);
+  if (gx > 1024) gx = 1024;
+  hipLaunchKernelGGL(pad_copy_kernel, dim3(gx, (unsigned)nmats), dim3(256), 0, stream, n, n_pad, M, W);
+  return hipGetLastError();
+}
+
+}  // namespace mctrg

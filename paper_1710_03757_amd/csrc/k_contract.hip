@@ -1,0 +1,320 @@
+// Contraction step: the four factor halves around a plaquette form the
+// coarse tensor (Levin-Nave TRG, paper Section III):
+//   T'[a,b,c,e] = sum_{p,q,s,t} G_A[a,p,t] G_B[b,q,p] F_A[s,q,c] F_B[t,s,e].
+// It is evaluated as
+//   X[(a,b)][(t,q)]  = sum_p G_A[a,p,t] G_B[b,q,p]     (2 k^2 D^3 flops, FP64)
+//   Yt[(c,e)][(t,q)] = sum_s F_A[s,q,c] F_B[t,s,e]     (2 k^2 D^3 flops, FP64)
+//   T'[(a,b)][(c,e)] = sum_{(t,q)} X Yt^T              (2 k^4 D^2 flops, MFMA)
+// The last product dominates; it runs in the contraction dtype:
+//   F64  v_mfma_f64_16x16x4_f64, FP64 output
+//   F32  v_mfma_f32_16x16x4_f32
+//   BF16 v_mfma_f32_16x16x32_bf16, FP32 accumulation
+//   FP8  v_mfma_f32_16x16x32_fp8_fp8 (OCP e4m3), FP32 accumulation
+// Narrow operands are scaled per (tensor, operand) by a power of two so
+// that max|x| < 2^target (1 for BF16/F32, 256 for e4m3) before rounding;
+// the normalisation step divides the scales back out.
+#include "mctrg_internal.h"
+#include "../../include/mctrg.h"
+
+namespace mctrg {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+// ---------------------------------------------------------------------------
+// X and Yt (FP64).  One workgroup per (a or c, output tensor).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void contract_X_kernel(int D, int kk, int kcap, const double* __restrict__ GApool,
+                                                         const double* __restrict__ GBpool, int64_t g_stride,
+                                                         const int32_t* __restrict__ jobs, double* __restrict__ X) {
+  extern __shared__ double sh[];
+  const int a = blockIdx.x;
+  const int64_t o = blockIdx.y;
+  const int DD = D * D, ld = D + 1;
+  double* GAa = sh;               // [p][t]
+  double* GBb = sh + D * ld;      // [q][p]
+  const double* GA = GApool + (size_t)jobs[4 * o + 0] * g_stride + (size_t)a * DD;
+  const double* GBbase = GBpool + (size_t)jobs[4 * o + 1] * g_stride;
+  for (int e = threadIdx.x; e < DD; e += 256) GAa[(e / D) * ld + e % D] = GA[e];
+  double* Xo = X + (size_t)o * kk * kk * DD;
+  for (int b = 0; b < kk; ++b) {
+    __syncthreads();
+    const double* GB = GBbase + (size_t)b * DD;
+    for (int e = threadIdx.x; e < DD; e += 256) GBb[(e / D) * ld + e % D] = GB[e];
+    __syncthreads();
+    for (int e = threadIdx.x; e < DD; e += 256) {
+      const int t = e / D, q = e % D;
+      double s = 0.0;
+      for (int p = 0; p < D; ++p) s += GAa[p * ld + t] * GBb[q * ld + p];
+      Xo[((size_t)a * kk + b) * DD + e] = s;
+    }
+  }
+  (void)kcap;
+}
+
+__global__ __launch_bounds__(256) void contract_Y_kernel(int D, int kk, int kcap, const double* __restrict__ FApool,
+                                                         const double* __restrict__ FBpool, int64_t f_stride,
+                                                         const int32_t* __restrict__ jobs, double* __restrict__ Yt) {
+  extern __shared__ double sh[];
+  const int c = blockIdx.x;
+  const int64_t o = blockIdx.y;
+  const int DD = D * D, ld = D + 1;
+  double* FAc = sh;               // [s][q]
+  double* FBe = sh + D * ld;      // [t][s]
+  const double* FA = FApool + (size_t)jobs[4 * o + 2] * f_stride;
+  const double* FB = FBpool + (size_t)jobs[4 * o + 3] * f_stride;
+  for (int e = threadIdx.x; e < DD; e += 256) FAc[(e / D) * ld + e % D] = FA[(size_t)e * kcap + c];
+  double* Yo = Yt + (size_t)o * kk * kk * DD;
+  for (int ee = 0; ee < kk; ++ee) {
+    __syncthreads();
+    for (int e = threadIdx.x; e < DD; e += 256) FBe[(e / D) * ld + e % D] = FB[(size_t)e * kcap + ee];
+    __syncthreads();
+    for (int e = threadIdx.x; e < DD; e += 256) {
+      const int t = e / D, q = e % D;
+      double s = 0.0;
+      for (int ss = 0; ss < D; ++ss) s += FBe[t * ld + ss] * FAc[ss * ld + q];
+      Yo[((size_t)c * kk + ee) * DD + e] = s;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Per-(tensor, operand) power-of-two scales and narrow casts.
+// ---------------------------------------------------------------------------
+__global__ void absmax_kernel(int64_t per, const double* __restrict__ A, double* __restrict__ mx) {
+  const int64_t o = blockIdx.y;
+  const double* Ao = A + o * per;
+  double m = 0.0;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < per; e += (int64_t)gridDim.x * blockDim.x)
+    m = fmax(m, fabs(Ao[e]));
+  for (int s = 32; s > 0; s >>= 1) m = fmax(m, __shfl_xor(m, s));
+  if ((threadIdx.x & 63) == 0) atomic_max_nonneg(&mx[o], m);
+}
+
+__global__ void fill_kernel(int64_t n, double* p, double v) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+// scale = 2^(target - E) with max = f 2^E, f in [0.5, 1)  (1 if max == 0)
+__global__ void make_scale_kernel(int64_t n, double* mx_to_scale, int target) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double m = mx_to_scale[i];
+  double s = 1.0;
+  if (m > 0.0 && isfinite(m)) {
+    int E;
+    frexp(m, &E);
+    s = ldexp(1.0, target - E);
+  }
+  mx_to_scale[i] = s;
+}
+
+__device__ __forceinline__ unsigned short f32_to_bf16_rne(float x) {
+  unsigned int u = __float_as_uint(x);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (unsigned short)(u >> 16);
+}
+
+template <int DT>
+__global__ void cast_kernel(int64_t per, const double* __restrict__ A, const double* __restrict__ scale,
+                            void* __restrict__ out) {
+  const int64_t o = blockIdx.y;
+  const double s = scale[o];
+  const double* Ao = A + o * per;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < per; e += (int64_t)gridDim.x * blockDim.x) {
+    const float v = (float)(Ao[e] * s);
+    if (DT == MCTRG_F32) {
+      reinterpret_cast<float*>(out)[o * per + e] = v;
+    } else if (DT == MCTRG_BF16) {
+      reinterpret_cast<unsigned short*>(out)[o * per + e] = f32_to_bf16_rne(v);
+    } else {
+      int packed = __builtin_amdgcn_cvt_pk_fp8_f32(v, 0.0f, 0, false);
+      reinterpret_cast<unsigned char*>(out)[o * per + e] = (unsigned char)(packed & 0xFF);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Batched GEMM C[o] = A[o] (M x K, row-major) * B[o]^T (B: N x K, row-major).
+// 64 x 64 tile per workgroup, four waves of 32 x 32 (2 x 2 MFMA 16x16 tiles),
+// K staged through LDS in chunks of 32.
+// ---------------------------------------------------------------------------
+template <int DT> struct Mma;
+template <> struct Mma<MCTRG_F64> {
+  typedef double elt; typedef double acc_t; typedef f64x4 frag_c;
+  static constexpr int KSTEP = 4, PAD = 1;
+};
+template <> struct Mma<MCTRG_F32> {
+  typedef float elt; typedef float acc_t; typedef f32x4 frag_c;
+  static constexpr int KSTEP = 4, PAD = 1;
+};
+template <> struct Mma<MCTRG_BF16> {
+  typedef unsigned short elt; typedef float acc_t; typedef f32x4 frag_c;
+  static constexpr int KSTEP = 32, PAD = 8;
+};
+template <> struct Mma<MCTRG_FP8_E4M3> {
+  typedef unsigned char elt; typedef float acc_t; typedef f32x4 frag_c;
+  static constexpr int KSTEP = 32, PAD = 16;
+};
+
+template <int DT>
+__device__ __forceinline__ typename Mma<DT>::frag_c mma_step(const typename Mma<DT>::elt* a,
+                                                             const typename Mma<DT>::elt* b,
+                                                             typename Mma<DT>::frag_c c) {
+  if constexpr (DT == MCTRG_F64) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(*a, *b, c, 0, 0, 0);
+  } else if constexpr (DT == MCTRG_F32) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(*a, *b, c, 0, 0, 0);
+  } else if constexpr (DT == MCTRG_BF16) {
+    bf16x8 av = *reinterpret_cast<const bf16x8*>(a);
+    bf16x8 bv = *reinterpret_cast<const bf16x8*>(b);
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, c, 0, 0, 0);
+  } else {
+    long av = *reinterpret_cast<const long*>(a);
+    long bv = *reinterpret_cast<const long*>(b);
+    return __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(av, bv, c, 0, 0, 0);
+  }
+}
+
+template <int DT>
+__global__ __launch_bounds__(256) void gemm_tn_kernel(int M, int N, int K, const void* __restrict__ Av,
+                                                      const void* __restrict__ Bv, void* __restrict__ Cv) {
+  typedef typename Mma<DT>::elt elt;
+  typedef typename Mma<DT>::acc_t acc_t;
+  typedef typename Mma<DT>::frag_c frag_c;
+  constexpr int BK = 32, LD = BK + Mma<DT>::PAD, KS = Mma<DT>::KSTEP;
+  constexpr int EPL = (KS == 4) ? 1 : 8;    // elements per lane per MFMA
+  __shared__ __attribute__((aligned(16))) elt As[64 * LD];
+  __shared__ __attribute__((aligned(16))) elt Bs[64 * LD];
+  const int64_t o = blockIdx.z;
+  const elt* A = reinterpret_cast<const elt*>(Av) + (size_t)o * M * K;
+  const elt* B = reinterpret_cast<const elt*>(Bv) + (size_t)o * N * K;
+  acc_t* C = reinterpret_cast<acc_t*>(Cv) + (size_t)o * M * N;
+  const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  const int lr = lane & 15, lg = lane >> 4;
+  frag_c acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = frag_c{0, 0, 0, 0};
+
+  for (int k0 = 0; k0 < K; k0 += BK) {
+    for (int e = tid; e < 64 * BK; e += 256) {
+      const int r = e / BK, kx = e % BK;
+      const int gm = m0 + r, gn = n0 + r, gk = k0 + kx;
+      As[r * LD + kx] = (gm < M && gk < K) ? A[(size_t)gm * K + gk] : elt(0);
+      Bs[r * LD + kx] = (gn < N && gk < K) ? B[(size_t)gn * K + gk] : elt(0);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < BK; ks += KS) {
+      const int kofs = ks + lg * EPL;
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        const elt* ap = &As[(wm + 16 * i + lr) * LD + kofs];
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          const elt* bp = &Bs[(wn + 16 * j + lr) * LD + kofs];
+          acc[i][j] = mma_step<DT>(ap, bp, acc[i][j]);
+        }
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int gm = m0 + wm + 16 * i + 4 * lg + r, gn = n0 + wn + 16 * j + lr;
+        if (gm < M && gn < N) C[(size_t)gm * N + gn] = acc[i][j][r];
+      }
+}
+
+template <typename T>
+__global__ void unscale_kernel(int64_t elems, const T* __restrict__ C, const double* __restrict__ scales,
+                               int64_t nout, double* __restrict__ out) {
+  const int64_t o = blockIdx.y;
+  const double inv = 1.0 / (scales[o] * scales[nout + o]);
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < elems; e += (int64_t)gridDim.x * blockDim.x)
+    out[o * elems + e] = (double)C[o * elems + e] * inv;
+}
+
+hipError_t launch_unscale(int64_t nout, int64_t elems, int src_is_f32, const void* C, const double* scales,
+                          double* T_out, hipStream_t stream) {
+  if (nout == 0) return hipSuccess;
+  int gx = (int)((elems + 255) / 256);
+  if (gx > 256) gx = 256;
+  if (src_is_f32)
+    hipLaunchKernelGGL(unscale_kernel<float>, dim3(gx, (unsigned)nout), dim3(256), 0, stream, elems,
+                       (const float*)C, scales, nout, T_out);
+  else
+    hipLaunchKernelGGL(unscale_kernel<double>, dim3(gx, (unsigned)nout), dim3(256), 0, stream, elems,
+                       (const double*)C, scales, nout, T_out);
+  return hipGetLastError();
+}
+
+static size_t elt_bytes(int dt) {
+  return dt == MCTRG_F64 ? 8 : dt == MCTRG_F32 ? 4 : dt == MCTRG_BF16 ? 2 : 1;
+}
+
+hipError_t launch_contract(const ContractArgs& a, hipStream_t stream) {
+  if (a.nout == 0) return hipSuccess;
+  const int D = a.D, kk = a.kk, DD = D * D, MM = kk * kk;
+  const size_t sh = (size_t)2 * D * (D + 1) * sizeof(double);
+  const int kcap = kk;
+  hipLaunchKernelGGL(contract_X_kernel, dim3(kk, (unsigned)a.nout), dim3(256), sh, stream, D, kk, kcap, a.GA,
+                     a.GB, a.g_stride, a.jobs, a.X);
+  hipLaunchKernelGGL(contract_Y_kernel, dim3(kk, (unsigned)a.nout), dim3(256), sh, stream, D, kk, kcap, a.FA,
+                     a.FB, a.f_stride, a.jobs, a.Y);
+  const int64_t per = (int64_t)MM * DD;
+  dim3 gg(ceil_div(MM, 64), ceil_div(MM, 64), (unsigned)a.nout);
+  if (a.dtype == MCTRG_F64) {
+    hipLaunchKernelGGL(fill_kernel, dim3(ceil_div(2 * a.nout, 256)), dim3(256), 0, stream, 2 * a.nout, a.scales, 1.0);
+    hipLaunchKernelGGL(gemm_tn_kernel<MCTRG_F64>, gg, dim3(256), 0, stream, MM, MM, DD, (const void*)a.X,
+                       (const void*)a.Y, a.Tout);
+    return hipGetLastError();
+  }
+  // scales: [o*2 + 0] for X, [o*2 + 1] for Yt
+  const int target = (a.dtype == MCTRG_FP8_E4M3) ? 8 : 0;
+  hipLaunchKernelGGL(fill_kernel, dim3(ceil_div(2 * a.nout, 256)), dim3(256), 0, stream, 2 * a.nout, a.scales, 0.0);
+  int gx = (int)((per + 255) / 256);
+  if (gx > 256) gx = 256;
+  // absmax writes to scales[o] with a stride of one tensor: run per operand
+  // into a contiguous view (X -> even slots, Yt -> odd slots) via two passes.
+  double* mxX = a.scales;            // first nout entries
+  double* mxY = a.scales + a.nout;   // next nout entries
+  hipLaunchKernelGGL(absmax_kernel, dim3(gx, (unsigned)a.nout), dim3(256), 0, stream, per, a.X, mxX);
+  hipLaunchKernelGGL(absmax_kernel, dim3(gx, (unsigned)a.nout), dim3(256), 0, stream, per, a.Y, mxY);
+  hipLaunchKernelGGL(make_scale_kernel, dim3(ceil_div(2 * a.nout, 256)), dim3(256), 0, stream, 2 * a.nout,
+                     a.scales, target);
+  switch (a.dtype) {
+    case MCTRG_F32:
+      hipLaunchKernelGGL(cast_kernel<MCTRG_F32>, dim3(gx, (unsigned)a.nout), dim3(256), 0, stream, per, a.X, mxX, a.Xlp);
+      hipLaunchKernelGGL(cast_kernel<MCTRG_F32>, dim3(gx, (unsigned)a.nout), dim3(256), 0, stream, per, a.Y, mxY, a.Ylp);
+      hipLaunchKernelGGL(gemm_tn_kernel<MCTRG_F32>, gg, dim3(256), 0, stream, MM, MM, DD, (const void*)a.Xlp,
+                         (const void*)a.Ylp, a.Tout);
+      break;
+    case MCTRG_BF16:
+      hipLaunchKernelGGL(cast_kernel<MCTRG_BF16>, dim3(gx, (unsigned)a.nout), dim3(256), 0, stream, per, a.X, mxX, a.Xlp);
+      hipLaunchKernelGGL(cast_kernel<MCTRG_BF16>, dim3(gx, (unsigned)a.nout), dim3(256), 0, stream, per, a.Y, mxY, a.Ylp);
+      hipLaunchKernelGGL(gemm_tn_kernel<MCTRG_BF16>, gg, dim3(256), 0, stream, MM, MM, DD, (const void*)a.Xlp,
+                         (const void*)a.Ylp, a.Tout);
+      break;
+    case MCTRG_FP8_E4M3:
+      hipLaunchKernelGGL(cast_kernel<MCTRG_FP8_E4M3>, dim3(gx, (unsigned)a.nout), dim3(256), 0, stream, per, a.X, mxX, a.Xlp);
+      hipLaunchKernelGGL(cast_kernel<MCTRG_FP8_E4M3>, dim3(gx, (unsigned)a.nout), dim3(256), 0, stream, per, a.Y, mxY, a.Ylp);
+      hipLaunchKernelGGL(gemm_tn_kernel<MCTRG_FP8_E4M3>, gg, dim3(256), 0, stream, MM, MM, DD, (const void*)a.Xlp,
+                         (const void*)a.Ylp, a.Tout);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  (void)elt_bytes;
+  return hipGetLastError();
+}
+
+}  // namespace mctrg

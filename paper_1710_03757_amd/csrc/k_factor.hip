@@ -1,0 +1,199 @@
+// Unfolding and factor construction.
+//
+// Unfold (paper Section II, the index grouping before Eq. exactSVD): a
+// tensor T[l][u][r][d] with all legs of (capacity) dimension D is viewed
+// as an n x n matrix, n = D^2:
+//   A split  M_A[(l,u)][(r,d)] = T[l][u][r][d]  (T itself, row-major);
+//   B split  M_B[(u,r)][(d,l)] = T[l][u][r][d].
+// The Jacobi workspace W receives a zero-padded copy (n_pad x n_pad).
+//
+// Factors (Section II: T~ = U S^(e) V restricted to the kept set, with
+// S^(e)_ii = S_ii / r(S_ii); the reweighted value is split symmetrically):
+//   G[a][:] = w_a v_{i_a}^T,          v = normalised Jacobi row, signed so
+//                                     that sum_j v_j / (1 + i1 + phi i2) > 0
+//   F[:][a] = w_a u_{i_a} = M G[a]^T / s_{i_a}
+// with w_a = sqrt(s_{i_a} / r_{i_a}); entries a >= kept are zero
+// (capacity padding).
+#include "mctrg_internal.h"
+
+namespace mctrg {
+
+__device__ __forceinline__ size_t unfold_index(int split, int D, int row, int col) {
+  if (split == 0) return (size_t)row * (D * D) + col;
+  const int u = row / D, r = row % D, d = col / D, l = col % D;
+  return (((size_t)l * D + u) * D + r) * D + d;
+}
+
+__global__ void unfold_kernel(int64_t njobs, int D, int n_pad, const double* __restrict__ T,
+                              const int32_t* __restrict__ src, const int32_t* __restrict__ split,
+                              double* __restrict__ W) {
+  const int64_t job = blockIdx.y;
+  const int n = D * D;
+  const size_t per = (size_t)n_pad * n_pad;
+  const double* Ts = T + (size_t)src[job] * n * n;
+  const int sp = split[job];
+  double* Wj = W + job * per;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < per; e += (size_t)gridDim.x * blockDim.x) {
+    const int row = (int)(e / n_pad), col = (int)(e % n_pad);
+    double v = 0.0;
+    if (row < n && col < n) v = Ts[unfold_index(sp, D, row, col)];
+    Wj[e] = v;
+  }
+}
+
+hipError_t launch_unfold(int64_t njobs, int D, int n_pad, const double* T, const int32_t* src,
+                         const int32_t* split, double* W, hipStream_t stream) {
+  if (njobs == 0) return hipSuccess;
+  const size_t per = (size_t)n_pad * n_pad;
+  int gx = (int)((per + 255) / 256);
+  if (gx > 1024) gx = 1024;
+  hipLaunchKernelGGL(unfold_kernel, dim3(gx, (unsigned)njobs), dim3(256), 0, stream, njobs, D, n_pad, T, src,
+                     split, W);
+  return hipGetLastError();
+}
+
+// One workgroup per (kept index a, job).
+__global__ __launch_bounds__(256) void factor_G_kernel(int D, int n_pad, int kcap, const double* __restrict__ W,
+                                                       const double* __restrict__ sigma,
+                                                       const int32_t* __restrict__ order,
+                                                       const int32_t* __restrict__ kept,
+                                                       const int32_t* __restrict__ sel,
+                                                       const double* __restrict__ weight,
+                                                       double* __restrict__ G) {
+  const int a = blockIdx.x;
+  const int64_t job = blockIdx.y;
+  const int n = D * D;
+  double* Ga = G + (size_t)job * kcap * n + (size_t)a * n;
+  if (a >= kept[job]) {
+    for (int e = threadIdx.x; e < n; e += 256) Ga[e] = 0.0;
+    return;
+  }
+  const int i = sel[job * kcap + a];
+  const int row = order[(size_t)job * n + i];
+  const double s = sigma[(size_t)job * n + i];
+  const double w = weight[job * kcap + a];
+  const double* v = W + (size_t)job * n_pad * n_pad + (size_t)row * n_pad;
+  __shared__ double red[4];
+  double g = 0.0;
+  for (int e = threadIdx.x; e < n; e += 256) {
+    const int i1 = e / D, i2 = e % D;
+    g += v[e] / (1.0 + (double)i1 + kGolden * (double)i2);
+  }
+  for (int o = 32; o > 0; o >>= 1) g += __shfl_xor(g, o);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = g;
+  __syncthreads();
+  g = (red[0] + red[1]) + (red[2] + red[3]);
+  const double f = (g < 0.0 ? -w : w) / s;
+  for (int e = threadIdx.x; e < n; e += 256) Ga[e] = f * v[e];
+}
+
+hipError_t launch_factor_G(int64_t njobs, int D, int n_pad, int kcap, const double* W, const double* sigma,
+                           const int32_t* order, const int32_t* kept, const int32_t* sel, const double* weight,
+                           double* G, hipStream_t stream) {
+  if (njobs == 0) return hipSuccess;
+  hipLaunchKernelGGL(factor_G_kernel, dim3(kcap, (unsigned)njobs), dim3(256), 0, stream, D, n_pad, kcap, W, sigma,
+                     order, kept, sel, weight, G);
+  return hipGetLastError();
+}
+
+// F[job][row][a] = (1/s_a) sum_col M[row][col] G[job][a][col].  One
+// workgroup per (64-row tile, job); column chunks of 32 staged in LDS.
+__global__ __launch_bounds__(256) void factor_F_kernel(int D, int kcap, const double* __restrict__ T,
+                                                       const int32_t* __restrict__ src,
+                                                       const int32_t* __restrict__ split,
+                                                       const double* __restrict__ sigma,
+                                                       const int32_t* __restrict__ kept,
+                                                       const int32_t* __restrict__ sel,
+                                                       const double* __restrict__ G, double* __restrict__ F) {
+  const int64_t job = blockIdx.y;
+  const int n = D * D;
+  const int row0 = blockIdx.x * 64;
+  const int sp = split[job];
+  const double* Ts = T + (size_t)src[job] * n * n;
+  const double* Gj = G + (size_t)job * kcap * n;
+  const int kk = kept[job];
+  __shared__ double Ms[64][33];
+  __shared__ double Gs[64][33];
+  const int tid = threadIdx.x;
+  const int rloc = tid & 63, agrp = tid >> 6;   // a = agrp + 4*q
+  double acc[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) acc[q] = 0.0;
+  for (int c0 = 0; c0 < n; c0 += 32) {
+    for (int e = tid; e < 64 * 32; e += 256) {
+      const int rr = e >> 5, cc = e & 31;
+      const int row = row0 + rr, col = c0 + cc;
+      Ms[rr][cc] = (row < n && col < n) ? Ts[unfold_index(sp, D, row, col)] : 0.0;
+    }
+    for (int e = tid; e < 64 * 32; e += 256) {
+      const int aa = e >> 5, cc = e & 31;
+      const int col = c0 + cc;
+      Gs[aa][cc] = (aa < kk && col < n) ? Gj[(size_t)aa * n + col] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int aa = agrp + 4 * q;
+      if (aa < kcap) {
+        double s = acc[q];
+#pragma unroll 8
+        for (int cc = 0; cc < 32; ++cc) s += Ms[rloc][cc] * Gs[aa][cc];
+        acc[q] = s;
+      }
+    }
+    __syncthreads();
+  }
+  const int row = row0 + rloc;
+  if (row < n) {
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int aa = agrp + 4 * q;
+      if (aa < kcap) {
+        double v = 0.0;
+        if (aa < kk) v = acc[q] / sigma[(size_t)job * n + sel[job * kcap + aa]];
+        F[(size_t)job * n * kcap + (size_t)row * kcap + aa] = v;
+      }
+    }
+  }
+}
+
+hipError_t launch_factor_F(int64_t njobs, int D, int kcap, const double* T, const int32_t* src,
+                           const int32_t* split, const double* sigma, const int32_t* kept,
+                           const int32_t* sel, const double* G, double* F, hipStream_t stream) {
+  if (njobs == 0) return hipSuccess;
+  const int n = D * D;
+  hipLaunchKernelGGL(factor_F_kernel, dim3(ceil_div(n, 64), (unsigned)njobs), dim3(256), 0, stream, D, kcap, T,
+                     src, split, sigma, kept, sel, G, F);
+  return hipGetLastError();
+}
+
+// V[i][:] = W[order[i]] / sigma_i, signed so that sum_j V[i][j] g_j > 0
+// with g_j = 1 / (1 + j/d2 + phi * (j % d2)).  One workgroup per (i, matrix).
+__global__ __launch_bounds__(256) void extract_V_kernel(int n, int n_pad, int d2, const double* __restrict__ W,
+                                                        const double* __restrict__ sigma,
+                                                        const int32_t* __restrict__ order, double* __restrict__ V) {
+  const int i = blockIdx.x;
+  const int64_t m = blockIdx.y;
+  const double s = sigma[(size_t)m * n + i];
+  const double* v = W + (size_t)m * n_pad * n_pad + (size_t)order[(size_t)m * n + i] * n_pad;
+  double* out = V + ((size_t)m * n + i) * n;
+  __shared__ double red[4];
+  double g = 0.0;
+  for (int e = threadIdx.x; e < n; e += 256) g += v[e] / (1.0 + (double)(e / d2) + kGolden * (double)(e % d2));
+  for (int o = 32; o > 0; o >>= 1) g += __shfl_xor(g, o);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = g;
+  __syncthreads();
+  g = (red[0] + red[1]) + (red[2] + red[3]);
+  const double f = s > 0.0 ? (g < 0.0 ? -1.0 : 1.0) / s : 0.0;
+  for (int e = threadIdx.x; e < n; e += 256) out[e] = f * v[e];
+}
+
+hipError_t launch_extract_V(int64_t nmats, int n, int n_pad, int d2, const double* W, const double* sigma,
+                            const int32_t* order, double* V, hipStream_t stream) {
+  if (nmats == 0) return hipSuccess;
+  hipLaunchKernelGGL(extract_V_kernel, dim3(n, (unsigned)nmats), dim3(256), 0, stream, n, n_pad, d2, W, sigma,
+                     order, V);
+  return hipGetLastError();
+}
+
+}  // namespace mctrg

@@ -1,0 +1,324 @@
+// Decomposition step: FP64 SVD of a batch of square unfoldings by one-sided
+// block Jacobi (Hestenes), the "full singular value decomposition" of each
+// tensor that precedes the stochastic truncation (paper Section III, first
+// paragraph after Eq. infiniteSum; Section II Eq. exactSVD).
+//
+// Each job holds W (n_pad x n_pad, row-major).  The rows of W are the
+// columns of A = M^T.  Rotating rows so that they become mutually orthogonal
+// gives W_final = Q^T W with rows sigma_i * v_i, where v_i are the right
+// singular vectors of M and sigma_i its singular values; left vectors follow
+// as u_i = M v_i / sigma_i (see the factor kernels).
+//
+// Rows are grouped into blocks of 16; a sweep visits every pair of blocks
+// once, in nb-1 rounds of nb/2 disjoint pairs (circle ordering).  One
+// workgroup handles one (job, pair):
+//   1. Gram G = W_pair W_pair^T (32 x 32) with v_mfma_f64_16x16x4, each wave
+//      streaming a quarter of the row length from HBM;
+//   2. if some |g_ij| > tol * sqrt(g_ii g_jj): cyclic Jacobi on G in LDS
+//      (two-sided, with the diagonal updated as g_pp - t g_pq for relative
+//      accuracy) accumulating Q (32 x 32);
+//   3. W_pair <- Q^T W_pair with v_mfma_f64_16x16x4 (Q^T fragments held in
+//      registers, W streamed chunk by chunk and written back in place).
+// A job has converged when a whole sweep applied no rotation; the host
+// checks a device counter once per sweep.
+#include "mctrg_internal.h"
+
+namespace mctrg {
+
+// Position -> block index in round r of the circle ordering on nb blocks.
+__device__ __forceinline__ int circle_block(int pos, int r, int nb) {
+  return pos == 0 ? 0 : 1 + (pos - 1 + r) % (nb - 1);
+}
+
+// MFMA f64 16x16x4 accumulator layout: lane l, register i holds
+// C[4*(l/16) + i][l % 16].
+__global__ __launch_bounds__(256) void jacobi_round_kernel(double* __restrict__ W, int n_pad, int nb,
+                                                           int round, const int* __restrict__ active,
+                                                           int* __restrict__ rotated, double tol) {
+  const int job = blockIdx.y;
+  if (!active[job]) return;
+  const int pair = blockIdx.x;
+  const int I = circle_block(pair, round, nb);
+  const int J = circle_block(nb - 1 - pair, round, nb);
+  double* Wj = W + (size_t)job * n_pad * n_pad;
+  double* rowI = Wj + (size_t)(16 * I) * n_pad;
+  double* rowJ = Wj + (size_t)(16 * J) * n_pad;
+
+  // per-wave partial Gram tiles, later reused for Q (32 x 33)
+  __shared__ double part_q[4 * 3 * 256];
+  __shared__ double G[32][33];
+  double(*part)[3][256] = reinterpret_cast<double(*)[3][256]>(part_q);
+  double(*Q)[33] = reinterpret_cast<double(*)[33]>(part_q);
+  __shared__ double rc[16], rs[16], rdp[16], rdq[16];
+  __shared__ int rp[16], rq[16];
+  __shared__ int flag_any;
+  __shared__ double redbuf[8];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int lr = lane & 15, lg = lane >> 4;
+
+  // ---- 1. Gram of the 32 rows -------------------------------------------
+  f64x4 aII = {0, 0, 0, 0}, aIJ = {0, 0, 0, 0}, aJJ = {0, 0, 0, 0};
+  for (int k0 = 16 * wave; k0 < n_pad; k0 += 64) {
+    const double* pa = rowI + (size_t)lr * n_pad + k0 + 4 * lg;
+    const double* pb = rowJ + (size_t)lr * n_pad + k0 + 4 * lg;
+    double2 a01 = *reinterpret_cast<const double2*>(pa);
+    double2 a23 = *reinterpret_cast<const double2*>(pa + 2);
+    double2 b01 = *reinterpret_cast<const double2*>(pb);
+    double2 b23 = *reinterpret_cast<const double2*>(pb + 2);
+    double av[4] = {a01.x, a01.y, a23.x, a23.y};
+    double bv[4] = {b01.x, b01.y, b23.x, b23.y};
+#pragma unroll
+    for (int jj = 0; jj < 4; ++jj) {
+      aII = __builtin_amdgcn_mfma_f64_16x16x4f64(av[jj], av[jj], aII, 0, 0, 0);
+      aIJ = __builtin_amdgcn_mfma_f64_16x16x4f64(av[jj], bv[jj], aIJ, 0, 0, 0);
+      aJJ = __builtin_amdgcn_mfma_f64_16x16x4f64(bv[jj], bv[jj], aJJ, 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    int idx = (4 * lg + i) * 16 + lr;
+    part[wave][0][idx] = aII[i];
+    part[wave][1][idx] = aIJ[i];
+    part[wave][2][idx] = aJJ[i];
+  }
+  __syncthreads();
+  for (int e = tid; e < 1024; e += 256) {
+    int i = e >> 5, j = e & 31;
+    int ti = i >> 4, tj = j >> 4, ii = i & 15, jj = j & 15;
+    int t, idx;
+    if (ti == 0 && tj == 0) { t = 0; idx = ii * 16 + jj; }
+    else if (ti == 0) { t = 1; idx = ii * 16 + jj; }
+    else if (tj == 0) { t = 1; idx = jj * 16 + ii; }
+    else { t = 2; idx = ii * 16 + jj; }
+    G[i][j] = ((part[0][t][idx] + part[1][t][idx]) + part[2][t][idx]) + part[3][t][idx];
+  }
+  __syncthreads();
+  for (int e = tid; e < 1024; e += 256) Q[e >> 5][e & 31] = ((e >> 5) == (e & 31)) ? 1.0 : 0.0;
+
+  // ---- convergence test of this pair ------------------------------------
+  double off = 0.0;
+  for (int e = tid; e < 1024; e += 256) {
+    int i = e >> 5, j = e & 31;
+    if (i < j) {
+      double d = G[i][i] * G[j][j];
+      if (d > 0.0) off = fmax(off, fabs(G[i][j]) / sqrt(d));
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1) off = fmax(off, __shfl_xor(off, o));
+  if (lane == 0) redbuf[wave] = off;
+  __syncthreads();
+  off = fmax(fmax(redbuf[0], redbuf[1]), fmax(redbuf[2], redbuf[3]));
+  if (!(off > tol)) return;            // pair already orthogonal (uniform)
+  if (tid == 0) atomicOr(&rotated[job], 1);
+
+  // ---- 2. cyclic Jacobi on G, accumulating Q ------------------------------
+  const double tol_in = 0x1.0p-53;
+  for (int sweep = 0; sweep < 16; ++sweep) {
+    if (tid == 0) flag_any = 0;
+    __syncthreads();   // also orders the Q initialisation before its first use
+    for (int r = 0; r < 31; ++r) {
+      if (tid < 16) {
+        int p = tid == 0 ? 0 : 1 + (tid - 1 + r) % 31;
+        int q = 1 + (31 - tid - 1 + r) % 31;
+        if (p > q) { int tmp = p; p = q; q = tmp; }
+        double gpp = G[p][p], gqq = G[q][q], gpq = G[p][q];
+        double c = 1.0, s = 0.0, dp = gpp, dq = gqq;
+        if (fabs(gpq) > tol_in * sqrt(gpp * gqq) && gpq != 0.0) {
+          double theta = (gqq - gpp) / (2.0 * gpq);
+          double t = (fabs(theta) > 1e150) ? 0.5 / theta
+                                           : copysign(1.0, theta) / (fabs(theta) + sqrt(1.0 + theta * theta));
+          c = 1.0 / sqrt(1.0 + t * t);
+          s = t * c;
+          dp = gpp - t * gpq;
+          dq = gqq + t * gpq;
+          flag_any = 1;
+        }
+        rp[tid] = p; rq[tid] = q; rc[tid] = c; rs[tid] = s; rdp[tid] = dp; rdq[tid] = dq;
+      }
+      __syncthreads();
+      {  // column rotations of G and Q: pair i = tid/16, rows tid%16 and +16
+        int i = tid >> 4, row0 = tid & 15;
+        int p = rp[i], q = rq[i];
+        double c = rc[i], s = rs[i];
+        if (s != 0.0) {
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            int row = row0 + 16 * h;
+            double gp = G[row][p], gq = G[row][q];
+            G[row][p] = c * gp - s * gq;
+            G[row][q] = s * gp + c * gq;
+            double qp = Q[row][p], qq = Q[row][q];
+            Q[row][p] = c * qp - s * qq;
+            Q[row][q] = s * qp + c * qq;
+          }
+        }
+      }
+      __syncthreads();
+      {  // row rotations of G
+        int i = tid >> 4, col0 = tid & 15;
+        int p = rp[i], q = rq[i];
+        double c = rc[i], s = rs[i];
+        if (s != 0.0) {
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            int col = col0 + 16 * h;
+            double gp = G[p][col], gq = G[q][col];
+            G[p][col] = c * gp - s * gq;
+            G[q][col] = s * gp + c * gq;
+          }
+        }
+      }
+      __syncthreads();
+      if (tid < 16 && rs[tid] != 0.0) {
+        int p = rp[tid], q = rq[tid];
+        G[p][p] = rdp[tid];
+        G[q][q] = rdq[tid];
+        G[p][q] = 0.0;
+        G[q][p] = 0.0;
+      }
+      __syncthreads();
+    }
+    const int any = flag_any;
+    __syncthreads();   // every thread has read the flag before it is reset
+    if (!any) break;
+  }
+
+  // ---- 3. W_pair <- Q^T W_pair ------------------------------------------
+  // A fragment (output rows i = 16t + l%16, K index j = 4s + l/16): Q[j][i].
+  double qa[2][8];
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int s = 0; s < 8; ++s) qa[t][s] = Q[4 * s + lg][16 * t + lr];
+
+  for (int k0 = 16 * wave; k0 < n_pad; k0 += 64) {
+    double bvals[8];
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+      int j = 4 * s + lg;
+      const double* src = (j < 16 ? rowI + (size_t)j * n_pad : rowJ + (size_t)(j - 16) * n_pad);
+      bvals[s] = src[k0 + lr];
+    }
+    f64x4 c0 = {0, 0, 0, 0}, c1 = {0, 0, 0, 0};
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+      c0 = __builtin_amdgcn_mfma_f64_16x16x4f64(qa[0][s], bvals[s], c0, 0, 0, 0);
+      c1 = __builtin_amdgcn_mfma_f64_16x16x4f64(qa[1][s], bvals[s], c1, 0, 0, 0);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      int r = 4 * lg + i;                      // new row within the tile
+      rowI[(size_t)r * n_pad + k0 + lr] = c0[i];
+      rowJ[(size_t)r * n_pad + k0 + lr] = c1[i];
+    }
+  }
+}
+
+__global__ void jacobi_init_kernel(int64_t njobs, int* active, int* rotated, int* sweeps) {
+  int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (j < njobs) { active[j] = 1; rotated[j] = 0; sweeps[j] = -1; }
+}
+
+__global__ void jacobi_sweep_end_kernel(int64_t njobs, int sweep, int* active, int* rotated,
+                                        int* sweeps, int* counter) {
+  int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  int still = 0;
+  if (j < njobs && active[j]) {
+    if (rotated[j]) still = 1;
+    else { active[j] = 0; sweeps[j] = sweep + 1; }
+    rotated[j] = 0;
+  }
+  // one atomic per wave
+  unsigned long long m = __ballot(still);
+  if ((threadIdx.x & 63) == 0 && m) atomicAdd(counter, __popcll(m));
+}
+
+__global__ void zero_int_kernel(int* p) { *p = 0; }
+
+hipError_t run_jacobi(int64_t njobs, int n_pad, double* W, const JacobiWork& wk, int max_sweeps,
+                      hipStream_t stream) {
+  if (njobs == 0) return hipSuccess;
+  const int nb = n_pad / 16;
+  const double tol = fmax(32.0, 8.0 * sqrt((double)n_pad)) * 0x1.0p-53;
+  int g = ceil_div(njobs, 256);
+  hipLaunchKernelGGL(jacobi_init_kernel, dim3(g), dim3(256), 0, stream, njobs, wk.active, wk.rotated,
+                     wk.sweeps);
+  for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+    for (int r = 0; r < nb - 1; ++r) {
+      hipLaunchKernelGGL(jacobi_round_kernel, dim3(nb / 2, (unsigned)njobs), dim3(256), 0, stream, W,
+                         n_pad, nb, r, wk.active, wk.rotated, tol);
+    }
+    hipLaunchKernelGGL(zero_int_kernel, dim3(1), dim3(1), 0, stream, wk.counter);
+    hipLaunchKernelGGL(jacobi_sweep_end_kernel, dim3(g), dim3(256), 0, stream, njobs, sweep, wk.active,
+                       wk.rotated, wk.sweeps, wk.counter);
+    hipError_t e = hipMemcpyAsync(wk.counter_host, wk.counter, sizeof(int), hipMemcpyDeviceToHost, stream);
+    if (e != hipSuccess) return e;
+    e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return e;
+    if (*wk.counter_host == 0) break;
+  }
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Finalisation: sigma_i = ||row_i||, sorted descending (ties by row index).
+// One workgroup of 256 threads per job; bitonic sort over n_pad <= 4096 keys.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void jacobi_finalize_kernel(int n, int n_pad, const double* __restrict__ W,
+                                                              double* __restrict__ sigma,
+                                                              int32_t* __restrict__ order) {
+  extern __shared__ unsigned char smem[];
+  int P = 1;
+  while (P < n_pad) P <<= 1;
+  double* key = reinterpret_cast<double*>(smem);
+  int* idx = reinterpret_cast<int*>(key + P);
+  const int job = blockIdx.x;
+  const double* Wj = W + (size_t)job * n_pad * n_pad;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int r = wave; r < P; r += 4) {
+    double s = 0.0;
+    if (r < n_pad) {
+      const double* row = Wj + (size_t)r * n_pad;
+      for (int c = lane; c < n_pad; c += 64) s += row[c] * row[c];
+      for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+    } else {
+      s = -1.0;   // padding sorts last
+    }
+    if (lane == 0) { key[r] = (r < n_pad) ? sqrt(s) : -1.0; idx[r] = r; }
+  }
+  __syncthreads();
+  // bitonic sort: descending key, ascending index on ties
+  for (int size = 2; size <= P; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int t = threadIdx.x; t < P / 2; t += 256) {
+        int i = 2 * stride * (t / stride) + (t % stride);
+        int jx = i + stride;
+        bool up = ((i & size) == 0);
+        double ki = key[i], kj = key[jx];
+        int ii = idx[i], ij = idx[jx];
+        bool i_first = (ki > kj) || (ki == kj && ii < ij);   // i should precede j
+        bool swap = up ? !i_first : i_first;
+        if (swap) { key[i] = kj; key[jx] = ki; idx[i] = ij; idx[jx] = ii; }
+      }
+      __syncthreads();
+    }
+  }
+  for (int i = threadIdx.x; i < n; i += 256) {
+    sigma[(size_t)job * n + i] = key[i];
+    order[(size_t)job * n + i] = idx[i];
+  }
+}
+
+hipError_t launch_jacobi_finalize(int64_t njobs, int n, int n_pad, const double* W, double* sigma,
+                                  int32_t* order, hipStream_t stream) {
+  if (njobs == 0) return hipSuccess;
+  int P = 1;
+  while (P < n_pad) P <<= 1;
+  size_t sh = (size_t)P * (sizeof(double) + sizeof(int));
+  hipLaunchKernelGGL(jacobi_finalize_kernel, dim3((unsigned)njobs), dim3(256), sh, stream, n, n_pad, W,
+                     sigma, order);
+  return hipGetLastError();
+}
+
+}  // namespace mctrg

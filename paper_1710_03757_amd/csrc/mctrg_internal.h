@@ -1,0 +1,174 @@
+// Internal declarations of the MI355X Monte Carlo TRG library: device
+// helpers shared by the HIP kernels and the launchers called by the host
+// runtime.  Not part of the public C ABI (see include/mctrg.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+namespace mctrg {
+
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr double kGolden = 1.6180339887498948482;   // gauge weight ratio
+
+// ---------------------------------------------------------------------------
+// Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11): four 64-bit counter
+// words, two key words, ten rounds of two 64x64->128 multiplies, Weyl key
+// schedule.  Counter map of one selection uniform:
+//   key = (seed, 0); counter = (sample, position, purpose<<32 | step<<1 |
+//   split, m >> 2); word m & 3; u = (word >> 11) * 2^-53.
+// ---------------------------------------------------------------------------
+struct u64x4 { uint64_t v[4]; };
+
+__device__ __forceinline__ u64x4 philox4x64_10(u64x4 x, uint64_t k0, uint64_t k1) {
+  const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+  const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    uint64_t hi0 = __umul64hi(M0, x.v[0]), lo0 = M0 * x.v[0];
+    uint64_t hi1 = __umul64hi(M1, x.v[2]), lo1 = M1 * x.v[2];
+    u64x4 y;
+    y.v[0] = hi1 ^ x.v[1] ^ k0;
+    y.v[1] = lo1;
+    y.v[2] = hi0 ^ x.v[3] ^ k1;
+    y.v[3] = lo0;
+    x = y;
+    k0 += W0;
+    k1 += W1;
+  }
+  return x;
+}
+
+__device__ __forceinline__ double word_to_uniform(uint64_t w) {
+  return (double)(w >> 11) * 0x1.0p-53;
+}
+
+// ln(e^a + e^b) with -inf handled exactly.
+__device__ __forceinline__ double logaddexp(double a, double b) {
+  if (a == -INFINITY) return b;
+  if (b == -INFINITY) return a;
+  double m = fmax(a, b), d = -fabs(a - b);
+  return m + log1p(exp(d));
+}
+
+// Order-preserving atomic max of non-negative doubles via their bit pattern.
+__device__ __forceinline__ void atomic_max_nonneg(double* addr, double v) {
+  atomicMax(reinterpret_cast<unsigned long long*>(addr), (unsigned long long)__double_as_longlong(v));
+}
+
+inline int ceil_div(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
+inline int round_up32(int n) { return ((n + 31) / 32) * 32; }
+
+// ---------------------------------------------------------------------------
+// Launchers (host functions, each enqueues on `stream`, returns hipError_t).
+// ---------------------------------------------------------------------------
+
+// Initial tensors.
+hipError_t launch_init_tensors(int model, int ngroups, const double* beta, const double* h,
+                               double* out, hipStream_t stream);
+// Gather per-sample starting tensors: T[s] = T0[group[s]] (d0^4 each).
+hipError_t launch_gather_tensors(int64_t nsamp, int d0, const double* T0, const int32_t* group,
+                                 double* T, hipStream_t stream);
+
+// Unfold: W[j] (n_pad x n_pad, zero padded) = M_split(T[src[j]]), n = D^2.
+hipError_t launch_unfold(int64_t njobs, int D, int n_pad, const double* T, const int32_t* src,
+                         const int32_t* split, double* W, hipStream_t stream);
+
+// One-sided block Jacobi SVD of W[j] (rows are rotated).  Host-driven sweeps.
+struct JacobiWork {
+  int* active;      // njobs
+  int* rotated;     // njobs
+  int* sweeps;      // njobs (-1 until converged)
+  int* counter;     // device 1 int
+  int* counter_host; // pinned host 1 int
+};
+hipError_t run_jacobi(int64_t njobs, int n_pad, double* W, const JacobiWork& wk, int max_sweeps,
+                      hipStream_t stream);
+// Norms of the rotated rows, sorted descending: sigma[j][0..n), order[j][0..n).
+hipError_t launch_jacobi_finalize(int64_t njobs, int n, int n_pad, const double* W, double* sigma,
+                                  int32_t* order, hipStream_t stream);
+
+// Sampler: chooses kept subsets, inclusion rates and weights.
+struct SampleArgs {
+  int64_t njobs;
+  int n;            // spectrum length per job (sigma stride)
+  int k;            // kept count capacity (sel/log_r/weight stride)
+  int mode;         // MCTRG_* mode (TOPK => top-k)
+  uint64_t seed;
+  double tau;
+  const double* sigma;
+  const uint64_t* rng;     // 3 words per job: sample, position, step
+  const int32_t* split;    // per job
+  int32_t* kept;
+  int32_t* cand;
+  int32_t* sel;
+  double* log_r;
+  double* weight;
+  double* scratch;         // njobs * (k+1) * (n+1) * 2 + njobs * n doubles
+};
+hipError_t launch_sample(const SampleArgs& a, hipStream_t stream);
+size_t sample_scratch_doubles(int64_t njobs, int n, int k);
+
+// Factors.  G[j]: kcap x n (row a = w_a v_a), F[j]: n x kcap (col a = w_a u_a).
+hipError_t launch_factor_G(int64_t njobs, int D, int n_pad, int kcap, const double* W,
+                           const double* sigma, const int32_t* order, const int32_t* kept,
+                           const int32_t* sel, const double* weight, double* G, hipStream_t stream);
+hipError_t launch_factor_F(int64_t njobs, int D, int kcap, const double* T, const int32_t* src,
+                           const int32_t* split, const double* sigma, const int32_t* kept,
+                           const int32_t* sel, const double* G, double* F, hipStream_t stream);
+
+// Contraction of four factors per output tensor.
+struct ContractArgs {
+  int64_t nout;            // number of output tensors
+  int D, kk, dtype;
+  const double* GA; const double* GB;   // factor pools indexed by decomposition job
+  const double* FA; const double* FB;
+  int64_t g_stride, f_stride;           // doubles per job in the G and F pools
+  const int32_t* jobs;     // nout x 4: (job of GA, job of GB, job of FA, job of FB)
+  double* X; double* Y;    // workspace: nout * kk^2 * D^2 each
+  void* Xlp; void* Ylp;    // low-precision copies (bytes: nout * kk^2 * D^2 * elt)
+  double* scales;          // nout * 2
+  void* Tout;              // nout * kk^4, FP64 (dtype F64) or FP32 (others)
+};
+hipError_t launch_contract(const ContractArgs& a, hipStream_t stream);
+
+// T_out = C / (scale_X * scale_Y) in FP64 (C FP64 or FP32).
+hipError_t launch_unscale(int64_t nout, int64_t elems, int src_is_f32, const void* C, const double* scales,
+                          double* T_out, hipStream_t stream);
+
+// Right singular vectors of the Jacobi result, gauge-fixed (row i of V).
+hipError_t launch_extract_V(int64_t nmats, int n, int n_pad, int d2, const double* W, const double* sigma,
+                            const int32_t* order, double* V, hipStream_t stream);
+
+// Normalisation: c = max|T'|, T = T'/c, ln c - ln(scales) written to lnc[j].
+hipError_t launch_normalize(int64_t nout, int64_t elems, int src_is_f32, const void* Tp,
+                            const double* scales, double* cbuf, double* T, double* lnc,
+                            hipStream_t stream);
+
+// Final trace and per-sample ln|Z~|.
+hipError_t launch_trace(int64_t nsamp, int D, const double* T, const double* lnc_steps, int n_steps,
+                        int shared_weights, const int* failed, int8_t* sign, double* ln_abs_Z,
+                        hipStream_t stream);
+
+// Estimator (single workgroup, deterministic order).
+hipError_t launch_estimate(int64_t n, const int8_t* sign, const double* ln_abs, double n_sites,
+                           double* out8, hipStream_t stream);
+
+// Chain bookkeeping (k_chain.hip).
+hipError_t launch_record(int64_t nsamp, int step, int n_steps, int kmax, int kcap, const int64_t* idx,
+                         const int32_t* cand, const int32_t* kept, const int32_t* sel, int32_t* rec,
+                         hipStream_t stream);
+hipError_t launch_lnc_accum(int64_t nsamp, int out_per_sample, int step, int n_steps, const double* lnc,
+                            double* lnc_steps, int* failed, hipStream_t stream);
+hipError_t launch_jacobi_fail(int64_t njobs, int jobs_per_sample, const int* sweeps, int* failed,
+                              hipStream_t stream);
+hipError_t launch_izero(int64_t n, int* p, hipStream_t stream);
+hipError_t launch_scatter(int64_t nsamp, int n_steps, const int64_t* idx, const int8_t* sign, const double* ln,
+                          const double* lnc_steps, int8_t* out_sign, double* out_ln, double* out_lnc,
+                          hipStream_t stream);
+hipError_t launch_pad_copy(int64_t nmats, int n, int n_pad, const double* M, double* W, hipStream_t stream);
+
+}  // namespace mctrg
