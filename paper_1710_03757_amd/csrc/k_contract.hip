@@ -229,7 +229,8 @@ __global__ __launch_bounds__(256) void gemm_tn_kernel(int M, int N, int K, const
     for (int j = 0; j < 2; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int gm = m0 + wm + 16 * i + 4 * lg + r, gn = n0 + wn + 16 * j + lr;
+        const int gm = m0 + wm + 16 * i + (DT == MCTRG_F64 ? acc_row_f64(lg, r) : acc_row_f32(lg, r));
+        const int gn = n0 + wn + 16 * j + lr;
         if (gm < M && gn < N) C[(size_t)gm * N + gn] = acc[i][j][r];
       }
 }

@@ -30,8 +30,6 @@ __device__ __forceinline__ int circle_block(int pos, int r, int nb) {
   return pos == 0 ? 0 : 1 + (pos - 1 + r) % (nb - 1);
 }
 
-// MFMA f64 16x16x4 accumulator layout: lane l, register i holds
-// C[4*(l/16) + i][l % 16].
 __global__ __launch_bounds__(256) void jacobi_round_kernel(double* __restrict__ W, int n_pad, int nb,
                                                            int round, const int* __restrict__ active,
                                                            int* __restrict__ rotated, double tol) {
@@ -77,7 +75,7 @@ __global__ __launch_bounds__(256) void jacobi_round_kernel(double* __restrict__ 
   }
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
-    int idx = (4 * lg + i) * 16 + lr;
+    int idx = acc_row_f64(lg, i) * 16 + lr;
     part[wave][0][idx] = aII[i];
     part[wave][1][idx] = aIJ[i];
     part[wave][2][idx] = aJJ[i];
@@ -124,7 +122,8 @@ __global__ __launch_bounds__(256) void jacobi_round_kernel(double* __restrict__ 
         if (p > q) { int tmp = p; p = q; q = tmp; }
         double gpp = G[p][p], gqq = G[q][q], gpq = G[p][q];
         double c = 1.0, s = 0.0, dp = gpp, dq = gqq;
-        if (fabs(gpq) > tol_in * sqrt(gpp * gqq) && gpq != 0.0) {
+        // |.| guards the tiny diagonal entries that rounding can push below 0
+        if (gpq != 0.0 && fabs(gpq) > tol_in * sqrt(fabs(gpp * gqq))) {
           double theta = (gqq - gpp) / (2.0 * gpq);
           double t = (fabs(theta) > 1e150) ? 0.5 / theta
                                            : copysign(1.0, theta) / (fabs(theta) + sqrt(1.0 + theta * theta));
@@ -208,7 +207,7 @@ __global__ __launch_bounds__(256) void jacobi_round_kernel(double* __restrict__ 
     }
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      int r = 4 * lg + i;                      // new row within the tile
+      int r = acc_row_f64(lg, i);              // new row within the tile
       rowI[(size_t)r * n_pad + k0 + lr] = c0[i];
       rowJ[(size_t)r * n_pad + k0 + lr] = c1[i];
     }

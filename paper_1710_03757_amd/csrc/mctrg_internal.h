@@ -14,6 +14,13 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr double kGolden = 1.6180339887498948482;   // gauge weight ratio
 
+// Accumulator layouts of the 16x16 MFMAs (measured on gfx950): lane l,
+// register i of the result holds C[row][l % 16] with
+//   v_mfma_f64_16x16x4_f64:            row = l/16 + 4*i
+//   f32-accumulating 16x16 variants:   row = 4*(l/16) + i
+__device__ __forceinline__ int acc_row_f64(int lg, int i) { return lg + 4 * i; }
+__device__ __forceinline__ int acc_row_f32(int lg, int i) { return 4 * lg + i; }
+
 // ---------------------------------------------------------------------------
 // Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11): four 64-bit counter
 // words, two key words, ten rounds of two 64x64->128 multiplies, Weyl key
