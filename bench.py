@@ -1,0 +1,213 @@
+#!/usr/bin/env python3
+"""Benchmark of the Monte Carlo TRG hot path on one MI355X.
+
+Workload (default): the k = 32 form of the batched configuration - 2-D
+Ising site tensors at beta_c, h = 0, a chain of 30 coarse-graining steps
+(2^30 sites), FP32 coarse-graining GEMM, FP64 decomposition, sampling and
+log-normalisation.  A "step" is one full TRG step of the hot path (unfold,
+Jacobi SVD of both splits, subset sampling and reweighting, factors,
+contraction, normalisation) over the whole batch of samples.  The first
+``--warmup`` steps (the ramp-up of the bond dimension 2 -> 4 -> 16 -> 32 and
+one steady step) are untimed; the next ``--steps`` steps are timed between
+device synchronisations, followed by the final trace and the estimator.
+
+Output: one JSON line with the throughput in sample-steps/s, a roofline
+record of the dominant kernel (the Jacobi rotation kernel, timed live with
+HIP events around every launch on the library's stream), the MFMA rate of
+the coarse-graining GEMM, the accuracy against the CPU oracle on the first
+samples, and the oracle's own rate on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+from workloads import BETA_C  # noqa: E402
+
+METRIC = "TRG sample-steps/s at χ=32 + MFMA util; |Δ ln Z|/site vs FP64 oracle"
+PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0, "fp8": 5000.0}
+
+
+def decomposition_flops(k: int) -> float:
+    """Algorithmic FP64 flops of the decomposition per steady sample-step:
+    two n x n splits (n = k^2), each n^3 (Gram) + 4/3 n^3 (reduction to
+    tridiagonal form), i.e. (14/3) k^6."""
+    return 14.0 / 3.0 * k ** 6
+
+
+def gemm_flops(k: int) -> float:
+    """Flops of the coarse-graining GEMM per steady sample-step: k^2 x k^2
+    output, inner dimension D^2 = k^2, i.e. 2 k^6."""
+    return 2.0 * k ** 6
+
+
+def cpu_baseline(k, beta, h, n_chain_steps, warmup, steps, samples, dtype):
+    """Times the CPU oracle on the same chains (steady steps only)."""
+    import numpy as np
+    from oracle import ising, trg
+    threads = None
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max((p.get("num_threads", 1) for p in threadpool_info()), default=None)
+    except Exception:
+        pass
+    T0 = ising.site_tensor(beta, h)
+    t_steady = 0.0
+    n_steady = 0
+    results = []
+    for sid in range(samples):
+        T = T0.copy()
+        ln_c = []
+        for step in range(warmup + steps):
+            t0 = time.perf_counter()
+            FA, GA, _ = trg.decompose_and_truncate(T, 0, k, "shared", 0, sid, 0, step, 1e-11)
+            FB, GB, _ = trg.decompose_and_truncate(T, 1, k, "shared", 0, sid, 0, step, 1e-11)
+            Tn = trg.contract(GA, GB, FA, FB)
+            c = float(np.max(np.abs(Tn)))
+            T = Tn / c
+            ln_c.append(math.log(c))
+            dt = time.perf_counter() - t0
+            if step >= warmup:
+                t_steady += dt
+                n_steady += 1
+        n = warmup + steps
+        tr = trg.trace(T)
+        N = 2.0 ** n
+        ln = sum((N / 2.0 ** (s + 1)) * v for s, v in enumerate(ln_c)) + math.log(abs(tr))
+        results.append((1 if tr > 0 else -1, ln))
+    return {
+        "value": n_steady / t_steady,
+        "unit": "sample-steps/s",
+        "cores": threads if threads else os.cpu_count(),
+        "kind": "oracle",
+        "sample": f"{samples} chains x {steps} steady steps at k={k} (n={k * k}), after {warmup} untimed "
+                  f"ramp-up steps; NumPy/LAPACK FP64, contraction FP64",
+        "seconds": t_steady,
+    }, results
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=4)
+    ap.add_argument("--batch", type=int, default=128)
+    ap.add_argument("--k", type=int, default=32)
+    ap.add_argument("--dtype", default="f32", choices=["f64", "f32", "bf16", "fp8"])
+    ap.add_argument("--beta", type=float, default=BETA_C)
+    ap.add_argument("--h", type=float, default=0.0)
+    ap.add_argument("--chain-steps", type=int, default=30)
+    ap.add_argument("--cpu-samples", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): samples are independent, so a "
+              "multi-GPU run would split sample ids across ranks and reduce the estimator partials once at "
+              "the end; that path is not built.", file=sys.stderr)
+        sys.exit(2)
+    if args.warmup + args.steps > args.chain_steps:
+        print("warmup + steps must not exceed the chain length", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1710_03757_amd as m
+
+    assert torch.cuda.is_available(), "bench needs a GPU"
+    torch.cuda.set_device(0)
+    k, B = args.k, args.batch
+    print(f"[bench] k={k} batch={B} dtype={args.dtype} warmup={args.warmup} steps={args.steps}", flush=True)
+    ts = m.init_tensor("site", [args.beta], [args.h])
+    chain = m.Chain(ts, B, n_steps=args.chain_steps, k=k, dtype=args.dtype, seed=0, profile=True)
+    for s in range(args.warmup):
+        chain.step(1)
+        print(f"[bench] warmup step {s} done, sweeps={chain.profile()['last_sweeps']}", flush=True)
+    torch.cuda.synchronize()
+    p0 = chain.profile()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record()
+    sweeps = []
+    for s in range(args.steps):
+        chain.step(1)
+        sweeps.append(chain.profile()["last_sweeps"])
+    res = chain.finish()
+    est = m.estimate_lnZ(res.sign, res.ln_abs_Z, 2.0 ** (args.warmup + args.steps))
+    ev1.record()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    p1 = chain.profile()
+    ms_total = ev0.elapsed_time(ev1)
+    wall = t1 - t0
+    print(f"[bench] timed {args.steps} steps: {ms_total:.1f} ms (events), {wall * 1e3:.1f} ms (wall), "
+          f"sweeps {sweeps}", flush=True)
+    ms_per_step = ms_total / args.steps
+    value = B * args.steps / (ms_total / 1e3)
+
+    jl = p1["jacobi_launches"] - p0["jacobi_launches"]
+    jms = p1["jacobi_ms"] - p0["jacobi_ms"]
+    gl = p1["gemm_launches"] - p0["gemm_launches"]
+    gms = p1["gemm_ms"] - p0["gemm_ms"]
+    # dominant kernel: Jacobi rotation kernel; algorithmic decomposition flops
+    # of the timed steps spread over its launches
+    alg = decomposition_flops(k) * B * args.steps
+    avg_launch_ms = jms / max(jl, 1)
+    achieved = alg / max(jl, 1) / (avg_launch_ms / 1e3) / 1e12 if jl else None
+    roofline = {"bound": "mfma", "kernel": "jacobi_round_kernel", "achieved": achieved, "peak": PEAK_TFLOPS["f64"],
+                "unit": "TFLOP/s", "frac": (achieved / PEAK_TFLOPS["f64"]) if achieved else None, "traffic": None,
+                "avg_launch_ms": avg_launch_ms, "launches": jl,
+                "share_of_step_time": jms / ms_total if ms_total else None}
+    galg = gemm_flops(k) * B * args.steps
+    gemm = {"kernel": f"gemm_tn_kernel<{args.dtype}>", "achieved": galg / (gms / 1e3) / 1e12 if gms else None,
+            "peak": PEAK_TFLOPS[args.dtype], "unit": "TFLOP/s", "avg_launch_ms": gms / max(gl, 1), "launches": gl}
+    gemm["frac"] = gemm["achieved"] / gemm["peak"] if gemm["achieved"] else None
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "sample-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"2-D Ising site tensors, beta={args.beta:.6f}, h={args.h}, k={k}, chain of "
+                               f"{args.chain_steps} steps (2^{args.chain_steps} sites), shared chain, "
+                               f"steady-state steps {args.warmup}..{args.warmup + args.steps - 1}",
+                   "k": k, "batch": B, "contract_dtype": args.dtype, "mode": "shared",
+                   "decomposition": "FP64 one-sided block Jacobi"},
+        "roofline": roofline,
+        "mfma_contraction": gemm,
+        "jacobi_sweeps_per_step": sweeps,
+        "estimate_partial_chain": {k2: est[k2] for k2 in ("mean_lnZ_per_site", "stderr_mean_lnZ", "n_failed")},
+    }
+
+    if not args.no_cpu_baseline:
+        base, ores = cpu_baseline(k, args.beta, args.h, args.chain_steps, args.warmup, args.steps,
+                                  args.cpu_samples, args.dtype)
+        out["cpu_baseline"] = base
+        ln = res.ln_abs_Z.cpu().numpy()
+        sg = res.sign.cpu().numpy()
+        N = 2.0 ** (args.warmup + args.steps)
+        diffs = [abs(float(ln[i]) - o[1]) / N for i, o in enumerate(ores)]
+        out["accuracy"] = {"abs_dlnZ_per_site_vs_f64_oracle": diffs, "samples": len(ores),
+                           "signs_equal": bool(all(int(sg[i]) == o[0] for i, o in enumerate(ores))),
+                           "lattice_sites": N, "note": "same Philox draws; GPU contraction in "
+                                                       f"{args.dtype}, oracle FP64"}
+    print(json.dumps(out), flush=True)
+    chain.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -87,6 +87,8 @@ enum mctrg_dtype { MCTRG_F64 = 0, MCTRG_F32 = 1, MCTRG_BF16 = 2, MCTRG_FP8_E4M3 
 /* flags */
 #define MCTRG_RECORD 1u   /* write per-step selection records to record_buf   */
 #define MCTRG_ASYNC  2u   /* return without synchronising hip_stream          */
+#define MCTRG_PROFILE 4u  /* chains: time the decomposition and GEMM kernels  */
+                          /* with HIP events (see mctrg_chain_get_profile)     */
 
 typedef struct mctrg_tensor_set mctrg_tensor_set;  /* opaque, library-owned */
 
@@ -162,6 +164,34 @@ typedef struct {
  * counted as failed).  *out is written on the host.  Blocks on hip_stream. */
 int mctrg_estimate_lnZ(int64_t n_samples, const int8_t* sign, const double* ln_abs_Z,
                        double n_sites, mctrg_estimate* out, void* hip_stream);
+
+/* ---- Stepping interface (one wave of samples, one kept count) ----------
+ * The same per-sample chain as mctrg_run_samples, advanced step by step:
+ * create gathers the starting tensors of n_samples samples (ids
+ * cfg->sample_offset + i, groups from the host array group_of_sample or 0)
+ * and allocates the device workspace; step applies n TRG steps (at most
+ * cfg->n_steps in total); finish traces the current tensor - after s
+ * steps this is the sample of Z for the 2^s-site lattice - and writes
+ * sign / ln|Z~| / ln c (device arrays, n_samples and n_samples *
+ * cfg->n_steps; out_ln_c may be NULL).  Errors as mctrg_run_samples;
+ * MCTRG_RECORD and out_tensor are ignored here. */
+typedef struct mctrg_chain mctrg_chain;
+int mctrg_chain_create(mctrg_tensor_set* ts, const mctrg_run_config* cfg, int64_t n_samples,
+                       const int32_t* group_of_sample, void* hip_stream, mctrg_chain** out);
+int mctrg_chain_step(mctrg_chain* ch, int32_t n);
+int mctrg_chain_finish(mctrg_chain* ch, int8_t* out_sign, double* out_ln_abs_Z, double* out_ln_c);
+
+typedef struct {
+  double jacobi_ms;         /* summed duration of the Jacobi rotation kernels    */
+  int64_t jacobi_launches;  /* number of those launches                          */
+  double gemm_ms;           /* summed duration of the coarse-graining GEMMs      */
+  int64_t gemm_launches;
+  int32_t steps_done;
+  int32_t last_sweeps;      /* Jacobi sweeps used by the last step               */
+} mctrg_chain_profile;
+/* Timings are collected only when cfg->flags has MCTRG_PROFILE. */
+int mctrg_chain_get_profile(const mctrg_chain* ch, mctrg_chain_profile* out);
+void mctrg_chain_destroy(mctrg_chain* ch);
 
 void mctrg_destroy(mctrg_tensor_set* ts);
 const char* mctrg_status_string(int status);

@@ -30,7 +30,7 @@ OK, EINVAL, ENOMEM, EDEVICE, ENUMERIC, EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 ISING_SITE, ISING_PLAQUETTE, USER = 0, 1, 2
 SHARED, INDEPENDENT, TOPK = 0, 1, 2
 F64, F32, BF16, FP8_E4M3 = 0, 1, 2, 3
-RECORD, ASYNC = 1, 2
+RECORD, ASYNC, PROFILE = 1, 2, 4
 
 MODES = {"shared": SHARED, "independent": INDEPENDENT, "topk": TOPK}
 DTYPES = {"f64": F64, "f32": F32, "bf16": BF16, "fp8": FP8_E4M3}
@@ -38,7 +38,8 @@ MODELS = {"site": ISING_SITE, "vertex": ISING_SITE, "plaquette": ISING_PLAQUETTE
 
 EXPORTED = ("mctrg_init_tensor", "mctrg_tensor_set_info", "mctrg_default_config", "mctrg_capacity_dim",
             "mctrg_run_samples", "mctrg_estimate_lnZ", "mctrg_destroy", "mctrg_status_string",
-            "mctrg_svd_batched", "mctrg_sample_batched", "mctrg_contract_batched")
+            "mctrg_svd_batched", "mctrg_sample_batched", "mctrg_contract_batched", "mctrg_chain_create",
+            "mctrg_chain_step", "mctrg_chain_finish", "mctrg_chain_get_profile", "mctrg_chain_destroy")
 
 
 class RunConfig(ctypes.Structure):
@@ -52,6 +53,14 @@ class Estimate(ctypes.Structure):
     _fields_ = [("ln_meanZ_per_site", ctypes.c_double), ("rel_stderr_Z", ctypes.c_double),
                 ("mean_lnZ_per_site", ctypes.c_double), ("stderr_mean_lnZ", ctypes.c_double),
                 ("n_used", ctypes.c_int64), ("n_negative", ctypes.c_int64), ("n_failed", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class ChainProfile(ctypes.Structure):
+    _fields_ = [("jacobi_ms", ctypes.c_double), ("jacobi_launches", ctypes.c_int64), ("gemm_ms", ctypes.c_double),
+                ("gemm_launches", ctypes.c_int64), ("steps_done", ctypes.c_int32), ("last_sweeps", ctypes.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -80,6 +89,16 @@ _lib.mctrg_sample_batched.argtypes = [_i64, _i32, _i32, _i32, _u64, _f64, _vp, _
 _lib.mctrg_sample_batched.restype = ctypes.c_int
 _lib.mctrg_contract_batched.argtypes = [_i64, _i32, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp]
 _lib.mctrg_contract_batched.restype = ctypes.c_int
+_lib.mctrg_chain_create.argtypes = [_vp, ctypes.POINTER(RunConfig), _i64, _vp, _vp, ctypes.POINTER(_vp)]
+_lib.mctrg_chain_create.restype = ctypes.c_int
+_lib.mctrg_chain_step.argtypes = [_vp, _i32]
+_lib.mctrg_chain_step.restype = ctypes.c_int
+_lib.mctrg_chain_finish.argtypes = [_vp, _vp, _vp, _vp]
+_lib.mctrg_chain_finish.restype = ctypes.c_int
+_lib.mctrg_chain_get_profile.argtypes = [_vp, ctypes.POINTER(ChainProfile)]
+_lib.mctrg_chain_get_profile.restype = ctypes.c_int
+_lib.mctrg_chain_destroy.argtypes = [_vp]
+_lib.mctrg_chain_destroy.restype = None
 
 
 class MctrgError(RuntimeError):
@@ -303,3 +322,54 @@ def contract_batched(GA, GB, FA, FB, dtype="f64"):
     _check(_lib.mctrg_contract_batched(nj, D, kk, dt, _ptr(GA), _ptr(GB), _ptr(FA), _ptr(FB), _ptr(out),
                                        _stream(torch)), "mctrg_contract_batched")
     return out
+
+
+class Chain:
+    """mctrg_chain_*: one wave of samples advanced step by step."""
+
+    def __init__(self, ts: TensorSet, n_samples: int, *, n_steps: int, k: int, mode="shared", dtype="f64",
+                 seed: int = 0, sample_offset: int = 0, tau_null: float = 1e-11, groups=None, profile=False):
+        import numpy as np
+        torch = _torch()
+        cfg = default_config()
+        cfg.seed, cfg.sample_offset, cfg.n_steps, cfg.k = seed, sample_offset, n_steps, k
+        cfg.mode = MODES[mode] if isinstance(mode, str) else int(mode)
+        cfg.contract_dtype = DTYPES[dtype] if isinstance(dtype, str) else int(dtype)
+        cfg.tau_null = tau_null
+        if profile:
+            cfg.flags |= PROFILE
+        g = None if groups is None else np.ascontiguousarray(groups, dtype=np.int32)
+        self._ts = ts
+        self.n_samples, self.n_steps = n_samples, n_steps
+        self._h = ctypes.c_void_p()
+        _check(_lib.mctrg_chain_create(ts.handle, ctypes.byref(cfg), n_samples,
+                                       None if g is None else g.ctypes.data_as(ctypes.c_void_p),
+                                       _stream(torch), ctypes.byref(self._h)), "mctrg_chain_create")
+
+    def step(self, n: int = 1):
+        _check(_lib.mctrg_chain_step(self._h, n), "mctrg_chain_step")
+
+    def finish(self, want_ln_c=False):
+        torch = _torch()
+        dev = torch.device("cuda", torch.cuda.current_device())
+        sign = torch.empty(self.n_samples, dtype=torch.int8, device=dev)
+        ln = torch.empty(self.n_samples, dtype=torch.float64, device=dev)
+        lnc = torch.zeros((self.n_samples, self.n_steps), dtype=torch.float64, device=dev) if want_ln_c else None
+        _check(_lib.mctrg_chain_finish(self._h, _ptr(sign), _ptr(ln), _ptr(lnc)), "mctrg_chain_finish")
+        return SampleResult(sign, ln, lnc, OK)
+
+    def profile(self) -> dict:
+        p = ChainProfile()
+        _check(_lib.mctrg_chain_get_profile(self._h, ctypes.byref(p)), "mctrg_chain_get_profile")
+        return p.as_dict()
+
+    def close(self):
+        if self._h and self._h.value:
+            _lib.mctrg_chain_destroy(self._h)
+            self._h = ctypes.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -171,6 +171,8 @@ struct Chain {
   int32_t *h_src = nullptr, *h_split = nullptr, *h_cjobs = nullptr;
   uint64_t* h_rng = nullptr;
   int64_t max_jobs = 0, max_out = 0;
+  KernelTimer tj, tg;
+  int last_sweeps = 0;
 
   ~Chain() {
     if (mem) (void)hipFree(mem);
@@ -340,7 +342,9 @@ int chain_start(Chain& c, const mctrg_tensor_set* ts, const std::vector<int32_t>
     CKH(launch_gather_tensors(c.nsamp * P0, ts->d0, ts->T0, dg2, c.Ta, c.st));
   }
   CKH(launch_izero(c.nsamp, c.failed, c.st));
+  CKH(hipMemsetAsync(c.lnc_steps, 0, sizeof(double) * c.nsamp * c.n_steps, c.st));
   CKH(hipStreamSynchronize(c.st));
+  c.tj.enabled = c.tg.enabled = (c.flags & MCTRG_PROFILE) != 0;
   return MCTRG_OK;
 }
 
@@ -388,7 +392,7 @@ int chain_step(Chain& c) {
   CKH(hipMemcpyAsync(c.cjobs, c.h_cjobs, 4 * no * sizeof(int32_t), hipMemcpyHostToDevice, c.st));
 
   CKH(launch_unfold(nj, sh.D, sh.n_pad, c.Ta, c.src, c.split, c.W, c.st));
-  CKH(run_jacobi(nj, sh.n_pad, c.W, c.jw, kMaxSweeps, c.st));
+  CKH(run_jacobi(nj, sh.n_pad, c.W, c.jw, kMaxSweeps, c.st, c.tj.enabled ? &c.tj : nullptr, &c.last_sweeps));
   CKH(launch_jacobi_fail(nj, sh.jps, c.jw.sweeps, c.failed, c.st));
   CKH(launch_jacobi_finalize(nj, sh.n, sh.n_pad, c.W, c.sigma, c.order, c.st));
   SampleArgs sa{};
@@ -405,19 +409,24 @@ int chain_step(Chain& c) {
   ca.GA = c.G; ca.GB = c.G; ca.FA = c.F; ca.FB = c.F;
   ca.g_stride = (int64_t)sh.kc * sh.n; ca.f_stride = (int64_t)sh.n * sh.kc;
   ca.jobs = c.cjobs; ca.X = c.X; ca.Y = c.Y; ca.Xlp = c.Xlp; ca.Ylp = c.Ylp; ca.scales = c.scales; ca.Tout = c.Tn;
-  CKH(launch_contract(ca, c.st));
+  CKH(launch_contract(ca, c.st, c.tg.enabled ? &c.tg : nullptr));
   const int64_t K4 = (int64_t)sh.kc * sh.kc * sh.kc * sh.kc;
   CKH(launch_normalize(no, K4, c.dtype != MCTRG_F64, c.Tn, c.scales, c.cbuf, c.Tb, c.lnc, c.st));
   CKH(launch_lnc_accum(c.nsamp, sh.ops, s, c.n_steps, c.lnc, c.lnc_steps, c.failed, c.st));
   std::swap(c.Ta, c.Tb);
   c.step++;
+  if (c.tg.enabled) {
+    CKH(hipStreamSynchronize(c.st));
+    CKH(c.tg.collect());
+  }
   return MCTRG_OK;
 }
 
 int chain_finish(Chain& c, int8_t* out_sign, double* out_ln, double* out_lnc, double* out_tensor) {
-  const int Df = c.Dsched[c.n_steps];
-  CKH(launch_trace(c.nsamp, Df, c.Ta, c.lnc_steps, c.n_steps, c.mode != MCTRG_INDEPENDENT, c.failed, c.sign,
-                   c.lnabs, c.st));
+  const int Df = c.Dsched[c.step];
+  if (c.mode == MCTRG_INDEPENDENT && c.step != c.n_steps) return MCTRG_EINVAL;
+  CKH(launch_trace(c.nsamp, Df, c.Ta, c.lnc_steps, c.n_steps, c.step, c.mode != MCTRG_INDEPENDENT, c.failed,
+                   c.sign, c.lnabs, c.st));
   CKH(launch_scatter(c.nsamp, c.n_steps, c.idx, c.sign, c.lnabs, c.lnc_steps, out_sign, out_ln, out_lnc, c.st));
   if (out_tensor) {
     const size_t per = (size_t)Df * Df * Df * Df;
@@ -647,6 +656,74 @@ int mctrg_run_samples(mctrg_tensor_set* ts, const mctrg_run_config* cfg, int64_t
   }
   return any_fail ? MCTRG_ENUMERIC : MCTRG_OK;
 }
+
+struct mctrg_chain {
+  Chain c;
+};
+
+int mctrg_chain_create(mctrg_tensor_set* ts, const mctrg_run_config* cfg, int64_t n_samples,
+                       const int32_t* group_of_sample, void* hip_stream, mctrg_chain** out) {
+  if (!ts || !out) return MCTRG_EINVAL;
+  int rc = validate_config(cfg);
+  if (rc != MCTRG_OK) return rc;
+  if (n_samples < 1 || n_samples > (int64_t)1 << 31) return MCTRG_EINVAL;
+  if (group_of_sample)
+    for (int64_t i = 0; i < n_samples; ++i)
+      if (group_of_sample[i] < 0 || group_of_sample[i] >= ts->ngroups) return MCTRG_EINVAL;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev != ts->device) return MCTRG_EINVAL;
+  mctrg_chain* ch = new (std::nothrow) mctrg_chain();
+  if (!ch) return MCTRG_ENOMEM;
+  Chain& c = ch->c;
+  c.st = reinterpret_cast<hipStream_t>(hip_stream);
+  c.mode = cfg->mode; c.dtype = cfg->contract_dtype; c.k = cfg->k; c.n_steps = cfg->n_steps;
+  c.tau = cfg->tau_null; c.seed = cfg->seed; c.flags = cfg->flags & MCTRG_PROFILE; c.record = nullptr;
+  c.kmax_rec = cfg->k;
+  c.Dsched = schedule(ts->d0, cfg->k, cfg->n_steps);
+  if (c.mode == MCTRG_INDEPENDENT && build_levels(c) != MCTRG_OK) { delete ch; return MCTRG_EINVAL; }
+  c.nsamp = n_samples;
+  std::vector<int32_t> groups(n_samples);
+  std::vector<int64_t> out_index(n_samples);
+  for (int64_t i = 0; i < n_samples; ++i) {
+    groups[i] = group_of_sample ? group_of_sample[i] : 0;
+    out_index[i] = i;
+    c.sids.push_back(cfg->sample_offset + i);
+  }
+  rc = chain_start(c, ts, groups, out_index);
+  if (rc != MCTRG_OK) { delete ch; return rc; }
+  *out = ch;
+  return MCTRG_OK;
+}
+
+int mctrg_chain_step(mctrg_chain* ch, int32_t n) {
+  if (!ch || n < 0 || ch->c.step + n > ch->c.n_steps) return MCTRG_EINVAL;
+  for (int i = 0; i < n; ++i) {
+    int rc = chain_step(ch->c);
+    if (rc != MCTRG_OK) return rc;
+  }
+  return MCTRG_OK;
+}
+
+int mctrg_chain_finish(mctrg_chain* ch, int8_t* out_sign, double* out_ln_abs_Z, double* out_ln_c) {
+  if (!ch || !out_sign || !out_ln_abs_Z) return MCTRG_EINVAL;
+  int rc = chain_finish(ch->c, out_sign, out_ln_abs_Z, out_ln_c, nullptr);
+  if (rc != MCTRG_OK) return rc;
+  if (hipStreamSynchronize(ch->c.st) != hipSuccess) return MCTRG_EDEVICE;
+  return MCTRG_OK;
+}
+
+int mctrg_chain_get_profile(const mctrg_chain* ch, mctrg_chain_profile* out) {
+  if (!ch || !out) return MCTRG_EINVAL;
+  out->jacobi_ms = ch->c.tj.ms;
+  out->jacobi_launches = ch->c.tj.launches;
+  out->gemm_ms = ch->c.tg.ms;
+  out->gemm_launches = ch->c.tg.launches;
+  out->steps_done = ch->c.step;
+  out->last_sweeps = ch->c.last_sweeps;
+  return MCTRG_OK;
+}
+
+void mctrg_chain_destroy(mctrg_chain* ch) { delete ch; }
 
 int mctrg_estimate_lnZ(int64_t n_samples, const int8_t* sign, const double* ln_abs_Z, double n_sites,
                        mctrg_estimate* out, void* hip_stream) {

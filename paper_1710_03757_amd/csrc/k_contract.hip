@@ -262,7 +262,7 @@ static size_t elt_bytes(int dt) {
   return dt == MCTRG_F64 ? 8 : dt == MCTRG_F32 ? 4 : dt == MCTRG_BF16 ? 2 : 1;
 }
 
-hipError_t launch_contract(const ContractArgs& a, hipStream_t stream) {
+hipError_t launch_contract(const ContractArgs& a, hipStream_t stream, KernelTimer* gt) {
   if (a.nout == 0) return hipSuccess;
   const int D = a.D, kk = a.kk, DD = D * D, MM = kk * kk;
   const size_t sh = (size_t)2 * D * (D + 1) * sizeof(double);
@@ -275,8 +275,10 @@ hipError_t launch_contract(const ContractArgs& a, hipStream_t stream) {
   dim3 gg(ceil_div(MM, 64), ceil_div(MM, 64), (unsigned)a.nout);
   if (a.dtype == MCTRG_F64) {
     hipLaunchKernelGGL(fill_kernel, dim3(ceil_div(2 * a.nout, 256)), dim3(256), 0, stream, 2 * a.nout, a.scales, 1.0);
+    if (gt) gt->begin(stream);
     hipLaunchKernelGGL(gemm_tn_kernel<MCTRG_F64>, gg, dim3(256), 0, stream, MM, MM, DD, (const void*)a.X,
                        (const void*)a.Y, a.Tout);
+    if (gt) gt->end(stream);
     return hipGetLastError();
   }
   // scales: [o*2 + 0] for X, [o*2 + 1] for Yt
@@ -296,20 +298,26 @@ hipError_t launch_contract(const ContractArgs& a, hipStream_t stream) {
     case MCTRG_F32:
       hipLaunchKernelGGL(cast_kernel<MCTRG_F32>, dim3(gx, (unsigned)a.nout), dim3(256), 0, stream, per, a.X, mxX, a.Xlp);
       hipLaunchKernelGGL(cast_kernel<MCTRG_F32>, dim3(gx, (unsigned)a.nout), dim3(256), 0, stream, per, a.Y, mxY, a.Ylp);
+      if (gt) gt->begin(stream);
       hipLaunchKernelGGL(gemm_tn_kernel<MCTRG_F32>, gg, dim3(256), 0, stream, MM, MM, DD, (const void*)a.Xlp,
                          (const void*)a.Ylp, a.Tout);
+      if (gt) gt->end(stream);
       break;
     case MCTRG_BF16:
       hipLaunchKernelGGL(cast_kernel<MCTRG_BF16>, dim3(gx, (unsigned)a.nout), dim3(256), 0, stream, per, a.X, mxX, a.Xlp);
       hipLaunchKernelGGL(cast_kernel<MCTRG_BF16>, dim3(gx, (unsigned)a.nout), dim3(256), 0, stream, per, a.Y, mxY, a.Ylp);
+      if (gt) gt->begin(stream);
       hipLaunchKernelGGL(gemm_tn_kernel<MCTRG_BF16>, gg, dim3(256), 0, stream, MM, MM, DD, (const void*)a.Xlp,
                          (const void*)a.Ylp, a.Tout);
+      if (gt) gt->end(stream);
       break;
     case MCTRG_FP8_E4M3:
       hipLaunchKernelGGL(cast_kernel<MCTRG_FP8_E4M3>, dim3(gx, (unsigned)a.nout), dim3(256), 0, stream, per, a.X, mxX, a.Xlp);
       hipLaunchKernelGGL(cast_kernel<MCTRG_FP8_E4M3>, dim3(gx, (unsigned)a.nout), dim3(256), 0, stream, per, a.Y, mxY, a.Ylp);
+      if (gt) gt->begin(stream);
       hipLaunchKernelGGL(gemm_tn_kernel<MCTRG_FP8_E4M3>, gg, dim3(256), 0, stream, MM, MM, DD, (const void*)a.Xlp,
                          (const void*)a.Ylp, a.Tout);
+      if (gt) gt->end(stream);
       break;
     default:
       return hipErrorInvalidValue;

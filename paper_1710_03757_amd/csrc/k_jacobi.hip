@@ -235,8 +235,44 @@ __global__ void jacobi_sweep_end_kernel(int64_t njobs, int sweep, int* active, i
 
 __global__ void zero_int_kernel(int* p) { *p = 0; }
 
+hipError_t KernelTimer::begin(hipStream_t s) {
+  if (!enabled) return hipSuccess;
+  if (used + 2 > 2 * 256) {
+    hipError_t e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return e;
+    e = collect();
+    if (e != hipSuccess) return e;
+  }
+  if (ev[used] == nullptr) {
+    hipError_t e = hipEventCreate(&ev[used]);
+    if (e != hipSuccess) return e;
+  }
+  return hipEventRecord(ev[used++], s);
+}
+
+hipError_t KernelTimer::end(hipStream_t s) {
+  if (!enabled) return hipSuccess;
+  if (ev[used] == nullptr) {
+    hipError_t e = hipEventCreate(&ev[used]);
+    if (e != hipSuccess) return e;
+  }
+  return hipEventRecord(ev[used++], s);
+}
+
+hipError_t KernelTimer::collect() {
+  for (int i = 0; i + 1 < used; i += 2) {
+    float t = 0.0f;
+    hipError_t e = hipEventElapsedTime(&t, ev[i], ev[i + 1]);
+    if (e != hipSuccess) return e;
+    ms += t;
+    ++launches;
+  }
+  used = 0;
+  return hipSuccess;
+}
+
 hipError_t run_jacobi(int64_t njobs, int n_pad, double* W, const JacobiWork& wk, int max_sweeps,
-                      hipStream_t stream) {
+                      hipStream_t stream, KernelTimer* timer, int* sweeps_done) {
   if (njobs == 0) return hipSuccess;
   const int nb = n_pad / 16;
   const double tol = fmax(32.0, 8.0 * sqrt((double)n_pad)) * 0x1.0p-53;
@@ -245,8 +281,10 @@ hipError_t run_jacobi(int64_t njobs, int n_pad, double* W, const JacobiWork& wk,
                      wk.sweeps);
   for (int sweep = 0; sweep < max_sweeps; ++sweep) {
     for (int r = 0; r < nb - 1; ++r) {
+      if (timer) { hipError_t e = timer->begin(stream); if (e != hipSuccess) return e; }
       hipLaunchKernelGGL(jacobi_round_kernel, dim3(nb / 2, (unsigned)njobs), dim3(256), 0, stream, W,
                          n_pad, nb, r, wk.active, wk.rotated, tol);
+      if (timer) { hipError_t e = timer->end(stream); if (e != hipSuccess) return e; }
     }
     hipLaunchKernelGGL(zero_int_kernel, dim3(1), dim3(1), 0, stream, wk.counter);
     hipLaunchKernelGGL(jacobi_sweep_end_kernel, dim3(g), dim3(256), 0, stream, njobs, sweep, wk.active,
@@ -255,6 +293,11 @@ hipError_t run_jacobi(int64_t njobs, int n_pad, double* W, const JacobiWork& wk,
     if (e != hipSuccess) return e;
     e = hipStreamSynchronize(stream);
     if (e != hipSuccess) return e;
+    if (timer && timer->enabled) {
+      e = timer->collect();
+      if (e != hipSuccess) return e;
+    }
+    if (sweeps_done) *sweeps_done = sweep + 1;
     if (*wk.counter_host == 0) break;
   }
   return hipGetLastError();

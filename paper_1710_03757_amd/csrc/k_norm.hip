@@ -131,7 +131,7 @@ hipError_t launch_normalize(int64_t nout, int64_t elems, int src_is_f32, const v
 // shared_weights: ln|Z| = sum_s 2^(n_steps-s-1) lnc[s] + ln|tr|; otherwise the
 // per-step values are already summed over the level's tensors.
 __global__ void trace_kernel(int64_t nsamp, int D, const double* __restrict__ T, const double* __restrict__ lnc,
-                             int n_steps, int shared_weights, const int* __restrict__ failed,
+                             int lnc_stride, int n_steps, int shared_weights, const int* __restrict__ failed,
                              int8_t* __restrict__ sign, double* __restrict__ ln_abs) {
   const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (s >= nsamp) return;
@@ -143,7 +143,7 @@ __global__ void trace_kernel(int64_t nsamp, int D, const double* __restrict__ T,
   double acc = 0.0;
   for (int st = 0; st < n_steps; ++st) {
     const double w = shared_weights ? ldexp(1.0, n_steps - st - 1) : 1.0;
-    acc += w * lnc[(size_t)s * n_steps + st];
+    acc += w * lnc[(size_t)s * lnc_stride + st];
   }
   const bool bad = failed[s] || !isfinite(acc) || !(tr != 0.0) || !isfinite(tr);
   if (bad) {
@@ -155,12 +155,12 @@ __global__ void trace_kernel(int64_t nsamp, int D, const double* __restrict__ T,
   }
 }
 
-hipError_t launch_trace(int64_t nsamp, int D, const double* T, const double* lnc_steps, int n_steps,
-                        int shared_weights, const int* failed, int8_t* sign, double* ln_abs_Z,
+hipError_t launch_trace(int64_t nsamp, int D, const double* T, const double* lnc_steps, int lnc_stride,
+                        int n_steps, int shared_weights, const int* failed, int8_t* sign, double* ln_abs_Z,
                         hipStream_t stream) {
   if (nsamp == 0) return hipSuccess;
   hipLaunchKernelGGL(trace_kernel, dim3(ceil_div(nsamp, 128)), dim3(128), 0, stream, nsamp, D, T, lnc_steps,
-                     n_steps, shared_weights, failed, sign, ln_abs_Z);
+                     lnc_stride, n_steps, shared_weights, failed, sign, ln_abs_Z);
   return hipGetLastError();
 }
 

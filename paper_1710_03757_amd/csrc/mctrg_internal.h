@@ -84,6 +84,24 @@ hipError_t launch_gather_tensors(int64_t nsamp, int d0, const double* T0, const 
 hipError_t launch_unfold(int64_t njobs, int D, int n_pad, const double* T, const int32_t* src,
                          const int32_t* split, double* W, hipStream_t stream);
 
+// Optional per-kernel timing with HIP events (profiling runs only): each
+// timed launch is bracketed by an event pair on its stream; elapsed times
+// are collected after the next host synchronisation.
+struct KernelTimer {
+  double ms = 0.0;
+  int64_t launches = 0;
+  hipEvent_t ev[2 * 256] = {};
+  int used = 0;
+  bool enabled = false;
+  ~KernelTimer() {
+    for (auto& e : ev)
+      if (e) (void)hipEventDestroy(e);
+  }
+  hipError_t begin(hipStream_t s);
+  hipError_t end(hipStream_t s);
+  hipError_t collect();   // call after the stream has been synchronised
+};
+
 // One-sided block Jacobi SVD of W[j] (rows are rotated).  Host-driven sweeps.
 struct JacobiWork {
   int* active;      // njobs
@@ -93,7 +111,7 @@ struct JacobiWork {
   int* counter_host; // pinned host 1 int
 };
 hipError_t run_jacobi(int64_t njobs, int n_pad, double* W, const JacobiWork& wk, int max_sweeps,
-                      hipStream_t stream);
+                      hipStream_t stream, KernelTimer* timer = nullptr, int* sweeps_done = nullptr);
 // Norms of the rotated rows, sorted descending: sigma[j][0..n), order[j][0..n).
 hipError_t launch_jacobi_finalize(int64_t njobs, int n, int n_pad, const double* W, double* sigma,
                                   int32_t* order, hipStream_t stream);
@@ -140,7 +158,7 @@ struct ContractArgs {
   double* scales;          // nout * 2
   void* Tout;              // nout * kk^4, FP64 (dtype F64) or FP32 (others)
 };
-hipError_t launch_contract(const ContractArgs& a, hipStream_t stream);
+hipError_t launch_contract(const ContractArgs& a, hipStream_t stream, KernelTimer* gemm_timer = nullptr);
 
 // T_out = C / (scale_X * scale_Y) in FP64 (C FP64 or FP32).
 hipError_t launch_unscale(int64_t nout, int64_t elems, int src_is_f32, const void* C, const double* scales,
@@ -156,8 +174,8 @@ hipError_t launch_normalize(int64_t nout, int64_t elems, int src_is_f32, const v
                             hipStream_t stream);
 
 // Final trace and per-sample ln|Z~|.
-hipError_t launch_trace(int64_t nsamp, int D, const double* T, const double* lnc_steps, int n_steps,
-                        int shared_weights, const int* failed, int8_t* sign, double* ln_abs_Z,
+hipError_t launch_trace(int64_t nsamp, int D, const double* T, const double* lnc_steps, int lnc_stride,
+                        int n_steps, int shared_weights, const int* failed, int8_t* sign, double* ln_abs_Z,
                         hipStream_t stream);
 
 // Estimator (single workgroup, deterministic order).

@@ -187,3 +187,25 @@ def test_argument_errors_leave_outputs():
     assert np.all(sign.cpu().numpy() == 7) and np.all(ln.cpu().numpy() == 3.5)
     r = m.run_samples(ts, 0, n_steps=4, k=4)
     assert r.status == m.OK
+
+
+def test_chain_api_matches_run_samples():
+    torch, m = need_gpu()
+    log("chain api")
+    ts = m.init_tensor("site", [0.42], [0.05])
+    a = m.run_samples(ts, 5, n_steps=7, k=6, seed=9, want_ln_c=True)
+    ch = m.Chain(ts, 5, n_steps=7, k=6, seed=9, profile=True)
+    ch.step(3)
+    ch.step(4)
+    b = ch.finish(want_ln_c=True)
+    prof = ch.profile()
+    assert prof["steps_done"] == 7 and prof["jacobi_launches"] > 0 and prof["gemm_launches"] == 7
+    assert np.array_equal(a.ln_abs_Z.cpu().numpy(), b.ln_abs_Z.cpu().numpy())
+    assert np.array_equal(a.ln_c.cpu().numpy(), b.ln_c.cpu().numpy())
+    # a partial chain traces the 2^s-site lattice: compare with the oracle
+    ch2 = m.Chain(ts, 2, n_steps=7, k=6, seed=9)
+    ch2.step(4)
+    p = ch2.finish()
+    for i in range(2):
+        o = trg.run_shared(ising.site_tensor(0.42, 0.05), 4, 6, 9, i)
+        assert abs(p.ln_abs_Z.cpu().numpy()[i] - o.ln_abs_Z) / 16 < 1e-12
