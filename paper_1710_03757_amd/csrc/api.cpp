@@ -159,6 +159,8 @@ struct Chain {
          *weight = nullptr, *sscr = nullptr, *G = nullptr, *F = nullptr, *X = nullptr, *Y = nullptr,
          *scales = nullptr, *cbuf = nullptr, *lnc = nullptr, *lnc_steps = nullptr, *lnabs = nullptr;
   void *Xlp = nullptr, *Ylp = nullptr;
+  double *S = nullptr, *Tws = nullptr;
+  int32_t* perm = nullptr;
   int32_t *order = nullptr, *kept = nullptr, *cand = nullptr, *sel = nullptr, *src = nullptr, *split = nullptr,
           *cjobs = nullptr;
   uint64_t* rng = nullptr;
@@ -225,6 +227,9 @@ void layout(Chain& c, Arena& ar) {
   c.Tb = ar.take<double>(tmax);
   c.Tn = ar.take<double>(tnmax);
   c.W = ar.take<double>(wmax);
+  c.S = ar.take<double>(wmax);
+  c.Tws = ar.take<double>((size_t)jmax * 1024);
+  c.perm = ar.take<int32_t>((size_t)jmax * 4096);
   c.sigma = ar.take<double>(nmax);
   c.order = ar.take<int32_t>(nmax);
   c.kept = ar.take<int32_t>(jmax);
@@ -391,7 +396,12 @@ int chain_step(Chain& c) {
   CKH(hipMemcpyAsync(c.rng, c.h_rng, 3 * nj * sizeof(uint64_t), hipMemcpyHostToDevice, c.st));
   CKH(hipMemcpyAsync(c.cjobs, c.h_cjobs, 4 * no * sizeof(int32_t), hipMemcpyHostToDevice, c.st));
 
-  CKH(launch_unfold(nj, sh.D, sh.n_pad, c.Ta, c.src, c.split, c.W, c.st));
+  if (sh.n_pad <= kQrMaxN) {
+    CKH(run_qr_precondition(nj, sh.n, sh.D, sh.n_pad, c.Ta, c.src, c.split, c.perm, c.S, c.Tws, c.W, c.st));
+  } else {
+    CKH(launch_unfold(nj, sh.D, sh.n_pad, c.Ta, c.src, c.split, c.W, c.st));
+    CKH(launch_iota(nj, sh.n_pad, c.perm, c.st));
+  }
   CKH(run_jacobi(nj, sh.n_pad, c.W, c.jw, kMaxSweeps, c.st, c.tj.enabled ? &c.tj : nullptr, &c.last_sweeps));
   CKH(launch_jacobi_fail(nj, sh.jps, c.jw.sweeps, c.failed, c.st));
   CKH(launch_jacobi_finalize(nj, sh.n, sh.n_pad, c.W, c.sigma, c.order, c.st));
@@ -402,7 +412,8 @@ int chain_step(Chain& c) {
   CKH(launch_sample(sa, c.st));
   if ((c.flags & MCTRG_RECORD) && c.record)
     CKH(launch_record(c.nsamp, s, c.n_steps, c.kmax_rec, sh.kc, c.idx, c.cand, c.kept, c.sel, c.record, c.st));
-  CKH(launch_factor_G(nj, sh.D, sh.n_pad, sh.kc, c.W, c.sigma, c.order, c.kept, c.sel, c.weight, c.G, c.st));
+  CKH(launch_factor_G(nj, sh.D, sh.n_pad, sh.kc, c.W, c.sigma, c.order, c.kept, c.sel, c.weight, c.perm, c.G,
+                      c.st));
   CKH(launch_factor_F(nj, sh.D, sh.kc, c.Ta, c.src, c.split, c.sigma, c.kept, c.sel, c.G, c.F, c.st));
   ContractArgs ca{};
   ca.nout = no; ca.D = sh.D; ca.kk = sh.kc; ca.dtype = c.dtype;
@@ -757,26 +768,50 @@ int mctrg_svd_batched(int64_t n_mats, int32_t d1, int32_t d2, const double* M, d
   if (n_mats == 0) return MCTRG_OK;
   hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
   const int n = d1 * d2, n_pad = std::max(32, round_up32(n));
+  const size_t per = (size_t)n_pad * n_pad;
   Arena ar;
-  double* W = ar.take<double>((size_t)n_mats * n_pad * n_pad);
-  int32_t* order = ar.take<int32_t>((size_t)n_mats * n);
-  int* jws = ar.take<int>(3 * n_mats + 1);
+  for (int pass = 0; pass < 2; ++pass) {
+    ar.off = 0;
+    (void)ar.take<double>(n_mats * per);          // W
+    (void)ar.take<double>(n_mats * per);          // S
+    (void)ar.take<double>((size_t)n_mats * 1024); // Tws
+    (void)ar.take<int32_t>((size_t)n_mats * n);   // order
+    (void)ar.take<int32_t>((size_t)n_mats * n_pad);  // perm
+    (void)ar.take<int32_t>(2 * n_mats);           // src, split
+    (void)ar.take<int>(3 * n_mats + 1);           // jacobi work
+    if (pass == 0) break;
+  }
   char* mem = nullptr;
   if (hipMalloc(&mem, ar.off) != hipSuccess) { (void)hipGetLastError(); return MCTRG_ENOMEM; }
   HostPinned pin;
   if (hipHostMalloc(&pin.p, 64, hipHostMallocDefault) != hipSuccess) { (void)hipFree(mem); return MCTRG_ENOMEM; }
   Arena a2;
   a2.base = mem; a2.counting = false;
-  W = a2.take<double>((size_t)n_mats * n_pad * n_pad);
-  order = a2.take<int32_t>((size_t)n_mats * n);
-  jws = a2.take<int>(3 * n_mats + 1);
+  double* W = a2.take<double>(n_mats * per);
+  double* S = a2.take<double>(n_mats * per);
+  double* Tws = a2.take<double>((size_t)n_mats * 1024);
+  int32_t* order = a2.take<int32_t>((size_t)n_mats * n);
+  int32_t* perm = a2.take<int32_t>((size_t)n_mats * n_pad);
+  int32_t* ss = a2.take<int32_t>(2 * n_mats);
+  int* jws = a2.take<int>(3 * n_mats + 1);
+  std::vector<int32_t> hs(2 * n_mats);
+  for (int64_t i = 0; i < n_mats; ++i) { hs[i] = (int32_t)i; hs[n_mats + i] = 2; }
   JacobiWork wk{jws, jws + n_mats, jws + 2 * n_mats, jws + 3 * n_mats, reinterpret_cast<int*>(pin.p)};
   int rc = MCTRG_OK;
-  if (launch_pad_copy(n_mats, n, n_pad, M, W, st) != hipSuccess ||
-      run_jacobi(n_mats, n_pad, W, wk, kMaxSweeps, st) != hipSuccess ||
-      launch_jacobi_finalize(n_mats, n, n_pad, W, sigma_out, order, st) != hipSuccess)
+  if (hipMemcpyAsync(ss, hs.data(), hs.size() * sizeof(int32_t), hipMemcpyHostToDevice, st) != hipSuccess)
     rc = MCTRG_EDEVICE;
-  if (rc == MCTRG_OK && V_out && launch_extract_V(n_mats, n, n_pad, d2, W, sigma_out, order, V_out, st) != hipSuccess)
+  if (rc == MCTRG_OK) {
+    hipError_t e = (n_pad <= kQrMaxN)
+                       ? run_qr_precondition(n_mats, n, 0, n_pad, M, ss, ss + n_mats, perm, S, Tws, W, st)
+                       : (launch_pad_copy(n_mats, n, n_pad, M, W, st) == hipSuccess ? launch_iota(n_mats, n_pad, perm, st)
+                                                                                    : hipErrorUnknown);
+    if (e != hipSuccess) rc = MCTRG_EDEVICE;
+  }
+  if (rc == MCTRG_OK && (run_jacobi(n_mats, n_pad, W, wk, kMaxSweeps, st) != hipSuccess ||
+                         launch_jacobi_finalize(n_mats, n, n_pad, W, sigma_out, order, st) != hipSuccess))
+    rc = MCTRG_EDEVICE;
+  if (rc == MCTRG_OK && V_out &&
+      launch_extract_V(n_mats, n, n_pad, d2, W, sigma_out, order, perm, V_out, st) != hipSuccess)
     rc = MCTRG_EDEVICE;
   if (rc == MCTRG_OK && sweeps_out &&
       hipMemcpyAsync(sweeps_out, wk.sweeps, n_mats * sizeof(int32_t), hipMemcpyDeviceToDevice, st) != hipSuccess)

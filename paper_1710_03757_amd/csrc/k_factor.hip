@@ -59,6 +59,7 @@ __global__ __launch_bounds__(256) void factor_G_kernel(int D, int n_pad, int kca
                                                        const int32_t* __restrict__ kept,
                                                        const int32_t* __restrict__ sel,
                                                        const double* __restrict__ weight,
+                                                       const int32_t* __restrict__ perm,
                                                        double* __restrict__ G) {
   const int a = blockIdx.x;
   const int64_t job = blockIdx.y;
@@ -73,26 +74,31 @@ __global__ __launch_bounds__(256) void factor_G_kernel(int D, int n_pad, int kca
   const double s = sigma[(size_t)job * n + i];
   const double w = weight[job * kcap + a];
   const double* v = W + (size_t)job * n_pad * n_pad + (size_t)row * n_pad;
+  const int32_t* pj = perm + job * n_pad;
   __shared__ double red[4];
   double g = 0.0;
-  for (int e = threadIdx.x; e < n; e += 256) {
-    const int i1 = e / D, i2 = e % D;
-    g += v[e] / (1.0 + (double)i1 + kGolden * (double)i2);
+  // entry c of the Jacobi row belongs to column perm[c] of the unfolding
+  for (int c = threadIdx.x; c < n_pad; c += 256) {
+    const int e = pj[c];
+    if (e < n) g += v[c] / (1.0 + (double)(e / D) + kGolden * (double)(e % D));
   }
   for (int o = 32; o > 0; o >>= 1) g += __shfl_xor(g, o);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = g;
   __syncthreads();
   g = (red[0] + red[1]) + (red[2] + red[3]);
   const double f = (g < 0.0 ? -w : w) / s;
-  for (int e = threadIdx.x; e < n; e += 256) Ga[e] = f * v[e];
+  for (int c = threadIdx.x; c < n_pad; c += 256) {
+    const int e = pj[c];
+    if (e < n) Ga[e] = f * v[c];
+  }
 }
 
 hipError_t launch_factor_G(int64_t njobs, int D, int n_pad, int kcap, const double* W, const double* sigma,
                            const int32_t* order, const int32_t* kept, const int32_t* sel, const double* weight,
-                           double* G, hipStream_t stream) {
+                           const int32_t* perm, double* G, hipStream_t stream) {
   if (njobs == 0) return hipSuccess;
   hipLaunchKernelGGL(factor_G_kernel, dim3(kcap, (unsigned)njobs), dim3(256), 0, stream, D, n_pad, kcap, W, sigma,
-                     order, kept, sel, weight, G);
+                     order, kept, sel, weight, perm, G);
   return hipGetLastError();
 }
 
@@ -171,28 +177,36 @@ hipError_t launch_factor_F(int64_t njobs, int D, int kcap, const double* T, cons
 // with g_j = 1 / (1 + j/d2 + phi * (j % d2)).  One workgroup per (i, matrix).
 __global__ __launch_bounds__(256) void extract_V_kernel(int n, int n_pad, int d2, const double* __restrict__ W,
                                                         const double* __restrict__ sigma,
-                                                        const int32_t* __restrict__ order, double* __restrict__ V) {
+                                                        const int32_t* __restrict__ order,
+                                                        const int32_t* __restrict__ perm, double* __restrict__ V) {
   const int i = blockIdx.x;
   const int64_t m = blockIdx.y;
   const double s = sigma[(size_t)m * n + i];
   const double* v = W + (size_t)m * n_pad * n_pad + (size_t)order[(size_t)m * n + i] * n_pad;
   double* out = V + ((size_t)m * n + i) * n;
+  const int32_t* pj = perm + m * n_pad;
   __shared__ double red[4];
   double g = 0.0;
-  for (int e = threadIdx.x; e < n; e += 256) g += v[e] / (1.0 + (double)(e / d2) + kGolden * (double)(e % d2));
+  for (int c = threadIdx.x; c < n_pad; c += 256) {
+    const int e = pj[c];
+    if (e < n) g += v[c] / (1.0 + (double)(e / d2) + kGolden * (double)(e % d2));
+  }
   for (int o = 32; o > 0; o >>= 1) g += __shfl_xor(g, o);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = g;
   __syncthreads();
   g = (red[0] + red[1]) + (red[2] + red[3]);
   const double f = s > 0.0 ? (g < 0.0 ? -1.0 : 1.0) / s : 0.0;
-  for (int e = threadIdx.x; e < n; e += 256) out[e] = f * v[e];
+  for (int c = threadIdx.x; c < n_pad; c += 256) {
+    const int e = pj[c];
+    if (e < n) out[e] = f * v[c];
+  }
 }
 
 hipError_t launch_extract_V(int64_t nmats, int n, int n_pad, int d2, const double* W, const double* sigma,
-                            const int32_t* order, double* V, hipStream_t stream) {
+                            const int32_t* order, const int32_t* perm, double* V, hipStream_t stream) {
   if (nmats == 0) return hipSuccess;
   hipLaunchKernelGGL(extract_V_kernel, dim3(n, (unsigned)nmats), dim3(256), 0, stream, n, n_pad, d2, W, sigma,
-                     order, V);
+                     order, perm, V);
   return hipGetLastError();
 }
 

@@ -1,0 +1,359 @@
+// QR preconditioning of the decomposition step.
+//
+// One-sided Jacobi converges slowly on the strongly graded TRG unfoldings
+// (tens of sweeps).  Rotating the rows of the triangular factor R of
+// M P = Q R instead (P orders the columns of M by decreasing norm) leaves
+// the right singular vectors unchanged up to P (R = Q^T M P) and cuts the
+// number of sweeps several-fold (preconditioned Jacobi in the sense of
+// Drmac and Veselic).  Only R and P are needed, never Q.
+//
+// Storage: S (n_pad x n_pad per job) holds M P column by column: S[c][r] =
+// M[r][P[c]], so every column is contiguous.  The factorisation is the
+// blocked Householder QR with 32-column panels:
+//   panel kernel     one workgroup per job factors the panel in registers
+//                    (each thread owns up to four rows of the 32 columns),
+//                    leaves the Householder vectors below the diagonal and
+//                    R on and above it, and forms the 32 x 32 triangular T of
+//                    the compact WY form I - V T V^T;
+//   trailing kernel  (job, 64-column tile) workgroups apply
+//                    C <- C - V (T^T (V^T C)) with v_mfma_f64_16x16x4.
+// Finally the rows of R are copied into the Jacobi workspace.
+#include "mctrg_internal.h"
+
+namespace mctrg {
+
+constexpr int QR_MAXQ = 4;   // rows per thread in the panel kernel: n_pad <= 1024
+
+// ---------------------------------------------------------------------------
+// Column norms of M and their descending order (ties by index): P.
+// ---------------------------------------------------------------------------
+// split 0: M_A of a D^4 tensor; 1: M_B; 2: a plain row-major n x n matrix
+__device__ __forceinline__ size_t unfold_idx(int split, int D, int n, int row, int col) {
+  if (split != 1) return (size_t)row * n + col;
+  const int u = row / D, r = row % D, d = col / D, l = col % D;
+  return (((size_t)l * D + u) * D + r) * D + d;
+}
+
+__global__ __launch_bounds__(256) void colnorm_order_kernel(int n, int D, int n_pad, const double* __restrict__ T,
+                                                            const int32_t* __restrict__ src,
+                                                            const int32_t* __restrict__ split,
+                                                            int32_t* __restrict__ perm) {
+  extern __shared__ unsigned char smem[];
+  int P = 1;
+  while (P < n_pad) P <<= 1;
+  double* key = reinterpret_cast<double*>(smem);
+  int* idx = reinterpret_cast<int*>(key + P);
+  const int64_t job = blockIdx.x;
+  const double* Ts = T + (size_t)src[job] * n * n;
+  const int sp = split[job];
+  for (int c = threadIdx.x; c < P; c += 256) {
+    double s = -1.0;
+    if (c < n) {
+      s = 0.0;
+      for (int r = 0; r < n; ++r) {
+        const double v = Ts[unfold_idx(sp, D, n, r, c)];
+        s += v * v;
+      }
+    } else if (c < n_pad) {
+      s = -0.5;
+    }
+    key[c] = s;
+    idx[c] = c;
+  }
+  __syncthreads();
+  for (int size = 2; size <= P; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int t = threadIdx.x; t < P / 2; t += 256) {
+        const int i = 2 * stride * (t / stride) + (t % stride), j = i + stride;
+        const bool up = (i & size) == 0;
+        const double ki = key[i], kj = key[j];
+        const int ii = idx[i], ij = idx[j];
+        const bool i_first = (ki > kj) || (ki == kj && ii < ij);
+        if (up ? !i_first : i_first) { key[i] = kj; key[j] = ki; idx[i] = ij; idx[j] = ii; }
+      }
+      __syncthreads();
+    }
+  }
+  for (int c = threadIdx.x; c < n_pad; c += 256) perm[job * n_pad + c] = idx[c];
+}
+
+// S[c][r] = M[r][perm[c]] (zero outside n x n).
+__global__ void unfold_cols_kernel(int n, int D, int n_pad, const double* __restrict__ T,
+                                   const int32_t* __restrict__ src, const int32_t* __restrict__ split,
+                                   const int32_t* __restrict__ perm, double* __restrict__ S) {
+  const int64_t job = blockIdx.y;
+  const size_t per = (size_t)n_pad * n_pad;
+  const double* Ts = T + (size_t)src[job] * n * n;
+  const int sp = split[job];
+  const int32_t* pj = perm + job * n_pad;
+  double* Sj = S + job * per;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < per; e += (size_t)gridDim.x * blockDim.x) {
+    const int c = (int)(e / n_pad), r = (int)(e % n_pad);
+    const int pc = pj[c];
+    Sj[e] = (r < n && pc < n) ? Ts[unfold_idx(sp, D, n, r, pc)] : 0.0;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Panel factorisation (columns j..j+31, rows j..n_pad-1), one workgroup/job.
+// Thread t owns rows j + t + 256 q, q < QR_MAXQ.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void block_reduce_vec(double* v, int cnt, double (*red)[33], int tid) {
+  // v[0..cnt) per thread -> summed over the 256 threads, result in red[0][..]
+  const int lane = tid & 63, wave = tid >> 6;
+  for (int x = 0; x < cnt; ++x) {
+    double s = v[x];
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+    if (lane == 0) red[wave + 1][x] = s;
+  }
+  __syncthreads();
+  if (tid < cnt) red[0][tid] = (red[1][tid] + red[2][tid]) + (red[3][tid] + red[4][tid]);
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(256) void qr_panel_kernel(int n_pad, int j, double* __restrict__ S,
+                                                       double* __restrict__ Tws) {
+  const int64_t job = blockIdx.x;
+  const int tid = threadIdx.x;
+  double* Sj = S + job * (size_t)n_pad * n_pad;
+  __shared__ double red[5][33];
+  __shared__ double Tm[32][33];
+  __shared__ double sh_alpha, sh_beta, sh_tau;
+
+  double A[QR_MAXQ][32];
+#pragma unroll
+  for (int q = 0; q < QR_MAXQ; ++q) {
+    const int r = j + tid + 256 * q;
+#pragma unroll
+    for (int c = 0; c < 32; ++c) A[q][c] = (r < n_pad) ? Sj[(size_t)(j + c) * n_pad + r] : 0.0;
+  }
+  for (int e = tid; e < 32 * 33; e += 256) Tm[e / 33][e % 33] = 0.0;
+
+  double part[32];
+#pragma unroll
+  for (int i = 0; i < 32; ++i) {
+    const int cj = j + i;
+    // --- Householder vector of column i --------------------------------------
+    double sq = 0.0;
+#pragma unroll
+    for (int q = 0; q < QR_MAXQ; ++q) {
+      const int r = j + tid + 256 * q;
+      if (r > cj && r < n_pad) sq += A[q][i] * A[q][i];
+      if (r == cj) sh_alpha = A[q][i];
+    }
+    part[0] = sq;
+    block_reduce_vec(part, 1, red, tid);
+    const double xn2 = red[0][0];
+    const double alpha = sh_alpha;
+    double beta, tau, scale;
+    if (xn2 == 0.0) {
+      beta = alpha; tau = 0.0; scale = 0.0;
+    } else {
+      beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
+      tau = (beta - alpha) / beta;
+      scale = 1.0 / (alpha - beta);
+    }
+    // v: 1 at r == cj, A * scale below, 0 above; stored in column i
+#pragma unroll
+    for (int q = 0; q < QR_MAXQ; ++q) {
+      const int r = j + tid + 256 * q;
+      if (r > cj) A[q][i] *= scale;
+      else if (r == cj) A[q][i] = beta;   // R diagonal; the implicit 1 is used below
+    }
+    // --- dots: w_c = v^T col_c (c > i), z_m = v_m^T v (m < i) ------------------
+#pragma unroll
+    for (int x = 0; x < 32; ++x) part[x] = 0.0;
+#pragma unroll
+    for (int q = 0; q < QR_MAXQ; ++q) {
+      const int r = j + tid + 256 * q;
+      if (r >= cj && r < n_pad) {
+        const double vr = (r == cj) ? 1.0 : A[q][i];
+#pragma unroll
+        for (int c = 0; c < 32; ++c) {
+          if (c > i) part[c] += vr * A[q][c];
+          else if (c < i) {
+            // v_c at row r: below its diagonal j+c it is stored, at j+c it is 1
+            const double vc = (r > j + c) ? A[q][c] : (r == j + c ? 1.0 : 0.0);
+            part[c] += vr * vc;
+          }
+        }
+      }
+    }
+    block_reduce_vec(part, 32, red, tid);
+    // --- apply H_i to the remaining panel columns ----------------------------
+#pragma unroll
+    for (int q = 0; q < QR_MAXQ; ++q) {
+      const int r = j + tid + 256 * q;
+      if (r >= cj && r < n_pad) {
+        const double vr = (r == cj) ? 1.0 : A[q][i];
+#pragma unroll
+        for (int c = 0; c < 32; ++c)
+          if (c > i) A[q][c] -= tau * red[0][c] * vr;
+      }
+    }
+    // --- T column i: T[0:i, i] = -tau T[0:i, 0:i] z[0:i], T[i][i] = tau --------
+    if (tid < 32) {
+      const int m = tid;
+      if (m < i) {
+        double s = 0.0;
+        for (int p = m; p < i; ++p) s += Tm[m][p] * red[0][p];
+        part[0] = -tau * s;
+      }
+    }
+    __syncthreads();
+    if (tid < i) Tm[tid][i] = part[0];
+    if (tid == 0) Tm[i][i] = tau;
+    __syncthreads();
+  }
+#pragma unroll
+  for (int q = 0; q < QR_MAXQ; ++q) {
+    const int r = j + tid + 256 * q;
+    if (r < n_pad) {
+#pragma unroll
+      for (int c = 0; c < 32; ++c) Sj[(size_t)(j + c) * n_pad + r] = A[q][c];
+    }
+  }
+  double* Tj = Tws + job * 32 * 32;
+  for (int e = tid; e < 1024; e += 256) Tj[e] = Tm[e >> 5][e & 31];
+}
+
+// ---------------------------------------------------------------------------
+// Trailing update of the columns right of the panel: C <- C - V T^T... in the
+// compact WY form H_0 H_1 ... H_31 = I - V T V^T, so Q^T C = C - V T^T V^T C.
+// One workgroup per (job, 64-column tile); wave w owns 16 columns.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double vload(const double* Sj, int n_pad, int j, int i, int r) {
+  // V[r][i]: stored below the diagonal of panel column j+i, 1 on it, 0 above
+  const int d = j + i;
+  if (r > d) return Sj[(size_t)d * n_pad + r];
+  return r == d ? 1.0 : 0.0;
+}
+
+__global__ __launch_bounds__(256) void qr_trailing_kernel(int n_pad, int j, double* __restrict__ S,
+                                                          const double* __restrict__ Tws) {
+  const int64_t job = blockIdx.y;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int lr = lane & 15, lg = lane >> 4;
+  double* Sj = S + job * (size_t)n_pad * n_pad;
+  const int c0w = j + 32 + 64 * blockIdx.x + 16 * wave;   // first column of this wave
+  __shared__ double W1[32][65];
+  __shared__ double Tm[32][33];
+  for (int e = tid; e < 1024; e += 256) Tm[e >> 5][e & 31] = Tws[job * 1024 + e];
+  const bool active = c0w < n_pad;
+
+  // ---- phase 1: W1 = V^T C (32 x 16 per wave) ------------------------------
+  f64x4 acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
+  if (active) {
+    for (int r0 = j; r0 < n_pad; r0 += 16) {
+      const int rb = r0 + 4 * lg;
+      double cv[4], v0[4], v1[4];
+      const double* cp = Sj + (size_t)(c0w + lr) * n_pad + rb;
+#pragma unroll
+      for (int jj = 0; jj < 4; ++jj) {
+        cv[jj] = cp[jj];
+        v0[jj] = vload(Sj, n_pad, j, lr, rb + jj);
+        v1[jj] = vload(Sj, n_pad, j, 16 + lr, rb + jj);
+      }
+#pragma unroll
+      for (int jj = 0; jj < 4; ++jj) {
+        acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(v0[jj], cv[jj], acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(v1[jj], cv[jj], acc1, 0, 0, 0);
+      }
+    }
+  }
+  // acc{0,1}[x]: row i = 16*tile + acc_row_f64(lg, x), column lr of the wave
+#pragma unroll
+  for (int x = 0; x < 4; ++x) {
+    W1[acc_row_f64(lg, x)][16 * wave + lr] = acc0[x];
+    W1[16 + acc_row_f64(lg, x)][16 * wave + lr] = acc1[x];
+  }
+  __syncthreads();
+  // ---- phase 2: W2 = T^T W1 (in place, column by column) -------------------
+  {
+    const int col = tid & 63, i0 = (tid >> 6) * 8;
+    double w2[8];
+#pragma unroll
+    for (int ii = 0; ii < 8; ++ii) {
+      const int i = i0 + ii;
+      double s = 0.0;
+      for (int m = 0; m <= i; ++m) s += Tm[m][i] * W1[m][col];
+      w2[ii] = s;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ii = 0; ii < 8; ++ii) W1[i0 + ii][col] = w2[ii];
+  }
+  __syncthreads();
+  if (!active) return;
+  // ---- phase 3: C <- C - V W2 ------------------------------------------------
+  // output tile C^T[c (16)][r (16)] = sum_i W2^T[c][i] V^T[i][r]
+  double aw[8];
+#pragma unroll
+  for (int ks = 0; ks < 8; ++ks) aw[ks] = W1[4 * ks + lg][16 * wave + lr];
+  for (int r0 = j; r0 < n_pad; r0 += 16) {
+    f64x4 acc = {0, 0, 0, 0};
+#pragma unroll
+    for (int ks = 0; ks < 8; ++ks) {
+      const double bv = vload(Sj, n_pad, j, 4 * ks + lg, r0 + lr);
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(aw[ks], bv, acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int x = 0; x < 4; ++x) {
+      double* p = Sj + (size_t)(c0w + acc_row_f64(lg, x)) * n_pad + r0 + lr;
+      *p -= acc[x];
+    }
+  }
+}
+
+// W[r][c] = R[r][c] = S[c][r] for r <= c, else 0 (rows of R for the Jacobi).
+__global__ void r_rows_kernel(int n_pad, const double* __restrict__ S, double* __restrict__ W) {
+  const int64_t job = blockIdx.z;
+  __shared__ double tile[32][33];
+  const size_t per = (size_t)n_pad * n_pad;
+  const int bx = blockIdx.x * 32, by = blockIdx.y * 32;   // bx: column c block, by: row r block
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8 threads
+  for (int yy = ty; yy < 32; yy += 8) tile[yy][tx] = S[job * per + (size_t)(bx + yy) * n_pad + by + tx];  // [c][r]
+  __syncthreads();
+  for (int yy = ty; yy < 32; yy += 8) {
+    const int r = by + yy, c = bx + tx;
+    W[job * per + (size_t)r * n_pad + c] = (r <= c) ? tile[tx][yy] : 0.0;
+  }
+}
+
+hipError_t run_qr_precondition(int64_t njobs, int n, int D, int n_pad, const double* T, const int32_t* src,
+                               const int32_t* split, int32_t* perm, double* S, double* Tws, double* W,
+                               hipStream_t stream) {
+  if (njobs == 0) return hipSuccess;
+  if (n_pad > 256 * QR_MAXQ) return hipErrorInvalidValue;
+  int P = 1;
+  while (P < n_pad) P <<= 1;
+  hipLaunchKernelGGL(colnorm_order_kernel, dim3((unsigned)njobs), dim3(256), (size_t)P * 12, stream, n, D, n_pad, T,
+                     src, split, perm);
+  const size_t per = (size_t)n_pad * n_pad;
+  int gx = (int)((per + 255) / 256);
+  if (gx > 1024) gx = 1024;
+  hipLaunchKernelGGL(unfold_cols_kernel, dim3(gx, (unsigned)njobs), dim3(256), 0, stream, n, D, n_pad, T, src, split,
+                     perm, S);
+  for (int j = 0; j < n_pad; j += 32) {
+    hipLaunchKernelGGL(qr_panel_kernel, dim3((unsigned)njobs), dim3(256), 0, stream, n_pad, j, S, Tws);
+    const int rest = n_pad - j - 32;
+    if (rest > 0)
+      hipLaunchKernelGGL(qr_trailing_kernel, dim3(ceil_div(rest, 64), (unsigned)njobs), dim3(256), 0, stream, n_pad, j,
+                         S, Tws);
+  }
+  hipLaunchKernelGGL(r_rows_kernel, dim3(n_pad / 32, n_pad / 32, (unsigned)njobs), dim3(256), 0, stream, n_pad, S, W);
+  return hipGetLastError();
+}
+
+__global__ void iota_kernel(int64_t njobs, int n_pad, int32_t* perm) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < njobs * n_pad) perm[i] = (int32_t)(i % n_pad);
+}
+
+hipError_t launch_iota(int64_t njobs, int n_pad, int32_t* perm, hipStream_t stream) {
+  if (njobs == 0) return hipSuccess;
+  hipLaunchKernelGGL(iota_kernel, dim3(ceil_div(njobs * n_pad, 256)), dim3(256), 0, stream, njobs, n_pad, perm);
+  return hipGetLastError();
+}
+
+}  // namespace mctrg

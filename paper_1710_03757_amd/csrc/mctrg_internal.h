@@ -112,6 +112,16 @@ struct JacobiWork {
 };
 hipError_t run_jacobi(int64_t njobs, int n_pad, double* W, const JacobiWork& wk, int max_sweeps,
                       hipStream_t stream, KernelTimer* timer = nullptr, int* sweeps_done = nullptr);
+// QR preconditioning (k_qr.hip): perm[j] (n_pad) orders the columns of the
+// unfolding by decreasing norm, S (n_pad^2 per job) holds M P column-wise
+// and is overwritten by V and R, Tws (1024 per job) is scratch, and W
+// receives the rows of R.  split 2 = plain row-major n x n matrices.
+constexpr int kQrMaxN = 1024;
+hipError_t run_qr_precondition(int64_t njobs, int n, int D, int n_pad, const double* T, const int32_t* src,
+                               const int32_t* split, int32_t* perm, double* S, double* Tws, double* W,
+                               hipStream_t stream);
+hipError_t launch_iota(int64_t njobs, int n_pad, int32_t* perm, hipStream_t stream);
+
 // Norms of the rotated rows, sorted descending: sigma[j][0..n), order[j][0..n).
 hipError_t launch_jacobi_finalize(int64_t njobs, int n, int n_pad, const double* W, double* sigma,
                                   int32_t* order, hipStream_t stream);
@@ -140,7 +150,8 @@ size_t sample_scratch_doubles(int64_t njobs, int n, int k);
 // Factors.  G[j]: kcap x n (row a = w_a v_a), F[j]: n x kcap (col a = w_a u_a).
 hipError_t launch_factor_G(int64_t njobs, int D, int n_pad, int kcap, const double* W,
                            const double* sigma, const int32_t* order, const int32_t* kept,
-                           const int32_t* sel, const double* weight, double* G, hipStream_t stream);
+                           const int32_t* sel, const double* weight, const int32_t* perm, double* G,
+                           hipStream_t stream);
 hipError_t launch_factor_F(int64_t njobs, int D, int kcap, const double* T, const int32_t* src,
                            const int32_t* split, const double* sigma, const int32_t* kept,
                            const int32_t* sel, const double* G, double* F, hipStream_t stream);
@@ -166,7 +177,7 @@ hipError_t launch_unscale(int64_t nout, int64_t elems, int src_is_f32, const voi
 
 // Right singular vectors of the Jacobi result, gauge-fixed (row i of V).
 hipError_t launch_extract_V(int64_t nmats, int n, int n_pad, int d2, const double* W, const double* sigma,
-                            const int32_t* order, double* V, hipStream_t stream);
+                            const int32_t* order, const int32_t* perm, double* V, hipStream_t stream);
 
 // Normalisation: c = max|T'|, T = T'/c, ln c - ln(scales) written to lnc[j].
 hipError_t launch_normalize(int64_t nout, int64_t elems, int src_is_f32, const void* Tp,
