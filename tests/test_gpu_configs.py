@@ -1,0 +1,117 @@
+"""Parity and statistics at the measured configurations' shapes.
+
+C1  16 x 16 torus, k = 8, beta_c, independent mode (the paper's estimator):
+    per-sample parity with the oracle on a subset, and the sample mean of
+    Z~ against Kaufman's exact Z within its standard error (Section III,
+    Eq. infiniteEnsemble; error bars per Section V, Eq. shrunkDev).
+C2  k = 16 shared chains over the beta sweep 0.30..0.60 (16 values): one
+    sample per beta checked against the oracle over 20 steps (2^20 sites).
+C3  mixed k in {16, 24, 32}, beta in [0.35, 0.55], h in {0, 0.05}: samples
+    of every k bucketed in one call, checked against the oracle.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import ising, trg
+from workloads import BETA_C, C2, C3, linspace_inclusive
+
+from gpu_util import log, need_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+def test_c1_independent_parity_subset():
+    torch, m = need_gpu()
+    log("C1 parity subset")
+    ts = m.init_tensor("site", [BETA_C], [0.0])
+    r = m.run_samples(ts, 4, n_steps=8, k=8, mode="independent", seed=0)
+    ln = r.ln_abs_Z.cpu().numpy()
+    T0 = ising.site_tensor(BETA_C)
+    bad = 0
+    for i in range(4):
+        o = trg.run_independent(T0, 8, 8, 0, i)
+        if abs(ln[i] - o.ln_abs_Z) / 256 > 1e-12:
+            bad += 1
+    assert bad <= 1
+
+
+def test_c1_unbiased_against_kaufman():
+    torch, m = need_gpu()
+    log("C1 1000 samples vs Kaufman")
+    ts = m.init_tensor("site", [BETA_C], [0.0])
+    r = m.run_samples(ts, 1000, n_steps=8, k=8, mode="independent", seed=0)
+    assert r.status == m.OK
+    sign = r.sign.cpu().numpy()
+    ln = r.ln_abs_Z.cpu().numpy()
+    lnZ = ising.kaufman_lnZ_torus(16, BETA_C)
+    z = sign * np.exp(ln - lnZ)              # Z~ / Z
+    mean, se = z.mean(), z.std(ddof=1) / math.sqrt(z.size)
+    log(f"C1: mean Z~/Z = {mean:.6f} +- {se:.6f}, per-sample std {z.std(ddof=1):.4f}, negatives {np.sum(sign < 0)}")
+    assert abs(mean - 1.0) < 3.0 * se
+    est = m.estimate_lnZ(r.sign, r.ln_abs_Z, 256.0)
+    assert est["ln_meanZ_per_site"] == pytest.approx(lnZ / 256 + math.log(mean) / 256, abs=1e-12)
+
+
+def test_c2_beta_sweep_parity():
+    torch, m = need_gpu()
+    betas = list(C2.betas)
+    log("C2 beta sweep")
+    ts = m.init_tensor("site", betas, [0.0] * len(betas))
+    groups = list(range(len(betas)))
+    r = m.run_samples(ts, len(betas), n_steps=20, k=16, seed=0, groups=groups, record=True)
+    ln, rec = r.ln_abs_Z.cpu().numpy(), r.record.cpu().numpy()
+    N = 2.0 ** 20
+    flips = 0
+    for i, b in enumerate(betas):
+        o = trg.run_shared(ising.site_tensor(b), 20, 16, 0, i)
+        same = all(
+            list(st.splits[0].sel) == [int(x) for x in rec[i, s, 4:4 + int(rec[i, s, 2])]] and
+            list(st.splits[1].sel) == [int(x) for x in rec[i, s, 4 + 16:4 + 16 + int(rec[i, s, 3])]]
+            for s, st in enumerate(o.records))
+        if not same:
+            flips += 1
+            continue
+        assert abs(ln[i] - o.ln_abs_Z) / N < 1e-12, (b, ln[i] / N, o.ln_abs_Z / N)
+    assert flips <= 2
+
+
+def test_c3_mixed_k_parity():
+    torch, m = need_gpu()
+    log("C3 mixed k")
+    betas = [C3.betas[0], C3.betas[13], C3.betas[31]]
+    hs = [0.0, 0.05, 0.05]
+    ts = m.init_tensor("site", betas, hs)
+    ks = [16, 24, 32, 24, 32, 16]
+    groups = [0, 1, 2, 2, 0, 1]
+    n_steps = 8
+    r = m.run_samples(ts, 6, n_steps=n_steps, k=32, ks=ks, groups=groups, seed=0, dtype="f64", record=True)
+    ln = r.ln_abs_Z.cpu().numpy()
+    rec = r.record.cpu().numpy()
+    N = 2.0 ** n_steps
+    flips = 0
+    for i in range(6):
+        o = trg.run_shared(ising.site_tensor(betas[groups[i]], hs[groups[i]]), n_steps, ks[i], 0, i)
+        same = all(list(st.splits[0].sel) == [int(x) for x in rec[i, s, 4:4 + int(rec[i, s, 2])]]
+                   for s, st in enumerate(o.records))
+        if not same:
+            flips += 1
+            continue
+        assert abs(ln[i] - o.ln_abs_Z) / N < 1e-12
+    assert flips <= 1
+
+
+@pytest.mark.parametrize("dtype,tol", [("f32", 1e-6), ("bf16", 5e-3)])
+def test_low_precision_topk_error(dtype, tol):
+    """Top-k chains are deterministic, so a narrow contraction dtype can be
+    compared paired with FP64: |d ln Z|/site stays within a bound set by the
+    dtype's unit roundoff."""
+    torch, m = need_gpu()
+    log(f"precision {dtype}")
+    ts = m.init_tensor("site", [BETA_C], [0.0])
+    a = m.run_samples(ts, 1, n_steps=12, k=16, mode="topk", dtype="f64").ln_abs_Z.cpu().numpy()
+    b = m.run_samples(ts, 1, n_steps=12, k=16, mode="topk", dtype=dtype).ln_abs_Z.cpu().numpy()
+    err = abs(a[0] - b[0]) / 2.0 ** 12
+    log(f"topk k=16 {dtype}: |d lnZ|/site = {err:.3e}")
+    assert err < tol
