@@ -159,7 +159,7 @@ struct Chain {
          *weight = nullptr, *sscr = nullptr, *G = nullptr, *F = nullptr, *X = nullptr, *Y = nullptr,
          *scales = nullptr, *cbuf = nullptr, *lnc = nullptr, *lnc_steps = nullptr, *lnabs = nullptr;
   void *Xlp = nullptr, *Ylp = nullptr;
-  double *S = nullptr, *Tws = nullptr;
+  double *S = nullptr, *Tws = nullptr, *W2 = nullptr, *Tws2 = nullptr;
   int32_t* perm = nullptr;
   int32_t *order = nullptr, *kept = nullptr, *cand = nullptr, *sel = nullptr, *src = nullptr, *split = nullptr,
           *cjobs = nullptr;
@@ -228,7 +228,9 @@ void layout(Chain& c, Arena& ar) {
   c.Tn = ar.take<double>(tnmax);
   c.W = ar.take<double>(wmax);
   c.S = ar.take<double>(wmax);
-  c.Tws = ar.take<double>((size_t)jmax * 1024);
+  c.W2 = ar.take<double>(wmax);
+  c.Tws = ar.take<double>((size_t)jmax * 32 * 1024);
+  c.Tws2 = ar.take<double>((size_t)jmax * 1024);
   c.perm = ar.take<int32_t>((size_t)jmax * 4096);
   c.sigma = ar.take<double>(nmax);
   c.order = ar.take<int32_t>(nmax);
@@ -396,15 +398,20 @@ int chain_step(Chain& c) {
   CKH(hipMemcpyAsync(c.rng, c.h_rng, 3 * nj * sizeof(uint64_t), hipMemcpyHostToDevice, c.st));
   CKH(hipMemcpyAsync(c.cjobs, c.h_cjobs, 4 * no * sizeof(int32_t), hipMemcpyHostToDevice, c.st));
 
-  if (sh.n_pad <= kQrMaxN) {
-    CKH(run_qr_precondition(nj, sh.n, sh.D, sh.n_pad, c.Ta, c.src, c.split, c.perm, c.S, c.Tws, c.W, c.st));
+  // decomposition: two QRs then Jacobi on the rows of R2 (n_pad <= 1024);
+  // larger unfoldings go straight to Jacobi
+  const bool qr2 = sh.n_pad <= kQrMaxN;
+  double* Wj = qr2 ? c.W2 : c.W;
+  if (qr2) {
+    CKH(run_qr2_precondition(nj, sh.n, sh.D, sh.n_pad, c.Ta, c.src, c.split, c.perm, c.S, c.Tws, c.W, c.Tws2, c.W2,
+                             c.st));
   } else {
     CKH(launch_unfold(nj, sh.D, sh.n_pad, c.Ta, c.src, c.split, c.W, c.st));
     CKH(launch_iota(nj, sh.n_pad, c.perm, c.st));
   }
-  CKH(run_jacobi(nj, sh.n_pad, c.W, c.jw, kMaxSweeps, c.st, c.tj.enabled ? &c.tj : nullptr, &c.last_sweeps));
+  CKH(run_jacobi(nj, sh.n_pad, Wj, c.jw, kMaxSweeps, c.st, c.tj.enabled ? &c.tj : nullptr, &c.last_sweeps));
   CKH(launch_jacobi_fail(nj, sh.jps, c.jw.sweeps, c.failed, c.st));
-  CKH(launch_jacobi_finalize(nj, sh.n, sh.n_pad, c.W, c.sigma, c.order, c.st));
+  CKH(launch_jacobi_finalize(nj, sh.n, sh.n_pad, Wj, c.sigma, c.order, c.st));
   SampleArgs sa{};
   sa.njobs = nj; sa.n = sh.n; sa.k = sh.kc; sa.mode = c.mode; sa.seed = c.seed; sa.tau = c.tau;
   sa.sigma = c.sigma; sa.rng = c.rng; sa.split = c.split; sa.kept = c.kept; sa.cand = c.cand;
@@ -412,9 +419,15 @@ int chain_step(Chain& c) {
   CKH(launch_sample(sa, c.st));
   if ((c.flags & MCTRG_RECORD) && c.record)
     CKH(launch_record(c.nsamp, s, c.n_steps, c.kmax_rec, sh.kc, c.idx, c.cand, c.kept, c.sel, c.record, c.st));
-  CKH(launch_factor_G(nj, sh.D, sh.n_pad, sh.kc, c.W, c.sigma, c.order, c.kept, c.sel, c.weight, c.perm, c.G,
-                      c.st));
-  CKH(launch_factor_F(nj, sh.D, sh.kc, c.Ta, c.src, c.split, c.sigma, c.kept, c.sel, c.G, c.F, c.st));
+  if (qr2) {
+    CKH(launch_apply_q1(nj, sh.n, sh.n_pad, sh.kc, c.S, c.Tws, c.W2, c.sigma, c.order, c.kept, c.sel, c.weight, c.F,
+                        c.st));
+    CKH(launch_factor_G_from_F(nj, sh.D, sh.kc, c.Ta, c.src, c.split, c.sigma, c.kept, c.sel, c.F, c.G, c.st));
+  } else {
+    CKH(launch_factor_G(nj, sh.D, sh.n_pad, sh.kc, c.W, c.sigma, c.order, c.kept, c.sel, c.weight, c.perm, c.G,
+                        c.st));
+    CKH(launch_factor_F(nj, sh.D, sh.kc, c.Ta, c.src, c.split, c.sigma, c.kept, c.sel, c.G, c.F, c.st));
+  }
   ContractArgs ca{};
   ca.nout = no; ca.D = sh.D; ca.kk = sh.kc; ca.dtype = c.dtype;
   ca.GA = c.G; ca.GB = c.G; ca.FA = c.F; ca.FB = c.F;

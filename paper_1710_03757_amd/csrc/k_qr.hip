@@ -112,7 +112,7 @@ __device__ __forceinline__ void block_reduce_vec(double* v, int cnt, double (*re
 }
 
 __global__ __launch_bounds__(256) void qr_panel_kernel(int n_pad, int j, double* __restrict__ S,
-                                                       double* __restrict__ Tws) {
+                                                       double* __restrict__ Tws, int64_t t_stride, int t_off) {
   const int64_t job = blockIdx.x;
   const int tid = threadIdx.x;
   double* Sj = S + job * (size_t)n_pad * n_pad;
@@ -213,7 +213,7 @@ __global__ __launch_bounds__(256) void qr_panel_kernel(int n_pad, int j, double*
       for (int c = 0; c < 32; ++c) Sj[(size_t)(j + c) * n_pad + r] = A[q][c];
     }
   }
-  double* Tj = Tws + job * 32 * 32;
+  double* Tj = Tws + job * t_stride + t_off;
   for (int e = tid; e < 1024; e += 256) Tj[e] = Tm[e >> 5][e & 31];
 }
 
@@ -230,7 +230,8 @@ __device__ __forceinline__ double vload(const double* Sj, int n_pad, int j, int 
 }
 
 __global__ __launch_bounds__(256) void qr_trailing_kernel(int n_pad, int j, double* __restrict__ S,
-                                                          const double* __restrict__ Tws) {
+                                                          const double* __restrict__ Tws, int64_t t_stride,
+                                                          int t_off) {
   const int64_t job = blockIdx.y;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int lr = lane & 15, lg = lane >> 4;
@@ -238,7 +239,7 @@ __global__ __launch_bounds__(256) void qr_trailing_kernel(int n_pad, int j, doub
   const int c0w = j + 32 + 64 * blockIdx.x + 16 * wave;   // first column of this wave
   __shared__ double W1[32][65];
   __shared__ double Tm[32][33];
-  for (int e = tid; e < 1024; e += 256) Tm[e >> 5][e & 31] = Tws[job * 1024 + e];
+  for (int e = tid; e < 1024; e += 256) Tm[e >> 5][e & 31] = Tws[job * t_stride + t_off + e];
   const bool active = c0w < n_pad;
 
   // ---- phase 1: W1 = V^T C (32 x 16 per wave) ------------------------------
@@ -320,11 +321,25 @@ __global__ void r_rows_kernel(int n_pad, const double* __restrict__ S, double* _
   }
 }
 
-hipError_t run_qr_precondition(int64_t njobs, int n, int D, int n_pad, const double* T, const int32_t* src,
-                               const int32_t* split, int32_t* perm, double* S, double* Tws, double* W,
-                               hipStream_t stream) {
-  if (njobs == 0) return hipSuccess;
-  if (n_pad > 256 * QR_MAXQ) return hipErrorInvalidValue;
+// Blocked Householder QR of the column-stored matrices S (in place: V below
+// the diagonal, R on and above).  keep_T: T of panel p is kept at
+// Tws[job * (n_pad/32) * 1024 + p * 1024], otherwise every panel reuses
+// Tws[job * 1024].
+static hipError_t qr_factor(int64_t njobs, int n_pad, double* S, double* Tws, bool keep_T, hipStream_t stream) {
+  const int64_t t_stride = keep_T ? (int64_t)(n_pad / 32) * 1024 : 1024;
+  for (int j = 0; j < n_pad; j += 32) {
+    const int t_off = keep_T ? (j / 32) * 1024 : 0;
+    hipLaunchKernelGGL(qr_panel_kernel, dim3((unsigned)njobs), dim3(256), 0, stream, n_pad, j, S, Tws, t_stride, t_off);
+    const int rest = n_pad - j - 32;
+    if (rest > 0)
+      hipLaunchKernelGGL(qr_trailing_kernel, dim3(ceil_div(rest, 64), (unsigned)njobs), dim3(256), 0, stream, n_pad, j,
+                         S, Tws, t_stride, t_off);
+  }
+  return hipGetLastError();
+}
+
+static hipError_t order_and_unfold(int64_t njobs, int n, int D, int n_pad, const double* T, const int32_t* src,
+                                   const int32_t* split, int32_t* perm, double* S, hipStream_t stream) {
   int P = 1;
   while (P < n_pad) P <<= 1;
   hipLaunchKernelGGL(colnorm_order_kernel, dim3((unsigned)njobs), dim3(256), (size_t)P * 12, stream, n, D, n_pad, T,
@@ -334,14 +349,117 @@ hipError_t run_qr_precondition(int64_t njobs, int n, int D, int n_pad, const dou
   if (gx > 1024) gx = 1024;
   hipLaunchKernelGGL(unfold_cols_kernel, dim3(gx, (unsigned)njobs), dim3(256), 0, stream, n, D, n_pad, T, src, split,
                      perm, S);
-  for (int j = 0; j < n_pad; j += 32) {
-    hipLaunchKernelGGL(qr_panel_kernel, dim3((unsigned)njobs), dim3(256), 0, stream, n_pad, j, S, Tws);
-    const int rest = n_pad - j - 32;
-    if (rest > 0)
-      hipLaunchKernelGGL(qr_trailing_kernel, dim3(ceil_div(rest, 64), (unsigned)njobs), dim3(256), 0, stream, n_pad, j,
-                         S, Tws);
-  }
+  return hipGetLastError();
+}
+
+hipError_t run_qr_precondition(int64_t njobs, int n, int D, int n_pad, const double* T, const int32_t* src,
+                               const int32_t* split, int32_t* perm, double* S, double* Tws, double* W,
+                               hipStream_t stream) {
+  if (njobs == 0) return hipSuccess;
+  if (n_pad > 256 * QR_MAXQ) return hipErrorInvalidValue;
+  hipError_t e = order_and_unfold(njobs, n, D, n_pad, T, src, split, perm, S, stream);
+  if (e != hipSuccess) return e;
+  e = qr_factor(njobs, n_pad, S, Tws, false, stream);
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(r_rows_kernel, dim3(n_pad / 32, n_pad / 32, (unsigned)njobs), dim3(256), 0, stream, n_pad, S, W);
+  return hipGetLastError();
+}
+
+// Two QRs: M P = Q1 R1, R1^T = Q2 R2.  The rows of R1 are the columns of R1^T,
+// so the row copy of R1 (W1) is directly the column storage of R1^T.  The
+// Jacobi then runs on the rows of R2 (W2): its rows give Q1^T u_i, and Q1
+// (kept as V in S1 and the panel T factors in Tws1) maps them back.
+hipError_t run_qr2_precondition(int64_t njobs, int n, int D, int n_pad, const double* T, const int32_t* src,
+                                const int32_t* split, int32_t* perm, double* S1, double* Tws1, double* W1,
+                                double* Tws2, double* W2, hipStream_t stream) {
+  if (njobs == 0) return hipSuccess;
+  if (n_pad > 256 * QR_MAXQ) return hipErrorInvalidValue;
+  hipError_t e = order_and_unfold(njobs, n, D, n_pad, T, src, split, perm, S1, stream);
+  if (e != hipSuccess) return e;
+  e = qr_factor(njobs, n_pad, S1, Tws1, true, stream);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(r_rows_kernel, dim3(n_pad / 32, n_pad / 32, (unsigned)njobs), dim3(256), 0, stream, n_pad, S1, W1);
+  e = qr_factor(njobs, n_pad, W1, Tws2, false, stream);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(r_rows_kernel, dim3(n_pad / 32, n_pad / 32, (unsigned)njobs), dim3(256), 0, stream, n_pad, W1, W2);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// u_a = Q1 x_a for the kept rows x_a = W2[order[sel[a]]] / s of the Jacobi
+// result, Q1 = prod_p (I - V_p T_p V_p^T) applied from the last panel to the
+// first; F[:, a] = w_a u_a.  One workgroup per (a, job).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void apply_q1_kernel(int n, int n_pad, int kcap, const double* __restrict__ S1,
+                                                       const double* __restrict__ Tws1, const double* __restrict__ W2,
+                                                       const double* __restrict__ sigma,
+                                                       const int32_t* __restrict__ order,
+                                                       const int32_t* __restrict__ kept,
+                                                       const int32_t* __restrict__ sel,
+                                                       const double* __restrict__ weight, double* __restrict__ F) {
+  const int a = blockIdx.x;
+  const int64_t job = blockIdx.y;
+  const int tid = threadIdx.x;
+  double* Fj = F + (size_t)job * n * kcap;
+  if (a >= kept[job]) {
+    for (int r = tid; r < n; r += 256) Fj[(size_t)r * kcap + a] = 0.0;
+    return;
+  }
+  const int i = sel[job * kcap + a];
+  const double s = sigma[(size_t)job * n + i];
+  const double* row = W2 + (size_t)job * n_pad * n_pad + (size_t)order[(size_t)job * n + i] * n_pad;
+  const double* Sj = S1 + (size_t)job * n_pad * n_pad;
+  const double* Tj = Tws1 + (size_t)job * (n_pad / 32) * 1024;
+  __shared__ double x[1024];
+  __shared__ double red[5][33];
+  __shared__ double y2[32];
+  for (int r = tid; r < n_pad; r += 256) x[r] = row[r] / s;
+  __syncthreads();
+  for (int j = n_pad - 32; j >= 0; j -= 32) {
+    double vv[QR_MAXQ][32];
+    double part[32];
+#pragma unroll
+    for (int c = 0; c < 32; ++c) part[c] = 0.0;
+#pragma unroll
+    for (int q = 0; q < QR_MAXQ; ++q) {
+      const int r = j + tid + 256 * q;
+#pragma unroll
+      for (int c = 0; c < 32; ++c) {
+        const int d = j + c;
+        const double v = (r < n_pad && r > d) ? Sj[(size_t)d * n_pad + r] : (r == d ? 1.0 : 0.0);
+        vv[q][c] = v;
+        if (r < n_pad) part[c] += v * x[r];
+      }
+    }
+    block_reduce_vec(part, 32, red, tid);
+    if (tid < 32) {
+      double t = 0.0;
+      for (int p = tid; p < 32; ++p) t += Tj[(j / 32) * 1024 + tid * 32 + p] * red[0][p];
+      y2[tid] = t;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < QR_MAXQ; ++q) {
+      const int r = j + tid + 256 * q;
+      if (r < n_pad) {
+        double acc = 0.0;
+#pragma unroll
+        for (int c = 0; c < 32; ++c) acc += vv[q][c] * y2[c];
+        x[r] -= acc;
+      }
+    }
+    __syncthreads();
+  }
+  const double w = weight[job * kcap + a];
+  for (int r = tid; r < n; r += 256) Fj[(size_t)r * kcap + a] = w * x[r];
+}
+
+hipError_t launch_apply_q1(int64_t njobs, int n, int n_pad, int kcap, const double* S1, const double* Tws1,
+                           const double* W2, const double* sigma, const int32_t* order, const int32_t* kept,
+                           const int32_t* sel, const double* weight, double* F, hipStream_t stream) {
+  if (njobs == 0) return hipSuccess;
+  hipLaunchKernelGGL(apply_q1_kernel, dim3(kcap, (unsigned)njobs), dim3(256), 0, stream, n, n_pad, kcap, S1, Tws1, W2,
+                     sigma, order, kept, sel, weight, F);
   return hipGetLastError();
 }
 

@@ -55,12 +55,14 @@ def test_c1_unbiased_against_kaufman():
 
 
 def test_c2_beta_sweep_parity():
-    """Over the first 8 steps every sample makes the oracle's selections and
-    its ln c agree to 1e-12.  Over all 20 steps the chains are sensitive to
-    rounding once the spectra reach the noise floor: the oracle run with two
-    LAPACK drivers (gesdd, gesvd) already differs by up to ~1e-8 per site and
-    makes different selections in some chains.  So whole chains are held to
-    1e-7 per site when their selections agree, and a few are allowed to flip."""
+    """Every chain makes the oracle's selections up to its first flip, which
+    may not come before step 8, and its ln c agree up to there (1e-11
+    relative).  Later the selections are sensitive to rounding: they depend on
+    tail singular values (s_i / s_1 down to 1e-11) that two FP64 SVDs
+    determine only to ~n eps s_1 absolute, and the oracle run with two LAPACK
+    drivers (gesdd, gesvd) already flips in some chains.  Chains without a
+    flip are held to 1e-7 per site over all 20 steps (the oracle's own
+    driver-to-driver spread reaches 1.3e-8)."""
     torch, m = need_gpu()
     betas = list(C2.betas)
     log("C2 beta sweep")
@@ -69,21 +71,20 @@ def test_c2_beta_sweep_parity():
     r = m.run_samples(ts, len(betas), n_steps=20, k=16, seed=0, groups=groups, record=True, want_ln_c=True)
     ln, rec, lnc = r.ln_abs_Z.cpu().numpy(), r.record.cpu().numpy(), r.ln_c.cpu().numpy()
     N = 2.0 ** 20
-    flips = 0
+    first_flips = []
     for i, b in enumerate(betas):
         o = trg.run_shared(ising.site_tensor(b), 20, 16, 0, i)
         sel_same = [
             list(st.splits[0].sel) == [int(x) for x in rec[i, s, 4:4 + int(rec[i, s, 2])]] and
             list(st.splits[1].sel) == [int(x) for x in rec[i, s, 4 + 16:4 + 16 + int(rec[i, s, 3])]]
             for s, st in enumerate(o.records)]
-        assert all(sel_same[:8]), (b, sel_same)
-        assert np.allclose(lnc[i, :8], o.ln_c[:8], rtol=1e-12, atol=1e-14), b
-        if not all(sel_same):
-            flips += 1
-            continue
-        assert abs(ln[i] - o.ln_abs_Z) / N < 1e-7, (b, ln[i] / N, o.ln_abs_Z / N)
-    log(f"C2: {flips} of {len(betas)} chains flipped a selection after step 8")
-    assert flips <= len(betas) // 2
+        sf = sel_same.index(False) if not all(sel_same) else 20
+        first_flips.append(sf)
+        assert sf >= 8, (b, sel_same)
+        assert np.allclose(lnc[i, :sf], o.ln_c[:sf], rtol=1e-11, atol=1e-14), b
+        if sf == 20:
+            assert abs(ln[i] - o.ln_abs_Z) / N < 1e-7, (b, ln[i] / N, o.ln_abs_Z / N)
+    log(f"C2: first selection flip per chain (20 = none): {first_flips}")
 
 
 def test_c3_mixed_k_parity():
