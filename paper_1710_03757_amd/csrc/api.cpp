@@ -168,6 +168,7 @@ struct Chain {
   int* failed = nullptr;
   int8_t* sign = nullptr;
   JacobiWork jw{};
+  int* nb_job = nullptr;
   // host staging (pinned)
   HostPinned pin;
   int32_t *h_src = nullptr, *h_split = nullptr, *h_cjobs = nullptr;
@@ -264,6 +265,7 @@ void layout(Chain& c, Arena& ar) {
   c.jw.rotated = ar.take<int>(jmax);
   c.jw.sweeps = ar.take<int>(jmax);
   c.jw.counter = ar.take<int>(1);
+  c.nb_job = ar.take<int>(jmax);
 }
 
 std::vector<int> schedule(int d0, int k, int n_steps) {
@@ -401,15 +403,19 @@ int chain_step(Chain& c) {
   // decomposition: two QRs then Jacobi on the rows of R2 (n_pad <= 1024);
   // larger unfoldings go straight to Jacobi
   const bool qr2 = sh.n_pad <= kQrMaxN;
-  double* Wj = qr2 ? c.W2 : c.W;
   if (qr2) {
     CKH(run_qr2_precondition(nj, sh.n, sh.D, sh.n_pad, c.Ta, c.src, c.split, c.perm, c.S, c.Tws, c.W, c.Tws2, c.W2,
                              c.st));
   } else {
-    CKH(launch_unfold(nj, sh.D, sh.n_pad, c.Ta, c.src, c.split, c.W, c.st));
+    CKH(launch_unfold(nj, sh.D, sh.n_pad, c.Ta, c.src, c.split, c.W2, c.st));
     CKH(launch_iota(nj, sh.n_pad, c.perm, c.st));
   }
-  CKH(run_jacobi(nj, sh.n_pad, Wj, c.jw, kMaxSweeps, c.st, c.tj.enabled ? &c.tj : nullptr, &c.last_sweeps));
+  // rows at the noise floor move behind the active ones and are not rotated
+  double* Wj = c.W;
+  int nb_max = 0;
+  CKH(run_deflate(nj, sh.n_pad, c.W2, Wj, c.nb_job, c.jw.counter, c.jw.counter_host, &nb_max, c.st));
+  CKH(run_jacobi(nj, sh.n_pad, Wj, c.jw, kMaxSweeps, c.st, c.tj.enabled ? &c.tj : nullptr, &c.last_sweeps, c.nb_job,
+                 nb_max));
   CKH(launch_jacobi_fail(nj, sh.jps, c.jw.sweeps, c.failed, c.st));
   CKH(launch_jacobi_finalize(nj, sh.n, sh.n_pad, Wj, c.sigma, c.order, c.st));
   SampleArgs sa{};
@@ -420,11 +426,11 @@ int chain_step(Chain& c) {
   if ((c.flags & MCTRG_RECORD) && c.record)
     CKH(launch_record(c.nsamp, s, c.n_steps, c.kmax_rec, sh.kc, c.idx, c.cand, c.kept, c.sel, c.record, c.st));
   if (qr2) {
-    CKH(launch_apply_q1(nj, sh.n, sh.n_pad, sh.kc, c.S, c.Tws, c.W2, c.sigma, c.order, c.kept, c.sel, c.weight, c.F,
+    CKH(launch_apply_q1(nj, sh.n, sh.n_pad, sh.kc, c.S, c.Tws, Wj, c.sigma, c.order, c.kept, c.sel, c.weight, c.F,
                         c.st));
     CKH(launch_factor_G_from_F(nj, sh.D, sh.kc, c.Ta, c.src, c.split, c.sigma, c.kept, c.sel, c.F, c.G, c.st));
   } else {
-    CKH(launch_factor_G(nj, sh.D, sh.n_pad, sh.kc, c.W, c.sigma, c.order, c.kept, c.sel, c.weight, c.perm, c.G,
+    CKH(launch_factor_G(nj, sh.D, sh.n_pad, sh.kc, Wj, c.sigma, c.order, c.kept, c.sel, c.weight, c.perm, c.G,
                         c.st));
     CKH(launch_factor_F(nj, sh.D, sh.kc, c.Ta, c.src, c.split, c.sigma, c.kept, c.sel, c.G, c.F, c.st));
   }

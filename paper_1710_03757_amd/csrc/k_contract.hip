@@ -176,46 +176,67 @@ __device__ __forceinline__ typename Mma<DT>::frag_c mma_step(const typename Mma<
   }
 }
 
+// Tile shapes: the 32-, 16- and 8-bit forms use 128 x 128 workgroup tiles
+// (each wave a 64 x 64 block of 4 x 4 MFMA tiles), FP64 uses 64 x 64 (each
+// wave 32 x 32) to keep its LDS footprint at 17 KB per operand.
+template <int DT> struct Tile { static constexpr int BM = 128, WT = 4; };
+template <> struct Tile<MCTRG_F64> { static constexpr int BM = 64, WT = 2; };
+
 template <int DT>
 __global__ __launch_bounds__(256) void gemm_tn_kernel(int M, int N, int K, const void* __restrict__ Av,
                                                       const void* __restrict__ Bv, void* __restrict__ Cv) {
   typedef typename Mma<DT>::elt elt;
   typedef typename Mma<DT>::acc_t acc_t;
   typedef typename Mma<DT>::frag_c frag_c;
+  constexpr int BM = Tile<DT>::BM, WT = Tile<DT>::WT;     // workgroup tile, MFMA tiles per wave side
   constexpr int BK = 32, LD = BK + Mma<DT>::PAD, KS = Mma<DT>::KSTEP;
-  constexpr int EPL = (KS == 4) ? 1 : 8;    // elements per lane per MFMA
-  __shared__ __attribute__((aligned(16))) elt As[64 * LD];
-  __shared__ __attribute__((aligned(16))) elt Bs[64 * LD];
+  constexpr int EPL = (KS == 4) ? 1 : 8;                  // elements per lane per MFMA
+  constexpr int LOADS = BM * BK / 256;                    // elements per thread per operand and K tile
+  __shared__ __attribute__((aligned(16))) elt As[BM * LD];
+  __shared__ __attribute__((aligned(16))) elt Bs[BM * LD];
   const int64_t o = blockIdx.z;
   const elt* A = reinterpret_cast<const elt*>(Av) + (size_t)o * M * K;
   const elt* B = reinterpret_cast<const elt*>(Bv) + (size_t)o * N * K;
   acc_t* C = reinterpret_cast<acc_t*>(Cv) + (size_t)o * M * N;
-  const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
+  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BM;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  const int wm = (wave >> 1) * (16 * WT), wn = (wave & 1) * (16 * WT);
   const int lr = lane & 15, lg = lane >> 4;
-  frag_c acc[2][2];
+  frag_c acc[WT][WT];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < WT; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) acc[i][j] = frag_c{0, 0, 0, 0};
+    for (int j = 0; j < WT; ++j) acc[i][j] = frag_c{0, 0, 0, 0};
 
+  // thread t loads LOADS consecutive K elements of row (t * LOADS) / BK
+  const int lrow = (tid * LOADS) / BK, lk = (tid * LOADS) % BK;
+  elt ra[LOADS], rb[LOADS];
+  auto gload = [&](int k0) {
+    const int gm = m0 + lrow, gn = n0 + lrow;
+#pragma unroll
+    for (int x = 0; x < LOADS; ++x) {
+      const int gk = k0 + lk + x;
+      ra[x] = (gm < M && gk < K) ? A[(size_t)gm * K + gk] : elt(0);
+      rb[x] = (gn < N && gk < K) ? B[(size_t)gn * K + gk] : elt(0);
+    }
+  };
+  gload(0);
   for (int k0 = 0; k0 < K; k0 += BK) {
-    for (int e = tid; e < 64 * BK; e += 256) {
-      const int r = e / BK, kx = e % BK;
-      const int gm = m0 + r, gn = n0 + r, gk = k0 + kx;
-      As[r * LD + kx] = (gm < M && gk < K) ? A[(size_t)gm * K + gk] : elt(0);
-      Bs[r * LD + kx] = (gn < N && gk < K) ? B[(size_t)gn * K + gk] : elt(0);
+#pragma unroll
+    for (int x = 0; x < LOADS; ++x) {
+      As[lrow * LD + lk + x] = ra[x];
+      Bs[lrow * LD + lk + x] = rb[x];
     }
     __syncthreads();
+    if (k0 + BK < K) gload(k0 + BK);    // next K tile in flight during the MFMAs
 #pragma unroll
     for (int ks = 0; ks < BK; ks += KS) {
       const int kofs = ks + lg * EPL;
 #pragma unroll
-      for (int i = 0; i < 2; ++i) {
+      for (int i = 0; i < WT; ++i) {
         const elt* ap = &As[(wm + 16 * i + lr) * LD + kofs];
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
+        for (int j = 0; j < WT; ++j) {
           const elt* bp = &Bs[(wn + 16 * j + lr) * LD + kofs];
           acc[i][j] = mma_step<DT>(ap, bp, acc[i][j]);
         }
@@ -224,9 +245,9 @@ __global__ __launch_bounds__(256) void gemm_tn_kernel(int M, int N, int K, const
     __syncthreads();
   }
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < WT; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int j = 0; j < WT; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int gm = m0 + wm + 16 * i + (DT == MCTRG_F64 ? acc_row_f64(lg, r) : acc_row_f32(lg, r));
@@ -272,7 +293,8 @@ hipError_t launch_contract(const ContractArgs& a, hipStream_t stream, KernelTime
   hipLaunchKernelGGL(contract_Y_kernel, dim3(kk, (unsigned)a.nout), dim3(256), sh, stream, D, kk, kcap, a.FA,
                      a.FB, a.f_stride, a.jobs, a.Y);
   const int64_t per = (int64_t)MM * DD;
-  dim3 gg(ceil_div(MM, 64), ceil_div(MM, 64), (unsigned)a.nout);
+  dim3 gg(ceil_div(MM, 64), ceil_div(MM, 64), (unsigned)a.nout);        // FP64 tiles
+  dim3 gn(ceil_div(MM, 128), ceil_div(MM, 128), (unsigned)a.nout);      // narrow tiles
   if (a.dtype == MCTRG_F64) {
     hipLaunchKernelGGL(fill_kernel, dim3(ceil_div(2 * a.nout, 256)), dim3(256), 0, stream, 2 * a.nout, a.scales, 1.0);
     if (gt) gt->begin(stream);
@@ -299,7 +321,7 @@ hipError_t launch_contract(const ContractArgs& a, hipStream_t stream, KernelTime
       hipLaunchKernelGGL(cast_kernel<MCTRG_F32>, dim3(gx, (unsigned)a.nout), dim3(256), 0, stream, per, a.X, mxX, a.Xlp);
       hipLaunchKernelGGL(cast_kernel<MCTRG_F32>, dim3(gx, (unsigned)a.nout), dim3(256), 0, stream, per, a.Y, mxY, a.Ylp);
       if (gt) gt->begin(stream);
-      hipLaunchKernelGGL(gemm_tn_kernel<MCTRG_F32>, gg, dim3(256), 0, stream, MM, MM, DD, (const void*)a.Xlp,
+      hipLaunchKernelGGL(gemm_tn_kernel<MCTRG_F32>, gn, dim3(256), 0, stream, MM, MM, DD, (const void*)a.Xlp,
                          (const void*)a.Ylp, a.Tout);
       if (gt) gt->end(stream);
       break;
@@ -307,7 +329,7 @@ hipError_t launch_contract(const ContractArgs& a, hipStream_t stream, KernelTime
       hipLaunchKernelGGL(cast_kernel<MCTRG_BF16>, dim3(gx, (unsigned)a.nout), dim3(256), 0, stream, per, a.X, mxX, a.Xlp);
       hipLaunchKernelGGL(cast_kernel<MCTRG_BF16>, dim3(gx, (unsigned)a.nout), dim3(256), 0, stream, per, a.Y, mxY, a.Ylp);
       if (gt) gt->begin(stream);
-      hipLaunchKernelGGL(gemm_tn_kernel<MCTRG_BF16>, gg, dim3(256), 0, stream, MM, MM, DD, (const void*)a.Xlp,
+      hipLaunchKernelGGL(gemm_tn_kernel<MCTRG_BF16>, gn, dim3(256), 0, stream, MM, MM, DD, (const void*)a.Xlp,
                          (const void*)a.Ylp, a.Tout);
       if (gt) gt->end(stream);
       break;
@@ -315,7 +337,7 @@ hipError_t launch_contract(const ContractArgs& a, hipStream_t stream, KernelTime
       hipLaunchKernelGGL(cast_kernel<MCTRG_FP8_E4M3>, dim3(gx, (unsigned)a.nout), dim3(256), 0, stream, per, a.X, mxX, a.Xlp);
       hipLaunchKernelGGL(cast_kernel<MCTRG_FP8_E4M3>, dim3(gx, (unsigned)a.nout), dim3(256), 0, stream, per, a.Y, mxY, a.Ylp);
       if (gt) gt->begin(stream);
-      hipLaunchKernelGGL(gemm_tn_kernel<MCTRG_FP8_E4M3>, gg, dim3(256), 0, stream, MM, MM, DD, (const void*)a.Xlp,
+      hipLaunchKernelGGL(gemm_tn_kernel<MCTRG_FP8_E4M3>, gn, dim3(256), 0, stream, MM, MM, DD, (const void*)a.Xlp,
                          (const void*)a.Ylp, a.Tout);
       if (gt) gt->end(stream);
       break;

@@ -30,12 +30,17 @@ __device__ __forceinline__ int circle_block(int pos, int r, int nb) {
   return pos == 0 ? 0 : 1 + (pos - 1 + r) % (nb - 1);
 }
 
-__global__ __launch_bounds__(256) void jacobi_round_kernel(double* __restrict__ W, int n_pad, int nb,
-                                                           int round, const int* __restrict__ active,
+__global__ __launch_bounds__(256) void jacobi_round_kernel(double* __restrict__ W, int n_pad, int nb_all,
+                                                           const int* __restrict__ nb_job, int round,
+                                                           const int* __restrict__ active,
                                                            int* __restrict__ rotated, double tol) {
   const int job = blockIdx.y;
   if (!active[job]) return;
+  // rows beyond the job's active blocks sit below the noise floor and stay
+  // as they are (see deflate_rows_kernel)
+  const int nb = nb_job ? nb_job[job] : nb_all;
   const int pair = blockIdx.x;
+  if (round >= nb - 1 || pair >= nb / 2) return;
   const int I = circle_block(pair, round, nb);
   const int J = circle_block(nb - 1 - pair, round, nb);
   double* Wj = W + (size_t)job * n_pad * n_pad;
@@ -275,9 +280,9 @@ hipError_t KernelTimer::collect() {
 }
 
 hipError_t run_jacobi(int64_t njobs, int n_pad, double* W, const JacobiWork& wk, int max_sweeps,
-                      hipStream_t stream, KernelTimer* timer, int* sweeps_done) {
+                      hipStream_t stream, KernelTimer* timer, int* sweeps_done, const int* nb_job, int nb_max) {
   if (njobs == 0) return hipSuccess;
-  const int nb = n_pad / 16;
+  const int nb = nb_job ? nb_max : n_pad / 16;
   const double tol = fmax(32.0, 8.0 * sqrt((double)n_pad)) * 0x1.0p-53;
   int g = ceil_div(njobs, 256);
   hipLaunchKernelGGL(jacobi_init_kernel, dim3(g), dim3(256), 0, stream, njobs, wk.active, wk.rotated,
@@ -286,7 +291,7 @@ hipError_t run_jacobi(int64_t njobs, int n_pad, double* W, const JacobiWork& wk,
     for (int r = 0; r < nb - 1; ++r) {
       if (timer) { hipError_t e = timer->begin(stream); if (e != hipSuccess) return e; }
       hipLaunchKernelGGL(jacobi_round_kernel, dim3(nb / 2, (unsigned)njobs), dim3(256), 0, stream, W,
-                         n_pad, nb, r, wk.active, wk.rotated, tol);
+                         n_pad, nb, nb_job, r, wk.active, wk.rotated, tol);
       if (timer) { hipError_t e = timer->end(stream); if (e != hipSuccess) return e; }
     }
     hipLaunchKernelGGL(zero_int_kernel, dim3(1), dim3(1), 0, stream, wk.counter);
@@ -303,6 +308,80 @@ hipError_t run_jacobi(int64_t njobs, int n_pad, double* W, const JacobiWork& wk,
     if (sweeps_done) *sweeps_done = sweep + 1;
     if (*wk.counter_host == 0) break;
   }
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Noise-floor deflation.  Rows whose norm is at most 2^-48 of the largest row
+// norm are moved behind the others (stable partition) and excluded from the
+// rotations: leaving them unrotated perturbs the singular values of the rest
+// by at most their norm (Weyl), i.e. at the rounding level of an FP64 SVD and
+// far below the candidate threshold tau_null * s_1.  nb_job receives the
+// number of 16-row blocks (even, at least 2) that cover the active rows.
+// One workgroup of 256 threads per job; n_pad <= 4096.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void deflate_rows_kernel(int n_pad, const double* __restrict__ Win,
+                                                           double* __restrict__ Wout, int* __restrict__ nb_job) {
+  __shared__ double nrm[4096];
+  __shared__ int newpos[4096];
+  __shared__ double red[4];
+  __shared__ int cnt_s[4];
+  const int64_t job = blockIdx.x;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const double* Wi = Win + (size_t)job * n_pad * n_pad;
+  double* Wo = Wout + (size_t)job * n_pad * n_pad;
+  double mx = 0.0;
+  for (int r = wave; r < n_pad; r += 4) {
+    double sq = 0.0;
+    for (int c = lane; c < n_pad; c += 64) sq += Wi[(size_t)r * n_pad + c] * Wi[(size_t)r * n_pad + c];
+    for (int o = 32; o > 0; o >>= 1) sq += __shfl_xor(sq, o);
+    if (lane == 0) nrm[r] = sq;
+    mx = fmax(mx, sq);
+  }
+  if (lane == 0) red[wave] = mx;
+  __syncthreads();
+  const double thr = fmax(fmax(red[0], red[1]), fmax(red[2], red[3])) * 0x1.0p-96;
+  if (threadIdx.x == 0) {
+    // stable partition (sequential scan over at most 4096 flags)
+    int a = 0;
+    for (int r = 0; r < n_pad; ++r) a += nrm[r] > thr ? 1 : 0;
+    int ia = 0, ib = a;
+    for (int r = 0; r < n_pad; ++r) newpos[r] = nrm[r] > thr ? ia++ : ib++;
+    int nbk = 2 * ((a + 31) / 32);
+    if (nbk < 2) nbk = 2;
+    nb_job[job] = nbk;
+    cnt_s[0] = a;
+  }
+  __syncthreads();
+  for (int r = wave; r < n_pad; r += 4) {
+    const int d = newpos[r];
+    for (int c = lane; c < n_pad; c += 64) Wo[(size_t)d * n_pad + c] = Wi[(size_t)r * n_pad + c];
+  }
+}
+
+__global__ void max_int_kernel(int64_t n, const int* __restrict__ v, int* __restrict__ out) {
+  int m = 0;
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) m = max(m, v[i]);
+  for (int o = 32; o > 0; o >>= 1) m = max(m, __shfl_xor(m, o));
+  __shared__ int red[16];
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) m = max(m, red[w]);
+    *out = max(m, red[0]);
+  }
+}
+
+hipError_t run_deflate(int64_t njobs, int n_pad, const double* Win, double* Wout, int* nb_job, int* scratch_dev,
+                       int* scratch_host, int* nb_max, hipStream_t stream) {
+  if (njobs == 0) { *nb_max = 2; return hipSuccess; }
+  hipLaunchKernelGGL(deflate_rows_kernel, dim3((unsigned)njobs), dim3(256), 0, stream, n_pad, Win, Wout, nb_job);
+  hipLaunchKernelGGL(max_int_kernel, dim3(1), dim3(1024), 0, stream, njobs, nb_job, scratch_dev);
+  hipError_t e = hipMemcpyAsync(scratch_host, scratch_dev, sizeof(int), hipMemcpyDeviceToHost, stream);
+  if (e != hipSuccess) return e;
+  e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) return e;
+  *nb_max = *scratch_host;
   return hipGetLastError();
 }
 

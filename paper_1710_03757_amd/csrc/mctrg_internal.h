@@ -111,7 +111,13 @@ struct JacobiWork {
   int* counter_host; // pinned host 1 int
 };
 hipError_t run_jacobi(int64_t njobs, int n_pad, double* W, const JacobiWork& wk, int max_sweeps,
-                      hipStream_t stream, KernelTimer* timer = nullptr, int* sweeps_done = nullptr);
+                      hipStream_t stream, KernelTimer* timer = nullptr, int* sweeps_done = nullptr,
+                      const int* nb_job = nullptr, int nb_max = 0);
+// Noise-floor deflation: Wout = rows of Win with the active rows (norm >
+// 2^-48 of the largest) first; nb_job = 16-row blocks covering them; the
+// maximum over jobs is returned in *nb_max (synchronises the stream).
+hipError_t run_deflate(int64_t njobs, int n_pad, const double* Win, double* Wout, int* nb_job, int* scratch_dev,
+                       int* scratch_host, int* nb_max, hipStream_t stream);
 // QR preconditioning (k_qr.hip): perm[j] (n_pad) orders the columns of the
 // unfolding by decreasing norm, S (n_pad^2 per job) holds M P column-wise
 // and is overwritten by V and R, Tws (1024 per job) is scratch, and W
