@@ -36,15 +36,20 @@ __global__ __launch_bounds__(256) void contract_X_kernel(int D, int kk, int kcap
   const double* GBbase = GBpool + (size_t)jobs[4 * o + 1] * g_stride;
   for (int e = threadIdx.x; e < DD; e += 256) GAa[(e / D) * ld + e % D] = GA[e];
   double* Xo = X + (size_t)o * kk * kk * DD;
+  const bool stage_b = D <= 45;   // both operands fit 32 KB of LDS each
   for (int b = 0; b < kk; ++b) {
     __syncthreads();
     const double* GB = GBbase + (size_t)b * DD;
-    for (int e = threadIdx.x; e < DD; e += 256) GBb[(e / D) * ld + e % D] = GB[e];
+    if (stage_b)
+      for (int e = threadIdx.x; e < DD; e += 256) GBb[(e / D) * ld + e % D] = GB[e];
     __syncthreads();
     for (int e = threadIdx.x; e < DD; e += 256) {
       const int t = e / D, q = e % D;
       double s = 0.0;
-      for (int p = 0; p < D; ++p) s += GAa[p * ld + t] * GBb[q * ld + p];
+      if (stage_b)
+        for (int p = 0; p < D; ++p) s += GAa[p * ld + t] * GBb[q * ld + p];
+      else
+        for (int p = 0; p < D; ++p) s += GAa[p * ld + t] * GB[q * D + p];
       Xo[((size_t)a * kk + b) * DD + e] = s;
     }
   }
@@ -64,14 +69,19 @@ __global__ __launch_bounds__(256) void contract_Y_kernel(int D, int kk, int kcap
   const double* FB = FBpool + (size_t)jobs[4 * o + 3] * f_stride;
   for (int e = threadIdx.x; e < DD; e += 256) FAc[(e / D) * ld + e % D] = FA[(size_t)e * kcap + c];
   double* Yo = Yt + (size_t)o * kk * kk * DD;
+  const bool stage_b = D <= 45;
   for (int ee = 0; ee < kk; ++ee) {
     __syncthreads();
-    for (int e = threadIdx.x; e < DD; e += 256) FBe[(e / D) * ld + e % D] = FB[(size_t)e * kcap + ee];
+    if (stage_b)
+      for (int e = threadIdx.x; e < DD; e += 256) FBe[(e / D) * ld + e % D] = FB[(size_t)e * kcap + ee];
     __syncthreads();
     for (int e = threadIdx.x; e < DD; e += 256) {
       const int t = e / D, q = e % D;
       double s = 0.0;
-      for (int ss = 0; ss < D; ++ss) s += FBe[t * ld + ss] * FAc[ss * ld + q];
+      if (stage_b)
+        for (int ss = 0; ss < D; ++ss) s += FBe[t * ld + ss] * FAc[ss * ld + q];
+      else
+        for (int ss = 0; ss < D; ++ss) s += FB[((size_t)t * D + ss) * kcap + ee] * FAc[ss * ld + q];
       Yo[((size_t)c * kk + ee) * DD + e] = s;
     }
   }
@@ -286,7 +296,7 @@ static size_t elt_bytes(int dt) {
 hipError_t launch_contract(const ContractArgs& a, hipStream_t stream, KernelTimer* gt) {
   if (a.nout == 0) return hipSuccess;
   const int D = a.D, kk = a.kk, DD = D * D, MM = kk * kk;
-  const size_t sh = (size_t)2 * D * (D + 1) * sizeof(double);
+  const size_t sh = (size_t)(D <= 45 ? 2 : 1) * D * (D + 1) * sizeof(double);
   const int kcap = kk;
   hipLaunchKernelGGL(contract_X_kernel, dim3(kk, (unsigned)a.nout), dim3(256), sh, stream, D, kk, kcap, a.GA,
                      a.GB, a.g_stride, a.jobs, a.X);

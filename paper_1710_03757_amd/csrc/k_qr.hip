@@ -9,9 +9,10 @@
 //
 // Storage: S (n_pad x n_pad per job) holds M P column by column: S[c][r] =
 // M[r][P[c]], so every column is contiguous.  The factorisation is the
-// blocked Householder QR with 32-column panels:
+// blocked Householder QR with 32-column panels (8-column panels for
+// n_pad > 1024):
 //   panel kernel     one workgroup per job factors the panel in registers
-//                    (each thread owns up to four rows of the 32 columns),
+//                    (each thread owns up to four (eight) rows of the panel),
 //                    leaves the Householder vectors below the diagonal and
 //                    R on and above it, and forms the 32 x 32 triangular T of
 //                    the compact WY form I - V T V^T;
@@ -22,7 +23,6 @@
 
 namespace mctrg {
 
-constexpr int QR_MAXQ = 4;   // rows per thread in the panel kernel: n_pad <= 1024
 
 // ---------------------------------------------------------------------------
 // Column norms of M and their descending order (ties by index): P.
@@ -98,8 +98,9 @@ __global__ void unfold_cols_kernel(int n, int D, int n_pad, const double* __rest
 // Panel factorisation (columns j..j+31, rows j..n_pad-1), one workgroup/job.
 // Thread t owns rows j + t + 256 q, q < QR_MAXQ.
 // ---------------------------------------------------------------------------
+template <int NT>
 __device__ __forceinline__ void block_reduce_vec(double* v, int cnt, double (*red)[33], int tid) {
-  // v[0..cnt) per thread -> summed over the 256 threads, result in red[0][..]
+  // v[0..cnt) per thread -> summed over the NT threads, result in red[0][..]
   const int lane = tid & 63, wave = tid >> 6;
   for (int x = 0; x < cnt; ++x) {
     double s = v[x];
@@ -107,42 +108,49 @@ __device__ __forceinline__ void block_reduce_vec(double* v, int cnt, double (*re
     if (lane == 0) red[wave + 1][x] = s;
   }
   __syncthreads();
-  if (tid < cnt) red[0][tid] = (red[1][tid] + red[2][tid]) + (red[3][tid] + red[4][tid]);
+  if (tid < cnt) {
+    double s = 0.0;
+#pragma unroll
+    for (int w = 0; w < NT / 64; ++w) s += red[w + 1][tid];
+    red[0][tid] = s;
+  }
   __syncthreads();
 }
 
-__global__ __launch_bounds__(256) void qr_panel_kernel(int n_pad, int j, double* __restrict__ S,
-                                                       double* __restrict__ Tws, int64_t t_stride, int t_off) {
+// Panel kernel: NT threads, MAXQ rows per thread, PW-column panels.
+template <int NT, int MAXQ, int PW>
+__global__ __launch_bounds__(NT) void qr_panel_kernel(int n_pad, int j, double* __restrict__ S,
+                                                      double* __restrict__ Tws, int64_t t_stride, int64_t t_off) {
   const int64_t job = blockIdx.x;
   const int tid = threadIdx.x;
   double* Sj = S + job * (size_t)n_pad * n_pad;
-  __shared__ double red[5][33];
-  __shared__ double Tm[32][33];
-  __shared__ double sh_alpha, sh_beta, sh_tau;
+  __shared__ double red[NT / 64 + 1][33];
+  __shared__ double Tm[PW][PW + 1];
+  __shared__ double sh_alpha;
 
-  double A[QR_MAXQ][32];
+  double A[MAXQ][PW];
 #pragma unroll
-  for (int q = 0; q < QR_MAXQ; ++q) {
-    const int r = j + tid + 256 * q;
+  for (int q = 0; q < MAXQ; ++q) {
+    const int r = j + tid + NT * q;
 #pragma unroll
-    for (int c = 0; c < 32; ++c) A[q][c] = (r < n_pad) ? Sj[(size_t)(j + c) * n_pad + r] : 0.0;
+    for (int c = 0; c < PW; ++c) A[q][c] = (r < n_pad) ? Sj[(size_t)(j + c) * n_pad + r] : 0.0;
   }
-  for (int e = tid; e < 32 * 33; e += 256) Tm[e / 33][e % 33] = 0.0;
+  for (int e = tid; e < PW * (PW + 1); e += NT) Tm[e / (PW + 1)][e % (PW + 1)] = 0.0;
 
-  double part[32];
+  double part[PW];
 #pragma unroll
-  for (int i = 0; i < 32; ++i) {
+  for (int i = 0; i < PW; ++i) {
     const int cj = j + i;
     // --- Householder vector of column i --------------------------------------
     double sq = 0.0;
 #pragma unroll
-    for (int q = 0; q < QR_MAXQ; ++q) {
-      const int r = j + tid + 256 * q;
+    for (int q = 0; q < MAXQ; ++q) {
+      const int r = j + tid + NT * q;
       if (r > cj && r < n_pad) sq += A[q][i] * A[q][i];
       if (r == cj) sh_alpha = A[q][i];
     }
     part[0] = sq;
-    block_reduce_vec(part, 1, red, tid);
+    block_reduce_vec<NT>(part, 1, red, tid);
     const double xn2 = red[0][0];
     const double alpha = sh_alpha;
     double beta, tau, scale;
@@ -155,21 +163,21 @@ __global__ __launch_bounds__(256) void qr_panel_kernel(int n_pad, int j, double*
     }
     // v: 1 at r == cj, A * scale below, 0 above; stored in column i
 #pragma unroll
-    for (int q = 0; q < QR_MAXQ; ++q) {
-      const int r = j + tid + 256 * q;
+    for (int q = 0; q < MAXQ; ++q) {
+      const int r = j + tid + NT * q;
       if (r > cj) A[q][i] *= scale;
       else if (r == cj) A[q][i] = beta;   // R diagonal; the implicit 1 is used below
     }
     // --- dots: w_c = v^T col_c (c > i), z_m = v_m^T v (m < i) ------------------
 #pragma unroll
-    for (int x = 0; x < 32; ++x) part[x] = 0.0;
+    for (int x = 0; x < PW; ++x) part[x] = 0.0;
 #pragma unroll
-    for (int q = 0; q < QR_MAXQ; ++q) {
-      const int r = j + tid + 256 * q;
+    for (int q = 0; q < MAXQ; ++q) {
+      const int r = j + tid + NT * q;
       if (r >= cj && r < n_pad) {
         const double vr = (r == cj) ? 1.0 : A[q][i];
 #pragma unroll
-        for (int c = 0; c < 32; ++c) {
+        for (int c = 0; c < PW; ++c) {
           if (c > i) part[c] += vr * A[q][c];
           else if (c < i) {
             // v_c at row r: below its diagonal j+c it is stored, at j+c it is 1
@@ -179,25 +187,25 @@ __global__ __launch_bounds__(256) void qr_panel_kernel(int n_pad, int j, double*
         }
       }
     }
-    block_reduce_vec(part, 32, red, tid);
+    block_reduce_vec<NT>(part, PW, red, tid);
     // --- apply H_i to the remaining panel columns ----------------------------
 #pragma unroll
-    for (int q = 0; q < QR_MAXQ; ++q) {
-      const int r = j + tid + 256 * q;
+    for (int q = 0; q < MAXQ; ++q) {
+      const int r = j + tid + NT * q;
       if (r >= cj && r < n_pad) {
         const double vr = (r == cj) ? 1.0 : A[q][i];
 #pragma unroll
-        for (int c = 0; c < 32; ++c)
+        for (int c = 0; c < PW; ++c)
           if (c > i) A[q][c] -= tau * red[0][c] * vr;
       }
     }
     // --- T column i: T[0:i, i] = -tau T[0:i, 0:i] z[0:i], T[i][i] = tau --------
-    if (tid < 32) {
+    if (tid < PW) {
       const int m = tid;
       if (m < i) {
-        double s = 0.0;
-        for (int p = m; p < i; ++p) s += Tm[m][p] * red[0][p];
-        part[0] = -tau * s;
+        double s2 = 0.0;
+        for (int p = m; p < i; ++p) s2 += Tm[m][p] * red[0][p];
+        part[0] = -tau * s2;
       }
     }
     __syncthreads();
@@ -206,15 +214,15 @@ __global__ __launch_bounds__(256) void qr_panel_kernel(int n_pad, int j, double*
     __syncthreads();
   }
 #pragma unroll
-  for (int q = 0; q < QR_MAXQ; ++q) {
-    const int r = j + tid + 256 * q;
+  for (int q = 0; q < MAXQ; ++q) {
+    const int r = j + tid + NT * q;
     if (r < n_pad) {
 #pragma unroll
-      for (int c = 0; c < 32; ++c) Sj[(size_t)(j + c) * n_pad + r] = A[q][c];
+      for (int c = 0; c < PW; ++c) Sj[(size_t)(j + c) * n_pad + r] = A[q][c];
     }
   }
   double* Tj = Tws + job * t_stride + t_off;
-  for (int e = tid; e < 1024; e += 256) Tj[e] = Tm[e >> 5][e & 31];
+  for (int e = tid; e < PW * PW; e += NT) Tj[e] = Tm[e / PW][e % PW];
 }
 
 // ---------------------------------------------------------------------------
@@ -222,52 +230,58 @@ __global__ __launch_bounds__(256) void qr_panel_kernel(int n_pad, int j, double*
 // compact WY form H_0 H_1 ... H_31 = I - V T V^T, so Q^T C = C - V T^T V^T C.
 // One workgroup per (job, 64-column tile); wave w owns 16 columns.
 // ---------------------------------------------------------------------------
+template <int PW>
 __device__ __forceinline__ double vload(const double* Sj, int n_pad, int j, int i, int r) {
   // V[r][i]: stored below the diagonal of panel column j+i, 1 on it, 0 above
+  // (and 0 for i >= PW or r >= n_pad)
   const int d = j + i;
+  if (i >= PW || r >= n_pad) return 0.0;
   if (r > d) return Sj[(size_t)d * n_pad + r];
   return r == d ? 1.0 : 0.0;
 }
 
+template <int PW>
 __global__ __launch_bounds__(256) void qr_trailing_kernel(int n_pad, int j, double* __restrict__ S,
                                                           const double* __restrict__ Tws, int64_t t_stride,
-                                                          int t_off) {
+                                                          int64_t t_off) {
+  constexpr int NI = (PW + 15) / 16;     // 16-row MFMA tiles of V^T C
   const int64_t job = blockIdx.y;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int lr = lane & 15, lg = lane >> 4;
   double* Sj = S + job * (size_t)n_pad * n_pad;
-  const int c0w = j + 32 + 64 * blockIdx.x + 16 * wave;   // first column of this wave
+  const int c0w = j + PW + 64 * blockIdx.x + 16 * wave;   // first column of this wave
   __shared__ double W1[32][65];
-  __shared__ double Tm[32][33];
-  for (int e = tid; e < 1024; e += 256) Tm[e >> 5][e & 31] = Tws[job * t_stride + t_off + e];
+  __shared__ double Tm[PW][PW + 1];
+  for (int e = tid; e < PW * PW; e += 256) Tm[e / PW][e % PW] = Tws[job * t_stride + t_off + e];
   const bool active = c0w < n_pad;
+  const bool col_ok = (c0w + lr) < n_pad;
 
-  // ---- phase 1: W1 = V^T C (32 x 16 per wave) ------------------------------
-  f64x4 acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
+  // ---- phase 1: W1 = V^T C (PW x 16 per wave) ------------------------------
+  f64x4 acc[NI];
+#pragma unroll
+  for (int t = 0; t < NI; ++t) acc[t] = f64x4{0, 0, 0, 0};
   if (active) {
     for (int r0 = j; r0 < n_pad; r0 += 16) {
       const int rb = r0 + 4 * lg;
-      double cv[4], v0[4], v1[4];
+      double cv[4];
       const double* cp = Sj + (size_t)(c0w + lr) * n_pad + rb;
 #pragma unroll
-      for (int jj = 0; jj < 4; ++jj) {
-        cv[jj] = cp[jj];
-        v0[jj] = vload(Sj, n_pad, j, lr, rb + jj);
-        v1[jj] = vload(Sj, n_pad, j, 16 + lr, rb + jj);
-      }
+      for (int jj = 0; jj < 4; ++jj) cv[jj] = (col_ok && rb + jj < n_pad) ? cp[jj] : 0.0;
 #pragma unroll
-      for (int jj = 0; jj < 4; ++jj) {
-        acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(v0[jj], cv[jj], acc0, 0, 0, 0);
-        acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(v1[jj], cv[jj], acc1, 0, 0, 0);
+      for (int t = 0; t < NI; ++t) {
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) {
+          const double v = vload<PW>(Sj, n_pad, j, 16 * t + lr, rb + jj);
+          acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(v, cv[jj], acc[t], 0, 0, 0);
+        }
       }
     }
   }
-  // acc{0,1}[x]: row i = 16*tile + acc_row_f64(lg, x), column lr of the wave
+  // acc[t][x]: row i = 16*t + acc_row_f64(lg, x), column lr of the wave
 #pragma unroll
-  for (int x = 0; x < 4; ++x) {
-    W1[acc_row_f64(lg, x)][16 * wave + lr] = acc0[x];
-    W1[16 + acc_row_f64(lg, x)][16 * wave + lr] = acc1[x];
-  }
+  for (int t = 0; t < NI; ++t)
+#pragma unroll
+    for (int x = 0; x < 4; ++x) W1[16 * t + acc_row_f64(lg, x)][16 * wave + lr] = acc[t][x];
   __syncthreads();
   // ---- phase 2: W2 = T^T W1 (in place, column by column) -------------------
   {
@@ -276,9 +290,10 @@ __global__ __launch_bounds__(256) void qr_trailing_kernel(int n_pad, int j, doub
 #pragma unroll
     for (int ii = 0; ii < 8; ++ii) {
       const int i = i0 + ii;
-      double s = 0.0;
-      for (int m = 0; m <= i; ++m) s += Tm[m][i] * W1[m][col];
-      w2[ii] = s;
+      double s2 = 0.0;
+      if (i < PW)
+        for (int m = 0; m <= i; ++m) s2 += Tm[m][i] * W1[m][col];
+      w2[ii] = s2;
     }
     __syncthreads();
 #pragma unroll
@@ -288,20 +303,22 @@ __global__ __launch_bounds__(256) void qr_trailing_kernel(int n_pad, int j, doub
   if (!active) return;
   // ---- phase 3: C <- C - V W2 ------------------------------------------------
   // output tile C^T[c (16)][r (16)] = sum_i W2^T[c][i] V^T[i][r]
-  double aw[8];
+  constexpr int KSTEPS = (PW + 3) / 4;
+  double aw[KSTEPS];
 #pragma unroll
-  for (int ks = 0; ks < 8; ++ks) aw[ks] = W1[4 * ks + lg][16 * wave + lr];
+  for (int ks = 0; ks < KSTEPS; ++ks) aw[ks] = W1[4 * ks + lg][16 * wave + lr];
   for (int r0 = j; r0 < n_pad; r0 += 16) {
-    f64x4 acc = {0, 0, 0, 0};
+    f64x4 a = {0, 0, 0, 0};
 #pragma unroll
-    for (int ks = 0; ks < 8; ++ks) {
-      const double bv = vload(Sj, n_pad, j, 4 * ks + lg, r0 + lr);
-      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(aw[ks], bv, acc, 0, 0, 0);
+    for (int ks = 0; ks < KSTEPS; ++ks) {
+      const double bv = vload<PW>(Sj, n_pad, j, 4 * ks + lg, r0 + lr);
+      a = __builtin_amdgcn_mfma_f64_16x16x4f64(aw[ks], bv, a, 0, 0, 0);
     }
+    const int r = r0 + lr;
 #pragma unroll
     for (int x = 0; x < 4; ++x) {
-      double* p = Sj + (size_t)(c0w + acc_row_f64(lg, x)) * n_pad + r0 + lr;
-      *p -= acc[x];
+      const int c = c0w + acc_row_f64(lg, x);
+      if (c < n_pad && r < n_pad) Sj[(size_t)c * n_pad + r] -= a[x];
     }
   }
 }
@@ -325,17 +342,30 @@ __global__ void r_rows_kernel(int n_pad, const double* __restrict__ S, double* _
 // the diagonal, R on and above).  keep_T: T of panel p is kept at
 // Tws[job * (n_pad/32) * 1024 + p * 1024], otherwise every panel reuses
 // Tws[job * 1024].
-static hipError_t qr_factor(int64_t njobs, int n_pad, double* S, double* Tws, bool keep_T, hipStream_t stream) {
-  const int64_t t_stride = keep_T ? (int64_t)(n_pad / 32) * 1024 : 1024;
-  for (int j = 0; j < n_pad; j += 32) {
-    const int t_off = keep_T ? (j / 32) * 1024 : 0;
-    hipLaunchKernelGGL(qr_panel_kernel, dim3((unsigned)njobs), dim3(256), 0, stream, n_pad, j, S, Tws, t_stride, t_off);
-    const int rest = n_pad - j - 32;
+// Blocked Householder QR of the column-stored matrices S (in place: V below
+// the diagonal, R on and above).  Panels of PW columns: 32 for n_pad <= 1024
+// (4 rows per thread in 256 threads), 8 for n_pad <= 4096 (8 rows per thread
+// in 512 threads).  keep_T: the T factor of panel p is kept at
+// Tws[job * n_pad * PW + p * PW^2], otherwise every panel reuses
+// Tws[job * PW^2].
+template <int NT, int MAXQ, int PW>
+static hipError_t qr_factor_t(int64_t njobs, int n_pad, double* S, double* Tws, bool keep_T, hipStream_t stream) {
+  const int64_t t_stride = keep_T ? (int64_t)n_pad * PW : (int64_t)PW * PW;
+  for (int j = 0; j < n_pad; j += PW) {
+    const int64_t t_off = keep_T ? (int64_t)(j / PW) * PW * PW : 0;
+    hipLaunchKernelGGL((qr_panel_kernel<NT, MAXQ, PW>), dim3((unsigned)njobs), dim3(NT), 0, stream, n_pad, j, S, Tws,
+                       t_stride, t_off);
+    const int rest = n_pad - j - PW;
     if (rest > 0)
-      hipLaunchKernelGGL(qr_trailing_kernel, dim3(ceil_div(rest, 64), (unsigned)njobs), dim3(256), 0, stream, n_pad, j,
-                         S, Tws, t_stride, t_off);
+      hipLaunchKernelGGL((qr_trailing_kernel<PW>), dim3(ceil_div(rest, 64), (unsigned)njobs), dim3(256), 0, stream,
+                         n_pad, j, S, Tws, t_stride, t_off);
   }
   return hipGetLastError();
+}
+
+static hipError_t qr_factor(int64_t njobs, int n_pad, double* S, double* Tws, bool keep_T, hipStream_t stream) {
+  if (n_pad <= 1024) return qr_factor_t<256, 4, 32>(njobs, n_pad, S, Tws, keep_T, stream);
+  return qr_factor_t<512, 8, 8>(njobs, n_pad, S, Tws, keep_T, stream);
 }
 
 static hipError_t order_and_unfold(int64_t njobs, int n, int D, int n_pad, const double* T, const int32_t* src,
@@ -356,7 +386,7 @@ hipError_t run_qr_precondition(int64_t njobs, int n, int D, int n_pad, const dou
                                const int32_t* split, int32_t* perm, double* S, double* Tws, double* W,
                                hipStream_t stream) {
   if (njobs == 0) return hipSuccess;
-  if (n_pad > 256 * QR_MAXQ) return hipErrorInvalidValue;
+  if (n_pad > kQrMaxN) return hipErrorInvalidValue;
   hipError_t e = order_and_unfold(njobs, n, D, n_pad, T, src, split, perm, S, stream);
   if (e != hipSuccess) return e;
   e = qr_factor(njobs, n_pad, S, Tws, false, stream);
@@ -373,7 +403,7 @@ hipError_t run_qr2_precondition(int64_t njobs, int n, int D, int n_pad, const do
                                 const int32_t* split, int32_t* perm, double* S1, double* Tws1, double* W1,
                                 double* Tws2, double* W2, hipStream_t stream) {
   if (njobs == 0) return hipSuccess;
-  if (n_pad > 256 * QR_MAXQ) return hipErrorInvalidValue;
+  if (n_pad > kQrMaxN) return hipErrorInvalidValue;
   hipError_t e = order_and_unfold(njobs, n, D, n_pad, T, src, split, perm, S1, stream);
   if (e != hipSuccess) return e;
   e = qr_factor(njobs, n_pad, S1, Tws1, true, stream);
@@ -390,6 +420,7 @@ hipError_t run_qr2_precondition(int64_t njobs, int n, int D, int n_pad, const do
 // result, Q1 = prod_p (I - V_p T_p V_p^T) applied from the last panel to the
 // first; F[:, a] = w_a u_a.  One workgroup per (a, job).
 // ---------------------------------------------------------------------------
+template <int MAXQ, int PW>
 __global__ __launch_bounds__(256) void apply_q1_kernel(int n, int n_pad, int kcap, const double* __restrict__ S1,
                                                        const double* __restrict__ Tws1, const double* __restrict__ W2,
                                                        const double* __restrict__ sigma,
@@ -409,42 +440,42 @@ __global__ __launch_bounds__(256) void apply_q1_kernel(int n, int n_pad, int kca
   const double s = sigma[(size_t)job * n + i];
   const double* row = W2 + (size_t)job * n_pad * n_pad + (size_t)order[(size_t)job * n + i] * n_pad;
   const double* Sj = S1 + (size_t)job * n_pad * n_pad;
-  const double* Tj = Tws1 + (size_t)job * (n_pad / 32) * 1024;
-  __shared__ double x[1024];
+  const double* Tj = Tws1 + (size_t)job * n_pad * PW;
+  __shared__ double x[4096];
   __shared__ double red[5][33];
-  __shared__ double y2[32];
+  __shared__ double y2[PW];
   for (int r = tid; r < n_pad; r += 256) x[r] = row[r] / s;
   __syncthreads();
-  for (int j = n_pad - 32; j >= 0; j -= 32) {
-    double vv[QR_MAXQ][32];
-    double part[32];
+  for (int j = n_pad - PW; j >= 0; j -= PW) {
+    double vv[MAXQ][PW];
+    double part[PW];
 #pragma unroll
-    for (int c = 0; c < 32; ++c) part[c] = 0.0;
+    for (int c = 0; c < PW; ++c) part[c] = 0.0;
 #pragma unroll
-    for (int q = 0; q < QR_MAXQ; ++q) {
+    for (int q = 0; q < MAXQ; ++q) {
       const int r = j + tid + 256 * q;
 #pragma unroll
-      for (int c = 0; c < 32; ++c) {
+      for (int c = 0; c < PW; ++c) {
         const int d = j + c;
         const double v = (r < n_pad && r > d) ? Sj[(size_t)d * n_pad + r] : (r == d ? 1.0 : 0.0);
         vv[q][c] = v;
         if (r < n_pad) part[c] += v * x[r];
       }
     }
-    block_reduce_vec(part, 32, red, tid);
-    if (tid < 32) {
+    block_reduce_vec<256>(part, PW, red, tid);
+    if (tid < PW) {
       double t = 0.0;
-      for (int p = tid; p < 32; ++p) t += Tj[(j / 32) * 1024 + tid * 32 + p] * red[0][p];
+      for (int p = tid; p < PW; ++p) t += Tj[(j / PW) * PW * PW + tid * PW + p] * red[0][p];
       y2[tid] = t;
     }
     __syncthreads();
 #pragma unroll
-    for (int q = 0; q < QR_MAXQ; ++q) {
+    for (int q = 0; q < MAXQ; ++q) {
       const int r = j + tid + 256 * q;
       if (r < n_pad) {
         double acc = 0.0;
 #pragma unroll
-        for (int c = 0; c < 32; ++c) acc += vv[q][c] * y2[c];
+        for (int c = 0; c < PW; ++c) acc += vv[q][c] * y2[c];
         x[r] -= acc;
       }
     }
@@ -458,8 +489,12 @@ hipError_t launch_apply_q1(int64_t njobs, int n, int n_pad, int kcap, const doub
                            const double* W2, const double* sigma, const int32_t* order, const int32_t* kept,
                            const int32_t* sel, const double* weight, double* F, hipStream_t stream) {
   if (njobs == 0) return hipSuccess;
-  hipLaunchKernelGGL(apply_q1_kernel, dim3(kcap, (unsigned)njobs), dim3(256), 0, stream, n, n_pad, kcap, S1, Tws1, W2,
-                     sigma, order, kept, sel, weight, F);
+  if (n_pad <= 1024)
+    hipLaunchKernelGGL((apply_q1_kernel<4, 32>), dim3(kcap, (unsigned)njobs), dim3(256), 0, stream, n, n_pad, kcap, S1,
+                       Tws1, W2, sigma, order, kept, sel, weight, F);
+  else
+    hipLaunchKernelGGL((apply_q1_kernel<16, 8>), dim3(kcap, (unsigned)njobs), dim3(256), 0, stream, n, n_pad, kcap, S1,
+                       Tws1, W2, sigma, order, kept, sel, weight, F);
   return hipGetLastError();
 }
 

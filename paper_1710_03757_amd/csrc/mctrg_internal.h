@@ -122,13 +122,14 @@ hipError_t run_deflate(int64_t njobs, int n_pad, const double* Win, double* Wout
 // unfolding by decreasing norm, S (n_pad^2 per job) holds M P column-wise
 // and is overwritten by V and R, Tws (1024 per job) is scratch, and W
 // receives the rows of R.  split 2 = plain row-major n x n matrices.
-constexpr int kQrMaxN = 1024;
+constexpr int kQrMaxN = 4096;
 hipError_t run_qr_precondition(int64_t njobs, int n, int D, int n_pad, const double* T, const int32_t* src,
                                const int32_t* split, int32_t* perm, double* S, double* Tws, double* W,
                                hipStream_t stream);
 hipError_t launch_iota(int64_t njobs, int n_pad, int32_t* perm, hipStream_t stream);
-// Two-QR form: M P = Q1 R1 (V1 in S1, panel T factors in Tws1: (n_pad/32)*1024
-// per job), R1^T = Q2 R2 (W1 scratch, Tws2 1024 per job), W2 = rows of R2.
+// Two-QR form: M P = Q1 R1 (V1 in S1, panel T factors in Tws1: n_pad * PW
+// <= 32768 per job), R1^T = Q2 R2 (W1 scratch, Tws2 1024 per job), W2 = rows
+// of R2.
 hipError_t run_qr2_precondition(int64_t njobs, int n, int D, int n_pad, const double* T, const int32_t* src,
                                 const int32_t* split, int32_t* perm, double* S1, double* Tws1, double* W1,
                                 double* Tws2, double* W2, hipStream_t stream);

@@ -86,14 +86,12 @@ def test_c2_beta_sweep_parity():
         # term sqrt(s_i/r_i) then dominates T' while any FP64 SVD fixes s_i
         # only to ~n eps s_1/s_i relative, so ln c agree to ~1e-5 there.
         assert np.allclose(lnc[i, :8], o.ln_c[:8], rtol=1e-11, atol=1e-14), b
-        rel = np.max(np.abs(lnc[i, 8:sf] - np.asarray(o.ln_c[8:sf])) / np.abs(np.asarray(o.ln_c[8:sf])),
-                     initial=0.0)
-        worst.append(rel)
+        worst.append(np.max(np.abs(lnc[i, 8:sf] - np.asarray(o.ln_c[8:sf])), initial=0.0))
         if sf == 20:
             # late steps enter ln Z/site with weight 2^-(s+1): 1e-3 there is < 1e-6 per site
             assert abs(ln[i] - o.ln_abs_Z) / N < 1e-6, (b, ln[i] / N, o.ln_abs_Z / N)
     log(f"C2: first selection flip per chain (20 = none): {first_flips}; "
-        f"max relative ln c difference after step 8: {max(worst):.2e}")
+        f"max |d ln c| after step 8 before the flip: {max(worst):.2e}")
 
 
 def test_c3_mixed_k_parity():
