@@ -106,6 +106,9 @@ def main():
     ap.add_argument("--chain-steps", type=int, default=30)
     ap.add_argument("--cpu-samples", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe-mb", type=int, default=0,
+                    help="after the timed region, copy this many MiB device-to-device (a plain copy kernel of known "
+                         "size whose counter readings calibrate FETCH_SIZE / WRITE_SIZE)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -205,6 +208,13 @@ def main():
                            "signs_equal": bool(all(int(sg[i]) == o[0] for i, o in enumerate(ores))),
                            "lattice_sites": N, "note": "same Philox draws; GPU contraction in "
                                                        f"{args.dtype}, oracle FP64"}
+    if args.copy_probe_mb:
+        src = torch.ones(args.copy_probe_mb * (1 << 20) // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_probe_bytes"] = args.copy_probe_mb * (1 << 20)
     print(json.dumps(out), flush=True)
     chain.close()
 

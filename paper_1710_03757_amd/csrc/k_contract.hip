@@ -218,10 +218,29 @@ __global__ __launch_bounds__(256) void gemm_tn_kernel(int M, int N, int K, const
 #pragma unroll
     for (int j = 0; j < WT; ++j) acc[i][j] = frag_c{0, 0, 0, 0};
 
+  // Tile-aligned shapes (the steady state): 16-byte loads with the lanes along
+  // K, so every wave reads whole 64..256-byte row segments.  Other shapes use
+  // masked element loads.
+  constexpr int VB = 16 / (int)sizeof(elt);   // elements per 16-byte vector
+  constexpr int LPR = BK / VB;                // lanes per tile row
+  constexpr int RPI = 256 / LPR;              // tile rows per pass
+  constexpr int ITERS = BM / RPI;
+  const bool vec = (M % BM == 0) && (N % BM == 0) && (K % BK == 0);
+  const int vrow = tid / LPR, vk = (tid % LPR) * VB;
+  uint4 va[ITERS], vb[ITERS];
   // thread t loads LOADS consecutive K elements of row (t * LOADS) / BK
   const int lrow = (tid * LOADS) / BK, lk = (tid * LOADS) % BK;
   elt ra[LOADS], rb[LOADS];
   auto gload = [&](int k0) {
+    if (vec) {
+#pragma unroll
+      for (int it = 0; it < ITERS; ++it) {
+        const int row = it * RPI + vrow;
+        va[it] = *reinterpret_cast<const uint4*>(A + (size_t)(m0 + row) * K + k0 + vk);
+        vb[it] = *reinterpret_cast<const uint4*>(B + (size_t)(n0 + row) * K + k0 + vk);
+      }
+      return;
+    }
     const int gm = m0 + lrow, gn = n0 + lrow;
 #pragma unroll
     for (int x = 0; x < LOADS; ++x) {
@@ -230,13 +249,30 @@ __global__ __launch_bounds__(256) void gemm_tn_kernel(int M, int N, int K, const
       rb[x] = (gn < N && gk < K) ? B[(size_t)gn * K + gk] : elt(0);
     }
   };
-  gload(0);
-  for (int k0 = 0; k0 < K; k0 += BK) {
+  auto lstore = [&]() {
+    if (vec) {
+#pragma unroll
+      for (int it = 0; it < ITERS; ++it) {
+        const int row = it * RPI + vrow;
+        const elt* ea = reinterpret_cast<const elt*>(&va[it]);
+        const elt* eb = reinterpret_cast<const elt*>(&vb[it]);
+#pragma unroll
+        for (int v = 0; v < VB; ++v) {
+          As[row * LD + vk + v] = ea[v];
+          Bs[row * LD + vk + v] = eb[v];
+        }
+      }
+      return;
+    }
 #pragma unroll
     for (int x = 0; x < LOADS; ++x) {
       As[lrow * LD + lk + x] = ra[x];
       Bs[lrow * LD + lk + x] = rb[x];
     }
+  };
+  gload(0);
+  for (int k0 = 0; k0 < K; k0 += BK) {
+    lstore();
     __syncthreads();
     if (k0 + BK < K) gload(k0 + BK);    // next K tile in flight during the MFMAs
 #pragma unroll
