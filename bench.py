@@ -137,10 +137,12 @@ def main():
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
     ev0.record()
-    sweeps = []
+    sweeps, pair_hist = [], []
     for s in range(args.steps):
         chain.step(1)
-        sweeps.append(chain.profile()["last_sweeps"])
+        pr = chain.profile()
+        sweeps.append(pr["last_sweeps"])
+        pair_hist.append(pr["last_pairs"])
     res = chain.finish()
     est = m.estimate_lnZ(res.sign, res.ln_abs_Z, 2.0 ** (args.warmup + args.steps))
     ev1.record()
@@ -193,6 +195,7 @@ def main():
         "roofline": roofline,
         "mfma_contraction": gemm,
         "jacobi_sweeps_per_step": sweeps,
+        "jacobi_rotated_pairs_per_sweep": pair_hist,
         "estimate_partial_chain": {k2: est[k2] for k2 in ("mean_lnZ_per_site", "stderr_mean_lnZ", "n_failed")},
     }
 

@@ -188,6 +188,10 @@ typedef struct {
   int64_t gemm_launches;
   int32_t steps_done;
   int32_t last_sweeps;      /* Jacobi sweeps used by the last step               */
+  int32_t last_pairs[64];   /* last step, per sweep: block pairs that rotated,
+                               summed over all decompositions of the step       */
+  int32_t last_active[64];  /* last step, per sweep: decompositions still
+                               rotating after that sweep                        */
 } mctrg_chain_profile;
 /* Timings are collected only when cfg->flags has MCTRG_PROFILE. */
 int mctrg_chain_get_profile(const mctrg_chain* ch, mctrg_chain_profile* out);

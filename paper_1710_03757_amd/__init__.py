@@ -60,10 +60,15 @@ class Estimate(ctypes.Structure):
 
 class ChainProfile(ctypes.Structure):
     _fields_ = [("jacobi_ms", ctypes.c_double), ("jacobi_launches", ctypes.c_int64), ("gemm_ms", ctypes.c_double),
-                ("gemm_launches", ctypes.c_int64), ("steps_done", ctypes.c_int32), ("last_sweeps", ctypes.c_int32)]
+                ("gemm_launches", ctypes.c_int64), ("steps_done", ctypes.c_int32), ("last_sweeps", ctypes.c_int32),
+                ("last_pairs", ctypes.c_int32 * 64), ("last_active", ctypes.c_int32 * 64)]
 
     def as_dict(self):
-        return {f: getattr(self, f) for f, _ in self._fields_}
+        d = {f: getattr(self, f) for f, _ in self._fields_}
+        n = max(0, min(64, self.last_sweeps))
+        d["last_pairs"] = list(self.last_pairs)[:n]
+        d["last_active"] = list(self.last_active)[:n]
+        return d
 
 
 _vp, _i32, _i64, _u64, _f64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_double

@@ -176,6 +176,7 @@ struct Chain {
   int64_t max_jobs = 0, max_out = 0;
   KernelTimer tj, tg;
   int last_sweeps = 0;
+  int sweep_hist[2 * kMaxSweeps] = {};   // last decomposition: (pairs rotated, jobs active) per sweep
 
   ~Chain() {
     if (mem) (void)hipFree(mem);
@@ -264,7 +265,7 @@ void layout(Chain& c, Arena& ar) {
   c.jw.active = ar.take<int>(jmax);
   c.jw.rotated = ar.take<int>(jmax);
   c.jw.sweeps = ar.take<int>(jmax);
-  c.jw.counter = ar.take<int>(1);
+  c.jw.counter = ar.take<int>(2);
   c.nb_job = ar.take<int>(jmax);
 }
 
@@ -318,7 +319,7 @@ int chain_start(Chain& c, const mctrg_tensor_set* ts, const std::vector<int32_t>
   ar.counting = false;
   layout(c, ar);
   const int64_t J = c.max_jobs, O = c.max_out;
-  const size_t hb = sizeof(int32_t) * (2 * J + 4 * O) + sizeof(uint64_t) * 3 * J + sizeof(int) + 64;
+  const size_t hb = sizeof(int32_t) * (2 * J + 4 * O) + sizeof(uint64_t) * 3 * J + 2 * sizeof(int) + 64;
   if (hipHostMalloc(&c.pin.p, hb, hipHostMallocDefault) != hipSuccess) return MCTRG_ENOMEM;
   char* hp = reinterpret_cast<char*>(c.pin.p);
   c.h_rng = reinterpret_cast<uint64_t*>(hp);
@@ -415,7 +416,7 @@ int chain_step(Chain& c) {
   int nb_max = 0;
   CKH(run_deflate(nj, sh.n_pad, c.W2, Wj, c.nb_job, c.jw.counter, c.jw.counter_host, &nb_max, c.st));
   CKH(run_jacobi(nj, sh.n_pad, Wj, c.jw, kMaxSweeps, c.st, c.tj.enabled ? &c.tj : nullptr, &c.last_sweeps, c.nb_job,
-                 nb_max));
+                 nb_max, c.sweep_hist));
   CKH(launch_jacobi_fail(nj, sh.jps, c.jw.sweeps, c.failed, c.st));
   CKH(launch_jacobi_finalize(nj, sh.n, sh.n_pad, Wj, c.sigma, c.order, c.st));
   SampleArgs sa{};
@@ -750,6 +751,11 @@ int mctrg_chain_get_profile(const mctrg_chain* ch, mctrg_chain_profile* out) {
   out->gemm_launches = ch->c.tg.launches;
   out->steps_done = ch->c.step;
   out->last_sweeps = ch->c.last_sweeps;
+  for (int s = 0; s < 64; ++s) {
+    const bool in = s < ch->c.last_sweeps && s < kMaxSweeps;
+    out->last_pairs[s] = in ? ch->c.sweep_hist[2 * s] : 0;
+    out->last_active[s] = in ? ch->c.sweep_hist[2 * s + 1] : 0;
+  }
   return MCTRG_OK;
 }
 
@@ -797,7 +803,7 @@ int mctrg_svd_batched(int64_t n_mats, int32_t d1, int32_t d2, const double* M, d
     (void)ar.take<int32_t>((size_t)n_mats * n);   // order
     (void)ar.take<int32_t>((size_t)n_mats * n_pad);  // perm
     (void)ar.take<int32_t>(2 * n_mats);           // src, split
-    (void)ar.take<int>(3 * n_mats + 1);           // jacobi work
+    (void)ar.take<int>(3 * n_mats + 2);           // jacobi work
     if (pass == 0) break;
   }
   char* mem = nullptr;
@@ -812,7 +818,7 @@ int mctrg_svd_batched(int64_t n_mats, int32_t d1, int32_t d2, const double* M, d
   int32_t* order = a2.take<int32_t>((size_t)n_mats * n);
   int32_t* perm = a2.take<int32_t>((size_t)n_mats * n_pad);
   int32_t* ss = a2.take<int32_t>(2 * n_mats);
-  int* jws = a2.take<int>(3 * n_mats + 1);
+  int* jws = a2.take<int>(3 * n_mats + 2);
   std::vector<int32_t> hs(2 * n_mats);
   for (int64_t i = 0; i < n_mats; ++i) { hs[i] = (int32_t)i; hs[n_mats + i] = 2; }
   JacobiWork wk{jws, jws + n_mats, jws + 2 * n_mats, jws + 3 * n_mats, reinterpret_cast<int*>(pin.p)};

@@ -9,9 +9,10 @@
 // singular vectors of M and sigma_i its singular values; left vectors follow
 // as u_i = M v_i / sigma_i (see the factor kernels).
 //
-// Rows are grouped into blocks of 16; a sweep visits every pair of blocks
-// once, in nb-1 rounds of nb/2 disjoint pairs (circle ordering).  One
-// workgroup handles one (job, pair):
+// Rows are grouped into blocks of 16 (32 when n_pad is a multiple of 64, see
+// jacobi_round64_kernel); a sweep visits every pair of blocks once, in nb-1
+// rounds of nb/2 disjoint pairs (circle ordering).  One workgroup handles one
+// (job, pair); for 16-row blocks:
 //   1. Gram G = W_pair W_pair^T (32 x 32) with v_mfma_f64_16x16x4, each wave
 //      streaming a quarter of the row length from HBM;
 //   2. if some |g_ij| > tol * sqrt(g_ii g_jj): two cyclic Jacobi sweeps on G
@@ -33,7 +34,8 @@ __device__ __forceinline__ int circle_block(int pos, int r, int nb) {
 __global__ __launch_bounds__(256) void jacobi_round_kernel(double* __restrict__ W, int n_pad, int nb_all,
                                                            const int* __restrict__ nb_job, int round,
                                                            const int* __restrict__ active,
-                                                           int* __restrict__ rotated, double tol) {
+                                                           int* __restrict__ rotated, int* __restrict__ pairs,
+                                                           double tol) {
   const int job = blockIdx.y;
   if (!active[job]) return;
   // rows beyond the job's active blocks sit below the noise floor and stay
@@ -113,7 +115,7 @@ __global__ __launch_bounds__(256) void jacobi_round_kernel(double* __restrict__ 
   __syncthreads();
   off = fmax(fmax(redbuf[0], redbuf[1]), fmax(redbuf[2], redbuf[3]));
   if (!(off > tol)) return;            // pair already orthogonal (uniform)
-  if (tid == 0) atomicOr(&rotated[job], 1);
+  if (tid == 0) { atomicOr(&rotated[job], 1); atomicAdd(pairs, 1); }
 
   // ---- 2. cyclic Jacobi on G, accumulating Q ------------------------------
   // Two inner sweeps are enough: the outer iteration recomputes the pair's
@@ -222,6 +224,271 @@ __global__ __launch_bounds__(256) void jacobi_round_kernel(double* __restrict__ 
   }
 }
 
+// ---------------------------------------------------------------------------
+// The same rotation step with 32-row blocks (pairs of 64 rows), used when
+// n_pad is a multiple of 64.  A sweep then takes nb - 1 = n_pad/32 - 1
+// rounds instead of n_pad/16 - 1, which halves the HBM traffic per sweep
+// (every round streams each active row through the Gram and update passes).
+//   1. Gram G (64 x 64): the ten distinct 16 x 16 tiles of the four 16-row
+//      sub-blocks, each wave over a quarter of the row length, partial tiles
+//      summed through LDS in a fixed order;
+//   2. one cyclic Jacobi sweep on G (63 rounds of 32 disjoint rotations).
+//      All rotations of a round are applied at once: every 2 x 2 block
+//      (rows p_i, q_i; columns p_j, q_j) of G becomes J_i^T A J_j, which
+//      needs no intermediate barrier; diagonal blocks take the exact
+//      (g_pp - t g_pq, g_qq + t g_pq, 0) form;
+//   3. W_pair <- Q^T W_pair with v_mfma_f64_16x16x4 (Q^T fragments in
+//      registers).
+// One inner sweep is enough: the outer iteration recomputes the Gram from
+// the rows, and a second inner sweep did not reduce the number of outer
+// sweeps on TRG unfoldings.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256, 2) void jacobi_round64_kernel(double* __restrict__ W, int n_pad, int nb_all,
+                                                                const int* __restrict__ nb_job, int round,
+                                                                const int* __restrict__ active,
+                                                                int* __restrict__ rotated, int* __restrict__ pairs,
+                                                                double tol) {
+  const int job = blockIdx.y;
+  if (!active[job]) return;
+  const int nb = nb_job ? nb_job[job] : nb_all;   // 32-row blocks
+  const int pair = blockIdx.x;
+  if (round >= nb - 1 || pair >= nb / 2) return;
+  const int I = circle_block(pair, round, nb);
+  const int J = circle_block(nb - 1 - pair, round, nb);
+  double* Wj = W + (size_t)job * n_pad * n_pad;
+  double* rowI = Wj + (size_t)(32 * I) * n_pad;
+  double* rowJ = Wj + (size_t)(32 * J) * n_pad;
+
+  __shared__ double G[64][65];
+  __shared__ double Qs[64 * 65];   // Q; before that, staging of partial Gram tiles
+  double(*Q)[65] = reinterpret_cast<double(*)[65]>(Qs);
+  double(*stage)[5][256] = reinterpret_cast<double(*)[5][256]>(Qs);   // [wave-1][tile][16x16]
+  __shared__ double2 rcs[32], rdd[32];   // (c, s) and (g_pp', g_qq') of the round's rotations
+  __shared__ int2 rpq[32];                // (p, q), p < q
+  __shared__ double redbuf[4];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int lr = lane & 15, lg = lane >> 4;
+
+  // ---- 1. Gram ------------------------------------------------------------
+  // sub-block sb: rows 16 sb .. 16 sb + 15 of the pair
+  const double* sub[4] = {rowI, rowI + (size_t)16 * n_pad, rowJ, rowJ + (size_t)16 * n_pad};
+  f64x4 acc[10];
+#pragma unroll
+  for (int t = 0; t < 10; ++t) acc[t] = f64x4{0, 0, 0, 0};
+  double cur[4][4], nxt[4][4];
+  auto load_chunk = [&](int k0, double (&v)[4][4]) {
+#pragma unroll
+    for (int sb = 0; sb < 4; ++sb) {
+      const double* p = sub[sb] + (size_t)lr * n_pad + k0 + 4 * lg;
+      double2 a01 = *reinterpret_cast<const double2*>(p);
+      double2 a23 = *reinterpret_cast<const double2*>(p + 2);
+      v[sb][0] = a01.x; v[sb][1] = a01.y; v[sb][2] = a23.x; v[sb][3] = a23.y;
+    }
+  };
+  int k0 = 16 * wave;
+  if (k0 < n_pad) load_chunk(k0, cur);
+  for (; k0 < n_pad; k0 += 64) {
+    if (k0 + 64 < n_pad) load_chunk(k0 + 64, nxt);
+#pragma unroll
+    for (int jj = 0; jj < 4; ++jj) {
+      int t = 0;
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = a; b < 4; ++b) {
+          acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(cur[a][jj], cur[b][jj], acc[t], 0, 0, 0);
+          ++t;
+        }
+    }
+#pragma unroll
+    for (int sb = 0; sb < 4; ++sb)
+#pragma unroll
+      for (int jj = 0; jj < 4; ++jj) cur[sb][jj] = nxt[sb][jj];
+  }
+  // partial tiles: waves 1..3 stage five tiles at a time, wave 0 sums
+#pragma unroll
+  for (int half = 0; half < 2; ++half) {
+    if (wave > 0) {
+#pragma unroll
+      for (int t = 5 * half; t < 5 * half + 5; ++t)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) stage[wave - 1][t - 5 * half][acc_row_f64(lg, i) * 16 + lr] = acc[t][i];
+    }
+    __syncthreads();
+    if (wave == 0) {
+      int t = 0;
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = a; b < 4; ++b) {
+          if (t >= 5 * half && t < 5 * half + 5) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              const int row = acc_row_f64(lg, i), idx = row * 16 + lr;
+              const double v = ((acc[t][i] + stage[0][t - 5 * half][idx]) + stage[1][t - 5 * half][idx]) +
+                               stage[2][t - 5 * half][idx];
+              G[16 * a + row][16 * b + lr] = v;
+              G[16 * b + lr][16 * a + row] = v;
+            }
+          }
+          ++t;
+        }
+    }
+    __syncthreads();
+  }
+
+  // ---- convergence test of this pair ------------------------------------
+  double off = 0.0;
+  for (int e = tid; e < 4096; e += 256) {
+    const int i = e >> 6, j = e & 63;
+    if (i < j) {
+      const double d = G[i][i] * G[j][j];
+      if (d > 0.0) off = fmax(off, fabs(G[i][j]) / sqrt(d));
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1) off = fmax(off, __shfl_xor(off, o));
+  if (lane == 0) redbuf[wave] = off;
+  for (int e = tid; e < 4096; e += 256) Q[e >> 6][e & 63] = ((e >> 6) == (e & 63)) ? 1.0 : 0.0;
+  __syncthreads();
+  off = fmax(fmax(redbuf[0], redbuf[1]), fmax(redbuf[2], redbuf[3]));
+  if (!(off > tol)) return;            // pair already orthogonal (uniform)
+  if (tid == 0) { atomicOr(&rotated[job], 1); atomicAdd(pairs, 1); }
+
+  // ---- 2. one cyclic Jacobi sweep on G, accumulating Q --------------------
+  // Every thread first issues all its LDS loads of a round, then computes and
+  // stores, so that the round costs one LDS round trip per phase.
+  const double tol_in2 = 0x1.0p-106;   // (2^-53)^2
+  for (int r = 0; r < 63; ++r) {
+    if (tid < 32) {
+      int p = tid == 0 ? 0 : 1 + (tid - 1 + r) % 63;
+      int q = 1 + (63 - tid - 1 + r) % 63;
+      if (p > q) { const int tmp = p; p = q; q = tmp; }
+      const double gpp = G[p][p], gqq = G[q][q], gpq = G[p][q];
+      double c = 1.0, s = 0.0, dp = gpp, dq = gqq;
+      // |.| guards the tiny diagonal entries that rounding can push below 0
+      if (gpq != 0.0 && gpq * gpq > tol_in2 * fabs(gpp * gqq)) {
+        const double theta = (gqq - gpp) / (2.0 * gpq);
+        const double t = (fabs(theta) > 1e150) ? 0.5 / theta
+                                               : copysign(1.0, theta) / (fabs(theta) + sqrt(1.0 + theta * theta));
+        c = 1.0 / sqrt(1.0 + t * t);
+        s = t * c;
+        dp = gpp - t * gpq;
+        dq = gqq + t * gpq;
+      }
+      rpq[tid] = make_int2(p, q);
+      rcs[tid] = make_double2(c, s);
+      rdd[tid] = make_double2(dp, dq);
+    }
+    __syncthreads();
+    // (a) G <- J^T G J block by block.  The 528 blocks (i <= j) of the
+    // 32 x 32 block grid are enumerated as 16 folded rows of 33 (row m and
+    // row 31 - m); thread tid takes blocks tid, tid + 256 and tid + 512.
+    int bi[3], bj[3];
+    bool bv[3];
+#pragma unroll
+    for (int u = 0; u < 3; ++u) {
+      const int e = tid + 256 * u;
+      bv[u] = e < 528;
+      const int m = e / 33, o = e - 33 * m;
+      if (o < 32 - m) { bi[u] = m; bj[u] = m + o; }
+      else { bi[u] = 31 - m; bj[u] = 31 - m + (o - (32 - m)); }
+    }
+    int2 pi[3], pj[3];
+    double2 ci[3], cj[3];
+    double ga[3], gb[3], gc[3], gd[3];
+#pragma unroll
+    for (int u = 0; u < 3; ++u) {
+      if (bv[u]) {
+        pi[u] = rpq[bi[u]]; pj[u] = rpq[bj[u]];
+        ci[u] = rcs[bi[u]]; cj[u] = rcs[bj[u]];
+      }
+    }
+    // (b) Q <- Q J: thread tid rotates columns (p, q) of pair tid / 8 in
+    // rows tid % 8 + 8 h
+    const int qi = tid >> 3, q0 = tid & 7;
+    const int2 qpq = rpq[qi];
+    const double2 qcs = rcs[qi];
+    double qv[8][2];
+    if (qcs.y != 0.0) {
+#pragma unroll
+      for (int h = 0; h < 8; ++h) { qv[h][0] = Q[q0 + 8 * h][qpq.x]; qv[h][1] = Q[q0 + 8 * h][qpq.y]; }
+    }
+#pragma unroll
+    for (int u = 0; u < 3; ++u) {
+      if (bv[u] && bi[u] != bj[u] && (ci[u].y != 0.0 || cj[u].y != 0.0)) {
+        ga[u] = G[pi[u].x][pj[u].x]; gb[u] = G[pi[u].x][pj[u].y];
+        gc[u] = G[pi[u].y][pj[u].x]; gd[u] = G[pi[u].y][pj[u].y];
+      }
+    }
+    double2 dd[3];
+#pragma unroll
+    for (int u = 0; u < 3; ++u)
+      if (bv[u] && bi[u] == bj[u] && ci[u].y != 0.0) dd[u] = rdd[bi[u]];
+    // all loads issued; compute and store
+#pragma unroll
+    for (int u = 0; u < 3; ++u) {
+      if (!bv[u]) continue;
+      const int pa = pi[u].x, qa_ = pi[u].y, pb = pj[u].x, qb = pj[u].y;
+      if (bi[u] == bj[u]) {
+        if (ci[u].y != 0.0) {
+          G[pa][pa] = dd[u].x;
+          G[qa_][qa_] = dd[u].y;
+          G[pa][qa_] = 0.0;
+          G[qa_][pa] = 0.0;
+        }
+      } else if (ci[u].y != 0.0 || cj[u].y != 0.0) {
+        const double c_i = ci[u].x, s_i = ci[u].y, c_j = cj[u].x, s_j = cj[u].y;
+        // A J_j: columns (p, q) -> (c p - s q, s p + c q)
+        const double a1 = c_j * ga[u] - s_j * gb[u], b1 = s_j * ga[u] + c_j * gb[u];
+        const double c1 = c_j * gc[u] - s_j * gd[u], d1 = s_j * gc[u] + c_j * gd[u];
+        // J_i^T (A J_j): rows (p, q) -> (c p - s q, s p + c q)
+        const double a2 = c_i * a1 - s_i * c1, c2 = s_i * a1 + c_i * c1;
+        const double b2 = c_i * b1 - s_i * d1, d2 = s_i * b1 + c_i * d1;
+        G[pa][pb] = a2; G[pa][qb] = b2; G[qa_][pb] = c2; G[qa_][qb] = d2;
+        G[pb][pa] = a2; G[qb][pa] = b2; G[pb][qa_] = c2; G[qb][qa_] = d2;
+      }
+    }
+    if (qcs.y != 0.0) {
+#pragma unroll
+      for (int h = 0; h < 8; ++h) {
+        Q[q0 + 8 * h][qpq.x] = qcs.x * qv[h][0] - qcs.y * qv[h][1];
+        Q[q0 + 8 * h][qpq.y] = qcs.y * qv[h][0] + qcs.x * qv[h][1];
+      }
+    }
+    __syncthreads();
+  }
+
+  // ---- 3. W_pair <- Q^T W_pair ------------------------------------------
+  // A fragment of output tile t, k-step s: lane (lr, lg) holds
+  // (Q^T)[16 t + lr][4 s + lg] = Q[4 s + lg][16 t + lr].
+  double qa[4][16];
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+#pragma unroll
+    for (int s = 0; s < 16; ++s) qa[t][s] = Q[4 * s + lg][16 * t + lr];
+
+  auto row_ptr = [&](int r) -> double* {
+    return r < 32 ? rowI + (size_t)r * n_pad : rowJ + (size_t)(r - 32) * n_pad;
+  };
+  for (int c0 = 16 * wave; c0 < n_pad; c0 += 64) {
+    double bc[16];
+#pragma unroll
+    for (int s = 0; s < 16; ++s) bc[s] = row_ptr(4 * s + lg)[c0 + lr];
+    f64x4 out[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) out[t] = f64x4{0, 0, 0, 0};
+#pragma unroll
+    for (int s = 0; s < 16; ++s)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) out[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(qa[t][s], bc[s], out[t], 0, 0, 0);
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) row_ptr(16 * t + acc_row_f64(lg, i))[c0 + lr] = out[t][i];
+  }
+}
+
 __global__ void jacobi_init_kernel(int64_t njobs, int* active, int* rotated, int* sweeps) {
   int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (j < njobs) { active[j] = 1; rotated[j] = 0; sweeps[j] = -1; }
@@ -241,7 +508,7 @@ __global__ void jacobi_sweep_end_kernel(int64_t njobs, int sweep, int* active, i
   if ((threadIdx.x & 63) == 0 && m) atomicAdd(counter, __popcll(m));
 }
 
-__global__ void zero_int_kernel(int* p) { *p = 0; }
+__global__ void zero_int_kernel(int* p) { p[threadIdx.x] = 0; }
 
 hipError_t KernelTimer::begin(hipStream_t s) {
   if (!enabled) return hipSuccess;
@@ -280,24 +547,30 @@ hipError_t KernelTimer::collect() {
 }
 
 hipError_t run_jacobi(int64_t njobs, int n_pad, double* W, const JacobiWork& wk, int max_sweeps,
-                      hipStream_t stream, KernelTimer* timer, int* sweeps_done, const int* nb_job, int nb_max) {
+                      hipStream_t stream, KernelTimer* timer, int* sweeps_done, const int* nb_job, int nb_max,
+                      int* history) {
   if (njobs == 0) return hipSuccess;
-  const int nb = nb_job ? nb_max : n_pad / 16;
+  const int brows = jacobi_block_rows(n_pad);
+  const int nb = nb_job ? nb_max : n_pad / brows;
   const double tol = fmax(32.0, 8.0 * sqrt((double)n_pad)) * 0x1.0p-53;
   int g = ceil_div(njobs, 256);
   hipLaunchKernelGGL(jacobi_init_kernel, dim3(g), dim3(256), 0, stream, njobs, wk.active, wk.rotated,
                      wk.sweeps);
   for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+    hipLaunchKernelGGL(zero_int_kernel, dim3(1), dim3(2), 0, stream, wk.counter);
     for (int r = 0; r < nb - 1; ++r) {
       if (timer) { hipError_t e = timer->begin(stream); if (e != hipSuccess) return e; }
-      hipLaunchKernelGGL(jacobi_round_kernel, dim3(nb / 2, (unsigned)njobs), dim3(256), 0, stream, W,
-                         n_pad, nb, nb_job, r, wk.active, wk.rotated, tol);
+      if (brows == 32)
+        hipLaunchKernelGGL(jacobi_round64_kernel, dim3(nb / 2, (unsigned)njobs), dim3(256), 0, stream, W,
+                           n_pad, nb, nb_job, r, wk.active, wk.rotated, wk.counter + 1, tol);
+      else
+        hipLaunchKernelGGL(jacobi_round_kernel, dim3(nb / 2, (unsigned)njobs), dim3(256), 0, stream, W,
+                           n_pad, nb, nb_job, r, wk.active, wk.rotated, wk.counter + 1, tol);
       if (timer) { hipError_t e = timer->end(stream); if (e != hipSuccess) return e; }
     }
-    hipLaunchKernelGGL(zero_int_kernel, dim3(1), dim3(1), 0, stream, wk.counter);
     hipLaunchKernelGGL(jacobi_sweep_end_kernel, dim3(g), dim3(256), 0, stream, njobs, sweep, wk.active,
                        wk.rotated, wk.sweeps, wk.counter);
-    hipError_t e = hipMemcpyAsync(wk.counter_host, wk.counter, sizeof(int), hipMemcpyDeviceToHost, stream);
+    hipError_t e = hipMemcpyAsync(wk.counter_host, wk.counter, 2 * sizeof(int), hipMemcpyDeviceToHost, stream);
     if (e != hipSuccess) return e;
     e = hipStreamSynchronize(stream);
     if (e != hipSuccess) return e;
@@ -306,6 +579,7 @@ hipError_t run_jacobi(int64_t njobs, int n_pad, double* W, const JacobiWork& wk,
       if (e != hipSuccess) return e;
     }
     if (sweeps_done) *sweeps_done = sweep + 1;
+    if (history) { history[2 * sweep] = wk.counter_host[1]; history[2 * sweep + 1] = wk.counter_host[0]; }
     if (*wk.counter_host == 0) break;
   }
   return hipGetLastError();
@@ -317,10 +591,10 @@ hipError_t run_jacobi(int64_t njobs, int n_pad, double* W, const JacobiWork& wk,
 // rotations: leaving them unrotated perturbs the singular values of the rest
 // by at most their norm (Weyl), i.e. at the rounding level of an FP64 SVD and
 // far below the candidate threshold tau_null * s_1.  nb_job receives the
-// number of 16-row blocks (even, at least 2) that cover the active rows.
+// number of row blocks (even, at least 2) that cover the active rows.
 // One workgroup of 256 threads per job; n_pad <= 4096.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void deflate_rows_kernel(int n_pad, const double* __restrict__ Win,
+__global__ __launch_bounds__(256) void deflate_rows_kernel(int n_pad, int brows, const double* __restrict__ Win,
                                                            double* __restrict__ Wout, int* __restrict__ nb_job) {
   __shared__ double nrm[4096];
   __shared__ int newpos[4096];
@@ -347,7 +621,7 @@ __global__ __launch_bounds__(256) void deflate_rows_kernel(int n_pad, const doub
     for (int r = 0; r < n_pad; ++r) a += nrm[r] > thr ? 1 : 0;
     int ia = 0, ib = a;
     for (int r = 0; r < n_pad; ++r) newpos[r] = nrm[r] > thr ? ia++ : ib++;
-    int nbk = 2 * ((a + 31) / 32);
+    int nbk = 2 * ((a + 2 * brows - 1) / (2 * brows));
     if (nbk < 2) nbk = 2;
     nb_job[job] = nbk;
     cnt_s[0] = a;
@@ -375,7 +649,8 @@ __global__ void max_int_kernel(int64_t n, const int* __restrict__ v, int* __rest
 hipError_t run_deflate(int64_t njobs, int n_pad, const double* Win, double* Wout, int* nb_job, int* scratch_dev,
                        int* scratch_host, int* nb_max, hipStream_t stream) {
   if (njobs == 0) { *nb_max = 2; return hipSuccess; }
-  hipLaunchKernelGGL(deflate_rows_kernel, dim3((unsigned)njobs), dim3(256), 0, stream, n_pad, Win, Wout, nb_job);
+  hipLaunchKernelGGL(deflate_rows_kernel, dim3((unsigned)njobs), dim3(256), 0, stream, n_pad,
+                     jacobi_block_rows(n_pad), Win, Wout, nb_job);
   hipLaunchKernelGGL(max_int_kernel, dim3(1), dim3(1024), 0, stream, njobs, nb_job, scratch_dev);
   hipError_t e = hipMemcpyAsync(scratch_host, scratch_dev, sizeof(int), hipMemcpyDeviceToHost, stream);
   if (e != hipSuccess) return e;

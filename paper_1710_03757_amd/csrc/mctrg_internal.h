@@ -103,16 +103,21 @@ struct KernelTimer {
 };
 
 // One-sided block Jacobi SVD of W[j] (rows are rotated).  Host-driven sweeps.
+// Rows per block of the block Jacobi rotations: 32 (pairs of 64 rows) when
+// n_pad is a multiple of 64, else 16.
+inline int jacobi_block_rows(int n_pad) { return n_pad % 64 == 0 ? 32 : 16; }
 struct JacobiWork {
   int* active;      // njobs
   int* rotated;     // njobs
   int* sweeps;      // njobs (-1 until converged)
-  int* counter;     // device 1 int
-  int* counter_host; // pinned host 1 int
+  int* counter;      // device 2 ints: jobs still rotating, block pairs rotated in the sweep
+  int* counter_host; // pinned host 2 ints
 };
+// history (optional, host, max_sweeps x 2): per sweep, the block pairs that
+// rotated (summed over jobs) and the jobs still rotating after it.
 hipError_t run_jacobi(int64_t njobs, int n_pad, double* W, const JacobiWork& wk, int max_sweeps,
                       hipStream_t stream, KernelTimer* timer = nullptr, int* sweeps_done = nullptr,
-                      const int* nb_job = nullptr, int nb_max = 0);
+                      const int* nb_job = nullptr, int nb_max = 0, int* history = nullptr);
 // Noise-floor deflation: Wout = rows of Win with the active rows (norm >
 // 2^-48 of the largest) first; nb_job = 16-row blocks covering them; the
 // maximum over jobs is returned in *nb_max (synchronises the stream).
