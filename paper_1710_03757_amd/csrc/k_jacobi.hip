@@ -224,6 +224,53 @@ __global__ __launch_bounds__(256) void jacobi_round_kernel(double* __restrict__ 
   }
 }
 
+// Circle ordering on 64 indices: slot t of round r pairs the indices at
+// positions t and 63 - t; position 0 holds index 0, position k >= 1 holds
+// 1 + (k - 1 + r) mod 63.  Returned with p < q; 0 <= t < 32, 0 <= r <= 63.
+__device__ __forceinline__ int mod63_small(int a) {   // a in [0, 189)
+  a = a >= 63 ? a - 63 : a;
+  return a >= 63 ? a - 63 : a;
+}
+__device__ __forceinline__ void circle_pair64(int t, int r, int& p, int& q) {
+  const int a = t == 0 ? 0 : 1 + mod63_small(t - 1 + r);
+  const int b = 1 + mod63_small(62 - t + r);
+  p = min(a, b);
+  q = max(a, b);
+}
+// Slot of index x in round r (0 <= r <= 63).
+__device__ __forceinline__ int circle_slot64(int x, int r) {
+  const int pos = x == 0 ? 0 : 1 + mod63_small(x - 1 + 126 - r);
+  return min(pos, 63 - pos);
+}
+
+// Tangent of the Jacobi rotation annihilating g_pq of (g_pp, g_pq; g_pq,
+// g_qq): t = sign(theta) / (|theta| + sqrt(1 + theta^2)), theta =
+// (g_qq - g_pp) / (2 g_pq), the smaller root (|t| <= 1).  Hardware
+// reciprocal / reciprocal square root with one Newton step each: t need not
+// be exact (the rotation stays orthogonal whatever t is; the cosine below is
+// what has to be accurate).
+__device__ __forceinline__ double rcp_nr(double x) {
+  const double r = __builtin_amdgcn_rcp(x);
+  return r * fma(-x, r, 2.0);
+}
+__device__ __forceinline__ double jacobi_tangent(double gpp, double gqq, double gpq) {
+  const double theta = (gqq - gpp) * rcp_nr(2.0 * gpq);
+  if (fabs(theta) > 1e150) return 0.5 / theta;
+  const double h = fma(theta, theta, 1.0);
+  double y = __builtin_amdgcn_rsq(h);
+  y = y * fma(-0.5 * h, y * y, 1.5);
+  return copysign(rcp_nr(fabs(theta) + h * y), theta);
+}
+// c = 1 / sqrt(1 + t^2) to full precision (two Newton steps on the hardware
+// reciprocal square root), so that c^2 + s^2 = 1 with s = t c up to rounding.
+__device__ __forceinline__ double unit_cosine(double t) {
+  const double h = fma(t, t, 1.0);
+  double y = __builtin_amdgcn_rsq(h);
+  y = y * fma(-0.5 * h, y * y, 1.5);
+  y = y * fma(-0.5 * h, y * y, 1.5);
+  return y;
+}
+
 // ---------------------------------------------------------------------------
 // The same rotation step with 32-row blocks (pairs of 64 rows), used when
 // n_pad is a multiple of 64.  A sweep then takes nb - 1 = n_pad/32 - 1
@@ -232,11 +279,8 @@ __global__ __launch_bounds__(256) void jacobi_round_kernel(double* __restrict__ 
 //   1. Gram G (64 x 64): the ten distinct 16 x 16 tiles of the four 16-row
 //      sub-blocks, each wave over a quarter of the row length, partial tiles
 //      summed through LDS in a fixed order;
-//   2. one cyclic Jacobi sweep on G (63 rounds of 32 disjoint rotations).
-//      All rotations of a round are applied at once: every 2 x 2 block
-//      (rows p_i, q_i; columns p_j, q_j) of G becomes J_i^T A J_j, which
-//      needs no intermediate barrier; diagonal blocks take the exact
-//      (g_pp - t g_pq, g_qq + t g_pq, 0) form;
+//   2. one cyclic Jacobi sweep on G (63 rounds of 32 disjoint rotations,
+//      one barrier per round, see below);
 //   3. W_pair <- Q^T W_pair with v_mfma_f64_16x16x4 (Q^T fragments in
 //      registers).
 // One inner sweep is enough: the outer iteration recomputes the Gram from
@@ -260,11 +304,12 @@ __global__ __launch_bounds__(256, 2) void jacobi_round64_kernel(double* __restri
   double* rowJ = Wj + (size_t)(32 * J) * n_pad;
 
   __shared__ double G[64][65];
-  __shared__ double Qs[64 * 65];   // Q; before that, staging of partial Gram tiles
-  double(*Q)[65] = reinterpret_cast<double(*)[65]>(Qs);
+  __shared__ double Qs[64 * 65];   // Q^T; before that, staging of partial Gram tiles
+  double(*QT)[65] = reinterpret_cast<double(*)[65]>(Qs);               // QT[col][row] = Q[row][col]
   double(*stage)[5][256] = reinterpret_cast<double(*)[5][256]>(Qs);   // [wave-1][tile][16x16]
-  __shared__ double2 rcs[32], rdd[32];   // (c, s) and (g_pp', g_qq') of the round's rotations
-  __shared__ int2 rpq[32];                // (p, q), p < q
+  __shared__ double2 rcs[32];      // (c, s) of the round's rotations, by slot
+  __shared__ int2 rpq[32];         // (p, q) of the round's pairs, by slot
+  __shared__ double dg[64];        // current diagonal of G
   __shared__ double redbuf[4];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -349,112 +394,94 @@ __global__ __launch_bounds__(256, 2) void jacobi_round64_kernel(double* __restri
   }
   for (int o = 32; o > 0; o >>= 1) off = fmax(off, __shfl_xor(off, o));
   if (lane == 0) redbuf[wave] = off;
-  for (int e = tid; e < 4096; e += 256) Q[e >> 6][e & 63] = ((e >> 6) == (e & 63)) ? 1.0 : 0.0;
+  for (int e = tid; e < 4096; e += 256) QT[e >> 6][e & 63] = ((e >> 6) == (e & 63)) ? 1.0 : 0.0;
+  if (tid < 64) dg[tid] = G[tid][tid];
   __syncthreads();
   off = fmax(fmax(redbuf[0], redbuf[1]), fmax(redbuf[2], redbuf[3]));
   if (!(off > tol)) return;            // pair already orthogonal (uniform)
   if (tid == 0) { atomicOr(&rotated[job], 1); atomicAdd(pairs, 1); }
 
   // ---- 2. one cyclic Jacobi sweep on G, accumulating Q --------------------
-  // Every thread first issues all its LDS loads of a round, then computes and
-  // stores, so that the round costs one LDS round trip per phase.
-  const double tol_in2 = 0x1.0p-106;   // (2^-53)^2
+  // Round r: (1) lanes 0..31 form the rotations of the round's 32 disjoint
+  // pairs (dg holds the diagonal of G, which G itself no longer tracks);
+  // (2) all rotations are applied at once: every 2 x 2 block (rows p_i,
+  // q_i; columns p_j, q_j; i <= j) of G becomes J_i^T A J_j in place, one
+  // owner per block, with the off-diagonal entry of a rotated pair set to
+  // 0; columns p_i, q_i of Q are rotated (rows of QT, lane = row of Q).
+  // Phase (2) has no data-dependent branches: an unrotated pair has c = 1,
+  // s = 0, which rewrites its entries unchanged.
+  //
+  // The block grid is enumerated as 16 folded rows of 33 (row m and row
+  // 31 - m); thread tid owns blocks tid, tid + 256 and (tid < 16) tid + 512.
+  int bi[3], bj[3];
+#pragma unroll
+  for (int u = 0; u < 3; ++u) {
+    const int e = min(tid + 256 * u, 527);
+    const int m = e / 33, o = e - 33 * m;
+    if (o < 32 - m) { bi[u] = m; bj[u] = m + o; }
+    else { bi[u] = 31 - m; bj[u] = 31 - m + (o - (32 - m)); }
+  }
+  const int wave_s = __builtin_amdgcn_readfirstlane(wave);
   for (int r = 0; r < 63; ++r) {
     if (tid < 32) {
-      int p = tid == 0 ? 0 : 1 + (tid - 1 + r) % 63;
-      int q = 1 + (63 - tid - 1 + r) % 63;
-      if (p > q) { const int tmp = p; p = q; q = tmp; }
-      const double gpp = G[p][p], gqq = G[q][q], gpq = G[p][q];
-      double c = 1.0, s = 0.0, dp = gpp, dq = gqq;
+      int p, q;
+      circle_pair64(tid, r, p, q);
+      const double gpp = dg[p], gqq = dg[q], gpq = G[p][q];
+      double c = 1.0, s = 0.0;
       // |.| guards the tiny diagonal entries that rounding can push below 0
-      if (gpq != 0.0 && gpq * gpq > tol_in2 * fabs(gpp * gqq)) {
-        const double theta = (gqq - gpp) / (2.0 * gpq);
-        const double t = (fabs(theta) > 1e150) ? 0.5 / theta
-                                               : copysign(1.0, theta) / (fabs(theta) + sqrt(1.0 + theta * theta));
-        c = 1.0 / sqrt(1.0 + t * t);
+      if (gpq != 0.0 && gpq * gpq > 0x1.0p-106 * fabs(gpp * gqq)) {
+        const double t = jacobi_tangent(gpp, gqq, gpq);
+        c = unit_cosine(t);
         s = t * c;
-        dp = gpp - t * gpq;
-        dq = gqq + t * gpq;
+        dg[p] = fma(-t, gpq, gpp);
+        dg[q] = fma(t, gpq, gqq);
       }
-      rpq[tid] = make_int2(p, q);
       rcs[tid] = make_double2(c, s);
-      rdd[tid] = make_double2(dp, dq);
+      rpq[tid] = make_int2(p, q);
     }
     __syncthreads();
-    // (a) G <- J^T G J block by block.  The 528 blocks (i <= j) of the
-    // 32 x 32 block grid are enumerated as 16 folded rows of 33 (row m and
-    // row 31 - m); thread tid takes blocks tid, tid + 256 and tid + 512.
-    int bi[3], bj[3];
-    bool bv[3];
+    // Q^T rows: wave w takes pairs w, w + 4, ..., w + 28
+    int2 qpq[8];
+    double2 qcs[8];
+    double qx[8], qy[8];
 #pragma unroll
-    for (int u = 0; u < 3; ++u) {
-      const int e = tid + 256 * u;
-      bv[u] = e < 528;
-      const int m = e / 33, o = e - 33 * m;
-      if (o < 32 - m) { bi[u] = m; bj[u] = m + o; }
-      else { bi[u] = 31 - m; bj[u] = 31 - m + (o - (32 - m)); }
-    }
+    for (int k = 0; k < 8; ++k) { qpq[k] = rpq[wave_s + 4 * k]; qcs[k] = rcs[wave_s + 4 * k]; }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) { qx[k] = QT[qpq[k].x][lane]; qy[k] = QT[qpq[k].y][lane]; }
     int2 pi[3], pj[3];
     double2 ci[3], cj[3];
     double ga[3], gb[3], gc[3], gd[3];
 #pragma unroll
     for (int u = 0; u < 3; ++u) {
-      if (bv[u]) {
-        pi[u] = rpq[bi[u]]; pj[u] = rpq[bj[u]];
-        ci[u] = rcs[bi[u]]; cj[u] = rcs[bj[u]];
-      }
-    }
-    // (b) Q <- Q J: thread tid rotates columns (p, q) of pair tid / 8 in
-    // rows tid % 8 + 8 h
-    const int qi = tid >> 3, q0 = tid & 7;
-    const int2 qpq = rpq[qi];
-    const double2 qcs = rcs[qi];
-    double qv[8][2];
-    if (qcs.y != 0.0) {
-#pragma unroll
-      for (int h = 0; h < 8; ++h) { qv[h][0] = Q[q0 + 8 * h][qpq.x]; qv[h][1] = Q[q0 + 8 * h][qpq.y]; }
+      if (u == 2 && tid >= 16) break;
+      pi[u] = rpq[bi[u]]; pj[u] = rpq[bj[u]];
+      ci[u] = rcs[bi[u]]; cj[u] = rcs[bj[u]];
     }
 #pragma unroll
     for (int u = 0; u < 3; ++u) {
-      if (bv[u] && bi[u] != bj[u] && (ci[u].y != 0.0 || cj[u].y != 0.0)) {
-        ga[u] = G[pi[u].x][pj[u].x]; gb[u] = G[pi[u].x][pj[u].y];
-        gc[u] = G[pi[u].y][pj[u].x]; gd[u] = G[pi[u].y][pj[u].y];
-      }
+      if (u == 2 && tid >= 16) break;
+      ga[u] = G[pi[u].x][pj[u].x]; gb[u] = G[pi[u].x][pj[u].y];
+      gc[u] = G[pi[u].y][pj[u].x]; gd[u] = G[pi[u].y][pj[u].y];
     }
-    double2 dd[3];
 #pragma unroll
-    for (int u = 0; u < 3; ++u)
-      if (bv[u] && bi[u] == bj[u] && ci[u].y != 0.0) dd[u] = rdd[bi[u]];
-    // all loads issued; compute and store
+    for (int k = 0; k < 8; ++k) {
+      QT[qpq[k].x][lane] = qcs[k].x * qx[k] - qcs[k].y * qy[k];
+      QT[qpq[k].y][lane] = qcs[k].y * qx[k] + qcs[k].x * qy[k];
+    }
 #pragma unroll
     for (int u = 0; u < 3; ++u) {
-      if (!bv[u]) continue;
-      const int pa = pi[u].x, qa_ = pi[u].y, pb = pj[u].x, qb = pj[u].y;
-      if (bi[u] == bj[u]) {
-        if (ci[u].y != 0.0) {
-          G[pa][pa] = dd[u].x;
-          G[qa_][qa_] = dd[u].y;
-          G[pa][qa_] = 0.0;
-          G[qa_][pa] = 0.0;
-        }
-      } else if (ci[u].y != 0.0 || cj[u].y != 0.0) {
-        const double c_i = ci[u].x, s_i = ci[u].y, c_j = cj[u].x, s_j = cj[u].y;
-        // A J_j: columns (p, q) -> (c p - s q, s p + c q)
-        const double a1 = c_j * ga[u] - s_j * gb[u], b1 = s_j * ga[u] + c_j * gb[u];
-        const double c1 = c_j * gc[u] - s_j * gd[u], d1 = s_j * gc[u] + c_j * gd[u];
-        // J_i^T (A J_j): rows (p, q) -> (c p - s q, s p + c q)
-        const double a2 = c_i * a1 - s_i * c1, c2 = s_i * a1 + c_i * c1;
-        const double b2 = c_i * b1 - s_i * d1, d2 = s_i * b1 + c_i * d1;
-        G[pa][pb] = a2; G[pa][qb] = b2; G[qa_][pb] = c2; G[qa_][qb] = d2;
-        G[pb][pa] = a2; G[qb][pa] = b2; G[pb][qa_] = c2; G[qb][qa_] = d2;
-      }
-    }
-    if (qcs.y != 0.0) {
-#pragma unroll
-      for (int h = 0; h < 8; ++h) {
-        Q[q0 + 8 * h][qpq.x] = qcs.x * qv[h][0] - qcs.y * qv[h][1];
-        Q[q0 + 8 * h][qpq.y] = qcs.y * qv[h][0] + qcs.x * qv[h][1];
-      }
+      if (u == 2 && tid >= 16) break;
+      const double c_i = ci[u].x, s_i = ci[u].y, c_j = cj[u].x, s_j = cj[u].y;
+      // A J_j: columns (p, q) -> (c p - s q, s p + c q)
+      const double a1 = c_j * ga[u] - s_j * gb[u], b1 = s_j * ga[u] + c_j * gb[u];
+      const double c1 = c_j * gc[u] - s_j * gd[u], d1 = s_j * gc[u] + c_j * gd[u];
+      // J_i^T (A J_j): rows (p, q) -> (c p - s q, s p + c q)
+      const double a2 = c_i * a1 - s_i * c1, d2 = s_i * b1 + c_i * d1;
+      double c2 = s_i * a1 + c_i * c1, b2 = c_i * b1 - s_i * d1;
+      if (bi[u] == bj[u] && s_i != 0.0) { b2 = 0.0; c2 = 0.0; }   // the rotated pair itself
+      const int xp = pi[u].x, xq = pi[u].y, yp = pj[u].x, yq = pj[u].y;
+      G[xp][yp] = a2; G[xp][yq] = b2; G[xq][yp] = c2; G[xq][yq] = d2;
+      G[yp][xp] = a2; G[yq][xp] = b2; G[yp][xq] = c2; G[yq][xq] = d2;
     }
     __syncthreads();
   }
@@ -466,7 +493,7 @@ __global__ __launch_bounds__(256, 2) void jacobi_round64_kernel(double* __restri
 #pragma unroll
   for (int t = 0; t < 4; ++t)
 #pragma unroll
-    for (int s = 0; s < 16; ++s) qa[t][s] = Q[4 * s + lg][16 * t + lr];
+    for (int s = 0; s < 16; ++s) qa[t][s] = QT[16 * t + lr][4 * s + lg];
 
   auto row_ptr = [&](int r) -> double* {
     return r < 32 ? rowI + (size_t)r * n_pad : rowJ + (size_t)(r - 32) * n_pad;
