@@ -485,14 +485,146 @@ __global__ __launch_bounds__(256) void apply_q1_kernel(int n, int n_pad, int kca
   for (int r = tid; r < n; r += 256) Fj[(size_t)r * kcap + a] = w * x[r];
 }
 
+// The same product for n_pad <= 1024 with all kept vectors of a job handled
+// together: one workgroup per (job, group of 16 vectors), X (n_pad x 16) in
+// LDS, and for each panel p (last to first, 32 columns d = j .. j + 31)
+//   Y = V_p^T X     (32 x 16, v_mfma_f64_16x16x4, waves split the rows),
+//   Z = T_p Y       (T_p upper triangular, 32 x 32),
+//   X <- X - V_p Z  (v_mfma_f64_16x16x4 over 16-row tiles).
+// V_p (row d of S1, entries r > d; unit diagonal implied) is streamed from
+// HBM twice per panel and workgroup instead of once per vector.
+__global__ __launch_bounds__(256) void apply_q1_mfma_kernel(int n, int n_pad, int kcap, const double* __restrict__ S1,
+                                                            const double* __restrict__ Tws1,
+                                                            const double* __restrict__ W2,
+                                                            const double* __restrict__ sigma,
+                                                            const int32_t* __restrict__ order,
+                                                            const int32_t* __restrict__ kept,
+                                                            const int32_t* __restrict__ sel,
+                                                            const double* __restrict__ weight, double* __restrict__ F) {
+  extern __shared__ unsigned char smem[];
+  double* X = reinterpret_cast<double*>(smem);   // [n_pad][16]
+  double* Yp = X + (size_t)n_pad * 16;     // [4 waves][2 tiles][256]
+  double* Ys = Yp + 4 * 2 * 256;           // [32][16]
+  double* Zs = Ys + 32 * 16;               // [32][16], holds -Z
+  __shared__ double sv[16], wv[16];
+  __shared__ const double* rowp[16];
+  const int64_t job = blockIdx.y;
+  const int a0 = 16 * blockIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int lr = lane & 15, lg = lane >> 4;
+  const int nk = kept[job];
+  const double* Sj = S1 + (size_t)job * n_pad * n_pad;
+  const double* Tj = Tws1 + (size_t)job * n_pad * 32;
+  if (tid < 16) {
+    const int a = a0 + tid;
+    if (a < nk) {
+      const int i = sel[job * kcap + a];
+      sv[tid] = sigma[(size_t)job * n + i];
+      wv[tid] = weight[job * kcap + a];
+      rowp[tid] = W2 + (size_t)job * n_pad * n_pad + (size_t)order[(size_t)job * n + i] * n_pad;
+    } else {
+      sv[tid] = 1.0;
+      wv[tid] = 0.0;
+      rowp[tid] = nullptr;
+    }
+  }
+  __syncthreads();
+  for (int e = tid; e < n_pad * 16; e += 256) {
+    const int r = e >> 4, v = e & 15;
+    X[e] = rowp[v] ? rowp[v][r] / sv[v] : 0.0;
+  }
+  __syncthreads();
+  for (int j = n_pad - 32; j >= 0; j -= 32) {
+    // ---- Y = V_p^T X: rows r = j .. n_pad - 1 in chunks of 16 ------------
+    f64x4 acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
+    for (int r0 = j + 16 * wave; r0 < n_pad; r0 += 64) {
+      const int rb = r0 + 4 * lg;
+      double av[2][4];
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        const int d = j + 16 * t + lr;
+        const double* src = Sj + (size_t)d * n_pad + rb;
+        const double2 x01 = *reinterpret_cast<const double2*>(src);
+        const double2 x23 = *reinterpret_cast<const double2*>(src + 2);
+        av[t][0] = x01.x; av[t][1] = x01.y; av[t][2] = x23.x; av[t][3] = x23.y;
+        if (r0 < j + 32) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int r = rb + q;
+            av[t][q] = r > d ? av[t][q] : (r == d ? 1.0 : 0.0);
+          }
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const double b = X[(rb + q) * 16 + lr];
+        acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[0][q], b, acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[1][q], b, acc1, 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int idx = acc_row_f64(lg, i) * 16 + lr;
+      Yp[(wave * 2 + 0) * 256 + idx] = acc0[i];
+      Yp[(wave * 2 + 1) * 256 + idx] = acc1[i];
+    }
+    __syncthreads();
+    for (int e = tid; e < 512; e += 256) {   // Y[c][v], c = 16 t + row
+      const int t = e >> 8, idx = e & 255;
+      Ys[e] = ((Yp[(0 * 2 + t) * 256 + idx] + Yp[(1 * 2 + t) * 256 + idx]) + Yp[(2 * 2 + t) * 256 + idx]) +
+              Yp[(3 * 2 + t) * 256 + idx];
+    }
+    __syncthreads();
+    for (int e = tid; e < 512; e += 256) {   // -Z[c][v] = -sum_{c' >= c} T[c][c'] Y[c'][v]
+      const int c = e >> 4, v = e & 15;
+      const double* Trow = Tj + (size_t)(j / 32) * 1024 + c * 32;
+      double z = 0.0;
+      for (int c2 = c; c2 < 32; ++c2) z += Trow[c2] * Ys[c2 * 16 + v];
+      Zs[e] = -z;
+    }
+    __syncthreads();
+    // ---- X <- X - V_p Z over 16-row tiles r0 = j + 16 m -----------------
+    double bz[8];
+#pragma unroll
+    for (int s = 0; s < 8; ++s) bz[s] = Zs[(4 * s + lg) * 16 + lr];
+    for (int r0 = j + 16 * wave; r0 < n_pad; r0 += 64) {
+      f64x4 cx;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) cx[i] = X[(r0 + acc_row_f64(lg, i)) * 16 + lr];
+      const int r = r0 + lr;
+#pragma unroll
+      for (int s = 0; s < 8; ++s) {
+        const int d = j + 4 * s + lg;
+        double v = Sj[(size_t)d * n_pad + r];
+        if (r0 < j + 32) v = r > d ? v : (r == d ? 1.0 : 0.0);
+        cx = __builtin_amdgcn_mfma_f64_16x16x4f64(v, bz[s], cx, 0, 0, 0);
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i) X[(r0 + acc_row_f64(lg, i)) * 16 + lr] = cx[i];
+    }
+    __syncthreads();
+  }
+  double* Fj = F + (size_t)job * n * kcap;
+  for (int e = tid; e < n * 16; e += 256) {
+    const int r = e >> 4, v = e & 15, a = a0 + v;
+    if (a < kcap) Fj[(size_t)r * kcap + a] = (a < nk) ? wv[v] * X[e] : 0.0;
+  }
+}
+
+size_t apply_q1_mfma_lds(int n_pad) { return sizeof(double) * ((size_t)n_pad * 16 + 4 * 2 * 256 + 2 * 32 * 16); }
+
 hipError_t launch_apply_q1(int64_t njobs, int n, int n_pad, int kcap, const double* S1, const double* Tws1,
                            const double* W2, const double* sigma, const int32_t* order, const int32_t* kept,
                            const int32_t* sel, const double* weight, double* F, hipStream_t stream) {
   if (njobs == 0) return hipSuccess;
-  if (n_pad <= 1024)
-    hipLaunchKernelGGL((apply_q1_kernel<4, 32>), dim3(kcap, (unsigned)njobs), dim3(256), 0, stream, n, n_pad, kcap, S1,
-                       Tws1, W2, sigma, order, kept, sel, weight, F);
-  else
+  if (n_pad <= 1024) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&apply_q1_mfma_kernel),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)apply_q1_mfma_lds(n_pad));
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(apply_q1_mfma_kernel, dim3((kcap + 15) / 16, (unsigned)njobs), dim3(256),
+                       apply_q1_mfma_lds(n_pad), stream, n, n_pad, kcap, S1, Tws1, W2, sigma, order, kept, sel, weight,
+                       F);
+  } else
     hipLaunchKernelGGL((apply_q1_kernel<16, 8>), dim3(kcap, (unsigned)njobs), dim3(256), 0, stream, n, n_pad, kcap, S1,
                        Tws1, W2, sigma, order, kept, sel, weight, F);
   return hipGetLastError();
