@@ -12,7 +12,8 @@
 // blocked Householder QR with 32-column panels (8-column panels for
 // n_pad > 1024):
 //   panel kernel     one workgroup per job factors the panel in registers
-//                    (each thread owns up to four (eight) rows of the panel),
+//                    (each thread owns up to four (eight) rows of the panel;
+//                    qr_panel32_kernel for the 32-column panels),
 //                    leaves the Householder vectors below the diagonal and
 //                    R on and above it, and forms the 32 x 32 triangular T of
 //                    the compact WY form I - V T V^T;
@@ -225,21 +226,167 @@ __global__ __launch_bounds__(NT) void qr_panel_kernel(int n_pad, int j, double* 
   for (int e = tid; e < PW * PW; e += NT) Tj[e] = Tm[e / PW][e % PW];
 }
 
+// Panel factorisation for n_pad <= 1024 with 32-column panels: 256 threads,
+// thread t owns rows j + t + 256 q (q < 4) of the 32 panel columns in
+// registers.  The register slots rotate by one column per step so that the
+// pivot column is always slot 0 (no dynamic register indexing): at step i,
+// slots 1 .. 31 - i hold columns i + 1 .. 31 and slots 32 - i .. 31 the
+// finished Householder vectors v_0 .. v_{i-1}.  One reduction per column
+// gives, with x = the pivot column below the diagonal row cj = j + i,
+//   x^T x (slot 0), x^T col_c (slots of later columns), x^T v_m (finished);
+// with the row-cj entries this yields the Householder reflector (LAPACK
+// dlarfg convention), w_c = v^T col_c and z_m = v_m^T v.  The 64 lanes of a
+// wave reduce their 32 partial sums by halving exchanges (16 + 8 + 4 + 2 + 1
+// + 1 shuffles).  T of the compact WY form follows at the end, row m by
+// thread m: T[m][m] = tau_m, T[m][i] = -tau_i sum_{p=m}^{i-1} T[m][p] z_p^(i).
+__global__ __launch_bounds__(256) void qr_panel32_kernel(int n_pad, int j, double* __restrict__ S,
+                                                         double* __restrict__ Tws, int64_t t_stride, int64_t t_off) {
+  const int64_t job = blockIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  double* Sj = S + job * (size_t)n_pad * n_pad;
+  __shared__ double red[4][32];
+  __shared__ double rowcj[32];
+  __shared__ double wz[32];
+  __shared__ double Zs[32][33];
+  __shared__ double taus[32];
+  __shared__ double prm[3];   // tau, scale, beta of the current column
+
+  double A[4][32];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int r = j + tid + 256 * q;
+#pragma unroll
+    for (int c = 0; c < 32; ++c) A[q][c] = (r < n_pad) ? Sj[(size_t)(j + c) * n_pad + r] : 0.0;
+  }
+  // lane l holds, after the halving exchanges, the sum of slot sidx
+  const int sidx = ((lane >> 5) & 1) * 16 + ((lane >> 4) & 1) * 8 + ((lane >> 3) & 1) * 4 + ((lane >> 2) & 1) * 2 +
+                   ((lane >> 1) & 1);
+  for (int i = 0; i < 32; ++i) {
+    const int cj = j + i;
+    double p[32];
+#pragma unroll
+    for (int c = 0; c < 32; ++c) p[c] = 0.0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int r = j + tid + 256 * q;
+      const double x = (r > cj && r < n_pad) ? A[q][0] : 0.0;
+#pragma unroll
+      for (int c = 0; c < 32; ++c) p[c] = fma(A[q][c], x, p[c]);
+    }
+    if (tid == i) {
+#pragma unroll
+      for (int c = 0; c < 32; ++c) rowcj[c] = A[0][c];
+    }
+    // halving exchanges: 32 -> 16 -> 8 -> 4 -> 2 -> 1 values per lane
+#pragma unroll
+    for (int h = 0; h < 16; ++h) {
+      const bool up = lane & 32;
+      const double keep = up ? p[16 + h] : p[h], send = up ? p[h] : p[16 + h];
+      p[h] = keep + __shfl_xor(send, 32);
+    }
+#pragma unroll
+    for (int h = 0; h < 8; ++h) {
+      const bool up = lane & 16;
+      const double keep = up ? p[8 + h] : p[h], send = up ? p[h] : p[8 + h];
+      p[h] = keep + __shfl_xor(send, 16);
+    }
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+      const bool up = lane & 8;
+      const double keep = up ? p[4 + h] : p[h], send = up ? p[h] : p[4 + h];
+      p[h] = keep + __shfl_xor(send, 8);
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const bool up = lane & 4;
+      const double keep = up ? p[2 + h] : p[h], send = up ? p[h] : p[2 + h];
+      p[h] = keep + __shfl_xor(send, 4);
+    }
+    {
+      const bool up = lane & 2;
+      const double keep = up ? p[1] : p[0], send = up ? p[0] : p[1];
+      p[0] = keep + __shfl_xor(send, 2);
+    }
+    p[0] += __shfl_xor(p[0], 1);
+    if ((lane & 1) == 0) red[wave][sidx] = p[0];
+    __syncthreads();
+    if (tid < 32) {
+      const int c = tid;
+      const double xn2 = ((red[0][0] + red[1][0]) + red[2][0]) + red[3][0];
+      const double sc = ((red[0][c] + red[1][c]) + red[2][c]) + red[3][c];
+      const double alpha = rowcj[0];
+      double tau, scale, beta;
+      if (xn2 == 0.0) {
+        tau = 0.0; scale = 0.0; beta = alpha;
+      } else {
+        beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
+        tau = (beta - alpha) / beta;
+        scale = 1.0 / (alpha - beta);
+      }
+      const double v = rowcj[c] + scale * sc;   // w_c (later columns) or z_m (finished v_m)
+      wz[c] = v;
+      if (c >= 32 - i) Zs[c + i - 32][i] = v;
+      if (c == 0) { prm[0] = tau; prm[1] = scale; prm[2] = beta; taus[i] = tau; }
+    }
+    __syncthreads();
+    const double tau = prm[0], scale = prm[1], beta = prm[2];
+    double wv[32];
+#pragma unroll
+    for (int c = 1; c < 32; ++c) wv[c] = (c <= 31 - i) ? tau * wz[c] : 0.0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int r = j + tid + 256 * q;
+      const bool below = r > cj && r < n_pad, at = r == cj;
+      const double vr = at ? 1.0 : (below ? scale * A[q][0] : 0.0);
+#pragma unroll
+      for (int c = 1; c < 32; ++c) A[q][c] = fma(-wv[c], vr, A[q][c]);
+      // the pivot column keeps v below the diagonal and beta on it
+      A[q][0] = below ? vr : (at ? beta : A[q][0]);
+    }
+    // rotate the slots: the finished column goes to slot 31
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const double f = A[q][0];
+#pragma unroll
+      for (int c = 0; c < 31; ++c) A[q][c] = A[q][c + 1];
+      A[q][31] = f;
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int r = j + tid + 256 * q;
+    if (r < n_pad) {
+#pragma unroll
+      for (int c = 0; c < 32; ++c) Sj[(size_t)(j + c) * n_pad + r] = A[q][c];
+    }
+  }
+  if (tid < 32) {
+    const int m = tid;
+    double Tr[32];
+#pragma unroll
+    for (int i = 0; i < 32; ++i) {
+      double t = 0.0;
+      if (i == m) t = taus[i];
+      else if (i > m) {
+        double acc = 0.0;
+#pragma unroll
+        for (int p2 = 0; p2 < i; ++p2)
+          if (p2 >= m) acc = fma(Tr[p2], Zs[p2][i], acc);
+        t = -taus[i] * acc;
+      }
+      Tr[i] = t;
+    }
+    double* Tj = Tws + job * t_stride + t_off;
+#pragma unroll
+    for (int i = 0; i < 32; ++i) Tj[m * 32 + i] = Tr[i];
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Trailing update of the columns right of the panel: C <- C - V T^T... in the
 // compact WY form H_0 H_1 ... H_31 = I - V T V^T, so Q^T C = C - V T^T V^T C.
 // One workgroup per (job, 64-column tile); wave w owns 16 columns.
 // ---------------------------------------------------------------------------
-template <int PW>
-__device__ __forceinline__ double vload(const double* Sj, int n_pad, int j, int i, int r) {
-  // V[r][i]: stored below the diagonal of panel column j+i, 1 on it, 0 above
-  // (and 0 for i >= PW or r >= n_pad)
-  const int d = j + i;
-  if (i >= PW || r >= n_pad) return 0.0;
-  if (r > d) return Sj[(size_t)d * n_pad + r];
-  return r == d ? 1.0 : 0.0;
-}
-
 template <int PW>
 __global__ __launch_bounds__(256) void qr_trailing_kernel(int n_pad, int j, double* __restrict__ S,
                                                           const double* __restrict__ Tws, int64_t t_stride,
@@ -261,19 +408,37 @@ __global__ __launch_bounds__(256) void qr_trailing_kernel(int n_pad, int j, doub
 #pragma unroll
   for (int t = 0; t < NI; ++t) acc[t] = f64x4{0, 0, 0, 0};
   if (active) {
+    // rows in chunks of 16; lane (lr, lg) takes rows rb .. rb + 3 of its
+    // column (C) and of V column 16 t + lr, as 16-byte loads
+    const double* cbase = Sj + (size_t)(col_ok ? c0w + lr : c0w) * n_pad;
     for (int r0 = j; r0 < n_pad; r0 += 16) {
       const int rb = r0 + 4 * lg;
-      double cv[4];
-      const double* cp = Sj + (size_t)(c0w + lr) * n_pad + rb;
-#pragma unroll
-      for (int jj = 0; jj < 4; ++jj) cv[jj] = (col_ok && rb + jj < n_pad) ? cp[jj] : 0.0;
+      // n_pad and rb are multiples of 4: rows rb .. rb + 3 exist iff rb < n_pad
+      const bool row_ok = rb < n_pad;
+      double2 c01 = {0.0, 0.0}, c23 = {0.0, 0.0};
+      if (row_ok) {
+        c01 = *reinterpret_cast<const double2*>(cbase + rb);
+        c23 = *reinterpret_cast<const double2*>(cbase + rb + 2);
+      }
+      const double cv[4] = {col_ok ? c01.x : 0.0, col_ok ? c01.y : 0.0, col_ok ? c23.x : 0.0, col_ok ? c23.y : 0.0};
 #pragma unroll
       for (int t = 0; t < NI; ++t) {
+        const int i = 16 * t + lr, d = j + i;
+        double v[4];
+        if (i < PW && row_ok) {
+          const double* vp = Sj + (size_t)d * n_pad + rb;
+          const double2 v01 = *reinterpret_cast<const double2*>(vp);
+          const double2 v23 = *reinterpret_cast<const double2*>(vp + 2);
+          v[0] = v01.x; v[1] = v01.y; v[2] = v23.x; v[3] = v23.y;
+          if (r0 < j + PW) {   // V is stored below the diagonal, 1 on it, 0 above
 #pragma unroll
-        for (int jj = 0; jj < 4; ++jj) {
-          const double v = vload<PW>(Sj, n_pad, j, 16 * t + lr, rb + jj);
-          acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(v, cv[jj], acc[t], 0, 0, 0);
+            for (int jj = 0; jj < 4; ++jj) v[jj] = rb + jj > d ? v[jj] : (rb + jj == d ? 1.0 : 0.0);
+          }
+        } else {
+          v[0] = v[1] = v[2] = v[3] = 0.0;
         }
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(v[jj], cv[jj], acc[t], 0, 0, 0);
       }
     }
   }
@@ -309,9 +474,15 @@ __global__ __launch_bounds__(256) void qr_trailing_kernel(int n_pad, int j, doub
   for (int ks = 0; ks < KSTEPS; ++ks) aw[ks] = W1[4 * ks + lg][16 * wave + lr];
   for (int r0 = j; r0 < n_pad; r0 += 16) {
     f64x4 a = {0, 0, 0, 0};
+    const int rr = r0 + lr;
 #pragma unroll
     for (int ks = 0; ks < KSTEPS; ++ks) {
-      const double bv = vload<PW>(Sj, n_pad, j, 4 * ks + lg, r0 + lr);
+      const int i = 4 * ks + lg, d = j + i;
+      double bv = 0.0;
+      if (i < PW && rr < n_pad) {
+        bv = Sj[(size_t)d * n_pad + rr];
+        if (r0 < j + PW) bv = rr > d ? bv : (rr == d ? 1.0 : 0.0);
+      }
       a = __builtin_amdgcn_mfma_f64_16x16x4f64(aw[ks], bv, a, 0, 0, 0);
     }
     const int r = r0 + lr;
@@ -353,8 +524,12 @@ static hipError_t qr_factor_t(int64_t njobs, int n_pad, double* S, double* Tws, 
   const int64_t t_stride = keep_T ? (int64_t)n_pad * PW : (int64_t)PW * PW;
   for (int j = 0; j < n_pad; j += PW) {
     const int64_t t_off = keep_T ? (int64_t)(j / PW) * PW * PW : 0;
-    hipLaunchKernelGGL((qr_panel_kernel<NT, MAXQ, PW>), dim3((unsigned)njobs), dim3(NT), 0, stream, n_pad, j, S, Tws,
-                       t_stride, t_off);
+    if (NT == 256 && MAXQ == 4 && PW == 32)
+      hipLaunchKernelGGL(qr_panel32_kernel, dim3((unsigned)njobs), dim3(256), 0, stream, n_pad, j, S, Tws, t_stride,
+                         t_off);
+    else
+      hipLaunchKernelGGL((qr_panel_kernel<NT, MAXQ, PW>), dim3((unsigned)njobs), dim3(NT), 0, stream, n_pad, j, S,
+                         Tws, t_stride, t_off);
     const int rest = n_pad - j - PW;
     if (rest > 0)
       hipLaunchKernelGGL((qr_trailing_kernel<PW>), dim3(ceil_div(rest, 64), (unsigned)njobs), dim3(256), 0, stream,
