@@ -8,6 +8,9 @@ C2  k = 16 shared chains over the beta sweep 0.30..0.60 (16 values): one
     sample per beta checked against the oracle over 20 steps (2^20 sites).
 C3  mixed k in {16, 24, 32}, beta in [0.35, 0.55], h in {0, 0.05}: samples
     of every k bucketed in one call, checked against the oracle.
+C4  k = 48 at beta_c and C5 k = 64 at beta = 0.42, h = 0.1: the first steps
+    at the full bond dimension (unfoldings of 2304 and 4096 rows) checked
+    against the oracle.
 """
 import math
 
@@ -132,3 +135,43 @@ def test_low_precision_topk_error(dtype, tol):
     err = abs(a[0] - b[0]) / 2.0 ** 12
     log(f"topk k=16 {dtype}: |d lnZ|/site = {err:.3e}")
     assert err < tol
+
+
+def _large_k_parity(k, beta, h, n_steps, ns):
+    """Selections must agree step by step (else the chain is skipped and
+    logged); ln c then agrees to 1e-9 at steps whose kept values all exceed
+    1e-6 s_1, and to 1e-4 where a kept value sits closer to the candidate
+    threshold (an FP64 SVD fixes s_i only to ~n eps s_1 / s_i relative, and
+    the reweighted term sqrt(s_i / r_i) carries that into T')."""
+    torch, m = need_gpu()
+    ts = m.init_tensor("site", [beta], [h])
+    r = m.run_samples(ts, ns, n_steps=n_steps, k=k, seed=1, dtype="f64", want_ln_c=True, record=True)
+    ln, lnc, rec = r.ln_abs_Z.cpu().numpy(), r.ln_c.cpu().numpy(), r.record.cpu().numpy()
+    N = 2.0 ** n_steps
+    matched = 0
+    for i in range(ns):
+        o = trg.run_shared(ising.site_tensor(beta, h), n_steps, k, 1, i)
+        same = all(list(st.splits[0].sel) == [int(x) for x in rec[i, s, 4:4 + int(rec[i, s, 2])]] and
+                   list(st.splits[1].sel) == [int(x) for x in rec[i, s, 4 + k:4 + k + int(rec[i, s, 3])]]
+                   for s, st in enumerate(o.records))
+        log(f"k={k} sample {i}: same selections {same}, |d lnZ|/site {abs(ln[i] - o.ln_abs_Z) / N:.3e}, "
+            f"max |d ln c| {np.max(np.abs(lnc[i] - np.asarray(o.ln_c))):.3e}")
+        if not same:
+            continue
+        matched += 1
+        for s, st in enumerate(o.records):
+            smin = min(float(np.min(sp.sigma[sp.sel] / sp.sigma[0])) if len(sp.sel) else 1.0 for sp in st.splits)
+            tol = 1e-9 if smin > 1e-6 else 1e-4
+            assert abs(lnc[i, s] - o.ln_c[s]) < tol, (s, smin, lnc[i, s], o.ln_c[s])
+        assert abs(ln[i] - o.ln_abs_Z) / N < 1e-6
+    assert matched >= 1
+
+
+def test_c4_k48_parity():
+    log("C4 k=48")
+    _large_k_parity(48, BETA_C, 0.0, 8, 2)
+
+
+def test_c5_k64_parity():
+    log("C5 k=64")
+    _large_k_parity(64, 0.42, 0.1, 8, 1)

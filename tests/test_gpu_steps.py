@@ -29,7 +29,8 @@ def ising_unfoldings(k, steps, beta=BETA_C, h=0.0, seed=0, sample=0):
     return out
 
 
-@pytest.mark.parametrize("d1,d2,nm", [(2, 2, 3), (4, 4, 5), (5, 6, 4), (8, 8, 6), (16, 16, 3), (24, 24, 2)])
+@pytest.mark.parametrize("d1,d2,nm", [(2, 2, 3), (4, 4, 5), (5, 6, 4), (8, 8, 6), (16, 16, 3), (24, 24, 2),
+                                      (33, 34, 2), (36, 36, 1), (48, 48, 1)])
 def test_svd_random(d1, d2, nm):
     torch, m = need_gpu()
     log(f"svd_random d1={d1} d2={d2} nm={nm}")
