@@ -308,8 +308,10 @@ __global__ __launch_bounds__(256, 2) void jacobi_round64_kernel(double* __restri
   double(*QT)[65] = reinterpret_cast<double(*)[65]>(Qs);               // QT[col][row] = Q[row][col]
   double(*stage)[5][256] = reinterpret_cast<double(*)[5][256]>(Qs);   // [wave-1][tile][16x16]
   __shared__ double2 rcs[32];      // (c, s) of the round's rotations, by slot
-  __shared__ int2 rpq[32];         // (p, q) of the round's pairs, by slot
+  __shared__ int2 rpq[32];         // (p, q) of the round's pairs, by slot (p < q)
+  __shared__ int rsw[32];          // 1 if position t holds the larger index q
   __shared__ double dg[64];        // current diagonal of G
+  __shared__ double xch[2][4][2][64];   // rows of Q^T handed to the neighbouring wave, by round parity
   __shared__ double redbuf[4];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -394,7 +396,6 @@ __global__ __launch_bounds__(256, 2) void jacobi_round64_kernel(double* __restri
   }
   for (int o = 32; o > 0; o >>= 1) off = fmax(off, __shfl_xor(off, o));
   if (lane == 0) redbuf[wave] = off;
-  for (int e = tid; e < 4096; e += 256) QT[e >> 6][e & 63] = ((e >> 6) == (e & 63)) ? 1.0 : 0.0;
   if (tid < 64) dg[tid] = G[tid][tid];
   __syncthreads();
   off = fmax(fmax(redbuf[0], redbuf[1]), fmax(redbuf[2], redbuf[3]));
@@ -403,13 +404,20 @@ __global__ __launch_bounds__(256, 2) void jacobi_round64_kernel(double* __restri
 
   // ---- 2. one cyclic Jacobi sweep on G, accumulating Q --------------------
   // Round r: (1) lanes 0..31 form the rotations of the round's 32 disjoint
-  // pairs (dg holds the diagonal of G, which G itself no longer tracks);
+  // pairs (dg holds the diagonal of G; G keeps its upper triangle only);
   // (2) all rotations are applied at once: every 2 x 2 block (rows p_i,
   // q_i; columns p_j, q_j; i <= j) of G becomes J_i^T A J_j in place, one
   // owner per block, with the off-diagonal entry of a rotated pair set to
-  // 0; columns p_i, q_i of Q are rotated (rows of QT, lane = row of Q).
-  // Phase (2) has no data-dependent branches: an unrotated pair has c = 1,
-  // s = 0, which rewrites its entries unchanged.
+  // 0, and the columns of Q are rotated.  Phase (2) has no data-dependent
+  // branches: an unrotated pair has c = 1, s = 0.
+  //
+  // Q lives in registers, by position of the circle ordering: slot t pairs
+  // positions t and 63 - t, and between rounds the index at position k + 1
+  // moves to position k (position 1 to 63; position 0 stays).  Wave w holds
+  // the Q^T rows at positions 8w .. 8w + 7 (qr[0..7]) and 56 - 8w .. 63 - 8w
+  // (qr[8..15]), lane = row of Q, so its slots 8w + a pair qr[a] with
+  // qr[15 - a]; each shift moves one row in from each neighbouring wave.
+  // After 63 rounds every index is back at its own position.
   //
   // The block grid is enumerated as 16 folded rows of 33 (row m and row
   // 31 - m); thread tid owns blocks tid, tid + 256 and (tid < 16) tid + 512.
@@ -421,7 +429,13 @@ __global__ __launch_bounds__(256, 2) void jacobi_round64_kernel(double* __restri
     if (o < 32 - m) { bi[u] = m; bj[u] = m + o; }
     else { bi[u] = 31 - m; bj[u] = 31 - m + (o - (32 - m)); }
   }
-  const int wave_s = __builtin_amdgcn_readfirstlane(wave);
+  const int ws = __builtin_amdgcn_readfirstlane(wave);
+  double qr[16];
+#pragma unroll
+  for (int a = 0; a < 8; ++a) {
+    qr[a] = (8 * ws + a == lane) ? 1.0 : 0.0;
+    qr[8 + a] = (56 - 8 * ws + a == lane) ? 1.0 : 0.0;
+  }
   for (int r = 0; r < 63; ++r) {
     if (tid < 32) {
       int p, q;
@@ -438,35 +452,53 @@ __global__ __launch_bounds__(256, 2) void jacobi_round64_kernel(double* __restri
       }
       rcs[tid] = make_double2(c, s);
       rpq[tid] = make_int2(p, q);
+      rsw[tid] = (tid == 0 ? 0 : 1 + mod63_small(tid - 1 + r)) == q;
     }
     __syncthreads();
-    // Q^T rows: wave w takes pairs w, w + 4, ..., w + 28
-    int2 qpq[8];
-    double2 qcs[8];
-    double qx[8], qy[8];
+    // Q: finish the shift of the previous round, then rotate this round's slots
+    if (r > 0) {
+      const double (*xp)[2][64] = xch[(r - 1) & 1];
+      double nq[16];
 #pragma unroll
-    for (int k = 0; k < 8; ++k) { qpq[k] = rpq[wave_s + 4 * k]; qcs[k] = rcs[wave_s + 4 * k]; }
+      for (int a = 0; a < 7; ++a) nq[a] = qr[a + 1];
+      nq[7] = ws < 3 ? xp[ws + 1][0][lane] : qr[8];          // position 8w + 8
 #pragma unroll
-    for (int k = 0; k < 8; ++k) { qx[k] = QT[qpq[k].x][lane]; qy[k] = QT[qpq[k].y][lane]; }
-    int2 pi[3], pj[3];
+      for (int b = 0; b < 7; ++b) nq[8 + b] = qr[9 + b];
+      nq[15] = ws > 0 ? xp[ws - 1][1][lane] : qr[1];          // position 64 - 8w (64 -> 1)
+      if (ws == 0) nq[0] = qr[0];                             // position 0 stays
+#pragma unroll
+      for (int a = 0; a < 16; ++a) qr[a] = nq[a];
+    }
+#pragma unroll
+    for (int a = 0; a < 8; ++a) {
+      const int t = 8 * ws + a;
+      const double2 cs = rcs[t];
+      // the rotation was formed for p < q, so s changes sign when position
+      // t holds the larger index
+      const double sg = rsw[t] ? -cs.y : cs.y;
+      const double x = qr[a], y = qr[15 - a];
+      qr[a] = cs.x * x - sg * y;
+      qr[15 - a] = sg * x + cs.x * y;
+    }
+    {
+      double (*xw)[2][64] = xch[r & 1];
+      xw[ws][0][lane] = qr[0];   // position 8w, wanted by wave w - 1
+      xw[ws][1][lane] = qr[8];   // position 56 - 8w, wanted by wave w + 1
+    }
+    // G blocks (upper triangle): loads first, then compute and store
+    int pi[3], qi[3], pj[3], qj[3];
     double2 ci[3], cj[3];
     double ga[3], gb[3], gc[3], gd[3];
 #pragma unroll
     for (int u = 0; u < 3; ++u) {
       if (u == 2 && tid >= 16) break;
-      pi[u] = rpq[bi[u]]; pj[u] = rpq[bj[u]];
+      const int2 pqi = rpq[bi[u]], pqj = rpq[bj[u]];
+      pi[u] = pqi.x; qi[u] = pqi.y; pj[u] = pqj.x; qj[u] = pqj.y;
       ci[u] = rcs[bi[u]]; cj[u] = rcs[bj[u]];
-    }
-#pragma unroll
-    for (int u = 0; u < 3; ++u) {
-      if (u == 2 && tid >= 16) break;
-      ga[u] = G[pi[u].x][pj[u].x]; gb[u] = G[pi[u].x][pj[u].y];
-      gc[u] = G[pi[u].y][pj[u].x]; gd[u] = G[pi[u].y][pj[u].y];
-    }
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      QT[qpq[k].x][lane] = qcs[k].x * qx[k] - qcs[k].y * qy[k];
-      QT[qpq[k].y][lane] = qcs[k].y * qx[k] + qcs[k].x * qy[k];
+      ga[u] = G[min(pi[u], pj[u])][max(pi[u], pj[u])];
+      gb[u] = G[min(pi[u], qj[u])][max(pi[u], qj[u])];
+      gc[u] = G[min(qi[u], pj[u])][max(qi[u], pj[u])];
+      gd[u] = G[min(qi[u], qj[u])][max(qi[u], qj[u])];
     }
 #pragma unroll
     for (int u = 0; u < 3; ++u) {
@@ -479,12 +511,30 @@ __global__ __launch_bounds__(256, 2) void jacobi_round64_kernel(double* __restri
       const double a2 = c_i * a1 - s_i * c1, d2 = s_i * b1 + c_i * d1;
       double c2 = s_i * a1 + c_i * c1, b2 = c_i * b1 - s_i * d1;
       if (bi[u] == bj[u] && s_i != 0.0) { b2 = 0.0; c2 = 0.0; }   // the rotated pair itself
-      const int xp = pi[u].x, xq = pi[u].y, yp = pj[u].x, yq = pj[u].y;
-      G[xp][yp] = a2; G[xp][yq] = b2; G[xq][yp] = c2; G[xq][yq] = d2;
-      G[yp][xp] = a2; G[yq][xp] = b2; G[yp][xq] = c2; G[yq][xq] = d2;
+      G[min(pi[u], pj[u])][max(pi[u], pj[u])] = a2;
+      G[min(pi[u], qj[u])][max(pi[u], qj[u])] = b2;
+      G[min(qi[u], pj[u])][max(qi[u], pj[u])] = c2;
+      G[min(qi[u], qj[u])][max(qi[u], qj[u])] = d2;
     }
     __syncthreads();
   }
+  {  // last shift (positions back to indices), then Q^T to LDS for the update
+    const double (*xp)[2][64] = xch[62 & 1];
+    double nq[16];
+#pragma unroll
+    for (int a = 0; a < 7; ++a) nq[a] = qr[a + 1];
+    nq[7] = ws < 3 ? xp[ws + 1][0][lane] : qr[8];
+#pragma unroll
+    for (int b = 0; b < 7; ++b) nq[8 + b] = qr[9 + b];
+    nq[15] = ws > 0 ? xp[ws - 1][1][lane] : qr[1];
+    if (ws == 0) nq[0] = qr[0];
+#pragma unroll
+    for (int a = 0; a < 8; ++a) {
+      QT[8 * ws + a][lane] = nq[a];
+      QT[56 - 8 * ws + a][lane] = nq[8 + a];
+    }
+  }
+  __syncthreads();
 
   // ---- 3. W_pair <- Q^T W_pair ------------------------------------------
   // A fragment of output tile t, k-step s: lane (lr, lg) holds
