@@ -285,7 +285,9 @@ __device__ __forceinline__ double unit_cosine(double t) {
 //      registers).
 // One inner sweep is enough: the outer iteration recomputes the Gram from
 // the rows, and a second inner sweep did not reduce the number of outer
-// sweeps on TRG unfoldings.
+// sweeps on TRG unfoldings.  The 64 rotated rows are written in decreasing
+// norm order, the larger half to the lower-numbered block (a few percent
+// fewer outer sweeps on TRG unfoldings).
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256, 2) void jacobi_round64_kernel(double* __restrict__ W, int n_pad, int nb_all,
                                                                 const int* __restrict__ nb_job, int round,
@@ -297,8 +299,9 @@ __global__ __launch_bounds__(256, 2) void jacobi_round64_kernel(double* __restri
   const int nb = nb_job ? nb_job[job] : nb_all;   // 32-row blocks
   const int pair = blockIdx.x;
   if (round >= nb - 1 || pair >= nb / 2) return;
-  const int I = circle_block(pair, round, nb);
-  const int J = circle_block(nb - 1 - pair, round, nb);
+  // the lower-numbered block of the pair takes the larger rotated rows
+  const int I0 = circle_block(pair, round, nb), J0 = circle_block(nb - 1 - pair, round, nb);
+  const int I = min(I0, J0), J = max(I0, J0);
   double* Wj = W + (size_t)job * n_pad * n_pad;
   double* rowI = Wj + (size_t)(32 * I) * n_pad;
   double* rowJ = Wj + (size_t)(32 * J) * n_pad;
@@ -311,6 +314,7 @@ __global__ __launch_bounds__(256, 2) void jacobi_round64_kernel(double* __restri
   __shared__ int2 rpq[32];         // (p, q) of the round's pairs, by slot (p < q)
   __shared__ int rsw[32];          // 1 if position t holds the larger index q
   __shared__ double dg[64];        // current diagonal of G
+  __shared__ int rank_s[64];       // output position of each index (decreasing new row norm)
   __shared__ double xch[2][4][2][64];   // rows of Q^T handed to the neighbouring wave, by round parity
   __shared__ double redbuf[4];
 
@@ -518,6 +522,18 @@ __global__ __launch_bounds__(256, 2) void jacobi_round64_kernel(double* __restri
     }
     __syncthreads();
   }
+  // output order: decreasing diagonal of Q^T G Q (the new squared row norms),
+  // ties by index, so that the rows drift towards their final order
+  if (tid < 64) {   // (a NaN sorts last, so the ranks always form a permutation)
+    const double d = dg[tid] == dg[tid] ? dg[tid] : -INFINITY;
+    int rk = 0;
+    for (int m = 0; m < 64; ++m) {
+      const double e = dg[m] == dg[m] ? dg[m] : -INFINITY;
+      rk += (e > d || (e == d && m < tid)) ? 1 : 0;
+    }
+    rank_s[tid] = rk;
+  }
+  __syncthreads();
   {  // last shift (positions back to indices), then Q^T to LDS for the update
     const double (*xp)[2][64] = xch[62 & 1];
     double nq[16];
@@ -530,8 +546,8 @@ __global__ __launch_bounds__(256, 2) void jacobi_round64_kernel(double* __restri
     if (ws == 0) nq[0] = qr[0];
 #pragma unroll
     for (int a = 0; a < 8; ++a) {
-      QT[8 * ws + a][lane] = nq[a];
-      QT[56 - 8 * ws + a][lane] = nq[8 + a];
+      QT[rank_s[8 * ws + a]][lane] = nq[a];
+      QT[rank_s[56 - 8 * ws + a]][lane] = nq[8 + a];
     }
   }
   __syncthreads();
