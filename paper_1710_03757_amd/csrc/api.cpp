@@ -161,6 +161,8 @@ struct Chain {
   void *Xlp = nullptr, *Ylp = nullptr;
   double *S = nullptr, *Tws = nullptr, *W2 = nullptr, *Tws2 = nullptr;
   int32_t* perm = nullptr;
+  int32_t* colmap = nullptr;   // column re-ordering of the first QR (n_pad <= 1024)
+  double* colnorm = nullptr;
   int32_t *order = nullptr, *kept = nullptr, *cand = nullptr, *sel = nullptr, *src = nullptr, *split = nullptr,
           *cjobs = nullptr;
   uint64_t* rng = nullptr;
@@ -234,6 +236,8 @@ void layout(Chain& c, Arena& ar) {
   c.Tws = ar.take<double>((size_t)jmax * 32 * 1024);
   c.Tws2 = ar.take<double>((size_t)jmax * 1024);
   c.perm = ar.take<int32_t>((size_t)jmax * 4096);
+  c.colmap = ar.take<int32_t>((size_t)jmax * 1024);
+  c.colnorm = ar.take<double>((size_t)jmax * 1024);
   c.sigma = ar.take<double>(nmax);
   c.order = ar.take<int32_t>(nmax);
   c.kept = ar.take<int32_t>(jmax);
@@ -406,7 +410,7 @@ int chain_step(Chain& c) {
   const bool qr2 = sh.n_pad <= kQrMaxN;
   if (qr2) {
     CKH(run_qr2_precondition(nj, sh.n, sh.D, sh.n_pad, c.Ta, c.src, c.split, c.perm, c.S, c.Tws, c.W, c.Tws2, c.W2,
-                             c.st));
+                             c.colmap, c.colnorm, c.st));
   } else {
     CKH(launch_unfold(nj, sh.D, sh.n_pad, c.Ta, c.src, c.split, c.W2, c.st));
     CKH(launch_iota(nj, sh.n_pad, c.perm, c.st));
@@ -427,8 +431,8 @@ int chain_step(Chain& c) {
   if ((c.flags & MCTRG_RECORD) && c.record)
     CKH(launch_record(c.nsamp, s, c.n_steps, c.kmax_rec, sh.kc, c.idx, c.cand, c.kept, c.sel, c.record, c.st));
   if (qr2) {
-    CKH(launch_apply_q1(nj, sh.n, sh.n_pad, sh.kc, c.S, c.Tws, Wj, c.sigma, c.order, c.kept, c.sel, c.weight, c.F,
-                        c.st));
+    CKH(launch_apply_q1(nj, sh.n, sh.n_pad, sh.kc, c.S, sh.n_pad <= 1024 ? c.colmap : nullptr, c.Tws, Wj, c.sigma,
+                        c.order, c.kept, c.sel, c.weight, c.F, c.st));
     CKH(launch_factor_G_from_F(nj, sh.D, sh.kc, c.Ta, c.src, c.split, c.sigma, c.kept, c.sel, c.F, c.G, c.st));
   } else {
     CKH(launch_factor_G(nj, sh.D, sh.n_pad, sh.kc, Wj, c.sigma, c.order, c.kept, c.sel, c.weight, c.perm, c.G,

@@ -240,10 +240,12 @@ __global__ __launch_bounds__(NT) void qr_panel_kernel(int n_pad, int j, double* 
 // + 1 shuffles).  T of the compact WY form follows at the end, row m by
 // thread m: T[m][m] = tau_m, T[m][i] = -tau_i sum_{p=m}^{i-1} T[m][p] z_p^(i).
 __global__ __launch_bounds__(256) void qr_panel32_kernel(int n_pad, int j, double* __restrict__ S,
-                                                         double* __restrict__ Tws, int64_t t_stride, int64_t t_off) {
+                                                         double* __restrict__ Tws, int64_t t_stride, int64_t t_off,
+                                                         const int32_t* __restrict__ colmap) {
   const int64_t job = blockIdx.x;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   double* Sj = S + job * (size_t)n_pad * n_pad;
+  const int32_t* cm = colmap ? colmap + job * n_pad : nullptr;   // logical -> stored column
   __shared__ double red[4][32];
   __shared__ double rowcj[32];
   __shared__ double wz[32];
@@ -256,7 +258,7 @@ __global__ __launch_bounds__(256) void qr_panel32_kernel(int n_pad, int j, doubl
   for (int q = 0; q < 4; ++q) {
     const int r = j + tid + 256 * q;
 #pragma unroll
-    for (int c = 0; c < 32; ++c) A[q][c] = (r < n_pad) ? Sj[(size_t)(j + c) * n_pad + r] : 0.0;
+    for (int c = 0; c < 32; ++c) A[q][c] = (r < n_pad) ? Sj[(size_t)(cm ? cm[j + c] : j + c) * n_pad + r] : 0.0;
   }
   // lane l holds, after the halving exchanges, the sum of slot sidx
   const int sidx = ((lane >> 5) & 1) * 16 + ((lane >> 4) & 1) * 8 + ((lane >> 3) & 1) * 4 + ((lane >> 2) & 1) * 2 +
@@ -357,7 +359,7 @@ __global__ __launch_bounds__(256) void qr_panel32_kernel(int n_pad, int j, doubl
     const int r = j + tid + 256 * q;
     if (r < n_pad) {
 #pragma unroll
-      for (int c = 0; c < 32; ++c) Sj[(size_t)(j + c) * n_pad + r] = A[q][c];
+      for (int c = 0; c < 32; ++c) Sj[(size_t)(cm ? cm[j + c] : j + c) * n_pad + r] = A[q][c];
     }
   }
   if (tid < 32) {
@@ -390,7 +392,8 @@ __global__ __launch_bounds__(256) void qr_panel32_kernel(int n_pad, int j, doubl
 template <int PW>
 __global__ __launch_bounds__(256) void qr_trailing_kernel(int n_pad, int j, double* __restrict__ S,
                                                           const double* __restrict__ Tws, int64_t t_stride,
-                                                          int64_t t_off) {
+                                                          int64_t t_off, const int32_t* __restrict__ colmap,
+                                                          double* __restrict__ colnorm) {
   constexpr int NI = (PW + 15) / 16;     // 16-row MFMA tiles of V^T C
   const int64_t job = blockIdx.y;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -402,6 +405,10 @@ __global__ __launch_bounds__(256) void qr_trailing_kernel(int n_pad, int j, doub
   for (int e = tid; e < PW * PW; e += 256) Tm[e / PW][e % PW] = Tws[job * t_stride + t_off + e];
   const bool active = c0w < n_pad;
   const bool col_ok = (c0w + lr) < n_pad;
+  // logical column -> stored column (identity without a column map); V
+  // column j + i is stored at vcol(j + i)
+  const int32_t* cm = colmap ? colmap + job * n_pad : nullptr;
+  auto scol = [&](int c) { return cm ? cm[c] : c; };
 
   // ---- phase 1: W1 = V^T C (PW x 16 per wave) ------------------------------
   f64x4 acc[NI];
@@ -410,7 +417,7 @@ __global__ __launch_bounds__(256) void qr_trailing_kernel(int n_pad, int j, doub
   if (active) {
     // rows in chunks of 16; lane (lr, lg) takes rows rb .. rb + 3 of its
     // column (C) and of V column 16 t + lr, as 16-byte loads
-    const double* cbase = Sj + (size_t)(col_ok ? c0w + lr : c0w) * n_pad;
+    const double* cbase = Sj + (size_t)scol(col_ok ? c0w + lr : c0w) * n_pad;
     for (int r0 = j; r0 < n_pad; r0 += 16) {
       const int rb = r0 + 4 * lg;
       // n_pad and rb are multiples of 4: rows rb .. rb + 3 exist iff rb < n_pad
@@ -426,7 +433,7 @@ __global__ __launch_bounds__(256) void qr_trailing_kernel(int n_pad, int j, doub
         const int i = 16 * t + lr, d = j + i;
         double v[4];
         if (i < PW && row_ok) {
-          const double* vp = Sj + (size_t)d * n_pad + rb;
+          const double* vp = Sj + (size_t)scol(d) * n_pad + rb;
           const double2 v01 = *reinterpret_cast<const double2*>(vp);
           const double2 v23 = *reinterpret_cast<const double2*>(vp + 2);
           v[0] = v01.x; v[1] = v01.y; v[2] = v23.x; v[3] = v23.y;
@@ -472,6 +479,17 @@ __global__ __launch_bounds__(256) void qr_trailing_kernel(int n_pad, int j, doub
   double aw[KSTEPS];
 #pragma unroll
   for (int ks = 0; ks < KSTEPS; ++ks) aw[ks] = W1[4 * ks + lg][16 * wave + lr];
+  int vcols[KSTEPS], ccols[4];
+#pragma unroll
+  for (int ks = 0; ks < KSTEPS; ++ks) vcols[ks] = (4 * ks + lg < PW) ? scol(j + 4 * ks + lg) : 0;
+#pragma unroll
+  for (int x = 0; x < 4; ++x) {
+    const int c = c0w + acc_row_f64(lg, x);
+    ccols[x] = c < n_pad ? scol(c) : -1;
+  }
+  // with colnorm: squared norms of the updated columns over rows >= j + PW
+  // (what remains for the next panels), for the column re-ordering
+  double sq[4] = {0.0, 0.0, 0.0, 0.0};
   for (int r0 = j; r0 < n_pad; r0 += 16) {
     f64x4 a = {0, 0, 0, 0};
     const int rr = r0 + lr;
@@ -480,7 +498,7 @@ __global__ __launch_bounds__(256) void qr_trailing_kernel(int n_pad, int j, doub
       const int i = 4 * ks + lg, d = j + i;
       double bv = 0.0;
       if (i < PW && rr < n_pad) {
-        bv = Sj[(size_t)d * n_pad + rr];
+        bv = Sj[(size_t)vcols[ks] * n_pad + rr];
         if (r0 < j + PW) bv = rr > d ? bv : (rr == d ? 1.0 : 0.0);
       }
       a = __builtin_amdgcn_mfma_f64_16x16x4f64(aw[ks], bv, a, 0, 0, 0);
@@ -488,20 +506,80 @@ __global__ __launch_bounds__(256) void qr_trailing_kernel(int n_pad, int j, doub
     const int r = r0 + lr;
 #pragma unroll
     for (int x = 0; x < 4; ++x) {
-      const int c = c0w + acc_row_f64(lg, x);
-      if (c < n_pad && r < n_pad) Sj[(size_t)c * n_pad + r] -= a[x];
+      if (ccols[x] >= 0 && r < n_pad) {
+        double* cp = Sj + (size_t)ccols[x] * n_pad + r;
+        const double v = *cp - a[x];
+        *cp = v;
+        if (r >= j + PW) sq[x] = fma(v, v, sq[x]);
+      }
+    }
+  }
+  if (colnorm) {
+    // lanes with equal lg share the four columns: sum over lr (xor 1..8)
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+      for (int o = 1; o < 16; o <<= 1) sq[x] += __shfl_xor(sq[x], o);
+    if (lr == 0) {
+#pragma unroll
+      for (int x = 0; x < 4; ++x)
+        if (ccols[x] >= 0) colnorm[job * n_pad + ccols[x]] = sq[x];
     }
   }
 }
 
-// W[r][c] = R[r][c] = S[c][r] for r <= c, else 0 (rows of R for the Jacobi).
-__global__ void r_rows_kernel(int n_pad, const double* __restrict__ S, double* __restrict__ W) {
+// Column re-ordering between panels: the not yet factored logical columns
+// j0 .. n_pad - 1 are put in decreasing order of their remaining squared
+// norms (ties by position), by permuting the column map.  One workgroup per
+// job, bitonic sort in LDS.
+__global__ __launch_bounds__(256) void resort_cols_kernel(int n_pad, int j0, const double* __restrict__ colnorm,
+                                                          int32_t* __restrict__ colmap) {
+  __shared__ double key[1024];
+  __shared__ int idx[1024];
+  __shared__ int32_t old[1024];
+  const int64_t job = blockIdx.x;
+  const int m = n_pad - j0;
+  int P = 1;
+  while (P < m) P <<= 1;
+  int32_t* cm = colmap + job * n_pad;
+  for (int t = threadIdx.x; t < P; t += 256) {
+    if (t < m) {
+      old[t] = cm[j0 + t];
+      const double v = colnorm[job * n_pad + old[t]];
+      key[t] = v == v ? v : 0.0;   // a NaN (failed job) must not break the order
+    } else {
+      key[t] = -1.0;   // padding sorts last
+    }
+    idx[t] = t;
+  }
+  __syncthreads();
+  for (int size = 2; size <= P; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int t = threadIdx.x; t < P / 2; t += 256) {
+        const int i = 2 * stride * (t / stride) + (t % stride), k = i + stride;
+        const bool up = (i & size) == 0;
+        const double ki = key[i], kk = key[k];
+        const int ii = idx[i], ik = idx[k];
+        const bool i_first = (ki > kk) || (ki == kk && ii < ik);
+        if (up ? !i_first : i_first) { key[i] = kk; key[k] = ki; idx[i] = ik; idx[k] = ii; }
+      }
+      __syncthreads();
+    }
+  }
+  for (int t = threadIdx.x; t < m; t += 256) cm[j0 + t] = old[idx[t] < m ? idx[t] : t];
+}
+
+// W[r][c] = R[r][c] = S[colmap[c]][r] for r <= c, else 0 (rows of R for the
+// Jacobi; colmap NULL: identity).
+__global__ void r_rows_kernel(int n_pad, const double* __restrict__ S, double* __restrict__ W,
+                              const int32_t* __restrict__ colmap) {
   const int64_t job = blockIdx.z;
   __shared__ double tile[32][33];
   const size_t per = (size_t)n_pad * n_pad;
   const int bx = blockIdx.x * 32, by = blockIdx.y * 32;   // bx: column c block, by: row r block
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8 threads
-  for (int yy = ty; yy < 32; yy += 8) tile[yy][tx] = S[job * per + (size_t)(bx + yy) * n_pad + by + tx];  // [c][r]
+  const int32_t* cm = colmap ? colmap + job * n_pad : nullptr;
+  for (int yy = ty; yy < 32; yy += 8)
+    tile[yy][tx] = S[job * per + (size_t)(cm ? cm[bx + yy] : bx + yy) * n_pad + by + tx];  // [c][r]
   __syncthreads();
   for (int yy = ty; yy < 32; yy += 8) {
     const int r = by + yy, c = bx + tx;
@@ -519,28 +597,43 @@ __global__ void r_rows_kernel(int n_pad, const double* __restrict__ S, double* _
 // in 512 threads).  keep_T: the T factor of panel p is kept at
 // Tws[job * n_pad * PW + p * PW^2], otherwise every panel reuses
 // Tws[job * PW^2].
+// colmap / colnorm (n_pad entries per job, 32-column panels only): before
+// every panel after the first, the remaining columns are re-ordered by their
+// current norms below the factored rows (a blocked form of column pivoting:
+// the columns are not moved, the panel and trailing kernels address them
+// through the map, which ends as the logical -> stored column permutation).
 template <int NT, int MAXQ, int PW>
-static hipError_t qr_factor_t(int64_t njobs, int n_pad, double* S, double* Tws, bool keep_T, hipStream_t stream) {
+static hipError_t qr_factor_t(int64_t njobs, int n_pad, double* S, double* Tws, bool keep_T, int32_t* colmap,
+                              double* colnorm, hipStream_t stream) {
   const int64_t t_stride = keep_T ? (int64_t)n_pad * PW : (int64_t)PW * PW;
+  if (colmap) {
+    hipError_t e = launch_iota(njobs, n_pad, colmap, stream);
+    if (e != hipSuccess) return e;
+  }
   for (int j = 0; j < n_pad; j += PW) {
     const int64_t t_off = keep_T ? (int64_t)(j / PW) * PW * PW : 0;
     if (NT == 256 && MAXQ == 4 && PW == 32)
       hipLaunchKernelGGL(qr_panel32_kernel, dim3((unsigned)njobs), dim3(256), 0, stream, n_pad, j, S, Tws, t_stride,
-                         t_off);
+                         t_off, (const int32_t*)colmap);
     else
       hipLaunchKernelGGL((qr_panel_kernel<NT, MAXQ, PW>), dim3((unsigned)njobs), dim3(NT), 0, stream, n_pad, j, S,
                          Tws, t_stride, t_off);
     const int rest = n_pad - j - PW;
-    if (rest > 0)
+    if (rest > 0) {
       hipLaunchKernelGGL((qr_trailing_kernel<PW>), dim3(ceil_div(rest, 64), (unsigned)njobs), dim3(256), 0, stream,
-                         n_pad, j, S, Tws, t_stride, t_off);
+                         n_pad, j, S, Tws, t_stride, t_off, (const int32_t*)colmap, colmap ? colnorm : nullptr);
+      if (colmap)
+        hipLaunchKernelGGL(resort_cols_kernel, dim3((unsigned)njobs), dim3(256), 0, stream, n_pad, j + PW,
+                           (const double*)colnorm, colmap);
+    }
   }
   return hipGetLastError();
 }
 
-static hipError_t qr_factor(int64_t njobs, int n_pad, double* S, double* Tws, bool keep_T, hipStream_t stream) {
-  if (n_pad <= 1024) return qr_factor_t<256, 4, 32>(njobs, n_pad, S, Tws, keep_T, stream);
-  return qr_factor_t<512, 8, 8>(njobs, n_pad, S, Tws, keep_T, stream);
+static hipError_t qr_factor(int64_t njobs, int n_pad, double* S, double* Tws, bool keep_T, int32_t* colmap,
+                            double* colnorm, hipStream_t stream) {
+  if (n_pad <= 1024) return qr_factor_t<256, 4, 32>(njobs, n_pad, S, Tws, keep_T, colmap, colnorm, stream);
+  return qr_factor_t<512, 8, 8>(njobs, n_pad, S, Tws, keep_T, nullptr, nullptr, stream);
 }
 
 static hipError_t order_and_unfold(int64_t njobs, int n, int D, int n_pad, const double* T, const int32_t* src,
@@ -564,29 +657,35 @@ hipError_t run_qr_precondition(int64_t njobs, int n, int D, int n_pad, const dou
   if (n_pad > kQrMaxN) return hipErrorInvalidValue;
   hipError_t e = order_and_unfold(njobs, n, D, n_pad, T, src, split, perm, S, stream);
   if (e != hipSuccess) return e;
-  e = qr_factor(njobs, n_pad, S, Tws, false, stream);
+  e = qr_factor(njobs, n_pad, S, Tws, false, nullptr, nullptr, stream);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(r_rows_kernel, dim3(n_pad / 32, n_pad / 32, (unsigned)njobs), dim3(256), 0, stream, n_pad, S, W);
+  hipLaunchKernelGGL(r_rows_kernel, dim3(n_pad / 32, n_pad / 32, (unsigned)njobs), dim3(256), 0, stream, n_pad, S, W,
+                     (const int32_t*)nullptr);
   return hipGetLastError();
 }
 
-// Two QRs: M P = Q1 R1, R1^T = Q2 R2.  The rows of R1 are the columns of R1^T,
+// Two QRs: M P = Q1 R1, R1^T = Q2 R2 (P: the static norm order, refined
+// panel by panel through colmap when n_pad <= 1024; the left singular
+// vectors do not depend on P).  The rows of R1 are the columns of R1^T,
 // so the row copy of R1 (W1) is directly the column storage of R1^T.  The
 // Jacobi then runs on the rows of R2 (W2): its rows give Q1^T u_i, and Q1
 // (kept as V in S1 and the panel T factors in Tws1) maps them back.
 hipError_t run_qr2_precondition(int64_t njobs, int n, int D, int n_pad, const double* T, const int32_t* src,
                                 const int32_t* split, int32_t* perm, double* S1, double* Tws1, double* W1,
-                                double* Tws2, double* W2, hipStream_t stream) {
+                                double* Tws2, double* W2, int32_t* colmap, double* colnorm, hipStream_t stream) {
   if (njobs == 0) return hipSuccess;
   if (n_pad > kQrMaxN) return hipErrorInvalidValue;
+  if (n_pad > 1024) colmap = nullptr;   // re-ordering only with 32-column panels
   hipError_t e = order_and_unfold(njobs, n, D, n_pad, T, src, split, perm, S1, stream);
   if (e != hipSuccess) return e;
-  e = qr_factor(njobs, n_pad, S1, Tws1, true, stream);
+  e = qr_factor(njobs, n_pad, S1, Tws1, true, colmap, colnorm, stream);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(r_rows_kernel, dim3(n_pad / 32, n_pad / 32, (unsigned)njobs), dim3(256), 0, stream, n_pad, S1, W1);
-  e = qr_factor(njobs, n_pad, W1, Tws2, false, stream);
+  hipLaunchKernelGGL(r_rows_kernel, dim3(n_pad / 32, n_pad / 32, (unsigned)njobs), dim3(256), 0, stream, n_pad, S1, W1,
+                     (const int32_t*)colmap);
+  e = qr_factor(njobs, n_pad, W1, Tws2, false, nullptr, nullptr, stream);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(r_rows_kernel, dim3(n_pad / 32, n_pad / 32, (unsigned)njobs), dim3(256), 0, stream, n_pad, W1, W2);
+  hipLaunchKernelGGL(r_rows_kernel, dim3(n_pad / 32, n_pad / 32, (unsigned)njobs), dim3(256), 0, stream, n_pad, W1, W2,
+                     (const int32_t*)nullptr);
   return hipGetLastError();
 }
 
@@ -669,6 +768,7 @@ __global__ __launch_bounds__(256) void apply_q1_kernel(int n, int n_pad, int kca
 // V_p (row d of S1, entries r > d; unit diagonal implied) is streamed from
 // HBM twice per panel and workgroup instead of once per vector.
 __global__ __launch_bounds__(256) void apply_q1_mfma_kernel(int n, int n_pad, int kcap, const double* __restrict__ S1,
+                                                            const int32_t* __restrict__ colmap,
                                                             const double* __restrict__ Tws1,
                                                             const double* __restrict__ W2,
                                                             const double* __restrict__ sigma,
@@ -689,6 +789,7 @@ __global__ __launch_bounds__(256) void apply_q1_mfma_kernel(int n, int n_pad, in
   const int lr = lane & 15, lg = lane >> 4;
   const int nk = kept[job];
   const double* Sj = S1 + (size_t)job * n_pad * n_pad;
+  const int32_t* cm = colmap ? colmap + job * n_pad : nullptr;   // V_d is stored in column cm[d]
   const double* Tj = Tws1 + (size_t)job * n_pad * 32;
   if (tid < 16) {
     const int a = a0 + tid;
@@ -718,7 +819,7 @@ __global__ __launch_bounds__(256) void apply_q1_mfma_kernel(int n, int n_pad, in
 #pragma unroll
       for (int t = 0; t < 2; ++t) {
         const int d = j + 16 * t + lr;
-        const double* src = Sj + (size_t)d * n_pad + rb;
+        const double* src = Sj + (size_t)(cm ? cm[d] : d) * n_pad + rb;
         const double2 x01 = *reinterpret_cast<const double2*>(src);
         const double2 x23 = *reinterpret_cast<const double2*>(src + 2);
         av[t][0] = x01.x; av[t][1] = x01.y; av[t][2] = x23.x; av[t][3] = x23.y;
@@ -760,8 +861,12 @@ __global__ __launch_bounds__(256) void apply_q1_mfma_kernel(int n, int n_pad, in
     __syncthreads();
     // ---- X <- X - V_p Z over 16-row tiles r0 = j + 16 m -----------------
     double bz[8];
+    int vc[8];
 #pragma unroll
-    for (int s = 0; s < 8; ++s) bz[s] = Zs[(4 * s + lg) * 16 + lr];
+    for (int s = 0; s < 8; ++s) {
+      bz[s] = Zs[(4 * s + lg) * 16 + lr];
+      vc[s] = cm ? cm[j + 4 * s + lg] : j + 4 * s + lg;
+    }
     for (int r0 = j + 16 * wave; r0 < n_pad; r0 += 64) {
       f64x4 cx;
 #pragma unroll
@@ -770,7 +875,7 @@ __global__ __launch_bounds__(256) void apply_q1_mfma_kernel(int n, int n_pad, in
 #pragma unroll
       for (int s = 0; s < 8; ++s) {
         const int d = j + 4 * s + lg;
-        double v = Sj[(size_t)d * n_pad + r];
+        double v = Sj[(size_t)vc[s] * n_pad + r];
         if (r0 < j + 32) v = r > d ? v : (r == d ? 1.0 : 0.0);
         cx = __builtin_amdgcn_mfma_f64_16x16x4f64(v, bz[s], cx, 0, 0, 0);
       }
@@ -788,17 +893,18 @@ __global__ __launch_bounds__(256) void apply_q1_mfma_kernel(int n, int n_pad, in
 
 size_t apply_q1_mfma_lds(int n_pad) { return sizeof(double) * ((size_t)n_pad * 16 + 4 * 2 * 256 + 2 * 32 * 16); }
 
-hipError_t launch_apply_q1(int64_t njobs, int n, int n_pad, int kcap, const double* S1, const double* Tws1,
-                           const double* W2, const double* sigma, const int32_t* order, const int32_t* kept,
-                           const int32_t* sel, const double* weight, double* F, hipStream_t stream) {
+hipError_t launch_apply_q1(int64_t njobs, int n, int n_pad, int kcap, const double* S1, const int32_t* colmap,
+                           const double* Tws1, const double* W2, const double* sigma, const int32_t* order,
+                           const int32_t* kept, const int32_t* sel, const double* weight, double* F,
+                           hipStream_t stream) {
   if (njobs == 0) return hipSuccess;
   if (n_pad <= 1024) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&apply_q1_mfma_kernel),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)apply_q1_mfma_lds(n_pad));
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(apply_q1_mfma_kernel, dim3((kcap + 15) / 16, (unsigned)njobs), dim3(256),
-                       apply_q1_mfma_lds(n_pad), stream, n, n_pad, kcap, S1, Tws1, W2, sigma, order, kept, sel, weight,
-                       F);
+                       apply_q1_mfma_lds(n_pad), stream, n, n_pad, kcap, S1, colmap, Tws1, W2, sigma, order, kept, sel,
+                       weight, F);
   } else
     hipLaunchKernelGGL((apply_q1_kernel<16, 8>), dim3(kcap, (unsigned)njobs), dim3(256), 0, stream, n, n_pad, kcap, S1,
                        Tws1, W2, sigma, order, kept, sel, weight, F);
