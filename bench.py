@@ -13,7 +13,9 @@ device synchronisations, followed by the final trace and the estimator.
 
 Output: one JSON line with the throughput in sample-steps/s, a roofline
 record of the dominant kernel (the Jacobi rotation kernel, timed live with
-HIP events around every launch on the library's stream), the MFMA rate of
+HIP events around every launch on the library's stream; its HBM traffic per
+launch from the committed rocprofv3 counter summary when that was taken on
+the same kernel source), the whole-step roofline fraction, the MFMA rate of
 the coarse-graining GEMM, the accuracy against the CPU oracle on the first
 samples, and the oracle's own rate on the host cores.
 """
@@ -33,6 +35,25 @@ from workloads import BETA_C  # noqa: E402
 
 METRIC = "TRG sample-steps/s at χ=32 + MFMA util; |Δ ln Z|/site vs FP64 oracle"
 PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0, "fp8": 5000.0}
+PEAK_HBM_TBS = 8.0
+JACOBI_KERNEL = "jacobi_round64_kernel"
+JACOBI_SRC = os.path.join(ROOT, "paper_1710_03757_amd", "csrc", "k_jacobi.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "jacobi_traffic_k32_batch128.json")
+
+
+def measured_traffic(k, batch):
+    """HBM bytes per launch of the Jacobi rotation kernel from the committed
+    rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE summary, if it was taken on the
+    same kernel source and workload shape; otherwise None."""
+    import hashlib
+    try:
+        rec = json.load(open(TRAFFIC_FILE))
+        sha = hashlib.sha256(open(JACOBI_SRC, "rb").read()).hexdigest()
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_sha256") != sha or rec.get("k") != k or rec.get("batch") != batch:
+        return None
+    return rec
 
 
 def decomposition_flops(k: int) -> float:
@@ -104,7 +125,7 @@ def main():
     ap.add_argument("--beta", type=float, default=BETA_C)
     ap.add_argument("--h", type=float, default=0.0)
     ap.add_argument("--chain-steps", type=int, default=30)
-    ap.add_argument("--cpu-samples", type=int, default=2)
+    ap.add_argument("--cpu-samples", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="after the timed region, copy this many MiB device-to-device (a plain copy kernel of known "
@@ -165,8 +186,14 @@ def main():
     alg = decomposition_flops(k) * B * args.steps
     avg_launch_ms = jms / max(jl, 1)
     achieved = alg / max(jl, 1) / (avg_launch_ms / 1e3) / 1e12 if jl else None
-    roofline = {"bound": "mfma", "kernel": "jacobi_round_kernel", "achieved": achieved, "peak": PEAK_TFLOPS["f64"],
-                "unit": "TFLOP/s", "frac": (achieved / PEAK_TFLOPS["f64"]) if achieved else None, "traffic": None,
+    tr = measured_traffic(k, B)
+    traffic = None
+    if tr:
+        traffic = tr["fetch_bytes_per_launch"] + tr["write_bytes_per_launch"]
+    roofline = {"bound": "mfma", "kernel": JACOBI_KERNEL, "achieved": achieved, "peak": PEAK_TFLOPS["f64"],
+                "unit": "TFLOP/s", "frac": (achieved / PEAK_TFLOPS["f64"]) if achieved else None, "traffic": traffic,
+                "traffic_unit": "bytes per launch (HBM, FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                "traffic_rate_TBs": (traffic / (avg_launch_ms / 1e3) / 1e12) if (traffic and avg_launch_ms) else None,
                 "avg_launch_ms": avg_launch_ms, "launches": jl,
                 "share_of_step_time": jms / ms_total if ms_total else None}
     galg = gemm_flops(k) * B * args.steps
@@ -174,6 +201,12 @@ def main():
             "peak": PEAK_TFLOPS[args.dtype], "unit": "TFLOP/s", "avg_launch_ms": gms / max(gl, 1), "launches": gl}
     gemm["frac"] = gemm["achieved"] / gemm["peak"] if gemm["achieved"] else None
 
+    # whole-step roofline fraction: ideal time per sample-step at the peaks
+    # (algorithmic decomposition flops at FP64, contraction flops at the GEMM
+    # dtype, compulsory tensor bytes at HBM peak) over the measured time
+    t_ideal = (decomposition_flops(k) / (PEAK_TFLOPS["f64"] * 1e12) + gemm_flops(k) / (PEAK_TFLOPS[args.dtype] * 1e12)
+               + 2.0 * k ** 4 * 8 / (PEAK_HBM_TBS * 1e12))
+    t_meas = (ms_total / 1e3) / (B * args.steps)
     out = {
         "metric": METRIC,
         "value": value,
@@ -193,6 +226,7 @@ def main():
                    "k": k, "batch": B, "contract_dtype": args.dtype, "mode": "shared",
                    "decomposition": "FP64 one-sided block Jacobi"},
         "roofline": roofline,
+        "end_to_end_roofline_frac": t_ideal / t_meas,
         "mfma_contraction": gemm,
         "jacobi_sweeps_per_step": sweeps,
         "jacobi_rotated_pairs_per_sweep": pair_hist,
