@@ -119,7 +119,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=7)
-    ap.add_argument("--batch", type=int, default=128)
+    ap.add_argument("--batch", type=int, default=256)
     ap.add_argument("--k", type=int, default=32)
     ap.add_argument("--dtype", default="f32", choices=["f64", "f32", "bf16", "fp8"])
     ap.add_argument("--beta", type=float, default=BETA_C)
