@@ -527,6 +527,128 @@ __global__ __launch_bounds__(256) void qr_trailing_kernel(int n_pad, int j, doub
   }
 }
 
+// The trailing update for 32-column panels (n_pad <= 1024) with the V
+// panel staged through LDS: every 16-row chunk of V (16 x 32) is loaded once
+// per workgroup, coalesced, masked to the unit lower trapezoid, and shared
+// by the four waves (instead of each wave fetching it), double-buffered with
+// one barrier per chunk.  Same arithmetic as qr_trailing_kernel<32>.
+__global__ __launch_bounds__(256) void qr_trailing32_kernel(int n_pad, int j, double* __restrict__ S,
+                                                            const double* __restrict__ Tws, int64_t t_stride,
+                                                            int64_t t_off, const int32_t* __restrict__ colmap,
+                                                            double* __restrict__ colnorm) {
+  const int64_t job = blockIdx.y;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int lr = lane & 15, lg = lane >> 4;
+  double* Sj = S + job * (size_t)n_pad * n_pad;
+  const int c0w = j + 32 + 64 * blockIdx.x + 16 * wave;   // first column of this wave
+  __shared__ double Vs[2][16][33];
+  __shared__ double W1[32][65];
+  __shared__ double Tm[32][33];
+  for (int e = tid; e < 1024; e += 256) Tm[e >> 5][e & 31] = Tws[job * t_stride + t_off + e];
+  const bool active = c0w < n_pad;
+  const bool col_ok = (c0w + lr) < n_pad;
+  const int32_t* cm = colmap ? colmap + job * n_pad : nullptr;
+  auto scol = [&](int c) { return cm ? cm[c] : c; };
+  // V staging: thread t takes V column vd = t / 8, rows 2 (t % 8) and +1 of a chunk
+  const int vd = tid >> 3, vr = 2 * (tid & 7);
+  const double* vbase = Sj + (size_t)scol(j + vd) * n_pad;
+  auto stage_v = [&](int r0, int buf) {
+    const double2 v = *reinterpret_cast<const double2*>(vbase + r0 + vr);
+    double a = v.x, b = v.y;
+    if (r0 < j + 32) {   // V is stored below the diagonal, 1 on it, 0 above
+      const int d = j + vd, ra = r0 + vr, rb = ra + 1;
+      a = ra > d ? a : (ra == d ? 1.0 : 0.0);
+      b = rb > d ? b : (rb == d ? 1.0 : 0.0);
+    }
+    Vs[buf][vr][vd] = a;
+    Vs[buf][vr + 1][vd] = b;
+  };
+  const int nch = (n_pad - j) / 16;   // n_pad - j is a multiple of 32
+
+  // ---- phase 1: W1 = V^T C (32 x 16 per wave) ------------------------------
+  f64x4 acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
+  const double* cbase = Sj + (size_t)scol(col_ok ? c0w + lr : (active ? c0w : j + 32)) * n_pad;
+  for (int ch = 0; ch < nch; ++ch) {
+    const int r0 = j + 16 * ch, buf = ch & 1;
+    stage_v(r0, buf);
+    const int rb = r0 + 4 * lg;
+    const double2 c01 = *reinterpret_cast<const double2*>(cbase + rb);
+    const double2 c23 = *reinterpret_cast<const double2*>(cbase + rb + 2);
+    const double cv[4] = {col_ok ? c01.x : 0.0, col_ok ? c01.y : 0.0, col_ok ? c23.x : 0.0, col_ok ? c23.y : 0.0};
+    __syncthreads();
+#pragma unroll
+    for (int jj = 0; jj < 4; ++jj) {
+      acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(Vs[buf][4 * lg + jj][lr], cv[jj], acc0, 0, 0, 0);
+      acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(Vs[buf][4 * lg + jj][16 + lr], cv[jj], acc1, 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int x = 0; x < 4; ++x) {
+    W1[acc_row_f64(lg, x)][16 * wave + lr] = acc0[x];
+    W1[16 + acc_row_f64(lg, x)][16 * wave + lr] = acc1[x];
+  }
+  __syncthreads();
+  // ---- phase 2: W2 = T^T W1 (in place, column by column) -------------------
+  {
+    const int col = tid & 63, i0 = (tid >> 6) * 8;
+    double w2[8];
+#pragma unroll
+    for (int ii = 0; ii < 8; ++ii) {
+      const int i = i0 + ii;
+      double s2 = 0.0;
+      for (int m = 0; m <= i; ++m) s2 += Tm[m][i] * W1[m][col];
+      w2[ii] = s2;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ii = 0; ii < 8; ++ii) W1[i0 + ii][col] = w2[ii];
+  }
+  __syncthreads();
+  // ---- phase 3: C <- C - V W2 ------------------------------------------------
+  // output tile C^T[c (16)][r (16)] = sum_i W2^T[c][i] V^T[i][r]
+  double aw[8];
+#pragma unroll
+  for (int ks = 0; ks < 8; ++ks) aw[ks] = W1[4 * ks + lg][16 * wave + lr];
+  int ccols[4];
+#pragma unroll
+  for (int x = 0; x < 4; ++x) {
+    const int c = c0w + acc_row_f64(lg, x);
+    ccols[x] = (active && c < n_pad) ? scol(c) : -1;
+  }
+  double sq[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int ch = 0; ch < nch; ++ch) {
+    const int r0 = j + 16 * ch, buf = ch & 1;
+    stage_v(r0, buf);
+    const int r = r0 + lr;
+    double cold[4];
+#pragma unroll
+    for (int x = 0; x < 4; ++x) cold[x] = ccols[x] >= 0 ? Sj[(size_t)ccols[x] * n_pad + r] : 0.0;
+    __syncthreads();
+    f64x4 a = {0, 0, 0, 0};
+#pragma unroll
+    for (int ks = 0; ks < 8; ++ks) a = __builtin_amdgcn_mfma_f64_16x16x4f64(aw[ks], Vs[buf][lr][4 * ks + lg], a, 0, 0, 0);
+#pragma unroll
+    for (int x = 0; x < 4; ++x) {
+      if (ccols[x] >= 0) {
+        const double v = cold[x] - a[x];
+        Sj[(size_t)ccols[x] * n_pad + r] = v;
+        if (r >= j + 32) sq[x] = fma(v, v, sq[x]);
+      }
+    }
+  }
+  if (colnorm) {
+    // lanes with equal lg share the four columns: sum over lr (xor 1..8)
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+      for (int o = 1; o < 16; o <<= 1) sq[x] += __shfl_xor(sq[x], o);
+    if (lr == 0) {
+#pragma unroll
+      for (int x = 0; x < 4; ++x)
+        if (ccols[x] >= 0) colnorm[job * n_pad + ccols[x]] = sq[x];
+    }
+  }
+}
+
 // Column re-ordering between panels: the not yet factored logical columns
 // j0 .. n_pad - 1 are put in decreasing order of their remaining squared
 // norms (ties by position), by permuting the column map.  One workgroup per
@@ -620,8 +742,12 @@ static hipError_t qr_factor_t(int64_t njobs, int n_pad, double* S, double* Tws, 
                          Tws, t_stride, t_off);
     const int rest = n_pad - j - PW;
     if (rest > 0) {
-      hipLaunchKernelGGL((qr_trailing_kernel<PW>), dim3(ceil_div(rest, 64), (unsigned)njobs), dim3(256), 0, stream,
-                         n_pad, j, S, Tws, t_stride, t_off, (const int32_t*)colmap, colmap ? colnorm : nullptr);
+      if (PW == 32)
+        hipLaunchKernelGGL(qr_trailing32_kernel, dim3(ceil_div(rest, 64), (unsigned)njobs), dim3(256), 0, stream,
+                           n_pad, j, S, Tws, t_stride, t_off, (const int32_t*)colmap, colmap ? colnorm : nullptr);
+      else
+        hipLaunchKernelGGL((qr_trailing_kernel<PW>), dim3(ceil_div(rest, 64), (unsigned)njobs), dim3(256), 0, stream,
+                           n_pad, j, S, Tws, t_stride, t_off, (const int32_t*)colmap, colmap ? colnorm : nullptr);
       if (colmap)
         hipLaunchKernelGGL(resort_cols_kernel, dim3((unsigned)njobs), dim3(256), 0, stream, n_pad, j + PW,
                            (const double*)colnorm, colmap);
