@@ -234,7 +234,7 @@ void layout(Chain& c, Arena& ar) {
   c.S = ar.take<double>(wmax);
   c.W2 = ar.take<double>(wmax);
   c.Tws = ar.take<double>((size_t)jmax * 32 * 1024);
-  c.Tws2 = ar.take<double>((size_t)jmax * 1024);
+  c.Tws2 = ar.take<double>((size_t)jmax * 32 * 1024);
   c.perm = ar.take<int32_t>((size_t)jmax * 4096);
   c.colmap = ar.take<int32_t>((size_t)jmax * 1024);
   c.colnorm = ar.take<double>((size_t)jmax * 1024);
@@ -405,20 +405,22 @@ int chain_step(Chain& c) {
   CKH(hipMemcpyAsync(c.rng, c.h_rng, 3 * nj * sizeof(uint64_t), hipMemcpyHostToDevice, c.st));
   CKH(hipMemcpyAsync(c.cjobs, c.h_cjobs, 4 * no * sizeof(int32_t), hipMemcpyHostToDevice, c.st));
 
-  // decomposition: two QRs then Jacobi on the rows of R2 (n_pad <= 1024);
+  // decomposition: three QRs then Jacobi on the rows of R3 (n_pad <= 4096);
   // larger unfoldings go straight to Jacobi
-  const bool qr2 = sh.n_pad <= kQrMaxN;
-  if (qr2) {
-    CKH(run_qr2_precondition(nj, sh.n, sh.D, sh.n_pad, c.Ta, c.src, c.split, c.perm, c.S, c.Tws, c.W, c.Tws2, c.W2,
-                             c.colmap, c.colnorm, c.st));
+  const bool qr = sh.n_pad <= kQrMaxN;
+  double* rows = c.W2;   // the rows handed to the Jacobi
+  double* Wj = c.W;      // the Jacobi workspace
+  if (qr) {
+    CKH(run_qr3_precondition(nj, sh.n, sh.D, sh.n_pad, c.Ta, c.src, c.split, c.perm, c.S, c.Tws, c.W, c.Tws2, c.W2,
+                             c.colmap, c.colnorm, &rows, c.st));
+    Wj = c.W2;           // c.W keeps Q2
   } else {
     CKH(launch_unfold(nj, sh.D, sh.n_pad, c.Ta, c.src, c.split, c.W2, c.st));
     CKH(launch_iota(nj, sh.n_pad, c.perm, c.st));
   }
   // rows at the noise floor move behind the active ones and are not rotated
-  double* Wj = c.W;
   int nb_max = 0;
-  CKH(run_deflate(nj, sh.n_pad, c.W2, Wj, c.nb_job, c.jw.counter, c.jw.counter_host, &nb_max, c.st));
+  CKH(run_deflate(nj, sh.n_pad, rows, Wj, c.nb_job, c.jw.counter, c.jw.counter_host, &nb_max, c.st));
   CKH(run_jacobi(nj, sh.n_pad, Wj, c.jw, kMaxSweeps, c.st, c.tj.enabled ? &c.tj : nullptr, &c.last_sweeps, c.nb_job,
                  nb_max, c.sweep_hist));
   CKH(launch_jacobi_fail(nj, sh.jps, c.jw.sweeps, c.failed, c.st));
@@ -430,10 +432,13 @@ int chain_step(Chain& c) {
   CKH(launch_sample(sa, c.st));
   if ((c.flags & MCTRG_RECORD) && c.record)
     CKH(launch_record(c.nsamp, s, c.n_steps, c.kmax_rec, sh.kc, c.idx, c.cand, c.kept, c.sel, c.record, c.st));
-  if (qr2) {
-    CKH(launch_apply_q1(nj, sh.n, sh.n_pad, sh.kc, c.S, sh.n_pad <= 1024 ? c.colmap : nullptr, c.Tws, Wj, c.sigma,
-                        c.order, c.kept, c.sel, c.weight, c.F, c.st));
-    CKH(launch_factor_G_from_F(nj, sh.D, sh.kc, c.Ta, c.src, c.split, c.sigma, c.kept, c.sel, c.F, c.G, c.st));
+  if (qr) {
+    // z = Q2 y (in F as scratch), v = P z into G with the gauge, u = M v / s
+    CKH(launch_apply_q1(nj, sh.n, sh.n_pad, sh.kc, c.W, nullptr, c.Tws2, Wj, c.sigma, c.order, c.kept, c.sel,
+                        c.weight, c.F, c.st));
+    CKH(launch_scatter_G(nj, sh.D, sh.n_pad, sh.kc, c.F, c.perm, sh.n_pad <= 1024 ? c.colmap : nullptr, c.kept, c.G,
+                         c.st));
+    CKH(launch_factor_F(nj, sh.D, sh.kc, c.Ta, c.src, c.split, c.sigma, c.kept, c.sel, c.G, c.F, c.st));
   } else {
     CKH(launch_factor_G(nj, sh.D, sh.n_pad, sh.kc, Wj, c.sigma, c.order, c.kept, c.sel, c.weight, c.perm, c.G,
                         c.st));

@@ -264,6 +264,48 @@ hipError_t launch_factor_G_from_F(int64_t njobs, int D, int kcap, const double* 
   return hipGetLastError();
 }
 
+// Right factors from the three-QR route: X[c][a] = w_a z_a[c] is the kept
+// right singular vector of M P (logical column c, c < n: the padding columns
+// sort last), so G[a][perm[colmap[c]]] = X[c][a] (= w_a v_a^T), signed so
+// that sum_e G[a][e] / (1 + e/D + phi (e % D)) > 0.  One workgroup per
+// (a, job).
+__global__ __launch_bounds__(256) void scatter_G_kernel(int D, int n_pad, int kcap, const double* __restrict__ X,
+                                                        const int32_t* __restrict__ perm,
+                                                        const int32_t* __restrict__ colmap,
+                                                        const int32_t* __restrict__ kept, double* __restrict__ G) {
+  const int a = blockIdx.x;
+  const int64_t job = blockIdx.y;
+  const int n = D * D;
+  double* Ga = G + (size_t)job * kcap * n + (size_t)a * n;
+  if (a >= kept[job]) {
+    for (int e = threadIdx.x; e < n; e += 256) Ga[e] = 0.0;
+    return;
+  }
+  const double* Xj = X + (size_t)job * n * kcap;
+  const int32_t* pj = perm + job * n_pad;
+  const int32_t* cm = colmap ? colmap + job * n_pad : nullptr;
+  __shared__ double red[4];
+  double g = 0.0;
+  for (int c = threadIdx.x; c < n; c += 256) {
+    const int e = pj[cm ? cm[c] : c];
+    g += Xj[(size_t)c * kcap + a] / (1.0 + (double)(e / D) + kGolden * (double)(e % D));
+  }
+  for (int o = 32; o > 0; o >>= 1) g += __shfl_xor(g, o);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = g;
+  __syncthreads();
+  g = (red[0] + red[1]) + (red[2] + red[3]);
+  const double sg = g < 0.0 ? -1.0 : 1.0;
+  for (int c = threadIdx.x; c < n; c += 256) Ga[pj[cm ? cm[c] : c]] = sg * Xj[(size_t)c * kcap + a];
+}
+
+hipError_t launch_scatter_G(int64_t njobs, int D, int n_pad, int kcap, const double* X, const int32_t* perm,
+                            const int32_t* colmap, const int32_t* kept, double* G, hipStream_t stream) {
+  if (njobs == 0) return hipSuccess;
+  hipLaunchKernelGGL(scatter_G_kernel, dim3(kcap, (unsigned)njobs), dim3(256), 0, stream, D, n_pad, kcap, X, perm,
+                     colmap, kept, G);
+  return hipGetLastError();
+}
+
 // V[i][:] = W[order[i]] / sigma_i, signed so that sum_j V[i][j] g_j > 0
 // with g_j = 1 / (1 + j/d2 + phi * (j % d2)).  One workgroup per (i, matrix).
 __global__ __launch_bounds__(256) void extract_V_kernel(int n, int n_pad, int d2, const double* __restrict__ W,

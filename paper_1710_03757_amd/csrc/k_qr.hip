@@ -790,35 +790,47 @@ hipError_t run_qr_precondition(int64_t njobs, int n, int D, int n_pad, const dou
   return hipGetLastError();
 }
 
-// Two QRs: M P = Q1 R1, R1^T = Q2 R2 (P: the static norm order, refined
-// panel by panel through colmap when n_pad <= 1024; the left singular
-// vectors do not depend on P).  The rows of R1 are the columns of R1^T,
-// so the row copy of R1 (W1) is directly the column storage of R1^T.  The
-// Jacobi then runs on the rows of R2 (W2): its rows give Q1^T u_i, and Q1
-// (kept as V in S1 and the panel T factors in Tws1) maps them back.
-hipError_t run_qr2_precondition(int64_t njobs, int n, int D, int n_pad, const double* T, const int32_t* src,
+// Three QRs: M P = Q1 R1, R1^T = Q2 R2, R2^T = Q3 R3 (P: the static norm
+// order, refined panel by panel through colmap when n_pad <= 1024).  Each
+// factorisation of the transposed triangle is one step of the unshifted QR
+// iteration and moves the factor closer to diagonal, so the Jacobi on the
+// rows of R3 needs fewer sweeps.  The rows of R_i are the columns of R_i^T,
+// so each row copy is directly the column storage of the next QR.
+// Since R1 = Q3 R3 Q2^T, M P = (Q1 Q3) R3 Q2^T: the right singular vectors
+// y of R3 (the normalised rows of the Jacobi result) give those of M P as
+// z = Q2 y, and those of M as v = P z; u = M v / s.  Q2 is kept (V in W1,
+// the panel T factors in Tws2); Q1 and Q3 are not needed.  Buffers: S1 (QR1
+// in place, then the rows of R3, returned in *rows), W1 (QR2 in place), W2
+// (rows of R2, QR3 in place); Tws1 is scratch.
+hipError_t run_qr3_precondition(int64_t njobs, int n, int D, int n_pad, const double* T, const int32_t* src,
                                 const int32_t* split, int32_t* perm, double* S1, double* Tws1, double* W1,
-                                double* Tws2, double* W2, int32_t* colmap, double* colnorm, hipStream_t stream) {
+                                double* Tws2, double* W2, int32_t* colmap, double* colnorm, double** rows,
+                                hipStream_t stream) {
   if (njobs == 0) return hipSuccess;
   if (n_pad > kQrMaxN) return hipErrorInvalidValue;
   if (n_pad > 1024) colmap = nullptr;   // re-ordering only with 32-column panels
   hipError_t e = order_and_unfold(njobs, n, D, n_pad, T, src, split, perm, S1, stream);
   if (e != hipSuccess) return e;
-  e = qr_factor(njobs, n_pad, S1, Tws1, true, colmap, colnorm, stream);
+  e = qr_factor(njobs, n_pad, S1, Tws1, false, colmap, colnorm, stream);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(r_rows_kernel, dim3(n_pad / 32, n_pad / 32, (unsigned)njobs), dim3(256), 0, stream, n_pad, S1, W1,
-                     (const int32_t*)colmap);
-  e = qr_factor(njobs, n_pad, W1, Tws2, false, nullptr, nullptr, stream);
+  const dim3 rg(n_pad / 32, n_pad / 32, (unsigned)njobs);
+  hipLaunchKernelGGL(r_rows_kernel, rg, dim3(256), 0, stream, n_pad, S1, W1, (const int32_t*)colmap);
+  e = qr_factor(njobs, n_pad, W1, Tws2, true, nullptr, nullptr, stream);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(r_rows_kernel, dim3(n_pad / 32, n_pad / 32, (unsigned)njobs), dim3(256), 0, stream, n_pad, W1, W2,
-                     (const int32_t*)nullptr);
+  hipLaunchKernelGGL(r_rows_kernel, rg, dim3(256), 0, stream, n_pad, W1, W2, (const int32_t*)nullptr);
+  e = qr_factor(njobs, n_pad, W2, Tws1, false, nullptr, nullptr, stream);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(r_rows_kernel, rg, dim3(256), 0, stream, n_pad, W2, S1, (const int32_t*)nullptr);
+  *rows = S1;
   return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
-// u_a = Q1 x_a for the kept rows x_a = W2[order[sel[a]]] / s of the Jacobi
-// result, Q1 = prod_p (I - V_p T_p V_p^T) applied from the last panel to the
-// first; F[:, a] = w_a u_a.  One workgroup per (a, job).
+// X[:, a] = w_a Q x_a for the kept rows x_a = W[order[sel[a]]] / s of the
+// Jacobi result, Q = prod_p (I - V_p T_p V_p^T) the orthogonal factor of a
+// blocked Householder QR (V below the diagonal of S, stored column c in
+// colmap[c]), applied from the last panel to the first.  One workgroup per
+// (a, job).
 // ---------------------------------------------------------------------------
 template <int MAXQ, int PW>
 __global__ __launch_bounds__(256) void apply_q1_kernel(int n, int n_pad, int kcap, const double* __restrict__ S1,

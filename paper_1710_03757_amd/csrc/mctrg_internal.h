@@ -132,20 +132,25 @@ hipError_t run_qr_precondition(int64_t njobs, int n, int D, int n_pad, const dou
                                const int32_t* split, int32_t* perm, double* S, double* Tws, double* W,
                                hipStream_t stream);
 hipError_t launch_iota(int64_t njobs, int n_pad, int32_t* perm, hipStream_t stream);
-// Two-QR form: M P = Q1 R1 (V1 in S1, panel T factors in Tws1: n_pad * PW
-// <= 32768 per job), R1^T = Q2 R2 (W1 scratch, Tws2 1024 per job), W2 = rows
-// of R2.
-// colmap / colnorm: n_pad int32 / doubles per job (the column re-ordering of
-// the first QR, n_pad <= 1024; NULL: static order only).  The column map
-// is needed again by launch_apply_q1.
-hipError_t run_qr2_precondition(int64_t njobs, int n, int D, int n_pad, const double* T, const int32_t* src,
+// Three-QR preconditioning (see k_qr.hip): *rows receives the buffer with
+// the rows of R3 (S1); W1 keeps Q2 (V) and Tws2 its panel T factors
+// (n_pad * 32 doubles per job).  colmap / colnorm: n_pad int32 / doubles per
+// job (the column re-ordering of the first QR, n_pad <= 1024; NULL: static
+// order only).
+hipError_t run_qr3_precondition(int64_t njobs, int n, int D, int n_pad, const double* T, const int32_t* src,
                                 const int32_t* split, int32_t* perm, double* S1, double* Tws1, double* W1,
-                                double* Tws2, double* W2, int32_t* colmap, double* colnorm, hipStream_t stream);
-// F[:, a] = w_a Q1 (W2[order[sel[a]]] / s)   (two-QR form)
+                                double* Tws2, double* W2, int32_t* colmap, double* colnorm, double** rows,
+                                hipStream_t stream);
+// X[:, a] = w_a Q (W[order[sel[a]]] / s) with Q the orthogonal factor kept
+// in S (V, stored columns via colmap, NULL: identity) and Tws (panel T)
 hipError_t launch_apply_q1(int64_t njobs, int n, int n_pad, int kcap, const double* S1, const int32_t* colmap,
                            const double* Tws1, const double* W2, const double* sigma, const int32_t* order,
                            const int32_t* kept, const int32_t* sel, const double* weight, double* F,
                            hipStream_t stream);
+// G[a][perm[colmap[c]]] = X[c][a] (c < n; colmap NULL: identity), signed
+// with the gauge of the factor kernels; zero rows for a >= kept.
+hipError_t launch_scatter_G(int64_t njobs, int D, int n_pad, int kcap, const double* X, const int32_t* perm,
+                            const int32_t* colmap, const int32_t* kept, double* G, hipStream_t stream);
 // G[a] = F[:, a]^T M / s_a, then the sign gauge on (G[a], F[:, a]).
 hipError_t launch_factor_G_from_F(int64_t njobs, int D, int kcap, const double* T, const int32_t* src,
                                   const int32_t* split, const double* sigma, const int32_t* kept, const int32_t* sel,
