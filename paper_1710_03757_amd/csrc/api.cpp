@@ -270,6 +270,8 @@ void layout(Chain& c, Arena& ar) {
   c.jw.rotated = ar.take<int>(jmax);
   c.jw.sweeps = ar.take<int>(jmax);
   c.jw.counter = ar.take<int>(2);
+  c.jw.lastmod = ar.take<int>((size_t)jmax * kJacobiMaxBlocks);
+  c.jw.lastchk = ar.take<int>((size_t)jmax * kJacobiMaxBlocks * kJacobiMaxBlocks);
   c.nb_job = ar.take<int>(jmax);
 }
 

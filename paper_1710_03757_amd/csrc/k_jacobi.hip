@@ -293,7 +293,8 @@ __global__ __launch_bounds__(256, 2) void jacobi_round64_kernel(double* __restri
                                                                 const int* __restrict__ nb_job, int round,
                                                                 const int* __restrict__ active,
                                                                 int* __restrict__ rotated, int* __restrict__ pairs,
-                                                                double tol) {
+                                                                double tol, int* __restrict__ lastmod,
+                                                                int* __restrict__ lastchk, int stamp) {
   const int job = blockIdx.y;
   if (!active[job]) return;
   const int nb = nb_job ? nb_job[job] : nb_all;   // 32-row blocks
@@ -302,6 +303,13 @@ __global__ __launch_bounds__(256, 2) void jacobi_round64_kernel(double* __restri
   // the lower-numbered block of the pair takes the larger rotated rows
   const int I0 = circle_block(pair, round, nb), J0 = circle_block(nb - 1 - pair, round, nb);
   const int I = min(I0, J0), J = max(I0, J0);
+  // a pair found orthogonal after the last change of both its blocks still
+  // is: skip it without reading the rows (uniform)
+  int* const chk = lastmod ? lastchk + ((size_t)job * kJacobiMaxBlocks + I) * kJacobiMaxBlocks + J : nullptr;
+  if (lastmod) {
+    const int tI = lastmod[(size_t)job * kJacobiMaxBlocks + I], tJ = lastmod[(size_t)job * kJacobiMaxBlocks + J];
+    if (*chk > max(tI, tJ)) return;
+  }
   double* Wj = W + (size_t)job * n_pad * n_pad;
   double* rowI = Wj + (size_t)(32 * I) * n_pad;
   double* rowJ = Wj + (size_t)(32 * J) * n_pad;
@@ -403,8 +411,18 @@ __global__ __launch_bounds__(256, 2) void jacobi_round64_kernel(double* __restri
   if (tid < 64) dg[tid] = G[tid][tid];
   __syncthreads();
   off = fmax(fmax(redbuf[0], redbuf[1]), fmax(redbuf[2], redbuf[3]));
-  if (!(off > tol)) return;            // pair already orthogonal (uniform)
-  if (tid == 0) { atomicOr(&rotated[job], 1); atomicAdd(pairs, 1); }
+  if (!(off > tol)) {                  // pair already orthogonal (uniform)
+    if (chk && tid == 0) *chk = stamp;
+    return;
+  }
+  if (tid == 0) {
+    atomicOr(&rotated[job], 1);
+    atomicAdd(pairs, 1);
+    if (lastmod) {
+      lastmod[(size_t)job * kJacobiMaxBlocks + I] = stamp;
+      lastmod[(size_t)job * kJacobiMaxBlocks + J] = stamp;
+    }
+  }
 
   // ---- 2. one cyclic Jacobi sweep on G, accumulating Q --------------------
   // Round r: (1) lanes 0..31 form the rotations of the round's 32 disjoint
@@ -649,13 +667,20 @@ hipError_t run_jacobi(int64_t njobs, int n_pad, double* W, const JacobiWork& wk,
   int g = ceil_div(njobs, 256);
   hipLaunchKernelGGL(jacobi_init_kernel, dim3(g), dim3(256), 0, stream, njobs, wk.active, wk.rotated,
                      wk.sweeps);
+  if (wk.lastmod && brows == 32) {
+    hipError_t e = hipMemsetAsync(wk.lastmod, 0, sizeof(int) * njobs * kJacobiMaxBlocks, stream);
+    if (e == hipSuccess)
+      e = hipMemsetAsync(wk.lastchk, 0, sizeof(int) * njobs * kJacobiMaxBlocks * kJacobiMaxBlocks, stream);
+    if (e != hipSuccess) return e;
+  }
   for (int sweep = 0; sweep < max_sweeps; ++sweep) {
     hipLaunchKernelGGL(zero_int_kernel, dim3(1), dim3(2), 0, stream, wk.counter);
     for (int r = 0; r < nb - 1; ++r) {
       if (timer) { hipError_t e = timer->begin(stream); if (e != hipSuccess) return e; }
       if (brows == 32)
         hipLaunchKernelGGL(jacobi_round64_kernel, dim3(nb / 2, (unsigned)njobs), dim3(256), 0, stream, W,
-                           n_pad, nb, nb_job, r, wk.active, wk.rotated, wk.counter + 1, tol);
+                           n_pad, nb, nb_job, r, wk.active, wk.rotated, wk.counter + 1, tol, wk.lastmod, wk.lastchk,
+                           1 + sweep * (nb - 1) + r);
       else
         hipLaunchKernelGGL(jacobi_round_kernel, dim3(nb / 2, (unsigned)njobs), dim3(256), 0, stream, W,
                            n_pad, nb, nb_job, r, wk.active, wk.rotated, wk.counter + 1, tol);

@@ -112,7 +112,14 @@ struct JacobiWork {
   int* sweeps;      // njobs (-1 until converged)
   int* counter;      // device 2 ints: jobs still rotating, block pairs rotated in the sweep
   int* counter_host; // pinned host 2 ints
+  // optional (64-row pairs): per job and 32-row block, the round stamp of its
+  // last rotation (kJacobiMaxBlocks ints), and per block pair the stamp at
+  // which it was last found orthogonal (kJacobiMaxBlocks^2 ints); a pair
+  // whose blocks have not changed since then is skipped without reading it
+  int* lastmod = nullptr;
+  int* lastchk = nullptr;
 };
+constexpr int kJacobiMaxBlocks = 128;   // n_pad / 32 for n_pad <= 4096
 // history (optional, host, max_sweeps x 2): per sweep, the block pairs that
 // rotated (summed over jobs) and the jobs still rotating after it.
 hipError_t run_jacobi(int64_t njobs, int n_pad, double* W, const JacobiWork& wk, int max_sweeps,
