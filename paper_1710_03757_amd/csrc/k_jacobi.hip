@@ -224,23 +224,17 @@ __global__ __launch_bounds__(256) void jacobi_round_kernel(double* __restrict__ 
   }
 }
 
-// Circle ordering on 64 indices: slot t of round r pairs the indices at
-// positions t and 63 - t; position 0 holds index 0, position k >= 1 holds
-// 1 + (k - 1 + r) mod 63.  Returned with p < q; 0 <= t < 32, 0 <= r <= 63.
-__device__ __forceinline__ int mod63_small(int a) {   // a in [0, 189)
-  a = a >= 63 ? a - 63 : a;
-  return a >= 63 ? a - 63 : a;
-}
-__device__ __forceinline__ void circle_pair64(int t, int r, int& p, int& q) {
-  const int a = t == 0 ? 0 : 1 + mod63_small(t - 1 + r);
-  const int b = 1 + mod63_small(62 - t + r);
-  p = min(a, b);
-  q = max(a, b);
-}
-// Slot of index x in round r (0 <= r <= 63).
-__device__ __forceinline__ int circle_slot64(int x, int r) {
-  const int pos = x == 0 ? 0 : 1 + mod63_small(x - 1 + 126 - r);
-  return min(pos, 63 - pos);
+// Circle ordering on 64 indices: slot t of every round pairs the indices at
+// positions t and 63 - t; in round r position 0 holds index 0 and position
+// k >= 1 holds index 1 + (k - 1 + r) mod 63.  Between two rounds the index
+// at position k moves to circle_next64(k).
+__device__ __forceinline__ int circle_next64(int k) { return k == 0 ? 0 : (k == 1 ? 63 : k - 1); }
+
+// Position of (Q^T)[row][col] (64 x 64) in A-fragment order for
+// v_mfma_f64_16x16x4: fragment (row / 16, col / 4), lane (row % 16) +
+// 16 (col % 4).
+__device__ __forceinline__ int qt_frag_index(int row, int col) {
+  return (((row >> 4) << 4) + (col >> 2)) * 64 + ((col & 3) << 4) + (row & 15);
 }
 
 // Tangent of the Jacobi rotation annihilating g_pq of (g_pp, g_pq; g_pq,
@@ -316,12 +310,10 @@ __global__ __launch_bounds__(256, 2) void jacobi_round64_kernel(double* __restri
 
   __shared__ double G[64][65];
   __shared__ double Qs[64 * 65];   // Q^T; before that, staging of partial Gram tiles
-  double(*QT)[65] = reinterpret_cast<double(*)[65]>(Qs);               // QT[col][row] = Q[row][col]
+  double* const QTf = Qs;   // Q^T in MFMA A-fragment order (qt_frag_index)
   double(*stage)[5][256] = reinterpret_cast<double(*)[5][256]>(Qs);   // [wave-1][tile][16x16]
   __shared__ double2 rcs[32];      // (c, s) of the round's rotations, by slot
-  __shared__ int2 rpq[32];         // (p, q) of the round's pairs, by slot (p < q)
-  __shared__ int rsw[32];          // 1 if position t holds the larger index q
-  __shared__ double dg[64];        // current diagonal of G
+  __shared__ double dg[2][64];     // diagonal of G by position, by round parity
   __shared__ int rank_s[64];       // output position of each index (decreasing new row norm)
   __shared__ double xch[2][4][2][64];   // rows of Q^T handed to the neighbouring wave, by round parity
   __shared__ double redbuf[4];
@@ -408,7 +400,7 @@ __global__ __launch_bounds__(256, 2) void jacobi_round64_kernel(double* __restri
   }
   for (int o = 32; o > 0; o >>= 1) off = fmax(off, __shfl_xor(off, o));
   if (lane == 0) redbuf[wave] = off;
-  if (tid < 64) dg[tid] = G[tid][tid];
+  if (tid < 64) dg[0][tid] = G[tid][tid];
   __syncthreads();
   off = fmax(fmax(redbuf[0], redbuf[1]), fmax(redbuf[2], redbuf[3]));
   if (!(off > tol)) {                  // pair already orthogonal (uniform)
@@ -425,31 +417,48 @@ __global__ __launch_bounds__(256, 2) void jacobi_round64_kernel(double* __restri
   }
 
   // ---- 2. one cyclic Jacobi sweep on G, accumulating Q --------------------
-  // Round r: (1) lanes 0..31 form the rotations of the round's 32 disjoint
-  // pairs (dg holds the diagonal of G; G keeps its upper triangle only);
-  // (2) all rotations are applied at once: every 2 x 2 block (rows p_i,
-  // q_i; columns p_j, q_j; i <= j) of G becomes J_i^T A J_j in place, one
-  // owner per block, with the off-diagonal entry of a rotated pair set to
-  // 0, and the columns of Q are rotated.  Phase (2) has no data-dependent
-  // branches: an unrotated pair has c = 1, s = 0.
+  // The sweep works in the positions of the circle ordering: slot t rotates
+  // positions t and 63 - t in every round, and between rounds the index at
+  // position k + 1 moves to position k (position 1 to 63; position 0 stays),
+  // so after 63 rounds every index is back at its own position.  G and its
+  // diagonal are kept by position: round r reads the off-diagonal upper
+  // triangle from one buffer and writes the rotated entries, already moved
+  // to their next positions, into the other, so each thread reads and
+  // writes the same LDS addresses in every round (no index tables).
+  // Round r: (1) lanes 0..31 form the rotations of the 32 slots from the
+  // diagonal and the slot's off-diagonal entry; (2) every 2 x 2 block
+  // (positions t_i, 63 - t_i; t_j, 63 - t_j; t_i <= t_j) of G becomes
+  // J_i^T A J_j, one owner per block, the off-diagonal entry of a rotated
+  // slot set to 0, and the columns of Q are rotated.  A rotation formed with
+  // the two positions in either order gives the same two rotated rows.
   //
-  // Q lives in registers, by position of the circle ordering: slot t pairs
-  // positions t and 63 - t, and between rounds the index at position k + 1
-  // moves to position k (position 1 to 63; position 0 stays).  Wave w holds
-  // the Q^T rows at positions 8w .. 8w + 7 (qr[0..7]) and 56 - 8w .. 63 - 8w
-  // (qr[8..15]), lane = row of Q, so its slots 8w + a pair qr[a] with
-  // qr[15 - a]; each shift moves one row in from each neighbouring wave.
-  // After 63 rounds every index is back at its own position.
+  // Q lives in registers, by position: wave w holds the Q^T rows at
+  // positions 8w .. 8w + 7 (qr[0..7]) and 56 - 8w .. 63 - 8w (qr[8..15]),
+  // lane = row of Q, so its slots 8w + a pair qr[a] with qr[15 - a]; each
+  // shift moves one row in from each neighbouring wave.
   //
   // The block grid is enumerated as 16 folded rows of 33 (row m and row
   // 31 - m); thread tid owns blocks tid, tid + 256 and (tid < 16) tid + 512.
-  int bi[3], bj[3];
+  double* const G0 = &G[0][0];   // round buffers: G0 and Qs (free until Q^T is stored)
+  int rd[3][4], wr[3][4], bi[3], bj[3];   // per block: read / write offsets, slots
+  bool dblk[3];
 #pragma unroll
   for (int u = 0; u < 3; ++u) {
     const int e = min(tid + 256 * u, 527);
     const int m = e / 33, o = e - 33 * m;
-    if (o < 32 - m) { bi[u] = m; bj[u] = m + o; }
-    else { bi[u] = 31 - m; bj[u] = 31 - m + (o - (32 - m)); }
+    int ti, tj;
+    if (o < 32 - m) { ti = m; tj = m + o; }
+    else { ti = 31 - m; tj = 31 - m + (o - (32 - m)); }
+    bi[u] = ti; bj[u] = tj;
+    dblk[u] = ti == tj;
+    const int pos[4][2] = {{ti, tj}, {ti, 63 - tj}, {63 - ti, tj}, {63 - ti, 63 - tj}};
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int a = pos[v][0], b = pos[v][1];
+      rd[u][v] = min(a, b) * 65 + max(a, b);
+      const int na = circle_next64(a), nb2 = circle_next64(b);
+      wr[u][v] = min(na, nb2) * 65 + max(na, nb2);
+    }
   }
   const int ws = __builtin_amdgcn_readfirstlane(wave);
   double qr[16];
@@ -458,23 +467,25 @@ __global__ __launch_bounds__(256, 2) void jacobi_round64_kernel(double* __restri
     qr[a] = (8 * ws + a == lane) ? 1.0 : 0.0;
     qr[8 + a] = (56 - 8 * ws + a == lane) ? 1.0 : 0.0;
   }
+#pragma unroll 2
   for (int r = 0; r < 63; ++r) {
+    const double* Gc = (r & 1) ? Qs : G0;
+    double* Gn = (r & 1) ? G0 : Qs;
     if (tid < 32) {
-      int p, q;
-      circle_pair64(tid, r, p, q);
-      const double gpp = dg[p], gqq = dg[q], gpq = G[p][q];
-      double c = 1.0, s = 0.0;
+      const int x = tid, y = 63 - tid;
+      const double gxx = dg[r & 1][x], gyy = dg[r & 1][y], gxy = Gc[x * 65 + y];
+      double c = 1.0, s = 0.0, dx = gxx, dy = gyy;
       // |.| guards the tiny diagonal entries that rounding can push below 0
-      if (gpq != 0.0 && gpq * gpq > 0x1.0p-106 * fabs(gpp * gqq)) {
-        const double t = jacobi_tangent(gpp, gqq, gpq);
+      if (gxy != 0.0 && gxy * gxy > 0x1.0p-106 * fabs(gxx * gyy)) {
+        const double t = jacobi_tangent(gxx, gyy, gxy);
         c = unit_cosine(t);
         s = t * c;
-        dg[p] = fma(-t, gpq, gpp);
-        dg[q] = fma(t, gpq, gqq);
+        dx = fma(-t, gxy, gxx);
+        dy = fma(t, gxy, gyy);
       }
       rcs[tid] = make_double2(c, s);
-      rpq[tid] = make_int2(p, q);
-      rsw[tid] = (tid == 0 ? 0 : 1 + mod63_small(tid - 1 + r)) == q;
+      dg[(r + 1) & 1][circle_next64(x)] = dx;
+      dg[(r + 1) & 1][circle_next64(y)] = dy;
     }
     __syncthreads();
     // Q: finish the shift of the previous round, then rotate this round's slots
@@ -493,60 +504,53 @@ __global__ __launch_bounds__(256, 2) void jacobi_round64_kernel(double* __restri
     }
 #pragma unroll
     for (int a = 0; a < 8; ++a) {
-      const int t = 8 * ws + a;
-      const double2 cs = rcs[t];
-      // the rotation was formed for p < q, so s changes sign when position
-      // t holds the larger index
-      const double sg = rsw[t] ? -cs.y : cs.y;
+      const double2 cs = rcs[8 * ws + a];
       const double x = qr[a], y = qr[15 - a];
-      qr[a] = cs.x * x - sg * y;
-      qr[15 - a] = sg * x + cs.x * y;
+      qr[a] = cs.x * x - cs.y * y;
+      qr[15 - a] = cs.y * x + cs.x * y;
     }
     {
       double (*xw)[2][64] = xch[r & 1];
       xw[ws][0][lane] = qr[0];   // position 8w, wanted by wave w - 1
       xw[ws][1][lane] = qr[8];   // position 56 - 8w, wanted by wave w + 1
     }
-    // G blocks (upper triangle): loads first, then compute and store
-    int pi[3], qi[3], pj[3], qj[3];
+    // G blocks: loads first, then compute and store into the other buffer
     double2 ci[3], cj[3];
     double ga[3], gb[3], gc[3], gd[3];
 #pragma unroll
     for (int u = 0; u < 3; ++u) {
       if (u == 2 && tid >= 16) break;
-      const int2 pqi = rpq[bi[u]], pqj = rpq[bj[u]];
-      pi[u] = pqi.x; qi[u] = pqi.y; pj[u] = pqj.x; qj[u] = pqj.y;
       ci[u] = rcs[bi[u]]; cj[u] = rcs[bj[u]];
-      ga[u] = G[min(pi[u], pj[u])][max(pi[u], pj[u])];
-      gb[u] = G[min(pi[u], qj[u])][max(pi[u], qj[u])];
-      gc[u] = G[min(qi[u], pj[u])][max(qi[u], pj[u])];
-      gd[u] = G[min(qi[u], qj[u])][max(qi[u], qj[u])];
+      ga[u] = Gc[rd[u][0]]; gb[u] = Gc[rd[u][1]]; gc[u] = Gc[rd[u][2]]; gd[u] = Gc[rd[u][3]];
     }
 #pragma unroll
     for (int u = 0; u < 3; ++u) {
       if (u == 2 && tid >= 16) break;
       const double c_i = ci[u].x, s_i = ci[u].y, c_j = cj[u].x, s_j = cj[u].y;
-      // A J_j: columns (p, q) -> (c p - s q, s p + c q)
+      // A J_j: columns (x, y) -> (c x - s y, s x + c y)
       const double a1 = c_j * ga[u] - s_j * gb[u], b1 = s_j * ga[u] + c_j * gb[u];
       const double c1 = c_j * gc[u] - s_j * gd[u], d1 = s_j * gc[u] + c_j * gd[u];
-      // J_i^T (A J_j): rows (p, q) -> (c p - s q, s p + c q)
+      // J_i^T (A J_j): rows (x, y) -> (c x - s y, s x + c y)
       const double a2 = c_i * a1 - s_i * c1, d2 = s_i * b1 + c_i * d1;
       double c2 = s_i * a1 + c_i * c1, b2 = c_i * b1 - s_i * d1;
-      if (bi[u] == bj[u] && s_i != 0.0) { b2 = 0.0; c2 = 0.0; }   // the rotated pair itself
-      G[min(pi[u], pj[u])][max(pi[u], pj[u])] = a2;
-      G[min(pi[u], qj[u])][max(pi[u], qj[u])] = b2;
-      G[min(qi[u], pj[u])][max(qi[u], pj[u])] = c2;
-      G[min(qi[u], qj[u])][max(qi[u], qj[u])] = d2;
+      // a slot's own block: its off-diagonal entry (stored once, at b and c)
+      // is 0 after the rotation; the diagonal slots of G are not used (dg)
+      if (dblk[u] && s_i != 0.0) { b2 = 0.0; c2 = 0.0; }
+      Gn[wr[u][0]] = a2;
+      Gn[wr[u][1]] = b2;
+      Gn[wr[u][2]] = c2;
+      Gn[wr[u][3]] = d2;
     }
     __syncthreads();
   }
   // output order: decreasing diagonal of Q^T G Q (the new squared row norms),
   // ties by index, so that the rows drift towards their final order
   if (tid < 64) {   // (a NaN sorts last, so the ranks always form a permutation)
-    const double d = dg[tid] == dg[tid] ? dg[tid] : -INFINITY;
+    const double* dgf = dg[63 & 1];
+    const double d = dgf[tid] == dgf[tid] ? dgf[tid] : -INFINITY;
     int rk = 0;
     for (int m = 0; m < 64; ++m) {
-      const double e = dg[m] == dg[m] ? dg[m] : -INFINITY;
+      const double e = dgf[m] == dgf[m] ? dgf[m] : -INFINITY;
       rk += (e > d || (e == d && m < tid)) ? 1 : 0;
     }
     rank_s[tid] = rk;
@@ -564,39 +568,45 @@ __global__ __launch_bounds__(256, 2) void jacobi_round64_kernel(double* __restri
     if (ws == 0) nq[0] = qr[0];
 #pragma unroll
     for (int a = 0; a < 8; ++a) {
-      QT[rank_s[8 * ws + a]][lane] = nq[a];
-      QT[rank_s[56 - 8 * ws + a]][lane] = nq[8 + a];
+      QTf[qt_frag_index(rank_s[8 * ws + a], lane)] = nq[a];
+      QTf[qt_frag_index(rank_s[56 - 8 * ws + a], lane)] = nq[8 + a];
     }
   }
   __syncthreads();
 
   // ---- 3. W_pair <- Q^T W_pair ------------------------------------------
-  // A fragment of output tile t, k-step s: lane (lr, lg) holds
-  // (Q^T)[16 t + lr][4 s + lg] = Q[4 s + lg][16 t + lr].
-  double qa[4][16];
-#pragma unroll
-  for (int t = 0; t < 4; ++t)
-#pragma unroll
-    for (int s = 0; s < 16; ++s) qa[t][s] = QT[16 * t + lr][4 * s + lg];
-
+  // Each wave takes 16-column chunks c0 = 16 wave + 64 i; lane (lr, lg) of
+  // the B fragment of k-step s holds W_pair[4 s + lg][c0 + lr].  The A
+  // fragments are read from LDS (64 consecutive doubles each, no bank
+  // conflicts), which leaves the registers for the next chunk's loads, so
+  // every wave keeps one chunk in flight while it multiplies the other.
   auto row_ptr = [&](int r) -> double* {
     return r < 32 ? rowI + (size_t)r * n_pad : rowJ + (size_t)(r - 32) * n_pad;
   };
-  for (int c0 = 16 * wave; c0 < n_pad; c0 += 64) {
-    double bc[16];
+  auto load_b = [&](int c0, double (&v)[16]) {
 #pragma unroll
-    for (int s = 0; s < 16; ++s) bc[s] = row_ptr(4 * s + lg)[c0 + lr];
+    for (int s = 0; s < 16; ++s) v[s] = row_ptr(4 * s + lg)[c0 + lr];
+  };
+  double bc[16], bn[16];
+  int c0 = 16 * wave;
+  if (c0 < n_pad) load_b(c0, bc);
+  for (; c0 < n_pad; c0 += 64) {
+    if (c0 + 64 < n_pad) load_b(c0 + 64, bn);
+    asm volatile("" ::: "memory");   // keep the fragment reads inside the loop
     f64x4 out[4];
 #pragma unroll
     for (int t = 0; t < 4; ++t) out[t] = f64x4{0, 0, 0, 0};
 #pragma unroll
     for (int s = 0; s < 16; ++s)
 #pragma unroll
-      for (int t = 0; t < 4; ++t) out[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(qa[t][s], bc[s], out[t], 0, 0, 0);
+      for (int t = 0; t < 4; ++t)
+        out[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(QTf[(16 * t + s) * 64 + lane], bc[s], out[t], 0, 0, 0);
 #pragma unroll
     for (int t = 0; t < 4; ++t)
 #pragma unroll
       for (int i = 0; i < 4; ++i) row_ptr(16 * t + acc_row_f64(lg, i))[c0 + lr] = out[t][i];
+#pragma unroll
+    for (int s = 0; s < 16; ++s) bc[s] = bn[s];
   }
 }
 
