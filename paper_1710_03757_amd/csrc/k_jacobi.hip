@@ -230,6 +230,13 @@ __global__ __launch_bounds__(256) void jacobi_round_kernel(double* __restrict__ 
 // at position k moves to circle_next64(k).
 __device__ __forceinline__ int circle_next64(int k) { return k == 0 ? 0 : (k == 1 ? 63 : k - 1); }
 
+// Packed strictly upper triangle of a 64 x 64 symmetric matrix: entry (i, j),
+// i < j, row by row.  Two such buffers (kGpk entries each) are followed by a
+// slot that holds 0 and a slot that absorbs writes.
+constexpr int kGpk = 64 * 63 / 2;
+constexpr int kGzero = 2 * kGpk, kGsink = 2 * kGpk + 1;
+__device__ __forceinline__ int gpk_index(int i, int j) { return 63 * i - ((i * (i + 1)) >> 1) + j - 1; }
+
 // Position of (Q^T)[row][col] (64 x 64) in A-fragment order for
 // v_mfma_f64_16x16x4: fragment (row / 16, col / 4), lane (row % 16) +
 // 16 (col % 4).
@@ -283,7 +290,7 @@ __device__ __forceinline__ double unit_cosine(double t) {
 // norm order, the larger half to the lower-numbered block (a few percent
 // fewer outer sweeps on TRG unfoldings).
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256, 2) void jacobi_round64_kernel(double* __restrict__ W, int n_pad, int nb_all,
+__global__ __launch_bounds__(256, 3) void jacobi_round64_kernel(double* __restrict__ W, int n_pad, int nb_all,
                                                                 const int* __restrict__ nb_job, int round,
                                                                 const int* __restrict__ active,
                                                                 int* __restrict__ rotated, int* __restrict__ pairs,
@@ -308,10 +315,12 @@ __global__ __launch_bounds__(256, 2) void jacobi_round64_kernel(double* __restri
   double* rowI = Wj + (size_t)(32 * I) * n_pad;
   double* rowJ = Wj + (size_t)(32 * J) * n_pad;
 
-  __shared__ double G[64][65];
-  __shared__ double Qs[64 * 65];   // Q^T; before that, staging of partial Gram tiles
-  double* const QTf = Qs;   // Q^T in MFMA A-fragment order (qt_frag_index)
-  double(*stage)[5][256] = reinterpret_cast<double(*)[5][256]>(Qs);   // [wave-1][tile][16x16]
+  // U: the staged partial Gram tiles, then the two position-space buffers of
+  // the strictly upper triangle of G (packed, kGpk entries each) with a zero
+  // slot and a sink slot behind them, then Q^T in A-fragment order.
+  __shared__ double U[4096];
+  double* const QTf = U;                                              // qt_frag_index
+  double(*stage)[5][256] = reinterpret_cast<double(*)[5][256]>(U);   // [wave-1][tile][16x16]
   __shared__ double2 rcs[32];      // (c, s) of the round's rotations, by slot
   __shared__ double dg[2][64];     // diagonal of G by position, by round parity
   __shared__ int rank_s[64];       // output position of each index (decreasing new row norm)
@@ -357,7 +366,10 @@ __global__ __launch_bounds__(256, 2) void jacobi_round64_kernel(double* __restri
 #pragma unroll
       for (int jj = 0; jj < 4; ++jj) cur[sb][jj] = nxt[sb][jj];
   }
-  // partial tiles: waves 1..3 stage five tiles at a time, wave 0 sums
+  // partial tiles: waves 1..3 stage five tiles at a time, wave 0 adds them
+  // to its own (same order for every entry), then stores G by position
+  // (= index before the first round): the diagonal in dg, the strictly upper
+  // triangle packed
 #pragma unroll
   for (int half = 0; half < 2; ++half) {
     if (wave > 0) {
@@ -368,39 +380,46 @@ __global__ __launch_bounds__(256, 2) void jacobi_round64_kernel(double* __restri
     }
     __syncthreads();
     if (wave == 0) {
-      int t = 0;
 #pragma unroll
-      for (int a = 0; a < 4; ++a)
+      for (int t = 5 * half; t < 5 * half + 5; ++t)
 #pragma unroll
-        for (int b = a; b < 4; ++b) {
-          if (t >= 5 * half && t < 5 * half + 5) {
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-              const int row = acc_row_f64(lg, i), idx = row * 16 + lr;
-              const double v = ((acc[t][i] + stage[0][t - 5 * half][idx]) + stage[1][t - 5 * half][idx]) +
-                               stage[2][t - 5 * half][idx];
-              G[16 * a + row][16 * b + lr] = v;
-              G[16 * b + lr][16 * a + row] = v;
-            }
-          }
-          ++t;
+        for (int i = 0; i < 4; ++i) {
+          const int idx = acc_row_f64(lg, i) * 16 + lr;
+          acc[t][i] = ((acc[t][i] + stage[0][t - 5 * half][idx]) + stage[1][t - 5 * half][idx]) +
+                      stage[2][t - 5 * half][idx];
         }
     }
     __syncthreads();
   }
+  if (wave == 0) {
+    int t = 0;
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = a; b < 4; ++b) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int row = 16 * a + acc_row_f64(lg, i), col = 16 * b + lr;
+          if (row < col) U[gpk_index(row, col)] = acc[t][i];
+          else if (row == col) dg[0][row] = acc[t][i];
+        }
+        ++t;
+      }
+  }
+  if (tid == 0) U[kGzero] = 0.0;
+  __syncthreads();
 
   // ---- convergence test of this pair ------------------------------------
   double off = 0.0;
   for (int e = tid; e < 4096; e += 256) {
     const int i = e >> 6, j = e & 63;
     if (i < j) {
-      const double d = G[i][i] * G[j][j];
-      if (d > 0.0) off = fmax(off, fabs(G[i][j]) / sqrt(d));
+      const double d = dg[0][i] * dg[0][j];
+      if (d > 0.0) off = fmax(off, fabs(U[gpk_index(i, j)]) / sqrt(d));
     }
   }
   for (int o = 32; o > 0; o >>= 1) off = fmax(off, __shfl_xor(off, o));
   if (lane == 0) redbuf[wave] = off;
-  if (tid < 64) dg[0][tid] = G[tid][tid];
   __syncthreads();
   off = fmax(fmax(redbuf[0], redbuf[1]), fmax(redbuf[2], redbuf[3]));
   if (!(off > tol)) {                  // pair already orthogonal (uniform)
@@ -439,7 +458,6 @@ __global__ __launch_bounds__(256, 2) void jacobi_round64_kernel(double* __restri
   //
   // The block grid is enumerated as 16 folded rows of 33 (row m and row
   // 31 - m); thread tid owns blocks tid, tid + 256 and (tid < 16) tid + 512.
-  double* const G0 = &G[0][0];   // round buffers: G0 and Qs (free until Q^T is stored)
   int rd[3][4], wr[3][4], bi[3], bj[3];   // per block: read / write offsets, slots
   bool dblk[3];
 #pragma unroll
@@ -451,13 +469,15 @@ __global__ __launch_bounds__(256, 2) void jacobi_round64_kernel(double* __restri
     else { ti = 31 - m; tj = 31 - m + (o - (32 - m)); }
     bi[u] = ti; bj[u] = tj;
     dblk[u] = ti == tj;
+    // a slot's own block holds two diagonal entries (kept in dg): they read
+    // the zero slot and are written to the sink
     const int pos[4][2] = {{ti, tj}, {ti, 63 - tj}, {63 - ti, tj}, {63 - ti, 63 - tj}};
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int a = pos[v][0], b = pos[v][1];
-      rd[u][v] = min(a, b) * 65 + max(a, b);
       const int na = circle_next64(a), nb2 = circle_next64(b);
-      wr[u][v] = min(na, nb2) * 65 + max(na, nb2);
+      rd[u][v] = a == b ? kGzero : gpk_index(min(a, b), max(a, b));
+      wr[u][v] = a == b ? kGsink : gpk_index(min(na, nb2), max(na, nb2));
     }
   }
   const int ws = __builtin_amdgcn_readfirstlane(wave);
@@ -469,11 +489,11 @@ __global__ __launch_bounds__(256, 2) void jacobi_round64_kernel(double* __restri
   }
 #pragma unroll 2
   for (int r = 0; r < 63; ++r) {
-    const double* Gc = (r & 1) ? Qs : G0;
-    double* Gn = (r & 1) ? G0 : Qs;
+    const double* Gc = U + (r & 1) * kGpk;
+    double* Gn = U + ((r + 1) & 1) * kGpk;
     if (tid < 32) {
       const int x = tid, y = 63 - tid;
-      const double gxx = dg[r & 1][x], gyy = dg[r & 1][y], gxy = Gc[x * 65 + y];
+      const double gxx = dg[r & 1][x], gyy = dg[r & 1][y], gxy = Gc[gpk_index(x, y)];
       double c = 1.0, s = 0.0, dx = gxx, dy = gyy;
       // |.| guards the tiny diagonal entries that rounding can push below 0
       if (gxy != 0.0 && gxy * gxy > 0x1.0p-106 * fabs(gxx * gyy)) {
@@ -514,27 +534,21 @@ __global__ __launch_bounds__(256, 2) void jacobi_round64_kernel(double* __restri
       xw[ws][0][lane] = qr[0];   // position 8w, wanted by wave w - 1
       xw[ws][1][lane] = qr[8];   // position 56 - 8w, wanted by wave w + 1
     }
-    // G blocks: loads first, then compute and store into the other buffer
-    double2 ci[3], cj[3];
-    double ga[3], gb[3], gc[3], gd[3];
+    // G blocks: read from this round's buffer, store into the other
 #pragma unroll
     for (int u = 0; u < 3; ++u) {
       if (u == 2 && tid >= 16) break;
-      ci[u] = rcs[bi[u]]; cj[u] = rcs[bj[u]];
-      ga[u] = Gc[rd[u][0]]; gb[u] = Gc[rd[u][1]]; gc[u] = Gc[rd[u][2]]; gd[u] = Gc[rd[u][3]];
-    }
-#pragma unroll
-    for (int u = 0; u < 3; ++u) {
-      if (u == 2 && tid >= 16) break;
-      const double c_i = ci[u].x, s_i = ci[u].y, c_j = cj[u].x, s_j = cj[u].y;
+      const double2 ci = rcs[bi[u]], cj = rcs[bj[u]];
+      const double ga = Gc[rd[u][0]], gb = Gc[rd[u][1]], gc = Gc[rd[u][2]], gd = Gc[rd[u][3]];
+      const double c_i = ci.x, s_i = ci.y, c_j = cj.x, s_j = cj.y;
       // A J_j: columns (x, y) -> (c x - s y, s x + c y)
-      const double a1 = c_j * ga[u] - s_j * gb[u], b1 = s_j * ga[u] + c_j * gb[u];
-      const double c1 = c_j * gc[u] - s_j * gd[u], d1 = s_j * gc[u] + c_j * gd[u];
+      const double a1 = c_j * ga - s_j * gb, b1 = s_j * ga + c_j * gb;
+      const double c1 = c_j * gc - s_j * gd, d1 = s_j * gc + c_j * gd;
       // J_i^T (A J_j): rows (x, y) -> (c x - s y, s x + c y)
       const double a2 = c_i * a1 - s_i * c1, d2 = s_i * b1 + c_i * d1;
       double c2 = s_i * a1 + c_i * c1, b2 = c_i * b1 - s_i * d1;
       // a slot's own block: its off-diagonal entry (stored once, at b and c)
-      // is 0 after the rotation; the diagonal slots of G are not used (dg)
+      // is 0 after the rotation
       if (dblk[u] && s_i != 0.0) { b2 = 0.0; c2 = 0.0; }
       Gn[wr[u][0]] = a2;
       Gn[wr[u][1]] = b2;
