@@ -41,7 +41,7 @@ __global__ __launch_bounds__(256) void jacobi_round_kernel(double* __restrict__ 
   // rows beyond the job's active blocks sit below the noise floor and stay
   // as they are (see deflate_rows_kernel)
   const int nb = nb_job ? nb_job[job] : nb_all;
-  const int pair = blockIdx.x;
+  const int pair = (int)((blockIdx.x + blockIdx.y) % gridDim.x);   // XCD balance (see jacobi_round64_kernel)
   if (round >= nb - 1 || pair >= nb / 2) return;
   const int I = circle_block(pair, round, nb);
   const int J = circle_block(nb - 1 - pair, round, nb);
@@ -299,7 +299,12 @@ __global__ __launch_bounds__(256, 3) void jacobi_round64_kernel(double* __restri
   const int job = blockIdx.y;
   if (!active[job]) return;
   const int nb = nb_job ? nb_job[job] : nb_all;   // 32-row blocks
-  const int pair = blockIdx.x;
+  // Workgroups reach the XCDs round-robin by linear index, so with pair =
+  // blockIdx.x each XCD would always get the same pair slots; how often a
+  // pair still rotates depends strongly on its slot (rows are kept sorted by
+  // norm), which would load some XCDs with most of the rotations.  Rotating
+  // the slot by the decomposition index spreads every slot over all XCDs.
+  const int pair = (int)((blockIdx.x + blockIdx.y) % gridDim.x);
   if (round >= nb - 1 || pair >= nb / 2) return;
   // the lower-numbered block of the pair takes the larger rotated rows
   const int I0 = circle_block(pair, round, nb), J0 = circle_block(nb - 1 - pair, round, nb);
