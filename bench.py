@@ -38,7 +38,7 @@ PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0, "fp8": 5000.0}
 PEAK_HBM_TBS = 8.0
 JACOBI_KERNEL = "jacobi_round64_kernel"
 JACOBI_SRC = os.path.join(ROOT, "paper_1710_03757_amd", "csrc", "k_jacobi.hip")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "jacobi_traffic_k32_batch128.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "jacobi_traffic_k32_batch256.json")
 
 
 def measured_traffic(k, batch):
