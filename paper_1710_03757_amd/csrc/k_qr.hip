@@ -527,12 +527,13 @@ __global__ __launch_bounds__(256) void qr_trailing_kernel(int n_pad, int j, doub
   }
 }
 
-// The trailing update for 32-column panels (n_pad <= 1024) with the V
+// The trailing update for 32-column panels (n_pad <= 1024; columns j + 32 ..
+// cend - 1) with the V
 // panel staged through LDS: every 16-row chunk of V (16 x 32) is loaded once
 // per workgroup, coalesced, masked to the unit lower trapezoid, and shared
 // by the four waves (instead of each wave fetching it), double-buffered with
 // one barrier per chunk.  Same arithmetic as qr_trailing_kernel<32>.
-__global__ __launch_bounds__(256) void qr_trailing32_kernel(int n_pad, int j, double* __restrict__ S,
+__global__ __launch_bounds__(256) void qr_trailing32_kernel(int n_pad, int j, int cend, double* __restrict__ S,
                                                             const double* __restrict__ Tws, int64_t t_stride,
                                                             int64_t t_off, const int32_t* __restrict__ colmap,
                                                             double* __restrict__ colnorm) {
@@ -545,8 +546,8 @@ __global__ __launch_bounds__(256) void qr_trailing32_kernel(int n_pad, int j, do
   __shared__ double W1[32][65];
   __shared__ double Tm[32][33];
   for (int e = tid; e < 1024; e += 256) Tm[e >> 5][e & 31] = Tws[job * t_stride + t_off + e];
-  const bool active = c0w < n_pad;
-  const bool col_ok = (c0w + lr) < n_pad;
+  const bool active = c0w < cend;   // columns j + 32 .. cend - 1 are updated
+  const bool col_ok = (c0w + lr) < cend;
   const int32_t* cm = colmap ? colmap + job * n_pad : nullptr;
   auto scol = [&](int c) { return cm ? cm[c] : c; };
   // V staging: thread t takes V column vd = t / 8, rows 2 (t % 8) and +1 of a chunk
@@ -613,7 +614,7 @@ __global__ __launch_bounds__(256) void qr_trailing32_kernel(int n_pad, int j, do
 #pragma unroll
   for (int x = 0; x < 4; ++x) {
     const int c = c0w + acc_row_f64(lg, x);
-    ccols[x] = (active && c < n_pad) ? scol(c) : -1;
+    ccols[x] = (active && c < cend) ? scol(c) : -1;
   }
   double sq[4] = {0.0, 0.0, 0.0, 0.0};
   for (int ch = 0; ch < nch; ++ch) {
@@ -646,6 +647,186 @@ __global__ __launch_bounds__(256) void qr_trailing32_kernel(int n_pad, int j, do
       for (int x = 0; x < 4; ++x)
         if (ccols[x] >= 0) colnorm[job * n_pad + ccols[x]] = sq[x];
     }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// 64-column blocks (factorisations without column re-ordering): the block's
+// two 32-column panels are factored one after the other (the second after the
+// first has been applied to it), then Q = (I - V1 T1 V1^T)(I - V2 T2 V2^T) =
+// I - V T V^T with V = [V1 V2] and T = [[T1, -T1 (V1^T V2) T2], [0, T2]] is
+// applied to the rest in one pass, half the passes over the trailing matrix
+// of 32-column blocks.
+//
+// qr_t64_kernel: T (64 x 64, row-major) of the block at column j into T64,
+// one workgroup per job.  V1^T V2 only involves rows >= j + 32 (V2 vanishes
+// above); each wave forms one 16 x 16 tile of it with MFMA, a lane taking
+// two consecutive rows per step (16-byte loads; V is stored column-major).
+__global__ __launch_bounds__(256) void qr_t64_kernel(int n_pad, int j, const double* __restrict__ S,
+                                                     const double* __restrict__ Tws, int64_t t_stride, int64_t t_off1,
+                                                     int64_t t_off2, double* __restrict__ T64) {
+  const int64_t job = blockIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int lr = lane & 15, lg = lane >> 4;
+  const double* Sj = S + job * (size_t)n_pad * n_pad;
+  __shared__ double X[32][33], T1[32][33], T2[32][33], Y[32][33];
+  for (int e = tid; e < 1024; e += 256) {
+    T1[e >> 5][e & 31] = Tws[job * t_stride + t_off1 + e];
+    T2[e >> 5][e & 31] = Tws[job * t_stride + t_off2 + e];
+  }
+  const int ta = wave >> 1, tb = wave & 1;
+  const double* c1 = Sj + (size_t)(j + 16 * ta + lr) * n_pad;        // column of V1 (all rows >= j + 32 below its diagonal)
+  const int d2 = j + 32 + 16 * tb + lr;                                // diagonal row of this V2 column
+  const double* c2 = Sj + (size_t)d2 * n_pad;
+  f64x4 acc = {0, 0, 0, 0};
+  for (int r0 = j + 32; r0 < n_pad; r0 += 8) {
+    const int r = r0 + 2 * lg;
+    const double2 a = *reinterpret_cast<const double2*>(c1 + r);
+    double2 b = *reinterpret_cast<const double2*>(c2 + r);
+    b.x = r > d2 ? b.x : (r == d2 ? 1.0 : 0.0);
+    b.y = r + 1 > d2 ? b.y : (r + 1 == d2 ? 1.0 : 0.0);
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.x, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b.y, acc, 0, 0, 0);
+  }
+#pragma unroll
+  for (int x = 0; x < 4; ++x) X[16 * ta + acc_row_f64(lg, x)][16 * tb + lr] = acc[x];
+  __syncthreads();
+  for (int e = tid; e < 1024; e += 256) {   // Y = X T2
+    const int a = e >> 5, b = e & 31;
+    double v = 0.0;
+    for (int m = 0; m <= b; ++m) v = fma(X[a][m], T2[m][b], v);
+    Y[a][b] = v;
+  }
+  __syncthreads();
+  double* Tj = T64 + job * 4096;
+  for (int e = tid; e < 4096; e += 256) {
+    const int i = e >> 6, k = e & 63;
+    double v;
+    if (i < 32 && k < 32) v = T1[i][k];
+    else if (i >= 32 && k >= 32) v = T2[i - 32][k - 32];
+    else if (i >= 32) v = 0.0;
+    else {   // T12 = -T1 Y
+      v = 0.0;
+      for (int m = i; m < 32; ++m) v = fma(T1[i][m], Y[m][k - 32], v);
+      v = -v;
+    }
+    Tj[e] = v;
+  }
+}
+
+// C <- C - V T^T V^T C for the 64-column block at column j (columns j + 64 ..
+// n_pad - 1, (job, 64-column tile) workgroups): phase 1 W = V^T C with the V
+// chunks staged through LDS as in qr_trailing32_kernel; phase 2 W <- T^T W
+// with MFMA (T packed upper in the staging buffer); phase 3 C <- C - V W.
+__global__ __launch_bounds__(256) void qr_trailing64_kernel(int n_pad, int j, double* __restrict__ S,
+                                                            const double* __restrict__ T64) {
+  const int64_t job = blockIdx.y;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int lr = lane & 15, lg = lane >> 4;
+  double* Sj = S + job * (size_t)n_pad * n_pad;
+  const int c0w = j + 64 + 64 * blockIdx.x + 16 * wave;   // first column of this wave
+  __shared__ double Vs[2][16][65];   // V chunks; T (packed upper, 2080 entries) in phase 2
+  __shared__ double W1[64][65];
+  const bool active = c0w < n_pad;
+  const bool col_ok = (c0w + lr) < n_pad;
+  // V staging: thread t takes V column vd = t / 4, rows 4 (t % 4) .. + 3 of a chunk
+  const int vd = tid >> 2, vr = 4 * (tid & 3);
+  const double* vbase = Sj + (size_t)(j + vd) * n_pad;
+  auto stage_v = [&](int r0, int buf) {
+    const double2 v01 = *reinterpret_cast<const double2*>(vbase + r0 + vr);
+    const double2 v23 = *reinterpret_cast<const double2*>(vbase + r0 + vr + 2);
+    double a[4] = {v01.x, v01.y, v23.x, v23.y};
+    if (r0 < j + 64) {   // V is stored below the diagonal, 1 on it, 0 above
+      const int d = j + vd;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int rr = r0 + vr + q;
+        a[q] = rr > d ? a[q] : (rr == d ? 1.0 : 0.0);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) Vs[buf][vr + q][vd] = a[q];
+  };
+  const int nch = (n_pad - j) / 16;   // n_pad - j is a multiple of 32
+
+  // ---- phase 1: W1 = V^T C (64 x 16 per wave) ------------------------------
+  f64x4 acc[4];
+#pragma unroll
+  for (int g = 0; g < 4; ++g) acc[g] = f64x4{0, 0, 0, 0};
+  const double* cbase = Sj + (size_t)(col_ok ? c0w + lr : (active ? c0w : j + 64)) * n_pad;
+  for (int ch = 0; ch < nch; ++ch) {
+    const int r0 = j + 16 * ch, buf = ch & 1;
+    stage_v(r0, buf);
+    const int rb = r0 + 4 * lg;
+    const double2 c01 = *reinterpret_cast<const double2*>(cbase + rb);
+    const double2 c23 = *reinterpret_cast<const double2*>(cbase + rb + 2);
+    const double cv[4] = {col_ok ? c01.x : 0.0, col_ok ? c01.y : 0.0, col_ok ? c23.x : 0.0, col_ok ? c23.y : 0.0};
+    __syncthreads();
+#pragma unroll
+    for (int jj = 0; jj < 4; ++jj)
+#pragma unroll
+      for (int g = 0; g < 4; ++g)
+        acc[g] = __builtin_amdgcn_mfma_f64_16x16x4f64(Vs[buf][4 * lg + jj][16 * g + lr], cv[jj], acc[g], 0, 0, 0);
+  }
+#pragma unroll
+  for (int g = 0; g < 4; ++g)
+#pragma unroll
+    for (int x = 0; x < 4; ++x) W1[16 * g + acc_row_f64(lg, x)][16 * wave + lr] = acc[g][x];
+  __syncthreads();
+  // ---- phase 2: W2 = T^T W1, each wave on its own 16 columns --------------
+  double* Tp = &Vs[0][0][0];   // T[m][i], m <= i, at i (i + 1) / 2 + m
+  const double* Tj = T64 + job * 4096;
+  for (int e = tid; e < 4096; e += 256) {
+    const int m = e >> 6, i = e & 63;
+    if (m <= i) Tp[((i * (i + 1)) >> 1) + m] = Tj[e];
+  }
+  __syncthreads();
+  {
+    f64x4 w2[4];
+#pragma unroll
+    for (int g = 0; g < 4; ++g) w2[g] = f64x4{0, 0, 0, 0};
+#pragma unroll
+    for (int ks = 0; ks < 16; ++ks) {
+      const double b = W1[4 * ks + lg][16 * wave + lr];
+      const int m = 4 * ks + lg;
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
+        const int i = 16 * g + lr;   // A = T^T: A[i][m] = T[m][i]
+        const double a = m <= i ? Tp[((i * (i + 1)) >> 1) + m] : 0.0;
+        w2[g] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, w2[g], 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int g = 0; g < 4; ++g)
+#pragma unroll
+      for (int x = 0; x < 4; ++x) W1[16 * g + acc_row_f64(lg, x)][16 * wave + lr] = w2[g][x];
+  }
+  __syncthreads();
+  // ---- phase 3: C <- C - V W2 ------------------------------------------------
+  // output tile C^T[c (16)][r (16)] = sum_i W2^T[c][i] V^T[i][r]
+  double aw[16];
+#pragma unroll
+  for (int ks = 0; ks < 16; ++ks) aw[ks] = W1[4 * ks + lg][16 * wave + lr];
+  int ccols[4];
+#pragma unroll
+  for (int x = 0; x < 4; ++x) {
+    const int c = c0w + acc_row_f64(lg, x);
+    ccols[x] = (active && c < n_pad) ? c : -1;
+  }
+  for (int ch = 0; ch < nch; ++ch) {
+    const int r0 = j + 16 * ch, buf = ch & 1;
+    stage_v(r0, buf);
+    const int r = r0 + lr;
+    double cold[4];
+#pragma unroll
+    for (int x = 0; x < 4; ++x) cold[x] = ccols[x] >= 0 ? Sj[(size_t)ccols[x] * n_pad + r] : 0.0;
+    __syncthreads();
+    f64x4 a = {0, 0, 0, 0};
+#pragma unroll
+    for (int ks = 0; ks < 16; ++ks) a = __builtin_amdgcn_mfma_f64_16x16x4f64(aw[ks], Vs[buf][lr][4 * ks + lg], a, 0, 0, 0);
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+      if (ccols[x] >= 0) Sj[(size_t)ccols[x] * n_pad + r] = cold[x] - a[x];
   }
 }
 
@@ -726,7 +907,28 @@ __global__ void r_rows_kernel(int n_pad, const double* __restrict__ S, double* _
 // through the map, which ends as the logical -> stored column permutation).
 template <int NT, int MAXQ, int PW>
 static hipError_t qr_factor_t(int64_t njobs, int n_pad, double* S, double* Tws, bool keep_T, int32_t* colmap,
-                              double* colnorm, hipStream_t stream) {
+                              double* colnorm, double* T64, hipStream_t stream) {
+  if (PW == 32 && !colmap && T64) {
+    // 64-column blocks: T of every 32-column panel at (j / 32) * 1024 when
+    // kept, else two slots per job; T64 holds 4096 doubles per job
+    const int64_t ts = keep_T ? (int64_t)n_pad * 32 : 2048;
+    for (int j = 0; j < n_pad; j += 64) {
+      const int64_t o1 = keep_T ? (int64_t)(j / 32) * 1024 : 0, o2 = keep_T ? o1 + 1024 : 1024;
+      hipLaunchKernelGGL(qr_panel32_kernel, dim3((unsigned)njobs), dim3(256), 0, stream, n_pad, j, S, Tws, ts, o1,
+                         (const int32_t*)nullptr);
+      if (j + 32 >= n_pad) break;
+      hipLaunchKernelGGL(qr_trailing32_kernel, dim3(1, (unsigned)njobs), dim3(256), 0, stream, n_pad, j, j + 64, S,
+                         (const double*)Tws, ts, o1, (const int32_t*)nullptr, (double*)nullptr);
+      hipLaunchKernelGGL(qr_panel32_kernel, dim3((unsigned)njobs), dim3(256), 0, stream, n_pad, j + 32, S, Tws, ts, o2,
+                         (const int32_t*)nullptr);
+      if (j + 64 >= n_pad) break;
+      hipLaunchKernelGGL(qr_t64_kernel, dim3((unsigned)njobs), dim3(256), 0, stream, n_pad, j, (const double*)S,
+                         (const double*)Tws, ts, o1, o2, T64);
+      hipLaunchKernelGGL(qr_trailing64_kernel, dim3(ceil_div(n_pad - j - 64, 64), (unsigned)njobs), dim3(256), 0,
+                         stream, n_pad, j, S, (const double*)T64);
+    }
+    return hipGetLastError();
+  }
   const int64_t t_stride = keep_T ? (int64_t)n_pad * PW : (int64_t)PW * PW;
   if (colmap) {
     hipError_t e = launch_iota(njobs, n_pad, colmap, stream);
@@ -744,7 +946,8 @@ static hipError_t qr_factor_t(int64_t njobs, int n_pad, double* S, double* Tws, 
     if (rest > 0) {
       if (PW == 32)
         hipLaunchKernelGGL(qr_trailing32_kernel, dim3(ceil_div(rest, 64), (unsigned)njobs), dim3(256), 0, stream,
-                           n_pad, j, S, Tws, t_stride, t_off, (const int32_t*)colmap, colmap ? colnorm : nullptr);
+                           n_pad, j, n_pad, S, Tws, t_stride, t_off, (const int32_t*)colmap,
+                           colmap ? colnorm : nullptr);
       else
         hipLaunchKernelGGL((qr_trailing_kernel<PW>), dim3(ceil_div(rest, 64), (unsigned)njobs), dim3(256), 0, stream,
                            n_pad, j, S, Tws, t_stride, t_off, (const int32_t*)colmap, colmap ? colnorm : nullptr);
@@ -756,10 +959,12 @@ static hipError_t qr_factor_t(int64_t njobs, int n_pad, double* S, double* Tws, 
   return hipGetLastError();
 }
 
+// T64 (4096 doubles per job, or NULL): scratch that enables the 64-column
+// blocks when the columns are not re-ordered (n_pad <= 1024).
 static hipError_t qr_factor(int64_t njobs, int n_pad, double* S, double* Tws, bool keep_T, int32_t* colmap,
-                            double* colnorm, hipStream_t stream) {
-  if (n_pad <= 1024) return qr_factor_t<256, 4, 32>(njobs, n_pad, S, Tws, keep_T, colmap, colnorm, stream);
-  return qr_factor_t<512, 8, 8>(njobs, n_pad, S, Tws, keep_T, nullptr, nullptr, stream);
+                            double* colnorm, hipStream_t stream, double* T64 = nullptr) {
+  if (n_pad <= 1024) return qr_factor_t<256, 4, 32>(njobs, n_pad, S, Tws, keep_T, colmap, colnorm, T64, stream);
+  return qr_factor_t<512, 8, 8>(njobs, n_pad, S, Tws, keep_T, nullptr, nullptr, nullptr, stream);
 }
 
 static hipError_t order_and_unfold(int64_t njobs, int n, int D, int n_pad, const double* T, const int32_t* src,
@@ -815,10 +1020,12 @@ hipError_t run_qr3_precondition(int64_t njobs, int n, int D, int n_pad, const do
   if (e != hipSuccess) return e;
   const dim3 rg(n_pad / 32, n_pad / 32, (unsigned)njobs);
   hipLaunchKernelGGL(r_rows_kernel, rg, dim3(256), 0, stream, n_pad, S1, W1, (const int32_t*)colmap);
-  e = qr_factor(njobs, n_pad, W1, Tws2, true, nullptr, nullptr, stream);
+  // the second and third QR do not re-order columns: 64-column blocks, with
+  // Tws1 (free after the first QR) as scratch for the block T factors
+  e = qr_factor(njobs, n_pad, W1, Tws2, true, nullptr, nullptr, stream, Tws1);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(r_rows_kernel, rg, dim3(256), 0, stream, n_pad, W1, W2, (const int32_t*)nullptr);
-  e = qr_factor(njobs, n_pad, W2, Tws1, false, nullptr, nullptr, stream);
+  e = qr_factor(njobs, n_pad, W2, Tws1, false, nullptr, nullptr, stream, Tws1 + (size_t)njobs * 2048);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(r_rows_kernel, rg, dim3(256), 0, stream, n_pad, W2, S1, (const int32_t*)nullptr);
   *rows = S1;

@@ -141,9 +141,11 @@ hipError_t run_qr_precondition(int64_t njobs, int n, int D, int n_pad, const dou
 hipError_t launch_iota(int64_t njobs, int n_pad, int32_t* perm, hipStream_t stream);
 // Three-QR preconditioning (see k_qr.hip): *rows receives the buffer with
 // the rows of R3 (S1); W1 keeps Q2 (V) and Tws2 its panel T factors
-// (n_pad * 32 doubles per job).  colmap / colnorm: n_pad int32 / doubles per
-// job (the column re-ordering of the first QR, n_pad <= 1024; NULL: static
-// order only).
+// (n_pad * 32 doubles per job).  Tws1 (n_pad * 32 doubles per job) is
+// scratch: the first QR's panel T, then the block T factors of the second
+// and third (6144 doubles per job).  colmap / colnorm: n_pad int32 / doubles
+// per job (the column re-ordering of the first QR, n_pad <= 1024; NULL:
+// static order only).
 hipError_t run_qr3_precondition(int64_t njobs, int n, int D, int n_pad, const double* T, const int32_t* src,
                                 const int32_t* split, int32_t* perm, double* S1, double* Tws1, double* W1,
                                 double* Tws2, double* W2, int32_t* colmap, double* colnorm, double** rows,
