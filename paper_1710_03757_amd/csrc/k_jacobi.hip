@@ -231,10 +231,8 @@ __global__ __launch_bounds__(256) void jacobi_round_kernel(double* __restrict__ 
 __device__ __forceinline__ int circle_next64(int k) { return k == 0 ? 0 : (k == 1 ? 63 : k - 1); }
 
 // Packed strictly upper triangle of a 64 x 64 symmetric matrix: entry (i, j),
-// i < j, row by row.  Two such buffers (kGpk entries each) are followed by a
-// slot that holds 0 and a slot that absorbs writes.
+// i < j, row by row, kGpk entries.
 constexpr int kGpk = 64 * 63 / 2;
-constexpr int kGzero = 2 * kGpk, kGsink = 2 * kGpk + 1;
 __device__ __forceinline__ int gpk_index(int i, int j) { return 63 * i - ((i * (i + 1)) >> 1) + j - 1; }
 
 // Position of (Q^T)[row][col] (64 x 64) in A-fragment order for
@@ -321,8 +319,8 @@ __global__ __launch_bounds__(256, 3) void jacobi_round64_kernel(double* __restri
   double* rowJ = Wj + (size_t)(32 * J) * n_pad;
 
   // U: the staged partial Gram tiles, then the two position-space buffers of
-  // the strictly upper triangle of G (packed, kGpk entries each) with a zero
-  // slot and a sink slot behind them, then Q^T in A-fragment order.
+  // the strictly upper triangle of G (packed, kGpk entries each), then Q^T in
+  // A-fragment order.
   __shared__ double U[4096];
   double* const QTf = U;                                              // qt_frag_index
   double(*stage)[5][256] = reinterpret_cast<double(*)[5][256]>(U);   // [wave-1][tile][16x16]
@@ -411,7 +409,6 @@ __global__ __launch_bounds__(256, 3) void jacobi_round64_kernel(double* __restri
         ++t;
       }
   }
-  if (tid == 0) U[kGzero] = 0.0;
   __syncthreads();
 
   // ---- convergence test of this pair ------------------------------------
@@ -463,28 +460,32 @@ __global__ __launch_bounds__(256, 3) void jacobi_round64_kernel(double* __restri
   //
   // The block grid is enumerated as 16 folded rows of 33 (row m and row
   // 31 - m); thread tid owns blocks tid, tid + 256 and (tid < 16) tid + 512.
-  int rd[3][4], wr[3][4], bi[3], bj[3];   // per block: read / write offsets, slots
-  bool dblk[3];
+  // Off-diagonal blocks (t_i < t_j, 496 of them): thread tid owns blocks
+  // tid and tid + 256 (tid < 240).  A slot's own block only has its
+  // off-diagonal entry to update (0 after a rotation; its diagonal entries
+  // are in dg), which the lane that forms the slot's rotation writes.
+  int rd[2][4], wr[2][4], bi[2], bj[2];   // per block: read / write offsets, slots
 #pragma unroll
-  for (int u = 0; u < 3; ++u) {
-    const int e = min(tid + 256 * u, 527);
-    const int m = e / 33, o = e - 33 * m;
-    int ti, tj;
-    if (o < 32 - m) { ti = m; tj = m + o; }
-    else { ti = 31 - m; tj = 31 - m + (o - (32 - m)); }
+  for (int u = 0; u < 2; ++u) {
+    int rem = min(tid + 256 * u, 495), ti = 0;
+    while (rem >= 31 - ti) { rem -= 31 - ti; ++ti; }
+    const int tj = ti + 1 + rem;
     bi[u] = ti; bj[u] = tj;
-    dblk[u] = ti == tj;
-    // a slot's own block holds two diagonal entries (kept in dg): they read
-    // the zero slot and are written to the sink
     const int pos[4][2] = {{ti, tj}, {ti, 63 - tj}, {63 - ti, tj}, {63 - ti, 63 - tj}};
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int a = pos[v][0], b = pos[v][1];
       const int na = circle_next64(a), nb2 = circle_next64(b);
-      rd[u][v] = a == b ? kGzero : gpk_index(min(a, b), max(a, b));
-      wr[u][v] = a == b ? kGsink : gpk_index(min(na, nb2), max(na, nb2));
+      rd[u][v] = gpk_index(min(a, b), max(a, b));
+      wr[u][v] = gpk_index(min(na, nb2), max(na, nb2));
     }
   }
+  const bool two = tid < 240;
+  // lanes 0..31: the slot's own entry (positions tid, 63 - tid), read and
+  // written after the move
+  const int own_rd = gpk_index(tid & 31, 63 - (tid & 31));
+  const int own_nx = circle_next64(tid & 31), own_ny = circle_next64(63 - (tid & 31));
+  const int own_wr = gpk_index(min(own_nx, own_ny), max(own_nx, own_ny));
   const int ws = __builtin_amdgcn_readfirstlane(wave);
   double qr[16];
 #pragma unroll
@@ -492,25 +493,25 @@ __global__ __launch_bounds__(256, 3) void jacobi_round64_kernel(double* __restri
     qr[a] = (8 * ws + a == lane) ? 1.0 : 0.0;
     qr[8 + a] = (56 - 8 * ws + a == lane) ? 1.0 : 0.0;
   }
-#pragma unroll 2
   for (int r = 0; r < 63; ++r) {
     const double* Gc = U + (r & 1) * kGpk;
     double* Gn = U + ((r + 1) & 1) * kGpk;
     if (tid < 32) {
       const int x = tid, y = 63 - tid;
-      const double gxx = dg[r & 1][x], gyy = dg[r & 1][y], gxy = Gc[gpk_index(x, y)];
-      double c = 1.0, s = 0.0, dx = gxx, dy = gyy;
+      const double gxx = dg[r & 1][x], gyy = dg[r & 1][y], gxy = Gc[own_rd];
+      double c = 1.0, t = 0.0, dx = gxx, dy = gyy, gn = gxy;
       // |.| guards the tiny diagonal entries that rounding can push below 0
       if (gxy != 0.0 && gxy * gxy > 0x1.0p-106 * fabs(gxx * gyy)) {
-        const double t = jacobi_tangent(gxx, gyy, gxy);
+        t = jacobi_tangent(gxx, gyy, gxy);
         c = unit_cosine(t);
-        s = t * c;
         dx = fma(-t, gxy, gxx);
         dy = fma(t, gxy, gyy);
+        gn = 0.0;
       }
-      rcs[tid] = make_double2(c, s);
-      dg[(r + 1) & 1][circle_next64(x)] = dx;
-      dg[(r + 1) & 1][circle_next64(y)] = dy;
+      rcs[tid] = make_double2(c, t);   // cosine and tangent
+      dg[(r + 1) & 1][own_nx] = dx;
+      dg[(r + 1) & 1][own_ny] = dy;
+      Gn[own_wr] = gn;
     }
     __syncthreads();
     // Q: finish the shift of the previous round, then rotate this round's slots
@@ -529,36 +530,32 @@ __global__ __launch_bounds__(256, 3) void jacobi_round64_kernel(double* __restri
     }
 #pragma unroll
     for (int a = 0; a < 8; ++a) {
-      const double2 cs = rcs[8 * ws + a];
+      const double2 ct = rcs[8 * ws + a];
       const double x = qr[a], y = qr[15 - a];
-      qr[a] = cs.x * x - cs.y * y;
-      qr[15 - a] = cs.y * x + cs.x * y;
+      qr[a] = ct.x * fma(-ct.y, y, x);
+      qr[15 - a] = ct.x * fma(ct.y, x, y);
     }
     {
       double (*xw)[2][64] = xch[r & 1];
       xw[ws][0][lane] = qr[0];   // position 8w, wanted by wave w - 1
       xw[ws][1][lane] = qr[8];   // position 56 - 8w, wanted by wave w + 1
     }
-    // G blocks: read from this round's buffer, store into the other
+    // G blocks: read from this round's buffer, store into the other.  With
+    // J = c [[1, t], [-t, 1]] acting on the columns (x, y) -> (c (x - t y),
+    // c (t x + y)), J_i^T A J_j = c_i c_j (the tangent products below).
 #pragma unroll
-    for (int u = 0; u < 3; ++u) {
-      if (u == 2 && tid >= 16) break;
+    for (int u = 0; u < 2; ++u) {
+      if (u == 1 && !two) break;
       const double2 ci = rcs[bi[u]], cj = rcs[bj[u]];
       const double ga = Gc[rd[u][0]], gb = Gc[rd[u][1]], gc = Gc[rd[u][2]], gd = Gc[rd[u][3]];
-      const double c_i = ci.x, s_i = ci.y, c_j = cj.x, s_j = cj.y;
-      // A J_j: columns (x, y) -> (c x - s y, s x + c y)
-      const double a1 = c_j * ga - s_j * gb, b1 = s_j * ga + c_j * gb;
-      const double c1 = c_j * gc - s_j * gd, d1 = s_j * gc + c_j * gd;
-      // J_i^T (A J_j): rows (x, y) -> (c x - s y, s x + c y)
-      const double a2 = c_i * a1 - s_i * c1, d2 = s_i * b1 + c_i * d1;
-      double c2 = s_i * a1 + c_i * c1, b2 = c_i * b1 - s_i * d1;
-      // a slot's own block: its off-diagonal entry (stored once, at b and c)
-      // is 0 after the rotation
-      if (dblk[u] && s_i != 0.0) { b2 = 0.0; c2 = 0.0; }
-      Gn[wr[u][0]] = a2;
-      Gn[wr[u][1]] = b2;
-      Gn[wr[u][2]] = c2;
-      Gn[wr[u][3]] = d2;
+      const double tj = cj.y, ti = ci.y;
+      const double u1 = fma(-tj, gb, ga), u2 = fma(tj, ga, gb);   // columns of A J_j / c_j, row x
+      const double u3 = fma(-tj, gd, gc), u4 = fma(tj, gc, gd);   // row y
+      const double cc = ci.x * cj.x;
+      Gn[wr[u][0]] = cc * fma(-ti, u3, u1);
+      Gn[wr[u][1]] = cc * fma(-ti, u4, u2);
+      Gn[wr[u][2]] = cc * fma(ti, u1, u3);
+      Gn[wr[u][3]] = cc * fma(ti, u2, u4);
     }
     __syncthreads();
   }
