@@ -239,6 +239,7 @@ __global__ __launch_bounds__(NT) void qr_panel_kernel(int n_pad, int j, double* 
 // wave reduce their 32 partial sums by halving exchanges (16 + 8 + 4 + 2 + 1
 // + 1 shuffles).  T of the compact WY form follows at the end, row m by
 // thread m: T[m][m] = tau_m, T[m][i] = -tau_i sum_{p=m}^{i-1} T[m][p] z_p^(i).
+template <int NQ>
 __global__ __launch_bounds__(256) void qr_panel32_kernel(int n_pad, int j, double* __restrict__ S,
                                                          double* __restrict__ Tws, int64_t t_stride, int64_t t_off,
                                                          const int32_t* __restrict__ colmap) {
@@ -253,9 +254,9 @@ __global__ __launch_bounds__(256) void qr_panel32_kernel(int n_pad, int j, doubl
   __shared__ double taus[32];
   __shared__ double prm[3];   // tau, scale, beta of the current column
 
-  double A[4][32];
+  double A[NQ][32];   // rows j + tid + 256 q, q < NQ (n_pad - j <= 256 NQ)
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
+  for (int q = 0; q < NQ; ++q) {
     const int r = j + tid + 256 * q;
 #pragma unroll
     for (int c = 0; c < 32; ++c) A[q][c] = (r < n_pad) ? Sj[(size_t)(cm ? cm[j + c] : j + c) * n_pad + r] : 0.0;
@@ -269,7 +270,7 @@ __global__ __launch_bounds__(256) void qr_panel32_kernel(int n_pad, int j, doubl
 #pragma unroll
     for (int c = 0; c < 32; ++c) p[c] = 0.0;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < NQ; ++q) {
       const int r = j + tid + 256 * q;
       const double x = (r > cj && r < n_pad) ? A[q][0] : 0.0;
 #pragma unroll
@@ -336,7 +337,7 @@ __global__ __launch_bounds__(256) void qr_panel32_kernel(int n_pad, int j, doubl
 #pragma unroll
     for (int c = 1; c < 32; ++c) wv[c] = (c <= 31 - i) ? tau * wz[c] : 0.0;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < NQ; ++q) {
       const int r = j + tid + 256 * q;
       const bool below = r > cj && r < n_pad, at = r == cj;
       const double vr = at ? 1.0 : (below ? scale * A[q][0] : 0.0);
@@ -347,7 +348,7 @@ __global__ __launch_bounds__(256) void qr_panel32_kernel(int n_pad, int j, doubl
     }
     // rotate the slots: the finished column goes to slot 31
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < NQ; ++q) {
       const double f = A[q][0];
 #pragma unroll
       for (int c = 0; c < 31; ++c) A[q][c] = A[q][c + 1];
@@ -355,7 +356,7 @@ __global__ __launch_bounds__(256) void qr_panel32_kernel(int n_pad, int j, doubl
     }
   }
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
+  for (int q = 0; q < NQ; ++q) {
     const int r = j + tid + 256 * q;
     if (r < n_pad) {
 #pragma unroll
@@ -382,6 +383,22 @@ __global__ __launch_bounds__(256) void qr_panel32_kernel(int n_pad, int j, doubl
 #pragma unroll
     for (int i = 0; i < 32; ++i) Tj[m * 32 + i] = Tr[i];
   }
+}
+
+// The panel at column j spans n_pad - j rows: NQ = ceil((n_pad - j) / 256)
+// row slots per thread, so that the later panels hold fewer registers and
+// fit more workgroups per CU.
+static void launch_panel32(dim3 grid, dim3 block, size_t shm, hipStream_t stream, int n_pad, int j, double* S,
+                           double* Tws, int64_t t_stride, int64_t t_off, const int32_t* colmap) {
+  const int nq = (n_pad - j + 255) / 256;
+  if (nq >= 4)
+    hipLaunchKernelGGL(qr_panel32_kernel<4>, grid, block, shm, stream, n_pad, j, S, Tws, t_stride, t_off, colmap);
+  else if (nq == 3)
+    hipLaunchKernelGGL(qr_panel32_kernel<3>, grid, block, shm, stream, n_pad, j, S, Tws, t_stride, t_off, colmap);
+  else if (nq == 2)
+    hipLaunchKernelGGL(qr_panel32_kernel<2>, grid, block, shm, stream, n_pad, j, S, Tws, t_stride, t_off, colmap);
+  else
+    hipLaunchKernelGGL(qr_panel32_kernel<1>, grid, block, shm, stream, n_pad, j, S, Tws, t_stride, t_off, colmap);
 }
 
 // ---------------------------------------------------------------------------
@@ -914,12 +931,12 @@ static hipError_t qr_factor_t(int64_t njobs, int n_pad, double* S, double* Tws, 
     const int64_t ts = keep_T ? (int64_t)n_pad * 32 : 2048;
     for (int j = 0; j < n_pad; j += 64) {
       const int64_t o1 = keep_T ? (int64_t)(j / 32) * 1024 : 0, o2 = keep_T ? o1 + 1024 : 1024;
-      hipLaunchKernelGGL(qr_panel32_kernel, dim3((unsigned)njobs), dim3(256), 0, stream, n_pad, j, S, Tws, ts, o1,
+      launch_panel32( dim3((unsigned)njobs), dim3(256), 0, stream, n_pad, j, S, Tws, ts, o1,
                          (const int32_t*)nullptr);
       if (j + 32 >= n_pad) break;
       hipLaunchKernelGGL(qr_trailing32_kernel, dim3(1, (unsigned)njobs), dim3(256), 0, stream, n_pad, j, j + 64, S,
                          (const double*)Tws, ts, o1, (const int32_t*)nullptr, (double*)nullptr);
-      hipLaunchKernelGGL(qr_panel32_kernel, dim3((unsigned)njobs), dim3(256), 0, stream, n_pad, j + 32, S, Tws, ts, o2,
+      launch_panel32( dim3((unsigned)njobs), dim3(256), 0, stream, n_pad, j + 32, S, Tws, ts, o2,
                          (const int32_t*)nullptr);
       if (j + 64 >= n_pad) break;
       hipLaunchKernelGGL(qr_t64_kernel, dim3((unsigned)njobs), dim3(256), 0, stream, n_pad, j, (const double*)S,
@@ -937,7 +954,7 @@ static hipError_t qr_factor_t(int64_t njobs, int n_pad, double* S, double* Tws, 
   for (int j = 0; j < n_pad; j += PW) {
     const int64_t t_off = keep_T ? (int64_t)(j / PW) * PW * PW : 0;
     if (NT == 256 && MAXQ == 4 && PW == 32)
-      hipLaunchKernelGGL(qr_panel32_kernel, dim3((unsigned)njobs), dim3(256), 0, stream, n_pad, j, S, Tws, t_stride,
+      launch_panel32( dim3((unsigned)njobs), dim3(256), 0, stream, n_pad, j, S, Tws, t_stride,
                          t_off, (const int32_t*)colmap);
     else
       hipLaunchKernelGGL((qr_panel_kernel<NT, MAXQ, PW>), dim3((unsigned)njobs), dim3(NT), 0, stream, n_pad, j, S,
