@@ -159,7 +159,7 @@ struct Chain {
          *weight = nullptr, *sscr = nullptr, *G = nullptr, *F = nullptr, *X = nullptr, *Y = nullptr,
          *scales = nullptr, *cbuf = nullptr, *lnc = nullptr, *lnc_steps = nullptr, *lnabs = nullptr;
   void *Xlp = nullptr, *Ylp = nullptr;
-  double *S = nullptr, *Tws = nullptr, *W2 = nullptr, *Tws2 = nullptr;
+  double *S = nullptr, *Tws = nullptr, *W2 = nullptr, *Tws2 = nullptr, *W3 = nullptr, *Tscr = nullptr;
   int32_t* perm = nullptr;
   int32_t* colmap = nullptr;   // column re-ordering of the first QR (n_pad <= 1024)
   double* colnorm = nullptr;
@@ -233,6 +233,8 @@ void layout(Chain& c, Arena& ar) {
   c.W = ar.take<double>(wmax);
   c.S = ar.take<double>(wmax);
   c.W2 = ar.take<double>(wmax);
+  c.W3 = ar.take<double>(wmax);
+  c.Tscr = ar.take<double>((size_t)jmax * 6144);
   c.Tws = ar.take<double>((size_t)jmax * 32 * 1024);
   c.Tws2 = ar.take<double>((size_t)jmax * 32 * 1024);
   c.perm = ar.take<int32_t>((size_t)jmax * 4096);
@@ -407,12 +409,17 @@ int chain_step(Chain& c) {
   CKH(hipMemcpyAsync(c.rng, c.h_rng, 3 * nj * sizeof(uint64_t), hipMemcpyHostToDevice, c.st));
   CKH(hipMemcpyAsync(c.cjobs, c.h_cjobs, 4 * no * sizeof(int32_t), hipMemcpyHostToDevice, c.st));
 
-  // decomposition: three QRs then Jacobi on the rows of R3 (n_pad <= 4096);
-  // larger unfoldings go straight to Jacobi
+  // decomposition: four QRs (n_pad <= 1024) or three (n_pad <= 4096) then
+  // Jacobi on the rows of the last R; larger unfoldings go straight to Jacobi
+  const bool qr4 = sh.n_pad <= 1024;
   const bool qr = sh.n_pad <= kQrMaxN;
   double* rows = c.W2;   // the rows handed to the Jacobi
   double* Wj = c.W;      // the Jacobi workspace
-  if (qr) {
+  if (qr4) {
+    CKH(run_qr4_precondition(nj, sh.n, sh.D, sh.n_pad, c.Ta, c.src, c.split, c.perm, c.S, c.Tws, c.W, c.W2, c.Tws2,
+                             c.W3, c.Tscr, c.colmap, c.colnorm, c.st));
+    rows = c.W3;         // c.S / c.Tws keep Q1, c.W2 / c.Tws2 keep Q3, c.W is free
+  } else if (qr) {
     CKH(run_qr3_precondition(nj, sh.n, sh.D, sh.n_pad, c.Ta, c.src, c.split, c.perm, c.S, c.Tws, c.W, c.Tws2, c.W2,
                              c.colmap, c.colnorm, &rows, c.st));
     Wj = c.W2;           // c.W keeps Q2
@@ -434,10 +441,15 @@ int chain_step(Chain& c) {
   CKH(launch_sample(sa, c.st));
   if ((c.flags & MCTRG_RECORD) && c.record)
     CKH(launch_record(c.nsamp, s, c.n_steps, c.kmax_rec, sh.kc, c.idx, c.cand, c.kept, c.sel, c.record, c.st));
-  if (qr) {
+  if (qr4) {
+    // u = Q1 Q3 y into F (w_a u_a), then G = F^T M / s with the sign gauge
+    CKH(launch_apply_q1(nj, sh.n, sh.n_pad, sh.kc, c.S, c.colmap, c.Tws, c.W2, c.Tws2, Wj, c.sigma, c.order, c.kept,
+                        c.sel, c.weight, c.F, c.st));
+    CKH(launch_factor_G_from_F(nj, sh.D, sh.kc, c.Ta, c.src, c.split, c.sigma, c.kept, c.sel, c.F, c.G, c.st));
+  } else if (qr) {
     // z = Q2 y (in F as scratch), v = P z into G with the gauge, u = M v / s
-    CKH(launch_apply_q1(nj, sh.n, sh.n_pad, sh.kc, c.W, nullptr, c.Tws2, Wj, c.sigma, c.order, c.kept, c.sel,
-                        c.weight, c.F, c.st));
+    CKH(launch_apply_q1(nj, sh.n, sh.n_pad, sh.kc, c.W, nullptr, c.Tws2, nullptr, nullptr, Wj, c.sigma, c.order,
+                        c.kept, c.sel, c.weight, c.F, c.st));
     CKH(launch_scatter_G(nj, sh.D, sh.n_pad, sh.kc, c.F, c.perm, sh.n_pad <= 1024 ? c.colmap : nullptr, c.kept, c.G,
                          c.st));
     CKH(launch_factor_F(nj, sh.D, sh.kc, c.Ta, c.src, c.split, c.sigma, c.kept, c.sel, c.G, c.F, c.st));

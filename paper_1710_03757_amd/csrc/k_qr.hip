@@ -1049,6 +1049,39 @@ hipError_t run_qr3_precondition(int64_t njobs, int n, int D, int n_pad, const do
   return hipGetLastError();
 }
 
+// Four QRs (n_pad <= 1024): M P = Q1 R1, R1^T = Q2 R2, R2^T = Q3 R3, R3^T =
+// Q4 R4, so M P = (Q1 Q3) R4^T (Q2 Q4)^T: the right singular vectors y of R4
+// (the normalised Jacobi rows) give the left singular vectors of M as u = Q1
+// Q3 y, and v = M^T u / s.  Q1 stays in S1 (V, stored columns via colmap)
+// with its panel T factors in Tws1, Q3 in W2 with its T factors in Tws3 (n_pad
+// * 32 doubles per job each); the second and fourth QR factor W1 in place
+// with Tscr (6144 doubles per job) as scratch for their block T factors.  The
+// rows of R4 end in W3.
+hipError_t run_qr4_precondition(int64_t njobs, int n, int D, int n_pad, const double* T, const int32_t* src,
+                                const int32_t* split, int32_t* perm, double* S1, double* Tws1, double* W1,
+                                double* W2, double* Tws3, double* W3, double* Tscr, int32_t* colmap, double* colnorm,
+                                hipStream_t stream) {
+  if (njobs == 0) return hipSuccess;
+  if (n_pad > 1024) return hipErrorInvalidValue;
+  hipError_t e = order_and_unfold(njobs, n, D, n_pad, T, src, split, perm, S1, stream);
+  if (e != hipSuccess) return e;
+  e = qr_factor(njobs, n_pad, S1, Tws1, true, colmap, colnorm, stream);
+  if (e != hipSuccess) return e;
+  const dim3 rg(n_pad / 32, n_pad / 32, (unsigned)njobs);
+  double* T64 = Tscr + (size_t)njobs * 2048;
+  hipLaunchKernelGGL(r_rows_kernel, rg, dim3(256), 0, stream, n_pad, S1, W1, (const int32_t*)colmap);
+  e = qr_factor(njobs, n_pad, W1, Tscr, false, nullptr, nullptr, stream, T64);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(r_rows_kernel, rg, dim3(256), 0, stream, n_pad, W1, W2, (const int32_t*)nullptr);
+  e = qr_factor(njobs, n_pad, W2, Tws3, true, nullptr, nullptr, stream, Tscr);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(r_rows_kernel, rg, dim3(256), 0, stream, n_pad, W2, W1, (const int32_t*)nullptr);
+  e = qr_factor(njobs, n_pad, W1, Tscr, false, nullptr, nullptr, stream, T64);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(r_rows_kernel, rg, dim3(256), 0, stream, n_pad, W1, W3, (const int32_t*)nullptr);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
 // X[:, a] = w_a Q x_a for the kept rows x_a = W[order[sel[a]]] / s of the
 // Jacobi result, Q = prod_p (I - V_p T_p V_p^T) the orthogonal factor of a
@@ -1132,6 +1165,8 @@ __global__ __launch_bounds__(256) void apply_q1_kernel(int n, int n_pad, int kca
 __global__ __launch_bounds__(256) void apply_q1_mfma_kernel(int n, int n_pad, int kcap, const double* __restrict__ S1,
                                                             const int32_t* __restrict__ colmap,
                                                             const double* __restrict__ Tws1,
+                                                            const double* __restrict__ S1b,
+                                                            const double* __restrict__ Tws1b,
                                                             const double* __restrict__ W2,
                                                             const double* __restrict__ sigma,
                                                             const int32_t* __restrict__ order,
@@ -1150,9 +1185,6 @@ __global__ __launch_bounds__(256) void apply_q1_mfma_kernel(int n, int n_pad, in
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int lr = lane & 15, lg = lane >> 4;
   const int nk = kept[job];
-  const double* Sj = S1 + (size_t)job * n_pad * n_pad;
-  const int32_t* cm = colmap ? colmap + job * n_pad : nullptr;   // V_d is stored in column cm[d]
-  const double* Tj = Tws1 + (size_t)job * n_pad * 32;
   if (tid < 16) {
     const int a = a0 + tid;
     if (a < nk) {
@@ -1172,6 +1204,10 @@ __global__ __launch_bounds__(256) void apply_q1_mfma_kernel(int n, int n_pad, in
     X[e] = rowp[v] ? rowp[v][r] / sv[v] : 0.0;
   }
   __syncthreads();
+  for (int set = S1b ? 0 : 1; set < 2; ++set) {   // the second factor (if any) first
+  const double* Sj = (set == 0 ? S1b : S1) + (size_t)job * n_pad * n_pad;
+  const int32_t* cm = (set == 1 && colmap) ? colmap + job * n_pad : nullptr;   // V_d is stored in column cm[d]
+  const double* Tj = (set == 0 ? Tws1b : Tws1) + (size_t)job * n_pad * 32;
   for (int j = n_pad - 32; j >= 0; j -= 32) {
     // ---- Y = V_p^T X: rows r = j .. n_pad - 1 in chunks of 16 ------------
     f64x4 acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
@@ -1246,6 +1282,7 @@ __global__ __launch_bounds__(256) void apply_q1_mfma_kernel(int n, int n_pad, in
     }
     __syncthreads();
   }
+  }
   double* Fj = F + (size_t)job * n * kcap;
   for (int e = tid; e < n * 16; e += 256) {
     const int r = e >> 4, v = e & 15, a = a0 + v;
@@ -1256,17 +1293,18 @@ __global__ __launch_bounds__(256) void apply_q1_mfma_kernel(int n, int n_pad, in
 size_t apply_q1_mfma_lds(int n_pad) { return sizeof(double) * ((size_t)n_pad * 16 + 4 * 2 * 256 + 2 * 32 * 16); }
 
 hipError_t launch_apply_q1(int64_t njobs, int n, int n_pad, int kcap, const double* S1, const int32_t* colmap,
-                           const double* Tws1, const double* W2, const double* sigma, const int32_t* order,
-                           const int32_t* kept, const int32_t* sel, const double* weight, double* F,
-                           hipStream_t stream) {
+                           const double* Tws1, const double* S1b, const double* Tws1b, const double* W2,
+                           const double* sigma, const int32_t* order, const int32_t* kept, const int32_t* sel,
+                           const double* weight, double* F, hipStream_t stream) {
   if (njobs == 0) return hipSuccess;
+  if (S1b && n_pad > 1024) return hipErrorInvalidValue;   // two factors only with 32-column panels
   if (n_pad <= 1024) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&apply_q1_mfma_kernel),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)apply_q1_mfma_lds(n_pad));
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(apply_q1_mfma_kernel, dim3((kcap + 15) / 16, (unsigned)njobs), dim3(256),
-                       apply_q1_mfma_lds(n_pad), stream, n, n_pad, kcap, S1, colmap, Tws1, W2, sigma, order, kept, sel,
-                       weight, F);
+                       apply_q1_mfma_lds(n_pad), stream, n, n_pad, kcap, S1, colmap, Tws1, S1b, Tws1b, W2, sigma,
+                       order, kept, sel, weight, F);
   } else
     hipLaunchKernelGGL((apply_q1_kernel<16, 8>), dim3(kcap, (unsigned)njobs), dim3(256), 0, stream, n, n_pad, kcap, S1,
                        Tws1, W2, sigma, order, kept, sel, weight, F);

@@ -150,12 +150,21 @@ hipError_t run_qr3_precondition(int64_t njobs, int n, int D, int n_pad, const do
                                 const int32_t* split, int32_t* perm, double* S1, double* Tws1, double* W1,
                                 double* Tws2, double* W2, int32_t* colmap, double* colnorm, double** rows,
                                 hipStream_t stream);
-// X[:, a] = w_a Q (W[order[sel[a]]] / s) with Q the orthogonal factor kept
-// in S (V, stored columns via colmap, NULL: identity) and Tws (panel T)
+// Four-QR preconditioning (see k_qr.hip; n_pad <= 1024): the rows of R4 in
+// W3; Q1 in S1 (via colmap) / Tws1, Q3 in W2 / Tws3 (n_pad * 32 doubles per
+// job each); Tscr: 6144 doubles per job of scratch.
+hipError_t run_qr4_precondition(int64_t njobs, int n, int D, int n_pad, const double* T, const int32_t* src,
+                                const int32_t* split, int32_t* perm, double* S1, double* Tws1, double* W1,
+                                double* W2, double* Tws3, double* W3, double* Tscr, int32_t* colmap, double* colnorm,
+                                hipStream_t stream);
+// X[:, a] = w_a Q Qb (W[order[sel[a]]] / s) with Q the orthogonal factor
+// kept in S1 (V, stored columns via colmap, NULL: identity) and Tws1 (panel
+// T), and Qb (optional: S1b / Tws1b, no column map, applied first; n_pad <=
+// 1024) a second factor in the same format
 hipError_t launch_apply_q1(int64_t njobs, int n, int n_pad, int kcap, const double* S1, const int32_t* colmap,
-                           const double* Tws1, const double* W2, const double* sigma, const int32_t* order,
-                           const int32_t* kept, const int32_t* sel, const double* weight, double* F,
-                           hipStream_t stream);
+                           const double* Tws1, const double* S1b, const double* Tws1b, const double* W2,
+                           const double* sigma, const int32_t* order, const int32_t* kept, const int32_t* sel,
+                           const double* weight, double* F, hipStream_t stream);
 // G[a][perm[colmap[c]]] = X[c][a] (c < n; colmap NULL: identity), signed
 // with the gauge of the factor kernels; zero rows for a >= kept.
 hipError_t launch_scatter_G(int64_t njobs, int D, int n_pad, int kcap, const double* X, const int32_t* perm,
