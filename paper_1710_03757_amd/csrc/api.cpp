@@ -409,16 +409,17 @@ int chain_step(Chain& c) {
   CKH(hipMemcpyAsync(c.rng, c.h_rng, 3 * nj * sizeof(uint64_t), hipMemcpyHostToDevice, c.st));
   CKH(hipMemcpyAsync(c.cjobs, c.h_cjobs, 4 * no * sizeof(int32_t), hipMemcpyHostToDevice, c.st));
 
-  // decomposition: four QRs (n_pad <= 1024) or three (n_pad <= 4096) then
+  // decomposition: five QRs (n_pad <= 1024) or three (n_pad <= 4096) then
   // Jacobi on the rows of the last R; larger unfoldings go straight to Jacobi
-  const bool qr4 = sh.n_pad <= 1024;
+  const bool qr5 = sh.n_pad <= 1024;
   const bool qr = sh.n_pad <= kQrMaxN;
   double* rows = c.W2;   // the rows handed to the Jacobi
   double* Wj = c.W;      // the Jacobi workspace
-  if (qr4) {
-    CKH(run_qr4_precondition(nj, sh.n, sh.D, sh.n_pad, c.Ta, c.src, c.split, c.perm, c.S, c.Tws, c.W, c.W2, c.Tws2,
+  if (qr5) {
+    CKH(run_qr5_precondition(nj, sh.n, sh.D, sh.n_pad, c.Ta, c.src, c.split, c.perm, c.S, c.W, c.Tws2, c.W2, c.Tws,
                              c.W3, c.Tscr, c.colmap, c.colnorm, c.st));
-    rows = c.W3;         // c.S / c.Tws keep Q1, c.W2 / c.Tws2 keep Q3, c.W is free
+    rows = c.W3;         // c.W / c.Tws2 keep Q2, c.S / c.Tws keep Q4
+    Wj = c.W2;
   } else if (qr) {
     CKH(run_qr3_precondition(nj, sh.n, sh.D, sh.n_pad, c.Ta, c.src, c.split, c.perm, c.S, c.Tws, c.W, c.Tws2, c.W2,
                              c.colmap, c.colnorm, &rows, c.st));
@@ -441,11 +442,12 @@ int chain_step(Chain& c) {
   CKH(launch_sample(sa, c.st));
   if ((c.flags & MCTRG_RECORD) && c.record)
     CKH(launch_record(c.nsamp, s, c.n_steps, c.kmax_rec, sh.kc, c.idx, c.cand, c.kept, c.sel, c.record, c.st));
-  if (qr4) {
-    // u = Q1 Q3 y into F (w_a u_a), then G = F^T M / s with the sign gauge
-    CKH(launch_apply_q1(nj, sh.n, sh.n_pad, sh.kc, c.S, c.colmap, c.Tws, c.W2, c.Tws2, Wj, c.sigma, c.order, c.kept,
+  if (qr5) {
+    // z = Q2 Q4 y (in F as scratch), v = P z into G with the gauge, u = M v / s
+    CKH(launch_apply_q1(nj, sh.n, sh.n_pad, sh.kc, c.W, nullptr, c.Tws2, c.S, c.Tws, Wj, c.sigma, c.order, c.kept,
                         c.sel, c.weight, c.F, c.st));
-    CKH(launch_factor_G_from_F(nj, sh.D, sh.kc, c.Ta, c.src, c.split, c.sigma, c.kept, c.sel, c.F, c.G, c.st));
+    CKH(launch_scatter_G(nj, sh.D, sh.n_pad, sh.kc, c.F, c.perm, c.colmap, c.kept, c.G, c.st));
+    CKH(launch_factor_F(nj, sh.D, sh.kc, c.Ta, c.src, c.split, c.sigma, c.kept, c.sel, c.G, c.F, c.st));
   } else if (qr) {
     // z = Q2 y (in F as scratch), v = P z into G with the gauge, u = M v / s
     CKH(launch_apply_q1(nj, sh.n, sh.n_pad, sh.kc, c.W, nullptr, c.Tws2, nullptr, nullptr, Wj, c.sigma, c.order,

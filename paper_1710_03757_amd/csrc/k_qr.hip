@@ -1082,6 +1082,41 @@ hipError_t run_qr4_precondition(int64_t njobs, int n, int D, int n_pad, const do
   return hipGetLastError();
 }
 
+// Five QRs (n_pad <= 1024): with R3 = Q5 R5 Q4^T as above, M P = Q1 Q3 Q5 R5
+// (Q2 Q4)^T, so the right singular vectors y of R5 (the normalised Jacobi
+// rows) give v = P Q2 Q4 y and u = M v / s; Q1, Q3 and Q5 are not needed.
+// Q2 stays in W1 with its panel T factors in Tws2, Q4 in S1 with its T
+// factors in Tws4 (n_pad * 32 doubles per job each); the first, third and
+// fifth QR use Tscr (6144 doubles per job) for their T factors.  The rows of
+// R5 end in W3; W2 is free afterwards.
+hipError_t run_qr5_precondition(int64_t njobs, int n, int D, int n_pad, const double* T, const int32_t* src,
+                                const int32_t* split, int32_t* perm, double* S1, double* W1, double* Tws2,
+                                double* W2, double* Tws4, double* W3, double* Tscr, int32_t* colmap, double* colnorm,
+                                hipStream_t stream) {
+  if (njobs == 0) return hipSuccess;
+  if (n_pad > 1024) return hipErrorInvalidValue;
+  hipError_t e = order_and_unfold(njobs, n, D, n_pad, T, src, split, perm, S1, stream);
+  if (e != hipSuccess) return e;
+  e = qr_factor(njobs, n_pad, S1, Tscr, false, colmap, colnorm, stream);
+  if (e != hipSuccess) return e;
+  const dim3 rg(n_pad / 32, n_pad / 32, (unsigned)njobs);
+  double* T64 = Tscr + (size_t)njobs * 2048;
+  hipLaunchKernelGGL(r_rows_kernel, rg, dim3(256), 0, stream, n_pad, S1, W1, (const int32_t*)colmap);
+  e = qr_factor(njobs, n_pad, W1, Tws2, true, nullptr, nullptr, stream, Tscr);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(r_rows_kernel, rg, dim3(256), 0, stream, n_pad, W1, W2, (const int32_t*)nullptr);
+  e = qr_factor(njobs, n_pad, W2, Tscr, false, nullptr, nullptr, stream, T64);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(r_rows_kernel, rg, dim3(256), 0, stream, n_pad, W2, S1, (const int32_t*)nullptr);
+  e = qr_factor(njobs, n_pad, S1, Tws4, true, nullptr, nullptr, stream, Tscr);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(r_rows_kernel, rg, dim3(256), 0, stream, n_pad, S1, W2, (const int32_t*)nullptr);
+  e = qr_factor(njobs, n_pad, W2, Tscr, false, nullptr, nullptr, stream, T64);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(r_rows_kernel, rg, dim3(256), 0, stream, n_pad, W2, W3, (const int32_t*)nullptr);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
 // X[:, a] = w_a Q x_a for the kept rows x_a = W[order[sel[a]]] / s of the
 // Jacobi result, Q = prod_p (I - V_p T_p V_p^T) the orthogonal factor of a

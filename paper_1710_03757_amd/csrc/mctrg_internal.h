@@ -157,6 +157,13 @@ hipError_t run_qr4_precondition(int64_t njobs, int n, int D, int n_pad, const do
                                 const int32_t* split, int32_t* perm, double* S1, double* Tws1, double* W1,
                                 double* W2, double* Tws3, double* W3, double* Tscr, int32_t* colmap, double* colnorm,
                                 hipStream_t stream);
+// Five-QR preconditioning (see k_qr.hip; n_pad <= 1024): the rows of R5 in
+// W3; Q2 in W1 / Tws2, Q4 in S1 / Tws4 (n_pad * 32 doubles per job each);
+// Tscr: 6144 doubles per job of scratch; W2 is free afterwards.
+hipError_t run_qr5_precondition(int64_t njobs, int n, int D, int n_pad, const double* T, const int32_t* src,
+                                const int32_t* split, int32_t* perm, double* S1, double* W1, double* Tws2,
+                                double* W2, double* Tws4, double* W3, double* Tscr, int32_t* colmap, double* colnorm,
+                                hipStream_t stream);
 // X[:, a] = w_a Q Qb (W[order[sel[a]]] / s) with Q the orthogonal factor
 // kept in S1 (V, stored columns via colmap, NULL: identity) and Tws1 (panel
 // T), and Qb (optional: S1b / Tws1b, no column map, applied first; n_pad <=
