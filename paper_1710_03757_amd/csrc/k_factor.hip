@@ -173,98 +173,8 @@ hipError_t launch_factor_F(int64_t njobs, int D, int kcap, const double* T, cons
   return hipGetLastError();
 }
 
-// G[job][a][col] = (1/s_a) sum_row F[job][row][a] M[row][col] (= w_a v_a^T
-// with v_a = M^T u_a / s_a), zero for a >= kept.  One workgroup per
-// (64-column tile, job); rows staged through LDS in chunks of 32.
-__global__ __launch_bounds__(256) void factor_G_from_F_kernel(int D, int kcap, const double* __restrict__ T,
-                                                              const int32_t* __restrict__ src,
-                                                              const int32_t* __restrict__ split,
-                                                              const double* __restrict__ sigma,
-                                                              const int32_t* __restrict__ kept,
-                                                              const int32_t* __restrict__ sel,
-                                                              const double* __restrict__ F, double* __restrict__ G) {
-  const int64_t job = blockIdx.y;
-  const int n = D * D;
-  const int col0 = blockIdx.x * 64;
-  const int sp = split[job];
-  const double* Ts = T + (size_t)src[job] * n * n;
-  const double* Fj = F + (size_t)job * n * kcap;
-  const int kk = kept[job];
-  __shared__ double Ms[32][65];
-  __shared__ double Fs[32][65];
-  const int tid = threadIdx.x, cloc = tid & 63, agrp = tid >> 6;
-  double acc[16];
-#pragma unroll
-  for (int q = 0; q < 16; ++q) acc[q] = 0.0;
-  for (int r0 = 0; r0 < n; r0 += 32) {
-    for (int e = tid; e < 32 * 64; e += 256) {
-      const int rr = e >> 6, cc = e & 63;
-      const int row = r0 + rr, col = col0 + cc;
-      Ms[rr][cc] = (row < n && col < n) ? Ts[unfold_index(sp, D, row, col)] : 0.0;
-      Fs[rr][cc] = (row < n && cc < kk) ? Fj[(size_t)row * kcap + cc] : 0.0;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int aa = agrp + 4 * q;
-      if (aa < kcap) {
-        double s = acc[q];
-#pragma unroll 8
-        for (int rr = 0; rr < 32; ++rr) s += Fs[rr][aa] * Ms[rr][cloc];
-        acc[q] = s;
-      }
-    }
-    __syncthreads();
-  }
-  const int col = col0 + cloc;
-  if (col < n) {
-#pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int aa = agrp + 4 * q;
-      if (aa < kcap) {
-        double v = 0.0;
-        if (aa < kk) v = acc[q] / sigma[(size_t)job * n + sel[job * kcap + aa]];
-        G[(size_t)job * kcap * n + (size_t)aa * n + col] = v;
-      }
-    }
-  }
-}
-
-// Sign gauge of kept pair a: flip G[a][:] and F[:][a] unless
-// sum_col G[a][col] / (1 + col/D + phi (col % D)) > 0.
-__global__ __launch_bounds__(256) void gauge_fix_kernel(int D, int kcap, const int32_t* __restrict__ kept,
-                                                        double* __restrict__ G, double* __restrict__ F) {
-  const int a = blockIdx.x;
-  const int64_t job = blockIdx.y;
-  if (a >= kept[job]) return;
-  const int n = D * D;
-  double* Ga = G + (size_t)job * kcap * n + (size_t)a * n;
-  __shared__ double red[4];
-  double g = 0.0;
-  for (int e = threadIdx.x; e < n; e += 256) g += Ga[e] / (1.0 + (double)(e / D) + kGolden * (double)(e % D));
-  for (int o = 32; o > 0; o >>= 1) g += __shfl_xor(g, o);
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = g;
-  __syncthreads();
-  g = (red[0] + red[1]) + (red[2] + red[3]);
-  if (g < 0.0) {
-    for (int e = threadIdx.x; e < n; e += 256) Ga[e] = -Ga[e];
-    double* Fj = F + (size_t)job * n * kcap;
-    for (int r = threadIdx.x; r < n; r += 256) Fj[(size_t)r * kcap + a] = -Fj[(size_t)r * kcap + a];
-  }
-}
-
-hipError_t launch_factor_G_from_F(int64_t njobs, int D, int kcap, const double* T, const int32_t* src,
-                                  const int32_t* split, const double* sigma, const int32_t* kept, const int32_t* sel,
-                                  double* F, double* G, hipStream_t stream) {
-  if (njobs == 0) return hipSuccess;
-  const int n = D * D;
-  hipLaunchKernelGGL(factor_G_from_F_kernel, dim3(ceil_div(n, 64), (unsigned)njobs), dim3(256), 0, stream, D, kcap, T,
-                     src, split, sigma, kept, sel, F, G);
-  hipLaunchKernelGGL(gauge_fix_kernel, dim3(kcap, (unsigned)njobs), dim3(256), 0, stream, D, kcap, kept, G, F);
-  return hipGetLastError();
-}
-
-// Right factors from the three-QR route: X[c][a] = w_a z_a[c] is the kept
+// Right factors from the QR routes (an odd number of QR steps): X[c][a] =
+// w_a z_a[c] is the kept
 // right singular vector of M P (logical column c, c < n: the padding columns
 // sort last), so G[a][perm[colmap[c]]] = X[c][a] (= w_a v_a^T), signed so
 // that sum_e G[a][e] / (1 + e/D + phi (e % D)) > 0.  One workgroup per

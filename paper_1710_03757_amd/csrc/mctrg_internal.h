@@ -150,13 +150,6 @@ hipError_t run_qr3_precondition(int64_t njobs, int n, int D, int n_pad, const do
                                 const int32_t* split, int32_t* perm, double* S1, double* Tws1, double* W1,
                                 double* Tws2, double* W2, int32_t* colmap, double* colnorm, double** rows,
                                 hipStream_t stream);
-// Four-QR preconditioning (see k_qr.hip; n_pad <= 1024): the rows of R4 in
-// W3; Q1 in S1 (via colmap) / Tws1, Q3 in W2 / Tws3 (n_pad * 32 doubles per
-// job each); Tscr: 6144 doubles per job of scratch.
-hipError_t run_qr4_precondition(int64_t njobs, int n, int D, int n_pad, const double* T, const int32_t* src,
-                                const int32_t* split, int32_t* perm, double* S1, double* Tws1, double* W1,
-                                double* W2, double* Tws3, double* W3, double* Tscr, int32_t* colmap, double* colnorm,
-                                hipStream_t stream);
 // Five-QR preconditioning (see k_qr.hip; n_pad <= 1024): the rows of R5 in
 // W3; Q2 in W1 / Tws2, Q4 in S1 / Tws4 (n_pad * 32 doubles per job each);
 // Tscr: 6144 doubles per job of scratch; W2 is free afterwards.
@@ -176,10 +169,6 @@ hipError_t launch_apply_q1(int64_t njobs, int n, int n_pad, int kcap, const doub
 // with the gauge of the factor kernels; zero rows for a >= kept.
 hipError_t launch_scatter_G(int64_t njobs, int D, int n_pad, int kcap, const double* X, const int32_t* perm,
                             const int32_t* colmap, const int32_t* kept, double* G, hipStream_t stream);
-// G[a] = F[:, a]^T M / s_a, then the sign gauge on (G[a], F[:, a]).
-hipError_t launch_factor_G_from_F(int64_t njobs, int D, int kcap, const double* T, const int32_t* src,
-                                  const int32_t* split, const double* sigma, const int32_t* kept, const int32_t* sel,
-                                  double* F, double* G, hipStream_t stream);
 
 // Norms of the rotated rows, sorted descending: sigma[j][0..n), order[j][0..n).
 hipError_t launch_jacobi_finalize(int64_t njobs, int n, int n_pad, const double* W, double* sigma,
