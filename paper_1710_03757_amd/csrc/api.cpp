@@ -156,7 +156,7 @@ struct Chain {
   // device
   char* mem = nullptr;
   double *Ta = nullptr, *Tb = nullptr, *Tn = nullptr, *W = nullptr, *sigma = nullptr, *logr = nullptr,
-         *weight = nullptr, *sscr = nullptr, *G = nullptr, *F = nullptr, *X = nullptr, *Y = nullptr,
+         *weight = nullptr, *sscr = nullptr, *G = nullptr, *Gt = nullptr, *F = nullptr, *X = nullptr, *Y = nullptr,
          *scales = nullptr, *cbuf = nullptr, *lnc = nullptr, *lnc_steps = nullptr, *lnabs = nullptr;
   void *Xlp = nullptr, *Ylp = nullptr;
   double *S = nullptr, *Tws = nullptr, *W2 = nullptr, *Tws2 = nullptr, *W3 = nullptr, *Tscr = nullptr;
@@ -171,6 +171,8 @@ struct Chain {
   int8_t* sign = nullptr;
   JacobiWork jw{};
   int* nb_job = nullptr;
+  double* dnrm = nullptr;    // deflation: squared row norms, target rows (n_pad per job)
+  int32_t* dpos = nullptr;
   // host staging (pinned)
   HostPinned pin;
   int32_t *h_src = nullptr, *h_split = nullptr, *h_cjobs = nullptr;
@@ -207,7 +209,7 @@ struct Chain {
 
 // Lays out (or, when counting, sizes) every device buffer of a chain.
 void layout(Chain& c, Arena& ar) {
-  size_t tmax = 0, wmax = 0, nmax = 0, selmax = 0, sscr = 0, gmax = 0, xmax = 0, tnmax = 0;
+  size_t tmax = 0, wmax = 0, nmax = 0, selmax = 0, sscr = 0, gmax = 0, xmax = 0, tnmax = 0, pmax = 0;
   int64_t jmax = 0, omax = 0;
   for (int s = 0; s < c.n_steps; ++s) {
     const StepShape sh = c.shape(s);
@@ -217,6 +219,7 @@ void layout(Chain& c, Arena& ar) {
     tmax = std::max(tmax, (size_t)no * K4);
     wmax = std::max(wmax, (size_t)nj * sh.n_pad * sh.n_pad);
     nmax = std::max(nmax, (size_t)nj * sh.n);
+    pmax = std::max(pmax, (size_t)nj * sh.n_pad);
     selmax = std::max(selmax, (size_t)nj * sh.kc);
     sscr = std::max(sscr, sample_scratch_doubles(nj, sh.n, sh.kc));
     gmax = std::max(gmax, (size_t)nj * sh.kc * sh.n);
@@ -249,6 +252,7 @@ void layout(Chain& c, Arena& ar) {
   c.weight = ar.take<double>(selmax);
   c.sscr = ar.take<double>(sscr);
   c.G = ar.take<double>(gmax);
+  c.Gt = ar.take<double>(gmax);
   c.F = ar.take<double>(gmax);
   c.X = ar.take<double>(xmax);
   c.Y = ar.take<double>(xmax);
@@ -275,6 +279,8 @@ void layout(Chain& c, Arena& ar) {
   c.jw.lastmod = ar.take<int>((size_t)jmax * kJacobiMaxBlocks);
   c.jw.lastchk = ar.take<int>((size_t)jmax * kJacobiMaxBlocks * kJacobiMaxBlocks);
   c.nb_job = ar.take<int>(jmax);
+  c.dnrm = ar.take<double>(pmax);
+  c.dpos = ar.take<int32_t>(pmax);
 }
 
 std::vector<int> schedule(int d0, int k, int n_steps) {
@@ -430,7 +436,7 @@ int chain_step(Chain& c) {
   }
   // rows at the noise floor move behind the active ones and are not rotated
   int nb_max = 0;
-  CKH(run_deflate(nj, sh.n_pad, rows, Wj, c.nb_job, c.jw.counter, c.jw.counter_host, &nb_max, c.st));
+  CKH(run_deflate(nj, sh.n_pad, rows, Wj, c.nb_job, c.dnrm, c.dpos, c.jw.counter, c.jw.counter_host, &nb_max, c.st));
   CKH(run_jacobi(nj, sh.n_pad, Wj, c.jw, kMaxSweeps, c.st, c.tj.enabled ? &c.tj : nullptr, &c.last_sweeps, c.nb_job,
                  nb_max, c.sweep_hist));
   CKH(launch_jacobi_fail(nj, sh.jps, c.jw.sweeps, c.failed, c.st));
@@ -447,18 +453,18 @@ int chain_step(Chain& c) {
     CKH(launch_apply_q1(nj, sh.n, sh.n_pad, sh.kc, c.W, nullptr, c.Tws2, c.S, c.Tws, Wj, c.sigma, c.order, c.kept,
                         c.sel, c.weight, c.F, c.st));
     CKH(launch_scatter_G(nj, sh.D, sh.n_pad, sh.kc, c.F, c.perm, c.colmap, c.kept, c.G, c.st));
-    CKH(launch_factor_F(nj, sh.D, sh.kc, c.Ta, c.src, c.split, c.sigma, c.kept, c.sel, c.G, c.F, c.st));
+    CKH(launch_factor_F(nj, sh.D, sh.kc, c.Ta, c.src, c.split, c.sigma, c.kept, c.sel, c.G, c.Gt, c.F, c.st));
   } else if (qr) {
     // z = Q2 y (in F as scratch), v = P z into G with the gauge, u = M v / s
     CKH(launch_apply_q1(nj, sh.n, sh.n_pad, sh.kc, c.W, nullptr, c.Tws2, nullptr, nullptr, Wj, c.sigma, c.order,
                         c.kept, c.sel, c.weight, c.F, c.st));
     CKH(launch_scatter_G(nj, sh.D, sh.n_pad, sh.kc, c.F, c.perm, sh.n_pad <= 1024 ? c.colmap : nullptr, c.kept, c.G,
                          c.st));
-    CKH(launch_factor_F(nj, sh.D, sh.kc, c.Ta, c.src, c.split, c.sigma, c.kept, c.sel, c.G, c.F, c.st));
+    CKH(launch_factor_F(nj, sh.D, sh.kc, c.Ta, c.src, c.split, c.sigma, c.kept, c.sel, c.G, c.Gt, c.F, c.st));
   } else {
     CKH(launch_factor_G(nj, sh.D, sh.n_pad, sh.kc, Wj, c.sigma, c.order, c.kept, c.sel, c.weight, c.perm, c.G,
                         c.st));
-    CKH(launch_factor_F(nj, sh.D, sh.kc, c.Ta, c.src, c.split, c.sigma, c.kept, c.sel, c.G, c.F, c.st));
+    CKH(launch_factor_F(nj, sh.D, sh.kc, c.Ta, c.src, c.split, c.sigma, c.kept, c.sel, c.G, c.Gt, c.F, c.st));
   }
   ContractArgs ca{};
   ca.nout = no; ca.D = sh.D; ca.kk = sh.kc; ca.dtype = c.dtype;

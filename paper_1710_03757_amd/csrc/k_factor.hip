@@ -102,21 +102,38 @@ hipError_t launch_factor_G(int64_t njobs, int D, int n_pad, int kcap, const doub
   return hipGetLastError();
 }
 
+// Gt[job][a][l D + d] = G[job][a][d D + l] for the B-split jobs: the columns
+// (d, l) of M_B in the order in which T stores them.
+__global__ void transpose_G_kernel(int D, int kcap, const int32_t* __restrict__ split, const double* __restrict__ G,
+                                   double* __restrict__ Gt) {
+  const int64_t job = blockIdx.z;
+  const int a = blockIdx.y, n = D * D;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;   // l D + d
+  if (split[job] != 1 || e >= n) return;
+  const int l = e / D, d = e - l * D;
+  const size_t base = ((size_t)job * kcap + a) * n;
+  Gt[base + e] = G[base + (size_t)d * D + l];
+}
+
 // F[job][row][a] = (1/s_a) sum_col M[row][col] G[job][a][col].  One
-// workgroup per (64-row tile, job); column chunks of 32 staged in LDS.
+// workgroup per (64-row tile, job); column chunks of 32 staged in LDS.  For
+// the B split M_B[(u,r)][(d,l)] = T[l][u][r][d], so the columns are taken in
+// T's order (l, d), contiguous per row, with G from its transposed copy Gt.
 __global__ __launch_bounds__(256) void factor_F_kernel(int D, int kcap, const double* __restrict__ T,
                                                        const int32_t* __restrict__ src,
                                                        const int32_t* __restrict__ split,
                                                        const double* __restrict__ sigma,
                                                        const int32_t* __restrict__ kept,
                                                        const int32_t* __restrict__ sel,
-                                                       const double* __restrict__ G, double* __restrict__ F) {
+                                                       const double* __restrict__ G, const double* __restrict__ Gt,
+                                                       double* __restrict__ F) {
   const int64_t job = blockIdx.y;
   const int n = D * D;
   const int row0 = blockIdx.x * 64;
   const int sp = split[job];
   const double* Ts = T + (size_t)src[job] * n * n;
-  const double* Gj = G + (size_t)job * kcap * n;
+  const double* Gj = (sp == 1 ? Gt : G) + (size_t)job * kcap * n;
+  const size_t D3 = (size_t)D * D * D;
   const int kk = kept[job];
   __shared__ double Ms[64][33];
   __shared__ double Gs[64][33];
@@ -129,7 +146,16 @@ __global__ __launch_bounds__(256) void factor_F_kernel(int D, int kcap, const do
     for (int e = tid; e < 64 * 32; e += 256) {
       const int rr = e >> 5, cc = e & 31;
       const int row = row0 + rr, col = c0 + cc;
-      Ms[rr][cc] = (row < n && col < n) ? Ts[unfold_index(sp, D, row, col)] : 0.0;
+      double v = 0.0;
+      if (row < n && col < n) {
+        if (sp == 1) {   // col = l D + d
+          const int l = col / D, d = col - l * D;
+          v = Ts[(size_t)l * D3 + (size_t)row * D + d];
+        } else {
+          v = Ts[(size_t)row * n + col];
+        }
+      }
+      Ms[rr][cc] = v;
     }
     for (int e = tid; e < 64 * 32; e += 256) {
       const int aa = e >> 5, cc = e & 31;
@@ -165,11 +191,13 @@ __global__ __launch_bounds__(256) void factor_F_kernel(int D, int kcap, const do
 
 hipError_t launch_factor_F(int64_t njobs, int D, int kcap, const double* T, const int32_t* src,
                            const int32_t* split, const double* sigma, const int32_t* kept,
-                           const int32_t* sel, const double* G, double* F, hipStream_t stream) {
+                           const int32_t* sel, const double* G, double* Gt, double* F, hipStream_t stream) {
   if (njobs == 0) return hipSuccess;
   const int n = D * D;
+  hipLaunchKernelGGL(transpose_G_kernel, dim3(ceil_div(n, 256), kcap, (unsigned)njobs), dim3(256), 0, stream, D, kcap,
+                     split, G, Gt);
   hipLaunchKernelGGL(factor_F_kernel, dim3(ceil_div(n, 64), (unsigned)njobs), dim3(256), 0, stream, D, kcap, T,
-                     src, split, sigma, kept, sel, G, F);
+                     src, split, sigma, kept, sel, G, (const double*)Gt, F);
   return hipGetLastError();
 }
 

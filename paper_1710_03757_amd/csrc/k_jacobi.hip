@@ -736,45 +736,77 @@ hipError_t run_jacobi(int64_t njobs, int n_pad, double* W, const JacobiWork& wk,
 // by at most their norm (Weyl), i.e. at the rounding level of an FP64 SVD and
 // far below the candidate threshold tau_null * s_1.  nb_job receives the
 // number of row blocks (even, at least 2) that cover the active rows.
-// One workgroup of 256 threads per job; n_pad <= 4096.
+// Three kernels: squared row norms and the row copy (one wave per row), and
+// the partition between them (one workgroup per job); n_pad <= 4096.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void deflate_rows_kernel(int n_pad, int brows, const double* __restrict__ Win,
-                                                           double* __restrict__ Wout, int* __restrict__ nb_job) {
-  __shared__ double nrm[4096];
-  __shared__ int newpos[4096];
-  __shared__ double red[4];
-  __shared__ int cnt_s[4];
+// Squared row norms, one wave per row (lane-strided sum, then a butterfly).
+__global__ __launch_bounds__(256) void deflate_norms_kernel(int n_pad, const double* __restrict__ Win,
+                                                            double* __restrict__ nrm) {
+  const int64_t job = blockIdx.y;
+  const int lane = threadIdx.x & 63, r = 4 * blockIdx.x + (threadIdx.x >> 6);
+  if (r >= n_pad) return;
+  const double* row = Win + ((size_t)job * n_pad + r) * n_pad;
+  double sq = 0.0;
+  for (int c = lane; c < n_pad; c += 64) sq += row[c] * row[c];
+  for (int o = 32; o > 0; o >>= 1) sq += __shfl_xor(sq, o);
+  if (lane == 0) nrm[(size_t)job * n_pad + r] = sq;
+}
+
+// Per job: the rows above the noise floor (squared norm > 2^-96 of the
+// largest) keep their order at the front, the others follow in order
+// (stable partition by a block scan, n_pad <= 4096: m = n_pad / 256 rows per
+// thread); nb_job = the number of row blocks to rotate (even, >= 2).
+__global__ __launch_bounds__(256) void deflate_plan_kernel(int n_pad, int brows, const double* __restrict__ nrm,
+                                                           int32_t* __restrict__ newpos, int* __restrict__ nb_job) {
   const int64_t job = blockIdx.x;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const double* Wi = Win + (size_t)job * n_pad * n_pad;
-  double* Wo = Wout + (size_t)job * n_pad * n_pad;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const double* nj = nrm + (size_t)job * n_pad;
+  __shared__ double red[4];
+  __shared__ int cnt[256];
   double mx = 0.0;
-  for (int r = wave; r < n_pad; r += 4) {
-    double sq = 0.0;
-    for (int c = lane; c < n_pad; c += 64) sq += Wi[(size_t)r * n_pad + c] * Wi[(size_t)r * n_pad + c];
-    for (int o = 32; o > 0; o >>= 1) sq += __shfl_xor(sq, o);
-    if (lane == 0) nrm[r] = sq;
-    mx = fmax(mx, sq);
-  }
+  for (int r = tid; r < n_pad; r += 256) mx = fmax(mx, nj[r]);
+  for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o));
   if (lane == 0) red[wave] = mx;
   __syncthreads();
   const double thr = fmax(fmax(red[0], red[1]), fmax(red[2], red[3])) * 0x1.0p-96;
-  if (threadIdx.x == 0) {
-    // stable partition (sequential scan over at most 4096 flags)
-    int a = 0;
-    for (int r = 0; r < n_pad; ++r) a += nrm[r] > thr ? 1 : 0;
-    int ia = 0, ib = a;
-    for (int r = 0; r < n_pad; ++r) newpos[r] = nrm[r] > thr ? ia++ : ib++;
-    int nbk = 2 * ((a + 2 * brows - 1) / (2 * brows));
-    if (nbk < 2) nbk = 2;
-    nb_job[job] = nbk;
-    cnt_s[0] = a;
-  }
+  const int m = (n_pad + 255) / 256, r0 = tid * m;
+  int own = 0;
+  for (int q = 0; q < m; ++q)
+    if (r0 + q < n_pad && nj[r0 + q] > thr) ++own;
+  cnt[tid] = own;
   __syncthreads();
-  for (int r = wave; r < n_pad; r += 4) {
-    const int d = newpos[r];
-    for (int c = lane; c < n_pad; c += 64) Wo[(size_t)d * n_pad + c] = Wi[(size_t)r * n_pad + c];
+  for (int o = 1; o < 256; o <<= 1) {   // inclusive scan
+    const int v = tid >= o ? cnt[tid - o] : 0;
+    __syncthreads();
+    cnt[tid] += v;
+    __syncthreads();
   }
+  const int a = cnt[255];                   // rows above the floor
+  int before = cnt[tid] - own;              // active rows before r0
+  int32_t* pj = newpos + (size_t)job * n_pad;
+  for (int q = 0; q < m; ++q) {
+    const int r = r0 + q;
+    if (r >= n_pad) break;
+    if (nj[r] > thr) pj[r] = before++;
+    else pj[r] = a + (r - before);
+  }
+  if (tid == 0) {
+    int nbk = 2 * ((a + 2 * brows - 1) / (2 * brows));
+    nb_job[job] = nbk < 2 ? 2 : nbk;
+  }
+}
+
+// Row r moves to newpos[r], one wave per row with 16-byte accesses.
+__global__ __launch_bounds__(256) void deflate_copy_kernel(int n_pad, const double* __restrict__ Win,
+                                                           const int32_t* __restrict__ newpos,
+                                                           double* __restrict__ Wout) {
+  const int64_t job = blockIdx.y;
+  const int lane = threadIdx.x & 63, r = 4 * blockIdx.x + (threadIdx.x >> 6);
+  if (r >= n_pad) return;
+  const int d = newpos[(size_t)job * n_pad + r];
+  const double2* src = reinterpret_cast<const double2*>(Win + ((size_t)job * n_pad + r) * n_pad);
+  double2* dst = reinterpret_cast<double2*>(Wout + ((size_t)job * n_pad + d) * n_pad);
+  for (int c = lane; c < n_pad / 2; c += 64) dst[c] = src[c];
 }
 
 __global__ void max_int_kernel(int64_t n, const int* __restrict__ v, int* __restrict__ out) {
@@ -790,11 +822,15 @@ __global__ void max_int_kernel(int64_t n, const int* __restrict__ v, int* __rest
   }
 }
 
-hipError_t run_deflate(int64_t njobs, int n_pad, const double* Win, double* Wout, int* nb_job, int* scratch_dev,
-                       int* scratch_host, int* nb_max, hipStream_t stream) {
+hipError_t run_deflate(int64_t njobs, int n_pad, const double* Win, double* Wout, int* nb_job, double* nrm,
+                       int32_t* newpos, int* scratch_dev, int* scratch_host, int* nb_max, hipStream_t stream) {
   if (njobs == 0) { *nb_max = 2; return hipSuccess; }
-  hipLaunchKernelGGL(deflate_rows_kernel, dim3((unsigned)njobs), dim3(256), 0, stream, n_pad,
-                     jacobi_block_rows(n_pad), Win, Wout, nb_job);
+  if (n_pad > 4096) return hipErrorInvalidValue;
+  const dim3 rg((unsigned)ceil_div(n_pad, 4), (unsigned)njobs);
+  hipLaunchKernelGGL(deflate_norms_kernel, rg, dim3(256), 0, stream, n_pad, Win, nrm);
+  hipLaunchKernelGGL(deflate_plan_kernel, dim3((unsigned)njobs), dim3(256), 0, stream, n_pad, jacobi_block_rows(n_pad),
+                     (const double*)nrm, newpos, nb_job);
+  hipLaunchKernelGGL(deflate_copy_kernel, rg, dim3(256), 0, stream, n_pad, Win, (const int32_t*)newpos, Wout);
   hipLaunchKernelGGL(max_int_kernel, dim3(1), dim3(1024), 0, stream, njobs, nb_job, scratch_dev);
   hipError_t e = hipMemcpyAsync(scratch_host, scratch_dev, sizeof(int), hipMemcpyDeviceToHost, stream);
   if (e != hipSuccess) return e;

@@ -126,10 +126,12 @@ hipError_t run_jacobi(int64_t njobs, int n_pad, double* W, const JacobiWork& wk,
                       hipStream_t stream, KernelTimer* timer = nullptr, int* sweeps_done = nullptr,
                       const int* nb_job = nullptr, int nb_max = 0, int* history = nullptr);
 // Noise-floor deflation: Wout = rows of Win with the active rows (norm >
-// 2^-48 of the largest) first; nb_job = 16-row blocks covering them; the
-// maximum over jobs is returned in *nb_max (synchronises the stream).
-hipError_t run_deflate(int64_t njobs, int n_pad, const double* Win, double* Wout, int* nb_job, int* scratch_dev,
-                       int* scratch_host, int* nb_max, hipStream_t stream);
+// 2^-48 of the largest) first, in order, the others after them; nb_job =
+// the even number of Jacobi row blocks covering the active rows; the maximum
+// over jobs is returned in *nb_max (synchronises the stream).  nrm / newpos:
+// n_pad doubles / int32 per job of scratch; n_pad <= 4096.
+hipError_t run_deflate(int64_t njobs, int n_pad, const double* Win, double* Wout, int* nb_job, double* nrm,
+                       int32_t* newpos, int* scratch_dev, int* scratch_host, int* nb_max, hipStream_t stream);
 // QR preconditioning (k_qr.hip): perm[j] (n_pad) orders the columns of the
 // unfolding by decreasing norm, S (n_pad^2 per job) holds M P column-wise
 // and is overwritten by V and R, Tws (1024 per job) is scratch, and W
@@ -202,7 +204,7 @@ hipError_t launch_factor_G(int64_t njobs, int D, int n_pad, int kcap, const doub
                            hipStream_t stream);
 hipError_t launch_factor_F(int64_t njobs, int D, int kcap, const double* T, const int32_t* src,
                            const int32_t* split, const double* sigma, const int32_t* kept,
-                           const int32_t* sel, const double* G, double* F, hipStream_t stream);
+                           const int32_t* sel, const double* G, double* Gt, double* F, hipStream_t stream);
 
 // Contraction of four factors per output tensor.
 struct ContractArgs {
