@@ -1297,6 +1297,149 @@ __global__ __launch_bounds__(256) void apply_q1_mfma_kernel(int n, int n_pad, in
   }
 }
 
+// The same for up to 32 kept vectors and n_pad <= 1024, one workgroup of 8
+// waves per job with X (n_pad x 32) in registers: wave w owns the 16-row
+// tiles g = 8 t + w (t < n_pad / 128), lane (lr, lg) holding X[16 g + 4 i +
+// lg][16 vt + lr] in xr[t][vt][i], which is both the B operand layout of Y =
+// V^T X (k-step i of tile g) and the accumulator layout of X - V Z.  Each V
+// tile is read by the wave that owns its rows only; Y is summed over the
+// waves in a fixed order.
+constexpr int kApplyTiles = 8;   // row tiles per wave (n_pad <= 1024)
+__global__ __launch_bounds__(512) void apply_q_reg_kernel(int n, int n_pad, int kcap, const double* __restrict__ S1,
+                                                          const int32_t* __restrict__ colmap,
+                                                          const double* __restrict__ Tws1,
+                                                          const double* __restrict__ S1b,
+                                                          const double* __restrict__ Tws1b,
+                                                          const double* __restrict__ W2,
+                                                          const double* __restrict__ sigma,
+                                                          const int32_t* __restrict__ order,
+                                                          const int32_t* __restrict__ kept,
+                                                          const int32_t* __restrict__ sel,
+                                                          const double* __restrict__ weight, double* __restrict__ F) {
+  const int64_t job = blockIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int lr = lane & 15, lg = lane >> 4;
+  const int nk = kept[job];
+  __shared__ double Yp[8][4][256];   // per wave: tiles (ct, vt) of its partial Y
+  __shared__ double Ys[32][33];      // Y = V^T X (32 reflectors x 32 vectors)
+  __shared__ double Zs[32][33];      // -T Y
+  __shared__ double sv[32], wv[32];
+  __shared__ const double* rowp[32];
+  if (tid < 32) {
+    const int a = tid;
+    if (a < nk && a < kcap) {
+      const int i = sel[job * kcap + a];
+      sv[a] = sigma[(size_t)job * n + i];
+      wv[a] = weight[job * kcap + a];
+      rowp[a] = W2 + (size_t)job * n_pad * n_pad + (size_t)order[(size_t)job * n + i] * n_pad;
+    } else {
+      sv[a] = 1.0;
+      wv[a] = 0.0;
+      rowp[a] = nullptr;
+    }
+  }
+  __syncthreads();
+  const int ntile = n_pad / 16;   // row tiles of the job
+  f64x4 xr[kApplyTiles][2];
+#pragma unroll
+  for (int t = 0; t < kApplyTiles; ++t)
+#pragma unroll
+    for (int vt = 0; vt < 2; ++vt) {
+      const int g = 8 * t + wave, v = 16 * vt + lr;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int r = 16 * g + 4 * i + lg;
+        xr[t][vt][i] = (g < ntile && rowp[v]) ? rowp[v][r] / sv[v] : 0.0;
+      }
+    }
+  for (int set = S1b ? 0 : 1; set < 2; ++set) {   // the second factor (if any) first
+    const double* Sj = (set == 0 ? S1b : S1) + (size_t)job * n_pad * n_pad;
+    const int32_t* cm = (set == 1 && colmap) ? colmap + job * n_pad : nullptr;   // V_d is stored in column cm[d]
+    const double* Tj = (set == 0 ? Tws1b : Tws1) + (size_t)job * n_pad * 32;
+    for (int j = n_pad - 32; j >= 0; j -= 32) {
+      // ---- partial Y over this wave's tiles at or below row j -------------
+      f64x4 yp[2][2];
+#pragma unroll
+      for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+        for (int vt = 0; vt < 2; ++vt) yp[ct][vt] = f64x4{0, 0, 0, 0};
+      const int d0 = j + lr, d1 = j + 16 + lr;   // V columns of the A fragments (ct = 0, 1)
+      const double* c0 = Sj + (size_t)(cm ? cm[d0] : d0) * n_pad;
+      const double* c1 = Sj + (size_t)(cm ? cm[d1] : d1) * n_pad;
+#pragma unroll
+      for (int t = 0; t < kApplyTiles; ++t) {
+        const int g = 8 * t + wave;
+        if (g >= ntile || 16 * g + 15 < j) continue;   // (uniform per wave)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int r = 16 * g + 4 * i + lg;
+          double a0 = c0[r], a1 = c1[r];
+          a0 = r > d0 ? a0 : (r == d0 ? 1.0 : 0.0);
+          a1 = r > d1 ? a1 : (r == d1 ? 1.0 : 0.0);
+#pragma unroll
+          for (int vt = 0; vt < 2; ++vt) {
+            yp[0][vt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, xr[t][vt][i], yp[0][vt], 0, 0, 0);
+            yp[1][vt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, xr[t][vt][i], yp[1][vt], 0, 0, 0);
+          }
+        }
+      }
+#pragma unroll
+      for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+        for (int vt = 0; vt < 2; ++vt)
+#pragma unroll
+          for (int x = 0; x < 4; ++x) Yp[wave][2 * ct + vt][acc_row_f64(lg, x) * 16 + lr] = yp[ct][vt][x];
+      __syncthreads();
+      for (int e = tid; e < 1024; e += 512) {   // Y[c][v], summed over the waves in order
+        const int c = e >> 5, v = e & 31, tile = 2 * (c >> 4) + (v >> 4), idx = (c & 15) * 16 + (v & 15);
+        double y = Yp[0][tile][idx];
+#pragma unroll
+        for (int w = 1; w < 8; ++w) y += Yp[w][tile][idx];
+        Ys[c][v] = y;
+      }
+      __syncthreads();
+      for (int e = tid; e < 1024; e += 512) {   // -Z[c][v] = -sum_{c' >= c} T[c][c'] Y[c'][v]
+        const int c = e >> 5, v = e & 31;
+        const double* Trow = Tj + (size_t)(j / 32) * 1024 + c * 32;
+        double z = 0.0;
+        for (int c2 = c; c2 < 32; ++c2) z += Trow[c2] * Ys[c2][v];
+        Zs[c][v] = -z;
+      }
+      __syncthreads();
+      // ---- X <- X - V Z on this wave's tiles -------------------------------
+#pragma unroll
+      for (int ks = 0; ks < 8; ++ks) {
+        const double bz0 = Zs[4 * ks + lg][lr], bz1 = Zs[4 * ks + lg][16 + lr];
+        const int d = j + 4 * ks + lg;
+        const double* vc = Sj + (size_t)(cm ? cm[d] : d) * n_pad;
+#pragma unroll
+        for (int t = 0; t < kApplyTiles; ++t) {
+          const int g = 8 * t + wave;
+          if (g >= ntile || 16 * g + 15 < j) continue;   // (uniform per wave)
+          const int r = 16 * g + lr;
+          double v = vc[r];
+          v = r > d ? v : (r == d ? 1.0 : 0.0);
+          xr[t][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(v, bz0, xr[t][0], 0, 0, 0);
+          xr[t][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(v, bz1, xr[t][1], 0, 0, 0);
+        }
+      }
+    }
+  }
+  double* Fj = F + (size_t)job * n * kcap;
+#pragma unroll
+  for (int t = 0; t < kApplyTiles; ++t)
+#pragma unroll
+    for (int vt = 0; vt < 2; ++vt) {
+      const int g = 8 * t + wave, a = 16 * vt + lr;
+      if (g >= ntile || a >= kcap) continue;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int r = 16 * g + 4 * i + lg;
+        if (r < n) Fj[(size_t)r * kcap + a] = (a < nk) ? wv[a] * xr[t][vt][i] : 0.0;
+      }
+    }
+}
+
 size_t apply_q1_mfma_lds(int n_pad) { return sizeof(double) * ((size_t)n_pad * 16 + 4 * 2 * 256 + 2 * 32 * 16); }
 
 hipError_t launch_apply_q1(int64_t njobs, int n, int n_pad, int kcap, const double* S1, const int32_t* colmap,
@@ -1305,7 +1448,10 @@ hipError_t launch_apply_q1(int64_t njobs, int n, int n_pad, int kcap, const doub
                            const double* weight, double* F, hipStream_t stream) {
   if (njobs == 0) return hipSuccess;
   if (S1b && n_pad > 1024) return hipErrorInvalidValue;   // two factors only with 32-column panels
-  if (n_pad <= 1024) {
+  if (n_pad <= 1024 && kcap > 16 && kcap <= 32) {
+    hipLaunchKernelGGL(apply_q_reg_kernel, dim3((unsigned)njobs), dim3(512), 0, stream, n, n_pad, kcap, S1, colmap,
+                       Tws1, S1b, Tws1b, W2, sigma, order, kept, sel, weight, F);
+  } else if (n_pad <= 1024) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&apply_q1_mfma_kernel),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)apply_q1_mfma_lds(n_pad));
     if (e != hipSuccess) return e;
