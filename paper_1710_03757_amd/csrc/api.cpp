@@ -422,12 +422,12 @@ int chain_step(Chain& c) {
   double* rows = c.W2;   // the rows handed to the Jacobi
   double* Wj = c.W;      // the Jacobi workspace
   if (qr5) {
-    CKH(run_qr5_precondition(nj, sh.n, sh.D, sh.n_pad, c.Ta, c.src, c.split, c.perm, c.S, c.W, c.Tws2, c.W2, c.Tws,
+    CKH(run_qr5_precondition(nj, sh.n, sh.D, sh.n_pad, c.Ta, c.src, c.split, c.perm, c.dpos, c.S, c.W, c.Tws2, c.W2, c.Tws,
                              c.W3, c.Tscr, c.colmap, c.colnorm, c.st));
     rows = c.W3;         // c.W / c.Tws2 keep Q2, c.S / c.Tws keep Q4
     Wj = c.W2;
   } else if (qr) {
-    CKH(run_qr3_precondition(nj, sh.n, sh.D, sh.n_pad, c.Ta, c.src, c.split, c.perm, c.S, c.Tws, c.W, c.Tws2, c.W2,
+    CKH(run_qr3_precondition(nj, sh.n, sh.D, sh.n_pad, c.Ta, c.src, c.split, c.perm, c.dpos, c.S, c.Tws, c.W, c.Tws2, c.W2,
                              c.colmap, c.colnorm, &rows, c.st));
     Wj = c.W2;           // c.W keeps Q2
   } else {
@@ -833,6 +833,7 @@ int mctrg_svd_batched(int64_t n_mats, int32_t d1, int32_t d2, const double* M, d
     (void)ar.take<double>((size_t)n_mats * 1024); // Tws
     (void)ar.take<int32_t>((size_t)n_mats * n);   // order
     (void)ar.take<int32_t>((size_t)n_mats * n_pad);  // perm
+    (void)ar.take<int32_t>((size_t)n_mats * n_pad);  // inverse of perm
     (void)ar.take<int32_t>(2 * n_mats);           // src, split
     (void)ar.take<int>(3 * n_mats + 2);           // jacobi work
     if (pass == 0) break;
@@ -848,6 +849,7 @@ int mctrg_svd_batched(int64_t n_mats, int32_t d1, int32_t d2, const double* M, d
   double* Tws = a2.take<double>((size_t)n_mats * 1024);
   int32_t* order = a2.take<int32_t>((size_t)n_mats * n);
   int32_t* perm = a2.take<int32_t>((size_t)n_mats * n_pad);
+  int32_t* iperm = a2.take<int32_t>((size_t)n_mats * n_pad);
   int32_t* ss = a2.take<int32_t>(2 * n_mats);
   int* jws = a2.take<int>(3 * n_mats + 2);
   std::vector<int32_t> hs(2 * n_mats);
@@ -858,7 +860,7 @@ int mctrg_svd_batched(int64_t n_mats, int32_t d1, int32_t d2, const double* M, d
     rc = MCTRG_EDEVICE;
   if (rc == MCTRG_OK) {
     hipError_t e = (n_pad <= kQrMaxN)
-                       ? run_qr_precondition(n_mats, n, 0, n_pad, M, ss, ss + n_mats, perm, S, Tws, W, st)
+                       ? run_qr_precondition(n_mats, n, 0, n_pad, M, ss, ss + n_mats, perm, iperm, S, Tws, W, st)
                        : (launch_pad_copy(n_mats, n, n_pad, M, W, st) == hipSuccess ? launch_iota(n_mats, n_pad, perm, st)
                                                                                     : hipErrorUnknown);
     if (e != hipSuccess) rc = MCTRG_EDEVICE;

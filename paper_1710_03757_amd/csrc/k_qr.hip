@@ -28,17 +28,16 @@ namespace mctrg {
 // ---------------------------------------------------------------------------
 // Column norms of M and their descending order (ties by index): P.
 // ---------------------------------------------------------------------------
-// split 0: M_A of a D^4 tensor; 1: M_B; 2: a plain row-major n x n matrix
-__device__ __forceinline__ size_t unfold_idx(int split, int D, int n, int row, int col) {
-  if (split != 1) return (size_t)row * n + col;
-  const int u = row / D, r = row % D, d = col / D, l = col % D;
-  return (((size_t)l * D + u) * D + r) * D + d;
-}
-
+// split 0: M_A of a D^4 tensor, M_A[(l,u)][(r,d)] = T[l][u][r][d]; 1: M_B,
+// M_B[(u,r)][(d,l)] = T[l][u][r][d]; 2: a plain row-major n x n matrix.
+// perm = the columns of M by decreasing norm (ties by index, padding
+// columns last), iperm its inverse.  The threads take the columns in the
+// order T stores them (for M_B, column (d, l) as l D + d), so that the loads
+// of a row are contiguous.
 __global__ __launch_bounds__(256) void colnorm_order_kernel(int n, int D, int n_pad, const double* __restrict__ T,
                                                             const int32_t* __restrict__ src,
                                                             const int32_t* __restrict__ split,
-                                                            int32_t* __restrict__ perm) {
+                                                            int32_t* __restrict__ perm, int32_t* __restrict__ iperm) {
   extern __shared__ unsigned char smem[];
   int P = 1;
   while (P < n_pad) P <<= 1;
@@ -47,15 +46,26 @@ __global__ __launch_bounds__(256) void colnorm_order_kernel(int n, int D, int n_
   const int64_t job = blockIdx.x;
   const double* Ts = T + (size_t)src[job] * n * n;
   const int sp = split[job];
-  for (int c = threadIdx.x; c < P; c += 256) {
+  for (int t = threadIdx.x; t < P; t += 256) {
     double s = -1.0;
-    if (c < n) {
+    int c = t;
+    if (t < n) {
       s = 0.0;
-      for (int r = 0; r < n; ++r) {
-        const double v = Ts[unfold_idx(sp, D, n, r, c)];
-        s += v * v;
+      if (sp == 1) {   // t = l D + d, column (d, l) of M_B: T[l][.][.][d]
+        const int l = t / D, d = t - l * D;
+        c = d * D + l;
+        const double* base = Ts + (size_t)l * D * D * D + d;
+        for (int r = 0; r < n; ++r) {
+          const double v = base[(size_t)r * D];
+          s += v * v;
+        }
+      } else {
+        for (int r = 0; r < n; ++r) {
+          const double v = Ts[(size_t)r * n + t];
+          s += v * v;
+        }
       }
-    } else if (c < n_pad) {
+    } else if (t < n_pad) {
       s = -0.5;
     }
     key[c] = s;
@@ -75,23 +85,54 @@ __global__ __launch_bounds__(256) void colnorm_order_kernel(int n, int D, int n_
       __syncthreads();
     }
   }
-  for (int c = threadIdx.x; c < n_pad; c += 256) perm[job * n_pad + c] = idx[c];
+  for (int c = threadIdx.x; c < n_pad; c += 256) {
+    perm[job * n_pad + c] = idx[c];
+    iperm[job * n_pad + idx[c]] = c;
+  }
 }
 
-// S[c][r] = M[r][perm[c]] (zero outside n x n).
-__global__ void unfold_cols_kernel(int n, int D, int n_pad, const double* __restrict__ T,
-                                   const int32_t* __restrict__ src, const int32_t* __restrict__ split,
-                                   const int32_t* __restrict__ perm, double* __restrict__ S) {
-  const int64_t job = blockIdx.y;
-  const size_t per = (size_t)n_pad * n_pad;
+// S[c][r] = M[r][perm[c]] (zero outside n x n).  Tiles of 64 rows x 32
+// columns of M, the columns taken in the order T stores them (as in
+// colnorm_order_kernel), are read row by row, transposed through LDS, and
+// each column written contiguously to its place S[iperm[col]].
+__global__ __launch_bounds__(256) void unfold_cols_kernel(int n, int D, int n_pad, const double* __restrict__ T,
+                                                          const int32_t* __restrict__ src,
+                                                          const int32_t* __restrict__ split,
+                                                          const int32_t* __restrict__ iperm, double* __restrict__ S) {
+  const int64_t job = blockIdx.z;
+  const int r0 = 64 * blockIdx.x, t0 = 32 * blockIdx.y, tid = threadIdx.x;
   const double* Ts = T + (size_t)src[job] * n * n;
   const int sp = split[job];
-  const int32_t* pj = perm + job * n_pad;
-  double* Sj = S + job * per;
-  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < per; e += (size_t)gridDim.x * blockDim.x) {
-    const int c = (int)(e / n_pad), r = (int)(e % n_pad);
-    const int pc = pj[c];
-    Sj[e] = (r < n && pc < n) ? Ts[unfold_idx(sp, D, n, r, pc)] : 0.0;
+  __shared__ double tile[32][65];   // [column][row]
+  {
+    const int tc = tid & 31, tr = tid >> 5, t = t0 + tc;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int r = r0 + tr + 8 * q;
+      double v = 0.0;
+      if (r < n && t < n) {
+        if (sp == 1) {
+          const int l = t / D, d = t - l * D;
+          v = Ts[(size_t)l * D * D * D + (size_t)r * D + d];
+        } else {
+          v = Ts[(size_t)r * n + t];
+        }
+      }
+      tile[tc][tr + 8 * q] = v;
+    }
+  }
+  __syncthreads();
+  double* Sj = S + (size_t)job * n_pad * n_pad;
+  const int32_t* ip = iperm + job * n_pad;
+  for (int e = tid; e < 32 * 64; e += 256) {
+    const int tc = e >> 6, rr = e & 63, t = t0 + tc, r = r0 + rr;
+    if (t >= n_pad || r >= n_pad) continue;
+    int col = t;
+    if (sp == 1 && t < n) {
+      const int l = t / D;
+      col = (t - l * D) * D + l;
+    }
+    Sj[(size_t)ip[col] * n_pad + r] = tile[tc][rr];
   }
 }
 
@@ -695,16 +736,31 @@ __global__ __launch_bounds__(256) void qr_t64_kernel(int n_pad, int j, const dou
   const double* c1 = Sj + (size_t)(j + 16 * ta + lr) * n_pad;        // column of V1 (all rows >= j + 32 below its diagonal)
   const int d2 = j + 32 + 16 * tb + lr;                                // diagonal row of this V2 column
   const double* c2 = Sj + (size_t)d2 * n_pad;
-  f64x4 acc = {0, 0, 0, 0};
-  for (int r0 = j + 32; r0 < n_pad; r0 += 8) {
-    const int r = r0 + 2 * lg;
-    const double2 a = *reinterpret_cast<const double2*>(c1 + r);
-    double2 b = *reinterpret_cast<const double2*>(c2 + r);
-    b.x = r > d2 ? b.x : (r == d2 ? 1.0 : 0.0);
-    b.y = r + 1 > d2 ? b.y : (r + 1 == d2 ? 1.0 : 0.0);
-    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.x, acc, 0, 0, 0);
-    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b.y, acc, 0, 0, 0);
+  // four independent accumulators over interleaved 8-row chunks, so that
+  // the loads of four chunks are in flight at once (n_pad - j - 32 is a
+  // multiple of 32)
+  f64x4 acc4[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) acc4[u] = f64x4{0, 0, 0, 0};
+  for (int r0 = j + 32; r0 < n_pad; r0 += 32) {
+    double2 a[4], b[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int r = r0 + 8 * u + 2 * lg;
+      a[u] = *reinterpret_cast<const double2*>(c1 + r);
+      b[u] = *reinterpret_cast<const double2*>(c2 + r);
+      b[u].x = r > d2 ? b[u].x : (r == d2 ? 1.0 : 0.0);
+      b[u].y = r + 1 > d2 ? b[u].y : (r + 1 == d2 ? 1.0 : 0.0);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      acc4[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u].x, b[u].x, acc4[u], 0, 0, 0);
+      acc4[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u].y, b[u].y, acc4[u], 0, 0, 0);
+    }
   }
+  f64x4 acc;
+#pragma unroll
+  for (int x = 0; x < 4; ++x) acc[x] = ((acc4[0][x] + acc4[1][x]) + acc4[2][x]) + acc4[3][x];
 #pragma unroll
   for (int x = 0; x < 4; ++x) X[16 * ta + acc_row_f64(lg, x)][16 * tb + lr] = acc[x];
   __syncthreads();
@@ -985,25 +1041,24 @@ static hipError_t qr_factor(int64_t njobs, int n_pad, double* S, double* Tws, bo
 }
 
 static hipError_t order_and_unfold(int64_t njobs, int n, int D, int n_pad, const double* T, const int32_t* src,
-                                   const int32_t* split, int32_t* perm, double* S, hipStream_t stream) {
+                                   const int32_t* split, int32_t* perm, int32_t* iperm, double* S,
+                                   hipStream_t stream) {
   int P = 1;
   while (P < n_pad) P <<= 1;
   hipLaunchKernelGGL(colnorm_order_kernel, dim3((unsigned)njobs), dim3(256), (size_t)P * 12, stream, n, D, n_pad, T,
-                     src, split, perm);
-  const size_t per = (size_t)n_pad * n_pad;
-  int gx = (int)((per + 255) / 256);
-  if (gx > 1024) gx = 1024;
-  hipLaunchKernelGGL(unfold_cols_kernel, dim3(gx, (unsigned)njobs), dim3(256), 0, stream, n, D, n_pad, T, src, split,
-                     perm, S);
+                     src, split, perm, iperm);
+  hipLaunchKernelGGL(unfold_cols_kernel, dim3((unsigned)ceil_div(n_pad, 64), (unsigned)ceil_div(n_pad, 32),
+                                              (unsigned)njobs),
+                     dim3(256), 0, stream, n, D, n_pad, T, src, split, (const int32_t*)iperm, S);
   return hipGetLastError();
 }
 
 hipError_t run_qr_precondition(int64_t njobs, int n, int D, int n_pad, const double* T, const int32_t* src,
-                               const int32_t* split, int32_t* perm, double* S, double* Tws, double* W,
+                               const int32_t* split, int32_t* perm, int32_t* iperm, double* S, double* Tws, double* W,
                                hipStream_t stream) {
   if (njobs == 0) return hipSuccess;
   if (n_pad > kQrMaxN) return hipErrorInvalidValue;
-  hipError_t e = order_and_unfold(njobs, n, D, n_pad, T, src, split, perm, S, stream);
+  hipError_t e = order_and_unfold(njobs, n, D, n_pad, T, src, split, perm, iperm, S, stream);
   if (e != hipSuccess) return e;
   e = qr_factor(njobs, n_pad, S, Tws, false, nullptr, nullptr, stream);
   if (e != hipSuccess) return e;
@@ -1025,13 +1080,13 @@ hipError_t run_qr_precondition(int64_t njobs, int n, int D, int n_pad, const dou
 // in place, then the rows of R3, returned in *rows), W1 (QR2 in place), W2
 // (rows of R2, QR3 in place); Tws1 is scratch.
 hipError_t run_qr3_precondition(int64_t njobs, int n, int D, int n_pad, const double* T, const int32_t* src,
-                                const int32_t* split, int32_t* perm, double* S1, double* Tws1, double* W1,
+                                const int32_t* split, int32_t* perm, int32_t* iperm, double* S1, double* Tws1, double* W1,
                                 double* Tws2, double* W2, int32_t* colmap, double* colnorm, double** rows,
                                 hipStream_t stream) {
   if (njobs == 0) return hipSuccess;
   if (n_pad > kQrMaxN) return hipErrorInvalidValue;
   if (n_pad > 1024) colmap = nullptr;   // re-ordering only with 32-column panels
-  hipError_t e = order_and_unfold(njobs, n, D, n_pad, T, src, split, perm, S1, stream);
+  hipError_t e = order_and_unfold(njobs, n, D, n_pad, T, src, split, perm, iperm, S1, stream);
   if (e != hipSuccess) return e;
   e = qr_factor(njobs, n_pad, S1, Tws1, false, colmap, colnorm, stream);
   if (e != hipSuccess) return e;
@@ -1062,12 +1117,12 @@ hipError_t run_qr3_precondition(int64_t njobs, int n, int D, int n_pad, const do
 // fifth QR use Tscr (6144 doubles per job) for their T factors.  The rows of
 // R5 end in W3; W2 is free afterwards.
 hipError_t run_qr5_precondition(int64_t njobs, int n, int D, int n_pad, const double* T, const int32_t* src,
-                                const int32_t* split, int32_t* perm, double* S1, double* W1, double* Tws2,
+                                const int32_t* split, int32_t* perm, int32_t* iperm, double* S1, double* W1, double* Tws2,
                                 double* W2, double* Tws4, double* W3, double* Tscr, int32_t* colmap, double* colnorm,
                                 hipStream_t stream) {
   if (njobs == 0) return hipSuccess;
   if (n_pad > 1024) return hipErrorInvalidValue;
-  hipError_t e = order_and_unfold(njobs, n, D, n_pad, T, src, split, perm, S1, stream);
+  hipError_t e = order_and_unfold(njobs, n, D, n_pad, T, src, split, perm, iperm, S1, stream);
   if (e != hipSuccess) return e;
   e = qr_factor(njobs, n_pad, S1, Tscr, false, colmap, colnorm, stream);
   if (e != hipSuccess) return e;

@@ -138,7 +138,7 @@ hipError_t run_deflate(int64_t njobs, int n_pad, const double* Win, double* Wout
 // receives the rows of R.  split 2 = plain row-major n x n matrices.
 constexpr int kQrMaxN = 4096;
 hipError_t run_qr_precondition(int64_t njobs, int n, int D, int n_pad, const double* T, const int32_t* src,
-                               const int32_t* split, int32_t* perm, double* S, double* Tws, double* W,
+                               const int32_t* split, int32_t* perm, int32_t* iperm, double* S, double* Tws, double* W,
                                hipStream_t stream);
 hipError_t launch_iota(int64_t njobs, int n_pad, int32_t* perm, hipStream_t stream);
 // Three-QR preconditioning (see k_qr.hip): *rows receives the buffer with
@@ -149,14 +149,14 @@ hipError_t launch_iota(int64_t njobs, int n_pad, int32_t* perm, hipStream_t stre
 // per job (the column re-ordering of the first QR, n_pad <= 1024; NULL:
 // static order only).
 hipError_t run_qr3_precondition(int64_t njobs, int n, int D, int n_pad, const double* T, const int32_t* src,
-                                const int32_t* split, int32_t* perm, double* S1, double* Tws1, double* W1,
+                                const int32_t* split, int32_t* perm, int32_t* iperm, double* S1, double* Tws1, double* W1,
                                 double* Tws2, double* W2, int32_t* colmap, double* colnorm, double** rows,
                                 hipStream_t stream);
 // Five-QR preconditioning (see k_qr.hip; n_pad <= 1024): the rows of R5 in
 // W3; Q2 in W1 / Tws2, Q4 in S1 / Tws4 (n_pad * 32 doubles per job each);
 // Tscr: 6144 doubles per job of scratch; W2 is free afterwards.
 hipError_t run_qr5_precondition(int64_t njobs, int n, int D, int n_pad, const double* T, const int32_t* src,
-                                const int32_t* split, int32_t* perm, double* S1, double* W1, double* Tws2,
+                                const int32_t* split, int32_t* perm, int32_t* iperm, double* S1, double* W1, double* Tws2,
                                 double* W2, double* Tws4, double* W3, double* Tscr, int32_t* colmap, double* colnorm,
                                 hipStream_t stream);
 // X[:, a] = w_a Q Qb (W[order[sel[a]]] / s) with Q the orthogonal factor
