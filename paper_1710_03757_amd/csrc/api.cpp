@@ -237,7 +237,7 @@ void layout(Chain& c, Arena& ar) {
   c.S = ar.take<double>(wmax);
   c.W2 = ar.take<double>(wmax);
   c.W3 = ar.take<double>(wmax);
-  c.Tscr = ar.take<double>((size_t)jmax * 6144);
+  c.Tscr = ar.take<double>((size_t)jmax * kQrTscr);
   c.Tws = ar.take<double>((size_t)jmax * 32 * 1024);
   c.Tws2 = ar.take<double>((size_t)jmax * 32 * 1024);
   c.perm = ar.take<int32_t>((size_t)jmax * 4096);

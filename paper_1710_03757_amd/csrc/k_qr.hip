@@ -587,19 +587,39 @@ __global__ __launch_bounds__(256) void qr_trailing_kernel(int n_pad, int j, doub
 
 // The trailing update for 32-column panels (n_pad <= 1024; columns j + 32 ..
 // cend - 1) with the V
+// Workgroups reach the eight XCDs round-robin by linear index, and each XCD
+// has its own L2.  The trailing updates launch (tile, job) grids with the
+// job count rounded up to a multiple of 8 and take their (job, tile) from
+// this map, which puts every tile of a job on one XCD: the V chunks, which
+// all tiles of a job read, are then fetched from HBM about once per job
+// instead of once per XCD.  False for the padding workgroups (uniform).
+__device__ __forceinline__ bool xcd_job_tile(int64_t njobs, int64_t& job, int& tile) {
+  const unsigned L = blockIdx.x + gridDim.x * blockIdx.y;
+  const unsigned q = L >> 3;
+  job = (int64_t)(q / gridDim.x) * 8 + (L & 7);
+  tile = (int)(q % gridDim.x);
+  return job < njobs;
+}
+static inline dim3 xcd_tile_grid(int ntiles, int64_t njobs) {
+  return dim3((unsigned)ntiles, (unsigned)((njobs + 7) / 8 * 8));
+}
+
 // panel staged through LDS: every 16-row chunk of V (16 x 32) is loaded once
 // per workgroup, coalesced, masked to the unit lower trapezoid, and shared
 // by the four waves (instead of each wave fetching it), double-buffered with
 // one barrier per chunk.  Same arithmetic as qr_trailing_kernel<32>.
-__global__ __launch_bounds__(256) void qr_trailing32_kernel(int n_pad, int j, int cend, double* __restrict__ S,
-                                                            const double* __restrict__ Tws, int64_t t_stride,
-                                                            int64_t t_off, const int32_t* __restrict__ colmap,
+__global__ __launch_bounds__(256) void qr_trailing32_kernel(int64_t njobs, int n_pad, int j, int cend,
+                                                            double* __restrict__ S, const double* __restrict__ Tws,
+                                                            int64_t t_stride, int64_t t_off,
+                                                            const int32_t* __restrict__ colmap,
                                                             double* __restrict__ colnorm) {
-  const int64_t job = blockIdx.y;
+  int64_t job;
+  int tile;
+  if (!xcd_job_tile(njobs, job, tile)) return;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int lr = lane & 15, lg = lane >> 4;
   double* Sj = S + job * (size_t)n_pad * n_pad;
-  const int c0w = j + 32 + 64 * blockIdx.x + 16 * wave;   // first column of this wave
+  const int c0w = j + 32 + 64 * tile + 16 * wave;   // first column of this wave
   __shared__ double Vs[2][16][33];
   __shared__ double W1[32][65];
   __shared__ double Tm[32][33];
@@ -608,11 +628,12 @@ __global__ __launch_bounds__(256) void qr_trailing32_kernel(int n_pad, int j, in
   const bool col_ok = (c0w + lr) < cend;
   const int32_t* cm = colmap ? colmap + job * n_pad : nullptr;
   auto scol = [&](int c) { return cm ? cm[c] : c; };
-  // V staging: thread t takes V column vd = t / 8, rows 2 (t % 8) and +1 of a chunk
+  // V staging: thread t takes V column vd = t / 8, rows 2 (t % 8) and +1 of
+  // a chunk; the next chunk's loads are issued before the products of the
+  // current one, the masking is done when they are stored
   const int vd = tid >> 3, vr = 2 * (tid & 7);
-  const double* vbase = Sj + (size_t)scol(j + vd) * n_pad;
-  auto stage_v = [&](int r0, int buf) {
-    const double2 v = *reinterpret_cast<const double2*>(vbase + r0 + vr);
+  const double* vbase = Sj + (size_t)scol(j + vd) * n_pad + vr;
+  auto store_v = [&](int r0, int buf, double2 v) {
     double a = v.x, b = v.y;
     if (r0 < j + 32) {   // V is stored below the diagonal, 1 on it, 0 above
       const int d = j + vd, ra = r0 + vr, rb = ra + 1;
@@ -626,14 +647,18 @@ __global__ __launch_bounds__(256) void qr_trailing32_kernel(int n_pad, int j, in
 
   // ---- phase 1: W1 = V^T C (32 x 16 per wave) ------------------------------
   f64x4 acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
-  const double* cbase = Sj + (size_t)scol(col_ok ? c0w + lr : (active ? c0w : j + 32)) * n_pad;
+  const double* cbase = Sj + (size_t)scol(col_ok ? c0w + lr : (active ? c0w : j + 32)) * n_pad + 4 * lg;
+  double2 vn = *reinterpret_cast<const double2*>(vbase + j);
+  double2 cn0 = *reinterpret_cast<const double2*>(cbase + j), cn1 = *reinterpret_cast<const double2*>(cbase + j + 2);
   for (int ch = 0; ch < nch; ++ch) {
     const int r0 = j + 16 * ch, buf = ch & 1;
-    stage_v(r0, buf);
-    const int rb = r0 + 4 * lg;
-    const double2 c01 = *reinterpret_cast<const double2*>(cbase + rb);
-    const double2 c23 = *reinterpret_cast<const double2*>(cbase + rb + 2);
-    const double cv[4] = {col_ok ? c01.x : 0.0, col_ok ? c01.y : 0.0, col_ok ? c23.x : 0.0, col_ok ? c23.y : 0.0};
+    store_v(r0, buf, vn);
+    const double cv[4] = {col_ok ? cn0.x : 0.0, col_ok ? cn0.y : 0.0, col_ok ? cn1.x : 0.0, col_ok ? cn1.y : 0.0};
+    if (ch + 1 < nch) {
+      vn = *reinterpret_cast<const double2*>(vbase + r0 + 16);
+      cn0 = *reinterpret_cast<const double2*>(cbase + r0 + 16);
+      cn1 = *reinterpret_cast<const double2*>(cbase + r0 + 18);
+    }
     __syncthreads();
 #pragma unroll
     for (int jj = 0; jj < 4; ++jj) {
@@ -674,14 +699,27 @@ __global__ __launch_bounds__(256) void qr_trailing32_kernel(int n_pad, int j, in
     const int c = c0w + acc_row_f64(lg, x);
     ccols[x] = (active && c < cend) ? scol(c) : -1;
   }
+  // columns not updated read a V column instead (always there, never stored)
+  const double* cp[4];
+#pragma unroll
+  for (int x = 0; x < 4; ++x) cp[x] = Sj + (size_t)(ccols[x] >= 0 ? ccols[x] : scol(j)) * n_pad + lr;
   double sq[4] = {0.0, 0.0, 0.0, 0.0};
+  double cold[4];
+  vn = *reinterpret_cast<const double2*>(vbase + j);
+#pragma unroll
+  for (int x = 0; x < 4; ++x) cold[x] = cp[x][j];
   for (int ch = 0; ch < nch; ++ch) {
     const int r0 = j + 16 * ch, buf = ch & 1;
-    stage_v(r0, buf);
+    store_v(r0, buf, vn);
     const int r = r0 + lr;
-    double cold[4];
+    double cc[4];
 #pragma unroll
-    for (int x = 0; x < 4; ++x) cold[x] = ccols[x] >= 0 ? Sj[(size_t)ccols[x] * n_pad + r] : 0.0;
+    for (int x = 0; x < 4; ++x) cc[x] = cold[x];
+    if (ch + 1 < nch) {
+      vn = *reinterpret_cast<const double2*>(vbase + r0 + 16);
+#pragma unroll
+      for (int x = 0; x < 4; ++x) cold[x] = cp[x][r0 + 16];
+    }
     __syncthreads();
     f64x4 a = {0, 0, 0, 0};
 #pragma unroll
@@ -689,7 +727,7 @@ __global__ __launch_bounds__(256) void qr_trailing32_kernel(int n_pad, int j, in
 #pragma unroll
     for (int x = 0; x < 4; ++x) {
       if (ccols[x] >= 0) {
-        const double v = cold[x] - a[x];
+        const double v = cc[x] - a[x];
         Sj[(size_t)ccols[x] * n_pad + r] = v;
         if (r >= j + 32) sq[x] = fma(v, v, sq[x]);
       }
@@ -716,8 +754,19 @@ __global__ __launch_bounds__(256) void qr_trailing32_kernel(int n_pad, int j, in
 // applied to the rest in one pass, half the passes over the trailing matrix
 // of 32-column blocks.
 //
-// qr_t64_kernel: T (64 x 64, row-major) of the block at column j into T64,
-// one workgroup per job.  V1^T V2 only involves rows >= j + 32 (V2 vanishes
+// Per-job scratch of the blocked path (kQrBlockScratch doubles): the T of
+// the first 64-column block of a 128-column step (row-major) at 0, of the
+// second at 4096, and the T of both, as MFMA A fragments of its transpose,
+// at 8192 (t128_frag).
+constexpr int64_t kT64Stride = kQrBlockScratch;
+constexpr int kT128Off = 8192;
+// Fragment (g, ks) of T^T (128 x 128, T upper triangular): rows 16 g .. 16 g
+// + 15, columns 4 ks .. 4 ks + 3, only ks <= 4 g + 3 (the rest is zero);
+// lane (lr, lg) holds T[4 ks + lg][16 g + lr].  144 fragments of 64 doubles.
+__device__ __forceinline__ int t128_frag(int g, int ks) { return 2 * g * (g + 1) + ks; }
+
+// qr_t64_kernel: T (64 x 64, row-major) of the block at column j into T64
+// (+ job * kT64Stride), one workgroup per job.  V1^T V2 only involves rows >= j + 32 (V2 vanishes
 // above); each wave forms one 16 x 16 tile of it with MFMA, a lane taking
 // two consecutive rows per step (16-byte loads; V is stored column-major).
 __global__ __launch_bounds__(256) void qr_t64_kernel(int n_pad, int j, const double* __restrict__ S,
@@ -771,7 +820,7 @@ __global__ __launch_bounds__(256) void qr_t64_kernel(int n_pad, int j, const dou
     Y[a][b] = v;
   }
   __syncthreads();
-  double* Tj = T64 + job * 4096;
+  double* Tj = T64 + job * kT64Stride;
   for (int e = tid; e < 4096; e += 256) {
     const int i = e >> 6, k = e & 63;
     double v;
@@ -791,17 +840,19 @@ __global__ __launch_bounds__(256) void qr_t64_kernel(int n_pad, int j, const dou
 // n_pad - 1, (job, 64-column tile) workgroups): phase 1 W = V^T C with the V
 // chunks staged through LDS as in qr_trailing32_kernel; phase 2 W <- T^T W
 // with MFMA (T packed upper in the staging buffer); phase 3 C <- C - V W.
-__global__ __launch_bounds__(256) void qr_trailing64_kernel(int n_pad, int j, double* __restrict__ S,
-                                                            const double* __restrict__ T64) {
-  const int64_t job = blockIdx.y;
+__global__ __launch_bounds__(256) void qr_trailing64_kernel(int64_t njobs, int n_pad, int j, int cend,
+                                                            double* __restrict__ S, const double* __restrict__ T64) {
+  int64_t job;
+  int tile;
+  if (!xcd_job_tile(njobs, job, tile)) return;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int lr = lane & 15, lg = lane >> 4;
   double* Sj = S + job * (size_t)n_pad * n_pad;
-  const int c0w = j + 64 + 64 * blockIdx.x + 16 * wave;   // first column of this wave
+  const int c0w = j + 64 + 64 * tile + 16 * wave;   // first column of this wave
   __shared__ double Vs[2][16][65];   // V chunks; T (packed upper, 2080 entries) in phase 2
   __shared__ double W1[64][65];
-  const bool active = c0w < n_pad;
-  const bool col_ok = (c0w + lr) < n_pad;
+  const bool active = c0w < cend;   // columns j + 64 .. cend - 1 are updated
+  const bool col_ok = (c0w + lr) < cend;
   // V staging: thread t takes V column vd = t / 4, rows 4 (t % 4) .. + 3 of a chunk
   const int vd = tid >> 2, vr = 4 * (tid & 3);
   const double* vbase = Sj + (size_t)(j + vd) * n_pad;
@@ -848,7 +899,7 @@ __global__ __launch_bounds__(256) void qr_trailing64_kernel(int n_pad, int j, do
   __syncthreads();
   // ---- phase 2: W2 = T^T W1, each wave on its own 16 columns --------------
   double* Tp = &Vs[0][0][0];   // T[m][i], m <= i, at i (i + 1) / 2 + m
-  const double* Tj = T64 + job * 4096;
+  const double* Tj = T64 + job * kT64Stride;
   for (int e = tid; e < 4096; e += 256) {
     const int m = e >> 6, i = e & 63;
     if (m <= i) Tp[((i * (i + 1)) >> 1) + m] = Tj[e];
@@ -884,7 +935,7 @@ __global__ __launch_bounds__(256) void qr_trailing64_kernel(int n_pad, int j, do
 #pragma unroll
   for (int x = 0; x < 4; ++x) {
     const int c = c0w + acc_row_f64(lg, x);
-    ccols[x] = (active && c < n_pad) ? c : -1;
+    ccols[x] = (active && c < cend) ? c : -1;
   }
   for (int ch = 0; ch < nch; ++ch) {
     const int r0 = j + 16 * ch, buf = ch & 1;
@@ -900,6 +951,263 @@ __global__ __launch_bounds__(256) void qr_trailing64_kernel(int n_pad, int j, do
 #pragma unroll
     for (int x = 0; x < 4; ++x)
       if (ccols[x] >= 0) Sj[(size_t)ccols[x] * n_pad + r] = cold[x] - a[x];
+  }
+}
+
+// qr_t128_kernel: T of the 128 columns j .. j + 127 (blocks A and B, their
+// 64 x 64 T factors at 0 and 4096 of the job's scratch) as
+// [[T_A, -T_A (V_A^T V_B) T_B], [0, T_B]], written as A fragments of its
+// transpose (t128_frag).  One workgroup per job.  X = V_A^T V_B only
+// involves rows >= j + 64 (V_B vanishes above), where every V_A entry lies
+// strictly below its diagonal; wave w forms the four 16 x 16 tiles of row
+// block w, a lane taking two consecutive rows per step.  The two 64 x 64
+// triangular products run on MFMA as well (only the upper triangles of T_A
+// and T_B are read); the tiles of T_AB end in the accumulator layout, which
+// is the fragment layout, and are stored from the registers.
+__global__ __launch_bounds__(256) void qr_t128_kernel(int n_pad, int j, const double* __restrict__ S,
+                                                      double* __restrict__ T64) {
+  const int64_t job = blockIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int lr = lane & 15, lg = lane >> 4;
+  const int ws = __builtin_amdgcn_readfirstlane(wave);
+  const double* Sj = S + job * (size_t)n_pad * n_pad;
+  double* Tb = T64 + job * kT64Stride;
+  const double* TA = Tb;
+  const double* TB = Tb + 4096;
+  __shared__ double L[64][65];   // X, then X T_B
+  const double* ca = Sj + (size_t)(j + 16 * ws + lr) * n_pad;
+  const double* cb[4];
+  int d2[4];
+#pragma unroll
+  for (int tb = 0; tb < 4; ++tb) {
+    d2[tb] = j + 64 + 16 * tb + lr;   // diagonal row of this V_B column
+    cb[tb] = Sj + (size_t)d2[tb] * n_pad;
+  }
+  f64x4 acc[4];
+#pragma unroll
+  for (int tb = 0; tb < 4; ++tb) acc[tb] = f64x4{0, 0, 0, 0};
+  for (int r0 = j + 64; r0 < n_pad; r0 += 16) {   // n_pad - j - 64 is a multiple of 32
+    double2 a[2], b[2][4];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int r = r0 + 8 * u + 2 * lg;
+      a[u] = *reinterpret_cast<const double2*>(ca + r);
+#pragma unroll
+      for (int tb = 0; tb < 4; ++tb) {
+        double2 v = *reinterpret_cast<const double2*>(cb[tb] + r);
+        v.x = r > d2[tb] ? v.x : (r == d2[tb] ? 1.0 : 0.0);
+        v.y = r + 1 > d2[tb] ? v.y : (r + 1 == d2[tb] ? 1.0 : 0.0);
+        b[u][tb] = v;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+#pragma unroll
+      for (int tb = 0; tb < 4; ++tb) acc[tb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u].x, b[u][tb].x, acc[tb], 0, 0, 0);
+#pragma unroll
+      for (int tb = 0; tb < 4; ++tb) acc[tb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u].y, b[u][tb].y, acc[tb], 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int tb = 0; tb < 4; ++tb)
+#pragma unroll
+    for (int x = 0; x < 4; ++x) L[16 * ws + acc_row_f64(lg, x)][16 * tb + lr] = acc[tb][x];
+  __syncthreads();
+  // Y = X T_B: tile (w, tb) over k-steps ks <= 4 tb + 3 (T_B upper)
+#pragma unroll
+  for (int tb = 0; tb < 4; ++tb) {
+    f64x4 y = {0, 0, 0, 0};
+#pragma unroll
+    for (int ks = 0; ks <= 4 * tb + 3; ++ks) {
+      const int k = 4 * ks + lg, c = 16 * tb + lr;
+      const double bv = k <= c ? TB[k * 64 + c] : 0.0;
+      y = __builtin_amdgcn_mfma_f64_16x16x4f64(L[16 * ws + lr][k], bv, y, 0, 0, 0);
+    }
+    acc[tb] = y;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int tb = 0; tb < 4; ++tb)
+#pragma unroll
+    for (int x = 0; x < 4; ++x) L[16 * ws + acc_row_f64(lg, x)][16 * tb + lr] = acc[tb][x];
+  __syncthreads();
+  // T_AB = -T_A Y: tile (w, tb) over k-steps ks >= 4 w (T_A upper)
+#pragma unroll
+  for (int tb = 0; tb < 4; ++tb) acc[tb] = f64x4{0, 0, 0, 0};
+  for (int ks = 4 * ws; ks < 16; ++ks) {
+    const int i = 16 * ws + lr, m = 4 * ks + lg;
+    const double av = m >= i ? TA[i * 64 + m] : 0.0;
+#pragma unroll
+    for (int tb = 0; tb < 4; ++tb)
+      acc[tb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, L[m][16 * tb + lr], acc[tb], 0, 0, 0);
+  }
+  // fragments (g, ks) of T^T: T_AB for g >= 4, ks < 16 from the registers
+  // (tile (ks / 4, g - 4), register ks % 4); T_A and T_B from the scratch
+  double* F = Tb + kT128Off + lane;
+#pragma unroll
+  for (int tb = 0; tb < 4; ++tb)
+#pragma unroll
+    for (int x = 0; x < 4; ++x) F[(size_t)t128_frag(4 + tb, 4 * ws + x) * 64] = -acc[tb][x];
+  for (int g = 0; g < 8; ++g)
+    for (int ks = g < 4 ? 0 : 16; ks <= 4 * g + 3; ++ks) {
+      const int f = t128_frag(g, ks);
+      if ((f & 3) != ws) continue;
+      const int m = 4 * ks + lg, i = 16 * g + lr;   // T[m][i]
+      double v = 0.0;
+      if (m <= i) v = g < 4 ? TA[m * 64 + i] : TB[(m - 64) * 64 + (i - 64)];
+      F[(size_t)f * 64] = v;
+    }
+}
+
+// C <- C - V T^T V^T C for the 128 columns j .. j + 127 (V = [V_A V_B], T
+// from qr_t128_kernel) on columns j + 128 .. n_pad - 1, one pass over C
+// for two 64-column blocks.  (job, 64-column tile) workgroups, wave w owning
+// 16 columns.  W = V^T C (128 x 16 per wave) stays in registers: the MFMA
+// accumulator of v_mfma_f64_16x16x4 holds row lg + 4 i of its tile in
+// register i, which is also where the B operand of the k-step over rows 4 i
+// .. 4 i + 3 and the A operand of the transposed product expect it, so W is
+// multiplied by T^T in place (tiles from the last to the first, each new
+// tile only reading the old ones at or above it) and used directly as the
+// left factor of C - V W.  The 16-row V chunks are staged through LDS,
+// double-buffered; V_B (zero above row j + 64) is skipped where it vanishes.
+__global__ __launch_bounds__(256, 3) void qr_trailing128_kernel(int64_t njobs, int n_pad, int j,
+                                                                double* __restrict__ S,
+                                                                const double* __restrict__ T64) {
+  int64_t job;
+  int tile;
+  if (!xcd_job_tile(njobs, job, tile)) return;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int lr = lane & 15, lg = lane >> 4;
+  double* Sj = S + job * (size_t)n_pad * n_pad;
+  const int c0w = j + 128 + 64 * tile + 16 * wave;   // first column of this wave
+  __shared__ double Vs[2][16][129];
+  const bool active = c0w < n_pad;
+  const bool col_ok = (c0w + lr) < n_pad;
+  // V staging: thread t takes V column vd = t / 2, rows 8 (t % 2) .. + 7 of
+  // a chunk; the loads of the next chunk are issued before the products of
+  // the current one, the masking is done when they are stored
+  const int vd = tid >> 1, vr = 8 * (tid & 1);
+  const double* vbase = Sj + (size_t)(j + vd) * n_pad;
+  auto load_v = [&](int r0, double2 (&a)[4]) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) a[q] = *reinterpret_cast<const double2*>(vbase + r0 + vr + 2 * q);
+  };
+  auto store_v = [&](int r0, int buf, const double2 (&a)[4]) {
+    double v[8];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      v[2 * q] = a[q].x;
+      v[2 * q + 1] = a[q].y;
+    }
+    if (r0 < j + 128) {   // V is stored below the diagonal, 1 on it, 0 above
+      const int d = j + vd;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int rr = r0 + vr + q;
+        v[q] = rr > d ? v[q] : (rr == d ? 1.0 : 0.0);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) Vs[buf][vr + q][vd] = v[q];
+  };
+  const int nch = (n_pad - j) / 16;   // n_pad - j is a multiple of 32
+
+  // ---- phase 1: W = V^T C --------------------------------------------------
+  f64x4 w[8];
+#pragma unroll
+  for (int g = 0; g < 8; ++g) w[g] = f64x4{0, 0, 0, 0};
+  const double* cbase = Sj + (size_t)(col_ok ? c0w + lr : (active ? c0w : j + 128)) * n_pad + 4 * lg;
+  double2 va[4], cn[2];
+  load_v(j, va);
+  cn[0] = *reinterpret_cast<const double2*>(cbase + j);
+  cn[1] = *reinterpret_cast<const double2*>(cbase + j + 2);
+  for (int ch = 0; ch < nch; ++ch) {
+    const int r0 = j + 16 * ch, buf = ch & 1;
+    store_v(r0, buf, va);
+    const double cv[4] = {col_ok ? cn[0].x : 0.0, col_ok ? cn[0].y : 0.0, col_ok ? cn[1].x : 0.0,
+                          col_ok ? cn[1].y : 0.0};
+    if (ch + 1 < nch) {
+      load_v(r0 + 16, va);
+      cn[0] = *reinterpret_cast<const double2*>(cbase + r0 + 16);
+      cn[1] = *reinterpret_cast<const double2*>(cbase + r0 + 18);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int jj = 0; jj < 4; ++jj)
+#pragma unroll
+      for (int g = 0; g < 4; ++g)
+        w[g] = __builtin_amdgcn_mfma_f64_16x16x4f64(Vs[buf][4 * lg + jj][16 * g + lr], cv[jj], w[g], 0, 0, 0);
+    if (r0 + 16 > j + 64) {   // V_B has entries in this chunk (uniform)
+#pragma unroll
+      for (int jj = 0; jj < 4; ++jj)
+#pragma unroll
+        for (int g = 4; g < 8; ++g)
+          w[g] = __builtin_amdgcn_mfma_f64_16x16x4f64(Vs[buf][4 * lg + jj][16 * g + lr], cv[jj], w[g], 0, 0, 0);
+    }
+  }
+  // ---- phase 2: W <- T^T W in registers ------------------------------------
+  {
+    const double* Tf = T64 + job * kT64Stride + kT128Off + lane;
+#pragma unroll
+    for (int g = 7; g >= 0; --g) {
+      f64x4 e0 = {0, 0, 0, 0}, e1 = {0, 0, 0, 0};
+#pragma unroll
+      for (int ks = 0; ks <= 4 * g + 3; ks += 2) {
+        e0 = __builtin_amdgcn_mfma_f64_16x16x4f64(Tf[t128_frag(g, ks) * 64], w[ks >> 2][ks & 3], e0, 0, 0, 0);
+        e1 = __builtin_amdgcn_mfma_f64_16x16x4f64(Tf[t128_frag(g, ks + 1) * 64], w[(ks + 1) >> 2][(ks + 1) & 3],
+                                                  e1, 0, 0, 0);
+      }
+#pragma unroll
+      for (int x = 0; x < 4; ++x) w[g][x] = e0[x] + e1[x];
+      __builtin_amdgcn_sched_barrier(0);   // keep each tile's fragment loads with its products
+    }
+  }
+  // ---- phase 3: C <- C - V W -----------------------------------------------
+  // output tile C^T[c (16)][r (16)] = sum_i W^T[c][i] V^T[i][r]
+  int ccols[4];
+#pragma unroll
+  for (int x = 0; x < 4; ++x) {
+    const int c = c0w + acc_row_f64(lg, x);
+    ccols[x] = (active && c < n_pad) ? c : -1;
+  }
+  double* cp[4];
+#pragma unroll
+  for (int x = 0; x < 4; ++x) cp[x] = Sj + (size_t)(ccols[x] >= 0 ? ccols[x] : j + 128) * n_pad + lr;
+  double cold[4];
+  load_v(j, va);
+#pragma unroll
+  for (int x = 0; x < 4; ++x) cold[x] = cp[x][j];
+  __syncthreads();   // every wave is done with the phase-1 V chunks
+  for (int ch = 0; ch < nch; ++ch) {
+    const int r0 = j + 16 * ch, buf = ch & 1;
+    store_v(r0, buf, va);
+    double cc[4];
+#pragma unroll
+    for (int x = 0; x < 4; ++x) cc[x] = cold[x];
+    if (ch + 1 < nch) {
+      load_v(r0 + 16, va);
+#pragma unroll
+      for (int x = 0; x < 4; ++x) cold[x] = cp[x][r0 + 16];
+    }
+    __syncthreads();
+    f64x4 a = {0, 0, 0, 0}, b = {0, 0, 0, 0};
+#pragma unroll
+    for (int ks = 0; ks < 16; ks += 2) {
+      a = __builtin_amdgcn_mfma_f64_16x16x4f64(w[ks >> 2][ks & 3], Vs[buf][lr][4 * ks + lg], a, 0, 0, 0);
+      b = __builtin_amdgcn_mfma_f64_16x16x4f64(w[(ks + 1) >> 2][(ks + 1) & 3], Vs[buf][lr][4 * ks + 4 + lg], b, 0,
+                                               0, 0);
+    }
+    if (r0 + 16 > j + 64) {
+#pragma unroll
+      for (int ks = 16; ks < 32; ks += 2) {
+        a = __builtin_amdgcn_mfma_f64_16x16x4f64(w[ks >> 2][ks & 3], Vs[buf][lr][4 * ks + lg], a, 0, 0, 0);
+        b = __builtin_amdgcn_mfma_f64_16x16x4f64(w[(ks + 1) >> 2][(ks + 1) & 3], Vs[buf][lr][4 * ks + 4 + lg], b, 0,
+                                                 0, 0);
+      }
+    }
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+      if (ccols[x] >= 0) cp[x][r0] = cc[x] - (a[x] + b[x]);
   }
 }
 
@@ -982,23 +1290,35 @@ template <int NT, int MAXQ, int PW>
 static hipError_t qr_factor_t(int64_t njobs, int n_pad, double* S, double* Tws, bool keep_T, int32_t* colmap,
                               double* colnorm, double* T64, hipStream_t stream) {
   if (PW == 32 && !colmap && T64) {
-    // 64-column blocks: T of every 32-column panel at (j / 32) * 1024 when
-    // kept, else two slots per job; T64 holds 4096 doubles per job
+    // Steps of 128 columns, each two 64-column blocks A (j .. j + 63) and B
+    // (j + 64 .. j + 127) of two 32-column panels: A is factored and
+    // applied to B's columns only, B is factored, and both are applied to
+    // the rest in one pass (T of the 128 columns from the two 64-column
+    // T).  T of every 32-column panel at (c / 32) * 1024 when kept, else two
+    // slots per job; T64 holds kQrBlockScratch doubles per job.
     const int64_t ts = keep_T ? (int64_t)n_pad * 32 : 2048;
-    for (int j = 0; j < n_pad; j += 64) {
-      const int64_t o1 = keep_T ? (int64_t)(j / 32) * 1024 : 0, o2 = keep_T ? o1 + 1024 : 1024;
-      launch_panel32( dim3((unsigned)njobs), dim3(256), 0, stream, n_pad, j, S, Tws, ts, o1,
-                         (const int32_t*)nullptr);
-      if (j + 32 >= n_pad) break;
-      hipLaunchKernelGGL(qr_trailing32_kernel, dim3(1, (unsigned)njobs), dim3(256), 0, stream, n_pad, j, j + 64, S,
-                         (const double*)Tws, ts, o1, (const int32_t*)nullptr, (double*)nullptr);
-      launch_panel32( dim3((unsigned)njobs), dim3(256), 0, stream, n_pad, j + 32, S, Tws, ts, o2,
-                         (const int32_t*)nullptr);
-      if (j + 64 >= n_pad) break;
-      hipLaunchKernelGGL(qr_t64_kernel, dim3((unsigned)njobs), dim3(256), 0, stream, n_pad, j, (const double*)S,
-                         (const double*)Tws, ts, o1, o2, T64);
-      hipLaunchKernelGGL(qr_trailing64_kernel, dim3(ceil_div(n_pad - j - 64, 64), (unsigned)njobs), dim3(256), 0,
-                         stream, n_pad, j, S, (const double*)T64);
+    auto block64 = [&](int c, double* Tslot) -> bool {   // false: the matrix ends inside the block
+      const int64_t o1 = keep_T ? (int64_t)(c / 32) * 1024 : 0, o2 = keep_T ? o1 + 1024 : 1024;
+      launch_panel32(dim3((unsigned)njobs), dim3(256), 0, stream, n_pad, c, S, Tws, ts, o1, (const int32_t*)nullptr);
+      if (c + 32 >= n_pad) return false;
+      hipLaunchKernelGGL(qr_trailing32_kernel, xcd_tile_grid(1, njobs), dim3(256), 0, stream, njobs, n_pad, c, c + 64,
+                         S, (const double*)Tws, ts, o1, (const int32_t*)nullptr, (double*)nullptr);
+      launch_panel32(dim3((unsigned)njobs), dim3(256), 0, stream, n_pad, c + 32, S, Tws, ts, o2,
+                     (const int32_t*)nullptr);
+      if (c + 64 >= n_pad) return false;
+      hipLaunchKernelGGL(qr_t64_kernel, dim3((unsigned)njobs), dim3(256), 0, stream, n_pad, c, (const double*)S,
+                         (const double*)Tws, ts, o1, o2, Tslot);
+      return true;
+    };
+    for (int j = 0; j < n_pad; j += 128) {
+      if (!block64(j, T64)) break;
+      hipLaunchKernelGGL(qr_trailing64_kernel, xcd_tile_grid(1, njobs), dim3(256), 0, stream, njobs, n_pad, j,
+                         min(j + 128, n_pad), S, (const double*)T64);
+      if (!block64(j + 64, T64 + 4096)) break;
+      hipLaunchKernelGGL(qr_t128_kernel, dim3((unsigned)njobs), dim3(256), 0, stream, n_pad, j, (const double*)S,
+                         T64);
+      hipLaunchKernelGGL(qr_trailing128_kernel, xcd_tile_grid(ceil_div(n_pad - j - 128, 64), njobs), dim3(256), 0,
+                         stream, njobs, n_pad, j, S, (const double*)T64);
     }
     return hipGetLastError();
   }
@@ -1018,8 +1338,8 @@ static hipError_t qr_factor_t(int64_t njobs, int n_pad, double* S, double* Tws, 
     const int rest = n_pad - j - PW;
     if (rest > 0) {
       if (PW == 32)
-        hipLaunchKernelGGL(qr_trailing32_kernel, dim3(ceil_div(rest, 64), (unsigned)njobs), dim3(256), 0, stream,
-                           n_pad, j, n_pad, S, Tws, t_stride, t_off, (const int32_t*)colmap,
+        hipLaunchKernelGGL(qr_trailing32_kernel, xcd_tile_grid(ceil_div(rest, 64), njobs), dim3(256), 0, stream,
+                           njobs, n_pad, j, n_pad, S, Tws, t_stride, t_off, (const int32_t*)colmap,
                            colmap ? colnorm : nullptr);
       else
         hipLaunchKernelGGL((qr_trailing_kernel<PW>), dim3(ceil_div(rest, 64), (unsigned)njobs), dim3(256), 0, stream,
@@ -1032,8 +1352,8 @@ static hipError_t qr_factor_t(int64_t njobs, int n_pad, double* S, double* Tws, 
   return hipGetLastError();
 }
 
-// T64 (4096 doubles per job, or NULL): scratch that enables the 64-column
-// blocks when the columns are not re-ordered (n_pad <= 1024).
+// T64 (kQrBlockScratch doubles per job, or NULL): scratch that enables the
+// 64-column blocks when the columns are not re-ordered (n_pad <= 1024).
 static hipError_t qr_factor(int64_t njobs, int n_pad, double* S, double* Tws, bool keep_T, int32_t* colmap,
                             double* colnorm, hipStream_t stream, double* T64 = nullptr) {
   if (n_pad <= 1024) return qr_factor_t<256, 4, 32>(njobs, n_pad, S, Tws, keep_T, colmap, colnorm, T64, stream);
@@ -1092,12 +1412,11 @@ hipError_t run_qr3_precondition(int64_t njobs, int n, int D, int n_pad, const do
   if (e != hipSuccess) return e;
   const dim3 rg(n_pad / 32, n_pad / 32, (unsigned)njobs);
   hipLaunchKernelGGL(r_rows_kernel, rg, dim3(256), 0, stream, n_pad, S1, W1, (const int32_t*)colmap);
-  // the second and third QR do not re-order columns: 64-column blocks, with
-  // Tws1 (free after the first QR) as scratch for the block T factors
-  e = qr_factor(njobs, n_pad, W1, Tws2, true, nullptr, nullptr, stream, Tws1);
+  // (n_pad > 1024: 8-column panels throughout, no block T scratch)
+  e = qr_factor(njobs, n_pad, W1, Tws2, true, nullptr, nullptr, stream, nullptr);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(r_rows_kernel, rg, dim3(256), 0, stream, n_pad, W1, W2, (const int32_t*)nullptr);
-  e = qr_factor(njobs, n_pad, W2, Tws1, false, nullptr, nullptr, stream, Tws1 + (size_t)njobs * 2048);
+  e = qr_factor(njobs, n_pad, W2, Tws1, false, nullptr, nullptr, stream, nullptr);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(r_rows_kernel, rg, dim3(256), 0, stream, n_pad, W2, S1, (const int32_t*)nullptr);
   *rows = S1;
@@ -1114,7 +1433,7 @@ hipError_t run_qr3_precondition(int64_t njobs, int n, int D, int n_pad, const do
 // five) at the cost of one more 64-column QR.
 // Q2 stays in W1 with its panel T factors in Tws2, Q4 in S1 with its T
 // factors in Tws4 (n_pad * 32 doubles per job each); the first, third and
-// fifth QR use Tscr (6144 doubles per job) for their T factors.  The rows of
+// fifth QR use Tscr (kQrTscr doubles per job) for their T factors.  The rows of
 // R5 end in W3; W2 is free afterwards.
 hipError_t run_qr5_precondition(int64_t njobs, int n, int D, int n_pad, const double* T, const int32_t* src,
                                 const int32_t* split, int32_t* perm, int32_t* iperm, double* S1, double* W1, double* Tws2,

@@ -137,6 +137,12 @@ hipError_t run_deflate(int64_t njobs, int n_pad, const double* Win, double* Wout
 // and is overwritten by V and R, Tws (1024 per job) is scratch, and W
 // receives the rows of R.  split 2 = plain row-major n x n matrices.
 constexpr int kQrMaxN = 4096;
+// Scratch of the blocked QR path per job: two 64 x 64 T factors and the
+// 128 x 128 T as 144 MFMA fragments of 64 doubles.
+constexpr int64_t kQrBlockScratch = 8192 + 144 * 64;
+// Tscr of the five-QR preconditioning per job: two 32 x 32 panel T slots and
+// the blocked-path scratch.
+constexpr int64_t kQrTscr = 2048 + kQrBlockScratch;
 hipError_t run_qr_precondition(int64_t njobs, int n, int D, int n_pad, const double* T, const int32_t* src,
                                const int32_t* split, int32_t* perm, int32_t* iperm, double* S, double* Tws, double* W,
                                hipStream_t stream);
@@ -144,8 +150,7 @@ hipError_t launch_iota(int64_t njobs, int n_pad, int32_t* perm, hipStream_t stre
 // Three-QR preconditioning (see k_qr.hip): *rows receives the buffer with
 // the rows of R3 (S1); W1 keeps Q2 (V) and Tws2 its panel T factors
 // (n_pad * 32 doubles per job).  Tws1 (n_pad * 32 doubles per job) is
-// scratch: the first QR's panel T, then the block T factors of the second
-// and third (6144 doubles per job).  colmap / colnorm: n_pad int32 / doubles
+// scratch for the panel T factors of the first and third QR.  colmap / colnorm: n_pad int32 / doubles
 // per job (the column re-ordering of the first QR, n_pad <= 1024; NULL:
 // static order only).
 hipError_t run_qr3_precondition(int64_t njobs, int n, int D, int n_pad, const double* T, const int32_t* src,
@@ -154,7 +159,7 @@ hipError_t run_qr3_precondition(int64_t njobs, int n, int D, int n_pad, const do
                                 hipStream_t stream);
 // Five-QR preconditioning (see k_qr.hip; n_pad <= 1024): the rows of R5 in
 // W3; Q2 in W1 / Tws2, Q4 in S1 / Tws4 (n_pad * 32 doubles per job each);
-// Tscr: 6144 doubles per job of scratch; W2 is free afterwards.
+// Tscr: kQrTscr doubles per job of scratch; W2 is free afterwards.
 hipError_t run_qr5_precondition(int64_t njobs, int n, int D, int n_pad, const double* T, const int32_t* src,
                                 const int32_t* split, int32_t* perm, int32_t* iperm, double* S1, double* W1, double* Tws2,
                                 double* W2, double* Tws4, double* W3, double* Tscr, int32_t* colmap, double* colnorm,
