@@ -39,7 +39,7 @@ __global__ __launch_bounds__(256) void jacobi_round_kernel(double* __restrict__ 
   const int job = blockIdx.y;
   if (!active[job]) return;
   // rows beyond the job's active blocks sit below the noise floor and stay
-  // as they are (see deflate_rows_kernel)
+  // as they are (see deflate_plan_kernel)
   const int nb = nb_job ? nb_job[job] : nb_all;
   const int pair = (int)((blockIdx.x + blockIdx.y) % gridDim.x);   // XCD balance (see jacobi_round64_kernel)
   if (round >= nb - 1 || pair >= nb / 2) return;
