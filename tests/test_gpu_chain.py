@@ -59,8 +59,14 @@ def align_gauge(Tg, To):
     return np.einsum("abce,a,b,c,e->abce", Tg, s, t, s, t)
 
 
+# k = 9, 12, 13, 14, 20: steady unfoldings with n_pad = 96, 160, 192, 224,
+# 416, which end the 128-column steps of the QR preconditioning after one
+# panel, one 64-column block, one and a half blocks, or several full steps
 @pytest.mark.parametrize("k,n_steps,beta,h,dtype", [(4, 6, BETA_C, 0.0, "f64"), (8, 8, BETA_C, 0.0, "f64"),
-                                                    (6, 7, 0.42, 0.1, "f64"), (16, 6, 0.35, 0.05, "f64")])
+                                                    (6, 7, 0.42, 0.1, "f64"), (16, 6, 0.35, 0.05, "f64"),
+                                                    (9, 6, BETA_C, 0.0, "f64"), (12, 6, 0.42, 0.1, "f64"),
+                                                    (13, 6, BETA_C, 0.0, "f64"), (14, 6, 0.35, 0.05, "f64"),
+                                                    (20, 6, BETA_C, 0.0, "f64")])
 def test_shared_chain_matches_oracle(k, n_steps, beta, h, dtype):
     torch, m = need_gpu()
     log(f"shared chain k={k} steps={n_steps} beta={beta} h={h}")
