@@ -1070,9 +1070,12 @@ __global__ __launch_bounds__(256) void qr_t128_kernel(int n_pad, int j, const do
 // tile only reading the old ones at or above it) and used directly as the
 // left factor of C - V W.  The 16-row V chunks are staged through LDS,
 // double-buffered; V_B (zero above row j + 64) is skipped where it vanishes.
+// lower_zero: every column c of C is still zero above row c (the first step
+// on a lower triangular matrix); chunks of V^T C above a wave's columns are
+// then skipped.
 __global__ __launch_bounds__(256, 3) void qr_trailing128_kernel(int64_t njobs, int n_pad, int j,
                                                                 double* __restrict__ S,
-                                                                const double* __restrict__ T64) {
+                                                                const double* __restrict__ T64, int lower_zero) {
   int64_t job;
   int tile;
   if (!xcd_job_tile(njobs, job, tile)) return;
@@ -1121,6 +1124,7 @@ __global__ __launch_bounds__(256, 3) void qr_trailing128_kernel(int64_t njobs, i
   load_v(j, va);
   cn[0] = *reinterpret_cast<const double2*>(cbase + j);
   cn[1] = *reinterpret_cast<const double2*>(cbase + j + 2);
+  const int zero_below = lower_zero ? c0w : 0;   // rows < zero_below of this wave's columns are zero
   for (int ch = 0; ch < nch; ++ch) {
     const int r0 = j + 16 * ch, buf = ch & 1;
     store_v(r0, buf, va);
@@ -1128,10 +1132,13 @@ __global__ __launch_bounds__(256, 3) void qr_trailing128_kernel(int64_t njobs, i
                           col_ok ? cn[1].y : 0.0};
     if (ch + 1 < nch) {
       load_v(r0 + 16, va);
-      cn[0] = *reinterpret_cast<const double2*>(cbase + r0 + 16);
-      cn[1] = *reinterpret_cast<const double2*>(cbase + r0 + 18);
+      if (r0 + 32 > zero_below) {
+        cn[0] = *reinterpret_cast<const double2*>(cbase + r0 + 16);
+        cn[1] = *reinterpret_cast<const double2*>(cbase + r0 + 18);
+      }
     }
     __syncthreads();
+    if (r0 + 16 <= zero_below) continue;   // C vanishes in this chunk (uniform per wave)
 #pragma unroll
     for (int jj = 0; jj < 4; ++jj)
 #pragma unroll
@@ -1253,7 +1260,9 @@ __global__ __launch_bounds__(256) void resort_cols_kernel(int n_pad, int j0, con
 }
 
 // W[r][c] = R[r][c] = S[colmap[c]][r] for r <= c, else 0 (rows of R for the
-// Jacobi; colmap NULL: identity).
+// Jacobi or the next QR; colmap NULL: identity).  One 32 x 32 tile per
+// workgroup, transposed through LDS; tiles wholly below the diagonal are
+// written as zeros without reading S.
 __global__ void r_rows_kernel(int n_pad, const double* __restrict__ S, double* __restrict__ W,
                               const int32_t* __restrict__ colmap) {
   const int64_t job = blockIdx.z;
@@ -1261,20 +1270,21 @@ __global__ void r_rows_kernel(int n_pad, const double* __restrict__ S, double* _
   const size_t per = (size_t)n_pad * n_pad;
   const int bx = blockIdx.x * 32, by = blockIdx.y * 32;   // bx: column c block, by: row r block
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8 threads
+  double* Wj = W + job * per;
+  if (by > bx + 31) {   // r > c everywhere (uniform)
+    for (int yy = ty; yy < 32; yy += 8) Wj[(size_t)(by + yy) * n_pad + bx + tx] = 0.0;
+    return;
+  }
   const int32_t* cm = colmap ? colmap + job * n_pad : nullptr;
   for (int yy = ty; yy < 32; yy += 8)
     tile[yy][tx] = S[job * per + (size_t)(cm ? cm[bx + yy] : bx + yy) * n_pad + by + tx];  // [c][r]
   __syncthreads();
   for (int yy = ty; yy < 32; yy += 8) {
     const int r = by + yy, c = bx + tx;
-    W[job * per + (size_t)r * n_pad + c] = (r <= c) ? tile[tx][yy] : 0.0;
+    Wj[(size_t)r * n_pad + c] = (r <= c) ? tile[tx][yy] : 0.0;
   }
 }
 
-// Blocked Householder QR of the column-stored matrices S (in place: V below
-// the diagonal, R on and above).  keep_T: T of panel p is kept at
-// Tws[job * (n_pad/32) * 1024 + p * 1024], otherwise every panel reuses
-// Tws[job * 1024].
 // Blocked Householder QR of the column-stored matrices S (in place: V below
 // the diagonal, R on and above).  Panels of PW columns: 32 for n_pad <= 1024
 // (4 rows per thread in 256 threads), 8 for n_pad <= 4096 (8 rows per thread
@@ -1288,7 +1298,7 @@ __global__ void r_rows_kernel(int n_pad, const double* __restrict__ S, double* _
 // through the map, which ends as the logical -> stored column permutation).
 template <int NT, int MAXQ, int PW>
 static hipError_t qr_factor_t(int64_t njobs, int n_pad, double* S, double* Tws, bool keep_T, int32_t* colmap,
-                              double* colnorm, double* T64, hipStream_t stream) {
+                              double* colnorm, double* T64, bool lower, hipStream_t stream) {
   if (PW == 32 && !colmap && T64) {
     // Steps of 128 columns, each two 64-column blocks A (j .. j + 63) and B
     // (j + 64 .. j + 127) of two 32-column panels: A is factored and
@@ -1318,7 +1328,7 @@ static hipError_t qr_factor_t(int64_t njobs, int n_pad, double* S, double* Tws, 
       hipLaunchKernelGGL(qr_t128_kernel, dim3((unsigned)njobs), dim3(256), 0, stream, n_pad, j, (const double*)S,
                          T64);
       hipLaunchKernelGGL(qr_trailing128_kernel, xcd_tile_grid(ceil_div(n_pad - j - 128, 64), njobs), dim3(256), 0,
-                         stream, njobs, n_pad, j, S, (const double*)T64);
+                         stream, njobs, n_pad, j, S, (const double*)T64, (int)(lower && j == 0));
     }
     return hipGetLastError();
   }
@@ -1354,10 +1364,12 @@ static hipError_t qr_factor_t(int64_t njobs, int n_pad, double* S, double* Tws, 
 
 // T64 (kQrBlockScratch doubles per job, or NULL): scratch that enables the
 // 64-column blocks when the columns are not re-ordered (n_pad <= 1024).
+// lower: S is lower triangular on entry (the transpose of an R factor).
 static hipError_t qr_factor(int64_t njobs, int n_pad, double* S, double* Tws, bool keep_T, int32_t* colmap,
-                            double* colnorm, hipStream_t stream, double* T64 = nullptr) {
-  if (n_pad <= 1024) return qr_factor_t<256, 4, 32>(njobs, n_pad, S, Tws, keep_T, colmap, colnorm, T64, stream);
-  return qr_factor_t<512, 8, 8>(njobs, n_pad, S, Tws, keep_T, nullptr, nullptr, nullptr, stream);
+                            double* colnorm, hipStream_t stream, double* T64 = nullptr, bool lower = false) {
+  if (n_pad <= 1024)
+    return qr_factor_t<256, 4, 32>(njobs, n_pad, S, Tws, keep_T, colmap, colnorm, T64, lower, stream);
+  return qr_factor_t<512, 8, 8>(njobs, n_pad, S, Tws, keep_T, nullptr, nullptr, nullptr, false, stream);
 }
 
 static hipError_t order_and_unfold(int64_t njobs, int n, int D, int n_pad, const double* T, const int32_t* src,
@@ -1448,16 +1460,16 @@ hipError_t run_qr5_precondition(int64_t njobs, int n, int D, int n_pad, const do
   const dim3 rg(n_pad / 32, n_pad / 32, (unsigned)njobs);
   double* T64 = Tscr + (size_t)njobs * 2048;
   hipLaunchKernelGGL(r_rows_kernel, rg, dim3(256), 0, stream, n_pad, S1, W1, (const int32_t*)colmap);
-  e = qr_factor(njobs, n_pad, W1, Tws2, true, nullptr, nullptr, stream, Tscr);
+  e = qr_factor(njobs, n_pad, W1, Tws2, true, nullptr, nullptr, stream, Tscr, true);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(r_rows_kernel, rg, dim3(256), 0, stream, n_pad, W1, W2, (const int32_t*)nullptr);
-  e = qr_factor(njobs, n_pad, W2, Tscr, false, nullptr, nullptr, stream, T64);
+  e = qr_factor(njobs, n_pad, W2, Tscr, false, nullptr, nullptr, stream, T64, true);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(r_rows_kernel, rg, dim3(256), 0, stream, n_pad, W2, S1, (const int32_t*)nullptr);
-  e = qr_factor(njobs, n_pad, S1, Tws4, true, nullptr, nullptr, stream, Tscr);
+  e = qr_factor(njobs, n_pad, S1, Tws4, true, nullptr, nullptr, stream, Tscr, true);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(r_rows_kernel, rg, dim3(256), 0, stream, n_pad, S1, W2, (const int32_t*)nullptr);
-  e = qr_factor(njobs, n_pad, W2, Tscr, false, nullptr, nullptr, stream, T64);
+  e = qr_factor(njobs, n_pad, W2, Tscr, false, nullptr, nullptr, stream, T64, true);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(r_rows_kernel, rg, dim3(256), 0, stream, n_pad, W2, W3, (const int32_t*)nullptr);
   return hipGetLastError();
