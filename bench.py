@@ -41,17 +41,19 @@ JACOBI_SRC = os.path.join(ROOT, "paper_1710_03757_amd", "csrc", "k_jacobi.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "jacobi_traffic_k32_batch256.json")
 
 
-def measured_traffic(k, batch):
-    """HBM bytes per launch of the Jacobi rotation kernel from the committed
+def measured_traffic(k, batch, parts):
+    """HBM bytes per dispatch of the Jacobi rotation kernel from the committed
     rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE summary, if it was taken on the
-    same kernel source and workload shape; otherwise None."""
+    same kernel source and workload shape (batch split in the same number of
+    parts); otherwise None."""
     import hashlib
     try:
         rec = json.load(open(TRAFFIC_FILE))
         sha = hashlib.sha256(open(JACOBI_SRC, "rb").read()).hexdigest()
     except (OSError, ValueError):
         return None
-    if rec.get("source_sha256") != sha or rec.get("k") != k or rec.get("batch") != batch:
+    if rec.get("source_sha256") != sha or rec.get("k") != k or rec.get("batch") != batch or \
+            rec.get("parts", 1) != parts:
         return None
     return rec
 
@@ -177,28 +179,38 @@ def main():
     ms_per_step = ms_total / args.steps
     value = B * args.steps / (ms_total / 1e3)
 
+    parts = p1["parts"]
     jl = p1["jacobi_launches"] - p0["jacobi_launches"]
     jms = p1["jacobi_ms"] - p0["jacobi_ms"]
+    jbusy = p1["jacobi_busy_ms"] - p0["jacobi_busy_ms"]
     gl = p1["gemm_launches"] - p0["gemm_launches"]
     gms = p1["gemm_ms"] - p0["gemm_ms"]
-    # dominant kernel: Jacobi rotation kernel; algorithmic decomposition flops
-    # of the timed steps spread over its launches
+    gbusy = p1["gemm_busy_ms"] - p0["gemm_busy_ms"]
+    # dominant kernel: the Jacobi rotation kernel.  Every round is one
+    # dispatch per part and the parts' dispatches run concurrently, so a
+    # round's duration is the union of its dispatches' intervals: achieved =
+    # algorithmic decomposition flops of the timed steps (per round x rounds)
+    # over the union of all Jacobi dispatch intervals.  avg_launch_ms is the
+    # mean duration of one dispatch (what rocprofv3 reports per dispatch).
     alg = decomposition_flops(k) * B * args.steps
     avg_launch_ms = jms / max(jl, 1)
-    achieved = alg / max(jl, 1) / (avg_launch_ms / 1e3) / 1e12 if jl else None
-    tr = measured_traffic(k, B)
+    rounds = jl / max(parts, 1)
+    achieved = alg / (jbusy / 1e3) / 1e12 if jbusy > 0 else None
+    tr = measured_traffic(k, B, parts)
     traffic = None
     if tr:
         traffic = tr["fetch_bytes_per_launch"] + tr["write_bytes_per_launch"]
     roofline = {"bound": "mfma", "kernel": JACOBI_KERNEL, "achieved": achieved, "peak": PEAK_TFLOPS["f64"],
                 "unit": "TFLOP/s", "frac": (achieved / PEAK_TFLOPS["f64"]) if achieved else None, "traffic": traffic,
-                "traffic_unit": "bytes per launch (HBM, FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-                "traffic_rate_TBs": (traffic / (avg_launch_ms / 1e3) / 1e12) if (traffic and avg_launch_ms) else None,
-                "avg_launch_ms": avg_launch_ms, "launches": jl,
-                "share_of_step_time": jms / ms_total if ms_total else None}
+                "traffic_unit": "bytes per dispatch (HBM, FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                "traffic_rate_TBs": (traffic * jl / (jbusy / 1e3) / 1e12) if (traffic and jbusy > 0) else None,
+                "avg_launch_ms": avg_launch_ms, "launches": jl, "parts": parts,
+                "avg_round_ms": jbusy / rounds if rounds else None, "busy_ms": jbusy,
+                "share_of_step_time": jbusy / ms_total if ms_total else None}
     galg = gemm_flops(k) * B * args.steps
-    gemm = {"kernel": f"gemm_tn_kernel<{args.dtype}>", "achieved": galg / (gms / 1e3) / 1e12 if gms else None,
-            "peak": PEAK_TFLOPS[args.dtype], "unit": "TFLOP/s", "avg_launch_ms": gms / max(gl, 1), "launches": gl}
+    gemm = {"kernel": f"gemm_tn_kernel<{args.dtype}>", "achieved": galg / (gbusy / 1e3) / 1e12 if gbusy > 0 else None,
+            "peak": PEAK_TFLOPS[args.dtype], "unit": "TFLOP/s", "avg_launch_ms": gms / max(gl, 1), "launches": gl,
+            "busy_ms": gbusy}
     gemm["frac"] = gemm["achieved"] / gemm["peak"] if gemm["achieved"] else None
 
     # whole-step roofline fraction: ideal time per sample-step at the peaks

@@ -89,6 +89,8 @@ enum mctrg_dtype { MCTRG_F64 = 0, MCTRG_F32 = 1, MCTRG_BF16 = 2, MCTRG_FP8_E4M3 
 #define MCTRG_ASYNC  2u   /* return without synchronising hip_stream          */
 #define MCTRG_PROFILE 4u  /* chains: time the decomposition and GEMM kernels  */
                           /* with HIP events (see mctrg_chain_get_profile)     */
+#define MCTRG_ONE_STREAM 8u  /* run every wave as one part on hip_stream (see */
+                             /* "Parts" below)                                  */
 
 typedef struct mctrg_tensor_set mctrg_tensor_set;  /* opaque, library-owned */
 
@@ -113,7 +115,7 @@ typedef struct {
   int32_t mode;            /* enum mctrg_mode                                         */
   int32_t contract_dtype;  /* enum mctrg_dtype                                        */
   double tau_null;         /* singular values <= tau_null * s_1 count as zero (1e-11) */
-  uint32_t flags;          /* MCTRG_RECORD | MCTRG_ASYNC                              */
+  uint32_t flags;          /* MCTRG_RECORD | MCTRG_ASYNC | MCTRG_PROFILE | ONE_STREAM */
   int32_t* record_buf;     /* device, n_samples * n_steps * (4 + 2k) int32, or NULL:  */
                            /*   per step: cA, cB (candidates), kA, kB (kept),        */
                            /*   selA[k], selB[k] (kept indices into the descending    */
@@ -131,7 +133,16 @@ void mctrg_default_config(mctrg_run_config* cfg);
  * Kept counts below the capacity are zero-padded. */
 int32_t mctrg_capacity_dim(int32_t d0, int32_t k, int32_t n_steps);
 
-/* Run n_samples independent Monte Carlo samples (Section III).
+/* Parts: a wave of two or more samples runs as two parts, the first half of
+ * its samples and the rest, each with its own device workspace and stream
+ * (the first on hip_stream, the second on a non-blocking stream of default
+ * priority that the library creates and destroys), advanced concurrently by
+ * two host threads, so that the kernels of one part fill the GPU while the
+ * other waits on a convergence count or runs latency-bound QR panels.
+ * hip_stream waits for both parts before a call returns or completes.
+ * Results do not depend on the split; MCTRG_ONE_STREAM keeps one part.
+ *
+ * Run n_samples independent Monte Carlo samples (Section III).
  *   group_of_sample: host, n_samples group indices, or NULL (all group 0)
  *   k_of_sample:     host, n_samples kept counts, or NULL (all cfg->k);
  *                    samples are bucketed by k internally
@@ -192,6 +203,10 @@ typedef struct {
                                summed over all decompositions of the step       */
   int32_t last_active[64];  /* last step, per sweep: decompositions still
                                rotating after that sweep                        */
+  double jacobi_busy_ms;    /* union of the Jacobi launch intervals over all
+                               parts (launches of two parts overlap in time)     */
+  double gemm_busy_ms;      /* the same for the GEMMs                            */
+  int32_t parts;            /* parts of the chain (1 or 2)                       */
 } mctrg_chain_profile;
 /* Timings are collected only when cfg->flags has MCTRG_PROFILE. */
 int mctrg_chain_get_profile(const mctrg_chain* ch, mctrg_chain_profile* out);

@@ -30,7 +30,7 @@ OK, EINVAL, ENOMEM, EDEVICE, ENUMERIC, EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 ISING_SITE, ISING_PLAQUETTE, USER = 0, 1, 2
 SHARED, INDEPENDENT, TOPK = 0, 1, 2
 F64, F32, BF16, FP8_E4M3 = 0, 1, 2, 3
-RECORD, ASYNC, PROFILE = 1, 2, 4
+RECORD, ASYNC, PROFILE, ONE_STREAM = 1, 2, 4, 8
 
 MODES = {"shared": SHARED, "independent": INDEPENDENT, "topk": TOPK}
 DTYPES = {"f64": F64, "f32": F32, "bf16": BF16, "fp8": FP8_E4M3}
@@ -61,7 +61,8 @@ class Estimate(ctypes.Structure):
 class ChainProfile(ctypes.Structure):
     _fields_ = [("jacobi_ms", ctypes.c_double), ("jacobi_launches", ctypes.c_int64), ("gemm_ms", ctypes.c_double),
                 ("gemm_launches", ctypes.c_int64), ("steps_done", ctypes.c_int32), ("last_sweeps", ctypes.c_int32),
-                ("last_pairs", ctypes.c_int32 * 64), ("last_active", ctypes.c_int32 * 64)]
+                ("last_pairs", ctypes.c_int32 * 64), ("last_active", ctypes.c_int32 * 64),
+                ("jacobi_busy_ms", ctypes.c_double), ("gemm_busy_ms", ctypes.c_double), ("parts", ctypes.c_int32)]
 
     def as_dict(self):
         d = {f: getattr(self, f) for f, _ in self._fields_}
@@ -224,8 +225,9 @@ class SampleResult:
 def run_samples(ts: TensorSet, n_samples: int, *, n_steps: int, k: int, mode="shared", dtype="f64",
                 seed: int = 0, sample_offset: int = 0, tau_null: float = 1e-11, groups=None,
                 ks=None, want_ln_c: bool = False, record: bool = False, want_tensor: bool = False,
-                async_: bool = False, out_sign=None, out_ln_abs_Z=None) -> SampleResult:
-    """mctrg_run_samples.  ``groups`` / ``ks``: host sequences (one per sample)."""
+                async_: bool = False, out_sign=None, out_ln_abs_Z=None, one_stream: bool = False) -> SampleResult:
+    """mctrg_run_samples.  ``groups`` / ``ks``: host sequences (one per sample).
+    ``one_stream``: run every wave as one part (MCTRG_ONE_STREAM)."""
     import numpy as np
     torch = _torch()
     cfg = default_config()
@@ -236,6 +238,8 @@ def run_samples(ts: TensorSet, n_samples: int, *, n_steps: int, k: int, mode="sh
     cfg.mode = MODES[mode] if isinstance(mode, str) else int(mode)
     cfg.contract_dtype = DTYPES[dtype] if isinstance(dtype, str) else int(dtype)
     cfg.tau_null = tau_null
+    if one_stream:
+        cfg.flags |= ONE_STREAM
     dev = torch.device("cuda", torch.cuda.current_device())
     sign = out_sign if out_sign is not None else torch.empty(n_samples, dtype=torch.int8, device=dev)
     ln = out_ln_abs_Z if out_ln_abs_Z is not None else torch.empty(n_samples, dtype=torch.float64, device=dev)
@@ -333,7 +337,8 @@ class Chain:
     """mctrg_chain_*: one wave of samples advanced step by step."""
 
     def __init__(self, ts: TensorSet, n_samples: int, *, n_steps: int, k: int, mode="shared", dtype="f64",
-                 seed: int = 0, sample_offset: int = 0, tau_null: float = 1e-11, groups=None, profile=False):
+                 seed: int = 0, sample_offset: int = 0, tau_null: float = 1e-11, groups=None, profile=False,
+                 one_stream=False):
         import numpy as np
         torch = _torch()
         cfg = default_config()
@@ -343,6 +348,8 @@ class Chain:
         cfg.tau_null = tau_null
         if profile:
             cfg.flags |= PROFILE
+        if one_stream:
+            cfg.flags |= ONE_STREAM
         g = None if groups is None else np.ascontiguousarray(groups, dtype=np.int32)
         self._ts = ts
         self.n_samples, self.n_steps = n_samples, n_steps

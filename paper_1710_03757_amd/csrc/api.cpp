@@ -11,7 +11,11 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <functional>
+#include <memory>
 #include <new>
+#include <system_error>
+#include <thread>
 #include <vector>
 
 #include "../../include/mctrg.h"
@@ -502,6 +506,132 @@ int chain_finish(Chain& c, int8_t* out_sign, double* out_ln, double* out_lnc, do
   return MCTRG_OK;
 }
 
+// A wave of samples advanced as up to two parts: each part is a Chain with its
+// own device memory and stream (part 0 on the caller's stream, part 1 on a
+// non-blocking stream of default priority created here), stepped by its own
+// host thread.  A part's host thread waits for the convergence count after
+// every Jacobi sweep, and its QR panels are latency-bound; meanwhile the
+// other part's kernels fill the GPU.  Per-sample results do not depend on the
+// split: every random draw is addressed by the global sample id and every
+// decomposition is independent.
+struct ChainParts {
+  int device = 0;
+  hipStream_t caller = nullptr;
+  std::vector<std::unique_ptr<Chain>> parts;
+  hipStream_t own = nullptr;   // stream of part 1
+  hipEvent_t ref = nullptr;    // common origin of the kernel timers
+  hipEvent_t done = nullptr;
+  ~ChainParts() {
+    parts.clear();   // frees the parts' device memory
+    if (own) (void)hipStreamDestroy(own);
+    if (ref) (void)hipEventDestroy(ref);
+    if (done) (void)hipEventDestroy(done);
+  }
+};
+
+// Starts the parts of samples [0, n) (groups, out_index and sids per
+// sample); configure sets a fresh Chain's configuration fields.
+int parts_start(ChainParts& cp, const std::function<void(Chain&)>& configure, const mctrg_tensor_set* ts,
+                const std::vector<int32_t>& groups, const std::vector<int64_t>& out_index,
+                const std::vector<int64_t>& sids, hipStream_t caller, bool one_part, bool profile) {
+  cp.caller = caller;
+  CKH(hipGetDevice(&cp.device));
+  const int64_t n = (int64_t)groups.size();
+  const int P = (!one_part && n >= 2) ? 2 : 1;
+  CKH(hipEventCreateWithFlags(&cp.done, hipEventDisableTiming));
+  if (profile) {
+    CKH(hipEventCreate(&cp.ref));
+    CKH(hipEventRecord(cp.ref, caller));
+  }
+  if (P > 1) {   // part 1 starts after the work already queued on the caller's stream
+    CKH(hipStreamCreateWithFlags(&cp.own, hipStreamNonBlocking));
+    CKH(hipEventRecord(cp.done, caller));
+    CKH(hipStreamWaitEvent(cp.own, cp.done, 0));
+  }
+  int64_t b = 0;
+  for (int p = 0; p < P; ++p) {
+    const int64_t e = (p + 1 == P) ? n : (n + 1) / 2;
+    std::unique_ptr<Chain> c(new (std::nothrow) Chain());
+    if (!c) return MCTRG_ENOMEM;
+    configure(*c);
+    c->st = p == 0 ? caller : cp.own;
+    c->nsamp = e - b;
+    c->sids.assign(sids.begin() + b, sids.begin() + e);
+    const std::vector<int32_t> g(groups.begin() + b, groups.begin() + e);
+    const std::vector<int64_t> oi(out_index.begin() + b, out_index.begin() + e);
+    const int rc = chain_start(*c, ts, g, oi);
+    if (rc != MCTRG_OK) return rc;
+    c->tj.ref = c->tg.ref = cp.ref;
+    cp.parts.push_back(std::move(c));
+    b = e;
+  }
+  return MCTRG_OK;
+}
+
+// The caller's stream waits for the work queued on the other parts' streams.
+int parts_join(ChainParts& cp) {
+  for (size_t p = 1; p < cp.parts.size(); ++p) {
+    CKH(hipEventRecord(cp.done, cp.parts[p]->st));
+    CKH(hipStreamWaitEvent(cp.caller, cp.done, 0));
+  }
+  return MCTRG_OK;
+}
+
+// n TRG steps on every part, part 0 on the calling thread and the others on
+// threads of their own (one after the other if a thread cannot be started).
+int parts_step(ChainParts& cp, int n) {
+  const int P = (int)cp.parts.size();
+  std::vector<int> rcs(P, MCTRG_OK);
+  auto run = [&](int p) {
+    if (p > 0 && hipSetDevice(cp.device) != hipSuccess) {
+      rcs[p] = MCTRG_EDEVICE;
+      return;
+    }
+    for (int i = 0; i < n && rcs[p] == MCTRG_OK; ++i) rcs[p] = chain_step(*cp.parts[p]);
+  };
+  std::vector<std::thread> th;
+  for (int p = 1; p < P; ++p) {
+    try {
+      th.emplace_back(run, p);
+    } catch (const std::system_error&) {
+      run(p);
+    }
+  }
+  run(0);
+  for (auto& t : th) t.join();
+  for (int p = 0; p < P; ++p)
+    if (rcs[p] != MCTRG_OK) return rcs[p];
+  return parts_join(cp);
+}
+
+int parts_finish(ChainParts& cp, int8_t* out_sign, double* out_ln, double* out_lnc, double* out_tensor) {
+  for (auto& c : cp.parts) {
+    const int rc = chain_finish(*c, out_sign, out_ln, out_lnc, out_tensor);
+    if (rc != MCTRG_OK) return rc;
+  }
+  return parts_join(cp);
+}
+
+// Length of the union of [begin, end) intervals.
+double union_ms(std::vector<std::pair<float, float>> v) {
+  std::sort(v.begin(), v.end());
+  double tot = 0.0;
+  bool open = false;
+  float lo = 0.0f, hi = 0.0f;
+  for (const auto& iv : v) {
+    if (open && iv.first <= hi) {
+      hi = std::max(hi, iv.second);
+    } else {
+      if (open) tot += hi - lo;
+      lo = iv.first;
+      hi = iv.second;
+      open = true;
+    }
+  }
+  if (open) tot += hi - lo;
+  return tot;
+}
+
 bool is_fin(double x) { return std::isfinite(x); }
 
 int validate_config(const mctrg_run_config* cfg) {
@@ -685,42 +815,46 @@ int mctrg_run_samples(mctrg_tensor_set* ts, const mctrg_run_config* cfg, int64_t
     wave = std::min<int64_t>(wave, (int64_t)members.size());
     for (size_t w0 = 0; w0 < members.size(); w0 += (size_t)wave) {
       const size_t w1 = std::min(members.size(), w0 + (size_t)wave);
-      Chain c;
-      c.st = st; c.mode = cfg->mode; c.dtype = cfg->contract_dtype; c.k = kb; c.n_steps = cfg->n_steps;
-      c.tau = cfg->tau_null; c.seed = cfg->seed; c.flags = cfg->flags; c.record = cfg->record_buf;
-      c.kmax_rec = cfg->k;
-      c.Dsched = probe.Dsched;
-      c.levels = probe.levels;
-      c.plaqs = probe.plaqs;
-      c.nsamp = (int64_t)(w1 - w0);
-      std::vector<int32_t> groups(c.nsamp);
-      std::vector<int64_t> out_index(c.nsamp);
-      for (int64_t s = 0; s < c.nsamp; ++s) {
+      const int64_t nw = (int64_t)(w1 - w0);
+      std::vector<int32_t> groups(nw);
+      std::vector<int64_t> out_index(nw), sids(nw);
+      for (int64_t s = 0; s < nw; ++s) {
         const int64_t i = members[w0 + s];
         groups[s] = group_of_sample ? group_of_sample[i] : 0;
         out_index[s] = i;
-        c.sids.push_back(cfg->sample_offset + i);
+        sids[s] = cfg->sample_offset + i;
       }
-      rc = chain_start(c, ts, groups, out_index);
+      auto configure = [&](Chain& c) {
+        c.mode = cfg->mode; c.dtype = cfg->contract_dtype; c.k = kb; c.n_steps = cfg->n_steps;
+        c.tau = cfg->tau_null; c.seed = cfg->seed; c.flags = cfg->flags; c.record = cfg->record_buf;
+        c.kmax_rec = cfg->k;
+        c.Dsched = probe.Dsched;
+        c.levels = probe.levels;
+        c.plaqs = probe.plaqs;
+      };
+      ChainParts cp;
+      rc = parts_start(cp, configure, ts, groups, out_index, sids, st, (cfg->flags & MCTRG_ONE_STREAM) != 0,
+                       false);
       if (rc != MCTRG_OK) return rc;
-      for (int s = 0; s < cfg->n_steps; ++s) {
-        rc = chain_step(c);
-        if (rc != MCTRG_OK) return rc;
-      }
-      rc = chain_finish(c, out_sign, out_ln_abs_Z, out_ln_c, cfg->out_tensor);
+      rc = parts_step(cp, cfg->n_steps);
+      if (rc != MCTRG_OK) return rc;
+      rc = parts_finish(cp, out_sign, out_ln_abs_Z, out_ln_c, cfg->out_tensor);
       if (rc != MCTRG_OK) return rc;
       if (hipStreamSynchronize(st) != hipSuccess) return MCTRG_EDEVICE;
-      std::vector<int8_t> sg(c.nsamp);
-      if (hipMemcpy(sg.data(), c.sign, c.nsamp, hipMemcpyDeviceToHost) != hipSuccess) return MCTRG_EDEVICE;
-      for (int8_t v : sg)
-        if (v == 0) any_fail = true;
+      for (auto& c : cp.parts) {
+        std::vector<int8_t> sg(c->nsamp);
+        if (hipMemcpy(sg.data(), c->sign, c->nsamp, hipMemcpyDeviceToHost) != hipSuccess) return MCTRG_EDEVICE;
+        for (int8_t v : sg)
+          if (v == 0) any_fail = true;
+      }
     }
   }
   return any_fail ? MCTRG_ENUMERIC : MCTRG_OK;
 }
 
 struct mctrg_chain {
-  Chain c;
+  ChainParts cp;
+  int n_steps = 0, steps = 0;
 };
 
 int mctrg_chain_create(mctrg_tensor_set* ts, const mctrg_run_config* cfg, int64_t n_samples,
@@ -734,59 +868,73 @@ int mctrg_chain_create(mctrg_tensor_set* ts, const mctrg_run_config* cfg, int64_
       if (group_of_sample[i] < 0 || group_of_sample[i] >= ts->ngroups) return MCTRG_EINVAL;
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess || dev != ts->device) return MCTRG_EINVAL;
+  Chain probe;
+  probe.mode = cfg->mode; probe.n_steps = cfg->n_steps;
+  probe.Dsched = schedule(ts->d0, cfg->k, cfg->n_steps);
+  if (probe.mode == MCTRG_INDEPENDENT && build_levels(probe) != MCTRG_OK) return MCTRG_EINVAL;
   mctrg_chain* ch = new (std::nothrow) mctrg_chain();
   if (!ch) return MCTRG_ENOMEM;
-  Chain& c = ch->c;
-  c.st = reinterpret_cast<hipStream_t>(hip_stream);
-  c.mode = cfg->mode; c.dtype = cfg->contract_dtype; c.k = cfg->k; c.n_steps = cfg->n_steps;
-  c.tau = cfg->tau_null; c.seed = cfg->seed; c.flags = cfg->flags & MCTRG_PROFILE; c.record = nullptr;
-  c.kmax_rec = cfg->k;
-  c.Dsched = schedule(ts->d0, cfg->k, cfg->n_steps);
-  if (c.mode == MCTRG_INDEPENDENT && build_levels(c) != MCTRG_OK) { delete ch; return MCTRG_EINVAL; }
-  c.nsamp = n_samples;
+  ch->n_steps = cfg->n_steps;
   std::vector<int32_t> groups(n_samples);
-  std::vector<int64_t> out_index(n_samples);
+  std::vector<int64_t> out_index(n_samples), sids(n_samples);
   for (int64_t i = 0; i < n_samples; ++i) {
     groups[i] = group_of_sample ? group_of_sample[i] : 0;
     out_index[i] = i;
-    c.sids.push_back(cfg->sample_offset + i);
+    sids[i] = cfg->sample_offset + i;
   }
-  rc = chain_start(c, ts, groups, out_index);
+  auto configure = [&](Chain& c) {
+    c.mode = cfg->mode; c.dtype = cfg->contract_dtype; c.k = cfg->k; c.n_steps = cfg->n_steps;
+    c.tau = cfg->tau_null; c.seed = cfg->seed; c.flags = cfg->flags & MCTRG_PROFILE; c.record = nullptr;
+    c.kmax_rec = cfg->k;
+    c.Dsched = probe.Dsched;
+    c.levels = probe.levels;
+    c.plaqs = probe.plaqs;
+  };
+  rc = parts_start(ch->cp, configure, ts, groups, out_index, sids, reinterpret_cast<hipStream_t>(hip_stream),
+                   (cfg->flags & MCTRG_ONE_STREAM) != 0, (cfg->flags & MCTRG_PROFILE) != 0);
   if (rc != MCTRG_OK) { delete ch; return rc; }
   *out = ch;
   return MCTRG_OK;
 }
 
 int mctrg_chain_step(mctrg_chain* ch, int32_t n) {
-  if (!ch || n < 0 || ch->c.step + n > ch->c.n_steps) return MCTRG_EINVAL;
-  for (int i = 0; i < n; ++i) {
-    int rc = chain_step(ch->c);
-    if (rc != MCTRG_OK) return rc;
-  }
+  if (!ch || n < 0 || ch->steps + n > ch->n_steps) return MCTRG_EINVAL;
+  const int rc = parts_step(ch->cp, n);
+  if (rc != MCTRG_OK) return rc;
+  ch->steps += n;
   return MCTRG_OK;
 }
 
 int mctrg_chain_finish(mctrg_chain* ch, int8_t* out_sign, double* out_ln_abs_Z, double* out_ln_c) {
   if (!ch || !out_sign || !out_ln_abs_Z) return MCTRG_EINVAL;
-  int rc = chain_finish(ch->c, out_sign, out_ln_abs_Z, out_ln_c, nullptr);
+  const int rc = parts_finish(ch->cp, out_sign, out_ln_abs_Z, out_ln_c, nullptr);
   if (rc != MCTRG_OK) return rc;
-  if (hipStreamSynchronize(ch->c.st) != hipSuccess) return MCTRG_EDEVICE;
+  if (hipStreamSynchronize(ch->cp.caller) != hipSuccess) return MCTRG_EDEVICE;
   return MCTRG_OK;
 }
 
 int mctrg_chain_get_profile(const mctrg_chain* ch, mctrg_chain_profile* out) {
   if (!ch || !out) return MCTRG_EINVAL;
-  out->jacobi_ms = ch->c.tj.ms;
-  out->jacobi_launches = ch->c.tj.launches;
-  out->gemm_ms = ch->c.tg.ms;
-  out->gemm_launches = ch->c.tg.launches;
-  out->steps_done = ch->c.step;
-  out->last_sweeps = ch->c.last_sweeps;
-  for (int s = 0; s < 64; ++s) {
-    const bool in = s < ch->c.last_sweeps && s < kMaxSweeps;
-    out->last_pairs[s] = in ? ch->c.sweep_hist[2 * s] : 0;
-    out->last_active[s] = in ? ch->c.sweep_hist[2 * s + 1] : 0;
+  std::memset(out, 0, sizeof(*out));
+  std::vector<std::pair<float, float>> js, gs;
+  for (const auto& c : ch->cp.parts) {
+    out->jacobi_ms += c->tj.ms;
+    out->jacobi_launches += c->tj.launches;
+    out->gemm_ms += c->tg.ms;
+    out->gemm_launches += c->tg.launches;
+    out->last_sweeps = std::max(out->last_sweeps, c->last_sweeps);
+    for (int s = 0; s < 64; ++s) {
+      const bool in = s < c->last_sweeps && s < kMaxSweeps;
+      out->last_pairs[s] += in ? c->sweep_hist[2 * s] : 0;
+      out->last_active[s] += in ? c->sweep_hist[2 * s + 1] : 0;
+    }
+    js.insert(js.end(), c->tj.spans.begin(), c->tj.spans.end());
+    gs.insert(gs.end(), c->tg.spans.begin(), c->tg.spans.end());
   }
+  out->steps_done = ch->steps;
+  out->jacobi_busy_ms = union_ms(std::move(js));
+  out->gemm_busy_ms = union_ms(std::move(gs));
+  out->parts = (int32_t)ch->cp.parts.size();
   return MCTRG_OK;
 }
 

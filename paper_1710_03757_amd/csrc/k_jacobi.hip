@@ -678,6 +678,13 @@ hipError_t KernelTimer::collect() {
     if (e != hipSuccess) return e;
     ms += t;
     ++launches;
+    if (ref) {
+      float a = 0.0f, b = 0.0f;
+      e = hipEventElapsedTime(&a, ref, ev[i]);
+      if (e == hipSuccess) e = hipEventElapsedTime(&b, ref, ev[i + 1]);
+      if (e != hipSuccess) return e;
+      spans.emplace_back(a, b);
+    }
   }
   used = 0;
   return hipSuccess;

@@ -7,6 +7,9 @@
 #include <stdint.h>
 #include <stddef.h>
 
+#include <utility>
+#include <vector>
+
 namespace mctrg {
 
 typedef double f64x4 __attribute__((ext_vector_type(4)));
@@ -93,6 +96,10 @@ struct KernelTimer {
   hipEvent_t ev[2 * 256] = {};
   int used = 0;
   bool enabled = false;
+  // optional common origin (not owned): when set, every launch's interval
+  // after it is kept, so that launches on several streams can be merged
+  hipEvent_t ref = nullptr;
+  std::vector<std::pair<float, float>> spans;
   ~KernelTimer() {
     for (auto& e : ev)
       if (e) (void)hipEventDestroy(e);

@@ -205,7 +205,9 @@ def test_chain_api_matches_run_samples():
     ch.step(4)
     b = ch.finish(want_ln_c=True)
     prof = ch.profile()
-    assert prof["steps_done"] == 7 and prof["jacobi_launches"] > 0 and prof["gemm_launches"] == 7
+    # five samples run as two parts (3 + 2), one GEMM per part and step
+    assert prof["parts"] == 2
+    assert prof["steps_done"] == 7 and prof["jacobi_launches"] > 0 and prof["gemm_launches"] == 7 * prof["parts"]
     assert np.array_equal(a.ln_abs_Z.cpu().numpy(), b.ln_abs_Z.cpu().numpy())
     assert np.array_equal(a.ln_c.cpu().numpy(), b.ln_c.cpu().numpy())
     # a partial chain traces the 2^s-site lattice: compare with the oracle
@@ -215,3 +217,45 @@ def test_chain_api_matches_run_samples():
     for i in range(2):
         o = trg.run_shared(ising.site_tensor(0.42, 0.05), 4, 6, 9, i)
         assert abs(p.ln_abs_Z.cpu().numpy()[i] - o.ln_abs_Z) / 16 < 1e-12
+
+
+@pytest.mark.parametrize("mode,k,n_steps,ns", [("shared", 8, 8, 5), ("independent", 4, 4, 3), ("topk", 8, 6, 4)])
+def test_two_parts_match_one(mode, k, n_steps, ns):
+    """A wave of two or more samples runs as two parts on two streams; the
+    results must be those of a single part, bit for bit (every draw is
+    addressed by the global sample id, every decomposition is independent)."""
+    torch, m = need_gpu()
+    log(f"two parts vs one: {mode} k={k} steps={n_steps} samples={ns}")
+    ts = m.init_tensor("site", [BETA_C, 0.42], [0.0, 0.1])
+    kw = dict(n_steps=n_steps, k=k, mode=mode, seed=7, sample_offset=11, groups=[i % 2 for i in range(ns)],
+              want_ln_c=True)
+    if mode != "independent":
+        kw.update(record=True, want_tensor=True)
+    a = m.run_samples(ts, ns, **kw)
+    b = m.run_samples(ts, ns, one_stream=True, **kw)
+    assert a.status == b.status == m.OK
+    for f in ("sign", "ln_abs_Z", "ln_c", "record", "tensor"):
+        x, y = getattr(a, f), getattr(b, f)
+        if x is None:
+            assert y is None
+            continue
+        assert np.array_equal(x.cpu().numpy(), y.cpu().numpy(), equal_nan=True), f
+
+
+def test_chain_parts_profile():
+    torch, m = need_gpu()
+    log("chain parts profile")
+    ts = m.init_tensor("site", [BETA_C], [0.0])
+    ch = m.Chain(ts, 6, n_steps=6, k=8, seed=3, profile=True)
+    ch.step(6)
+    p = ch.profile()
+    assert p["parts"] == 2 and p["steps_done"] == 6
+    assert p["jacobi_launches"] > 0 and 0.0 < p["jacobi_busy_ms"] <= p["jacobi_ms"] + 1e-3
+    r = ch.finish()
+    one = m.Chain(ts, 6, n_steps=6, k=8, seed=3, profile=True, one_stream=True)
+    one.step(6)
+    assert one.profile()["parts"] == 1
+    r1 = one.finish()
+    assert torch.equal(r.sign, r1.sign) and torch.equal(r.ln_abs_Z, r1.ln_abs_Z)
+    ch.close()
+    one.close()
