@@ -810,7 +810,11 @@ int mctrg_run_samples(mctrg_tensor_set* ts, const mctrg_run_config* cfg, int64_t
     size_t freeb = 0, totalb = 0;
     if (hipMemGetInfo(&freeb, &totalb) != hipSuccess) return MCTRG_EDEVICE;
     const double budget = 0.70 * (double)freeb;
-    int64_t wave = (int64_t)std::max(1.0, std::floor((budget - (double)per1) / (double)per_sample) + 1);
+    // a wave of two or more samples runs as two parts, each with its own
+    // per-chain (sample-independent) allocations
+    const double fixed = std::max(0.0, (double)per1 - (double)per_sample);
+    const int parts = (cfg->flags & MCTRG_ONE_STREAM) ? 1 : 2;
+    int64_t wave = (int64_t)std::max(1.0, std::floor((budget - parts * fixed) / (double)per_sample));
     if ((double)per1 > budget) return MCTRG_ENOMEM;
     wave = std::min<int64_t>(wave, (int64_t)members.size());
     for (size_t w0 = 0; w0 < members.size(); w0 += (size_t)wave) {
