@@ -14,7 +14,6 @@
 #include <functional>
 #include <memory>
 #include <new>
-#include <system_error>
 #include <thread>
 #include <vector>
 
@@ -582,18 +581,26 @@ int parts_join(ChainParts& cp) {
 int parts_step(ChainParts& cp, int n) {
   const int P = (int)cp.parts.size();
   std::vector<int> rcs(P, MCTRG_OK);
-  auto run = [&](int p) {
-    if (p > 0 && hipSetDevice(cp.device) != hipSuccess) {
-      rcs[p] = MCTRG_EDEVICE;
-      return;
+  auto run = [&](int p) {   // no exception leaves a part's thread
+    try {
+      if (p > 0 && hipSetDevice(cp.device) != hipSuccess) {
+        rcs[p] = MCTRG_EDEVICE;
+        return;
+      }
+      for (int i = 0; i < n && rcs[p] == MCTRG_OK; ++i) rcs[p] = chain_step(*cp.parts[p]);
+    } catch (...) {
+      rcs[p] = MCTRG_ENOMEM;
     }
-    for (int i = 0; i < n && rcs[p] == MCTRG_OK; ++i) rcs[p] = chain_step(*cp.parts[p]);
   };
   std::vector<std::thread> th;
+  try {
+    th.reserve(P);
+  } catch (...) {
+  }
   for (int p = 1; p < P; ++p) {
     try {
       th.emplace_back(run, p);
-    } catch (const std::system_error&) {
+    } catch (...) {   // no thread: step this part here
       run(p);
     }
   }
