@@ -207,6 +207,8 @@ typedef struct {
                                parts (launches of two parts overlap in time)     */
   double gemm_busy_ms;      /* the same for the GEMMs                            */
   int32_t parts;            /* parts of the chain (1 or 2)                       */
+  int32_t step_sweeps[64];  /* Jacobi sweeps of every step done (the most over
+                               the step's decompositions), steps 0..63          */
 } mctrg_chain_profile;
 /* Timings are collected only when cfg->flags has MCTRG_PROFILE. */
 int mctrg_chain_get_profile(const mctrg_chain* ch, mctrg_chain_profile* out);

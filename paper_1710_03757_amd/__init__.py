@@ -62,13 +62,15 @@ class ChainProfile(ctypes.Structure):
     _fields_ = [("jacobi_ms", ctypes.c_double), ("jacobi_launches", ctypes.c_int64), ("gemm_ms", ctypes.c_double),
                 ("gemm_launches", ctypes.c_int64), ("steps_done", ctypes.c_int32), ("last_sweeps", ctypes.c_int32),
                 ("last_pairs", ctypes.c_int32 * 64), ("last_active", ctypes.c_int32 * 64),
-                ("jacobi_busy_ms", ctypes.c_double), ("gemm_busy_ms", ctypes.c_double), ("parts", ctypes.c_int32)]
+                ("jacobi_busy_ms", ctypes.c_double), ("gemm_busy_ms", ctypes.c_double), ("parts", ctypes.c_int32),
+                ("step_sweeps", ctypes.c_int32 * 64)]
 
     def as_dict(self):
         d = {f: getattr(self, f) for f, _ in self._fields_}
         n = max(0, min(64, self.last_sweeps))
         d["last_pairs"] = list(self.last_pairs)[:n]
         d["last_active"] = list(self.last_active)[:n]
+        d["step_sweeps"] = list(self.step_sweeps)[:max(0, min(64, self.steps_done))]
         return d
 
 

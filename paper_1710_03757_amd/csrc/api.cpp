@@ -184,6 +184,7 @@ struct Chain {
   KernelTimer tj, tg;
   int last_sweeps = 0;
   int sweep_hist[2 * kMaxSweeps] = {};   // last decomposition: (pairs rotated, jobs active) per sweep
+  int step_sweeps[64] = {};               // Jacobi sweeps of every step
 
   ~Chain() {
     if (mem) (void)hipFree(mem);
@@ -442,6 +443,7 @@ int chain_step(Chain& c) {
   CKH(run_deflate(nj, sh.n_pad, rows, Wj, c.nb_job, c.dnrm, c.dpos, c.jw.counter, c.jw.counter_host, &nb_max, c.st));
   CKH(run_jacobi(nj, sh.n_pad, Wj, c.jw, kMaxSweeps, c.st, c.tj.enabled ? &c.tj : nullptr, &c.last_sweeps, c.nb_job,
                  nb_max, c.sweep_hist));
+  if (s < 64) c.step_sweeps[s] = c.last_sweeps;
   CKH(launch_jacobi_fail(nj, sh.jps, c.jw.sweeps, c.failed, c.st));
   CKH(launch_jacobi_finalize(nj, sh.n, sh.n_pad, Wj, c.sigma, c.order, c.st));
   SampleArgs sa{};
@@ -934,6 +936,7 @@ int mctrg_chain_get_profile(const mctrg_chain* ch, mctrg_chain_profile* out) {
     out->gemm_ms += c->tg.ms;
     out->gemm_launches += c->tg.launches;
     out->last_sweeps = std::max(out->last_sweeps, c->last_sweeps);
+    for (int s = 0; s < 64; ++s) out->step_sweeps[s] = std::max(out->step_sweeps[s], c->step_sweeps[s]);
     for (int s = 0; s < 64; ++s) {
       const bool in = s < c->last_sweeps && s < kMaxSweeps;
       out->last_pairs[s] += in ? c->sweep_hist[2 * s] : 0;
