@@ -445,7 +445,7 @@ int chain_step(Chain& c) {
                  nb_max, c.sweep_hist));
   if (s < 64) c.step_sweeps[s] = c.last_sweeps;
   CKH(launch_jacobi_fail(nj, sh.jps, c.jw.sweeps, c.failed, c.st));
-  CKH(launch_jacobi_finalize(nj, sh.n, sh.n_pad, Wj, c.sigma, c.order, c.st));
+  CKH(launch_jacobi_finalize(nj, sh.n, sh.n_pad, Wj, c.sigma, c.order, c.st, c.dnrm));
   SampleArgs sa{};
   sa.njobs = nj; sa.n = sh.n; sa.k = sh.kc; sa.mode = c.mode; sa.seed = c.seed; sa.tau = c.tau;
   sa.sigma = c.sigma; sa.rng = c.rng; sa.split = c.split; sa.kept = c.kept; sa.cand = c.cand;

@@ -850,8 +850,11 @@ hipError_t run_deflate(int64_t njobs, int n_pad, const double* Win, double* Wout
 // ---------------------------------------------------------------------------
 // Finalisation: sigma_i = ||row_i||, sorted descending (ties by row index).
 // One workgroup of 256 threads per job; bitonic sort over n_pad <= 4096 keys.
+// nrm (or NULL): the squared row norms, already summed by deflate_norms_kernel
+// (one wavefront per row over the whole grid, the same summation order).
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void jacobi_finalize_kernel(int n, int n_pad, const double* __restrict__ W,
+                                                              const double* __restrict__ nrm,
                                                               double* __restrict__ sigma,
                                                               int32_t* __restrict__ order) {
   extern __shared__ unsigned char smem[];
@@ -862,7 +865,13 @@ __global__ __launch_bounds__(256) void jacobi_finalize_kernel(int n, int n_pad, 
   const int job = blockIdx.x;
   const double* Wj = W + (size_t)job * n_pad * n_pad;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int r = wave; r < P; r += 4) {
+  if (nrm) {
+    for (int r = threadIdx.x; r < P; r += 256) {
+      key[r] = r < n_pad ? sqrt(nrm[(size_t)job * n_pad + r]) : -1.0;   // padding sorts last
+      idx[r] = r;
+    }
+  }
+  for (int r = wave; r < P && !nrm; r += 4) {
     double s = 0.0;
     if (r < n_pad) {
       const double* row = Wj + (size_t)r * n_pad;
@@ -897,13 +906,16 @@ __global__ __launch_bounds__(256) void jacobi_finalize_kernel(int n, int n_pad, 
 }
 
 hipError_t launch_jacobi_finalize(int64_t njobs, int n, int n_pad, const double* W, double* sigma,
-                                  int32_t* order, hipStream_t stream) {
+                                  int32_t* order, hipStream_t stream, double* nrm) {
   if (njobs == 0) return hipSuccess;
   int P = 1;
   while (P < n_pad) P <<= 1;
   size_t sh = (size_t)P * (sizeof(double) + sizeof(int));
+  if (nrm)
+    hipLaunchKernelGGL(deflate_norms_kernel, dim3((unsigned)ceil_div(n_pad, 4), (unsigned)njobs), dim3(256), 0,
+                       stream, n_pad, W, nrm);
   hipLaunchKernelGGL(jacobi_finalize_kernel, dim3((unsigned)njobs), dim3(256), sh, stream, n, n_pad, W,
-                     sigma, order);
+                     (const double*)nrm, sigma, order);
   return hipGetLastError();
 }
 

@@ -185,8 +185,10 @@ hipError_t launch_scatter_G(int64_t njobs, int D, int n_pad, int kcap, const dou
                             const int32_t* colmap, const int32_t* kept, double* G, hipStream_t stream);
 
 // Norms of the rotated rows, sorted descending: sigma[j][0..n), order[j][0..n).
+// nrm (n_pad doubles per job, or NULL): scratch for the squared row norms,
+// which are then summed by a grid of one wavefront per row first.
 hipError_t launch_jacobi_finalize(int64_t njobs, int n, int n_pad, const double* W, double* sigma,
-                                  int32_t* order, hipStream_t stream);
+                                  int32_t* order, hipStream_t stream, double* nrm = nullptr);
 
 // Sampler: chooses kept subsets, inclusion rates and weights.
 struct SampleArgs {
