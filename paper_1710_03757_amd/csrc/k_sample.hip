@@ -80,39 +80,62 @@ __global__ __launch_bounds__(64) void sample_kernel(SampleArgs a) {
       if (4 * blk + w < c) U[4 * blk + w] = word_to_uniform(y.v[w]);
   }
 
+  // The sequential loops below take ln lambda_m (and the uniforms) from
+  // registers: 64 consecutive indices at a time, one per lane, read back by
+  // shuffles, so that no global load or logarithm sits on their critical path.
+  auto ln_lambda = [&](int m) { return m >= 0 && m < c ? 2.0 * log(sig[m] / s0) : 0.0; };
+
   // ---- suffix table ------------------------------------------------------
   const int j = lane + 1;                 // column owned by this lane
   double prev = -INFINITY;                // LS[c][j], j >= 1
   if (lane == 0) LS[(size_t)c * K1] = 0.0;
   if (j <= k) LS[(size_t)c * K1 + j] = -INFINITY;
-  for (int m = c - 1; m >= 0; --m) {
-    const double lm = 2.0 * log(sig[m] / s0);
-    double left = __shfl_up(prev, 1);     // LS[m+1][j-1]
-    if (lane == 0) left = 0.0;
-    const double cur = logaddexp(prev, lm + left);
-    prev = cur;
-    if (j <= k) LS[(size_t)m * K1 + j] = cur;
-    if (lane == 0) LS[(size_t)m * K1] = 0.0;
+  for (int m1 = c - 1; m1 >= 0; m1 -= 64) {    // indices m1, m1 - 1, ..., m1 - 63
+    const double lmc = ln_lambda(m1 - lane);
+    for (int d = 0; d < 64 && m1 - d >= 0; ++d) {
+      const int m = m1 - d;
+      const double lm = __shfl(lmc, d);
+      double left = __shfl_up(prev, 1);   // LS[m+1][j-1]
+      if (lane == 0) left = 0.0;
+      const double cur = logaddexp(prev, lm + left);
+      prev = cur;
+      if (j <= k) LS[(size_t)m * K1 + j] = cur;
+      if (lane == 0) LS[(size_t)m * K1] = 0.0;
+    }
   }
   __threadfence_block();
   __syncthreads();
 
   // ---- sequential draw (wave-uniform walk) --------------------------------
+  // rows m and m + 1 of LS sit in the lanes (lane j: column j), loaded one
+  // row ahead; column 64 (k = 64 only) has no lane and is loaded when needed
   int rem = k, nsel = 0, last = -1;
-  for (int m = 0; m < c && rem > 0; ++m) {
-    bool take;
-    if (rem == c - m) {
-      take = true;
-    } else {
-      const double lm = 2.0 * log(sig[m] / s0);
-      const double q = exp(lm + LS[(size_t)(m + 1) * K1 + (rem - 1)] - LS[(size_t)m * K1 + rem]);
-      take = U[m] < q;
-    }
-    if (take) {
-      if (lane == 0) sel[nsel] = m;
-      ++nsel;
-      --rem;
-      last = m;
+  auto ls_row = [&](int m) { return (m <= c && lane < K1) ? LS[(size_t)m * K1 + lane] : 0.0; };
+  double row0 = ls_row(0), row1 = ls_row(1);
+  for (int m0 = 0; m0 < c && rem > 0; m0 += 64) {
+    const double lmc = ln_lambda(m0 + lane);
+    const double uc = m0 + lane < c ? U[m0 + lane] : 0.0;
+    for (int d = 0; d < 64 && m0 + d < c && rem > 0; ++d) {
+      const int m = m0 + d;
+      const double row2 = ls_row(m + 2);
+      bool take;
+      if (rem == c - m) {
+        take = true;
+      } else {
+        const double lm = __shfl(lmc, d);
+        const double a1 = __shfl(row1, rem - 1);                                     // LS[m+1][rem-1]
+        const double a0 = rem < 64 ? __shfl(row0, rem) : LS[(size_t)m * K1 + rem];   // LS[m][rem]
+        const double q = exp(lm + a1 - a0);
+        take = __shfl(uc, d) < q;
+      }
+      if (take) {
+        if (lane == 0) sel[nsel] = m;
+        ++nsel;
+        --rem;
+        last = m;
+      }
+      row0 = row1;
+      row1 = row2;
     }
   }
   for (int t = nsel + lane; t < k; t += 64) sel[t] = -1;   // (nsel == k always)
@@ -122,14 +145,18 @@ __global__ __launch_bounds__(64) void sample_kernel(SampleArgs a) {
   prev = -INFINITY;                       // LP[0][j], j >= 1
   if (lane == 0) LP[0] = 0.0;
   if (j <= k) LP[j] = -INFINITY;
-  for (int m = 0; m < last; ++m) {
-    const double lm = 2.0 * log(sig[m] / s0);
-    double left = __shfl_up(prev, 1);     // LP[m][j-1]
-    if (lane == 0) left = 0.0;
-    const double cur = logaddexp(prev, lm + left);
-    prev = cur;
-    if (j <= k) LP[(size_t)(m + 1) * K1 + j] = cur;
-    if (lane == 0) LP[(size_t)(m + 1) * K1] = 0.0;
+  for (int m0 = 0; m0 < last; m0 += 64) {
+    const double lmc = ln_lambda(m0 + lane);
+    for (int d = 0; d < 64 && m0 + d < last; ++d) {
+      const int m = m0 + d;
+      const double lm = __shfl(lmc, d);
+      double left = __shfl_up(prev, 1);   // LP[m][j-1]
+      if (lane == 0) left = 0.0;
+      const double cur = logaddexp(prev, lm + left);
+      prev = cur;
+      if (j <= k) LP[(size_t)(m + 1) * K1 + j] = cur;
+      if (lane == 0) LP[(size_t)(m + 1) * K1] = 0.0;
+    }
   }
   __threadfence_block();
   __syncthreads();
