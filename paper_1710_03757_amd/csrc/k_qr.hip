@@ -608,11 +608,15 @@ static inline dim3 xcd_tile_grid(int ntiles, int64_t njobs) {
 // per workgroup, coalesced, masked to the unit lower trapezoid, and shared
 // by the four waves (instead of each wave fetching it), double-buffered with
 // one barrier per chunk.  Same arithmetic as qr_trailing_kernel<32>.
+// probe (colnorm required): C is not written; instead every column c gets
+// colnorm = |c[j:]|^2 - |(Q^T c)[j : j + 32]|^2, its squared norm below the
+// panel's rows after the panel's reflectors, by downdating (for the column
+// re-ordering only, so the rounding of the difference is harmless).
 __global__ __launch_bounds__(256) void qr_trailing32_kernel(int64_t njobs, int n_pad, int j, int cend,
                                                             double* __restrict__ S, const double* __restrict__ Tws,
                                                             int64_t t_stride, int64_t t_off,
                                                             const int32_t* __restrict__ colmap,
-                                                            double* __restrict__ colnorm) {
+                                                            double* __restrict__ colnorm, int probe) {
   int64_t job;
   int tile;
   if (!xcd_job_tile(njobs, job, tile)) return;
@@ -650,10 +654,15 @@ __global__ __launch_bounds__(256) void qr_trailing32_kernel(int64_t njobs, int n
   const double* cbase = Sj + (size_t)scol(col_ok ? c0w + lr : (active ? c0w : j + 32)) * n_pad + 4 * lg;
   double2 vn = *reinterpret_cast<const double2*>(vbase + j);
   double2 cn0 = *reinterpret_cast<const double2*>(cbase + j), cn1 = *reinterpret_cast<const double2*>(cbase + j + 2);
+  double sqn = 0.0;   // probe: |c[j:]|^2, this lane's rows
   for (int ch = 0; ch < nch; ++ch) {
     const int r0 = j + 16 * ch, buf = ch & 1;
     store_v(r0, buf, vn);
     const double cv[4] = {col_ok ? cn0.x : 0.0, col_ok ? cn0.y : 0.0, col_ok ? cn1.x : 0.0, col_ok ? cn1.y : 0.0};
+    if (probe) {
+#pragma unroll
+      for (int jj = 0; jj < 4; ++jj) sqn = fma(cv[jj], cv[jj], sqn);
+    }
     if (ch + 1 < nch) {
       vn = *reinterpret_cast<const double2*>(vbase + r0 + 16);
       cn0 = *reinterpret_cast<const double2*>(cbase + r0 + 16);
@@ -688,6 +697,33 @@ __global__ __launch_bounds__(256) void qr_trailing32_kernel(int64_t njobs, int n
     for (int ii = 0; ii < 8; ++ii) W1[i0 + ii][col] = w2[ii];
   }
   __syncthreads();
+  if (probe) {
+    // top 32 rows of Q^T c = c[j + i] - sum_{m <= i} V[j + i][m] W2[m][c]
+    // (the panel's top V block is unit lower triangular, staged in Tm); lane
+    // (lr, lg) takes rows 8 lg .. 8 lg + 7 of column c0w + lr
+    for (int e = tid; e < 1024; e += 256) {
+      const int i = e >> 5, m = e & 31;
+      Tm[i][m] = i == m ? 1.0 : (i > m ? Sj[(size_t)scol(j + m) * n_pad + j + i] : 0.0);
+    }
+    __syncthreads();
+    const int wc = 16 * wave + lr;
+    const double* ctop = Sj + (size_t)scol(col_ok ? c0w + lr : j) * n_pad + j + 8 * lg;
+    double tsq = 0.0;
+#pragma unroll
+    for (int ii = 0; ii < 8; ++ii) {
+      const int i = 8 * lg + ii;
+      double t = ctop[ii];
+      for (int m = 0; m <= i; ++m) t = fma(-Tm[i][m], W1[m][wc], t);
+      tsq = fma(t, t, tsq);
+    }
+    // sum over the four lane groups of the column
+    sqn += __shfl_xor(sqn, 16);
+    sqn += __shfl_xor(sqn, 32);
+    tsq += __shfl_xor(tsq, 16);
+    tsq += __shfl_xor(tsq, 32);
+    if (lg == 0 && col_ok) colnorm[job * n_pad + scol(c0w + lr)] = fmax(sqn - tsq, 0.0);
+    return;
+  }
   // ---- phase 3: C <- C - V W2 ------------------------------------------------
   // output tile C^T[c (16)][r (16)] = sum_i W2^T[c][i] V^T[i][r]
   double aw[8];
@@ -771,7 +807,8 @@ __device__ __forceinline__ int t128_frag(int g, int ks) { return 2 * g * (g + 1)
 // two consecutive rows per step (16-byte loads; V is stored column-major).
 __global__ __launch_bounds__(256) void qr_t64_kernel(int n_pad, int j, const double* __restrict__ S,
                                                      const double* __restrict__ Tws, int64_t t_stride, int64_t t_off1,
-                                                     int64_t t_off2, double* __restrict__ T64) {
+                                                     int64_t t_off2, double* __restrict__ T64,
+                                                     const int32_t* __restrict__ colmap) {
   const int64_t job = blockIdx.x;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int lr = lane & 15, lg = lane >> 4;
@@ -782,9 +819,11 @@ __global__ __launch_bounds__(256) void qr_t64_kernel(int n_pad, int j, const dou
     T2[e >> 5][e & 31] = Tws[job * t_stride + t_off2 + e];
   }
   const int ta = wave >> 1, tb = wave & 1;
-  const double* c1 = Sj + (size_t)(j + 16 * ta + lr) * n_pad;        // column of V1 (all rows >= j + 32 below its diagonal)
+  const int32_t* cm = colmap ? colmap + job * n_pad : nullptr;
+  auto scol = [&](int c) { return cm ? cm[c] : c; };                  // logical -> stored column
+  const double* c1 = Sj + (size_t)scol(j + 16 * ta + lr) * n_pad;    // column of V1 (all rows >= j + 32 below its diagonal)
   const int d2 = j + 32 + 16 * tb + lr;                                // diagonal row of this V2 column
-  const double* c2 = Sj + (size_t)d2 * n_pad;
+  const double* c2 = Sj + (size_t)scol(d2) * n_pad;
   // four independent accumulators over interleaved 8-row chunks, so that
   // the loads of four chunks are in flight at once (n_pad - j - 32 is a
   // multiple of 32)
@@ -841,25 +880,33 @@ __global__ __launch_bounds__(256) void qr_t64_kernel(int n_pad, int j, const dou
 // chunks staged through LDS as in qr_trailing32_kernel; phase 2 W <- T^T W
 // with MFMA (T packed upper in the staging buffer); phase 3 C <- C - V W.
 __global__ __launch_bounds__(256) void qr_trailing64_kernel(int64_t njobs, int n_pad, int j, int cend,
-                                                            double* __restrict__ S, const double* __restrict__ T64) {
+                                                            double* __restrict__ S, const double* __restrict__ T64,
+                                                            const int32_t* __restrict__ colmap,
+                                                            double* __restrict__ colnorm) {
   int64_t job;
   int tile;
   if (!xcd_job_tile(njobs, job, tile)) return;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int lr = lane & 15, lg = lane >> 4;
   double* Sj = S + job * (size_t)n_pad * n_pad;
-  const int c0w = j + 64 + 64 * tile + 16 * wave;   // first column of this wave
+  const int c0w = j + 64 + 64 * tile + 16 * wave;   // first (logical) column of this wave
   __shared__ double Vs[2][16][65];   // V chunks; T (packed upper, 2080 entries) in phase 2
   __shared__ double W1[64][65];
   const bool active = c0w < cend;   // columns j + 64 .. cend - 1 are updated
   const bool col_ok = (c0w + lr) < cend;
-  // V staging: thread t takes V column vd = t / 4, rows 4 (t % 4) .. + 3 of a chunk
+  const int32_t* cm = colmap ? colmap + job * n_pad : nullptr;
+  auto scol = [&](int c) { return cm ? cm[c] : c; };   // logical -> stored column
+  // V staging: thread t takes V column vd = t / 4, rows 4 (t % 4) .. + 3 of a
+  // chunk; the next chunk's loads are issued before the products of the
+  // current one, the masking is done when they are stored
   const int vd = tid >> 2, vr = 4 * (tid & 3);
-  const double* vbase = Sj + (size_t)(j + vd) * n_pad;
-  auto stage_v = [&](int r0, int buf) {
-    const double2 v01 = *reinterpret_cast<const double2*>(vbase + r0 + vr);
-    const double2 v23 = *reinterpret_cast<const double2*>(vbase + r0 + vr + 2);
-    double a[4] = {v01.x, v01.y, v23.x, v23.y};
+  const double* vbase = Sj + (size_t)scol(j + vd) * n_pad + vr;
+  auto load_v = [&](int r0, double2 (&v)[2]) {
+    v[0] = *reinterpret_cast<const double2*>(vbase + r0);
+    v[1] = *reinterpret_cast<const double2*>(vbase + r0 + 2);
+  };
+  auto store_v = [&](int r0, int buf, const double2 (&v)[2]) {
+    double a[4] = {v[0].x, v[0].y, v[1].x, v[1].y};
     if (r0 < j + 64) {   // V is stored below the diagonal, 1 on it, 0 above
       const int d = j + vd;
 #pragma unroll
@@ -877,14 +924,21 @@ __global__ __launch_bounds__(256) void qr_trailing64_kernel(int64_t njobs, int n
   f64x4 acc[4];
 #pragma unroll
   for (int g = 0; g < 4; ++g) acc[g] = f64x4{0, 0, 0, 0};
-  const double* cbase = Sj + (size_t)(col_ok ? c0w + lr : (active ? c0w : j + 64)) * n_pad;
+  const double* cbase = Sj + (size_t)scol(col_ok ? c0w + lr : (active ? c0w : j + 64)) * n_pad + 4 * lg;
+  double2 vn[2], cn[2];
+  load_v(j, vn);
+  cn[0] = *reinterpret_cast<const double2*>(cbase + j);
+  cn[1] = *reinterpret_cast<const double2*>(cbase + j + 2);
   for (int ch = 0; ch < nch; ++ch) {
     const int r0 = j + 16 * ch, buf = ch & 1;
-    stage_v(r0, buf);
-    const int rb = r0 + 4 * lg;
-    const double2 c01 = *reinterpret_cast<const double2*>(cbase + rb);
-    const double2 c23 = *reinterpret_cast<const double2*>(cbase + rb + 2);
-    const double cv[4] = {col_ok ? c01.x : 0.0, col_ok ? c01.y : 0.0, col_ok ? c23.x : 0.0, col_ok ? c23.y : 0.0};
+    store_v(r0, buf, vn);
+    const double cv[4] = {col_ok ? cn[0].x : 0.0, col_ok ? cn[0].y : 0.0, col_ok ? cn[1].x : 0.0,
+                          col_ok ? cn[1].y : 0.0};
+    if (ch + 1 < nch) {
+      load_v(r0 + 16, vn);
+      cn[0] = *reinterpret_cast<const double2*>(cbase + r0 + 16);
+      cn[1] = *reinterpret_cast<const double2*>(cbase + r0 + 18);
+    }
     __syncthreads();
 #pragma unroll
     for (int jj = 0; jj < 4; ++jj)
@@ -926,7 +980,8 @@ __global__ __launch_bounds__(256) void qr_trailing64_kernel(int64_t njobs, int n
       for (int x = 0; x < 4; ++x) W1[16 * g + acc_row_f64(lg, x)][16 * wave + lr] = w2[g][x];
   }
   __syncthreads();
-  // ---- phase 3: C <- C - V W2 ------------------------------------------------
+  // ---- phase 3: C <- C - V W2 (and, with colnorm, the squared norms of the
+  // updated columns below the block's rows for the re-ordering) -------------
   // output tile C^T[c (16)][r (16)] = sum_i W2^T[c][i] V^T[i][r]
   double aw[16];
 #pragma unroll
@@ -935,22 +990,52 @@ __global__ __launch_bounds__(256) void qr_trailing64_kernel(int64_t njobs, int n
 #pragma unroll
   for (int x = 0; x < 4; ++x) {
     const int c = c0w + acc_row_f64(lg, x);
-    ccols[x] = (active && c < cend) ? c : -1;
+    ccols[x] = (active && c < cend) ? scol(c) : -1;
   }
+  // columns not updated read a V column instead (always there, never stored)
+  const double* cp[4];
+#pragma unroll
+  for (int x = 0; x < 4; ++x) cp[x] = Sj + (size_t)(ccols[x] >= 0 ? ccols[x] : scol(j)) * n_pad + lr;
+  double sq[4] = {0.0, 0.0, 0.0, 0.0};
+  double cold[4];
+  load_v(j, vn);
+#pragma unroll
+  for (int x = 0; x < 4; ++x) cold[x] = cp[x][j];
   for (int ch = 0; ch < nch; ++ch) {
     const int r0 = j + 16 * ch, buf = ch & 1;
-    stage_v(r0, buf);
+    store_v(r0, buf, vn);
     const int r = r0 + lr;
-    double cold[4];
+    double cc[4];
 #pragma unroll
-    for (int x = 0; x < 4; ++x) cold[x] = ccols[x] >= 0 ? Sj[(size_t)ccols[x] * n_pad + r] : 0.0;
+    for (int x = 0; x < 4; ++x) cc[x] = cold[x];
+    if (ch + 1 < nch) {
+      load_v(r0 + 16, vn);
+#pragma unroll
+      for (int x = 0; x < 4; ++x) cold[x] = cp[x][r0 + 16];
+    }
     __syncthreads();
     f64x4 a = {0, 0, 0, 0};
 #pragma unroll
     for (int ks = 0; ks < 16; ++ks) a = __builtin_amdgcn_mfma_f64_16x16x4f64(aw[ks], Vs[buf][lr][4 * ks + lg], a, 0, 0, 0);
 #pragma unroll
+    for (int x = 0; x < 4; ++x) {
+      if (ccols[x] >= 0) {
+        const double v = cc[x] - a[x];
+        Sj[(size_t)ccols[x] * n_pad + r] = v;
+        if (r >= j + 64) sq[x] = fma(v, v, sq[x]);
+      }
+    }
+  }
+  if (colnorm) {
+    // lanes with equal lg share the four columns: sum over lr (xor 1..8)
+#pragma unroll
     for (int x = 0; x < 4; ++x)
-      if (ccols[x] >= 0) Sj[(size_t)ccols[x] * n_pad + r] = cold[x] - a[x];
+      for (int o = 1; o < 16; o <<= 1) sq[x] += __shfl_xor(sq[x], o);
+    if (lr == 0) {
+#pragma unroll
+      for (int x = 0; x < 4; ++x)
+        if (ccols[x] >= 0) colnorm[job * n_pad + ccols[x]] = sq[x];
+    }
   }
 }
 
@@ -1312,23 +1397,58 @@ static hipError_t qr_factor_t(int64_t njobs, int n_pad, double* S, double* Tws, 
       launch_panel32(dim3((unsigned)njobs), dim3(256), 0, stream, n_pad, c, S, Tws, ts, o1, (const int32_t*)nullptr);
       if (c + 32 >= n_pad) return false;
       hipLaunchKernelGGL(qr_trailing32_kernel, xcd_tile_grid(1, njobs), dim3(256), 0, stream, njobs, n_pad, c, c + 64,
-                         S, (const double*)Tws, ts, o1, (const int32_t*)nullptr, (double*)nullptr);
+                         S, (const double*)Tws, ts, o1, (const int32_t*)nullptr, (double*)nullptr, 0);
       launch_panel32(dim3((unsigned)njobs), dim3(256), 0, stream, n_pad, c + 32, S, Tws, ts, o2,
                      (const int32_t*)nullptr);
       if (c + 64 >= n_pad) return false;
       hipLaunchKernelGGL(qr_t64_kernel, dim3((unsigned)njobs), dim3(256), 0, stream, n_pad, c, (const double*)S,
-                         (const double*)Tws, ts, o1, o2, Tslot);
+                         (const double*)Tws, ts, o1, o2, Tslot, (const int32_t*)nullptr);
       return true;
     };
     for (int j = 0; j < n_pad; j += 128) {
       if (!block64(j, T64)) break;
       hipLaunchKernelGGL(qr_trailing64_kernel, xcd_tile_grid(1, njobs), dim3(256), 0, stream, njobs, n_pad, j,
-                         min(j + 128, n_pad), S, (const double*)T64);
+                         min(j + 128, n_pad), S, (const double*)T64, (const int32_t*)nullptr, (double*)nullptr);
       if (!block64(j + 64, T64 + 4096)) break;
       hipLaunchKernelGGL(qr_t128_kernel, dim3((unsigned)njobs), dim3(256), 0, stream, n_pad, j, (const double*)S,
                          T64);
       hipLaunchKernelGGL(qr_trailing128_kernel, xcd_tile_grid(ceil_div(n_pad - j - 128, 64), njobs), dim3(256), 0,
                          stream, njobs, n_pad, j, S, (const double*)T64, (int)(lower && j == 0));
+    }
+    return hipGetLastError();
+  }
+  if (PW == 32 && colmap && colnorm && T64) {
+    // Re-ordered columns in 64-column steps: panel A (the 32 columns of
+    // largest remaining norm), a read-only pass that gives every remaining
+    // column its squared norm below A's rows by downdating, the re-ordering,
+    // A applied to the 32 columns chosen for panel B only, panel B, and one
+    // pass of both over the rest, which also leaves the exact norms below
+    // the step's rows for the next re-ordering: four passes over the
+    // trailing columns per 64 columns instead of six.
+    hipError_t e = launch_iota(njobs, n_pad, colmap, stream);
+    if (e != hipSuccess) return e;
+    const int64_t ts = keep_T ? (int64_t)n_pad * 32 : 2048;
+    for (int j = 0; j < n_pad; j += 64) {
+      const int64_t o1 = keep_T ? (int64_t)(j / 32) * 1024 : 0, o2 = keep_T ? o1 + 1024 : 1024;
+      if (j > 0)
+        hipLaunchKernelGGL(resort_cols_kernel, dim3((unsigned)njobs), dim3(256), 0, stream, n_pad, j,
+                           (const double*)colnorm, colmap);
+      launch_panel32(dim3((unsigned)njobs), dim3(256), 0, stream, n_pad, j, S, Tws, ts, o1, (const int32_t*)colmap);
+      const int rest = n_pad - j - 32;
+      if (rest <= 0) break;
+      hipLaunchKernelGGL(qr_trailing32_kernel, xcd_tile_grid(ceil_div(rest, 64), njobs), dim3(256), 0, stream, njobs,
+                         n_pad, j, n_pad, S, (const double*)Tws, ts, o1, (const int32_t*)colmap, colnorm, 1);
+      hipLaunchKernelGGL(resort_cols_kernel, dim3((unsigned)njobs), dim3(256), 0, stream, n_pad, j + 32,
+                         (const double*)colnorm, colmap);
+      hipLaunchKernelGGL(qr_trailing32_kernel, xcd_tile_grid(1, njobs), dim3(256), 0, stream, njobs, n_pad, j, j + 64,
+                         S, (const double*)Tws, ts, o1, (const int32_t*)colmap, (double*)nullptr, 0);
+      launch_panel32(dim3((unsigned)njobs), dim3(256), 0, stream, n_pad, j + 32, S, Tws, ts, o2,
+                     (const int32_t*)colmap);
+      if (j + 64 >= n_pad) break;
+      hipLaunchKernelGGL(qr_t64_kernel, dim3((unsigned)njobs), dim3(256), 0, stream, n_pad, j, (const double*)S,
+                         (const double*)Tws, ts, o1, o2, T64, (const int32_t*)colmap);
+      hipLaunchKernelGGL(qr_trailing64_kernel, xcd_tile_grid(ceil_div(n_pad - j - 64, 64), njobs), dim3(256), 0,
+                         stream, njobs, n_pad, j, n_pad, S, (const double*)T64, (const int32_t*)colmap, colnorm);
     }
     return hipGetLastError();
   }
@@ -1350,7 +1470,7 @@ static hipError_t qr_factor_t(int64_t njobs, int n_pad, double* S, double* Tws, 
       if (PW == 32)
         hipLaunchKernelGGL(qr_trailing32_kernel, xcd_tile_grid(ceil_div(rest, 64), njobs), dim3(256), 0, stream,
                            njobs, n_pad, j, n_pad, S, Tws, t_stride, t_off, (const int32_t*)colmap,
-                           colmap ? colnorm : nullptr);
+                           colmap ? colnorm : nullptr, 0);
       else
         hipLaunchKernelGGL((qr_trailing_kernel<PW>), dim3(ceil_div(rest, 64), (unsigned)njobs), dim3(256), 0, stream,
                            n_pad, j, S, Tws, t_stride, t_off, (const int32_t*)colmap, colmap ? colnorm : nullptr);
@@ -1455,10 +1575,10 @@ hipError_t run_qr5_precondition(int64_t njobs, int n, int D, int n_pad, const do
   if (n_pad > 1024) return hipErrorInvalidValue;
   hipError_t e = order_and_unfold(njobs, n, D, n_pad, T, src, split, perm, iperm, S1, stream);
   if (e != hipSuccess) return e;
-  e = qr_factor(njobs, n_pad, S1, Tscr, false, colmap, colnorm, stream);
+  double* T64 = Tscr + (size_t)njobs * 2048;
+  e = qr_factor(njobs, n_pad, S1, Tscr, false, colmap, colnorm, stream, T64);
   if (e != hipSuccess) return e;
   const dim3 rg(n_pad / 32, n_pad / 32, (unsigned)njobs);
-  double* T64 = Tscr + (size_t)njobs * 2048;
   hipLaunchKernelGGL(r_rows_kernel, rg, dim3(256), 0, stream, n_pad, S1, W1, (const int32_t*)colmap);
   e = qr_factor(njobs, n_pad, W1, Tws2, true, nullptr, nullptr, stream, Tscr, true);
   if (e != hipSuccess) return e;
