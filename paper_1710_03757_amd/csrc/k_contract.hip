@@ -94,6 +94,8 @@ __global__ void absmax_kernel(int64_t per, const double* __restrict__ A, double*
   const int64_t o = blockIdx.y;
   const double* Ao = A + o * per;
   double m = 0.0;
+  // unrolled so that each thread keeps four loads in flight
+#pragma unroll 4
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < per; e += (int64_t)gridDim.x * blockDim.x)
     m = fmax(m, fabs(Ao[e]));
   for (int s = 32; s > 0; s >>= 1) m = fmax(m, __shfl_xor(m, s));
@@ -131,6 +133,7 @@ __global__ void cast_kernel(int64_t per, const double* __restrict__ A, const dou
   const int64_t o = blockIdx.y;
   const double s = scale[o];
   const double* Ao = A + o * per;
+#pragma unroll 4
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < per; e += (int64_t)gridDim.x * blockDim.x) {
     const float v = (float)(Ao[e] * s);
     if (DT == MCTRG_F32) {

@@ -77,6 +77,7 @@ __global__ void absmax_out_kernel(int64_t elems, const T* __restrict__ A, double
   const T* Ao = A + o * elems;
   double m = 0.0;
   bool bad = false;
+#pragma unroll 4
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < elems; e += (int64_t)gridDim.x * blockDim.x) {
     const double v = (double)Ao[e];
     if (!isfinite(v)) bad = true;
@@ -93,6 +94,7 @@ __global__ void scale_out_kernel(int64_t elems, const T* __restrict__ A, const d
   const int64_t o = blockIdx.y;
   const double c = cbuf[o];
   const double inv = (c > 0.0 && isfinite(c)) ? 1.0 / c : 0.0;
+#pragma unroll 4
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < elems; e += (int64_t)gridDim.x * blockDim.x)
     out[o * elems + e] = (double)A[o * elems + e] * inv;
 }
