@@ -507,24 +507,26 @@ int chain_finish(Chain& c, int8_t* out_sign, double* out_ln, double* out_lnc, do
   return MCTRG_OK;
 }
 
-// A wave of samples advanced as up to two parts: each part is a Chain with its
-// own device memory and stream (part 0 on the caller's stream, part 1 on a
-// non-blocking stream of default priority created here), stepped by its own
-// host thread.  A part's host thread waits for the convergence count after
+// A wave of samples advanced as up to kParts parts: each part is a Chain with
+// its own device memory and stream (part 0 on the caller's stream, the others
+// on non-blocking streams of default priority created here), stepped by its
+// own host thread.  A part's host thread waits for the convergence count after
 // every Jacobi sweep, and its QR panels are latency-bound; meanwhile the
-// other part's kernels fill the GPU.  Per-sample results do not depend on the
+// other parts' kernels fill the GPU.  Per-sample results do not depend on the
 // split: every random draw is addressed by the global sample id and every
 // decomposition is independent.
+constexpr int kParts = 2;
+
 struct ChainParts {
   int device = 0;
   hipStream_t caller = nullptr;
   std::vector<std::unique_ptr<Chain>> parts;
-  hipStream_t own = nullptr;   // stream of part 1
+  std::vector<hipStream_t> own;   // streams of parts 1, 2, ...
   hipEvent_t ref = nullptr;    // common origin of the kernel timers
   hipEvent_t done = nullptr;
   ~ChainParts() {
     parts.clear();   // frees the parts' device memory
-    if (own) (void)hipStreamDestroy(own);
+    for (hipStream_t s : own) (void)hipStreamDestroy(s);
     if (ref) (void)hipEventDestroy(ref);
     if (done) (void)hipEventDestroy(done);
   }
@@ -538,24 +540,28 @@ int parts_start(ChainParts& cp, const std::function<void(Chain&)>& configure, co
   cp.caller = caller;
   CKH(hipGetDevice(&cp.device));
   const int64_t n = (int64_t)groups.size();
-  const int P = (!one_part && n >= 2) ? 2 : 1;
+  const int P = one_part ? 1 : (int)std::max<int64_t>(1, std::min<int64_t>(kParts, n));
   CKH(hipEventCreateWithFlags(&cp.done, hipEventDisableTiming));
   if (profile) {
     CKH(hipEventCreate(&cp.ref));
     CKH(hipEventRecord(cp.ref, caller));
   }
-  if (P > 1) {   // part 1 starts after the work already queued on the caller's stream
-    CKH(hipStreamCreateWithFlags(&cp.own, hipStreamNonBlocking));
+  if (P > 1) {   // the other parts start after the work already queued on the caller's stream
     CKH(hipEventRecord(cp.done, caller));
-    CKH(hipStreamWaitEvent(cp.own, cp.done, 0));
+    for (int p = 1; p < P; ++p) {
+      hipStream_t s = nullptr;
+      CKH(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+      cp.own.push_back(s);
+      CKH(hipStreamWaitEvent(s, cp.done, 0));
+    }
   }
   int64_t b = 0;
   for (int p = 0; p < P; ++p) {
-    const int64_t e = (p + 1 == P) ? n : (n + 1) / 2;
+    const int64_t e = (n * (p + 1) + P - 1) / P;
     std::unique_ptr<Chain> c(new (std::nothrow) Chain());
     if (!c) return MCTRG_ENOMEM;
     configure(*c);
-    c->st = p == 0 ? caller : cp.own;
+    c->st = p == 0 ? caller : cp.own[p - 1];
     c->nsamp = e - b;
     c->sids.assign(sids.begin() + b, sids.begin() + e);
     const std::vector<int32_t> g(groups.begin() + b, groups.begin() + e);
@@ -819,10 +825,10 @@ int mctrg_run_samples(mctrg_tensor_set* ts, const mctrg_run_config* cfg, int64_t
     size_t freeb = 0, totalb = 0;
     if (hipMemGetInfo(&freeb, &totalb) != hipSuccess) return MCTRG_EDEVICE;
     const double budget = 0.70 * (double)freeb;
-    // a wave of two or more samples runs as two parts, each with its own
+    // a wave of two or more samples runs as up to kParts parts, each with its own
     // per-chain (sample-independent) allocations
     const double fixed = std::max(0.0, (double)per1 - (double)per_sample);
-    const int parts = (cfg->flags & MCTRG_ONE_STREAM) ? 1 : 2;
+    const int parts = (cfg->flags & MCTRG_ONE_STREAM) ? 1 : kParts;
     int64_t wave = (int64_t)std::max(1.0, std::floor((budget - parts * fixed) / (double)per_sample));
     if ((double)per1 > budget) return MCTRG_ENOMEM;
     wave = std::min<int64_t>(wave, (int64_t)members.size());
