@@ -115,6 +115,11 @@ typedef struct {
   int32_t mode;            /* enum mctrg_mode                                         */
   int32_t contract_dtype;  /* enum mctrg_dtype                                        */
   double tau_null;         /* singular values <= tau_null * s_1 count as zero (1e-11) */
+                           /*   With a narrow contraction dtype the rounding of T'   */
+                           /*   gives exactly low-rank tensors singular values near  */
+                           /*   its unit roundoff times s_1 (1e-8..1e-7 for F32);    */
+                           /*   a cut above that (1e-6 for F32) keeps such steps     */
+                           /*   exact.                                               */
   uint32_t flags;          /* MCTRG_RECORD | MCTRG_ASYNC | MCTRG_PROFILE | ONE_STREAM */
   int32_t* record_buf;     /* device, n_samples * n_steps * (4 + 2k) int32, or NULL:  */
                            /*   per step: cA, cB (candidates), kA, kB (kept),        */

@@ -23,6 +23,11 @@ LIB_PATH = os.path.join(_HERE, "libmctrg.so")
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1710_03757_amd.build` "
                       "(the HIP library is the only implementation; there is no fallback)")
+# torch ships its own HIP runtime under the same soname as the one the library
+# links (libamdhip64.so.7).  Loading torch first makes the dynamic loader bind
+# the library to that runtime, so both share one device context; loaded the
+# other way round, the first HIP call of the library fails.
+import torch  # noqa: E402,F401
 _lib = ctypes.CDLL(LIB_PATH)
 
 # ---- constants (include/mctrg.h) ------------------------------------------------

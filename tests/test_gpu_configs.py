@@ -175,3 +175,70 @@ def test_c4_k48_parity():
 def test_c5_k64_parity():
     log("C5 k=64")
     _large_k_parity(64, 0.42, 0.1, 8, 1)
+
+
+_K32_ORACLE = {}
+
+
+def _k32_oracle(i, n_steps, k, tau):
+    """Oracle chains of the k = 32 sampled parity test, shared by its cases."""
+    key = (i, n_steps, k, tau)
+    if key not in _K32_ORACLE:
+        _K32_ORACLE[key] = trg.run_shared(ising.site_tensor(BETA_C, 0.0), n_steps, k, 0, i, tau_null=tau)
+    return _K32_ORACLE[key]
+
+
+@pytest.mark.parametrize("dtype,tau", [("f64", 1e-11), ("f32", 1e-6), ("f32", 1e-11)])
+def test_k32_batch256_sampled_parity(dtype, tau):
+    """The timed configuration itself: 256 samples at k = 32, beta_c, h = 0,
+    seed 0 (two parts of 128 on two streams, steady unfoldings of 1024 rows
+    from step 7 on), nine steps, of which four samples spanning both parts are
+    recomputed by the oracle one by one.
+
+    FP64 contraction: the selections must agree step by step, and ln c to
+    1e-9 where every kept value exceeds 1e-6 s_1, else 1e-4 (the bound of
+    the k = 48 and 64 chains).
+
+    FP32 contraction (the timed dtype): T' carries a relative rounding of
+    about 2^-24 per operand, which gives the exactly low-rank early tensors
+    (rank 4 and 16 at steps 2 and 4) rounding-noise singular values of
+    1e-8..1e-7 s_1.  With the candidate cut at 1e-6 s_1, above that floor,
+    both sides take the same decisions: the selections must agree.  At the
+    default cut of 1e-11 s_1 those noise values are candidates on the GPU
+    and not in the FP64 oracle, so only the values are compared.  Either
+    way ln c must agree to 1e-5 per step and ln|Z~| to 1e-6 per site
+    (measured: <= 1.3e-6 and 2e-8..1e-7)."""
+    torch, m = need_gpu()
+    B, k, n_steps = 256, 32, 9
+    picks = [0, 127, 128, 255]
+    log(f"k=32 batch 256 sampled parity ({dtype}, tau_null {tau:g})")
+    ts = m.init_tensor("site", [BETA_C], [0.0])
+    r = m.run_samples(ts, B, n_steps=n_steps, k=k, seed=0, dtype=dtype, want_ln_c=True, record=True,
+                      tau_null=tau)
+    assert r.status == m.OK
+    ln, lnc, rec = r.ln_abs_Z.cpu().numpy(), r.ln_c.cpu().numpy(), r.record.cpu().numpy()
+    assert np.all(r.sign.cpu().numpy() != 0) and np.all(np.isfinite(ln))
+    N = 2.0 ** n_steps
+    compare_sel = dtype == "f64" or tau >= 1e-6
+    matched = 0
+    for i in picks:
+        o = _k32_oracle(i, n_steps, k, tau)
+        same = all(list(st.splits[0].sel) == [int(x) for x in rec[i, s, 4:4 + int(rec[i, s, 2])]] and
+                   list(st.splits[1].sel) == [int(x) for x in rec[i, s, 4 + k:4 + k + int(rec[i, s, 3])]]
+                   for s, st in enumerate(o.records))
+        d = abs(ln[i] - o.ln_abs_Z) / N
+        dc = float(np.max(np.abs(lnc[i] - np.asarray(o.ln_c))))
+        log(f"sample {i}: same selections {same}, max |d ln c| {dc:.3e}, |d lnZ|/site {d:.3e}")
+        if compare_sel and not same:
+            continue
+        matched += 1
+        if dtype == "f64":
+            for s, st in enumerate(o.records):
+                smin = min(float(np.min(sp.sigma[sp.sel] / sp.sigma[0])) if len(sp.sel) else 1.0
+                           for sp in st.splits)
+                tol = 1e-9 if smin > 1e-6 else 1e-4
+                assert abs(lnc[i, s] - o.ln_c[s]) < tol, (i, s, smin, lnc[i, s], o.ln_c[s])
+        else:
+            assert dc < 1e-5, (i, dc)
+        assert d < 1e-6, (i, d)
+    assert matched >= 3
