@@ -4,7 +4,7 @@
 Workload (default): the k = 32 form of the batched configuration - 2-D
 Ising site tensors at beta_c, h = 0, a chain of 30 coarse-graining steps
 (2^30 sites), FP32 coarse-graining GEMM, FP64 decomposition, sampling and
-log-normalisation.  A "step" is one full TRG step of the hot path (unfold,
+log-normalisation, candidate cut tau_null = 1e-6 s_1 (see TAU_NULL).  A "step" is one full TRG step of the hot path (unfold,
 Jacobi SVD of both splits, subset sampling and reweighting, factors,
 contraction, normalisation) over the whole batch of samples.  The first
 ``--warmup`` steps (the ramp-up of the bond dimension 2 -> 4 -> 16 -> 32 and
@@ -12,12 +12,14 @@ one steady step) are untimed; the next ``--steps`` steps are timed between
 device synchronisations, followed by the final trace and the estimator.
 
 Output: one JSON line with the throughput in sample-steps/s, a roofline
-record of the dominant kernel (the Jacobi rotation kernel, timed live with
-HIP events around every launch on the library's stream; its HBM traffic per
-launch from the committed rocprofv3 counter summary when that was taken on
-the same kernel source), the whole-step roofline fraction, the MFMA rate of
-the coarse-graining GEMM, the accuracy against the CPU oracle on the first
-samples, and the oracle's own rate on the host cores.
+record of the dominant kernel (the 128-column trailing update of the QR
+preconditioning, timed live with HIP events around every launch on the
+library's streams; its HBM traffic per launch from the committed rocprofv3
+counter summary when that was taken on the same kernel source and workload),
+the same timing for the Jacobi rotation kernel, the whole-step roofline
+fraction, the MFMA rate of the coarse-graining GEMM, the accuracy against the
+CPU oracle on the first samples, and the oracle's own rate on the host
+cores.
 """
 from __future__ import annotations
 
@@ -37,23 +39,34 @@ METRIC = "TRG sample-steps/s at χ=32 + MFMA util; |Δ ln Z|/site vs FP64 oracle
 PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0, "fp8": 5000.0}
 PEAK_HBM_TBS = 8.0
 JACOBI_KERNEL = "jacobi_round64_kernel"
-JACOBI_SRC = os.path.join(ROOT, "paper_1710_03757_amd", "csrc", "k_jacobi.hip")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "jacobi_traffic_k32_batch256.json")
+QR128_KERNEL = "qr_trailing128_kernel"
+KERNEL_SRC = {JACOBI_KERNEL: os.path.join(ROOT, "paper_1710_03757_amd", "csrc", "k_jacobi.hip"),
+              QR128_KERNEL: os.path.join(ROOT, "paper_1710_03757_amd", "csrc", "k_qr.hip")}
+# Candidate cut tau_null (singular values <= tau_null * s_1 count as zero) per
+# contraction dtype: about ten times the noise floor of the tensor the FP64
+# decomposition sees.  For an FP64 contraction that floor is the SVD's own
+# rounding (n eps), hence 1e-11; an FP32 contraction rounds T' at 2^-24 per
+# operand, which gives singular values of 1e-8..1e-7 s_1 that carry no signal,
+# hence 1e-6 (the library then also leaves rows below a tenth of the cut
+# unrotated).  BF16 and FP8 keep the FP64 cut: ten times their rounding floor
+# would cut most of the spectrum.
+TAU_NULL = {"f64": 1e-11, "f32": 1e-6, "bf16": 1e-11, "fp8": 1e-11}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k32_batch256.json")
 
 
-def measured_traffic(k, batch, parts):
-    """HBM bytes per dispatch of the Jacobi rotation kernel from the committed
-    rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE summary, if it was taken on the
-    same kernel source and workload shape (batch split in the same number of
-    parts); otherwise None."""
+def measured_traffic(kernel, k, batch, parts, tau):
+    """HBM bytes per dispatch of a kernel from the committed rocprofv3 --pmc
+    FETCH_SIZE / WRITE_SIZE summary, if it was taken on the same kernel
+    source and workload shape (batch split in the same number of parts, same
+    candidate cut); otherwise None."""
     import hashlib
     try:
-        rec = json.load(open(TRAFFIC_FILE))
-        sha = hashlib.sha256(open(JACOBI_SRC, "rb").read()).hexdigest()
-    except (OSError, ValueError):
+        rec = json.load(open(TRAFFIC_FILE))[kernel]
+        sha = hashlib.sha256(open(KERNEL_SRC[kernel], "rb").read()).hexdigest()
+    except (OSError, ValueError, KeyError):
         return None
     if rec.get("source_sha256") != sha or rec.get("k") != k or rec.get("batch") != batch or \
-            rec.get("parts", 1) != parts:
+            rec.get("parts", 1) != parts or rec.get("tau_null") != tau:
         return None
     return rec
 
@@ -127,6 +140,8 @@ def main():
     ap.add_argument("--beta", type=float, default=BETA_C)
     ap.add_argument("--h", type=float, default=0.0)
     ap.add_argument("--chain-steps", type=int, default=30)
+    ap.add_argument("--tau-null", type=float, default=None,
+                    help="candidate cut (default: per contraction dtype, see TAU_NULL)")
     ap.add_argument("--cpu-samples", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
@@ -151,7 +166,8 @@ def main():
     k, B = args.k, args.batch
     print(f"[bench] k={k} batch={B} dtype={args.dtype} warmup={args.warmup} steps={args.steps}", flush=True)
     ts = m.init_tensor("site", [args.beta], [args.h])
-    chain = m.Chain(ts, B, n_steps=args.chain_steps, k=k, dtype=args.dtype, seed=0, profile=True)
+    tau = TAU_NULL[args.dtype] if args.tau_null is None else args.tau_null
+    chain = m.Chain(ts, B, n_steps=args.chain_steps, k=k, dtype=args.dtype, seed=0, profile=True, tau_null=tau)
     for s in range(args.warmup):
         chain.step(1)
         print(f"[bench] warmup step {s} done, sweeps={chain.profile()['last_sweeps']}", flush=True)
@@ -185,27 +201,42 @@ def main():
     gl = p1["gemm_launches"] - p0["gemm_launches"]
     gms = p1["gemm_ms"] - p0["gemm_ms"]
     gbusy = p1["gemm_busy_ms"] - p0["gemm_busy_ms"]
-    # dominant kernel: the Jacobi rotation kernel.  Every round is one
-    # dispatch per part and the parts' dispatches run concurrently, so a
-    # round's duration is the union of its dispatches' intervals: achieved =
-    # algorithmic decomposition flops of the timed steps (per round x rounds)
-    # over the union of all Jacobi dispatch intervals.  avg_launch_ms is the
-    # mean duration of one dispatch (what rocprofv3 reports per dispatch).
-    alg = decomposition_flops(k) * B * args.steps
-    avg_launch_ms = jms / max(jl, 1)
-    rounds = jl / max(parts, 1)
-    achieved = alg / (jbusy / 1e3) / 1e12 if jbusy > 0 else None
-    tr = measured_traffic(k, B, parts)
-    traffic = None
-    if tr:
-        traffic = tr["fetch_bytes_per_launch"] + tr["write_bytes_per_launch"]
-    roofline = {"bound": "mfma", "kernel": JACOBI_KERNEL, "achieved": achieved, "peak": PEAK_TFLOPS["f64"],
+    ql = p1["qr128_launches"] - p0["qr128_launches"]
+    qms = p1["qr128_ms"] - p0["qr128_ms"]
+    qbusy = p1["qr128_busy_ms"] - p0["qr128_busy_ms"]
+    qflops = p1["qr128_flops"] - p0["qr128_flops"]
+
+    def traffic_of(kernel, launches, busy):
+        tr = measured_traffic(kernel, k, B, parts, tau)
+        t = tr["fetch_bytes_per_launch"] + tr["write_bytes_per_launch"] if tr else None
+        return t, (t * launches / (busy / 1e3) / 1e12) if (t and busy > 0) else None
+
+    # dominant kernel: the 128-column trailing update of the second to fifth
+    # QR (the largest busy time of the step).  Its algorithmic flops are the
+    # dense count of C <- C - V (T^T (V^T C)) summed by the library over the
+    # timed launches; the parts' launches run concurrently, so achieved =
+    # those flops over the union of the launch intervals (busy_ms), and
+    # avg_launch_ms is the mean duration of one dispatch (what rocprofv3
+    # reports per dispatch).
+    achieved = qflops / (qbusy / 1e3) / 1e12 if qbusy > 0 else None
+    traffic, rate = traffic_of(QR128_KERNEL, ql, qbusy)
+    roofline = {"bound": "mfma", "kernel": QR128_KERNEL, "achieved": achieved, "peak": PEAK_TFLOPS["f64"],
                 "unit": "TFLOP/s", "frac": (achieved / PEAK_TFLOPS["f64"]) if achieved else None, "traffic": traffic,
                 "traffic_unit": "bytes per dispatch (HBM, FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-                "traffic_rate_TBs": (traffic * jl / (jbusy / 1e3) / 1e12) if (traffic and jbusy > 0) else None,
-                "avg_launch_ms": avg_launch_ms, "launches": jl, "parts": parts,
-                "avg_round_ms": jbusy / rounds if rounds else None, "busy_ms": jbusy,
-                "share_of_step_time": jbusy / ms_total if ms_total else None}
+                "traffic_rate_TBs": rate, "avg_launch_ms": qms / max(ql, 1), "launches": ql, "parts": parts,
+                "flops_per_launch": qflops / max(ql, 1), "busy_ms": qbusy,
+                "share_of_step_time": qbusy / ms_total if ms_total else None}
+    # the Jacobi rotation kernel (the dominant kernel before the candidate cut
+    # was tied to the contraction's rounding floor): timing and traffic only
+    jtraffic, jrate = traffic_of(JACOBI_KERNEL, jl, jbusy)
+    jacobi = {"kernel": JACOBI_KERNEL, "avg_launch_ms": jms / max(jl, 1), "launches": jl, "busy_ms": jbusy,
+              "share_of_step_time": jbusy / ms_total if ms_total else None, "traffic": jtraffic,
+              "traffic_rate_TBs": jrate}
+    # the whole FP64 decomposition against the algorithmic count of the
+    # method ((14/3) k^6 per sample-step), over the step time
+    decomposition = {"algorithmic_flops_per_sample_step": decomposition_flops(k),
+                     "achieved_over_step_time": decomposition_flops(k) * B * args.steps / (ms_total / 1e3) / 1e12,
+                     "unit": "TFLOP/s", "peak": PEAK_TFLOPS["f64"]}
     galg = gemm_flops(k) * B * args.steps
     gemm = {"kernel": f"gemm_tn_kernel<{args.dtype}>", "achieved": galg / (gbusy / 1e3) / 1e12 if gbusy > 0 else None,
             "peak": PEAK_TFLOPS[args.dtype], "unit": "TFLOP/s", "avg_launch_ms": gms / max(gl, 1), "launches": gl,
@@ -234,9 +265,11 @@ def main():
         "config": {"workload": f"2-D Ising site tensors, beta={args.beta:.6f}, h={args.h}, k={k}, chain of "
                                f"{args.chain_steps} steps (2^{args.chain_steps} sites), shared chain, "
                                f"steady-state steps {args.warmup}..{args.warmup + args.steps - 1}",
-                   "k": k, "batch": B, "contract_dtype": args.dtype, "mode": "shared",
+                   "k": k, "batch": B, "contract_dtype": args.dtype, "mode": "shared", "tau_null": tau,
                    "decomposition": "FP64 one-sided block Jacobi"},
         "roofline": roofline,
+        "jacobi": jacobi,
+        "decomposition": decomposition,
         "end_to_end_roofline_frac": t_ideal / t_meas,
         "mfma_contraction": gemm,
         "jacobi_sweeps_per_step": sweeps,
@@ -255,7 +288,8 @@ def main():
         out["accuracy"] = {"abs_dlnZ_per_site_vs_f64_oracle": diffs, "samples": len(ores),
                            "signs_equal": bool(all(int(sg[i]) == o[0] for i, o in enumerate(ores))),
                            "lattice_sites": N, "note": "same Philox draws; GPU contraction in "
-                                                       f"{args.dtype}, oracle FP64"}
+                                                       f"{args.dtype} with tau_null {tau:g}, oracle FP64 "
+                                                       "with tau_null 1e-11"}
     if args.copy_probe_mb:
         src = torch.ones(args.copy_probe_mb * (1 << 20) // 4, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)

@@ -115,11 +115,14 @@ typedef struct {
   int32_t mode;            /* enum mctrg_mode                                         */
   int32_t contract_dtype;  /* enum mctrg_dtype                                        */
   double tau_null;         /* singular values <= tau_null * s_1 count as zero (1e-11) */
-                           /*   With a narrow contraction dtype the rounding of T'   */
-                           /*   gives exactly low-rank tensors singular values near  */
-                           /*   its unit roundoff times s_1 (1e-8..1e-7 for F32);    */
-                           /*   a cut above that (1e-6 for F32) keeps such steps     */
-                           /*   exact.                                               */
+                           /*   and are never drawn; rows of the decomposition below */
+                           /*   max(2^-48, tau_null / 10) of the largest row are not */
+                           /*   rotated (their values stay below the cut).  With a  */
+                           /*   narrow contraction dtype the rounding of T' gives    */
+                           /*   singular values near its unit roundoff times s_1     */
+                           /*   (1e-8..1e-7 for F32) that carry no signal: a cut     */
+                           /*   above them (1e-6 for F32) drops them from both the   */
+                           /*   candidates and the rotations.                        */
   uint32_t flags;          /* MCTRG_RECORD | MCTRG_ASYNC | MCTRG_PROFILE | ONE_STREAM */
   int32_t* record_buf;     /* device, n_samples * n_steps * (4 + 2k) int32, or NULL:  */
                            /*   per step: cA, cB (candidates), kA, kB (kept),        */
@@ -214,6 +217,12 @@ typedef struct {
   int32_t parts;            /* parts of the chain (1 or 2)                       */
   int32_t step_sweeps[64];  /* Jacobi sweeps of every step done (the most over
                                the step's decompositions), steps 0..63          */
+  double qr128_ms;          /* summed duration of the 128-column trailing updates
+                               of the second to fifth QR (qr_trailing128)        */
+  int64_t qr128_launches;   /* number of those launches                          */
+  double qr128_busy_ms;     /* union of their intervals over all parts           */
+  double qr128_flops;       /* their algorithmic flops: per job and launch
+                               4 m 128 c + 128^2 c (m rows, c columns updated)  */
 } mctrg_chain_profile;
 /* Timings are collected only when cfg->flags has MCTRG_PROFILE. */
 int mctrg_chain_get_profile(const mctrg_chain* ch, mctrg_chain_profile* out);

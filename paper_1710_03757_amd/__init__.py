@@ -68,7 +68,9 @@ class ChainProfile(ctypes.Structure):
                 ("gemm_launches", ctypes.c_int64), ("steps_done", ctypes.c_int32), ("last_sweeps", ctypes.c_int32),
                 ("last_pairs", ctypes.c_int32 * 64), ("last_active", ctypes.c_int32 * 64),
                 ("jacobi_busy_ms", ctypes.c_double), ("gemm_busy_ms", ctypes.c_double), ("parts", ctypes.c_int32),
-                ("step_sweeps", ctypes.c_int32 * 64)]
+                ("step_sweeps", ctypes.c_int32 * 64), ("qr128_ms", ctypes.c_double),
+                ("qr128_launches", ctypes.c_int64), ("qr128_busy_ms", ctypes.c_double),
+                ("qr128_flops", ctypes.c_double)]
 
     def as_dict(self):
         d = {f: getattr(self, f) for f, _ in self._fields_}

@@ -181,7 +181,8 @@ struct Chain {
   int32_t *h_src = nullptr, *h_split = nullptr, *h_cjobs = nullptr;
   uint64_t* h_rng = nullptr;
   int64_t max_jobs = 0, max_out = 0;
-  KernelTimer tj, tg;
+  KernelTimer tj, tg, tq;   // Jacobi rounds, GEMMs, 128-column QR trailing updates
+  double tq_flops = 0.0;    // algorithmic flops of the timed QR trailing updates
   int last_sweeps = 0;
   int sweep_hist[2 * kMaxSweeps] = {};   // last decomposition: (pairs rotated, jobs active) per sweep
   int step_sweeps[64] = {};               // Jacobi sweeps of every step
@@ -372,7 +373,7 @@ int chain_start(Chain& c, const mctrg_tensor_set* ts, const std::vector<int32_t>
   CKH(launch_izero(c.nsamp, c.failed, c.st));
   CKH(hipMemsetAsync(c.lnc_steps, 0, sizeof(double) * c.nsamp * c.n_steps, c.st));
   CKH(hipStreamSynchronize(c.st));
-  c.tj.enabled = c.tg.enabled = (c.flags & MCTRG_PROFILE) != 0;
+  c.tj.enabled = c.tg.enabled = c.tq.enabled = (c.flags & MCTRG_PROFILE) != 0;
   return MCTRG_OK;
 }
 
@@ -427,7 +428,7 @@ int chain_step(Chain& c) {
   double* Wj = c.W;      // the Jacobi workspace
   if (qr5) {
     CKH(run_qr5_precondition(nj, sh.n, sh.D, sh.n_pad, c.Ta, c.src, c.split, c.perm, c.dpos, c.S, c.W, c.Tws2, c.W2, c.Tws,
-                             c.W3, c.Tscr, c.colmap, c.colnorm, c.st));
+                             c.W3, c.Tscr, c.colmap, c.colnorm, c.st, c.tq.enabled ? &c.tq : nullptr, &c.tq_flops));
     rows = c.W3;         // c.W / c.Tws2 keep Q2, c.S / c.Tws keep Q4
     Wj = c.W2;
   } else if (qr) {
@@ -438,9 +439,11 @@ int chain_step(Chain& c) {
     CKH(launch_unfold(nj, sh.D, sh.n_pad, c.Ta, c.src, c.split, c.W2, c.st));
     CKH(launch_iota(nj, sh.n_pad, c.perm, c.st));
   }
-  // rows at the noise floor move behind the active ones and are not rotated
+  // rows at the noise floor or below a tenth of the candidate cut move behind
+  // the active ones and are not rotated
   int nb_max = 0;
-  CKH(run_deflate(nj, sh.n_pad, rows, Wj, c.nb_job, c.dnrm, c.dpos, c.jw.counter, c.jw.counter_host, &nb_max, c.st));
+  CKH(run_deflate(nj, sh.n_pad, c.tau, rows, Wj, c.nb_job, c.dnrm, c.dpos, c.jw.counter, c.jw.counter_host, &nb_max,
+                  c.st));
   CKH(run_jacobi(nj, sh.n_pad, Wj, c.jw, kMaxSweeps, c.st, c.tj.enabled ? &c.tj : nullptr, &c.last_sweeps, c.nb_job,
                  nb_max, c.sweep_hist));
   if (s < 64) c.step_sweeps[s] = c.last_sweeps;
@@ -485,6 +488,7 @@ int chain_step(Chain& c) {
   if (c.tg.enabled) {
     CKH(hipStreamSynchronize(c.st));
     CKH(c.tg.collect());
+    CKH(c.tq.collect());
   }
   return MCTRG_OK;
 }
@@ -568,7 +572,7 @@ int parts_start(ChainParts& cp, const std::function<void(Chain&)>& configure, co
     const std::vector<int64_t> oi(out_index.begin() + b, out_index.begin() + e);
     const int rc = chain_start(*c, ts, g, oi);
     if (rc != MCTRG_OK) return rc;
-    c->tj.ref = c->tg.ref = cp.ref;
+    c->tj.ref = c->tg.ref = c->tq.ref = cp.ref;
     cp.parts.push_back(std::move(c));
     b = e;
   }
@@ -935,12 +939,15 @@ int mctrg_chain_finish(mctrg_chain* ch, int8_t* out_sign, double* out_ln_abs_Z, 
 int mctrg_chain_get_profile(const mctrg_chain* ch, mctrg_chain_profile* out) {
   if (!ch || !out) return MCTRG_EINVAL;
   std::memset(out, 0, sizeof(*out));
-  std::vector<std::pair<float, float>> js, gs;
+  std::vector<std::pair<float, float>> js, gs, qs;
   for (const auto& c : ch->cp.parts) {
     out->jacobi_ms += c->tj.ms;
     out->jacobi_launches += c->tj.launches;
     out->gemm_ms += c->tg.ms;
     out->gemm_launches += c->tg.launches;
+    out->qr128_ms += c->tq.ms;
+    out->qr128_launches += c->tq.launches;
+    out->qr128_flops += c->tq_flops;
     out->last_sweeps = std::max(out->last_sweeps, c->last_sweeps);
     for (int s = 0; s < 64; ++s) out->step_sweeps[s] = std::max(out->step_sweeps[s], c->step_sweeps[s]);
     for (int s = 0; s < 64; ++s) {
@@ -950,10 +957,12 @@ int mctrg_chain_get_profile(const mctrg_chain* ch, mctrg_chain_profile* out) {
     }
     js.insert(js.end(), c->tj.spans.begin(), c->tj.spans.end());
     gs.insert(gs.end(), c->tg.spans.begin(), c->tg.spans.end());
+    qs.insert(qs.end(), c->tq.spans.begin(), c->tq.spans.end());
   }
   out->steps_done = ch->steps;
   out->jacobi_busy_ms = union_ms(std::move(js));
   out->gemm_busy_ms = union_ms(std::move(gs));
+  out->qr128_busy_ms = union_ms(std::move(qs));
   out->parts = (int32_t)ch->cp.parts.size();
   return MCTRG_OK;
 }

@@ -737,11 +737,15 @@ hipError_t run_jacobi(int64_t njobs, int n_pad, double* W, const JacobiWork& wk,
 }
 
 // ---------------------------------------------------------------------------
-// Noise-floor deflation.  Rows whose norm is at most 2^-48 of the largest row
-// norm are moved behind the others (stable partition) and excluded from the
-// rotations: leaving them unrotated perturbs the singular values of the rest
-// by at most their norm (Weyl), i.e. at the rounding level of an FP64 SVD and
-// far below the candidate threshold tau_null * s_1.  nb_job receives the
+// Noise-floor deflation.  Rows whose norm is at most floor_rel times the
+// largest row norm are moved behind the others (stable partition) and
+// excluded from the rotations.  floor_rel is 2^-48 (the rounding level of an
+// FP64 SVD) or a tenth of the candidate cut tau_null, whichever is larger:
+// such a row has norm <= 0.1 tau_null s_1 (the largest row norm is at most
+// s_1), so its singular value can never be a candidate, and leaving it
+// unrotated perturbs the singular values of the rest by at most its norm
+// (Weyl; to second order when, as after the QR preconditioning, it is nearly
+// orthogonal to the larger rows).  nb_job receives the
 // number of row blocks (even, at least 2) that cover the active rows.
 // Three kernels: squared row norms and the row copy (one wave per row), and
 // the partition between them (one workgroup per job); n_pad <= 4096.
@@ -759,11 +763,12 @@ __global__ __launch_bounds__(256) void deflate_norms_kernel(int n_pad, const dou
   if (lane == 0) nrm[(size_t)job * n_pad + r] = sq;
 }
 
-// Per job: the rows above the noise floor (squared norm > 2^-96 of the
+// Per job: the rows above the floor (squared norm > floor_sq times the
 // largest) keep their order at the front, the others follow in order
 // (stable partition by a block scan, n_pad <= 4096: m = n_pad / 256 rows per
 // thread); nb_job = the number of row blocks to rotate (even, >= 2).
-__global__ __launch_bounds__(256) void deflate_plan_kernel(int n_pad, int brows, const double* __restrict__ nrm,
+__global__ __launch_bounds__(256) void deflate_plan_kernel(int n_pad, int brows, double floor_sq,
+                                                           const double* __restrict__ nrm,
                                                            int32_t* __restrict__ newpos, int* __restrict__ nb_job) {
   const int64_t job = blockIdx.x;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -775,7 +780,7 @@ __global__ __launch_bounds__(256) void deflate_plan_kernel(int n_pad, int brows,
   for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o));
   if (lane == 0) red[wave] = mx;
   __syncthreads();
-  const double thr = fmax(fmax(red[0], red[1]), fmax(red[2], red[3])) * 0x1.0p-96;
+  const double thr = fmax(fmax(red[0], red[1]), fmax(red[2], red[3])) * floor_sq;
   const int m = (n_pad + 255) / 256, r0 = tid * m;
   int own = 0;
   for (int q = 0; q < m; ++q)
@@ -829,14 +834,16 @@ __global__ void max_int_kernel(int64_t n, const int* __restrict__ v, int* __rest
   }
 }
 
-hipError_t run_deflate(int64_t njobs, int n_pad, const double* Win, double* Wout, int* nb_job, double* nrm,
-                       int32_t* newpos, int* scratch_dev, int* scratch_host, int* nb_max, hipStream_t stream) {
+hipError_t run_deflate(int64_t njobs, int n_pad, double tau_null, const double* Win, double* Wout, int* nb_job,
+                       double* nrm, int32_t* newpos, int* scratch_dev, int* scratch_host, int* nb_max,
+                       hipStream_t stream) {
   if (njobs == 0) { *nb_max = 2; return hipSuccess; }
   if (n_pad > 4096) return hipErrorInvalidValue;
+  const double floor_rel = fmax(0x1.0p-48, 0.1 * tau_null);
   const dim3 rg((unsigned)ceil_div(n_pad, 4), (unsigned)njobs);
   hipLaunchKernelGGL(deflate_norms_kernel, rg, dim3(256), 0, stream, n_pad, Win, nrm);
   hipLaunchKernelGGL(deflate_plan_kernel, dim3((unsigned)njobs), dim3(256), 0, stream, n_pad, jacobi_block_rows(n_pad),
-                     (const double*)nrm, newpos, nb_job);
+                     floor_rel * floor_rel, (const double*)nrm, newpos, nb_job);
   hipLaunchKernelGGL(deflate_copy_kernel, rg, dim3(256), 0, stream, n_pad, Win, (const int32_t*)newpos, Wout);
   hipLaunchKernelGGL(max_int_kernel, dim3(1), dim3(1024), 0, stream, njobs, nb_job, scratch_dev);
   hipError_t e = hipMemcpyAsync(scratch_host, scratch_dev, sizeof(int), hipMemcpyDeviceToHost, stream);

@@ -1383,7 +1383,8 @@ __global__ void r_rows_kernel(int n_pad, const double* __restrict__ S, double* _
 // through the map, which ends as the logical -> stored column permutation).
 template <int NT, int MAXQ, int PW>
 static hipError_t qr_factor_t(int64_t njobs, int n_pad, double* S, double* Tws, bool keep_T, int32_t* colmap,
-                              double* colnorm, double* T64, bool lower, hipStream_t stream) {
+                              double* colnorm, double* T64, bool lower, hipStream_t stream, KernelTimer* tq,
+                              double* tq_flops) {
   if (PW == 32 && !colmap && T64) {
     // Steps of 128 columns, each two 64-column blocks A (j .. j + 63) and B
     // (j + 64 .. j + 127) of two 32-column panels: A is factored and
@@ -1412,8 +1413,20 @@ static hipError_t qr_factor_t(int64_t njobs, int n_pad, double* S, double* Tws, 
       if (!block64(j + 64, T64 + 4096)) break;
       hipLaunchKernelGGL(qr_t128_kernel, dim3((unsigned)njobs), dim3(256), 0, stream, n_pad, j, (const double*)S,
                          T64);
+      if (tq) {
+        const hipError_t e = tq->begin(stream);
+        if (e != hipSuccess) return e;
+      }
       hipLaunchKernelGGL(qr_trailing128_kernel, xcd_tile_grid(ceil_div(n_pad - j - 128, 64), njobs), dim3(256), 0,
                          stream, njobs, n_pad, j, S, (const double*)T64, (int)(lower && j == 0));
+      if (tq) {
+        const hipError_t e = tq->end(stream);
+        if (e != hipSuccess) return e;
+        // dense count of C <- C - V (T^T (V^T C)): m = n_pad - j rows,
+        // c = n_pad - j - 128 columns, V m x 128, T triangular
+        const double m = n_pad - j, c = n_pad - j - 128;
+        *tq_flops += (double)njobs * (4.0 * m * 128.0 * c + 128.0 * 128.0 * c);
+      }
     }
     return hipGetLastError();
   }
@@ -1485,11 +1498,15 @@ static hipError_t qr_factor_t(int64_t njobs, int n_pad, double* S, double* Tws, 
 // T64 (kQrBlockScratch doubles per job, or NULL): scratch that enables the
 // 64-column blocks when the columns are not re-ordered (n_pad <= 1024).
 // lower: S is lower triangular on entry (the transpose of an R factor).
+// tq / tq_flops (or NULL): HIP-event timer of the 128-column trailing
+// updates and the running sum of their algorithmic flops.
 static hipError_t qr_factor(int64_t njobs, int n_pad, double* S, double* Tws, bool keep_T, int32_t* colmap,
-                            double* colnorm, hipStream_t stream, double* T64 = nullptr, bool lower = false) {
+                            double* colnorm, hipStream_t stream, double* T64 = nullptr, bool lower = false,
+                            KernelTimer* tq = nullptr, double* tq_flops = nullptr) {
   if (n_pad <= 1024)
-    return qr_factor_t<256, 4, 32>(njobs, n_pad, S, Tws, keep_T, colmap, colnorm, T64, lower, stream);
-  return qr_factor_t<512, 8, 8>(njobs, n_pad, S, Tws, keep_T, nullptr, nullptr, nullptr, false, stream);
+    return qr_factor_t<256, 4, 32>(njobs, n_pad, S, Tws, keep_T, colmap, colnorm, T64, lower, stream, tq, tq_flops);
+  return qr_factor_t<512, 8, 8>(njobs, n_pad, S, Tws, keep_T, nullptr, nullptr, nullptr, false, stream, nullptr,
+                                nullptr);
 }
 
 static hipError_t order_and_unfold(int64_t njobs, int n, int D, int n_pad, const double* T, const int32_t* src,
@@ -1570,9 +1587,10 @@ hipError_t run_qr3_precondition(int64_t njobs, int n, int D, int n_pad, const do
 hipError_t run_qr5_precondition(int64_t njobs, int n, int D, int n_pad, const double* T, const int32_t* src,
                                 const int32_t* split, int32_t* perm, int32_t* iperm, double* S1, double* W1, double* Tws2,
                                 double* W2, double* Tws4, double* W3, double* Tscr, int32_t* colmap, double* colnorm,
-                                hipStream_t stream) {
+                                hipStream_t stream, KernelTimer* tq, double* tq_flops) {
   if (njobs == 0) return hipSuccess;
   if (n_pad > 1024) return hipErrorInvalidValue;
+  if (tq && !tq_flops) return hipErrorInvalidValue;
   hipError_t e = order_and_unfold(njobs, n, D, n_pad, T, src, split, perm, iperm, S1, stream);
   if (e != hipSuccess) return e;
   double* T64 = Tscr + (size_t)njobs * 2048;
@@ -1580,16 +1598,16 @@ hipError_t run_qr5_precondition(int64_t njobs, int n, int D, int n_pad, const do
   if (e != hipSuccess) return e;
   const dim3 rg(n_pad / 32, n_pad / 32, (unsigned)njobs);
   hipLaunchKernelGGL(r_rows_kernel, rg, dim3(256), 0, stream, n_pad, S1, W1, (const int32_t*)colmap);
-  e = qr_factor(njobs, n_pad, W1, Tws2, true, nullptr, nullptr, stream, Tscr, true);
+  e = qr_factor(njobs, n_pad, W1, Tws2, true, nullptr, nullptr, stream, Tscr, true, tq, tq_flops);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(r_rows_kernel, rg, dim3(256), 0, stream, n_pad, W1, W2, (const int32_t*)nullptr);
-  e = qr_factor(njobs, n_pad, W2, Tscr, false, nullptr, nullptr, stream, T64, true);
+  e = qr_factor(njobs, n_pad, W2, Tscr, false, nullptr, nullptr, stream, T64, true, tq, tq_flops);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(r_rows_kernel, rg, dim3(256), 0, stream, n_pad, W2, S1, (const int32_t*)nullptr);
-  e = qr_factor(njobs, n_pad, S1, Tws4, true, nullptr, nullptr, stream, Tscr, true);
+  e = qr_factor(njobs, n_pad, S1, Tws4, true, nullptr, nullptr, stream, Tscr, true, tq, tq_flops);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(r_rows_kernel, rg, dim3(256), 0, stream, n_pad, S1, W2, (const int32_t*)nullptr);
-  e = qr_factor(njobs, n_pad, W2, Tscr, false, nullptr, nullptr, stream, T64, true);
+  e = qr_factor(njobs, n_pad, W2, Tscr, false, nullptr, nullptr, stream, T64, true, tq, tq_flops);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(r_rows_kernel, rg, dim3(256), 0, stream, n_pad, W2, W3, (const int32_t*)nullptr);
   return hipGetLastError();

@@ -133,12 +133,14 @@ hipError_t run_jacobi(int64_t njobs, int n_pad, double* W, const JacobiWork& wk,
                       hipStream_t stream, KernelTimer* timer = nullptr, int* sweeps_done = nullptr,
                       const int* nb_job = nullptr, int nb_max = 0, int* history = nullptr);
 // Noise-floor deflation: Wout = rows of Win with the active rows (norm >
-// 2^-48 of the largest) first, in order, the others after them; nb_job =
-// the even number of Jacobi row blocks covering the active rows; the maximum
-// over jobs is returned in *nb_max (synchronises the stream).  nrm / newpos:
-// n_pad doubles / int32 per job of scratch; n_pad <= 4096.
-hipError_t run_deflate(int64_t njobs, int n_pad, const double* Win, double* Wout, int* nb_job, double* nrm,
-                       int32_t* newpos, int* scratch_dev, int* scratch_host, int* nb_max, hipStream_t stream);
+// max(2^-48, tau_null / 10) times the largest) first, in order, the others
+// after them; nb_job = the even number of Jacobi row blocks covering the
+// active rows; the maximum over jobs is returned in *nb_max (synchronises the
+// stream).  nrm / newpos: n_pad doubles / int32 per job of scratch;
+// n_pad <= 4096.
+hipError_t run_deflate(int64_t njobs, int n_pad, double tau_null, const double* Win, double* Wout, int* nb_job,
+                       double* nrm, int32_t* newpos, int* scratch_dev, int* scratch_host, int* nb_max,
+                       hipStream_t stream);
 // QR preconditioning (k_qr.hip): perm[j] (n_pad) orders the columns of the
 // unfolding by decreasing norm, S (n_pad^2 per job) holds M P column-wise
 // and is overwritten by V and R, Tws (1024 per job) is scratch, and W
@@ -166,11 +168,15 @@ hipError_t run_qr3_precondition(int64_t njobs, int n, int D, int n_pad, const do
                                 hipStream_t stream);
 // Five-QR preconditioning (see k_qr.hip; n_pad <= 1024): the rows of R5 in
 // W3; Q2 in W1 / Tws2, Q4 in S1 / Tws4 (n_pad * 32 doubles per job each);
-// Tscr: kQrTscr doubles per job of scratch; W2 is free afterwards.
+// Tscr: kQrTscr doubles per job of scratch; W2 is free afterwards.  tq /
+// tq_flops (optional, both or neither): a HIP-event timer around every
+// 128-column trailing update of the second to fifth QR, and the running sum
+// of their algorithmic flops (4 m 128 c + 128^2 c per job for m rows and c
+// updated columns).
 hipError_t run_qr5_precondition(int64_t njobs, int n, int D, int n_pad, const double* T, const int32_t* src,
                                 const int32_t* split, int32_t* perm, int32_t* iperm, double* S1, double* W1, double* Tws2,
                                 double* W2, double* Tws4, double* W3, double* Tscr, int32_t* colmap, double* colnorm,
-                                hipStream_t stream);
+                                hipStream_t stream, KernelTimer* tq = nullptr, double* tq_flops = nullptr);
 // X[:, a] = w_a Q Qb (W[order[sel[a]]] / s) with Q the orthogonal factor
 // kept in S1 (V, stored columns via colmap, NULL: identity) and Tws1 (panel
 // T), and Qb (optional: S1b / Tws1b, no column map, applied first; n_pad <=
