@@ -223,6 +223,8 @@ typedef struct {
   double qr128_busy_ms;     /* union of their intervals over all parts           */
   double qr128_flops;       /* their algorithmic flops: per job and launch
                                4 m 128 c + 128^2 c (m rows, c columns updated)  */
+  int64_t jacobi_rotated_pairs; /* block pairs (2 x 32 rows) rotated by the
+                               Jacobi, summed over all steps and sweeps         */
 } mctrg_chain_profile;
 /* Timings are collected only when cfg->flags has MCTRG_PROFILE. */
 int mctrg_chain_get_profile(const mctrg_chain* ch, mctrg_chain_profile* out);

@@ -185,6 +185,7 @@ struct Chain {
   double tq_flops = 0.0;    // algorithmic flops of the timed QR trailing updates
   int last_sweeps = 0;
   int sweep_hist[2 * kMaxSweeps] = {};   // last decomposition: (pairs rotated, jobs active) per sweep
+  int64_t rotated_pairs = 0;              // block pairs rotated, summed over all steps and sweeps
   int step_sweeps[64] = {};               // Jacobi sweeps of every step
 
   ~Chain() {
@@ -420,17 +421,34 @@ int chain_step(Chain& c) {
   CKH(hipMemcpyAsync(c.rng, c.h_rng, 3 * nj * sizeof(uint64_t), hipMemcpyHostToDevice, c.st));
   CKH(hipMemcpyAsync(c.cjobs, c.h_cjobs, 4 * no * sizeof(int32_t), hipMemcpyHostToDevice, c.st));
 
-  // decomposition: five QRs (n_pad <= 1024) or three (n_pad <= 4096) then
-  // Jacobi on the rows of the last R; larger unfoldings go straight to Jacobi
+  // decomposition: three or five QRs (n_pad <= 1024) or three (n_pad <= 4096)
+  // then Jacobi on the rows of the last R; larger unfoldings go straight to
+  // Jacobi.  Rows at the noise floor or below a tenth of the candidate cut
+  // move behind the active ones and are not rotated (deflation).
   const bool qr5 = sh.n_pad <= 1024;
   const bool qr = sh.n_pad <= kQrMaxN;
+  bool three = false;    // the n_pad <= 1024 preconditioner stopped after three QRs
   double* rows = c.W2;   // the rows handed to the Jacobi
   double* Wj = c.W;      // the Jacobi workspace
+  int nb_max = 0;
+  KernelTimer* tq = c.tq.enabled ? &c.tq : nullptr;
   if (qr5) {
     CKH(run_qr5_precondition(nj, sh.n, sh.D, sh.n_pad, c.Ta, c.src, c.split, c.perm, c.dpos, c.S, c.W, c.Tws2, c.W2, c.Tws,
-                             c.W3, c.Tscr, c.colmap, c.colnorm, c.st, c.tq.enabled ? &c.tq : nullptr, &c.tq_flops));
-    rows = c.W3;         // c.W / c.Tws2 keep Q2, c.S / c.Tws keep Q4
-    Wj = c.W2;
+                             c.W3, c.Tscr, c.colmap, c.colnorm, c.st, tq, &c.tq_flops, 3));
+    // The QR iteration stops after three steps when the rows left to rotate
+    // are at most half of the matrix (a cut above the tensor's rounding floor
+    // deflates its noise subspace): the Jacobi on them then costs less than
+    // the fourth and fifth QR would save.  Otherwise those follow.
+    CKH(run_deflate(nj, sh.n_pad, c.tau, c.W3, c.S, c.nb_job, c.dnrm, c.dpos, c.jw.counter, c.jw.counter_host,
+                    &nb_max, c.st));
+    if (2 * nb_max * jacobi_block_rows(sh.n_pad) <= sh.n_pad) {
+      three = true;
+      Wj = c.S;          // c.W / c.Tws2 keep Q2
+    } else {
+      CKH(run_qr45(nj, sh.n_pad, c.S, c.W2, c.Tws, c.W3, c.Tscr, c.st, tq, &c.tq_flops));
+      rows = c.W3;       // c.W / c.Tws2 keep Q2, c.S / c.Tws keep Q4
+      Wj = c.W2;
+    }
   } else if (qr) {
     CKH(run_qr3_precondition(nj, sh.n, sh.D, sh.n_pad, c.Ta, c.src, c.split, c.perm, c.dpos, c.S, c.Tws, c.W, c.Tws2, c.W2,
                              c.colmap, c.colnorm, &rows, c.st));
@@ -439,14 +457,13 @@ int chain_step(Chain& c) {
     CKH(launch_unfold(nj, sh.D, sh.n_pad, c.Ta, c.src, c.split, c.W2, c.st));
     CKH(launch_iota(nj, sh.n_pad, c.perm, c.st));
   }
-  // rows at the noise floor or below a tenth of the candidate cut move behind
-  // the active ones and are not rotated
-  int nb_max = 0;
-  CKH(run_deflate(nj, sh.n_pad, c.tau, rows, Wj, c.nb_job, c.dnrm, c.dpos, c.jw.counter, c.jw.counter_host, &nb_max,
-                  c.st));
+  if (!three)
+    CKH(run_deflate(nj, sh.n_pad, c.tau, rows, Wj, c.nb_job, c.dnrm, c.dpos, c.jw.counter, c.jw.counter_host, &nb_max,
+                    c.st));
   CKH(run_jacobi(nj, sh.n_pad, Wj, c.jw, kMaxSweeps, c.st, c.tj.enabled ? &c.tj : nullptr, &c.last_sweeps, c.nb_job,
                  nb_max, c.sweep_hist));
   if (s < 64) c.step_sweeps[s] = c.last_sweeps;
+  for (int w = 0; w < c.last_sweeps && w < kMaxSweeps; ++w) c.rotated_pairs += c.sweep_hist[2 * w];
   CKH(launch_jacobi_fail(nj, sh.jps, c.jw.sweeps, c.failed, c.st));
   CKH(launch_jacobi_finalize(nj, sh.n, sh.n_pad, Wj, c.sigma, c.order, c.st, c.dnrm));
   SampleArgs sa{};
@@ -456,14 +473,14 @@ int chain_step(Chain& c) {
   CKH(launch_sample(sa, c.st));
   if ((c.flags & MCTRG_RECORD) && c.record)
     CKH(launch_record(c.nsamp, s, c.n_steps, c.kmax_rec, sh.kc, c.idx, c.cand, c.kept, c.sel, c.record, c.st));
-  if (qr5) {
+  if (qr5 && !three) {
     // z = Q2 Q4 y (in F as scratch), v = P z into G with the gauge, u = M v / s
     CKH(launch_apply_q1(nj, sh.n, sh.n_pad, sh.kc, c.W, nullptr, c.Tws2, c.S, c.Tws, Wj, c.sigma, c.order, c.kept,
                         c.sel, c.weight, c.F, c.st));
     CKH(launch_scatter_G(nj, sh.D, sh.n_pad, sh.kc, c.F, c.perm, c.colmap, c.kept, c.G, c.st));
     CKH(launch_factor_F(nj, sh.D, sh.kc, c.Ta, c.src, c.split, c.sigma, c.kept, c.sel, c.G, c.Gt, c.F, c.st));
   } else if (qr) {
-    // z = Q2 y (in F as scratch), v = P z into G with the gauge, u = M v / s
+    // z = Q2 y (in F as scratch; three QRs), v = P z into G with the gauge, u = M v / s
     CKH(launch_apply_q1(nj, sh.n, sh.n_pad, sh.kc, c.W, nullptr, c.Tws2, nullptr, nullptr, Wj, c.sigma, c.order,
                         c.kept, c.sel, c.weight, c.F, c.st));
     CKH(launch_scatter_G(nj, sh.D, sh.n_pad, sh.kc, c.F, c.perm, sh.n_pad <= 1024 ? c.colmap : nullptr, c.kept, c.G,
@@ -948,6 +965,7 @@ int mctrg_chain_get_profile(const mctrg_chain* ch, mctrg_chain_profile* out) {
     out->qr128_ms += c->tq.ms;
     out->qr128_launches += c->tq.launches;
     out->qr128_flops += c->tq_flops;
+    out->jacobi_rotated_pairs += c->rotated_pairs;
     out->last_sweeps = std::max(out->last_sweeps, c->last_sweeps);
     for (int s = 0; s < 64; ++s) out->step_sweeps[s] = std::max(out->step_sweeps[s], c->step_sweeps[s]);
     for (int s = 0; s < 64; ++s) {

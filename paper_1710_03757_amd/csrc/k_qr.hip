@@ -1587,9 +1587,9 @@ hipError_t run_qr3_precondition(int64_t njobs, int n, int D, int n_pad, const do
 hipError_t run_qr5_precondition(int64_t njobs, int n, int D, int n_pad, const double* T, const int32_t* src,
                                 const int32_t* split, int32_t* perm, int32_t* iperm, double* S1, double* W1, double* Tws2,
                                 double* W2, double* Tws4, double* W3, double* Tscr, int32_t* colmap, double* colnorm,
-                                hipStream_t stream, KernelTimer* tq, double* tq_flops) {
+                                hipStream_t stream, KernelTimer* tq, double* tq_flops, int nqr) {
   if (njobs == 0) return hipSuccess;
-  if (n_pad > 1024) return hipErrorInvalidValue;
+  if (n_pad > 1024 || (nqr != 3 && nqr != 5)) return hipErrorInvalidValue;
   if (tq && !tq_flops) return hipErrorInvalidValue;
   hipError_t e = order_and_unfold(njobs, n, D, n_pad, T, src, split, perm, iperm, S1, stream);
   if (e != hipSuccess) return e;
@@ -1603,6 +1603,21 @@ hipError_t run_qr5_precondition(int64_t njobs, int n, int D, int n_pad, const do
   hipLaunchKernelGGL(r_rows_kernel, rg, dim3(256), 0, stream, n_pad, W1, W2, (const int32_t*)nullptr);
   e = qr_factor(njobs, n_pad, W2, Tscr, false, nullptr, nullptr, stream, T64, true, tq, tq_flops);
   if (e != hipSuccess) return e;
+  if (nqr == 3) {   // Jacobi on the rows of R3; v = P Q2 y
+    hipLaunchKernelGGL(r_rows_kernel, rg, dim3(256), 0, stream, n_pad, W2, W3, (const int32_t*)nullptr);
+    return hipGetLastError();
+  }
+  return run_qr45(njobs, n_pad, S1, W2, Tws4, W3, Tscr, stream, tq, tq_flops);
+}
+
+hipError_t run_qr45(int64_t njobs, int n_pad, double* S1, double* W2, double* Tws4, double* W3, double* Tscr,
+                    hipStream_t stream, KernelTimer* tq, double* tq_flops) {
+  if (njobs == 0) return hipSuccess;
+  if (n_pad > 1024) return hipErrorInvalidValue;
+  if (tq && !tq_flops) return hipErrorInvalidValue;
+  double* T64 = Tscr + (size_t)njobs * 2048;
+  const dim3 rg(n_pad / 32, n_pad / 32, (unsigned)njobs);
+  hipError_t e;
   hipLaunchKernelGGL(r_rows_kernel, rg, dim3(256), 0, stream, n_pad, W2, S1, (const int32_t*)nullptr);
   e = qr_factor(njobs, n_pad, S1, Tws4, true, nullptr, nullptr, stream, Tscr, true, tq, tq_flops);
   if (e != hipSuccess) return e;

@@ -168,7 +168,10 @@ hipError_t run_qr3_precondition(int64_t njobs, int n, int D, int n_pad, const do
                                 hipStream_t stream);
 // Five-QR preconditioning (see k_qr.hip; n_pad <= 1024): the rows of R5 in
 // W3; Q2 in W1 / Tws2, Q4 in S1 / Tws4 (n_pad * 32 doubles per job each);
-// Tscr: kQrTscr doubles per job of scratch; W2 is free afterwards.  tq /
+// Tscr: kQrTscr doubles per job of scratch; W2 is free afterwards.  nqr = 3
+// stops after the third QR: the rows of R3 in W3 (then v = P Q2 y), W2 still
+// holding the factored third QR, so that run_qr45 can continue with the
+// fourth and fifth (S1 / Tws4 are not written before).  tq /
 // tq_flops (optional, both or neither): a HIP-event timer around every
 // 128-column trailing update of the second to fifth QR, and the running sum
 // of their algorithmic flops (4 m 128 c + 128^2 c per job for m rows and c
@@ -176,7 +179,12 @@ hipError_t run_qr3_precondition(int64_t njobs, int n, int D, int n_pad, const do
 hipError_t run_qr5_precondition(int64_t njobs, int n, int D, int n_pad, const double* T, const int32_t* src,
                                 const int32_t* split, int32_t* perm, int32_t* iperm, double* S1, double* W1, double* Tws2,
                                 double* W2, double* Tws4, double* W3, double* Tscr, int32_t* colmap, double* colnorm,
-                                hipStream_t stream, KernelTimer* tq = nullptr, double* tq_flops = nullptr);
+                                hipStream_t stream, KernelTimer* tq = nullptr, double* tq_flops = nullptr,
+                                int nqr = 5);
+// The fourth and fifth QR after run_qr5_precondition(..., nqr = 3): the rows
+// of R5 in W3, Q4 in S1 / Tws4.
+hipError_t run_qr45(int64_t njobs, int n_pad, double* S1, double* W2, double* Tws4, double* W3, double* Tscr,
+                    hipStream_t stream, KernelTimer* tq = nullptr, double* tq_flops = nullptr);
 // X[:, a] = w_a Q Qb (W[order[sel[a]]] / s) with Q the orthogonal factor
 // kept in S1 (V, stored columns via colmap, NULL: identity) and Tws1 (panel
 // T), and Qb (optional: S1b / Tws1b, no column map, applied first; n_pad <=
