@@ -221,18 +221,18 @@ def main():
     #   fifth QR): the dense count of C <- C - V (T^T (V^T C)), summed by the
     #   library over the timed launches.
     # * jacobi_round64_kernel: per rotated pair of 32-row blocks the 64 x 64
-    #   Gram over the row length (64^2 n_pad, symmetric) and the update
-    #   W <- Q^T W (2 64^2 n_pad); the Grams of pairs found orthogonal are not
-    #   counted, so this is a lower bound of the kernel's work.
-    n_pad = -(-k * k // 32) * 32
+    #   Gram over the rotated row length (64^2 len, symmetric) and the update
+    #   W <- Q^T W (2 64^2 len), summed by the library (len = the columns up
+    #   to the rank limit of the QRs); the Grams of pairs found orthogonal are
+    #   not counted, so this is a lower bound of the kernel's work.
     jpairs = p1["jacobi_rotated_pairs"] - p0["jacobi_rotated_pairs"]
-    jflops = jpairs * 3.0 * 64 ** 2 * n_pad
+    jflops = p1["jacobi_flops"] - p0["jacobi_flops"]
     recs = {
         QR128_KERNEL: dict(launches=ql, ms=qms, busy=qbusy, flops=qflops,
                            count="dense C <- C - V (T^T (V^T C)): 4 m 128 c + 128^2 c per job and launch"),
         JACOBI_KERNEL: dict(launches=jl, ms=jms, busy=jbusy, flops=jflops,
-                            count=f"rotated block pairs ({jpairs}) x 3 * 64^2 * n_pad (Gram + update; "
-                                  "Grams of orthogonal pairs not counted)"),
+                            count=f"rotated block pairs ({jpairs}) x 3 * 64^2 * rotated row length (Gram + "
+                                  "update; Grams of orthogonal pairs not counted)"),
     }
 
     def record(name):

@@ -225,6 +225,10 @@ typedef struct {
                                4 m 128 c + 128^2 c (m rows, c columns updated)  */
   int64_t jacobi_rotated_pairs; /* block pairs (2 x 32 rows) rotated by the
                                Jacobi, summed over all steps and sweeps         */
+  double jacobi_flops;      /* their algorithmic flops: per rotated pair of
+                               r = 64 rows the Gram r^2 len and the update
+                               2 r^2 len, len = the row length rotated (the
+                               columns up to the rank limit of the QRs)        */
 } mctrg_chain_profile;
 /* Timings are collected only when cfg->flags has MCTRG_PROFILE. */
 int mctrg_chain_get_profile(const mctrg_chain* ch, mctrg_chain_profile* out);

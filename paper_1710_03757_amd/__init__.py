@@ -70,7 +70,8 @@ class ChainProfile(ctypes.Structure):
                 ("jacobi_busy_ms", ctypes.c_double), ("gemm_busy_ms", ctypes.c_double), ("parts", ctypes.c_int32),
                 ("step_sweeps", ctypes.c_int32 * 64), ("qr128_ms", ctypes.c_double),
                 ("qr128_launches", ctypes.c_int64), ("qr128_busy_ms", ctypes.c_double),
-                ("qr128_flops", ctypes.c_double), ("jacobi_rotated_pairs", ctypes.c_int64)]
+                ("qr128_flops", ctypes.c_double), ("jacobi_rotated_pairs", ctypes.c_int64),
+                ("jacobi_flops", ctypes.c_double)]
 
     def as_dict(self):
         d = {f: getattr(self, f) for f, _ in self._fields_}

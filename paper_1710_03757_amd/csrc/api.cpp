@@ -186,6 +186,7 @@ struct Chain {
   int last_sweeps = 0;
   int sweep_hist[2 * kMaxSweeps] = {};   // last decomposition: (pairs rotated, jobs active) per sweep
   int64_t rotated_pairs = 0;              // block pairs rotated, summed over all steps and sweeps
+  double jacobi_flops = 0.0;              // their Gram + update flops at the row length used
   int step_sweeps[64] = {};               // Jacobi sweeps of every step
 
   ~Chain() {
@@ -431,10 +432,21 @@ int chain_step(Chain& c) {
   double* rows = c.W2;   // the rows handed to the Jacobi
   double* Wj = c.W;      // the Jacobi workspace
   int nb_max = 0;
+  int jcols = 0;         // the Jacobi rows are zero from this column on (0: none)
   KernelTimer* tq = c.tq.enabled ? &c.tq : nullptr;
   if (qr5) {
-    CKH(run_qr5_precondition(nj, sh.n, sh.D, sh.n_pad, c.Ta, c.src, c.split, c.perm, c.dpos, c.S, c.W, c.Tws2, c.W2, c.Tws,
-                             c.W3, c.Tscr, c.colmap, c.colnorm, c.st, tq, &c.tq_flops, 3));
+    CKH(run_qr1(nj, sh.n, sh.D, sh.n_pad, c.Ta, c.src, c.split, c.perm, c.dpos, c.S, c.W, c.Tscr, c.colmap, c.colnorm,
+                c.st));
+    // The first QR re-orders the columns by norm, so the rows of R1 above the
+    // deflation floor come first: the later QRs run over the leading ncols
+    // columns only (the rows from ncols on, all at the floor, are set to zero,
+    // which moves the singular values by at most their norm, as the
+    // deflation does).
+    int rows1 = 0;
+    CKH(run_rank_rows(nj, sh.n_pad, c.tau, c.W, c.dnrm, c.nb_job, c.jw.counter, c.jw.counter_host, &rows1, c.st));
+    const int ncols = std::min(sh.n_pad, std::max(128, 128 * ceil_div(rows1, 128)));
+    CKH(run_qr23(nj, sh.n_pad, ncols, c.W, c.Tws2, c.W2, c.W3, c.Tscr, c.st, tq, &c.tq_flops));
+    jcols = ncols;
     // The QR iteration stops after three steps when the rows left to rotate
     // are at most half of the matrix (a cut above the tensor's rounding floor
     // deflates its noise subspace): the Jacobi on them then costs less than
@@ -445,7 +457,7 @@ int chain_step(Chain& c) {
       three = true;
       Wj = c.S;          // c.W / c.Tws2 keep Q2
     } else {
-      CKH(run_qr45(nj, sh.n_pad, c.S, c.W2, c.Tws, c.W3, c.Tscr, c.st, tq, &c.tq_flops));
+      CKH(run_qr45(nj, sh.n_pad, ncols, c.S, c.W2, c.Tws, c.W3, c.Tscr, c.st, tq, &c.tq_flops));
       rows = c.W3;       // c.W / c.Tws2 keep Q2, c.S / c.Tws keep Q4
       Wj = c.W2;
     }
@@ -461,9 +473,17 @@ int chain_step(Chain& c) {
     CKH(run_deflate(nj, sh.n_pad, c.tau, rows, Wj, c.nb_job, c.dnrm, c.dpos, c.jw.counter, c.jw.counter_host, &nb_max,
                     c.st));
   CKH(run_jacobi(nj, sh.n_pad, Wj, c.jw, kMaxSweeps, c.st, c.tj.enabled ? &c.tj : nullptr, &c.last_sweeps, c.nb_job,
-                 nb_max, c.sweep_hist));
+                 nb_max, c.sweep_hist, jcols));
   if (s < 64) c.step_sweeps[s] = c.last_sweeps;
-  for (int w = 0; w < c.last_sweeps && w < kMaxSweeps; ++w) c.rotated_pairs += c.sweep_hist[2 * w];
+  {
+    int64_t rp = 0;
+    for (int w = 0; w < c.last_sweeps && w < kMaxSweeps; ++w) rp += c.sweep_hist[2 * w];
+    // per rotated pair of two row blocks (2 brows rows): the symmetric Gram
+    // (2 brows)^2 len and the update W <- Q^T W, 2 (2 brows)^2 len
+    const double rows = 2.0 * jacobi_block_rows(sh.n_pad), len = jcols > 0 ? jcols : sh.n_pad;
+    c.rotated_pairs += rp;
+    c.jacobi_flops += (double)rp * 3.0 * rows * rows * len;
+  }
   CKH(launch_jacobi_fail(nj, sh.jps, c.jw.sweeps, c.failed, c.st));
   CKH(launch_jacobi_finalize(nj, sh.n, sh.n_pad, Wj, c.sigma, c.order, c.st, c.dnrm));
   SampleArgs sa{};
@@ -966,6 +986,7 @@ int mctrg_chain_get_profile(const mctrg_chain* ch, mctrg_chain_profile* out) {
     out->qr128_launches += c->tq.launches;
     out->qr128_flops += c->tq_flops;
     out->jacobi_rotated_pairs += c->rotated_pairs;
+    out->jacobi_flops += c->jacobi_flops;
     out->last_sweeps = std::max(out->last_sweeps, c->last_sweeps);
     for (int s = 0; s < 64; ++s) out->step_sweeps[s] = std::max(out->step_sweeps[s], c->step_sweeps[s]);
     for (int s = 0; s < 64; ++s) {

@@ -288,7 +288,7 @@ __device__ __forceinline__ double unit_cosine(double t) {
 // norm order, the larger half to the lower-numbered block (a few percent
 // fewer outer sweeps on TRG unfoldings).
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256, 3) void jacobi_round64_kernel(double* __restrict__ W, int n_pad, int nb_all,
+__global__ __launch_bounds__(256, 3) void jacobi_round64_kernel(double* __restrict__ W, int n_pad, int ncol, int nb_all,
                                                                 const int* __restrict__ nb_job, int round,
                                                                 const int* __restrict__ active,
                                                                 int* __restrict__ rotated, int* __restrict__ pairs,
@@ -350,9 +350,9 @@ __global__ __launch_bounds__(256, 3) void jacobi_round64_kernel(double* __restri
     }
   };
   int k0 = 16 * wave;
-  if (k0 < n_pad) load_chunk(k0, cur);
-  for (; k0 < n_pad; k0 += 64) {
-    if (k0 + 64 < n_pad) load_chunk(k0 + 64, nxt);
+  if (k0 < ncol) load_chunk(k0, cur);
+  for (; k0 < ncol; k0 += 64) {
+    if (k0 + 64 < ncol) load_chunk(k0 + 64, nxt);
 #pragma unroll
     for (int jj = 0; jj < 4; ++jj) {
       int t = 0;
@@ -605,9 +605,9 @@ __global__ __launch_bounds__(256, 3) void jacobi_round64_kernel(double* __restri
   };
   double bc[16], bn[16];
   int c0 = 16 * wave;
-  if (c0 < n_pad) load_b(c0, bc);
-  for (; c0 < n_pad; c0 += 64) {
-    if (c0 + 64 < n_pad) load_b(c0 + 64, bn);
+  if (c0 < ncol) load_b(c0, bc);
+  for (; c0 < ncol; c0 += 64) {
+    if (c0 + 64 < ncol) load_b(c0 + 64, bn);
     asm volatile("" ::: "memory");   // keep the fragment reads inside the loop
     f64x4 out[4];
 #pragma unroll
@@ -692,7 +692,8 @@ hipError_t KernelTimer::collect() {
 
 hipError_t run_jacobi(int64_t njobs, int n_pad, double* W, const JacobiWork& wk, int max_sweeps,
                       hipStream_t stream, KernelTimer* timer, int* sweeps_done, const int* nb_job, int nb_max,
-                      int* history) {
+                      int* history, int ncol) {
+  if (ncol <= 0 || ncol > n_pad || ncol % 64) ncol = n_pad;
   if (njobs == 0) return hipSuccess;
   const int brows = jacobi_block_rows(n_pad);
   const int nb = nb_job ? nb_max : n_pad / brows;
@@ -712,7 +713,7 @@ hipError_t run_jacobi(int64_t njobs, int n_pad, double* W, const JacobiWork& wk,
       if (timer) { hipError_t e = timer->begin(stream); if (e != hipSuccess) return e; }
       if (brows == 32)
         hipLaunchKernelGGL(jacobi_round64_kernel, dim3(nb / 2, (unsigned)njobs), dim3(256), 0, stream, W,
-                           n_pad, nb, nb_job, r, wk.active, wk.rotated, wk.counter + 1, tol, wk.lastmod, wk.lastchk,
+                           n_pad, ncol, nb, nb_job, r, wk.active, wk.rotated, wk.counter + 1, tol, wk.lastmod, wk.lastchk,
                            1 + sweep * (nb - 1) + r);
       else
         hipLaunchKernelGGL(jacobi_round_kernel, dim3(nb / 2, (unsigned)njobs), dim3(256), 0, stream, W,
@@ -821,6 +822,30 @@ __global__ __launch_bounds__(256) void deflate_copy_kernel(int n_pad, const doub
   for (int c = lane; c < n_pad / 2; c += 64) dst[c] = src[c];
 }
 
+// Per job: one past the last row whose squared norm exceeds floor_sq times
+// the largest (0 when every row is at the floor).
+__global__ __launch_bounds__(256) void last_row_above_kernel(int n_pad, double floor_sq,
+                                                             const double* __restrict__ nrm, int* __restrict__ last) {
+  const int64_t job = blockIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const double* nj = nrm + (size_t)job * n_pad;
+  __shared__ double red[4];
+  __shared__ int redi[4];
+  double mx = 0.0;
+  for (int r = tid; r < n_pad; r += 256) mx = fmax(mx, nj[r]);
+  for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o));
+  if (lane == 0) red[wave] = mx;
+  __syncthreads();
+  const double thr = fmax(fmax(red[0], red[1]), fmax(red[2], red[3])) * floor_sq;
+  int l = 0;
+  for (int r = tid; r < n_pad; r += 256)
+    if (nj[r] > thr) l = r + 1;
+  for (int o = 32; o > 0; o >>= 1) l = max(l, __shfl_xor(l, o));
+  if (lane == 0) redi[wave] = l;
+  __syncthreads();
+  if (tid == 0) last[job] = max(max(redi[0], redi[1]), max(redi[2], redi[3]));
+}
+
 __global__ void max_int_kernel(int64_t n, const int* __restrict__ v, int* __restrict__ out) {
   int m = 0;
   for (int64_t i = threadIdx.x; i < n; i += blockDim.x) m = max(m, v[i]);
@@ -851,6 +876,24 @@ hipError_t run_deflate(int64_t njobs, int n_pad, double tau_null, const double* 
   e = hipStreamSynchronize(stream);
   if (e != hipSuccess) return e;
   *nb_max = *scratch_host;
+  return hipGetLastError();
+}
+
+hipError_t run_rank_rows(int64_t njobs, int n_pad, double tau_null, const double* W, double* nrm, int* last,
+                         int* scratch_dev, int* scratch_host, int* rows_max, hipStream_t stream) {
+  if (njobs == 0) { *rows_max = 0; return hipSuccess; }
+  if (n_pad > 4096) return hipErrorInvalidValue;
+  const double floor_rel = fmax(0x1.0p-48, 0.1 * tau_null);
+  const dim3 rg((unsigned)ceil_div(n_pad, 4), (unsigned)njobs);
+  hipLaunchKernelGGL(deflate_norms_kernel, rg, dim3(256), 0, stream, n_pad, W, nrm);
+  hipLaunchKernelGGL(last_row_above_kernel, dim3((unsigned)njobs), dim3(256), 0, stream, n_pad, floor_rel * floor_rel,
+                     (const double*)nrm, last);
+  hipLaunchKernelGGL(max_int_kernel, dim3(1), dim3(1024), 0, stream, njobs, (const int*)last, scratch_dev);
+  hipError_t e = hipMemcpyAsync(scratch_host, scratch_dev, sizeof(int), hipMemcpyDeviceToHost, stream);
+  if (e != hipSuccess) return e;
+  e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) return e;
+  *rows_max = *scratch_host;
   return hipGetLastError();
 }
 

@@ -1381,11 +1381,21 @@ __global__ void r_rows_kernel(int n_pad, const double* __restrict__ S, double* _
 // current norms below the factored rows (a blocked form of column pivoting:
 // the columns are not moved, the panel and trailing kernels address them
 // through the map, which ends as the logical -> stored column permutation).
+// p[job * stride + e] = 0 for e < n (one job per grid row).
+__global__ void zero_tail_kernel(int64_t n, double* __restrict__ p, int64_t stride) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e < n) p[blockIdx.y * stride + e] = 0.0;
+}
+
 template <int NT, int MAXQ, int PW>
 static hipError_t qr_factor_t(int64_t njobs, int n_pad, double* S, double* Tws, bool keep_T, int32_t* colmap,
                               double* colnorm, double* T64, bool lower, hipStream_t stream, KernelTimer* tq,
-                              double* tq_flops) {
+                              double* tq_flops, int ncols) {
   if (PW == 32 && !colmap && T64) {
+    // ncols (a multiple of 128, or n_pad): only the first ncols columns are
+    // factored and updated; the others must be zero (then they stay zero,
+    // and the kept T of their panels is set to zero: those reflectors are
+    // the identity)
     // Steps of 128 columns, each two 64-column blocks A (j .. j + 63) and B
     // (j + 64 .. j + 127) of two 32-column panels: A is factored and
     // applied to B's columns only, B is factored, and both are applied to
@@ -1406,27 +1416,33 @@ static hipError_t qr_factor_t(int64_t njobs, int n_pad, double* S, double* Tws, 
                          (const double*)Tws, ts, o1, o2, Tslot, (const int32_t*)nullptr);
       return true;
     };
-    for (int j = 0; j < n_pad; j += 128) {
+    for (int j = 0; j < ncols; j += 128) {
       if (!block64(j, T64)) break;
       hipLaunchKernelGGL(qr_trailing64_kernel, xcd_tile_grid(1, njobs), dim3(256), 0, stream, njobs, n_pad, j,
                          min(j + 128, n_pad), S, (const double*)T64, (const int32_t*)nullptr, (double*)nullptr);
       if (!block64(j + 64, T64 + 4096)) break;
+      if (j + 128 >= ncols) break;   // no columns left to update
       hipLaunchKernelGGL(qr_t128_kernel, dim3((unsigned)njobs), dim3(256), 0, stream, n_pad, j, (const double*)S,
                          T64);
       if (tq) {
         const hipError_t e = tq->begin(stream);
         if (e != hipSuccess) return e;
       }
-      hipLaunchKernelGGL(qr_trailing128_kernel, xcd_tile_grid(ceil_div(n_pad - j - 128, 64), njobs), dim3(256), 0,
+      hipLaunchKernelGGL(qr_trailing128_kernel, xcd_tile_grid(ceil_div(ncols - j - 128, 64), njobs), dim3(256), 0,
                          stream, njobs, n_pad, j, S, (const double*)T64, (int)(lower && j == 0));
       if (tq) {
         const hipError_t e = tq->end(stream);
         if (e != hipSuccess) return e;
         // dense count of C <- C - V (T^T (V^T C)): m = n_pad - j rows,
         // c = n_pad - j - 128 columns, V m x 128, T triangular
-        const double m = n_pad - j, c = n_pad - j - 128;
+        const double m = n_pad - j, c = ncols - j - 128;
         *tq_flops += (double)njobs * (4.0 * m * 128.0 * c + 128.0 * 128.0 * c);
       }
+    }
+    if (keep_T && ncols < n_pad) {
+      const int64_t nz = (int64_t)(n_pad - ncols) * 32;   // T of the panels from column ncols on
+      hipLaunchKernelGGL(zero_tail_kernel, dim3((unsigned)ceil_div(nz, 256), (unsigned)njobs), dim3(256), 0, stream,
+                         nz, Tws + (int64_t)ncols * 32, ts);
     }
     return hipGetLastError();
   }
@@ -1500,13 +1516,17 @@ static hipError_t qr_factor_t(int64_t njobs, int n_pad, double* S, double* Tws, 
 // lower: S is lower triangular on entry (the transpose of an R factor).
 // tq / tq_flops (or NULL): HIP-event timer of the 128-column trailing
 // updates and the running sum of their algorithmic flops.
+// ncols (0: n_pad): with T64 and no column map, factor the first ncols
+// columns only (the rest zero).
 static hipError_t qr_factor(int64_t njobs, int n_pad, double* S, double* Tws, bool keep_T, int32_t* colmap,
                             double* colnorm, hipStream_t stream, double* T64 = nullptr, bool lower = false,
-                            KernelTimer* tq = nullptr, double* tq_flops = nullptr) {
+                            KernelTimer* tq = nullptr, double* tq_flops = nullptr, int ncols = 0) {
+  if (ncols <= 0 || ncols > n_pad) ncols = n_pad;
   if (n_pad <= 1024)
-    return qr_factor_t<256, 4, 32>(njobs, n_pad, S, Tws, keep_T, colmap, colnorm, T64, lower, stream, tq, tq_flops);
+    return qr_factor_t<256, 4, 32>(njobs, n_pad, S, Tws, keep_T, colmap, colnorm, T64, lower, stream, tq, tq_flops,
+                                   ncols);
   return qr_factor_t<512, 8, 8>(njobs, n_pad, S, Tws, keep_T, nullptr, nullptr, nullptr, false, stream, nullptr,
-                                nullptr);
+                                nullptr, n_pad);
 }
 
 static hipError_t order_and_unfold(int64_t njobs, int n, int D, int n_pad, const double* T, const int32_t* src,
@@ -1584,45 +1604,67 @@ hipError_t run_qr3_precondition(int64_t njobs, int n, int D, int n_pad, const do
 // factors in Tws4 (n_pad * 32 doubles per job each); the first, third and
 // fifth QR use Tscr (kQrTscr doubles per job) for their T factors.  The rows of
 // R5 end in W3; W2 is free afterwards.
+hipError_t run_qr1(int64_t njobs, int n, int D, int n_pad, const double* T, const int32_t* src, const int32_t* split,
+                   int32_t* perm, int32_t* iperm, double* S1, double* W1, double* Tscr, int32_t* colmap,
+                   double* colnorm, hipStream_t stream) {
+  if (njobs == 0) return hipSuccess;
+  if (n_pad > 1024) return hipErrorInvalidValue;
+  hipError_t e = order_and_unfold(njobs, n, D, n_pad, T, src, split, perm, iperm, S1, stream);
+  if (e != hipSuccess) return e;
+  e = qr_factor(njobs, n_pad, S1, Tscr, false, colmap, colnorm, stream, Tscr + (size_t)njobs * 2048);
+  if (e != hipSuccess) return e;
+  const dim3 rg(n_pad / 32, n_pad / 32, (unsigned)njobs);
+  hipLaunchKernelGGL(r_rows_kernel, rg, dim3(256), 0, stream, n_pad, S1, W1, (const int32_t*)colmap);
+  return hipGetLastError();
+}
+
+hipError_t run_qr23(int64_t njobs, int n_pad, int ncols, double* W1, double* Tws2, double* W2, double* W3,
+                    double* Tscr, hipStream_t stream, KernelTimer* tq, double* tq_flops) {
+  if (njobs == 0) return hipSuccess;
+  if (n_pad > 1024 || ncols <= 0 || ncols > n_pad || (ncols % 128 && ncols != n_pad)) return hipErrorInvalidValue;
+  if (tq && !tq_flops) return hipErrorInvalidValue;
+  double* T64 = Tscr + (size_t)njobs * 2048;
+  const dim3 rg(n_pad / 32, n_pad / 32, (unsigned)njobs);
+  if (ncols < n_pad) {   // the rows of R1 from ncols on (all at the floor) become zero
+    const int64_t nz = (int64_t)(n_pad - ncols) * n_pad;
+    hipLaunchKernelGGL(zero_tail_kernel, dim3((unsigned)ceil_div(nz, 256), (unsigned)njobs), dim3(256), 0, stream, nz,
+                       W1 + (int64_t)ncols * n_pad, (int64_t)n_pad * n_pad);
+  }
+  hipError_t e = qr_factor(njobs, n_pad, W1, Tws2, true, nullptr, nullptr, stream, Tscr, true, tq, tq_flops, ncols);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(r_rows_kernel, rg, dim3(256), 0, stream, n_pad, W1, W2, (const int32_t*)nullptr);
+  e = qr_factor(njobs, n_pad, W2, Tscr, false, nullptr, nullptr, stream, T64, true, tq, tq_flops, ncols);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(r_rows_kernel, rg, dim3(256), 0, stream, n_pad, W2, W3, (const int32_t*)nullptr);
+  return hipGetLastError();
+}
+
 hipError_t run_qr5_precondition(int64_t njobs, int n, int D, int n_pad, const double* T, const int32_t* src,
                                 const int32_t* split, int32_t* perm, int32_t* iperm, double* S1, double* W1, double* Tws2,
                                 double* W2, double* Tws4, double* W3, double* Tscr, int32_t* colmap, double* colnorm,
                                 hipStream_t stream, KernelTimer* tq, double* tq_flops, int nqr) {
   if (njobs == 0) return hipSuccess;
   if (n_pad > 1024 || (nqr != 3 && nqr != 5)) return hipErrorInvalidValue;
-  if (tq && !tq_flops) return hipErrorInvalidValue;
-  hipError_t e = order_and_unfold(njobs, n, D, n_pad, T, src, split, perm, iperm, S1, stream);
+  hipError_t e = run_qr1(njobs, n, D, n_pad, T, src, split, perm, iperm, S1, W1, Tscr, colmap, colnorm, stream);
   if (e != hipSuccess) return e;
-  double* T64 = Tscr + (size_t)njobs * 2048;
-  e = qr_factor(njobs, n_pad, S1, Tscr, false, colmap, colnorm, stream, T64);
-  if (e != hipSuccess) return e;
-  const dim3 rg(n_pad / 32, n_pad / 32, (unsigned)njobs);
-  hipLaunchKernelGGL(r_rows_kernel, rg, dim3(256), 0, stream, n_pad, S1, W1, (const int32_t*)colmap);
-  e = qr_factor(njobs, n_pad, W1, Tws2, true, nullptr, nullptr, stream, Tscr, true, tq, tq_flops);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(r_rows_kernel, rg, dim3(256), 0, stream, n_pad, W1, W2, (const int32_t*)nullptr);
-  e = qr_factor(njobs, n_pad, W2, Tscr, false, nullptr, nullptr, stream, T64, true, tq, tq_flops);
-  if (e != hipSuccess) return e;
-  if (nqr == 3) {   // Jacobi on the rows of R3; v = P Q2 y
-    hipLaunchKernelGGL(r_rows_kernel, rg, dim3(256), 0, stream, n_pad, W2, W3, (const int32_t*)nullptr);
-    return hipGetLastError();
-  }
-  return run_qr45(njobs, n_pad, S1, W2, Tws4, W3, Tscr, stream, tq, tq_flops);
+  e = run_qr23(njobs, n_pad, n_pad, W1, Tws2, W2, W3, Tscr, stream, tq, tq_flops);
+  if (e != hipSuccess || nqr == 3) return e;
+  return run_qr45(njobs, n_pad, n_pad, S1, W2, Tws4, W3, Tscr, stream, tq, tq_flops);
 }
 
-hipError_t run_qr45(int64_t njobs, int n_pad, double* S1, double* W2, double* Tws4, double* W3, double* Tscr,
-                    hipStream_t stream, KernelTimer* tq, double* tq_flops) {
+hipError_t run_qr45(int64_t njobs, int n_pad, int ncols, double* S1, double* W2, double* Tws4, double* W3,
+                    double* Tscr, hipStream_t stream, KernelTimer* tq, double* tq_flops) {
   if (njobs == 0) return hipSuccess;
-  if (n_pad > 1024) return hipErrorInvalidValue;
+  if (n_pad > 1024 || ncols <= 0 || ncols > n_pad || (ncols % 128 && ncols != n_pad)) return hipErrorInvalidValue;
   if (tq && !tq_flops) return hipErrorInvalidValue;
   double* T64 = Tscr + (size_t)njobs * 2048;
   const dim3 rg(n_pad / 32, n_pad / 32, (unsigned)njobs);
   hipError_t e;
   hipLaunchKernelGGL(r_rows_kernel, rg, dim3(256), 0, stream, n_pad, W2, S1, (const int32_t*)nullptr);
-  e = qr_factor(njobs, n_pad, S1, Tws4, true, nullptr, nullptr, stream, Tscr, true, tq, tq_flops);
+  e = qr_factor(njobs, n_pad, S1, Tws4, true, nullptr, nullptr, stream, Tscr, true, tq, tq_flops, ncols);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(r_rows_kernel, rg, dim3(256), 0, stream, n_pad, S1, W2, (const int32_t*)nullptr);
-  e = qr_factor(njobs, n_pad, W2, Tscr, false, nullptr, nullptr, stream, T64, true, tq, tq_flops);
+  e = qr_factor(njobs, n_pad, W2, Tscr, false, nullptr, nullptr, stream, T64, true, tq, tq_flops, ncols);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(r_rows_kernel, rg, dim3(256), 0, stream, n_pad, W2, W3, (const int32_t*)nullptr);
   return hipGetLastError();

@@ -128,10 +128,20 @@ struct JacobiWork {
 };
 constexpr int kJacobiMaxBlocks = 128;   // n_pad / 32 for n_pad <= 4096
 // history (optional, host, max_sweeps x 2): per sweep, the block pairs that
-// rotated (summed over jobs) and the jobs still rotating after it.
+// rotated (summed over jobs) and the jobs still rotating after it.  ncol
+// (0: n_pad; a multiple of 64 for the 64-row pairs): the rows are zero from
+// column ncol on, so the Gram and the update stop there (rotations keep those
+// columns zero).
 hipError_t run_jacobi(int64_t njobs, int n_pad, double* W, const JacobiWork& wk, int max_sweeps,
                       hipStream_t stream, KernelTimer* timer = nullptr, int* sweeps_done = nullptr,
-                      const int* nb_job = nullptr, int nb_max = 0, int* history = nullptr);
+                      const int* nb_job = nullptr, int nb_max = 0, int* history = nullptr, int ncol = 0);
+// Rank of the rows of W (n_pad x n_pad per job, row-major): *rows_max = the
+// largest over the jobs of one past the last row whose norm exceeds
+// max(2^-48, tau_null / 10) times the largest row norm of its job (the
+// deflation floor).  nrm: n_pad doubles per job, last: one int per job, of
+// scratch; synchronises the stream.
+hipError_t run_rank_rows(int64_t njobs, int n_pad, double tau_null, const double* W, double* nrm, int* last,
+                         int* scratch_dev, int* scratch_host, int* rows_max, hipStream_t stream);
 // Noise-floor deflation: Wout = rows of Win with the active rows (norm >
 // max(2^-48, tau_null / 10) times the largest) first, in order, the others
 // after them; nb_job = the even number of Jacobi row blocks covering the
@@ -181,10 +191,21 @@ hipError_t run_qr5_precondition(int64_t njobs, int n, int D, int n_pad, const do
                                 double* W2, double* Tws4, double* W3, double* Tscr, int32_t* colmap, double* colnorm,
                                 hipStream_t stream, KernelTimer* tq = nullptr, double* tq_flops = nullptr,
                                 int nqr = 5);
-// The fourth and fifth QR after run_qr5_precondition(..., nqr = 3): the rows
-// of R5 in W3, Q4 in S1 / Tws4.
-hipError_t run_qr45(int64_t njobs, int n_pad, double* S1, double* W2, double* Tws4, double* W3, double* Tscr,
-                    hipStream_t stream, KernelTimer* tq = nullptr, double* tq_flops = nullptr);
+// The same in parts.  run_qr1: the unfolding and the first (re-ordered) QR,
+// the rows of R1 in W1.  run_qr23: the second and third QR over the first
+// ncols columns (a multiple of 128, or n_pad; the rows of R1 from ncols on
+// are set to zero first, so that R2 and R3 are zero outside their leading
+// ncols x ncols block): Q2 in W1 / Tws2 (the T of the panels from column
+// ncols on set to zero), the rows of R3 in W3, W2 holding the factored third
+// QR.  run_qr45: the fourth and fifth after it, the rows of R5 in W3, Q4 in
+// S1 / Tws4.
+hipError_t run_qr1(int64_t njobs, int n, int D, int n_pad, const double* T, const int32_t* src, const int32_t* split,
+                   int32_t* perm, int32_t* iperm, double* S1, double* W1, double* Tscr, int32_t* colmap,
+                   double* colnorm, hipStream_t stream);
+hipError_t run_qr23(int64_t njobs, int n_pad, int ncols, double* W1, double* Tws2, double* W2, double* W3,
+                    double* Tscr, hipStream_t stream, KernelTimer* tq = nullptr, double* tq_flops = nullptr);
+hipError_t run_qr45(int64_t njobs, int n_pad, int ncols, double* S1, double* W2, double* Tws4, double* W3,
+                    double* Tscr, hipStream_t stream, KernelTimer* tq = nullptr, double* tq_flops = nullptr);
 // X[:, a] = w_a Q Qb (W[order[sel[a]]] / s) with Q the orthogonal factor
 // kept in S1 (V, stored columns via colmap, NULL: identity) and Tws1 (panel
 // T), and Qb (optional: S1b / Tws1b, no column map, applied first; n_pad <=
