@@ -435,8 +435,14 @@ int chain_step(Chain& c) {
   int jcols = 0;         // the Jacobi rows are zero from this column on (0: none)
   KernelTimer* tq = c.tq.enabled ? &c.tq : nullptr;
   if (qr5) {
+    // the first QR stops once the columns it has not factored lie below the
+    // deflation floor in every job (their rows of R1 are then set to zero)
+    QrStop stop;
+    stop.floor_rel = std::max(0x1.0p-48, 0.1 * c.tau);
+    stop.dev = c.jw.counter;
+    stop.host = c.jw.counter_host;
     CKH(run_qr1(nj, sh.n, sh.D, sh.n_pad, c.Ta, c.src, c.split, c.perm, c.dpos, c.S, c.W, c.Tscr, c.colmap, c.colnorm,
-                c.st));
+                c.st, &stop));
     // The first QR re-orders the columns by norm, so the rows of R1 above the
     // deflation floor come first: the later QRs run over the leading ncols
     // columns only (the rows from ncols on, all at the floor, are set to zero,

@@ -1381,6 +1381,34 @@ __global__ void r_rows_kernel(int n_pad, const double* __restrict__ S, double* _
 // current norms below the factored rows (a blocked form of column pivoting:
 // the columns are not moved, the panel and trailing kernels address them
 // through the map, which ends as the logical -> stored column permutation).
+// Early stop of the re-ordered first QR.  Per job: the squared norms (below
+// the factored rows) of the columns from logical position j0 on, averaged,
+// against floor_sq times the squared leading diagonal entry of R (dropping
+// those m columns' rest then perturbs the singular values by at most
+// sqrt(m) floor |R00|, the bound of the row deflation); *any becomes 1 when
+// some job still exceeds it.
+__global__ __launch_bounds__(256) void trailing_above_kernel(int n_pad, int j0, double floor_sq,
+                                                             const double* __restrict__ S,
+                                                             const int32_t* __restrict__ colmap,
+                                                             const double* __restrict__ colnorm, int* __restrict__ any) {
+  const int64_t job = blockIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int32_t* cm = colmap + job * n_pad;
+  __shared__ double red[4];
+  double sum = 0.0;
+  for (int p = j0 + tid; p < n_pad; p += 256) sum += colnorm[job * n_pad + cm[p]];
+  for (int o = 32; o > 0; o >>= 1) sum += __shfl_xor(sum, o);
+  if (lane == 0) red[wave] = sum;
+  __syncthreads();
+  if (tid == 0) {
+    const double tot = (red[0] + red[1]) + (red[2] + red[3]);
+    const double r00 = S[(size_t)job * n_pad * n_pad + (size_t)cm[0] * n_pad];
+    if (!(tot <= floor_sq * r00 * r00 * (double)(n_pad - j0))) atomicMax(any, 1);   // NaN counts as above
+  }
+}
+
+__global__ void set_int_kernel(int* p, int v) { *p = v; }
+
 // p[job * stride + e] = 0 for e < n (one job per grid row).
 __global__ void zero_tail_kernel(int64_t n, double* __restrict__ p, int64_t stride) {
   const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -1390,7 +1418,7 @@ __global__ void zero_tail_kernel(int64_t n, double* __restrict__ p, int64_t stri
 template <int NT, int MAXQ, int PW>
 static hipError_t qr_factor_t(int64_t njobs, int n_pad, double* S, double* Tws, bool keep_T, int32_t* colmap,
                               double* colnorm, double* T64, bool lower, hipStream_t stream, KernelTimer* tq,
-                              double* tq_flops, int ncols) {
+                              double* tq_flops, int ncols, QrStop* stop) {
   if (PW == 32 && !colmap && T64) {
     // ncols (a multiple of 128, or n_pad): only the first ncols columns are
     // factored and updated; the others must be zero (then they stay zero,
@@ -1478,6 +1506,19 @@ static hipError_t qr_factor_t(int64_t njobs, int n_pad, double* S, double* Tws, 
                          (const double*)Tws, ts, o1, o2, T64, (const int32_t*)colmap);
       hipLaunchKernelGGL(qr_trailing64_kernel, xcd_tile_grid(ceil_div(n_pad - j - 64, 64), njobs), dim3(256), 0,
                          stream, njobs, n_pad, j, n_pad, S, (const double*)T64, (const int32_t*)colmap, colnorm);
+      if (stop) {   // the remaining columns below the floor in every job: stop here
+        hipLaunchKernelGGL(set_int_kernel, dim3(1), dim3(1), 0, stream, stop->dev, 0);
+        hipLaunchKernelGGL(trailing_above_kernel, dim3((unsigned)njobs), dim3(256), 0, stream, n_pad, j + 64,
+                           stop->floor_rel * stop->floor_rel, (const double*)S, (const int32_t*)colmap,
+                           (const double*)colnorm, stop->dev);
+        hipError_t e = hipMemcpyAsync(stop->host, stop->dev, sizeof(int), hipMemcpyDeviceToHost, stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(stream);
+        if (e != hipSuccess) return e;
+        if (*stop->host == 0) {
+          stop->rows = j + 64;
+          break;
+        }
+      }
     }
     return hipGetLastError();
   }
@@ -1520,13 +1561,15 @@ static hipError_t qr_factor_t(int64_t njobs, int n_pad, double* S, double* Tws, 
 // columns only (the rest zero).
 static hipError_t qr_factor(int64_t njobs, int n_pad, double* S, double* Tws, bool keep_T, int32_t* colmap,
                             double* colnorm, hipStream_t stream, double* T64 = nullptr, bool lower = false,
-                            KernelTimer* tq = nullptr, double* tq_flops = nullptr, int ncols = 0) {
+                            KernelTimer* tq = nullptr, double* tq_flops = nullptr, int ncols = 0,
+                            QrStop* stop = nullptr) {
   if (ncols <= 0 || ncols > n_pad) ncols = n_pad;
+  if (stop) stop->rows = n_pad;
   if (n_pad <= 1024)
     return qr_factor_t<256, 4, 32>(njobs, n_pad, S, Tws, keep_T, colmap, colnorm, T64, lower, stream, tq, tq_flops,
-                                   ncols);
+                                   ncols, stop);
   return qr_factor_t<512, 8, 8>(njobs, n_pad, S, Tws, keep_T, nullptr, nullptr, nullptr, false, stream, nullptr,
-                                nullptr, n_pad);
+                                nullptr, n_pad, nullptr);
 }
 
 static hipError_t order_and_unfold(int64_t njobs, int n, int D, int n_pad, const double* T, const int32_t* src,
@@ -1606,15 +1649,21 @@ hipError_t run_qr3_precondition(int64_t njobs, int n, int D, int n_pad, const do
 // R5 end in W3; W2 is free afterwards.
 hipError_t run_qr1(int64_t njobs, int n, int D, int n_pad, const double* T, const int32_t* src, const int32_t* split,
                    int32_t* perm, int32_t* iperm, double* S1, double* W1, double* Tscr, int32_t* colmap,
-                   double* colnorm, hipStream_t stream) {
+                   double* colnorm, hipStream_t stream, QrStop* stop) {
   if (njobs == 0) return hipSuccess;
   if (n_pad > 1024) return hipErrorInvalidValue;
   hipError_t e = order_and_unfold(njobs, n, D, n_pad, T, src, split, perm, iperm, S1, stream);
   if (e != hipSuccess) return e;
-  e = qr_factor(njobs, n_pad, S1, Tscr, false, colmap, colnorm, stream, Tscr + (size_t)njobs * 2048);
+  e = qr_factor(njobs, n_pad, S1, Tscr, false, colmap, colnorm, stream, Tscr + (size_t)njobs * 2048, false, nullptr,
+                nullptr, 0, stop);
   if (e != hipSuccess) return e;
   const dim3 rg(n_pad / 32, n_pad / 32, (unsigned)njobs);
   hipLaunchKernelGGL(r_rows_kernel, rg, dim3(256), 0, stream, n_pad, S1, W1, (const int32_t*)colmap);
+  if (stop && stop->rows < n_pad) {   // rows from the stop on: the unfactored rest, below the floor
+    const int64_t nz = (int64_t)(n_pad - stop->rows) * n_pad;
+    hipLaunchKernelGGL(zero_tail_kernel, dim3((unsigned)ceil_div(nz, 256), (unsigned)njobs), dim3(256), 0, stream, nz,
+                       W1 + (int64_t)stop->rows * n_pad, (int64_t)n_pad * n_pad);
+  }
   return hipGetLastError();
 }
 
@@ -1645,7 +1694,8 @@ hipError_t run_qr5_precondition(int64_t njobs, int n, int D, int n_pad, const do
                                 hipStream_t stream, KernelTimer* tq, double* tq_flops, int nqr) {
   if (njobs == 0) return hipSuccess;
   if (n_pad > 1024 || (nqr != 3 && nqr != 5)) return hipErrorInvalidValue;
-  hipError_t e = run_qr1(njobs, n, D, n_pad, T, src, split, perm, iperm, S1, W1, Tscr, colmap, colnorm, stream);
+  hipError_t e = run_qr1(njobs, n, D, n_pad, T, src, split, perm, iperm, S1, W1, Tscr, colmap, colnorm, stream,
+                         nullptr);
   if (e != hipSuccess) return e;
   e = run_qr23(njobs, n_pad, n_pad, W1, Tws2, W2, W3, Tscr, stream, tq, tq_flops);
   if (e != hipSuccess || nqr == 3) return e;

@@ -199,9 +199,21 @@ hipError_t run_qr5_precondition(int64_t njobs, int n, int D, int n_pad, const do
 // ncols on set to zero), the rows of R3 in W3, W2 holding the factored third
 // QR.  run_qr45: the fourth and fifth after it, the rows of R5 in W3, Q4 in
 // S1 / Tws4.
+// stop (or NULL): after every 64 columns of the first QR, if in every job
+// the columns not yet factored hold (in mean square below the factored rows)
+// at most floor_rel^2 times the squared leading diagonal entry of R, the QR
+// stops there; rows = the factored rows (n_pad if it ran to the end);
+// the rows of R1 from there on are written as zero.  dev / host: one int of
+// device and pinned host scratch; each check synchronises the stream.
+struct QrStop {
+  double floor_rel = 0.0;
+  int* dev = nullptr;
+  int* host = nullptr;
+  int rows = 0;
+};
 hipError_t run_qr1(int64_t njobs, int n, int D, int n_pad, const double* T, const int32_t* src, const int32_t* split,
                    int32_t* perm, int32_t* iperm, double* S1, double* W1, double* Tscr, int32_t* colmap,
-                   double* colnorm, hipStream_t stream);
+                   double* colnorm, hipStream_t stream, QrStop* stop = nullptr);
 hipError_t run_qr23(int64_t njobs, int n_pad, int ncols, double* W1, double* Tws2, double* W2, double* W3,
                     double* Tscr, hipStream_t stream, KernelTimer* tq = nullptr, double* tq_flops = nullptr);
 hipError_t run_qr45(int64_t njobs, int n_pad, int ncols, double* S1, double* W2, double* Tws4, double* W3,
