@@ -1344,19 +1344,20 @@ __global__ __launch_bounds__(256) void resort_cols_kernel(int n_pad, int j0, con
   for (int t = threadIdx.x; t < m; t += 256) cm[j0 + t] = old[idx[t] < m ? idx[t] : t];
 }
 
-// W[r][c] = R[r][c] = S[colmap[c]][r] for r <= c, else 0 (rows of R for the
-// Jacobi or the next QR; colmap NULL: identity).  One 32 x 32 tile per
-// workgroup, transposed through LDS; tiles wholly below the diagonal are
-// written as zeros without reading S.
+// W[r][c] = R[r][c] = S[colmap[c]][r] for r <= c, r < rlim and c < clim,
+// else 0 (rows of R for the Jacobi or the next QR; colmap NULL: identity;
+// rlim / clim multiples of 32: the rows and columns of R known to be zero).
+// One 32 x 32 tile per workgroup, transposed through LDS; tiles wholly below
+// the diagonal or beyond the limits are written as zeros without reading S.
 __global__ void r_rows_kernel(int n_pad, const double* __restrict__ S, double* __restrict__ W,
-                              const int32_t* __restrict__ colmap) {
+                              const int32_t* __restrict__ colmap, int rlim, int clim) {
   const int64_t job = blockIdx.z;
   __shared__ double tile[32][33];
   const size_t per = (size_t)n_pad * n_pad;
   const int bx = blockIdx.x * 32, by = blockIdx.y * 32;   // bx: column c block, by: row r block
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8 threads
   double* Wj = W + job * per;
-  if (by > bx + 31) {   // r > c everywhere (uniform)
+  if (by > bx + 31 || by >= rlim || bx >= clim) {   // zero everywhere (uniform)
     for (int yy = ty; yy < 32; yy += 8) Wj[(size_t)(by + yy) * n_pad + bx + tx] = 0.0;
     return;
   }
@@ -1595,7 +1596,7 @@ hipError_t run_qr_precondition(int64_t njobs, int n, int D, int n_pad, const dou
   e = qr_factor(njobs, n_pad, S, Tws, false, nullptr, nullptr, stream);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(r_rows_kernel, dim3(n_pad / 32, n_pad / 32, (unsigned)njobs), dim3(256), 0, stream, n_pad, S, W,
-                     (const int32_t*)nullptr);
+                     (const int32_t*)nullptr, n_pad, n_pad);
   return hipGetLastError();
 }
 
@@ -1623,14 +1624,14 @@ hipError_t run_qr3_precondition(int64_t njobs, int n, int D, int n_pad, const do
   e = qr_factor(njobs, n_pad, S1, Tws1, false, colmap, colnorm, stream);
   if (e != hipSuccess) return e;
   const dim3 rg(n_pad / 32, n_pad / 32, (unsigned)njobs);
-  hipLaunchKernelGGL(r_rows_kernel, rg, dim3(256), 0, stream, n_pad, S1, W1, (const int32_t*)colmap);
+  hipLaunchKernelGGL(r_rows_kernel, rg, dim3(256), 0, stream, n_pad, S1, W1, (const int32_t*)colmap, n_pad, n_pad);
   // (n_pad > 1024: 8-column panels throughout, no block T scratch)
   e = qr_factor(njobs, n_pad, W1, Tws2, true, nullptr, nullptr, stream, nullptr);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(r_rows_kernel, rg, dim3(256), 0, stream, n_pad, W1, W2, (const int32_t*)nullptr);
+  hipLaunchKernelGGL(r_rows_kernel, rg, dim3(256), 0, stream, n_pad, W1, W2, (const int32_t*)nullptr, n_pad, n_pad);
   e = qr_factor(njobs, n_pad, W2, Tws1, false, nullptr, nullptr, stream, nullptr);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(r_rows_kernel, rg, dim3(256), 0, stream, n_pad, W2, S1, (const int32_t*)nullptr);
+  hipLaunchKernelGGL(r_rows_kernel, rg, dim3(256), 0, stream, n_pad, W2, S1, (const int32_t*)nullptr, n_pad, n_pad);
   *rows = S1;
   return hipGetLastError();
 }
@@ -1658,12 +1659,9 @@ hipError_t run_qr1(int64_t njobs, int n, int D, int n_pad, const double* T, cons
                 nullptr, 0, stop);
   if (e != hipSuccess) return e;
   const dim3 rg(n_pad / 32, n_pad / 32, (unsigned)njobs);
-  hipLaunchKernelGGL(r_rows_kernel, rg, dim3(256), 0, stream, n_pad, S1, W1, (const int32_t*)colmap);
-  if (stop && stop->rows < n_pad) {   // rows from the stop on: the unfactored rest, below the floor
-    const int64_t nz = (int64_t)(n_pad - stop->rows) * n_pad;
-    hipLaunchKernelGGL(zero_tail_kernel, dim3((unsigned)ceil_div(nz, 256), (unsigned)njobs), dim3(256), 0, stream, nz,
-                       W1 + (int64_t)stop->rows * n_pad, (int64_t)n_pad * n_pad);
-  }
+  // rows from the stop on (the unfactored rest, below the floor) are written as zero
+  hipLaunchKernelGGL(r_rows_kernel, rg, dim3(256), 0, stream, n_pad, S1, W1, (const int32_t*)colmap,
+                     stop ? stop->rows : n_pad, n_pad);
   return hipGetLastError();
 }
 
@@ -1681,10 +1679,10 @@ hipError_t run_qr23(int64_t njobs, int n_pad, int ncols, double* W1, double* Tws
   }
   hipError_t e = qr_factor(njobs, n_pad, W1, Tws2, true, nullptr, nullptr, stream, Tscr, true, tq, tq_flops, ncols);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(r_rows_kernel, rg, dim3(256), 0, stream, n_pad, W1, W2, (const int32_t*)nullptr);
+  hipLaunchKernelGGL(r_rows_kernel, rg, dim3(256), 0, stream, n_pad, W1, W2, (const int32_t*)nullptr, ncols, ncols);
   e = qr_factor(njobs, n_pad, W2, Tscr, false, nullptr, nullptr, stream, T64, true, tq, tq_flops, ncols);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(r_rows_kernel, rg, dim3(256), 0, stream, n_pad, W2, W3, (const int32_t*)nullptr);
+  hipLaunchKernelGGL(r_rows_kernel, rg, dim3(256), 0, stream, n_pad, W2, W3, (const int32_t*)nullptr, ncols, ncols);
   return hipGetLastError();
 }
 
@@ -1710,13 +1708,13 @@ hipError_t run_qr45(int64_t njobs, int n_pad, int ncols, double* S1, double* W2,
   double* T64 = Tscr + (size_t)njobs * 2048;
   const dim3 rg(n_pad / 32, n_pad / 32, (unsigned)njobs);
   hipError_t e;
-  hipLaunchKernelGGL(r_rows_kernel, rg, dim3(256), 0, stream, n_pad, W2, S1, (const int32_t*)nullptr);
+  hipLaunchKernelGGL(r_rows_kernel, rg, dim3(256), 0, stream, n_pad, W2, S1, (const int32_t*)nullptr, ncols, ncols);
   e = qr_factor(njobs, n_pad, S1, Tws4, true, nullptr, nullptr, stream, Tscr, true, tq, tq_flops, ncols);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(r_rows_kernel, rg, dim3(256), 0, stream, n_pad, S1, W2, (const int32_t*)nullptr);
+  hipLaunchKernelGGL(r_rows_kernel, rg, dim3(256), 0, stream, n_pad, S1, W2, (const int32_t*)nullptr, ncols, ncols);
   e = qr_factor(njobs, n_pad, W2, Tscr, false, nullptr, nullptr, stream, T64, true, tq, tq_flops, ncols);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(r_rows_kernel, rg, dim3(256), 0, stream, n_pad, W2, W3, (const int32_t*)nullptr);
+  hipLaunchKernelGGL(r_rows_kernel, rg, dim3(256), 0, stream, n_pad, W2, W3, (const int32_t*)nullptr, ncols, ncols);
   return hipGetLastError();
 }
 
