@@ -141,13 +141,13 @@ void mctrg_default_config(mctrg_run_config* cfg);
  * Kept counts below the capacity are zero-padded. */
 int32_t mctrg_capacity_dim(int32_t d0, int32_t k, int32_t n_steps);
 
-/* Parts: a wave of two or more samples runs as two parts, the first half of
- * its samples and the rest, each with its own device workspace and stream
- * (the first on hip_stream, the second on a non-blocking stream of default
+/* Parts: a wave of n samples runs as min(3, n) parts of consecutive samples
+ * (as equal as possible), each with its own device workspace and stream (the
+ * first on hip_stream, the others on non-blocking streams of default
  * priority that the library creates and destroys), advanced concurrently by
- * two host threads, so that the kernels of one part fill the GPU while the
- * other waits on a convergence count or runs latency-bound QR panels.
- * hip_stream waits for both parts before a call returns or completes.
+ * one host thread each, so that the kernels of some parts fill the GPU while
+ * another waits on a convergence count or runs latency-bound QR panels.
+ * hip_stream waits for all parts before a call returns or completes.
  * Results do not depend on the split; MCTRG_ONE_STREAM keeps one part.
  *
  * Run n_samples independent Monte Carlo samples (Section III).
@@ -212,9 +212,9 @@ typedef struct {
   int32_t last_active[64];  /* last step, per sweep: decompositions still
                                rotating after that sweep                        */
   double jacobi_busy_ms;    /* union of the Jacobi launch intervals over all
-                               parts (launches of two parts overlap in time)     */
+                               parts (launches of the parts overlap in time)     */
   double gemm_busy_ms;      /* the same for the GEMMs                            */
-  int32_t parts;            /* parts of the chain (1 or 2)                       */
+  int32_t parts;            /* parts of the chain (1 to 3)                       */
   int32_t step_sweeps[64];  /* Jacobi sweeps of every step done (the most over
                                the step's decompositions), steps 0..63          */
   double qr128_ms;          /* summed duration of the 128-column trailing updates

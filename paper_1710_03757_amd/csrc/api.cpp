@@ -562,7 +562,7 @@ int chain_finish(Chain& c, int8_t* out_sign, double* out_ln, double* out_lnc, do
 // other parts' kernels fill the GPU.  Per-sample results do not depend on the
 // split: every random draw is addressed by the global sample id and every
 // decomposition is independent.
-constexpr int kParts = 2;
+constexpr int kParts = 3;
 
 struct ChainParts {
   int device = 0;
