@@ -21,7 +21,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmctrg.so")
 
 if not os.path.exists(LIB_PATH):
-    raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1710_03757_amd.build` "
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python paper_1710_03757_amd/build.py` "
                       "(the HIP library is the only implementation; there is no fallback)")
 # torch ships its own HIP runtime under the same soname as the one the library
 # links (libamdhip64.so.7).  Loading torch first makes the dynamic loader bind

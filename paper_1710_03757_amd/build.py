@@ -3,7 +3,7 @@
 Every source under csrc/ is compiled with hipcc (device code for gfx950,
 packed-FP32 instructions disabled) into an object file, and the objects are
 linked into paper_1710_03757_amd/libmctrg.so.  Run as
-    python -m paper_1710_03757_amd.build
+    python paper_1710_03757_amd/build.py
 or through __graft_entry__.build().
 """
 from __future__ import annotations
