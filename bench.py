@@ -1,29 +1,38 @@
 #!/usr/bin/env python3
 """Benchmark of the Monte Carlo TRG hot path on one MI355X.
 
-Workload (default): the k = 32 form of the batched configuration - 2-D
-Ising site tensors at beta_c, h = 0, a chain of 30 coarse-graining steps
-(2^30 sites), FP32 coarse-graining GEMM, FP64 decomposition, sampling and
-log-normalisation, candidate cut tau_null = 1e-6 s_1 (see TAU_NULL).  A "step" is one full TRG step of the hot path (unfold,
-Jacobi SVD of both splits, subset sampling and reweighting, factors,
-contraction, normalisation) over the whole batch of samples.  The first
-``--warmup`` steps (the ramp-up of the bond dimension 2 -> 4 -> 16 -> 32 and
-one steady step) are untimed; the next ``--steps`` steps are timed between
-device synchronisations, followed by the final trace and the estimator.
+Workload: the k = 32 form of the batched configuration - 2-D Ising site
+tensors at beta_c, h = 0, 256 samples, a shared chain of warmup + steps
+coarse-graining steps (default 5 + 20 = 25 steps, a 2^25-site lattice).  A
+"step" is one full TRG step of the hot path (unfold, SVD of both splits,
+subset sampling and reweighting, factors, contraction, normalisation) over
+the whole batch.  The first ``--warmup`` steps (bond dimension 2 -> 4 ->
+16 -> 32 and the first steps at 32) are untimed; the next ``--steps`` steps
+are timed between device synchronisations, followed by the final trace and
+the estimator.
 
-Output: one JSON line with the throughput in sample-steps/s, a roofline
-record of the dominant kernel (the 128-column trailing update of the QR
-preconditioning, timed live with HIP events around every launch on the
-library's streams; its HBM traffic per launch from the committed rocprofv3
-counter summary when that was taken on the same kernel source and workload),
-the same timing for the Jacobi rotation kernel, the whole-step roofline
-fraction, the MFMA rate of the coarse-graining GEMM, the accuracy against the
-CPU oracle on the first samples, and the oracle's own rate on the host
-cores.
+Headline (``value``, ``dtype``): the paper's arithmetic, an FP64
+contraction with the candidate cut tau_null = 1e-11.  Beside it
+(``side_form``) the same window with an FP32 contraction (tau_null = 1e-6,
+above that contraction's rounding floor), with its speedup over the FP64
+form and both forms' |d ln Z|/site against the FP64 oracle.
+
+``roofline``: the dominant kernel (larger busy time of the Jacobi rotation
+kernel and the QR trailing update) against the FP64 MFMA peak, in the
+method's algorithmic flops: the decomposition's (14/3) k^6 per
+sample-step, attributed to the dominant kernel's dispatches of the window,
+over their average duration (HIP events around every dispatch on the
+library's own streams).  The kernel's own executed flops are reported
+separately (``implementation_flops_per_launch``).  HBM traffic per dispatch
+comes from the committed rocprofv3 counter summary when that was taken on
+the same kernel source and workload window.  Also reported: the whole-step
+roofline fraction, the MFMA rate of the coarse-graining GEMM and the CPU
+oracle's rate on the host cores.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import math
 import os
@@ -47,26 +56,27 @@ KERNEL_SRC = {JACOBI_KERNEL: os.path.join(ROOT, "paper_1710_03757_amd", "csrc", 
 # decomposition sees.  For an FP64 contraction that floor is the SVD's own
 # rounding (n eps), hence 1e-11; an FP32 contraction rounds T' at 2^-24 per
 # operand, which gives singular values of 1e-8..1e-7 s_1 that carry no signal,
-# hence 1e-6 (the library then also leaves rows below a tenth of the cut
-# unrotated).  BF16 and FP8 keep the FP64 cut: ten times their rounding floor
+# hence 1e-6.  BF16 and FP8 keep the FP64 cut: ten times their rounding floor
 # would cut most of the spectrum.
 TAU_NULL = {"f64": 1e-11, "f32": 1e-6, "bf16": 1e-11, "fp8": 1e-11}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k32_batch256.json")
 
 
-def measured_traffic(kernel, k, batch, parts, tau):
+def window_key(k, batch, parts, tau, dtype, warmup, steps):
+    return {"k": k, "batch": batch, "parts": parts, "tau_null": tau, "dtype": dtype, "warmup": warmup,
+            "steps": steps}
+
+
+def measured_traffic(kernel, key):
     """HBM bytes per dispatch of a kernel from the committed rocprofv3 --pmc
     FETCH_SIZE / WRITE_SIZE summary, if it was taken on the same kernel
-    source and workload shape (batch split in the same number of parts, same
-    candidate cut); otherwise None."""
-    import hashlib
+    source and the same workload window (key); otherwise None."""
     try:
         rec = json.load(open(TRAFFIC_FILE))[kernel]
         sha = hashlib.sha256(open(KERNEL_SRC[kernel], "rb").read()).hexdigest()
     except (OSError, ValueError, KeyError):
         return None
-    if rec.get("source_sha256") != sha or rec.get("k") != k or rec.get("batch") != batch or \
-            rec.get("parts", 1) != parts or rec.get("tau_null") != tau:
+    if rec.get("source_sha256") != sha or rec.get("window") != key:
         return None
     return rec
 
@@ -84,8 +94,105 @@ def gemm_flops(k: int) -> float:
     return 2.0 * k ** 6
 
 
-def cpu_baseline(k, beta, h, n_chain_steps, warmup, steps, samples, dtype):
-    """Times the CPU oracle on the same chains (steady steps only)."""
+def run_form(m, torch, args, dtype, tau):
+    """Runs the chains of one form over the window; returns its measurements."""
+    k, B = args.k, args.batch
+    n_chain = args.warmup + args.steps
+    ts = m.init_tensor("site", [args.beta], [args.h])
+    chain = m.Chain(ts, B, n_steps=n_chain, k=k, dtype=dtype, seed=0, profile=True, tau_null=tau)
+    for s in range(args.warmup):
+        chain.step(1)
+        print(f"[bench] {dtype}: warmup step {s} done, sweeps={chain.profile()['last_sweeps']}", flush=True)
+    torch.cuda.synchronize()
+    p0 = chain.profile()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    chain.step(args.steps)   # the timed steps in one call, as mctrg_run_samples advances a wave
+    res = chain.finish()
+    est = m.estimate_lnZ(res.sign, res.ln_abs_Z, 2.0 ** n_chain)
+    ev1.record()
+    torch.cuda.synchronize()
+    p1 = chain.profile()
+    ms_total = ev0.elapsed_time(ev1)
+    print(f"[bench] {dtype}: timed {args.steps} steps in {ms_total:.1f} ms, sweeps "
+          f"{p1['step_sweeps'][args.warmup:n_chain]}", flush=True)
+    out = dict(ms_total=ms_total, value=B * args.steps / (ms_total / 1e3), ms_per_step=ms_total / args.steps,
+               p0=p0, p1=p1, parts=p1["parts"], sweeps=p1["step_sweeps"][args.warmup:n_chain],
+               pairs_last=p1["last_pairs"], ln=res.ln_abs_Z.cpu().numpy(), sign=res.sign.cpu().numpy(),
+               est={k2: est[k2] for k2 in ("mean_lnZ_per_site", "stderr_mean_lnZ", "n_failed")})
+    chain.close()
+    ts.close()
+    return out
+
+
+def kernel_records(r, args, dtype, tau):
+    """Roofline records of the Jacobi and the 128-column QR update for one
+    form (the dominant first)."""
+    k, B = args.k, args.batch
+    p0, p1 = r["p0"], r["p1"]
+    d = lambda f: p1[f] - p0[f]  # noqa: E731
+    dec_alg = decomposition_flops(k) * B * args.steps
+    recs = {
+        JACOBI_KERNEL: dict(launches=d("jacobi_launches"), ms=d("jacobi_ms"), busy=d("jacobi_busy_ms"),
+                            impl=d("jacobi_flops"),
+                            impl_count=f"rotated block pairs ({d('jacobi_rotated_pairs')}) x 3 * 64^2 * rotated row "
+                                       "length (Gram + update; Grams of orthogonal pairs not counted)"),
+        QR128_KERNEL: dict(launches=d("qr128_launches"), ms=d("qr128_ms"), busy=d("qr128_busy_ms"),
+                           impl=d("qr128_flops"),
+                           impl_count="dense C <- C - V (T^T (V^T C)): 4 m 128 c + 128^2 c per job and launch"),
+    }
+    key = window_key(k, B, r["parts"], tau, dtype, args.warmup, args.steps)
+
+    def record(name):
+        x = recs[name]
+        n = max(x["launches"], 1)
+        avg = x["ms"] / n
+        alg = dec_alg / n
+        ach = alg / (avg / 1e3) / 1e12 if avg > 0 else None
+        tr = measured_traffic(name, key)
+        traffic = tr["fetch_bytes_per_launch"] + tr["write_bytes_per_launch"] if tr else None
+        return {"bound": "mfma", "kernel": name, "achieved": ach, "peak": PEAK_TFLOPS["f64"], "unit": "TFLOP/s",
+                "frac": ach / PEAK_TFLOPS["f64"] if ach else None, "traffic": traffic,
+                "traffic_unit": "HBM bytes per dispatch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                "algorithmic_flops_per_launch": alg,
+                "flop_count": "the decomposition's (14/3) k^6 FP64 flops per sample-step over the window, divided "
+                              "by this kernel's dispatches in the window",
+                "avg_launch_ms": avg, "launches": x["launches"], "parts": r["parts"], "busy_ms": x["busy"],
+                "achieved_over_busy_time": dec_alg / (x["busy"] / 1e3) / 1e12 if x["busy"] > 0 else None,
+                "implementation_flops_per_launch": x["impl"] / n,
+                "implementation_rate_TFLOPs": x["impl"] / (x["ms"] / 1e3) / 1e12 if x["ms"] > 0 else None,
+                "implementation_flop_count": x["impl_count"],
+                "share_of_step_time": x["busy"] / r["ms_total"] if r["ms_total"] else None}
+
+    dom = max(recs, key=lambda nme: recs[nme]["busy"])
+    other = QR128_KERNEL if dom == JACOBI_KERNEL else JACOBI_KERNEL
+    return record(dom), record(other)
+
+
+def gemm_record(r, args, dtype):
+    k, B = args.k, args.batch
+    p0, p1 = r["p0"], r["p1"]
+    gl, gms, gbusy = (p1[f] - p0[f] for f in ("gemm_launches", "gemm_ms", "gemm_busy_ms"))
+    galg = gemm_flops(k) * B * args.steps
+    g = {"kernel": f"gemm_tn_kernel<{dtype}>", "achieved": galg / (gms / 1e3) / 1e12 if gms > 0 else None,
+         "achieved_over_busy_time": galg / (gbusy / 1e3) / 1e12 if gbusy > 0 else None,
+         "peak": PEAK_TFLOPS[dtype], "unit": "TFLOP/s", "avg_launch_ms": gms / max(gl, 1), "launches": gl,
+         "busy_ms": gbusy, "flop_count": "2 k^6 per sample-step (k^2 x k^2 output, inner dimension k^2)"}
+    g["frac"] = g["achieved"] / g["peak"] if g["achieved"] else None
+    return g
+
+
+def t_ideal(k, dtype):
+    """SURVEY-style ideal time per sample-step at the peaks: algorithmic
+    decomposition flops at FP64, contraction flops at the GEMM dtype,
+    compulsory tensor bytes (read T, write T', FP64) at HBM peak."""
+    return (decomposition_flops(k) / (PEAK_TFLOPS["f64"] * 1e12) + gemm_flops(k) / (PEAK_TFLOPS[dtype] * 1e12)
+            + 2.0 * k ** 4 * 8 / (PEAK_HBM_TBS * 1e12))
+
+
+def cpu_baseline(args):
+    """Times the CPU oracle (FP64, tau_null 1e-11) on the first chains of the
+    batch; returns the rate over the timed window's steps and its results."""
     import numpy as np
     from oracle import ising, trg
     threads = None
@@ -94,14 +201,14 @@ def cpu_baseline(k, beta, h, n_chain_steps, warmup, steps, samples, dtype):
         threads = max((p.get("num_threads", 1) for p in threadpool_info()), default=None)
     except Exception:
         pass
-    T0 = ising.site_tensor(beta, h)
-    t_steady = 0.0
-    n_steady = 0
-    results = []
-    for sid in range(samples):
+    k = args.k
+    T0 = ising.site_tensor(args.beta, args.h)
+    t_steady, n_steady, results = 0.0, 0, []
+    n = args.warmup + args.steps
+    for sid in range(args.cpu_samples):
         T = T0.copy()
         ln_c = []
-        for step in range(warmup + steps):
+        for step in range(n):
             t0 = time.perf_counter()
             FA, GA, _ = trg.decompose_and_truncate(T, 0, k, "shared", 0, sid, 0, step, 1e-11)
             FB, GB, _ = trg.decompose_and_truncate(T, 1, k, "shared", 0, sid, 0, step, 1e-11)
@@ -110,39 +217,49 @@ def cpu_baseline(k, beta, h, n_chain_steps, warmup, steps, samples, dtype):
             T = Tn / c
             ln_c.append(math.log(c))
             dt = time.perf_counter() - t0
-            if step >= warmup:
+            if step >= args.warmup:
                 t_steady += dt
                 n_steady += 1
-        n = warmup + steps
         tr = trg.trace(T)
         N = 2.0 ** n
         ln = sum((N / 2.0 ** (s + 1)) * v for s, v in enumerate(ln_c)) + math.log(abs(tr))
         results.append((1 if tr > 0 else -1, ln))
+        print(f"[bench] oracle chain {sid} done", flush=True)
     return {
         "value": n_steady / t_steady,
         "unit": "sample-steps/s",
         "cores": threads if threads else os.cpu_count(),
         "kind": "oracle",
-        "sample": f"{samples} chains x {steps} steady steps at k={k} (n={k * k}), after {warmup} untimed "
-                  f"ramp-up steps; NumPy/LAPACK FP64, contraction FP64",
+        "sample": f"{args.cpu_samples} chains x {args.steps} timed steps (steps {args.warmup}..{n - 1}) at k={k} "
+                  f"(n={k * k}); NumPy/LAPACK FP64 SVD and einsum contraction, tau_null 1e-11",
         "seconds": t_steady,
     }, results
+
+
+def accuracy(r, ores, n_chain, dtype, tau):
+    N = 2.0 ** n_chain
+    diffs = [abs(float(r["ln"][i]) - o[1]) / N for i, o in enumerate(ores)]
+    return {"abs_dlnZ_per_site_vs_f64_oracle": diffs, "max": max(diffs), "samples": len(ores),
+            "signs_equal": bool(all(int(r["sign"][i]) == o[0] for i, o in enumerate(ores))), "lattice_sites": N,
+            "note": f"same Philox draws; GPU contraction {dtype} with tau_null {tau:g}; oracle FP64, tau_null 1e-11"}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=7)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--batch", type=int, default=256)
     ap.add_argument("--k", type=int, default=32)
-    ap.add_argument("--dtype", default="f32", choices=["f64", "f32", "bf16", "fp8"])
+    ap.add_argument("--dtype", default="f64", choices=["f64", "f32", "bf16", "fp8"],
+                    help="contraction dtype of the headline form")
+    ap.add_argument("--side-dtype", default="f32", choices=["none", "f64", "f32", "bf16", "fp8"],
+                    help="contraction dtype of the form run beside the headline")
     ap.add_argument("--beta", type=float, default=BETA_C)
     ap.add_argument("--h", type=float, default=0.0)
-    ap.add_argument("--chain-steps", type=int, default=30)
     ap.add_argument("--tau-null", type=float, default=None,
-                    help="candidate cut (default: per contraction dtype, see TAU_NULL)")
-    ap.add_argument("--cpu-samples", type=int, default=8)
+                    help="candidate cut of the headline form (default: per contraction dtype, see TAU_NULL)")
+    ap.add_argument("--cpu-samples", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="after the timed region, copy this many MiB device-to-device (a plain copy kernel of known "
@@ -154,9 +271,6 @@ def main():
               "multi-GPU run would split sample ids across ranks and reduce the estimator partials once at "
               "the end; that path is not built.", file=sys.stderr)
         sys.exit(2)
-    if args.warmup + args.steps > args.chain_steps:
-        print("warmup + steps must not exceed the chain length", file=sys.stderr)
-        sys.exit(2)
 
     import torch
     import paper_1710_03757_amd as m
@@ -164,150 +278,63 @@ def main():
     assert torch.cuda.is_available(), "bench needs a GPU"
     torch.cuda.set_device(0)
     k, B = args.k, args.batch
-    print(f"[bench] k={k} batch={B} dtype={args.dtype} warmup={args.warmup} steps={args.steps}", flush=True)
-    ts = m.init_tensor("site", [args.beta], [args.h])
+    n_chain = args.warmup + args.steps
     tau = TAU_NULL[args.dtype] if args.tau_null is None else args.tau_null
-    chain = m.Chain(ts, B, n_steps=args.chain_steps, k=k, dtype=args.dtype, seed=0, profile=True, tau_null=tau)
-    for s in range(args.warmup):
-        chain.step(1)
-        print(f"[bench] warmup step {s} done, sweeps={chain.profile()['last_sweeps']}", flush=True)
-    torch.cuda.synchronize()
-    p0 = chain.profile()
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    t0 = time.perf_counter()
-    ev0.record()
-    # the timed steps in one call, as mctrg_run_samples advances a wave: the
-    # two parts of the batch run free instead of joining after every step
-    chain.step(args.steps)
-    res = chain.finish()
-    est = m.estimate_lnZ(res.sign, res.ln_abs_Z, 2.0 ** (args.warmup + args.steps))
-    ev1.record()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    p1 = chain.profile()
-    sweeps = p1["step_sweeps"][args.warmup:args.warmup + args.steps]
-    pair_hist = p1["last_pairs"]
-    ms_total = ev0.elapsed_time(ev1)
-    wall = t1 - t0
-    print(f"[bench] timed {args.steps} steps: {ms_total:.1f} ms (events), {wall * 1e3:.1f} ms (wall), "
-          f"sweeps {sweeps}", flush=True)
-    ms_per_step = ms_total / args.steps
-    value = B * args.steps / (ms_total / 1e3)
-
-    parts = p1["parts"]
-    jl = p1["jacobi_launches"] - p0["jacobi_launches"]
-    jms = p1["jacobi_ms"] - p0["jacobi_ms"]
-    jbusy = p1["jacobi_busy_ms"] - p0["jacobi_busy_ms"]
-    gl = p1["gemm_launches"] - p0["gemm_launches"]
-    gms = p1["gemm_ms"] - p0["gemm_ms"]
-    gbusy = p1["gemm_busy_ms"] - p0["gemm_busy_ms"]
-    ql = p1["qr128_launches"] - p0["qr128_launches"]
-    qms = p1["qr128_ms"] - p0["qr128_ms"]
-    qbusy = p1["qr128_busy_ms"] - p0["qr128_busy_ms"]
-    qflops = p1["qr128_flops"] - p0["qr128_flops"]
-
-    def traffic_of(kernel, launches, busy):
-        tr = measured_traffic(kernel, k, B, parts, tau)
-        t = tr["fetch_bytes_per_launch"] + tr["write_bytes_per_launch"] if tr else None
-        return t, (t * launches / (busy / 1e3) / 1e12) if (t and busy > 0) else None
-
-    # The roofline record is the dominant kernel's: of the two FP64 MFMA
-    # kernels that take most of the step, the one with the larger busy time
-    # (union of its launch intervals over both parts, whose launches run
-    # concurrently).  achieved = its algorithmic flops over that busy time;
-    # avg_launch_ms is the mean duration of one dispatch (what rocprofv3
-    # reports per dispatch).
-    # * qr_trailing128_kernel (the 128-column trailing update of the second to
-    #   fifth QR): the dense count of C <- C - V (T^T (V^T C)), summed by the
-    #   library over the timed launches.
-    # * jacobi_round64_kernel: per rotated pair of 32-row blocks the 64 x 64
-    #   Gram over the rotated row length (64^2 len, symmetric) and the update
-    #   W <- Q^T W (2 64^2 len), summed by the library (len = the columns up
-    #   to the rank limit of the QRs); the Grams of pairs found orthogonal are
-    #   not counted, so this is a lower bound of the kernel's work.
-    jpairs = p1["jacobi_rotated_pairs"] - p0["jacobi_rotated_pairs"]
-    jflops = p1["jacobi_flops"] - p0["jacobi_flops"]
-    recs = {
-        QR128_KERNEL: dict(launches=ql, ms=qms, busy=qbusy, flops=qflops,
-                           count="dense C <- C - V (T^T (V^T C)): 4 m 128 c + 128^2 c per job and launch"),
-        JACOBI_KERNEL: dict(launches=jl, ms=jms, busy=jbusy, flops=jflops,
-                            count=f"rotated block pairs ({jpairs}) x 3 * 64^2 * rotated row length (Gram + "
-                                  "update; Grams of orthogonal pairs not counted)"),
-    }
-
-    def record(name):
-        r = recs[name]
-        ach = r["flops"] / (r["busy"] / 1e3) / 1e12 if r["busy"] > 0 else None
-        traffic, rate = traffic_of(name, r["launches"], r["busy"])
-        return {"bound": "mfma", "kernel": name, "achieved": ach, "peak": PEAK_TFLOPS["f64"], "unit": "TFLOP/s",
-                "frac": (ach / PEAK_TFLOPS["f64"]) if ach else None, "traffic": traffic,
-                "traffic_unit": "bytes per dispatch (HBM, FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-                "traffic_rate_TBs": rate, "avg_launch_ms": r["ms"] / max(r["launches"], 1),
-                "launches": r["launches"], "parts": parts, "flops_per_launch": r["flops"] / max(r["launches"], 1),
-                "flop_count": r["count"], "busy_ms": r["busy"],
-                "share_of_step_time": r["busy"] / ms_total if ms_total else None}
-
-    dom = max(recs, key=lambda n: recs[n]["busy"])
-    roofline = record(dom)
-    other = record(QR128_KERNEL if dom == JACOBI_KERNEL else JACOBI_KERNEL)
-    # the whole FP64 decomposition against the algorithmic count of the
-    # method ((14/3) k^6 per sample-step), over the step time
-    decomposition = {"algorithmic_flops_per_sample_step": decomposition_flops(k),
-                     "achieved_over_step_time": decomposition_flops(k) * B * args.steps / (ms_total / 1e3) / 1e12,
-                     "unit": "TFLOP/s", "peak": PEAK_TFLOPS["f64"]}
-    galg = gemm_flops(k) * B * args.steps
-    gemm = {"kernel": f"gemm_tn_kernel<{args.dtype}>", "achieved": galg / (gbusy / 1e3) / 1e12 if gbusy > 0 else None,
-            "peak": PEAK_TFLOPS[args.dtype], "unit": "TFLOP/s", "avg_launch_ms": gms / max(gl, 1), "launches": gl,
-            "busy_ms": gbusy}
-    gemm["frac"] = gemm["achieved"] / gemm["peak"] if gemm["achieved"] else None
-
-    # whole-step roofline fraction: ideal time per sample-step at the peaks
-    # (algorithmic decomposition flops at FP64, contraction flops at the GEMM
-    # dtype, compulsory tensor bytes at HBM peak) over the measured time
-    t_ideal = (decomposition_flops(k) / (PEAK_TFLOPS["f64"] * 1e12) + gemm_flops(k) / (PEAK_TFLOPS[args.dtype] * 1e12)
-               + 2.0 * k ** 4 * 8 / (PEAK_HBM_TBS * 1e12))
-    t_meas = (ms_total / 1e3) / (B * args.steps)
+    print(f"[bench] k={k} batch={B} dtype={args.dtype} warmup={args.warmup} steps={args.steps}", flush=True)
+    r = run_form(m, torch, args, args.dtype, tau)
+    roof, other = kernel_records(r, args, args.dtype, tau)
+    dec_alg = decomposition_flops(k) * B * args.steps
     out = {
         "metric": METRIC,
-        "value": value,
+        "value": r["value"],
         "unit": "sample-steps/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": r["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": args.dtype,
         "data": "synthetic",
-        "config": {"workload": f"2-D Ising site tensors, beta={args.beta:.6f}, h={args.h}, k={k}, chain of "
-                               f"{args.chain_steps} steps (2^{args.chain_steps} sites), shared chain, "
-                               f"steady-state steps {args.warmup}..{args.warmup + args.steps - 1}",
+        "config": {"workload": f"2-D Ising site tensors, beta={args.beta:.6f}, h={args.h}, k={k}, {B} samples, "
+                               f"shared chain of {n_chain} steps (2^{n_chain} sites), steps "
+                               f"{args.warmup}..{n_chain - 1} timed",
                    "k": k, "batch": B, "contract_dtype": args.dtype, "mode": "shared", "tau_null": tau,
-                   "decomposition": "FP64 one-sided block Jacobi"},
-        "roofline": roofline,
+                   "decomposition": "FP64 QR-preconditioned one-sided block Jacobi SVD",
+                   "sampling_and_log_norm": "FP64"},
+        "roofline": roof,
         "second_kernel": other,
-        "decomposition": decomposition,
-        "end_to_end_roofline_frac": t_ideal / t_meas,
-        "mfma_contraction": gemm,
-        "jacobi_sweeps_per_step": sweeps,
-        "jacobi_rotated_pairs_per_sweep_last_step": pair_hist,
-        "estimate_partial_chain": {k2: est[k2] for k2 in ("mean_lnZ_per_site", "stderr_mean_lnZ", "n_failed")},
+        "decomposition": {"algorithmic_flops_per_sample_step": decomposition_flops(k),
+                          "achieved_over_step_time": dec_alg / (r["ms_total"] / 1e3) / 1e12,
+                          "frac_over_step_time": dec_alg / (r["ms_total"] / 1e3) / 1e12 / PEAK_TFLOPS["f64"],
+                          "unit": "TFLOP/s", "peak": PEAK_TFLOPS["f64"]},
+        "end_to_end_roofline_frac": t_ideal(k, args.dtype) / ((r["ms_total"] / 1e3) / (B * args.steps)),
+        "mfma_contraction": gemm_record(r, args, args.dtype),
+        "jacobi_sweeps_per_step": r["sweeps"],
+        "jacobi_rotated_pairs_per_sweep_last_step": r["pairs_last"],
+        "estimate_partial_chain": r["est"],
     }
-
+    side = None
+    if args.side_dtype != "none":
+        stau = TAU_NULL[args.side_dtype]
+        side = run_form(m, torch, args, args.side_dtype, stau)
+        sroof, _ = kernel_records(side, args, args.side_dtype, stau)
+        out["side_form"] = {
+            "dtype": args.side_dtype, "tau_null": stau, "value": side["value"], "unit": "sample-steps/s",
+            "ms_per_step": side["ms_per_step"], "speedup_vs_headline": side["value"] / r["value"],
+            "end_to_end_roofline_frac": t_ideal(k, args.side_dtype) / ((side["ms_total"] / 1e3) / (B * args.steps)),
+            "mfma_contraction": gemm_record(side, args, args.side_dtype),
+            "dominant_kernel": {f: sroof[f] for f in ("kernel", "frac", "avg_launch_ms", "launches", "busy_ms",
+                                                      "share_of_step_time")},
+            "jacobi_sweeps_per_step": side["sweeps"], "estimate_partial_chain": side["est"]}
     if not args.no_cpu_baseline:
-        base, ores = cpu_baseline(k, args.beta, args.h, args.chain_steps, args.warmup, args.steps,
-                                  args.cpu_samples, args.dtype)
+        base, ores = cpu_baseline(args)
         out["cpu_baseline"] = base
-        ln = res.ln_abs_Z.cpu().numpy()
-        sg = res.sign.cpu().numpy()
-        N = 2.0 ** (args.warmup + args.steps)
-        diffs = [abs(float(ln[i]) - o[1]) / N for i, o in enumerate(ores)]
-        out["accuracy"] = {"abs_dlnZ_per_site_vs_f64_oracle": diffs, "samples": len(ores),
-                           "signs_equal": bool(all(int(sg[i]) == o[0] for i, o in enumerate(ores))),
-                           "lattice_sites": N, "note": "same Philox draws; GPU contraction in "
-                                                       f"{args.dtype} with tau_null {tau:g}, oracle FP64 "
-                                                       "with tau_null 1e-11"}
+        out["accuracy"] = {args.dtype: accuracy(r, ores, n_chain, args.dtype, tau)}
+        if side is not None:
+            out["accuracy"][args.side_dtype] = accuracy(side, ores, n_chain, args.side_dtype,
+                                                        TAU_NULL[args.side_dtype])
     if args.copy_probe_mb:
         src = torch.ones(args.copy_probe_mb * (1 << 20) // 4, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
@@ -316,7 +343,6 @@ def main():
         torch.cuda.synchronize()
         out["copy_probe_bytes"] = args.copy_probe_mb * (1 << 20)
     print(json.dumps(out), flush=True)
-    chain.close()
 
 
 if __name__ == "__main__":

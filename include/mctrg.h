@@ -86,7 +86,7 @@ enum mctrg_dtype { MCTRG_F64 = 0, MCTRG_F32 = 1, MCTRG_BF16 = 2, MCTRG_FP8_E4M3 
 
 /* flags */
 #define MCTRG_RECORD 1u   /* write per-step selection records to record_buf   */
-#define MCTRG_ASYNC  2u   /* return without synchronising hip_stream          */
+                          /* (bit 2u is not used)                              */
 #define MCTRG_PROFILE 4u  /* chains: time the decomposition and GEMM kernels  */
                           /* with HIP events (see mctrg_chain_get_profile)     */
 #define MCTRG_ONE_STREAM 8u  /* run every wave as one part on hip_stream (see */
@@ -123,14 +123,23 @@ typedef struct {
                            /*   (1e-8..1e-7 for F32) that carry no signal: a cut     */
                            /*   above them (1e-6 for F32) drops them from both the   */
                            /*   candidates and the rotations.                        */
-  uint32_t flags;          /* MCTRG_RECORD | MCTRG_ASYNC | MCTRG_PROFILE | ONE_STREAM */
-  int32_t* record_buf;     /* device, n_samples * n_steps * (4 + 2k) int32, or NULL:  */
-                           /*   per step: cA, cB (candidates), kA, kB (kept),        */
-                           /*   selA[k], selB[k] (kept indices into the descending    */
-                           /*   spectrum, -1 padded).  Shared and top-k modes only.   */
+  uint32_t flags;          /* MCTRG_RECORD | MCTRG_PROFILE | MCTRG_ONE_STREAM         */
+  int32_t* record_buf;     /* device int32, or NULL; with MCTRG_RECORD the kept sets: */
+                           /*   shared / top-k: n_samples * n_steps * (4 + 2k):       */
+                           /*   per step cA, cB (candidates), kA, kB (kept), selA[k], */
+                           /*   selB[k] (kept indices into the descending spectrum,   */
+                           /*   -1 padded);                                           */
+                           /*   independent: n_samples * sum_s 2^(n_steps-s) * (2+k): */
+                           /*   per step s, per position p of its level (in position  */
+                           /*   order: the rank of the originating A-site id), c,     */
+                           /*   kept, sel[k] of that tensor's one decomposition.      */
   double* out_tensor;      /* device or NULL: final normalised tensor of every sample */
                            /*   (shared/top-k), n_samples * Dc^4 with Dc the capacity */
                            /*   bond dimension after n_steps (mctrg_capacity_dim)     */
+  size_t max_workspace_bytes; /* device workspace the library may hold at once:      */
+                           /*   0 = 70% of the free device memory; waves of samples   */
+                           /*   are sized to fit; ENOMEM (outputs untouched) when one */
+                           /*   sample does not fit                                   */
 } mctrg_run_config;
 
 /* Fill *cfg with the defaults (seed 0, offset 0, tau_null 1e-11, F64, shared). */
@@ -161,8 +170,14 @@ int32_t mctrg_capacity_dim(int32_t d0, int32_t k, int32_t n_steps);
  *                    tensor; independent: sum over the level's tensors)
  * Per-sample results depend only on (seed, global sample id, group, k,
  * n_steps, mode, dtype, tau_null) - not on batch size or order.
- * Returns ENUMERIC if any sample failed (its sign is 0); other samples are
- * valid.  Errors: EINVAL, ENOMEM, EDEVICE, EUNSUPPORTED. */
+ * Returns ENUMERIC if any sample failed (its sign is 0, its ln|Z~| NaN: a
+ * non-finite normalisation, a zero trace or a decomposition that did not
+ * converge); the other samples are valid.  Blocks until the outputs are
+ * written.  Errors: EINVAL, ENOMEM, EDEVICE, EUNSUPPORTED.
+ * Test hook: when the environment variable MCTRG_TEST_FAIL_SAMPLE holds a
+ * global sample id, that sample's normalisation at the last step is made
+ * non-finite (the failure path above, without feeding a non-finite value
+ * through the decomposition kernels). */
 int mctrg_run_samples(mctrg_tensor_set* ts, const mctrg_run_config* cfg, int64_t n_samples,
                       const int32_t* group_of_sample, const int32_t* k_of_sample,
                       int8_t* out_sign, double* out_ln_abs_Z, double* out_ln_c,
@@ -193,12 +208,20 @@ int mctrg_estimate_lnZ(int64_t n_samples, const int8_t* sign, const double* ln_a
  * steps this is the sample of Z for the 2^s-site lattice - and writes
  * sign / ln|Z~| / ln c (device arrays, n_samples and n_samples *
  * cfg->n_steps; out_ln_c may be NULL).  Errors as mctrg_run_samples;
- * MCTRG_RECORD and out_tensor are ignored here. */
+ * MCTRG_RECORD writes cfg->record_buf as mctrg_run_samples does (sample i
+ * of the chain at index i); out_tensor is ignored here. */
 typedef struct mctrg_chain mctrg_chain;
 int mctrg_chain_create(mctrg_tensor_set* ts, const mctrg_run_config* cfg, int64_t n_samples,
                        const int32_t* group_of_sample, void* hip_stream, mctrg_chain** out);
 int mctrg_chain_step(mctrg_chain* ch, int32_t n);
 int mctrg_chain_finish(mctrg_chain* ch, int8_t* out_sign, double* out_ln_abs_Z, double* out_ln_c);
+/* The current normalised tensor T-hat of every sample after the steps done
+ * so far (Section III: the coarse tensor of the last step, divided by its
+ * largest |entry|): out (device FP64, caller-owned) receives n_samples * D^4
+ * values, sample i at offset i * D^4, legs [l][u][r][d] row-major, with D =
+ * mctrg_capacity_dim(d0, k, steps done).  Shared and top-k chains only
+ * (EUNSUPPORTED in independent mode).  Blocks until the copy is done. */
+int mctrg_chain_tensor(const mctrg_chain* ch, double* out);
 
 typedef struct {
   double jacobi_ms;         /* summed duration of the Jacobi rotation kernels    */

@@ -100,6 +100,7 @@ class SplitRecord:
     c: int
     sel: np.ndarray
     log_r: np.ndarray
+    split: int = 0
 
 
 @dataclass
@@ -115,6 +116,7 @@ class ChainResult:
     ln_abs_Z: float
     ln_c: List[float]
     records: List[StepRecord] = field(default_factory=list)
+    positions: List[List[SplitRecord]] = field(default_factory=list)   # independent mode: per step, per position
 
 
 def _split_mode(mode: str) -> str:
@@ -135,7 +137,7 @@ def decompose_and_truncate(T, split, k, mode, seed, sample_id, position, step, t
                       lambda c: selection_uniforms(seed, sample_id, position, step, split, c),
                       tau_null, forced_sel=forced)
     F, G = factors(U, Vt, tr, rs, cs)
-    return F, G, SplitRecord(s, tr.c, tr.sel, tr.log_r)
+    return F, G, SplitRecord(s, tr.c, tr.sel, tr.log_r, split)
 
 
 def run_shared(T0: np.ndarray, n_steps: int, k: int, seed: int, sample_id: int,
@@ -165,17 +167,19 @@ def run_shared(T0: np.ndarray, n_steps: int, k: int, seed: int, sample_id: int,
     return ChainResult(1 if tr > 0 else -1, ln_abs + math.log(abs(tr)), ln_c, recs)
 
 
-def step_independent(tensors, lev, k, mode, seed, sample_id, step, tau_null=1e-11, chooser=None):
+def step_independent(tensors, lev, k, mode, seed, sample_id, step, tau_null=1e-11, chooser=None, records=None):
     """One independent-mode TRG step over a whole lattice level.
 
     Returns (new_tensors, next_level, sum of ln c over the new positions),
-    or None if a coarse tensor is zero or not finite."""
+    or None if a coarse tensor is zero or not finite.  ``records``, if a
+    list, receives the step's SplitRecord of every position."""
     plaq, nxt = lattice.coarsen(lev)
     F, G = [None] * lev.n, [None] * lev.n
+    recs = [None] * lev.n
     for p in range(lev.n):
         split = 0 if lev.is_a[p] else 1
-        F[p], G[p], _ = decompose_and_truncate(tensors[p], split, k, mode, seed, sample_id, p, step,
-                                               tau_null, chooser)
+        F[p], G[p], recs[p] = decompose_and_truncate(tensors[p], split, k, mode, seed, sample_id, p, step,
+                                                     tau_null, chooser)
     new = []
     step_sum = 0.0
     for P, (p0, q0, p1, q1) in enumerate(plaq):
@@ -185,6 +189,8 @@ def step_independent(tensors, lev, k, mode, seed, sample_id, step, tau_null=1e-1
             return None
         new.append(Tn / c)
         step_sum += math.log(c)
+    if records is not None:
+        records.append(recs)
     return new, nxt, step_sum
 
 
@@ -208,17 +214,18 @@ def run_independent(T0: np.ndarray, n_steps: int, k: int, seed: int, sample_id: 
         tensors = [T0.copy() for _ in range(lev.n)]
     total = 0.0
     ln_c_steps: List[float] = []
+    positions: List[List[SplitRecord]] = []
     for step in range(n_steps):
-        out = step_independent(tensors, lev, k, mode, seed, sample_id, step, tau_null, chooser)
+        out = step_independent(tensors, lev, k, mode, seed, sample_id, step, tau_null, chooser, positions)
         if out is None:
-            return ChainResult(0, math.nan, ln_c_steps)
+            return ChainResult(0, math.nan, ln_c_steps, positions=positions)
         tensors, lev, step_sum = out
         total += step_sum
         ln_c_steps.append(step_sum)
     tr = trace(tensors[0])
     if tr == 0.0:
-        return ChainResult(0, -math.inf, ln_c_steps)
-    return ChainResult(1 if tr > 0 else -1, total + math.log(abs(tr)), ln_c_steps)
+        return ChainResult(0, -math.inf, ln_c_steps, positions=positions)
+    return ChainResult(1 if tr > 0 else -1, total + math.log(abs(tr)), ln_c_steps, positions=positions)
 
 
 def run(T0, n_steps, k, seed, sample_id, mode="shared", tau_null=1e-11, keep_tensors=False) -> ChainResult:

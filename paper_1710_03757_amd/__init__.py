@@ -35,7 +35,7 @@ OK, EINVAL, ENOMEM, EDEVICE, ENUMERIC, EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 ISING_SITE, ISING_PLAQUETTE, USER = 0, 1, 2
 SHARED, INDEPENDENT, TOPK = 0, 1, 2
 F64, F32, BF16, FP8_E4M3 = 0, 1, 2, 3
-RECORD, ASYNC, PROFILE, ONE_STREAM = 1, 2, 4, 8
+RECORD, PROFILE, ONE_STREAM = 1, 4, 8
 
 MODES = {"shared": SHARED, "independent": INDEPENDENT, "topk": TOPK}
 DTYPES = {"f64": F64, "f32": F32, "bf16": BF16, "fp8": FP8_E4M3}
@@ -44,14 +44,16 @@ MODELS = {"site": ISING_SITE, "vertex": ISING_SITE, "plaquette": ISING_PLAQUETTE
 EXPORTED = ("mctrg_init_tensor", "mctrg_tensor_set_info", "mctrg_default_config", "mctrg_capacity_dim",
             "mctrg_run_samples", "mctrg_estimate_lnZ", "mctrg_destroy", "mctrg_status_string",
             "mctrg_svd_batched", "mctrg_sample_batched", "mctrg_contract_batched", "mctrg_chain_create",
-            "mctrg_chain_step", "mctrg_chain_finish", "mctrg_chain_get_profile", "mctrg_chain_destroy")
+            "mctrg_chain_step", "mctrg_chain_finish", "mctrg_chain_get_profile", "mctrg_chain_destroy",
+            "mctrg_chain_tensor")
 
 
 class RunConfig(ctypes.Structure):
     _fields_ = [("seed", ctypes.c_uint64), ("sample_offset", ctypes.c_int64), ("n_steps", ctypes.c_int32),
                 ("k", ctypes.c_int32), ("mode", ctypes.c_int32), ("contract_dtype", ctypes.c_int32),
                 ("tau_null", ctypes.c_double), ("flags", ctypes.c_uint32),
-                ("record_buf", ctypes.c_void_p), ("out_tensor", ctypes.c_void_p)]
+                ("record_buf", ctypes.c_void_p), ("out_tensor", ctypes.c_void_p),
+                ("max_workspace_bytes", ctypes.c_size_t)]
 
 
 class Estimate(ctypes.Structure):
@@ -111,6 +113,8 @@ _lib.mctrg_chain_step.argtypes = [_vp, _i32]
 _lib.mctrg_chain_step.restype = ctypes.c_int
 _lib.mctrg_chain_finish.argtypes = [_vp, _vp, _vp, _vp]
 _lib.mctrg_chain_finish.restype = ctypes.c_int
+_lib.mctrg_chain_tensor.argtypes = [_vp, _vp]
+_lib.mctrg_chain_tensor.restype = ctypes.c_int
 _lib.mctrg_chain_get_profile.argtypes = [_vp, ctypes.POINTER(ChainProfile)]
 _lib.mctrg_chain_get_profile.restype = ctypes.c_int
 _lib.mctrg_chain_destroy.argtypes = [_vp]
@@ -235,9 +239,11 @@ class SampleResult:
 def run_samples(ts: TensorSet, n_samples: int, *, n_steps: int, k: int, mode="shared", dtype="f64",
                 seed: int = 0, sample_offset: int = 0, tau_null: float = 1e-11, groups=None,
                 ks=None, want_ln_c: bool = False, record: bool = False, want_tensor: bool = False,
-                async_: bool = False, out_sign=None, out_ln_abs_Z=None, one_stream: bool = False) -> SampleResult:
+                out_sign=None, out_ln_abs_Z=None, one_stream: bool = False,
+                max_workspace_bytes: int = 0, out_ln_c=None, allow=()) -> SampleResult:
     """mctrg_run_samples.  ``groups`` / ``ks``: host sequences (one per sample).
-    ``one_stream``: run every wave as one part (MCTRG_ONE_STREAM)."""
+    ``one_stream``: run every wave as one part (MCTRG_ONE_STREAM).  ``allow``:
+    further status codes returned instead of raised (as ``status``)."""
     import numpy as np
     torch = _torch()
     cfg = default_config()
@@ -255,10 +261,13 @@ def run_samples(ts: TensorSet, n_samples: int, *, n_steps: int, k: int, mode="sh
     ln = out_ln_abs_Z if out_ln_abs_Z is not None else torch.empty(n_samples, dtype=torch.float64, device=dev)
     _dev(torch, sign, torch.int8, "out_sign")
     _dev(torch, ln, torch.float64, "out_ln_abs_Z")
-    lnc = torch.empty((n_samples, n_steps), dtype=torch.float64, device=dev) if want_ln_c else None
+    lnc = out_ln_c if out_ln_c is not None else \
+        (torch.empty((n_samples, n_steps), dtype=torch.float64, device=dev) if want_ln_c else None)
     rec = None
     if record:
-        rec = torch.full((n_samples, n_steps, 4 + 2 * k), -7, dtype=torch.int32, device=dev)
+        shape = (n_samples, n_steps, 4 + 2 * k) if cfg.mode != INDEPENDENT else \
+            (n_samples, record_positions(n_steps), 2 + k)
+        rec = torch.full(shape, -7, dtype=torch.int32, device=dev)
         cfg.flags |= RECORD
         cfg.record_buf = rec.data_ptr()
     ten = None
@@ -266,8 +275,7 @@ def run_samples(ts: TensorSet, n_samples: int, *, n_steps: int, k: int, mode="sh
         Dc = capacity_dim(ts.d0, k, n_steps)
         ten = torch.empty((n_samples, Dc, Dc, Dc, Dc), dtype=torch.float64, device=dev)
         cfg.out_tensor = ten.data_ptr()
-    if async_:
-        cfg.flags |= ASYNC
+    cfg.max_workspace_bytes = int(max_workspace_bytes)
     g = None if groups is None else np.ascontiguousarray(groups, dtype=np.int32)
     kk = None if ks is None else np.ascontiguousarray(ks, dtype=np.int32)
     for arr, nm in ((g, "groups"), (kk, "ks")):
@@ -277,8 +285,25 @@ def run_samples(ts: TensorSet, n_samples: int, *, n_steps: int, k: int, mode="sh
                                 None if g is None else g.ctypes.data_as(ctypes.c_void_p),
                                 None if kk is None else kk.ctypes.data_as(ctypes.c_void_p),
                                 _ptr(sign), _ptr(ln), _ptr(lnc), _stream(torch))
-    _check(st, "mctrg_run_samples", allow=(OK, ENUMERIC))
+    _check(st, "mctrg_run_samples", allow=(OK, ENUMERIC) + tuple(allow))
     return SampleResult(sign, ln, lnc, st, rec, ten)
+
+
+def record_positions(n_steps: int) -> int:
+    """Positions over all levels of an independent-mode record: level s of a
+    2^n_steps-site torus holds 2^(n_steps - s) tensors."""
+    return sum(2 ** (n_steps - s) for s in range(n_steps))
+
+
+def split_independent_record(rec, n_steps: int):
+    """Host view of one sample's independent-mode record (positions x (2 + k)
+    int array) as a list over steps of (c, kept, sel) arrays per position."""
+    out, base = [], 0
+    for s in range(n_steps):
+        npos = 2 ** (n_steps - s)
+        out.append(rec[base:base + npos])
+        base += npos
+    return out
 
 
 def estimate_lnZ(sign, ln_abs_Z, n_sites: float) -> dict:
@@ -348,7 +373,7 @@ class Chain:
 
     def __init__(self, ts: TensorSet, n_samples: int, *, n_steps: int, k: int, mode="shared", dtype="f64",
                  seed: int = 0, sample_offset: int = 0, tau_null: float = 1e-11, groups=None, profile=False,
-                 one_stream=False):
+                 one_stream=False, record=False):
         import numpy as np
         torch = _torch()
         cfg = default_config()
@@ -360,8 +385,16 @@ class Chain:
             cfg.flags |= PROFILE
         if one_stream:
             cfg.flags |= ONE_STREAM
+        self.k = k
+        self.record = None
+        if record:
+            dev = torch.device("cuda", torch.cuda.current_device())
+            self.record = torch.full((n_samples, n_steps, 4 + 2 * k), -7, dtype=torch.int32, device=dev)
+            cfg.flags |= RECORD
+            cfg.record_buf = self.record.data_ptr()
         g = None if groups is None else np.ascontiguousarray(groups, dtype=np.int32)
         self._ts = ts
+        self.steps_done = 0
         self.n_samples, self.n_steps = n_samples, n_steps
         self._h = ctypes.c_void_p()
         _check(_lib.mctrg_chain_create(ts.handle, ctypes.byref(cfg), n_samples,
@@ -370,6 +403,16 @@ class Chain:
 
     def step(self, n: int = 1):
         _check(_lib.mctrg_chain_step(self._h, n), "mctrg_chain_step")
+        self.steps_done += n
+
+    def tensor(self):
+        """mctrg_chain_tensor: the current normalised tensors (n, D, D, D, D)."""
+        torch = _torch()
+        D = capacity_dim(self._ts.d0, self.k, self.steps_done)
+        out = torch.empty((self.n_samples, D, D, D, D), dtype=torch.float64,
+                          device=torch.device("cuda", torch.cuda.current_device()))
+        _check(_lib.mctrg_chain_tensor(self._h, _ptr(out)), "mctrg_chain_tensor")
+        return out
 
     def finish(self, want_ln_c=False):
         torch = _torch()

@@ -10,6 +10,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <functional>
 #include <memory>
@@ -188,6 +189,7 @@ struct Chain {
   int64_t rotated_pairs = 0;              // block pairs rotated, summed over all steps and sweeps
   double jacobi_flops = 0.0;              // their Gram + update flops at the row length used
   int step_sweeps[64] = {};               // Jacobi sweeps of every step
+  int64_t fail_sid = -1;                  // test hook: global sample id whose last ln c is made non-finite
 
   ~Chain() {
     if (mem) (void)hipFree(mem);
@@ -310,6 +312,16 @@ int build_levels(Chain& c) {
   }
   if (lev.n != 1) return MCTRG_EINVAL;
   return MCTRG_OK;
+}
+
+// int32 entries of the selection record per sample: shared and top-k
+// n_steps * (4 + 2 kmax); independent mode (2 + kmax) per position of every
+// level.
+int64_t record_per_sample(const Chain& c) {
+  if (c.mode != MCTRG_INDEPENDENT) return (int64_t)c.n_steps * (4 + 2 * c.kmax_rec);
+  int64_t n = 0;
+  for (int t = 0; t < c.n_steps; ++t) n += (int64_t)c.levels[t].n * (2 + c.kmax_rec);
+  return n;
 }
 
 size_t chain_bytes(Chain& c) {
@@ -435,19 +447,19 @@ int chain_step(Chain& c) {
   int jcols = 0;         // the Jacobi rows are zero from this column on (0: none)
   KernelTimer* tq = c.tq.enabled ? &c.tq : nullptr;
   if (qr5) {
-    // the first QR stops once the columns it has not factored lie below the
-    // deflation floor in every job (their rows of R1 are then set to zero)
+    // the first QR stops once the columns it has not factored hold at most the
+    // approximation budget in every job (their rows of R1 are then set to zero)
     QrStop stop;
-    stop.floor_rel = std::max(0x1.0p-48, 0.1 * c.tau);
+    stop.budget = approx_budget(c.tau);
     stop.dev = c.jw.counter;
     stop.host = c.jw.counter_host;
     CKH(run_qr1(nj, sh.n, sh.D, sh.n_pad, c.Ta, c.src, c.split, c.perm, c.dpos, c.S, c.W, c.Tscr, c.colmap, c.colnorm,
                 c.st, &stop));
-    // The first QR re-orders the columns by norm, so the rows of R1 above the
-    // deflation floor come first: the later QRs run over the leading ncols
-    // columns only (the rows from ncols on, all at the floor, are set to zero,
-    // which moves the singular values by at most their norm, as the
-    // deflation does).
+    // The first QR re-orders the columns by norm, so the rows of R1 come in
+    // roughly decreasing norm: the later QRs run over the leading ncols
+    // columns only, where the rows from ncols on hold at most the
+    // approximation budget in total (they are set to zero, which moves the
+    // singular values by at most their Frobenius norm).
     int rows1 = 0;
     CKH(run_rank_rows(nj, sh.n_pad, c.tau, c.W, c.dnrm, c.nb_job, c.jw.counter, c.jw.counter_host, &rows1, c.st));
     const int ncols = std::min(sh.n_pad, std::max(128, 128 * ceil_div(rows1, 128)));
@@ -497,8 +509,16 @@ int chain_step(Chain& c) {
   sa.sigma = c.sigma; sa.rng = c.rng; sa.split = c.split; sa.kept = c.kept; sa.cand = c.cand;
   sa.sel = c.sel; sa.log_r = c.logr; sa.weight = c.weight; sa.scratch = c.sscr;
   CKH(launch_sample(sa, c.st));
-  if ((c.flags & MCTRG_RECORD) && c.record)
-    CKH(launch_record(c.nsamp, s, c.n_steps, c.kmax_rec, sh.kc, c.idx, c.cand, c.kept, c.sel, c.record, c.st));
+  if ((c.flags & MCTRG_RECORD) && c.record) {
+    if (c.mode == MCTRG_INDEPENDENT) {
+      int64_t base = 0;
+      for (int t = 0; t < s; ++t) base += (int64_t)c.levels[t].n * (2 + c.kmax_rec);
+      CKH(launch_record_positions(c.nsamp, sh.P, record_per_sample(c), base, c.kmax_rec, sh.kc, c.idx, c.cand, c.kept,
+                                  c.sel, c.record, c.st));
+    } else {
+      CKH(launch_record(c.nsamp, s, c.n_steps, c.kmax_rec, sh.kc, c.idx, c.cand, c.kept, c.sel, c.record, c.st));
+    }
+  }
   if (qr5 && !three) {
     // z = Q2 Q4 y (in F as scratch), v = P z into G with the gauge, u = M v / s
     CKH(launch_apply_q1(nj, sh.n, sh.n_pad, sh.kc, c.W, nullptr, c.Tws2, c.S, c.Tws, Wj, c.sigma, c.order, c.kept,
@@ -525,6 +545,9 @@ int chain_step(Chain& c) {
   CKH(launch_contract(ca, c.st, c.tg.enabled ? &c.tg : nullptr));
   const int64_t K4 = (int64_t)sh.kc * sh.kc * sh.kc * sh.kc;
   CKH(launch_normalize(no, K4, c.dtype != MCTRG_F64, c.Tn, c.scales, c.cbuf, c.Tb, c.lnc, c.st));
+  if (c.fail_sid >= 0 && s == c.n_steps - 1)
+    for (int64_t i = 0; i < c.nsamp; ++i)
+      if (c.sids[i] == c.fail_sid) CKH(launch_set_double(c.lnc + i * sh.ops, std::nan(""), c.st));
   CKH(launch_lnc_accum(c.nsamp, sh.ops, s, c.n_steps, c.lnc, c.lnc_steps, c.failed, c.st));
   std::swap(c.Ta, c.Tb);
   c.step++;
@@ -830,7 +853,6 @@ int mctrg_run_samples(mctrg_tensor_set* ts, const mctrg_run_config* cfg, int64_t
       if (k_of_sample[i] < 1 || k_of_sample[i] > 64) return MCTRG_EINVAL;
   const bool record = (cfg->flags & MCTRG_RECORD) != 0;
   if (record) {
-    if (cfg->mode == MCTRG_INDEPENDENT) return MCTRG_EUNSUPPORTED;
     if (!cfg->record_buf) return MCTRG_EINVAL;
     if (k_of_sample)
       for (int64_t i = 0; i < n_samples; ++i)
@@ -856,28 +878,39 @@ int mctrg_run_samples(mctrg_tensor_set* ts, const mctrg_run_config* cfg, int64_t
     ks.push_back(cfg->k);
   }
   bool any_fail = false;
-  for (int kb : ks) {
+  int64_t fail_sid = -1;   // test hook (see mctrg.h): this sample's last normalisation is made non-finite
+  if (const char* e = std::getenv("MCTRG_TEST_FAIL_SAMPLE")) fail_sid = std::strtoll(e, nullptr, 10);
+  size_t freeb = 0, totalb = 0;
+  if (hipMemGetInfo(&freeb, &totalb) != hipSuccess) return MCTRG_EDEVICE;
+  double budget = 0.70 * (double)freeb;
+  if (cfg->max_workspace_bytes > 0) budget = std::min(budget, (double)cfg->max_workspace_bytes);
+  // every bucket's chains are sized before anything is enqueued: one sample
+  // that does not fit the workspace budget gives ENOMEM with the outputs untouched
+  std::vector<Chain> probes(ks.size());
+  for (size_t b = 0; b < ks.size(); ++b) {
+    Chain& probe = probes[b];
+    probe.mode = cfg->mode; probe.dtype = cfg->contract_dtype; probe.k = ks[b]; probe.n_steps = cfg->n_steps;
+    probe.Dsched = schedule(ts->d0, ks[b], cfg->n_steps);
+    if (cfg->mode == MCTRG_INDEPENDENT && build_levels(probe) != MCTRG_OK) return MCTRG_EINVAL;
+    probe.nsamp = 1;
+    if ((double)chain_bytes(probe) > budget) return MCTRG_ENOMEM;
+  }
+  for (size_t b = 0; b < ks.size(); ++b) {
+    const int kb = ks[b];
+    Chain& probe = probes[b];
     std::vector<int64_t> members;
     for (int64_t i = 0; i < n_samples; ++i)
       if ((k_of_sample ? k_of_sample[i] : cfg->k) == kb) members.push_back(i);
-    // wave size from free device memory
-    Chain probe;
-    probe.mode = cfg->mode; probe.dtype = cfg->contract_dtype; probe.k = kb; probe.n_steps = cfg->n_steps;
-    probe.Dsched = schedule(ts->d0, kb, cfg->n_steps);
-    if (cfg->mode == MCTRG_INDEPENDENT && build_levels(probe) != MCTRG_OK) return MCTRG_EINVAL;
+    // wave size from the workspace budget
     probe.nsamp = 1;
     const size_t per1 = chain_bytes(probe);
     probe.nsamp = 2;
     const size_t per_sample = std::max<size_t>(1, chain_bytes(probe) - per1);
-    size_t freeb = 0, totalb = 0;
-    if (hipMemGetInfo(&freeb, &totalb) != hipSuccess) return MCTRG_EDEVICE;
-    const double budget = 0.70 * (double)freeb;
     // a wave of two or more samples runs as up to kParts parts, each with its own
     // per-chain (sample-independent) allocations
     const double fixed = std::max(0.0, (double)per1 - (double)per_sample);
     const int parts = (cfg->flags & MCTRG_ONE_STREAM) ? 1 : kParts;
     int64_t wave = (int64_t)std::max(1.0, std::floor((budget - parts * fixed) / (double)per_sample));
-    if ((double)per1 > budget) return MCTRG_ENOMEM;
     wave = std::min<int64_t>(wave, (int64_t)members.size());
     for (size_t w0 = 0; w0 < members.size(); w0 += (size_t)wave) {
       const size_t w1 = std::min(members.size(), w0 + (size_t)wave);
@@ -897,6 +930,7 @@ int mctrg_run_samples(mctrg_tensor_set* ts, const mctrg_run_config* cfg, int64_t
         c.Dsched = probe.Dsched;
         c.levels = probe.levels;
         c.plaqs = probe.plaqs;
+        c.fail_sid = fail_sid;
       };
       ChainParts cp;
       rc = parts_start(cp, configure, ts, groups, out_index, sids, st, (cfg->flags & MCTRG_ONE_STREAM) != 0,
@@ -932,6 +966,7 @@ int mctrg_chain_create(mctrg_tensor_set* ts, const mctrg_run_config* cfg, int64_
   if (group_of_sample)
     for (int64_t i = 0; i < n_samples; ++i)
       if (group_of_sample[i] < 0 || group_of_sample[i] >= ts->ngroups) return MCTRG_EINVAL;
+  if ((cfg->flags & MCTRG_RECORD) && !cfg->record_buf) return MCTRG_EINVAL;
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess || dev != ts->device) return MCTRG_EINVAL;
   Chain probe;
@@ -950,7 +985,8 @@ int mctrg_chain_create(mctrg_tensor_set* ts, const mctrg_run_config* cfg, int64_
   }
   auto configure = [&](Chain& c) {
     c.mode = cfg->mode; c.dtype = cfg->contract_dtype; c.k = cfg->k; c.n_steps = cfg->n_steps;
-    c.tau = cfg->tau_null; c.seed = cfg->seed; c.flags = cfg->flags & MCTRG_PROFILE; c.record = nullptr;
+    c.tau = cfg->tau_null; c.seed = cfg->seed; c.flags = cfg->flags & (MCTRG_PROFILE | MCTRG_RECORD);
+    c.record = (cfg->flags & MCTRG_RECORD) ? cfg->record_buf : nullptr;
     c.kmax_rec = cfg->k;
     c.Dsched = probe.Dsched;
     c.levels = probe.levels;
@@ -976,6 +1012,21 @@ int mctrg_chain_finish(mctrg_chain* ch, int8_t* out_sign, double* out_ln_abs_Z, 
   const int rc = parts_finish(ch->cp, out_sign, out_ln_abs_Z, out_ln_c, nullptr);
   if (rc != MCTRG_OK) return rc;
   if (hipStreamSynchronize(ch->cp.caller) != hipSuccess) return MCTRG_EDEVICE;
+  return MCTRG_OK;
+}
+
+int mctrg_chain_tensor(const mctrg_chain* ch, double* out) {
+  if (!ch || !out || ch->cp.parts.empty()) return MCTRG_EINVAL;
+  if (ch->cp.parts[0]->mode == MCTRG_INDEPENDENT) return MCTRG_EUNSUPPORTED;
+  size_t off = 0;
+  for (const auto& c : ch->cp.parts) {
+    const size_t D = (size_t)c->Dsched[c->step], per = D * D * D * D;
+    CKH(hipMemcpyAsync(out + off, c->Ta, (size_t)c->nsamp * per * sizeof(double), hipMemcpyDeviceToDevice, c->st));
+    off += (size_t)c->nsamp * per;
+  }
+  const int rc = parts_join(const_cast<ChainParts&>(ch->cp));
+  if (rc != MCTRG_OK) return rc;
+  CKH(hipStreamSynchronize(ch->cp.caller));
   return MCTRG_OK;
 }
 

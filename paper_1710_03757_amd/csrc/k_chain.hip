@@ -39,6 +39,36 @@ hipError_t launch_record(int64_t nsamp, int step, int n_steps, int kmax, int kca
   return hipGetLastError();
 }
 
+// Independent mode: rec[idx[s] * per_sample + base + p * (2 + kmax) + ...] =
+// c, kept, sel[kmax] of the decomposition at position p of this step's level
+// (jobs s * npos + p), -1 padded.
+__global__ void record_positions_kernel(int npos, int64_t per_sample, int64_t base, int kmax, int kcap,
+                                        const int64_t* __restrict__ idx, const int32_t* __restrict__ cand,
+                                        const int32_t* __restrict__ kept, const int32_t* __restrict__ sel,
+                                        int32_t* __restrict__ rec) {
+  const int64_t s = blockIdx.y;
+  const int p = blockIdx.x;
+  const int stride = 2 + kmax;
+  const int64_t j = s * npos + p;
+  int32_t* r = rec + (size_t)idx[s] * per_sample + base + (int64_t)p * stride;
+  for (int t = threadIdx.x; t < stride; t += blockDim.x) {
+    int32_t v;
+    if (t == 0) v = cand[j];
+    else if (t == 1) v = kept[j];
+    else v = (t - 2) < kcap ? sel[j * kcap + (t - 2)] : -1;
+    r[t] = v;
+  }
+}
+
+hipError_t launch_record_positions(int64_t nsamp, int npos, int64_t per_sample, int64_t base, int kmax, int kcap,
+                                   const int64_t* idx, const int32_t* cand, const int32_t* kept, const int32_t* sel,
+                                   int32_t* rec, hipStream_t stream) {
+  if (nsamp == 0 || npos == 0) return hipSuccess;
+  hipLaunchKernelGGL(record_positions_kernel, dim3((unsigned)npos, (unsigned)nsamp), dim3(64), 0, stream, npos,
+                     per_sample, base, kmax, kcap, idx, cand, kept, sel, rec);
+  return hipGetLastError();
+}
+
 // lnc_steps[s * n_steps + step] = sum over the sample's outputs (fixed order);
 // failed[s] |= any non-finite.
 __global__ void lnc_accum_kernel(int64_t nsamp, int out_per_sample, int step, int n_steps,
@@ -71,6 +101,13 @@ hipError_t launch_jacobi_fail(int64_t njobs, int jobs_per_sample, const int* swe
   if (njobs == 0) return hipSuccess;
   hipLaunchKernelGGL(jacobi_fail_kernel, dim3(ceil_div(njobs, 256)), dim3(256), 0, stream, njobs, jobs_per_sample,
                      sweeps, failed);
+  return hipGetLastError();
+}
+
+__global__ void set_double_kernel(double* p, double v) { *p = v; }
+
+hipError_t launch_set_double(double* p, double v, hipStream_t stream) {
+  hipLaunchKernelGGL(set_double_kernel, dim3(1), dim3(1), 0, stream, p, v);
   return hipGetLastError();
 }
 

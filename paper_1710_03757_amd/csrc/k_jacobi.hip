@@ -738,16 +738,17 @@ hipError_t run_jacobi(int64_t njobs, int n_pad, double* W, const JacobiWork& wk,
 }
 
 // ---------------------------------------------------------------------------
-// Noise-floor deflation.  Rows whose norm is at most floor_rel times the
-// largest row norm are moved behind the others (stable partition) and
-// excluded from the rotations.  floor_rel is 2^-48 (the rounding level of an
-// FP64 SVD) or a tenth of the candidate cut tau_null, whichever is larger:
-// such a row has norm <= 0.1 tau_null s_1 (the largest row norm is at most
-// s_1), so its singular value can never be a candidate, and leaving it
-// unrotated perturbs the singular values of the rest by at most its norm
-// (Weyl; to second order when, as after the QR preconditioning, it is nearly
-// orthogonal to the larger rows).  nb_job receives the
-// number of row blocks (even, at least 2) that cover the active rows.
+// ---------------------------------------------------------------------------
+// Noise-floor deflation.  Rows whose squared norm is at most budget^2 / n_pad
+// times the largest squared row norm (budget = approx_budget(tau_null)) are
+// moved behind the others (stable partition) and excluded from the
+// rotations.  Together they hold at most budget^2 times the largest squared
+// row norm (at most s_1^2), so leaving them unrotated perturbs the singular
+// values of the rest by at most budget s_1 (Weyl; to second order when, as
+// after the QR preconditioning, they are nearly orthogonal to the larger
+// rows), and their own values (each below budget s_1, a thirtieth of the
+// cut) can never be candidates.  nb_job receives the number of row blocks
+// (even, at least 2) that cover the active rows.
 // Three kernels: squared row norms and the row copy (one wave per row), and
 // the partition between them (one workgroup per job); n_pad <= 4096.
 // ---------------------------------------------------------------------------
@@ -822,28 +823,50 @@ __global__ __launch_bounds__(256) void deflate_copy_kernel(int n_pad, const doub
   for (int c = lane; c < n_pad / 2; c += 64) dst[c] = src[c];
 }
 
-// Per job: one past the last row whose squared norm exceeds floor_sq times
-// the largest (0 when every row is at the floor).
-__global__ __launch_bounds__(256) void last_row_above_kernel(int n_pad, double floor_sq,
+// Per job: the smallest L such that the rows from L on hold at most
+// budget_sq times the largest squared row norm in total (suffix sums of the
+// squared norms, which do not increase with L; n_pad <= 4096: m = n_pad / 256
+// consecutive rows per thread, scanned from the end).
+__global__ __launch_bounds__(256) void last_row_above_kernel(int n_pad, double budget_sq,
                                                              const double* __restrict__ nrm, int* __restrict__ last) {
   const int64_t job = blockIdx.x;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const double* nj = nrm + (size_t)job * n_pad;
   __shared__ double red[4];
+  __shared__ double suf[256];
   __shared__ int redi[4];
   double mx = 0.0;
   for (int r = tid; r < n_pad; r += 256) mx = fmax(mx, nj[r]);
   for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o));
   if (lane == 0) red[wave] = mx;
+  const int m = (n_pad + 255) / 256, r0 = tid * m;
+  double own = 0.0;
+  for (int q = 0; q < m; ++q)
+    if (r0 + q < n_pad) own += nj[r0 + q];
+  suf[tid] = own;
   __syncthreads();
-  const double thr = fmax(fmax(red[0], red[1]), fmax(red[2], red[3])) * floor_sq;
-  int l = 0;
-  for (int r = tid; r < n_pad; r += 256)
-    if (nj[r] > thr) l = r + 1;
-  for (int o = 32; o > 0; o >>= 1) l = max(l, __shfl_xor(l, o));
-  if (lane == 0) redi[wave] = l;
+  const double thr = fmax(fmax(red[0], red[1]), fmax(red[2], red[3])) * budget_sq;
+  for (int o = 1; o < 256; o <<= 1) {   // inclusive suffix scan over the chunks
+    const double v = tid + o < 256 ? suf[tid + o] : 0.0;
+    __syncthreads();
+    suf[tid] += v;
+    __syncthreads();
+  }
+  double acc = suf[tid] - own;   // the rows after this thread's chunk
+  int cand = n_pad;
+  if (acc <= thr) {
+    for (int q = m - 1; q >= 0; --q) {
+      const int r = r0 + q;
+      if (r >= n_pad) continue;
+      acc += nj[r];
+      if (!(acc <= thr)) break;   // NaN counts as above
+      cand = r;
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1) cand = min(cand, __shfl_xor(cand, o));
+  if (lane == 0) redi[wave] = cand;
   __syncthreads();
-  if (tid == 0) last[job] = max(max(redi[0], redi[1]), max(redi[2], redi[3]));
+  if (tid == 0) last[job] = min(min(redi[0], redi[1]), min(redi[2], redi[3]));
 }
 
 __global__ void max_int_kernel(int64_t n, const int* __restrict__ v, int* __restrict__ out) {
@@ -864,11 +887,11 @@ hipError_t run_deflate(int64_t njobs, int n_pad, double tau_null, const double* 
                        hipStream_t stream) {
   if (njobs == 0) { *nb_max = 2; return hipSuccess; }
   if (n_pad > 4096) return hipErrorInvalidValue;
-  const double floor_rel = fmax(0x1.0p-48, 0.1 * tau_null);
+  const double budget = approx_budget(tau_null);
   const dim3 rg((unsigned)ceil_div(n_pad, 4), (unsigned)njobs);
   hipLaunchKernelGGL(deflate_norms_kernel, rg, dim3(256), 0, stream, n_pad, Win, nrm);
   hipLaunchKernelGGL(deflate_plan_kernel, dim3((unsigned)njobs), dim3(256), 0, stream, n_pad, jacobi_block_rows(n_pad),
-                     floor_rel * floor_rel, (const double*)nrm, newpos, nb_job);
+                     budget * budget / (double)n_pad, (const double*)nrm, newpos, nb_job);
   hipLaunchKernelGGL(deflate_copy_kernel, rg, dim3(256), 0, stream, n_pad, Win, (const int32_t*)newpos, Wout);
   hipLaunchKernelGGL(max_int_kernel, dim3(1), dim3(1024), 0, stream, njobs, nb_job, scratch_dev);
   hipError_t e = hipMemcpyAsync(scratch_host, scratch_dev, sizeof(int), hipMemcpyDeviceToHost, stream);
@@ -883,10 +906,10 @@ hipError_t run_rank_rows(int64_t njobs, int n_pad, double tau_null, const double
                          int* scratch_dev, int* scratch_host, int* rows_max, hipStream_t stream) {
   if (njobs == 0) { *rows_max = 0; return hipSuccess; }
   if (n_pad > 4096) return hipErrorInvalidValue;
-  const double floor_rel = fmax(0x1.0p-48, 0.1 * tau_null);
+  const double budget = approx_budget(tau_null);
   const dim3 rg((unsigned)ceil_div(n_pad, 4), (unsigned)njobs);
   hipLaunchKernelGGL(deflate_norms_kernel, rg, dim3(256), 0, stream, n_pad, W, nrm);
-  hipLaunchKernelGGL(last_row_above_kernel, dim3((unsigned)njobs), dim3(256), 0, stream, n_pad, floor_rel * floor_rel,
+  hipLaunchKernelGGL(last_row_above_kernel, dim3((unsigned)njobs), dim3(256), 0, stream, n_pad, budget * budget,
                      (const double*)nrm, last);
   hipLaunchKernelGGL(max_int_kernel, dim3(1), dim3(1024), 0, stream, njobs, (const int*)last, scratch_dev);
   hipError_t e = hipMemcpyAsync(scratch_host, scratch_dev, sizeof(int), hipMemcpyDeviceToHost, stream);

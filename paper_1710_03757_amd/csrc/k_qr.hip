@@ -1383,12 +1383,12 @@ __global__ void r_rows_kernel(int n_pad, const double* __restrict__ S, double* _
 // the columns are not moved, the panel and trailing kernels address them
 // through the map, which ends as the logical -> stored column permutation).
 // Early stop of the re-ordered first QR.  Per job: the squared norms (below
-// the factored rows) of the columns from logical position j0 on, averaged,
-// against floor_sq times the squared leading diagonal entry of R (dropping
-// those m columns' rest then perturbs the singular values by at most
-// sqrt(m) floor |R00|, the bound of the row deflation); *any becomes 1 when
-// some job still exceeds it.
-__global__ __launch_bounds__(256) void trailing_above_kernel(int n_pad, int j0, double floor_sq,
+// the factored rows) of the columns from logical position j0 on, summed,
+// against budget_sq times the squared leading diagonal entry of R (at most
+// s_1^2): dropping that rest perturbs M P by at most its Frobenius norm, so
+// the singular values move by at most sqrt(budget_sq) s_1; *any becomes 1
+// when some job still exceeds it.
+__global__ __launch_bounds__(256) void trailing_above_kernel(int n_pad, int j0, double budget_sq,
                                                              const double* __restrict__ S,
                                                              const int32_t* __restrict__ colmap,
                                                              const double* __restrict__ colnorm, int* __restrict__ any) {
@@ -1404,7 +1404,7 @@ __global__ __launch_bounds__(256) void trailing_above_kernel(int n_pad, int j0, 
   if (tid == 0) {
     const double tot = (red[0] + red[1]) + (red[2] + red[3]);
     const double r00 = S[(size_t)job * n_pad * n_pad + (size_t)cm[0] * n_pad];
-    if (!(tot <= floor_sq * r00 * r00 * (double)(n_pad - j0))) atomicMax(any, 1);   // NaN counts as above
+    if (!(tot <= budget_sq * r00 * r00)) atomicMax(any, 1);   // NaN counts as above
   }
 }
 
@@ -1507,10 +1507,10 @@ static hipError_t qr_factor_t(int64_t njobs, int n_pad, double* S, double* Tws, 
                          (const double*)Tws, ts, o1, o2, T64, (const int32_t*)colmap);
       hipLaunchKernelGGL(qr_trailing64_kernel, xcd_tile_grid(ceil_div(n_pad - j - 64, 64), njobs), dim3(256), 0,
                          stream, njobs, n_pad, j, n_pad, S, (const double*)T64, (const int32_t*)colmap, colnorm);
-      if (stop) {   // the remaining columns below the floor in every job: stop here
+      if (stop) {   // the remaining columns within the budget in every job: stop here
         hipLaunchKernelGGL(set_int_kernel, dim3(1), dim3(1), 0, stream, stop->dev, 0);
         hipLaunchKernelGGL(trailing_above_kernel, dim3((unsigned)njobs), dim3(256), 0, stream, n_pad, j + 64,
-                           stop->floor_rel * stop->floor_rel, (const double*)S, (const int32_t*)colmap,
+                           stop->budget * stop->budget, (const double*)S, (const int32_t*)colmap,
                            (const double*)colnorm, stop->dev);
         hipError_t e = hipMemcpyAsync(stop->host, stop->dev, sizeof(int), hipMemcpyDeviceToHost, stream);
         if (e == hipSuccess) e = hipStreamSynchronize(stream);
@@ -1659,7 +1659,7 @@ hipError_t run_qr1(int64_t njobs, int n, int D, int n_pad, const double* T, cons
                 nullptr, 0, stop);
   if (e != hipSuccess) return e;
   const dim3 rg(n_pad / 32, n_pad / 32, (unsigned)njobs);
-  // rows from the stop on (the unfactored rest, below the floor) are written as zero
+  // rows from the stop on (the unfactored rest, within the budget) are written as zero
   hipLaunchKernelGGL(r_rows_kernel, rg, dim3(256), 0, stream, n_pad, S1, W1, (const int32_t*)colmap,
                      stop ? stop->rows : n_pad, n_pad);
   return hipGetLastError();
@@ -1672,7 +1672,7 @@ hipError_t run_qr23(int64_t njobs, int n_pad, int ncols, double* W1, double* Tws
   if (tq && !tq_flops) return hipErrorInvalidValue;
   double* T64 = Tscr + (size_t)njobs * 2048;
   const dim3 rg(n_pad / 32, n_pad / 32, (unsigned)njobs);
-  if (ncols < n_pad) {   // the rows of R1 from ncols on (all at the floor) become zero
+  if (ncols < n_pad) {   // the rows of R1 from ncols on (within the budget in total) become zero
     const int64_t nz = (int64_t)(n_pad - ncols) * n_pad;
     hipLaunchKernelGGL(zero_tail_kernel, dim3((unsigned)ceil_div(nz, 256), (unsigned)njobs), dim3(256), 0, stream, nz,
                        W1 + (int64_t)ncols * n_pad, (int64_t)n_pad * n_pad);

@@ -127,6 +127,15 @@ struct JacobiWork {
   int* lastchk = nullptr;
 };
 constexpr int kJacobiMaxBlocks = 128;   // n_pad / 32 for n_pad <= 4096
+// Three approximations of the decomposition drop parts of the matrix below
+// the candidate cut: the early stop of the first QR, the rank limit of the
+// later QRs and the row deflation before the Jacobi.  Each may drop at most
+// approx_budget(tau_null) times s_1 in Frobenius norm (relative to the
+// largest column or row norm of its matrix, which is at most s_1), so
+// together they move every singular value by at most max(2^-48, tau_null /
+// 10) times s_1 (Weyl's inequality; all three perturb M by orthogonal
+// transforms of the dropped parts), a tenth of the cut.
+inline double approx_budget(double tau_null) { return fmax(0x1.0p-48, 0.1 * tau_null) / 3.0; }
 // history (optional, host, max_sweeps x 2): per sweep, the block pairs that
 // rotated (summed over jobs) and the jobs still rotating after it.  ncol
 // (0: n_pad; a multiple of 64 for the 64-row pairs): the rows are zero from
@@ -136,15 +145,17 @@ hipError_t run_jacobi(int64_t njobs, int n_pad, double* W, const JacobiWork& wk,
                       hipStream_t stream, KernelTimer* timer = nullptr, int* sweeps_done = nullptr,
                       const int* nb_job = nullptr, int nb_max = 0, int* history = nullptr, int ncol = 0);
 // Rank of the rows of W (n_pad x n_pad per job, row-major): *rows_max = the
-// largest over the jobs of one past the last row whose norm exceeds
-// max(2^-48, tau_null / 10) times the largest row norm of its job (the
-// deflation floor).  nrm: n_pad doubles per job, last: one int per job, of
+// largest over the jobs of the smallest L such that the rows from L on hold
+// at most approx_budget(tau_null)^2 times the largest squared row norm of
+// their job in total (setting them to zero moves no singular value by more
+// than approx_budget times s_1).  nrm: n_pad doubles per job, last: one int per job, of
 // scratch; synchronises the stream.
 hipError_t run_rank_rows(int64_t njobs, int n_pad, double tau_null, const double* W, double* nrm, int* last,
                          int* scratch_dev, int* scratch_host, int* rows_max, hipStream_t stream);
 // Noise-floor deflation: Wout = rows of Win with the active rows (norm >
-// max(2^-48, tau_null / 10) times the largest) first, in order, the others
-// after them; nb_job = the even number of Jacobi row blocks covering the
+// approx_budget(tau_null) / sqrt(n_pad) times the largest, so that the rows
+// left out hold at most approx_budget^2 times the largest squared norm in
+// total) first, in order, the others after them; nb_job = the even number of Jacobi row blocks covering the
 // active rows; the maximum over jobs is returned in *nb_max (synchronises the
 // stream).  nrm / newpos: n_pad doubles / int32 per job of scratch;
 // n_pad <= 4096.
@@ -200,13 +211,13 @@ hipError_t run_qr5_precondition(int64_t njobs, int n, int D, int n_pad, const do
 // QR.  run_qr45: the fourth and fifth after it, the rows of R5 in W3, Q4 in
 // S1 / Tws4.
 // stop (or NULL): after every 64 columns of the first QR, if in every job
-// the columns not yet factored hold (in mean square below the factored rows)
-// at most floor_rel^2 times the squared leading diagonal entry of R, the QR
+// the columns not yet factored hold (summed squares below the factored rows)
+// at most budget^2 times the squared leading diagonal entry of R, the QR
 // stops there; rows = the factored rows (n_pad if it ran to the end);
 // the rows of R1 from there on are written as zero.  dev / host: one int of
 // device and pinned host scratch; each check synchronises the stream.
 struct QrStop {
-  double floor_rel = 0.0;
+  double budget = 0.0;   // approx_budget(tau_null)
   int* dev = nullptr;
   int* host = nullptr;
   int rows = 0;
@@ -305,6 +316,10 @@ hipError_t launch_estimate(int64_t n, const int8_t* sign, const double* ln_abs, 
                            double* out8, hipStream_t stream);
 
 // Chain bookkeeping (k_chain.hip).
+hipError_t launch_set_double(double* p, double v, hipStream_t stream);
+hipError_t launch_record_positions(int64_t nsamp, int npos, int64_t per_sample, int64_t base, int kmax, int kcap,
+                                   const int64_t* idx, const int32_t* cand, const int32_t* kept, const int32_t* sel,
+                                   int32_t* rec, hipStream_t stream);
 hipError_t launch_record(int64_t nsamp, int step, int n_steps, int kmax, int kcap, const int64_t* idx,
                          const int32_t* cand, const int32_t* kept, const int32_t* sel, int32_t* rec,
                          hipStream_t stream);

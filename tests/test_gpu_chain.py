@@ -121,21 +121,31 @@ def test_plaquette_exact():
 
 @pytest.mark.parametrize("k,n_steps", [(2, 4), (4, 4), (8, 6)])
 def test_independent_matches_oracle(k, n_steps):
+    """Independent mode, every position of every level: the kept sets must
+    be the oracle's (a differing one must be a validated rounding-distance
+    flip, after which the sample is no longer compared), the per-step sums
+    of ln c within the conditioning bound, and ln|Z~| per site to 1e-12
+    for samples compared to the end."""
+    import parity
     torch, m = need_gpu()
     log(f"independent k={k} steps={n_steps}")
     beta = BETA_C
     ts = m.init_tensor("site", [beta], [0.0])
     ns, seed = 6 if n_steps == 4 else 3, 11
-    r = m.run_samples(ts, ns, n_steps=n_steps, k=k, mode="independent", seed=seed, want_ln_c=True)
-    ln = r.ln_abs_Z.cpu().numpy()
+    r = m.run_samples(ts, ns, n_steps=n_steps, k=k, mode="independent", seed=seed, want_ln_c=True, record=True)
+    ln, lnc, rec = r.ln_abs_Z.cpu().numpy(), r.ln_c.cpu().numpy(), r.record.cpu().numpy()
     T0 = ising.site_tensor(beta)
     N = 2.0 ** n_steps
-    bad = 0
+    ends = 0
     for i in range(ns):
         o = trg.run_independent(T0, n_steps, k, seed, i)
-        if abs(ln[i] - o.ln_abs_Z) / N > 1e-12:
-            bad += 1
-    assert bad <= 1
+        g = parity.compare_independent(o, m.split_independent_record(rec[i], n_steps), lnc[i], k, seed, i, 1e-11,
+                                       100 * parity.EPS64)
+        log(f"sample {i}: {g.checked} steps compared ({g.reason}) {g.notes}")
+        if g.reason == "end":
+            ends += 1
+            assert abs(ln[i] - o.ln_abs_Z) / N <= 1e-12
+    assert ends >= ns - 1
 
 
 def test_topk_matches_oracle():
@@ -228,9 +238,9 @@ def test_two_parts_match_one(mode, k, n_steps, ns):
     log(f"several parts vs one: {mode} k={k} steps={n_steps} samples={ns}")
     ts = m.init_tensor("site", [BETA_C, 0.42], [0.0, 0.1])
     kw = dict(n_steps=n_steps, k=k, mode=mode, seed=7, sample_offset=11, groups=[i % 2 for i in range(ns)],
-              want_ln_c=True)
+              want_ln_c=True, record=True)
     if mode != "independent":
-        kw.update(record=True, want_tensor=True)
+        kw.update(want_tensor=True)
     a = m.run_samples(ts, ns, **kw)
     b = m.run_samples(ts, ns, one_stream=True, **kw)
     assert a.status == b.status == m.OK

@@ -1,0 +1,37 @@
+"""Table I of the paper (Section IV) on the GPU: the per-sample standard
+deviation of Z~ / Z for 128 Ising spins on the bonds of a periodic 8 x 8
+network (plaquette construction, Fig. 1), zero field, six TRG steps with
+every tensor sampled independently, at the paper's three (kept count,
+temperature) pairs.  The exact Z comes from the oracle's direct network
+contraction.  The paper states neither its sample count nor how it
+estimated the deviation, and these distributions are heavy-tailed at small
+k, so agreement is required within a factor of 2 (the first row is also
+pinned on the CPU oracle, tests/test_oracle_table1.py)."""
+import math
+
+import numpy as np
+import pytest
+
+from test_oracle_table1 import exact_lnZ_8x8_plaquette, table1_rows
+
+from gpu_util import log, need_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("row", [0, 1, 2])
+def test_table1_row(row):
+    torch, m = need_gpu()
+    k, T, paper_sd = table1_rows()[row]
+    lnZ = exact_lnZ_8x8_plaquette(T)
+    ts = m.init_tensor("plaquette", [1.0 / T], [0.0])
+    S = 400
+    r = m.run_samples(ts, S, n_steps=6, k=k, mode="independent", seed=row)
+    assert r.status == m.OK
+    v = r.sign.cpu().numpy() * np.exp(r.ln_abs_Z.cpu().numpy() - lnZ)
+    sd = v.std(ddof=1)
+    se = sd / math.sqrt(S)
+    log(f"Table I row {row}: k={k} T={T}: std of Z~/Z {sd:.4e} (paper {paper_sd:.4e}, ratio {sd / paper_sd:.3f}), "
+        f"mean {v.mean():.6f} +- {se:.6f}")
+    assert abs(v.mean() - 1.0) < 4.0 * se
+    assert 0.5 < sd / paper_sd < 2.0

@@ -105,3 +105,13 @@ def positive_tensor(d: int, seed: int) -> np.ndarray:
 
 def sample_ids(offset: int, n: int) -> np.ndarray:
     return np.arange(offset, offset + n, dtype=np.int64)
+
+
+def projection_pairs(D: int, J: int = 64, seed: int = 20171010):
+    """J pairs of seeded standard-normal D x D matrices (P_j, Q_j) that the
+    parity tests use to fingerprint a D^4 tensor: f_j = sum P_j[a,b]
+    T[a,b,c,e] Q_j[c,e].  Inputs only: the same arrays serve both sides."""
+    rng = np.random.default_rng([seed, D, J])
+    P = rng.standard_normal((J, D * D))
+    Q = rng.standard_normal((J, D * D))
+    return P, Q
