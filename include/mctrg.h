@@ -84,6 +84,21 @@ enum mctrg_mode { MCTRG_SHARED = 0, MCTRG_INDEPENDENT = 1, MCTRG_TOPK = 2 };
  * with one power-of-two scale per operand tensor and sample). */
 enum mctrg_dtype { MCTRG_F64 = 0, MCTRG_F32 = 1, MCTRG_BF16 = 2, MCTRG_FP8_E4M3 = 3 };
 
+/* Decomposition of each unfolding M:
+ *   MCTRG_DEC_SVD  the exact FP64 SVD (Section II, Eq. exactSVD; default);
+ *   MCTRG_DEC_QR3, MCTRG_DEC_QR5  a cheaper decomposition that keeps the
+ *                  estimator unbiased: an orthonormal basis V from three
+ *                  (five) steps of QR iteration (M P = Q1 R1 with column
+ *                  re-ordering, R_i^T = Q_{i+1} R_{i+1}, V = P Q2 (Q4)) and
+ *                  the exact expansion M = sum_j (M v_j) v_j^T, whose terms
+ *                  are drawn and reweighted as the SVD terms are (Section II
+ *                  needs only inclusion rates r > 0 for Eqs. Tsum, Ssum), with
+ *                  weights |M v_j| = the column norms of the last R.  No
+ *                  Jacobi; the variance of the samples grows where V is
+ *                  far from the singular vectors.  k <= 32 (unfoldings of at
+ *                  most 1024 rows). */
+enum mctrg_decomposition { MCTRG_DEC_SVD = 0, MCTRG_DEC_QR3 = 1, MCTRG_DEC_QR5 = 2 };
+
 /* flags */
 #define MCTRG_RECORD 1u   /* write per-step selection records to record_buf   */
                           /* (bit 2u is not used)                              */
@@ -140,6 +155,19 @@ typedef struct {
                            /*   0 = 70% of the free device memory; waves of samples   */
                            /*   are sized to fit; ENOMEM (outputs untouched) when one */
                            /*   sample does not fit                                   */
+  int32_t n_det;           /* 0..n_steps: the first n_det steps are deterministic     */
+                           /*   (top-k: the first min(k, c) values, r = 1), the rest  */
+                           /*   stochastic (Section V, Discussion: deterministic       */
+                           /*   coarse-graining steps before switching to Monte Carlo */
+                           /*   for translation-invariant systems).  Independent mode:*/
+                           /*   the prefix coarse-grains one tensor per sample, whose */
+                           /*   result starts every position of level n_det, from     */
+                           /*   where each tensor is sampled on its own; out_ln_c of a*/
+                           /*   prefix step is the sum over the level's equal tensors.*/
+                           /*   Unbiased for Z when every prefix step keeps all its   */
+                           /*   candidates (c <= k); otherwise for the network left  */
+                           /*   by the deterministic truncation.  Default 0.          */
+  int32_t decomposition;   /* enum mctrg_decomposition (default MCTRG_DEC_SVD)         */
 } mctrg_run_config;
 
 /* Fill *cfg with the defaults (seed 0, offset 0, tau_null 1e-11, F64, shared). */

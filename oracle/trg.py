@@ -76,6 +76,47 @@ def decompose(M: np.ndarray, col_shape):
     return U, s, Vt
 
 
+def qr_basis(M: np.ndarray, n_qr: int):
+    """An orthonormal basis V from n_qr steps of QR iteration: M P = Q1 R1
+    with column pivoting (LAPACK geqp3 via scipy), then R_i^T = Q_{i+1}
+    R_{i+1}; V = P Q2 Q4 ... (the even-numbered Q factors).  Each pair of
+    steps is one unshifted QR iteration on M^T M, so V tends to the right
+    singular vectors; for any n_qr it is orthonormal."""
+    import scipy.linalg as sla
+    n = M.shape[1]
+    _, R, piv = sla.qr(M, pivoting=True, mode="economic")
+    V = np.eye(n)[:, piv]                     # P
+    for step in range(2, n_qr + 1):
+        Q, R = np.linalg.qr(R.T)
+        if step % 2 == 0:
+            V = V @ Q
+    return V
+
+
+def decompose_qr(M: np.ndarray, col_shape, n_qr: int):
+    """The cheaper decomposition: M = sum_j (M v_j) v_j^T for the
+    orthonormal basis V of ``qr_basis``, written like an SVD - s_j = |M v_j|
+    (descending), U[:, j] = M v_j / s_j (unit, not orthogonal), Vt = V^T -
+    so that the same truncation keeps a random subset of the terms and
+    divides each by its inclusion rate.  Section II's argument (the
+    average of the kept terms over p(e) is the full sum whenever every
+    inclusion rate is positive) needs only the exact expansion, not the
+    orthogonality of the U columns: the estimator stays unbiased and only
+    its variance depends on the basis."""
+    V = qr_basis(M, n_qr)
+    A = M @ V
+    s = np.linalg.norm(A, axis=0)
+    order = np.argsort(-s, kind="stable")
+    s, A, V = s[order], A[:, order], V[:, order]
+    U = np.divide(A, s, out=np.zeros_like(A), where=s > 0)
+    Vt = V.T.copy()
+    g = Vt @ gauge_weights(col_shape)
+    flip = g < 0
+    U[:, flip] *= -1.0
+    Vt[flip, :] *= -1.0
+    return U, s, Vt
+
+
 def factors(U, Vt, tr: esp.Truncation, row_shape, col_shape):
     w = tr.weights
     kk = len(tr.sel)
@@ -124,12 +165,17 @@ def _split_mode(mode: str) -> str:
 
 
 def decompose_and_truncate(T, split, k, mode, seed, sample_id, position, step, tau_null,
-                           chooser=None):
-    """Unfold, SVD, truncate and factor one tensor.  ``chooser``, if given,
-    is called as chooser(position, step, split, sigma, c) and returns the
-    kept subset instead of a random draw (None: draw as usual)."""
+                           chooser=None, basis="svd"):
+    """Unfold, decompose, truncate and factor one tensor.  ``chooser``, if
+    given, is called as chooser(position, step, split, sigma, c) and returns
+    the kept subset instead of a random draw (None: draw as usual).
+    ``basis``: "svd" (Section II's exact SVD) or "qr3" / "qr5" (the
+    QR-iteration basis of ``decompose_qr``)."""
     M, rs, cs = unfold(T, split)
-    U, s, Vt = decompose(M, cs)
+    if basis == "svd":
+        U, s, Vt = decompose(M, cs)
+    else:
+        U, s, Vt = decompose_qr(M, cs, {"qr3": 3, "qr5": 5}[basis])
     forced = None
     if chooser is not None:
         forced = chooser(position, step, split, s, esp.n_candidates(s, tau_null))
@@ -142,16 +188,19 @@ def decompose_and_truncate(T, split, k, mode, seed, sample_id, position, step, t
 
 def run_shared(T0: np.ndarray, n_steps: int, k: int, seed: int, sample_id: int,
                mode: str = "shared", tau_null: float = 1e-11, keep_tensors: bool = False,
-               chooser=None) -> ChainResult:
+               chooser=None, n_det: int = 0, basis: str = "svd") -> ChainResult:
     """One sample of the translation-invariant chain on 2**n_steps sites.
+    The first ``n_det`` steps keep the largest values deterministically
+    (top-k), the later ones use ``mode``.
 
     ln|Z~| = sum_s (N / 2^(s+1)) ln c_s + ln|Tr T_hat_final|, N = 2**n_steps."""
     T = np.array(T0, dtype=np.float64)
     ln_c: List[float] = []
     recs: List[StepRecord] = []
     for step in range(n_steps):
-        FA, GA, ra = decompose_and_truncate(T, 0, k, mode, seed, sample_id, 0, step, tau_null, chooser)
-        FB, GB, rb = decompose_and_truncate(T, 1, k, mode, seed, sample_id, 0, step, tau_null, chooser)
+        md = "topk" if step < n_det else mode
+        FA, GA, ra = decompose_and_truncate(T, 0, k, md, seed, sample_id, 0, step, tau_null, chooser, basis)
+        FB, GB, rb = decompose_and_truncate(T, 1, k, md, seed, sample_id, 0, step, tau_null, chooser, basis)
         Tn = contract(GA, GB, FA, FB)
         c = float(np.max(np.abs(Tn))) if Tn.size else 0.0
         if not (c > 0.0 and math.isfinite(c)):
@@ -167,7 +216,8 @@ def run_shared(T0: np.ndarray, n_steps: int, k: int, seed: int, sample_id: int,
     return ChainResult(1 if tr > 0 else -1, ln_abs + math.log(abs(tr)), ln_c, recs)
 
 
-def step_independent(tensors, lev, k, mode, seed, sample_id, step, tau_null=1e-11, chooser=None, records=None):
+def step_independent(tensors, lev, k, mode, seed, sample_id, step, tau_null=1e-11, chooser=None, records=None,
+                     basis="svd"):
     """One independent-mode TRG step over a whole lattice level.
 
     Returns (new_tensors, next_level, sum of ln c over the new positions),
@@ -179,7 +229,7 @@ def step_independent(tensors, lev, k, mode, seed, sample_id, step, tau_null=1e-1
     for p in range(lev.n):
         split = 0 if lev.is_a[p] else 1
         F[p], G[p], recs[p] = decompose_and_truncate(tensors[p], split, k, mode, seed, sample_id, p, step,
-                                                     tau_null, chooser)
+                                                     tau_null, chooser, basis)
     new = []
     step_sum = 0.0
     for P, (p0, q0, p1, q1) in enumerate(plaq):
@@ -195,10 +245,18 @@ def step_independent(tensors, lev, k, mode, seed, sample_id, step, tau_null=1e-1
 
 
 def run_independent(T0: np.ndarray, n_steps: int, k: int, seed: int, sample_id: int,
-                    mode: str = "independent", tau_null: float = 1e-11, chooser=None) -> ChainResult:
+                    mode: str = "independent", tau_null: float = 1e-11, chooser=None,
+                    n_det: int = 0, basis: str = "svd") -> ChainResult:
     """One sample of the paper's estimator on an L x L torus, L = 2**(n_steps/2):
     every tensor of every level gets its own independent truncation.
     ``T0`` is one tensor for every site or an array of per-site tensors.
+
+    ``n_det`` > 0 (one tensor for every site): the Discussion's deterministic
+    coarse-graining steps before Monte Carlo.  The first n_det steps
+    coarse-grain the one tensor with top-k truncation (every tensor of those
+    levels is the same); its result starts every position of level n_det,
+    from where each tensor is truncated independently.  A prefix step adds
+    (number of new tensors) * ln c; its record holds the A and B split.
 
     ln|Z~| = sum over levels and positions of ln c + ln|Tr T_hat_final|."""
     if n_steps % 2:
@@ -207,16 +265,28 @@ def run_independent(T0: np.ndarray, n_steps: int, k: int, seed: int, sample_id: 
     lev = lattice.square_torus(L)
     T0 = np.asarray(T0, dtype=np.float64)
     if T0.ndim == 5:      # one tensor per site, site id x + L*y
-        if T0.shape[0] != lev.n:
-            raise ValueError("need one tensor per site")
+        if T0.shape[0] != lev.n or n_det:
+            raise ValueError("need one tensor per site (and no deterministic prefix)")
         tensors = [T0[i].copy() for i in range(lev.n)]
     else:
         tensors = [T0.copy() for _ in range(lev.n)]
     total = 0.0
     ln_c_steps: List[float] = []
     positions: List[List[SplitRecord]] = []
-    for step in range(n_steps):
-        out = step_independent(tensors, lev, k, mode, seed, sample_id, step, tau_null, chooser, positions)
+    if n_det:
+        pre = run_shared(T0, n_det, k, seed, sample_id, mode="topk", tau_null=tau_null, keep_tensors=True,
+                         basis=basis)
+        if pre.sign == 0 and len(pre.ln_c) < n_det:
+            return ChainResult(0, math.nan, pre.ln_c, positions=positions)
+        for step in range(n_det):
+            lev = lattice.coarsen(lev)[1]
+            n_new = lev.n
+            total += n_new * pre.ln_c[step]
+            ln_c_steps.append(n_new * pre.ln_c[step])
+            positions.append(list(pre.records[step].splits))
+        tensors = [pre.records[-1].T_hat.copy() for _ in range(lev.n)]
+    for step in range(n_det, n_steps):
+        out = step_independent(tensors, lev, k, mode, seed, sample_id, step, tau_null, chooser, positions, basis)
         if out is None:
             return ChainResult(0, math.nan, ln_c_steps, positions=positions)
         tensors, lev, step_sum = out

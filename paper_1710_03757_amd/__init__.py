@@ -38,6 +38,8 @@ F64, F32, BF16, FP8_E4M3 = 0, 1, 2, 3
 RECORD, PROFILE, ONE_STREAM = 1, 4, 8
 
 MODES = {"shared": SHARED, "independent": INDEPENDENT, "topk": TOPK}
+DEC_SVD, DEC_QR3, DEC_QR5 = 0, 1, 2
+DECOMPOSITIONS = {"svd": DEC_SVD, "qr3": DEC_QR3, "qr5": DEC_QR5}
 DTYPES = {"f64": F64, "f32": F32, "bf16": BF16, "fp8": FP8_E4M3}
 MODELS = {"site": ISING_SITE, "vertex": ISING_SITE, "plaquette": ISING_PLAQUETTE, "user": USER}
 
@@ -53,7 +55,8 @@ class RunConfig(ctypes.Structure):
                 ("k", ctypes.c_int32), ("mode", ctypes.c_int32), ("contract_dtype", ctypes.c_int32),
                 ("tau_null", ctypes.c_double), ("flags", ctypes.c_uint32),
                 ("record_buf", ctypes.c_void_p), ("out_tensor", ctypes.c_void_p),
-                ("max_workspace_bytes", ctypes.c_size_t)]
+                ("max_workspace_bytes", ctypes.c_size_t), ("n_det", ctypes.c_int32),
+                ("decomposition", ctypes.c_int32)]
 
 
 class Estimate(ctypes.Structure):
@@ -240,7 +243,8 @@ def run_samples(ts: TensorSet, n_samples: int, *, n_steps: int, k: int, mode="sh
                 seed: int = 0, sample_offset: int = 0, tau_null: float = 1e-11, groups=None,
                 ks=None, want_ln_c: bool = False, record: bool = False, want_tensor: bool = False,
                 out_sign=None, out_ln_abs_Z=None, one_stream: bool = False,
-                max_workspace_bytes: int = 0, out_ln_c=None, allow=()) -> SampleResult:
+                max_workspace_bytes: int = 0, out_ln_c=None, allow=(), n_det: int = 0,
+                decomposition="svd") -> SampleResult:
     """mctrg_run_samples.  ``groups`` / ``ks``: host sequences (one per sample).
     ``one_stream``: run every wave as one part (MCTRG_ONE_STREAM).  ``allow``:
     further status codes returned instead of raised (as ``status``)."""
@@ -276,6 +280,8 @@ def run_samples(ts: TensorSet, n_samples: int, *, n_steps: int, k: int, mode="sh
         ten = torch.empty((n_samples, Dc, Dc, Dc, Dc), dtype=torch.float64, device=dev)
         cfg.out_tensor = ten.data_ptr()
     cfg.max_workspace_bytes = int(max_workspace_bytes)
+    cfg.n_det = int(n_det)
+    cfg.decomposition = DECOMPOSITIONS[decomposition] if isinstance(decomposition, str) else int(decomposition)
     g = None if groups is None else np.ascontiguousarray(groups, dtype=np.int32)
     kk = None if ks is None else np.ascontiguousarray(ks, dtype=np.int32)
     for arr, nm in ((g, "groups"), (kk, "ks")):
@@ -348,9 +354,9 @@ def sample_batched(sigma, rng, split, k: int, mode="shared", seed: int = 0, tau_
     lr = torch.empty((nj, k), dtype=torch.float64, device=d)
     w = torch.empty((nj, k), dtype=torch.float64, device=d)
     m = MODES[mode] if isinstance(mode, str) else int(mode)
-    _check(_lib.mctrg_sample_batched(nj, n, k, m, seed, tau_null, _ptr(sigma), _ptr(rng), _ptr(split),
-                                     _ptr(kept), _ptr(cand), _ptr(sel), _ptr(lr), _ptr(w), _stream(torch)),
-           "mctrg_sample_batched")
+    fn = _lib.mctrg_sample_batched
+    _check(fn(nj, n, k, m, seed, tau_null, _ptr(sigma), _ptr(rng), _ptr(split), _ptr(kept), _ptr(cand), _ptr(sel),
+              _ptr(lr), _ptr(w), _stream(torch)), fn.__name__)
     return {"kept": kept, "cand": cand, "sel": sel, "log_r": lr, "weight": w}
 
 
@@ -373,7 +379,7 @@ class Chain:
 
     def __init__(self, ts: TensorSet, n_samples: int, *, n_steps: int, k: int, mode="shared", dtype="f64",
                  seed: int = 0, sample_offset: int = 0, tau_null: float = 1e-11, groups=None, profile=False,
-                 one_stream=False, record=False):
+                 one_stream=False, record=False, n_det: int = 0, decomposition="svd"):
         import numpy as np
         torch = _torch()
         cfg = default_config()
@@ -381,6 +387,8 @@ class Chain:
         cfg.mode = MODES[mode] if isinstance(mode, str) else int(mode)
         cfg.contract_dtype = DTYPES[dtype] if isinstance(dtype, str) else int(dtype)
         cfg.tau_null = tau_null
+        cfg.n_det = int(n_det)
+        cfg.decomposition = DECOMPOSITIONS[decomposition] if isinstance(decomposition, str) else int(decomposition)
         if profile:
             cfg.flags |= PROFILE
         if one_stream:

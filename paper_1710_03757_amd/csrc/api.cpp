@@ -147,6 +147,8 @@ struct StepShape {
 struct Chain {
   hipStream_t st = nullptr;
   int mode = 0, dtype = 0, k = 0, n_steps = 0, kmax_rec = 0;
+  int n_det = 0;   // leading deterministic (top-k) steps; independent mode: on one shared tensor
+  int dec = MCTRG_DEC_SVD;   // decomposition: SVD, or the QR-iteration basis of 3 or 5 QRs
   double tau = 1e-11;
   uint64_t seed = 0;
   int64_t nsamp = 0;
@@ -201,7 +203,7 @@ struct Chain {
     sh.kc = Dsched[s + 1];
     sh.n = sh.D * sh.D;
     sh.n_pad = std::max(32, round_up32(sh.n));
-    if (mode == MCTRG_INDEPENDENT) {
+    if (mode == MCTRG_INDEPENDENT && s >= n_det) {
       sh.P = levels[s].n;
       sh.jps = sh.P;
       sh.ops = sh.P / 2;
@@ -372,7 +374,7 @@ int chain_start(Chain& c, const mctrg_tensor_set* ts, const std::vector<int32_t>
   CKH(hipMemcpyAsync(dgroups, g.data(), g.size() * sizeof(int32_t), hipMemcpyHostToDevice, c.st));
   CKH(hipMemcpyAsync(c.idx, out_index.data(), out_index.size() * sizeof(int64_t), hipMemcpyHostToDevice, c.st));
   // every position of a sample starts from the sample's group tensor
-  const int P0 = (c.mode == MCTRG_INDEPENDENT) ? c.levels[0].n : 1;
+  const int P0 = (c.mode == MCTRG_INDEPENDENT && c.n_det == 0) ? c.levels[0].n : 1;
   if (P0 == 1) {
     CKH(launch_gather_tensors(c.nsamp, ts->d0, ts->T0, dgroups, c.Ta, c.st));
   } else {
@@ -396,7 +398,8 @@ int chain_step(Chain& c) {
   const StepShape sh = c.shape(s);
   const int64_t nj = c.nsamp * sh.jps, no = c.nsamp * sh.ops;
   // job descriptors
-  if (c.mode == MCTRG_INDEPENDENT) {
+  const bool indep = c.mode == MCTRG_INDEPENDENT && s >= c.n_det;
+  if (indep) {
     const Level& lev = c.levels[s];
     const std::vector<int>& pl = c.plaqs[s];
     for (int64_t i = 0; i < c.nsamp; ++i) {
@@ -446,7 +449,27 @@ int chain_step(Chain& c) {
   int nb_max = 0;
   int jcols = 0;         // the Jacobi rows are zero from this column on (0: none)
   KernelTimer* tq = c.tq.enabled ? &c.tq : nullptr;
-  if (qr5) {
+  const bool qr_basis = qr5 && c.dec != MCTRG_DEC_SVD;
+  if (qr_basis) {
+    // the cheaper decomposition: the basis V = P Q2 (Q4) of three (five) QR
+    // steps, the terms (M v_j) v_j^T weighted by |M v_j| = the column norms
+    // of R3 (R5); no Jacobi
+    QrStop stop;
+    stop.budget = approx_budget(c.tau);
+    stop.dev = c.jw.counter;
+    stop.host = c.jw.counter_host;
+    CKH(run_qr1(nj, sh.n, sh.D, sh.n_pad, c.Ta, c.src, c.split, c.perm, c.dpos, c.S, c.W, c.Tscr, c.colmap, c.colnorm,
+                c.st, &stop));
+    int rows1 = 0;
+    CKH(run_rank_rows(nj, sh.n_pad, c.tau, c.W, c.dnrm, c.nb_job, c.jw.counter, c.jw.counter_host, &rows1, c.st));
+    const int ncols = std::min(sh.n_pad, std::max(128, 128 * ceil_div(rows1, 128)));
+    CKH(run_qr23(nj, sh.n_pad, ncols, c.W, c.Tws2, c.W2, c.W3, c.Tscr, c.st, tq, &c.tq_flops));
+    if (c.dec == MCTRG_DEC_QR5) CKH(run_qr45(nj, sh.n_pad, ncols, c.S, c.W2, c.Tws, c.W3, c.Tscr, c.st, tq, &c.tq_flops));
+    three = c.dec == MCTRG_DEC_QR3;
+    Wj = c.W2;
+    CKH(launch_qr_basis(nj, sh.n, sh.n_pad, ncols, c.W3, c.dnrm, Wj, c.sigma, c.order, c.st));
+    c.last_sweeps = 0;
+  } else if (qr5) {
     // the first QR stops once the columns it has not factored hold at most the
     // approximation budget in every job (their rows of R1 are then set to zero)
     QrStop stop;
@@ -487,13 +510,14 @@ int chain_step(Chain& c) {
     CKH(launch_unfold(nj, sh.D, sh.n_pad, c.Ta, c.src, c.split, c.W2, c.st));
     CKH(launch_iota(nj, sh.n_pad, c.perm, c.st));
   }
-  if (!three)
+  if (!three && !qr_basis)
     CKH(run_deflate(nj, sh.n_pad, c.tau, rows, Wj, c.nb_job, c.dnrm, c.dpos, c.jw.counter, c.jw.counter_host, &nb_max,
                     c.st));
-  CKH(run_jacobi(nj, sh.n_pad, Wj, c.jw, kMaxSweeps, c.st, c.tj.enabled ? &c.tj : nullptr, &c.last_sweeps, c.nb_job,
-                 nb_max, c.sweep_hist, jcols));
+  if (!qr_basis)
+    CKH(run_jacobi(nj, sh.n_pad, Wj, c.jw, kMaxSweeps, c.st, c.tj.enabled ? &c.tj : nullptr, &c.last_sweeps, c.nb_job,
+                   nb_max, c.sweep_hist, jcols));
   if (s < 64) c.step_sweeps[s] = c.last_sweeps;
-  {
+  if (!qr_basis) {
     int64_t rp = 0;
     for (int w = 0; w < c.last_sweeps && w < kMaxSweeps; ++w) rp += c.sweep_hist[2 * w];
     // per rotated pair of two row blocks (2 brows rows): the symmetric Gram
@@ -502,10 +526,13 @@ int chain_step(Chain& c) {
     c.rotated_pairs += rp;
     c.jacobi_flops += (double)rp * 3.0 * rows * rows * len;
   }
-  CKH(launch_jacobi_fail(nj, sh.jps, c.jw.sweeps, c.failed, c.st));
-  CKH(launch_jacobi_finalize(nj, sh.n, sh.n_pad, Wj, c.sigma, c.order, c.st, c.dnrm));
+  if (!qr_basis) {
+    CKH(launch_jacobi_fail(nj, sh.jps, c.jw.sweeps, c.failed, c.st));
+    CKH(launch_jacobi_finalize(nj, sh.n, sh.n_pad, Wj, c.sigma, c.order, c.st, c.dnrm));
+  }
   SampleArgs sa{};
-  sa.njobs = nj; sa.n = sh.n; sa.k = sh.kc; sa.mode = c.mode; sa.seed = c.seed; sa.tau = c.tau;
+  sa.njobs = nj; sa.n = sh.n; sa.k = sh.kc; sa.mode = s < c.n_det ? MCTRG_TOPK : c.mode; sa.seed = c.seed;
+  sa.tau = c.tau;
   sa.sigma = c.sigma; sa.rng = c.rng; sa.split = c.split; sa.kept = c.kept; sa.cand = c.cand;
   sa.sel = c.sel; sa.log_r = c.logr; sa.weight = c.weight; sa.scratch = c.sscr;
   CKH(launch_sample(sa, c.st));
@@ -513,8 +540,10 @@ int chain_step(Chain& c) {
     if (c.mode == MCTRG_INDEPENDENT) {
       int64_t base = 0;
       for (int t = 0; t < s; ++t) base += (int64_t)c.levels[t].n * (2 + c.kmax_rec);
-      CKH(launch_record_positions(c.nsamp, sh.P, record_per_sample(c), base, c.kmax_rec, sh.kc, c.idx, c.cand, c.kept,
-                                  c.sel, c.record, c.st));
+      // the deterministic prefix decomposes one tensor per sample: its A and
+      // B split fill positions 0 and 1 of the level
+      CKH(launch_record_positions(c.nsamp, indep ? sh.P : 2, record_per_sample(c), base, c.kmax_rec, sh.kc, c.idx,
+                                  c.cand, c.kept, c.sel, c.record, c.st));
     } else {
       CKH(launch_record(c.nsamp, s, c.n_steps, c.kmax_rec, sh.kc, c.idx, c.cand, c.kept, c.sel, c.record, c.st));
     }
@@ -548,9 +577,23 @@ int chain_step(Chain& c) {
   if (c.fail_sid >= 0 && s == c.n_steps - 1)
     for (int64_t i = 0; i < c.nsamp; ++i)
       if (c.sids[i] == c.fail_sid) CKH(launch_set_double(c.lnc + i * sh.ops, std::nan(""), c.st));
-  CKH(launch_lnc_accum(c.nsamp, sh.ops, s, c.n_steps, c.lnc, c.lnc_steps, c.failed, c.st));
+  // independent mode sums ln c over the level's tensors: a step of the
+  // deterministic prefix stands for all 2^(n_steps - s - 1) equal new tensors
+  const double mult = (c.mode == MCTRG_INDEPENDENT && s < c.n_det) ? std::ldexp(1.0, c.n_steps - s - 1) : 1.0;
+  CKH(launch_lnc_accum(c.nsamp, sh.ops, s, c.n_steps, mult, c.lnc, c.lnc_steps, c.failed, c.st));
   std::swap(c.Ta, c.Tb);
   c.step++;
+  if (c.mode == MCTRG_INDEPENDENT && c.step == c.n_det && c.n_det < c.n_steps) {
+    // switch to the independent estimator: every position of the coarse
+    // lattice starts from the sample's deterministic tensor
+    const int P = c.levels[c.n_det].n;
+    for (int64_t j = 0; j < c.nsamp * P; ++j) c.h_src[j] = (int32_t)(j / P);
+    CKH(hipMemcpyAsync(c.src, c.h_src, c.nsamp * P * sizeof(int32_t), hipMemcpyHostToDevice, c.st));
+    CKH(launch_gather_tensors(c.nsamp * P, c.Dsched[c.n_det], c.Ta, c.src, c.Tb, c.st));
+    // the next step refills the pinned staging buffer: the copy above must be done first
+    CKH(hipStreamSynchronize(c.st));
+    std::swap(c.Ta, c.Tb);
+  }
   if (c.tg.enabled) {
     CKH(hipStreamSynchronize(c.st));
     CKH(c.tg.collect());
@@ -730,6 +773,9 @@ int validate_config(const mctrg_run_config* cfg) {
   if (cfg->mode == MCTRG_INDEPENDENT) {
     if ((cfg->n_steps % 2) != 0 || cfg->n_steps > 12) return MCTRG_EINVAL;
   }
+  if (cfg->n_det < 0 || cfg->n_det > cfg->n_steps) return MCTRG_EINVAL;
+  if (cfg->decomposition < MCTRG_DEC_SVD || cfg->decomposition > MCTRG_DEC_QR5) return MCTRG_EINVAL;
+  if (cfg->decomposition != MCTRG_DEC_SVD && cfg->k > 32) return MCTRG_EUNSUPPORTED;
   return MCTRG_OK;
 }
 
@@ -849,8 +895,10 @@ int mctrg_run_samples(mctrg_tensor_set* ts, const mctrg_run_config* cfg, int64_t
     for (int64_t i = 0; i < n_samples; ++i)
       if (group_of_sample[i] < 0 || group_of_sample[i] >= ts->ngroups) return MCTRG_EINVAL;
   if (k_of_sample)
-    for (int64_t i = 0; i < n_samples; ++i)
+    for (int64_t i = 0; i < n_samples; ++i) {
       if (k_of_sample[i] < 1 || k_of_sample[i] > 64) return MCTRG_EINVAL;
+      if (cfg->decomposition != MCTRG_DEC_SVD && k_of_sample[i] > 32) return MCTRG_EUNSUPPORTED;
+    }
   const bool record = (cfg->flags & MCTRG_RECORD) != 0;
   if (record) {
     if (!cfg->record_buf) return MCTRG_EINVAL;
@@ -927,6 +975,8 @@ int mctrg_run_samples(mctrg_tensor_set* ts, const mctrg_run_config* cfg, int64_t
         c.mode = cfg->mode; c.dtype = cfg->contract_dtype; c.k = kb; c.n_steps = cfg->n_steps;
         c.tau = cfg->tau_null; c.seed = cfg->seed; c.flags = cfg->flags; c.record = cfg->record_buf;
         c.kmax_rec = cfg->k;
+        c.n_det = cfg->n_det;
+        c.dec = cfg->decomposition;
         c.Dsched = probe.Dsched;
         c.levels = probe.levels;
         c.plaqs = probe.plaqs;
@@ -988,6 +1038,8 @@ int mctrg_chain_create(mctrg_tensor_set* ts, const mctrg_run_config* cfg, int64_
     c.tau = cfg->tau_null; c.seed = cfg->seed; c.flags = cfg->flags & (MCTRG_PROFILE | MCTRG_RECORD);
     c.record = (cfg->flags & MCTRG_RECORD) ? cfg->record_buf : nullptr;
     c.kmax_rec = cfg->k;
+    c.n_det = cfg->n_det;
+    c.dec = cfg->decomposition;
     c.Dsched = probe.Dsched;
     c.levels = probe.levels;
     c.plaqs = probe.plaqs;

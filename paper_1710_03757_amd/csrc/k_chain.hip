@@ -69,24 +69,25 @@ hipError_t launch_record_positions(int64_t nsamp, int npos, int64_t per_sample, 
   return hipGetLastError();
 }
 
-// lnc_steps[s * n_steps + step] = sum over the sample's outputs (fixed order);
-// failed[s] |= any non-finite.
-__global__ void lnc_accum_kernel(int64_t nsamp, int out_per_sample, int step, int n_steps,
+// lnc_steps[s * n_steps + step] = mult * sum over the sample's outputs (fixed
+// order); failed[s] |= any non-finite.
+__global__ void lnc_accum_kernel(int64_t nsamp, int out_per_sample, int step, int n_steps, double mult,
                                  const double* __restrict__ lnc, double* __restrict__ lnc_steps,
                                  int* __restrict__ failed) {
   const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (s >= nsamp) return;
   double acc = 0.0;
   for (int P = 0; P < out_per_sample; ++P) acc += lnc[s * out_per_sample + P];
+  acc *= mult;
   lnc_steps[s * n_steps + step] = acc;
   if (!isfinite(acc)) failed[s] = 1;
 }
 
-hipError_t launch_lnc_accum(int64_t nsamp, int out_per_sample, int step, int n_steps, const double* lnc,
+hipError_t launch_lnc_accum(int64_t nsamp, int out_per_sample, int step, int n_steps, double mult, const double* lnc,
                             double* lnc_steps, int* failed, hipStream_t stream) {
   if (nsamp == 0) return hipSuccess;
   hipLaunchKernelGGL(lnc_accum_kernel, dim3(ceil_div(nsamp, 128)), dim3(128), 0, stream, nsamp, out_per_sample,
-                     step, n_steps, lnc, lnc_steps, failed);
+                     step, n_steps, mult, lnc, lnc_steps, failed);
   return hipGetLastError();
 }
 

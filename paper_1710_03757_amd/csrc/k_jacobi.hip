@@ -978,6 +978,60 @@ __global__ __launch_bounds__(256) void jacobi_finalize_kernel(int n, int n_pad, 
   }
 }
 
+// ---------------------------------------------------------------------------
+// QR-iteration basis (the decomposition that skips the Jacobi): with M P Q =
+// Q' R (Q = Q2 or Q2 Q4, R the last triangular factor, rows stored row-major
+// in R), the columns of M P Q have the norms of the columns of R.
+// basis_colnorm_kernel: their squares, one thread per column, summed over
+// the first nrows rows (the rest are zero).  basis_rows_kernel: W = diag of
+// those norms, so that the vector recovery reads the unit vector e_j as the
+// j-th "rotated row" over its norm.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void basis_colnorm_kernel(int n_pad, int nrows, const double* __restrict__ R,
+                                                            double* __restrict__ nrm) {
+  const int64_t job = blockIdx.y;
+  const int j = blockIdx.x * 256 + threadIdx.x;
+  if (j >= n_pad) return;
+  const double* Rj = R + (size_t)job * n_pad * n_pad + j;
+  double s = 0.0;
+  for (int r = 0; r < nrows; ++r) {
+    const double x = Rj[(size_t)r * n_pad];
+    s += x * x;
+  }
+  nrm[(size_t)job * n_pad + j] = s;
+}
+
+__global__ __launch_bounds__(256) void basis_rows_kernel(int n_pad, const double* __restrict__ nrm,
+                                                         double* __restrict__ W) {
+  const int64_t job = blockIdx.y;
+  const int lane = threadIdx.x & 63, r = 4 * blockIdx.x + (threadIdx.x >> 6);
+  if (r >= n_pad) return;
+  double2* row = reinterpret_cast<double2*>(W + ((size_t)job * n_pad + r) * n_pad);
+  const double d = sqrt(nrm[(size_t)job * n_pad + r]);
+  for (int c = lane; c < n_pad / 2; c += 64) {
+    double2 v;
+    v.x = (2 * c == r) ? d : 0.0;
+    v.y = (2 * c + 1 == r) ? d : 0.0;
+    row[c] = v;
+  }
+}
+
+hipError_t launch_qr_basis(int64_t njobs, int n, int n_pad, int nrows, const double* R, double* nrm, double* W,
+                           double* sigma, int32_t* order, hipStream_t stream) {
+  if (njobs == 0) return hipSuccess;
+  if (n_pad % 32 || nrows < 0 || nrows > n_pad) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(basis_colnorm_kernel, dim3((unsigned)ceil_div(n_pad, 256), (unsigned)njobs), dim3(256), 0, stream,
+                     n_pad, nrows, R, nrm);
+  hipLaunchKernelGGL(basis_rows_kernel, dim3((unsigned)ceil_div(n_pad, 4), (unsigned)njobs), dim3(256), 0, stream,
+                     n_pad, (const double*)nrm, W);
+  int P = 1;
+  while (P < n_pad) P <<= 1;
+  const size_t sh = (size_t)P * (sizeof(double) + sizeof(int));
+  hipLaunchKernelGGL(jacobi_finalize_kernel, dim3((unsigned)njobs), dim3(256), sh, stream, n, n_pad,
+                     (const double*)W, (const double*)nrm, sigma, order);
+  return hipGetLastError();
+}
+
 hipError_t launch_jacobi_finalize(int64_t njobs, int n, int n_pad, const double* W, double* sigma,
                                   int32_t* order, hipStream_t stream, double* nrm) {
   if (njobs == 0) return hipSuccess;

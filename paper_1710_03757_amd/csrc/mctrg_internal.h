@@ -162,6 +162,12 @@ hipError_t run_rank_rows(int64_t njobs, int n_pad, double tau_null, const double
 hipError_t run_deflate(int64_t njobs, int n_pad, double tau_null, const double* Win, double* Wout, int* nb_job,
                        double* nrm, int32_t* newpos, int* scratch_dev, int* scratch_host, int* nb_max,
                        hipStream_t stream);
+// QR-iteration basis instead of the Jacobi: nrm (n_pad per job) receives the
+// squared column norms of the row-major triangular factors R (rows from nrows
+// on are zero), W the diagonal matrix of the norms, sigma / order (n per job)
+// the norms in descending order and their columns, as after the Jacobi.
+hipError_t launch_qr_basis(int64_t njobs, int n, int n_pad, int nrows, const double* R, double* nrm, double* W,
+                           double* sigma, int32_t* order, hipStream_t stream);
 // QR preconditioning (k_qr.hip): perm[j] (n_pad) orders the columns of the
 // unfolding by decreasing norm, S (n_pad^2 per job) holds M P column-wise
 // and is overwritten by V and R, Tws (1024 per job) is scratch, and W
@@ -323,7 +329,7 @@ hipError_t launch_record_positions(int64_t nsamp, int npos, int64_t per_sample, 
 hipError_t launch_record(int64_t nsamp, int step, int n_steps, int kmax, int kcap, const int64_t* idx,
                          const int32_t* cand, const int32_t* kept, const int32_t* sel, int32_t* rec,
                          hipStream_t stream);
-hipError_t launch_lnc_accum(int64_t nsamp, int out_per_sample, int step, int n_steps, const double* lnc,
+hipError_t launch_lnc_accum(int64_t nsamp, int out_per_sample, int step, int n_steps, double mult, const double* lnc,
                             double* lnc_steps, int* failed, hipStream_t stream);
 hipError_t launch_jacobi_fail(int64_t njobs, int jobs_per_sample, const int* sweeps, int* failed,
                               hipStream_t stream);

@@ -15,11 +15,15 @@ where delta is the relative Frobenius distance of the normalised tensors and
 base the rounding level of one step.  Two LAPACK drivers running the same
 oracle chain obey this with a margin of ~30 and still drift apart to O(1)
 within 10-13 steps at the C2 temperatures.  The gate below checks every
-step while its bound stays under ``stop_bound``; a step where the kept sets
-differ (a flip) must be a rounding-distance event: the uniform u of the
+step until the kept sets differ: the tensors within 3 kappa_s (base +
+delta_in) and ln c within kappa_tau (base + delta_in) (kappa_tau adds the
+squared smallest kept value, which governs the inclusion rates), delta_in
+being the measured discrepancy of the step's input.  A step where the kept
+sets differ (a flip) must be a rounding-distance event: the uniform u of the
 first differing decision must lie within the interval that q (the
 probability of keeping that candidate, Section II's sequential draw) sweeps
-when every singular value moves by (2 base + delta_{s-1}) s_1.
+when every singular value moves by (2 base + delta_in) s_1; the chain is
+compared no further.
 
 Tensors are compared through J = 64 Gaussian fingerprints
 f_j = vec(P_j)^T M_A(T) vec(Q_j), whose mean square estimates ||T||_F^2.
@@ -38,6 +42,26 @@ EPS64 = 2.0 ** -52
 HOST_THREADS = 16          # host cores the oracle pools may use together
 
 
+def kappa_tau(sigma: np.ndarray, c: int, sel) -> float:
+    """The conditioning of the per-step tolerance tau_T = max(floor, 100 u
+    kappa) of one decomposition: max(1 / min gap between a kept value and a
+    neighbour not kept, 1 / (smallest kept value)^2), values relative to
+    s_1 (the squared term covers the inclusion rates, which depend on the
+    squared values of every candidate)."""
+    sig = np.asarray(sigma[:c], dtype=np.float64) / float(sigma[0])
+    sel = set(int(j) for j in sel)
+    if not sel:
+        return 1.0
+    gmin = math.inf
+    for j in sel:
+        for j2 in (j - 1, j + 1):
+            if 0 <= j2 < c and j2 not in sel:
+                gmin = min(gmin, abs(sig[j] - sig[j2]))
+    k1 = 1.0 / gmin if gmin > 0 else math.inf
+    smin = min(sig[j] for j in sel)
+    return max(k1, 1.0 / (smin * smin))
+
+
 def kappa_split(sigma: np.ndarray, c: int, sel) -> float:
     sig = np.asarray(sigma[:c], dtype=np.float64) / float(sigma[0])
     sel = set(int(j) for j in sel)
@@ -53,6 +77,16 @@ def kappa_split(sigma: np.ndarray, c: int, sel) -> float:
     return max(k1, k2)
 
 
+def pad_to_capacity(T: np.ndarray, D: int) -> np.ndarray:
+    """The oracle keeps exactly the kept count on every new leg; the library
+    stores every tensor at the capacity bond dimension D = min(k, D_prev^2)
+    with zero padding after the kept indices.  Same padding here."""
+    out = np.zeros((D, D, D, D))
+    a, b, c, e = T.shape
+    out[:a, :b, :c, :e] = T
+    return out
+
+
 def fingerprint(T: np.ndarray, P: np.ndarray, Q: np.ndarray) -> np.ndarray:
     D = T.shape[0]
     M = np.asarray(T, dtype=np.float64).reshape(D * D, D * D)
@@ -65,9 +99,10 @@ class OracleStep:
     c: List[int]
     sel: List[List[int]]
     sigma: List[np.ndarray]          # candidate spectra (first c values), both splits
-    kappa: float
+    kappa: float                     # amplification of a tensor perturbation (kappa_split)
     fp: np.ndarray
     norm: float
+    kappa_t: float = 1.0             # conditioning of the ln c tolerance (kappa_tau)
 
 
 @dataclass
@@ -89,13 +124,16 @@ def oracle_chain_summary(beta, h, n_steps, k, seed, sid, tau_null=1e-11, mode="s
     res = trg.run_shared(ising.site_tensor(beta, h), n_steps, k, seed, sid, mode=mode, tau_null=tau_null,
                          keep_tensors=True)
     steps = []
+    D = 2
     for st in res.records:
-        T = st.T_hat
-        P, Q = projection_pairs(T.shape[0], J)
+        D = min(k, D * D)
+        T = pad_to_capacity(st.T_hat, D)
+        P, Q = projection_pairs(D, J)
         kap = max(kappa_split(sp.sigma, sp.c, sp.sel) for sp in st.splits)
         steps.append(OracleStep(st.ln_c, [sp.c for sp in st.splits], [list(map(int, sp.sel)) for sp in st.splits],
                                 [np.array(sp.sigma[:min(sp.sigma.size, sp.c + 8)]) for sp in st.splits], kap,
-                                fingerprint(T, P, Q), float(np.linalg.norm(T))))
+                                fingerprint(T, P, Q), float(np.linalg.norm(T)),
+                                max(kappa_tau(sp.sigma, sp.c, sp.sel) for sp in st.splits)))
     return OracleChain(sid, steps, res.ln_abs_Z, res.sign)
 
 
@@ -153,12 +191,15 @@ def q_interval(sigma, c, k, sel_prefix, m, delta):
 
 @dataclass
 class GateResult:
-    checked: int = 0
-    stopped_at: Optional[int] = None          # first step not compared
-    reason: str = "end"                        # end | flip | conditioning
-    max_ratio: float = 0.0                     # worst measured / bound over checked steps
+    checked: int = 0                           # steps whose kept sets and ln c were compared
+    tensor_checked: int = 0                    # of those, steps whose tensors were compared too
+    stopped_at: Optional[int] = None           # first step not compared (a flip)
+    reason: str = "end"                        # end | flip
+    max_ratio: float = 0.0                     # worst measured / bound over compared values
     worst_delta: float = 0.0
     worst_dlnc: float = 0.0
+    worst_tau: float = 0.0                     # largest ln c tolerance used
+    lnZ_tol: Optional[float] = None            # tolerance of ln|Z~| per site (None: not comparable)
     notes: List[str] = field(default_factory=list)
 
 
@@ -190,11 +231,20 @@ def check_flip(sigma, c, sel, gsel, gc, k, tau, delta, u_of, notes, label):
     assert lo <= u <= hi, (label, m, u, q, lo, hi, "flip outside the rounding interval")
 
 
-def compare_chain(orc: OracleChain, gpu_sel, gpu_c, gpu_lnc, gpu_fp, k, seed, tau, base, stop_bound=1e-2,
-                  floor=1e-12):
+def compare_chain(orc: OracleChain, gpu_sel, gpu_c, gpu_lnc, gpu_fp, k, seed, tau, base, lnc_floor=1e-10,
+                  tensor_floor=1e-12):
     """Gate of one shared-mode chain.  gpu_sel[s][split], gpu_c[s][split]:
     kept indices and candidate counts; gpu_lnc[s]; gpu_fp[s]: fingerprints of
-    the GPU's normalised tensor after step s (None: not compared).  Returns a
+    the GPU's normalised tensor after step s (None: not compared).
+
+    At every step until a flip: the kept sets equal the oracle's;
+    |d ln c| <= max(lnc_floor, kappa_tau (base + delta_in)); the tensors
+    (fingerprints) within max(tensor_floor, 3 kappa (base + delta_in)),
+    where delta_in is the discrepancy the step inherits - the measured
+    tensor distance after the previous step, or with no fingerprints the
+    previous step's bound - and kappa, kappa_tau come from the oracle's
+    spectrum of the step.  A step whose kept set differs must be a validated
+    rounding-distance flip; the chain is compared no further.  Returns a
     GateResult; raises AssertionError on a violation."""
     from oracle.philox import selection_uniforms
 
@@ -203,6 +253,7 @@ def compare_chain(orc: OracleChain, gpu_sel, gpu_c, gpu_lnc, gpu_fp, k, seed, ta
 
     r = GateResult()
     dprev = 0.0
+    wsum = 0.0
     for s, o in enumerate(orc.steps):
         same = all(list(gpu_sel[s][p]) == o.sel[p] and int(gpu_c[s][p]) == o.c[p] for p in (0, 1))
         if not same:
@@ -214,32 +265,41 @@ def compare_chain(orc: OracleChain, gpu_sel, gpu_c, gpu_lnc, gpu_fp, k, seed, ta
             if any(list(gpu_sel[s][p]) != o.sel[p] for p in (0, 1)):
                 r.stopped_at, r.reason = s, "flip"
                 return r
-        bound = 3.0 * o.kappa * (base + dprev)
-        if bound > stop_bound:
-            r.stopped_at, r.reason = s, "conditioning"
-            return r
         dl = abs(float(gpu_lnc[s]) - o.ln_c)
-        tol = max(bound, floor)
-        d = 0.0
+        tau_t = max(lnc_floor, o.kappa_t * (base + dprev))
+        r.worst_tau = max(r.worst_tau, tau_t)
+        r.worst_dlnc = max(r.worst_dlnc, dl)
+        r.max_ratio = max(r.max_ratio, dl / tau_t)
+        assert dl <= tau_t, (s, "ln c", dl, tau_t, o.kappa_t, dprev)
+        r.checked += 1
+        bound = max(tensor_floor, 3.0 * o.kappa * (base + dprev))
         if gpu_fp is not None and gpu_fp[s] is not None:
             d = float(np.sqrt(np.mean((np.asarray(gpu_fp[s]) - o.fp) ** 2)) / o.norm)
-        r.max_ratio = max(r.max_ratio, d / tol, dl / tol)
-        r.worst_delta = max(r.worst_delta, d)
-        r.worst_dlnc = max(r.worst_dlnc, dl)
-        assert d <= tol and dl <= tol, (s, d, dl, tol, o.kappa, dprev)
-        r.checked += 1
-        dprev = max(d, dl)
+            r.max_ratio = max(r.max_ratio, d / bound)
+            r.worst_delta = max(r.worst_delta, d)
+            assert d <= bound, (s, "tensor", d, bound, o.kappa, dprev)
+            r.tensor_checked += 1
+            dprev = max(d, dl)
+        else:
+            dprev = min(1.0, max(bound, dl))
+        wsum += 2.0 ** -(s + 1) * tau_t
+    # ln|Z~| per site = sum_s 2^-(s+1) ln c_s + ln|Tr| / N: comparable while the
+    # final tensors agree to 1e-6 (the trace then moves by about as much)
+    n = len(orc.steps)
+    if dprev <= 1e-6:
+        r.lnZ_tol = max(1e-12, wsum + 10.0 * dprev / 2.0 ** n)
     return r
 
 
-def compare_independent(orc, gpu_levels, gpu_lnc, k, seed, sid, tau, base, stop_bound=1e-2, floor=1e-12):
+def compare_independent(orc, gpu_levels, gpu_lnc, k, seed, sid, tau, base, floor=1e-12):
     """Gate of one independent-mode sample (the paper's estimator): orc is
     the oracle's ChainResult (per-position records), gpu_levels[s] the
     GPU's record rows (c, kept, sel[k]) of step s's positions, gpu_lnc[s]
     the sum of ln c over the step's new tensors.  Every position must keep
     the oracle's set (else the flip is validated and the comparison stops);
-    the per-step sums agree within the conditioning bound times the number
-    of new tensors."""
+    the per-step sums agree within the conditioning bound (kappa_tau times
+    the rounding level plus the bound inherited from the previous step)
+    times the number of new tensors."""
     from oracle.philox import selection_uniforms
     r = GateResult()
     dprev = 0.0
@@ -258,19 +318,16 @@ def compare_independent(orc, gpu_levels, gpu_lnc, k, seed, sid, tau, base, stop_
         if flipped:
             r.stopped_at, r.reason = s, "flip"
             return r
-        kap = max(kappa_split(sp.sigma, sp.c, sp.sel) for sp in recs)
-        bound = 3.0 * kap * (base + dprev)
-        if bound > stop_bound:
-            r.stopped_at, r.reason = s, "conditioning"
-            return r
-        n_new = max(1, len(recs) // 2)
+        kap = max(kappa_tau(sp.sigma, sp.c, sp.sel) for sp in recs)
+        bound = max(floor, kap * (base + dprev))
+        n_new = 2 ** (len(orc.positions) - s - 1)      # new tensors of the level (also for a prefix step)
         dl = abs(float(gpu_lnc[s]) - orc.ln_c[s])
-        tol = max(bound, floor) * n_new
+        tol = bound * n_new
         r.max_ratio = max(r.max_ratio, dl / tol)
         r.worst_dlnc = max(r.worst_dlnc, dl)
         assert dl <= tol, (s, dl, tol, kap, dprev)
         r.checked += 1
-        dprev = dl
+        dprev = min(1.0, bound)
     return r
 
 

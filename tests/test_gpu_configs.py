@@ -6,7 +6,7 @@ step's conditioning bound).
 C1  16 x 16 torus, k = 8, beta_c, independent mode (the paper's estimator):
     per-position parity with the oracle (also on 32 x 32 and 64 x 64 tori,
     10 and 12 steps), and the sample mean of Z~ against Kaufman's exact Z
-    over five seeds (Section III, Eq. infiniteEnsemble; error bars per
+    over ten seeds (Section III, Eq. infiniteEnsemble; error bars per
     Section V, Eq. shrunkDev).
 C2  k = 16 shared chains over the beta sweep 0.30..0.60 (16 values), 20
     steps (2^20 sites), every chain compared step by step.
@@ -70,15 +70,15 @@ def test_independent_parity_larger_tori(n_steps, picks):
 
 
 def test_c1_unbiased_against_kaufman():
-    """Five seeds of 1000 samples: the pooled mean of Z~/Z within two
-    standard errors of 1 and the five z-scores consistent with N(0,1)
-    (sum of squares below the 99 % point of chi^2 with 5 degrees, 15.09)."""
+    """Ten seeds of 1000 samples: the pooled mean of Z~/Z within two
+    standard errors of 1 and the ten z-scores consistent with N(0,1) (sum
+    of squares below the 99 % point of chi^2 with 10 degrees, 23.21)."""
     torch, m = need_gpu()
-    log("C1 1000 samples x 5 seeds vs Kaufman")
+    log("C1 1000 samples x 10 seeds vs Kaufman")
     ts = m.init_tensor("site", [BETA_C], [0.0])
     lnZ = ising.kaufman_lnZ_torus(16, BETA_C)
     zs, allv = [], []
-    for seed in range(5):
+    for seed in range(10):
         r = m.run_samples(ts, 1000, n_steps=8, k=8, mode="independent", seed=seed)
         assert r.status == m.OK
         v = r.sign.cpu().numpy() * np.exp(r.ln_abs_Z.cpu().numpy() - lnZ)     # Z~ / Z
@@ -95,7 +95,7 @@ def test_c1_unbiased_against_kaufman():
     log(f"C1 pooled: mean Z~/Z = {mean:.5f} +- {se:.5f} (z = {(mean - 1) / se:+.2f}); z-scores "
         f"{[round(z, 2) for z in zs]}, sum of squares {sum(z * z for z in zs):.2f}")
     assert abs(mean - 1.0) <= 2.0 * se
-    assert sum(z * z for z in zs) < 15.09
+    assert sum(z * z for z in zs) < 23.21
 
 
 def test_c2_beta_sweep_parity():
@@ -116,13 +116,14 @@ def test_c2_beta_sweep_parity():
     for i, (b, f) in enumerate(zip(betas, futs)):
         orc = f.result(timeout=900)
         r = parity.compare_chain(orc, g[i]["sel"], g[i]["c"], g[i]["lnc"], g[i]["fp"], 16, 0, 1e-11, BASE64)
-        log(f"beta {b:.3f}: compared {r.checked} steps, stop {r.stopped_at} ({r.reason}), worst delta "
-            f"{r.worst_delta:.2e}, worst |d ln c| {r.worst_dlnc:.2e}")
+        log(f"beta {b:.3f}: compared {r.checked} steps ({r.tensor_checked} with tensors), stop {r.stopped_at} "
+            f"({r.reason}), worst delta {r.worst_delta:.2e}, worst |d ln c| {r.worst_dlnc:.2e} (largest tolerance "
+            f"{r.worst_tau:.1e})")
         for n in r.notes:
             log("   " + n)
         checked.append(r.checked)
-        if r.reason == "end":
-            assert abs(g[i]["ln_abs_Z"] - orc.ln_abs_Z) / 2.0 ** 20 < 1e-12
+        if r.reason == "end" and r.lnZ_tol is not None:
+            assert abs(g[i]["ln_abs_Z"] - orc.ln_abs_Z) / 2.0 ** 20 <= r.lnZ_tol
     log(f"C2 steps compared per chain: {checked}")
     assert min(checked) >= 8
 

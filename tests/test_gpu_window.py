@@ -10,16 +10,17 @@ parallel on the host, in both benchmarked forms:
 * FP32 contraction, tau_null = 1e-6 (the oracle, FP64, at 1e-6).
 
 Gate (tests/parity.py): at every step the kept sets and candidate counts
-must equal the oracle's, the normalised tensor (Gaussian fingerprints) and
-ln c must agree within 3 kappa_s (base + delta_{s-1}) - the step's
-conditioning times the rounding level plus the discrepancy it inherits -
-and a step whose kept set differs must be a rounding-distance event (the
-uniform within the interval its keep probability sweeps under that
-perturbation), after which the chain is no longer compared.  base is
-100 eps for the FP64 contraction and 2^-19 (32 units of FP32 rounding of
-T') for the FP32 one.  The first eight steps (the ramp-up and the first
-steady steps, which carry most of ln Z per site) must be compared in every
-chain."""
+must equal the oracle's, or differ by a validated rounding-distance flip
+(the uniform within the interval its keep probability sweeps under the
+step's perturbation), after which the chain is no longer compared; ln c
+within kappa_tau (base + delta_in) and the normalised tensor (Gaussian
+fingerprints) within 3 kappa (base + delta_in), kappa from the oracle's
+spectrum of the step and delta_in the measured discrepancy of its input.
+base is 100 eps for the FP64 contraction; for the FP32 one it is D^2 2^-24
+(the worst case of a K = D^2 FP32 accumulation), also the floor of its ln c
+tolerance.  The first eight steps (the ramp-up and the first steady steps,
+which carry most of ln Z per site) must be compared in every chain; the
+FP64 chains without a flip, through step 24."""
 import numpy as np
 import pytest
 
@@ -32,7 +33,7 @@ pytestmark = pytest.mark.gpu
 
 B, K, STEPS = 256, 32, 25
 PICKS = [0, 85, 128, 255]          # parts 0, 0, 1, 2 of 0..85, 86..170, 171..255
-FORMS = {"f64": (1e-11, 100 * parity.EPS64), "f32": (1e-6, 2.0 ** -19)}
+FORMS = {"f64": (1e-11, 100 * parity.EPS64), "f32": (1e-6, K * K * 2.0 ** -24)}
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
@@ -47,12 +48,15 @@ def test_k32_timed_window(dtype):
     stops = []
     for i, f in zip(PICKS, futs):
         orc = f.result(timeout=900)
-        r = parity.compare_chain(orc, g[i]["sel"], g[i]["c"], g[i]["lnc"], g[i]["fp"], K, 0, tau, base)
-        log(f"sample {i}: compared {r.checked} steps, stop {r.stopped_at} ({r.reason}), worst delta "
-            f"{r.worst_delta:.2e}, worst |d ln c| {r.worst_dlnc:.2e}, worst ratio to bound {r.max_ratio:.2e}")
+        r = parity.compare_chain(orc, g[i]["sel"], g[i]["c"], g[i]["lnc"], g[i]["fp"], K, 0, tau, base,
+                                 lnc_floor=1e-10 if dtype == "f64" else base)
+        log(f"sample {i}: compared {r.checked} steps ({r.tensor_checked} with tensors), stop {r.stopped_at} "
+            f"({r.reason}), worst delta {r.worst_delta:.2e}, worst |d ln c| {r.worst_dlnc:.2e} (largest tolerance "
+            f"{r.worst_tau:.1e}), worst ratio to bound {r.max_ratio:.2e}, |d lnZ|/site "
+            f"{abs(g[i]['ln_abs_Z'] - orc.ln_abs_Z) / 2.0 ** STEPS:.2e}")
         for n in r.notes:
             log("   " + n)
         stops.append(r.checked)
-        if r.reason == "end":
-            assert abs(g[i]["ln_abs_Z"] - orc.ln_abs_Z) / 2.0 ** STEPS < 1e-9
+        if r.reason == "end" and r.lnZ_tol is not None:
+            assert abs(g[i]["ln_abs_Z"] - orc.ln_abs_Z) / 2.0 ** STEPS <= r.lnZ_tol
     assert min(stops) >= 8, stops

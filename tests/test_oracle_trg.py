@@ -93,7 +93,7 @@ def _subsets_with_p(sigma, k, tau):
     return list(zip(subs, w / w.sum()))
 
 
-def _expected_Z_independent(T0s, k, tau=1e-11):
+def _expected_Z_independent(T0s, k, tau=1e-11, basis="svd"):
     """sum over every path of p(path) * Z~(path) for a 2 x 2 torus."""
     lev0 = lattice.square_torus(2)
     tensors0 = [T0s[i] for i in range(4)]
@@ -102,8 +102,11 @@ def _expected_Z_independent(T0s, k, tau=1e-11):
     def options(tensors, lev):
         opts = []
         for p in range(lev.n):
-            M, _, _ = trg.unfold(tensors[p], 0 if lev.is_a[p] else 1)
-            s = np.linalg.svd(M, compute_uv=False)
+            M, _, cs = trg.unfold(tensors[p], 0 if lev.is_a[p] else 1)
+            if basis == "svd":
+                s = np.linalg.svd(M, compute_uv=False)
+            else:
+                s = trg.decompose_qr(M, cs, {"qr3": 3, "qr5": 5}[basis])[1]
             opts.append(_subsets_with_p(s, k, tau))
         return opts
 
@@ -111,13 +114,13 @@ def _expected_Z_independent(T0s, k, tau=1e-11):
     for path0 in itertools.product(*opts0):
         p0 = math.prod(pe for _, pe in path0)
         ch0 = lambda pos, step, split, s, c, path=path0: path[pos][0]
-        out = trg.step_independent(tensors0, lev0, k, "independent", 0, 0, 0, tau, ch0)
+        out = trg.step_independent(tensors0, lev0, k, "independent", 0, 0, 0, tau, ch0, basis=basis)
         t1, lev1, sum1 = out
         opts1 = options(t1, lev1)
         for path1 in itertools.product(*opts1):
             p1 = math.prod(pe for _, pe in path1)
             ch1 = lambda pos, step, split, s, c, path=path1: path[pos][0]
-            t2, lev2, sum2 = trg.step_independent(t1, lev1, k, "independent", 0, 0, 1, tau, ch1)
+            t2, lev2, sum2 = trg.step_independent(t1, lev1, k, "independent", 0, 0, 1, tau, ch1, basis=basis)
             total += p0 * p1 * math.exp(sum1 + sum2) * trg.trace(t2[0])
     return total
 
