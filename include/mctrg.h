@@ -314,6 +314,22 @@ int mctrg_sample_batched(int64_t n_jobs, int32_t n, int32_t k, int32_t mode, uin
                          const int32_t* split, int32_t* kept, int32_t* cand, int32_t* sel,
                          double* log_r, double* weight, void* hip_stream);
 
+/* mctrg_sample_batched without any device allocation, for callers that
+ * cannot allocate (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): the same arguments, kernel and results.
+ * The draw's tables live in a fixed per-device scratch array of 64 MiB
+ * (8,388,608 doubles), which each device holds until the process ends; a
+ * call needs n_jobs * (2 (k+1) (n+1) + n + 8) doubles of it (e.g. 122 jobs at
+ * n = 1024, k = 32) and returns ENOMEM, with nothing enqueued, beyond that.
+ * Nothing in the scratch must start at zero (every table entry is written
+ * before it is read).  Calls on one device share its scratch: calls that
+ * overlap in time on one device (several host threads or streams) race.
+ * Blocks on hip_stream.  Errors: EINVAL, ENOMEM, EDEVICE. */
+int mctrg_sample_batched_noalloc(int64_t n_jobs, int32_t n, int32_t k, int32_t mode, uint64_t seed,
+                                 double tau_null, const double* sigma, const uint64_t* rng,
+                                 const int32_t* split, int32_t* kept, int32_t* cand, int32_t* sel,
+                                 double* log_r, double* weight, void* hip_stream);
+
 /* Contraction step (Section III, Levin-Nave TRG): for each job,
  *   T'[a,b,c,e] = sum_{p,q,s,t} GA[a,p,t] GB[b,q,p] FA[s,q,c] FB[t,s,e]
  * with GA, GB: kk x D x D, FA, FB: D x D x kk (device, FP64, per job

@@ -47,7 +47,7 @@ EXPORTED = ("mctrg_init_tensor", "mctrg_tensor_set_info", "mctrg_default_config"
             "mctrg_run_samples", "mctrg_estimate_lnZ", "mctrg_destroy", "mctrg_status_string",
             "mctrg_svd_batched", "mctrg_sample_batched", "mctrg_contract_batched", "mctrg_chain_create",
             "mctrg_chain_step", "mctrg_chain_finish", "mctrg_chain_get_profile", "mctrg_chain_destroy",
-            "mctrg_chain_tensor")
+            "mctrg_chain_tensor", "mctrg_sample_batched_noalloc")
 
 
 class RunConfig(ctypes.Structure):
@@ -108,6 +108,8 @@ _lib.mctrg_svd_batched.restype = ctypes.c_int
 _lib.mctrg_sample_batched.argtypes = [_i64, _i32, _i32, _i32, _u64, _f64, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
                                       _vp, _vp]
 _lib.mctrg_sample_batched.restype = ctypes.c_int
+_lib.mctrg_sample_batched_noalloc.argtypes = _lib.mctrg_sample_batched.argtypes
+_lib.mctrg_sample_batched_noalloc.restype = ctypes.c_int
 _lib.mctrg_contract_batched.argtypes = [_i64, _i32, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp]
 _lib.mctrg_contract_batched.restype = ctypes.c_int
 _lib.mctrg_chain_create.argtypes = [_vp, ctypes.POINTER(RunConfig), _i64, _vp, _vp, ctypes.POINTER(_vp)]
@@ -338,10 +340,12 @@ def svd_batched(M, d1: int, d2: int, want_V: bool = True):
     return sig, V, sw
 
 
-def sample_batched(sigma, rng, split, k: int, mode="shared", seed: int = 0, tau_null: float = 1e-11):
-    """mctrg_sample_batched.  sigma (n_jobs, n) float64, rng (n_jobs, 3)
-    int64 (sample id, position id, step), split (n_jobs,) int32 - all on the
-    device.  Returns dict of kept, cand, sel, log_r, weight."""
+def sample_batched(sigma, rng, split, k: int, mode="shared", seed: int = 0, tau_null: float = 1e-11,
+                   no_alloc: bool = False):
+    """mctrg_sample_batched (mctrg_sample_batched_noalloc with ``no_alloc``).
+    sigma (n_jobs, n) float64, rng (n_jobs, 3) int64 (sample id, position
+    id, step), split (n_jobs,) int32 - all on the device.  Returns dict of
+    kept, cand, sel, log_r, weight."""
     torch = _torch()
     _dev(torch, sigma, torch.float64, "sigma")
     _dev(torch, rng, torch.int64, "rng")
@@ -354,7 +358,7 @@ def sample_batched(sigma, rng, split, k: int, mode="shared", seed: int = 0, tau_
     lr = torch.empty((nj, k), dtype=torch.float64, device=d)
     w = torch.empty((nj, k), dtype=torch.float64, device=d)
     m = MODES[mode] if isinstance(mode, str) else int(mode)
-    fn = _lib.mctrg_sample_batched
+    fn = _lib.mctrg_sample_batched_noalloc if no_alloc else _lib.mctrg_sample_batched
     _check(fn(nj, n, k, m, seed, tau_null, _ptr(sigma), _ptr(rng), _ptr(split), _ptr(kept), _ptr(cand), _ptr(sel),
               _ptr(lr), _ptr(w), _stream(torch)), fn.__name__)
     return {"kept": kept, "cand": cand, "sel": sel, "log_r": lr, "weight": w}

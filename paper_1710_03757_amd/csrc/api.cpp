@@ -1227,6 +1227,25 @@ int mctrg_sample_batched(int64_t n_jobs, int32_t n, int32_t k, int32_t mode, uin
   return rc;
 }
 
+int mctrg_sample_batched_noalloc(int64_t n_jobs, int32_t n, int32_t k, int32_t mode, uint64_t seed, double tau_null,
+                                 const double* sigma, const uint64_t* rng, const int32_t* split, int32_t* kept,
+                                 int32_t* cand, int32_t* sel, double* log_r, double* weight, void* hip_stream) {
+  if (n_jobs < 0 || n < 1 || n > 4096 || k < 1 || k > 64 || mode < 0 || mode > MCTRG_TOPK) return MCTRG_EINVAL;
+  if (!is_fin(tau_null) || tau_null < 0 || tau_null >= 1) return MCTRG_EINVAL;
+  if (n_jobs == 0) return MCTRG_OK;
+  if (!sigma || !rng || !split || !kept || !cand || !sel || !log_r || !weight) return MCTRG_EINVAL;
+  if (sample_scratch_doubles(n_jobs, n, k) > noalloc_scratch_doubles()) return MCTRG_ENOMEM;
+  double* scr = nullptr;
+  if (noalloc_scratch(&scr) != hipSuccess) return MCTRG_EDEVICE;
+  hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+  SampleArgs sa{};
+  sa.njobs = n_jobs; sa.n = n; sa.k = k; sa.mode = mode; sa.seed = seed; sa.tau = tau_null; sa.sigma = sigma;
+  sa.rng = rng; sa.split = split; sa.kept = kept; sa.cand = cand; sa.sel = sel; sa.log_r = log_r;
+  sa.weight = weight; sa.scratch = scr;
+  if (launch_sample(sa, st) != hipSuccess || hipStreamSynchronize(st) != hipSuccess) return MCTRG_EDEVICE;
+  return MCTRG_OK;
+}
+
 int mctrg_contract_batched(int64_t n_jobs, int32_t D, int32_t kk, int32_t dtype, const double* GA,
                            const double* GB, const double* FA, const double* FB, double* T_out, void* hip_stream) {
   if (n_jobs < 0 || D < 1 || D > 64 || kk < 1 || kk > 64 || dtype < MCTRG_F64 || dtype > MCTRG_FP8_E4M3)

@@ -273,6 +273,11 @@ struct SampleArgs {
   double* scratch;         // njobs * (k+1) * (n+1) * 2 + njobs * n doubles
 };
 hipError_t launch_sample(const SampleArgs& a, hipStream_t stream);
+// The fixed per-device scratch of the allocation-free sampler (k_noalloc.hip):
+// its size in doubles, and its device address on the current device (looked
+// up once per device with hipGetSymbolAddress).
+size_t noalloc_scratch_doubles();
+hipError_t noalloc_scratch(double** out);
 size_t sample_scratch_doubles(int64_t njobs, int n, int k);
 
 // Factors.  G[j]: kcap x n (row a = w_a v_a), F[j]: n x kcap (col a = w_a u_a).
