@@ -116,7 +116,7 @@ def test_c2_beta_sweep_parity():
     for i, (b, f) in enumerate(zip(betas, futs)):
         orc = f.result(timeout=900)
         r = parity.compare_chain(orc, g[i]["sel"], g[i]["c"], g[i]["lnc"], g[i]["fp"], 16, 0, 1e-11, BASE64)
-        log(f"beta {b:.3f}: compared {r.checked} steps ({r.tensor_checked} with tensors), stop {r.stopped_at} "
+        log(f"beta {b:.3f}: compared {r.checked} steps ({r.tensor_checked} with tensors, {r.tight} with a tensor bound <= 1e-4), stop {r.stopped_at} "
             f"({r.reason}), worst delta {r.worst_delta:.2e}, worst |d ln c| {r.worst_dlnc:.2e} (largest tolerance "
             f"{r.worst_tau:.1e})")
         for n in r.notes:

@@ -45,18 +45,21 @@ def test_k32_timed_window(dtype):
                                      for i in PICKS], workers=len(PICKS))
     ts = m.init_tensor("site", [BETA_C], [0.0])
     g = parity.gpu_chain_trace(m, ts, B, STEPS, K, PICKS, dtype=dtype, tau=tau, log=log)
-    stops = []
+    stops, tights = [], []
     for i, f in zip(PICKS, futs):
         orc = f.result(timeout=900)
         r = parity.compare_chain(orc, g[i]["sel"], g[i]["c"], g[i]["lnc"], g[i]["fp"], K, 0, tau, base,
                                  lnc_floor=1e-10 if dtype == "f64" else base)
-        log(f"sample {i}: compared {r.checked} steps ({r.tensor_checked} with tensors), stop {r.stopped_at} "
+        log(f"sample {i}: compared {r.checked} steps ({r.tensor_checked} with tensors, {r.tight} with a tensor bound <= 1e-4), stop {r.stopped_at} "
             f"({r.reason}), worst delta {r.worst_delta:.2e}, worst |d ln c| {r.worst_dlnc:.2e} (largest tolerance "
             f"{r.worst_tau:.1e}), worst ratio to bound {r.max_ratio:.2e}, |d lnZ|/site "
             f"{abs(g[i]['ln_abs_Z'] - orc.ln_abs_Z) / 2.0 ** STEPS:.2e}")
         for n in r.notes:
             log("   " + n)
         stops.append(r.checked)
+        tights.append(r.tight)
         if r.reason == "end" and r.lnZ_tol is not None:
             assert abs(g[i]["ln_abs_Z"] - orc.ln_abs_Z) / 2.0 ** STEPS <= r.lnZ_tol
     assert min(stops) >= 8, stops
+    if dtype == "f64":
+        assert min(tights) >= 8, tights
