@@ -26,8 +26,10 @@ library's own streams).  The kernel's own executed flops are reported
 separately (``implementation_flops_per_launch``).  HBM traffic per dispatch
 comes from the committed rocprofv3 counter summary when that was taken on
 the same kernel source and workload window.  Also reported: the whole-step
-roofline fraction, the MFMA rate of the coarse-graining GEMM and the CPU
-oracle's rate on the host cores.
+roofline fraction, the MFMA rate of the coarse-graining GEMM, the same
+window with the cheaper unbiased decomposition (``cheaper_decomposition``:
+a QR-iteration basis instead of the SVD, its speedup and the spread of its
+samples against the SVD form's) and the CPU oracle's rate on the host cores.
 """
 from __future__ import annotations
 
@@ -94,12 +96,13 @@ def gemm_flops(k: int) -> float:
     return 2.0 * k ** 6
 
 
-def run_form(m, torch, args, dtype, tau):
+def run_form(m, torch, args, dtype, tau, decomposition="svd"):
     """Runs the chains of one form over the window; returns its measurements."""
     k, B = args.k, args.batch
     n_chain = args.warmup + args.steps
     ts = m.init_tensor("site", [args.beta], [args.h])
-    chain = m.Chain(ts, B, n_steps=n_chain, k=k, dtype=dtype, seed=0, profile=True, tau_null=tau)
+    chain = m.Chain(ts, B, n_steps=n_chain, k=k, dtype=dtype, seed=0, profile=True, tau_null=tau,
+                    decomposition=decomposition)
     for s in range(args.warmup):
         chain.step(1)
         print(f"[bench] {dtype}: warmup step {s} done, sweeps={chain.profile()['last_sweeps']}", flush=True)
@@ -255,6 +258,8 @@ def main():
                     help="contraction dtype of the headline form")
     ap.add_argument("--side-dtype", default="f32", choices=["none", "f64", "f32", "bf16", "fp8"],
                     help="contraction dtype of the form run beside the headline")
+    ap.add_argument("--cheap-decomposition", default="qr3", choices=["none", "qr3", "qr5"],
+                    help="also run the headline dtype with the QR-iteration basis instead of the SVD")
     ap.add_argument("--beta", type=float, default=BETA_C)
     ap.add_argument("--h", type=float, default=0.0)
     ap.add_argument("--tau-null", type=float, default=None,
@@ -328,6 +333,24 @@ def main():
             "dominant_kernel": {f: sroof[f] for f in ("kernel", "frac", "avg_launch_ms", "launches", "busy_ms",
                                                       "share_of_step_time")},
             "jacobi_sweeps_per_step": side["sweeps"], "estimate_partial_chain": side["est"]}
+    if args.cheap_decomposition != "none":
+        q = run_form(m, torch, args, args.dtype, tau, decomposition=args.cheap_decomposition)
+        import numpy as np
+        N = 2.0 ** n_chain
+        phi_s, phi_q = r["ln"] / N, q["ln"] / N
+        sd_s, sd_q = float(np.std(phi_s, ddof=1)), float(np.std(phi_q, ddof=1))
+        out["cheaper_decomposition"] = {
+            "decomposition": f"{args.cheap_decomposition}: orthonormal basis of "
+                             f"{3 if args.cheap_decomposition == 'qr3' else 5} QR-iteration steps, terms (M v)(v^T) "
+                             "drawn and reweighted like SVD terms (unbiased for any orthonormal basis), no Jacobi",
+            "dtype": args.dtype, "value": q["value"], "unit": "sample-steps/s", "ms_per_step": q["ms_per_step"],
+            "speedup_vs_headline": q["value"] / r["value"],
+            "spread_ln_Z_per_site": sd_q, "spread_ln_Z_per_site_svd": sd_s,
+            "variance_ratio_vs_svd": (sd_q / sd_s) ** 2 if sd_s > 0 else None,
+            "mean_ln_Z_per_site": float(np.mean(phi_q)), "mean_ln_Z_per_site_svd": float(np.mean(phi_s)),
+            "mean_difference_over_stderr": float((np.mean(phi_q) - np.mean(phi_s)) /
+                                                 math.sqrt(sd_q ** 2 / len(phi_q) + sd_s ** 2 / len(phi_s))),
+            "note": "same samples and draws addressing as the headline; shared chains (one tensor per level)"}
     if not args.no_cpu_baseline:
         base, ores = cpu_baseline(args)
         out["cpu_baseline"] = base

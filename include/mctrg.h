@@ -197,7 +197,14 @@ int32_t mctrg_capacity_dim(int32_t d0, int32_t k, int32_t n_steps);
  *                    ln of the normalisation (shared: max|T'| of the one
  *                    tensor; independent: sum over the level's tensors)
  * Per-sample results depend only on (seed, global sample id, group, k,
- * n_steps, mode, dtype, tau_null) - not on batch size or order.
+ * n_steps, mode, dtype, tau_null, n_det, decomposition), up to rounding:
+ * every random draw is addressed by the global sample id, but the
+ * decomposition's early QR stop, rank limit, number of QR steps and
+ * deflation take one decision per part of a wave (the largest over its
+ * decompositions), so the rounding of a sample - never more than the
+ * approximation budget of tau_null / 10 times s_1 - can depend on the
+ * samples that share its part.  Samples of different k run as concurrent
+ * buckets.
  * Returns ENUMERIC if any sample failed (its sign is 0, its ln|Z~| NaN: a
  * non-finite normalisation, a zero trace or a decomposition that did not
  * converge); the other samples are valid.  Blocks until the outputs are
@@ -334,7 +341,11 @@ int mctrg_sample_batched_noalloc(int64_t n_jobs, int32_t n, int32_t k, int32_t m
  *   T'[a,b,c,e] = sum_{p,q,s,t} GA[a,p,t] GB[b,q,p] FA[s,q,c] FB[t,s,e]
  * with GA, GB: kk x D x D, FA, FB: D x D x kk (device, FP64, per job
  * contiguous).  T_out: device FP64, n_jobs * kk^4.  dtype selects the
- * precision of the kk^2 x kk^2 x D^2 GEMM.  Blocks on hip_stream. */
+ * precision of the kk^2 x kk^2 x D^2 GEMM.  Blocks on hip_stream.
+ * The GEMM's tile shape (64 x 64 or 128 x 128 per workgroup) is chosen by
+ * timing both on the first GEMM of each (dtype, shape, batch) on a device
+ * (also inside the chains); the environment variable MCTRG_GEMM_TILE = 64
+ * or 128 forces one (a test hook). */
 int mctrg_contract_batched(int64_t n_jobs, int32_t D, int32_t kk, int32_t dtype,
                            const double* GA, const double* GB, const double* FA,
                            const double* FB, double* T_out, void* hip_stream);

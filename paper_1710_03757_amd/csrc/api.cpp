@@ -943,62 +943,153 @@ int mctrg_run_samples(mctrg_tensor_set* ts, const mctrg_run_config* cfg, int64_t
     probe.nsamp = 1;
     if ((double)chain_bytes(probe) > budget) return MCTRG_ENOMEM;
   }
+  // Buckets of different k run concurrently (each wave of a bucket as its
+  // parts on streams and host threads of its own), the workspace budget
+  // shared in proportion to what each bucket would need in one wave; when a
+  // share cannot hold one sample, the buckets run one after another with the
+  // whole budget.
+  const int parts = (cfg->flags & MCTRG_ONE_STREAM) ? 1 : kParts;
+  struct Bucket {
+    std::vector<int64_t> members;
+    size_t per1 = 0, per_sample = 0;
+    int64_t wave = 1;
+  };
+  std::vector<Bucket> bk(ks.size());
+  double need_tot = 0.0;
   for (size_t b = 0; b < ks.size(); ++b) {
+    Chain& probe = probes[b];
+    for (int64_t i = 0; i < n_samples; ++i)
+      if ((k_of_sample ? k_of_sample[i] : cfg->k) == ks[b]) bk[b].members.push_back(i);
+    probe.nsamp = 1;
+    bk[b].per1 = chain_bytes(probe);
+    probe.nsamp = 2;
+    bk[b].per_sample = std::max<size_t>(1, chain_bytes(probe) - bk[b].per1);
+    const double fixed = std::max(0.0, (double)bk[b].per1 - (double)bk[b].per_sample);
+    need_tot += parts * fixed + (double)bk[b].per_sample * bk[b].members.size();
+  }
+  bool together = ks.size() > 1;
+  for (size_t b = 0; b < ks.size(); ++b) {
+    const double fixed = std::max(0.0, (double)bk[b].per1 - (double)bk[b].per_sample);
+    const double need = parts * fixed + (double)bk[b].per_sample * bk[b].members.size();
+    const double share = need_tot > budget && together ? budget * need / need_tot : budget;
+    if (share < (double)bk[b].per1) together = false;
+    bk[b].wave = (int64_t)std::max(1.0, std::floor((share - parts * fixed) / (double)bk[b].per_sample));
+    bk[b].wave = std::min<int64_t>(bk[b].wave, (int64_t)bk[b].members.size());
+  }
+  if (!together)   // one after another, each with the whole budget
+    for (size_t b = 0; b < ks.size(); ++b) {
+      const double fixed = std::max(0.0, (double)bk[b].per1 - (double)bk[b].per_sample);
+      bk[b].wave = (int64_t)std::max(1.0, std::floor((budget - parts * fixed) / (double)bk[b].per_sample));
+      bk[b].wave = std::min<int64_t>(bk[b].wave, (int64_t)bk[b].members.size());
+    }
+  // streams of the buckets after the first (which uses the caller's)
+  std::vector<hipStream_t> bst(ks.size(), st);
+  hipEvent_t ready = nullptr;
+  int brc = MCTRG_OK;
+  auto cleanup = [&]() {
+    for (size_t b = 1; b < bst.size(); ++b)
+      if (bst[b] != st) (void)hipStreamDestroy(bst[b]);
+    if (ready) (void)hipEventDestroy(ready);
+  };
+  if (together) {
+    if (hipEventCreateWithFlags(&ready, hipEventDisableTiming) != hipSuccess) return MCTRG_EDEVICE;
+    for (size_t b = 1; b < ks.size(); ++b)
+      if (hipStreamCreateWithFlags(&bst[b], hipStreamNonBlocking) != hipSuccess) { bst[b] = st; cleanup(); return MCTRG_EDEVICE; }
+  }
+  // one wave of bucket b: samples members[w0, w1)
+  auto run_wave = [&](size_t b, size_t w0, ChainParts& cp) -> int {
     const int kb = ks[b];
     Chain& probe = probes[b];
-    std::vector<int64_t> members;
-    for (int64_t i = 0; i < n_samples; ++i)
-      if ((k_of_sample ? k_of_sample[i] : cfg->k) == kb) members.push_back(i);
-    // wave size from the workspace budget
-    probe.nsamp = 1;
-    const size_t per1 = chain_bytes(probe);
-    probe.nsamp = 2;
-    const size_t per_sample = std::max<size_t>(1, chain_bytes(probe) - per1);
-    // a wave of two or more samples runs as up to kParts parts, each with its own
-    // per-chain (sample-independent) allocations
-    const double fixed = std::max(0.0, (double)per1 - (double)per_sample);
-    const int parts = (cfg->flags & MCTRG_ONE_STREAM) ? 1 : kParts;
-    int64_t wave = (int64_t)std::max(1.0, std::floor((budget - parts * fixed) / (double)per_sample));
-    wave = std::min<int64_t>(wave, (int64_t)members.size());
-    for (size_t w0 = 0; w0 < members.size(); w0 += (size_t)wave) {
-      const size_t w1 = std::min(members.size(), w0 + (size_t)wave);
-      const int64_t nw = (int64_t)(w1 - w0);
-      std::vector<int32_t> groups(nw);
-      std::vector<int64_t> out_index(nw), sids(nw);
-      for (int64_t s = 0; s < nw; ++s) {
-        const int64_t i = members[w0 + s];
-        groups[s] = group_of_sample ? group_of_sample[i] : 0;
-        out_index[s] = i;
-        sids[s] = cfg->sample_offset + i;
+    const size_t w1 = std::min(bk[b].members.size(), w0 + (size_t)bk[b].wave);
+    const int64_t nw = (int64_t)(w1 - w0);
+    std::vector<int32_t> groups(nw);
+    std::vector<int64_t> out_index(nw), sids(nw);
+    for (int64_t s = 0; s < nw; ++s) {
+      const int64_t i = bk[b].members[w0 + s];
+      groups[s] = group_of_sample ? group_of_sample[i] : 0;
+      out_index[s] = i;
+      sids[s] = cfg->sample_offset + i;
+    }
+    auto configure = [&](Chain& c) {
+      c.mode = cfg->mode; c.dtype = cfg->contract_dtype; c.k = kb; c.n_steps = cfg->n_steps;
+      c.tau = cfg->tau_null; c.seed = cfg->seed; c.flags = cfg->flags; c.record = cfg->record_buf;
+      c.kmax_rec = cfg->k;
+      c.n_det = cfg->n_det;
+      c.dec = cfg->decomposition;
+      c.Dsched = probe.Dsched;
+      c.levels = probe.levels;
+      c.plaqs = probe.plaqs;
+      c.fail_sid = fail_sid;
+    };
+    int r = parts_start(cp, configure, ts, groups, out_index, sids, bst[b], (cfg->flags & MCTRG_ONE_STREAM) != 0,
+                        false);
+    if (r != MCTRG_OK) return r;
+    r = parts_step(cp, cfg->n_steps);
+    if (r != MCTRG_OK) return r;
+    return parts_finish(cp, out_sign, out_ln_abs_Z, out_ln_c, cfg->out_tensor);
+  };
+  auto check_signs = [&](ChainParts& cp) -> int {
+    for (auto& c : cp.parts) {
+      std::vector<int8_t> sg(c->nsamp);
+      if (hipMemcpy(sg.data(), c->sign, c->nsamp, hipMemcpyDeviceToHost) != hipSuccess) return MCTRG_EDEVICE;
+      for (int8_t v : sg)
+        if (v == 0) any_fail = true;
+    }
+    return MCTRG_OK;
+  };
+  if (!together) {
+    for (size_t b = 0; b < ks.size() && brc == MCTRG_OK; ++b)
+      for (size_t w0 = 0; w0 < bk[b].members.size() && brc == MCTRG_OK; w0 += (size_t)bk[b].wave) {
+        ChainParts cp;
+        brc = run_wave(b, w0, cp);
+        if (brc == MCTRG_OK && hipStreamSynchronize(st) != hipSuccess) brc = MCTRG_EDEVICE;
+        if (brc == MCTRG_OK) brc = check_signs(cp);
       }
-      auto configure = [&](Chain& c) {
-        c.mode = cfg->mode; c.dtype = cfg->contract_dtype; c.k = kb; c.n_steps = cfg->n_steps;
-        c.tau = cfg->tau_null; c.seed = cfg->seed; c.flags = cfg->flags; c.record = cfg->record_buf;
-        c.kmax_rec = cfg->k;
-        c.n_det = cfg->n_det;
-        c.dec = cfg->decomposition;
-        c.Dsched = probe.Dsched;
-        c.levels = probe.levels;
-        c.plaqs = probe.plaqs;
-        c.fail_sid = fail_sid;
-      };
-      ChainParts cp;
-      rc = parts_start(cp, configure, ts, groups, out_index, sids, st, (cfg->flags & MCTRG_ONE_STREAM) != 0,
-                       false);
-      if (rc != MCTRG_OK) return rc;
-      rc = parts_step(cp, cfg->n_steps);
-      if (rc != MCTRG_OK) return rc;
-      rc = parts_finish(cp, out_sign, out_ln_abs_Z, out_ln_c, cfg->out_tensor);
-      if (rc != MCTRG_OK) return rc;
-      if (hipStreamSynchronize(st) != hipSuccess) return MCTRG_EDEVICE;
-      for (auto& c : cp.parts) {
-        std::vector<int8_t> sg(c->nsamp);
-        if (hipMemcpy(sg.data(), c->sign, c->nsamp, hipMemcpyDeviceToHost) != hipSuccess) return MCTRG_EDEVICE;
-        for (int8_t v : sg)
-          if (v == 0) any_fail = true;
+    cleanup();
+    if (brc != MCTRG_OK) return brc;
+    return any_fail ? MCTRG_ENUMERIC : MCTRG_OK;
+  }
+  size_t rounds = 0;
+  for (const Bucket& x : bk) rounds = std::max(rounds, (x.members.size() + x.wave - 1) / x.wave);
+  for (size_t w = 0; w < rounds && brc == MCTRG_OK; ++w) {
+    // the buckets' streams start after the work already queued on the caller's
+    if (hipEventRecord(ready, st) != hipSuccess) { brc = MCTRG_EDEVICE; break; }
+    for (size_t b = 1; b < ks.size(); ++b)
+      if (hipStreamWaitEvent(bst[b], ready, 0) != hipSuccess) brc = MCTRG_EDEVICE;
+    std::vector<ChainParts> cps(ks.size());
+    std::vector<int> rcs(ks.size(), MCTRG_OK);
+    std::vector<std::thread> th;
+    auto go = [&](size_t b) {
+      try {
+        if (hipSetDevice(dev) != hipSuccess) { rcs[b] = MCTRG_EDEVICE; return; }
+        const size_t w0 = w * (size_t)bk[b].wave;
+        if (w0 < bk[b].members.size()) rcs[b] = run_wave(b, w0, cps[b]);
+      } catch (...) {
+        rcs[b] = MCTRG_ENOMEM;
+      }
+    };
+    for (size_t b = 1; b < ks.size() && brc == MCTRG_OK; ++b) {
+      try {
+        th.emplace_back(go, b);
+      } catch (...) {
+        go(b);
       }
     }
+    if (brc == MCTRG_OK) go(0);
+    for (auto& t : th) t.join();
+    for (size_t b = 0; b < ks.size(); ++b)
+      if (rcs[b] != MCTRG_OK && brc == MCTRG_OK) brc = rcs[b];
+    // the caller's stream waits for every bucket
+    for (size_t b = 1; b < ks.size() && brc == MCTRG_OK; ++b) {
+      if (hipEventRecord(ready, bst[b]) != hipSuccess || hipStreamWaitEvent(st, ready, 0) != hipSuccess)
+        brc = MCTRG_EDEVICE;
+    }
+    if (brc == MCTRG_OK && hipStreamSynchronize(st) != hipSuccess) brc = MCTRG_EDEVICE;
+    for (size_t b = 0; b < ks.size() && brc == MCTRG_OK; ++b)
+      if (!cps[b].parts.empty()) brc = check_signs(cps[b]);
   }
+  cleanup();
+  if (brc != MCTRG_OK) return brc;
   return any_fail ? MCTRG_ENUMERIC : MCTRG_OK;
 }
 

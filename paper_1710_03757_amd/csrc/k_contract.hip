@@ -13,6 +13,11 @@
 // Narrow operands are scaled per (tensor, operand) by a power of two so
 // that max|x| < 2^target (1 for BF16/F32, 256 for e4m3) before rounding;
 // the normalisation step divides the scales back out.
+#include <cstdlib>
+#include <map>
+#include <mutex>
+#include <tuple>
+
 #include "mctrg_internal.h"
 #include "../../include/mctrg.h"
 
@@ -189,19 +194,20 @@ __device__ __forceinline__ typename Mma<DT>::frag_c mma_step(const typename Mma<
   }
 }
 
-// Tile shapes: the 32-, 16- and 8-bit forms use 128 x 128 workgroup tiles
-// (each wave a 64 x 64 block of 4 x 4 MFMA tiles), FP64 uses 64 x 64 (each
-// wave 32 x 32) to keep its LDS footprint at 17 KB per operand.
-template <int DT> struct Tile { static constexpr int BM = 128, WT = 4; };
-template <> struct Tile<MCTRG_F64> { static constexpr int BM = 64, WT = 2; };
+// Tile shapes (template parameter BM, picked per dtype and GEMM shape by the
+// autotuner in launch_contract): BM x BM workgroup tiles of four waves, each
+// wave a (BM/2) x (BM/2) block of WT x WT MFMA 16 x 16 tiles, WT = BM / 32.
+// BM = 128 halves the operand loads per flop of BM = 64 at four times the
+// accumulator registers (FP64: 128 VGPRs) and twice the LDS (FP64: 67 KB,
+// two workgroups per CU).
 
-template <int DT>
+template <int DT, int BM>
 __global__ __launch_bounds__(256) void gemm_tn_kernel(int M, int N, int K, const void* __restrict__ Av,
                                                       const void* __restrict__ Bv, void* __restrict__ Cv) {
   typedef typename Mma<DT>::elt elt;
   typedef typename Mma<DT>::acc_t acc_t;
   typedef typename Mma<DT>::frag_c frag_c;
-  constexpr int BM = Tile<DT>::BM, WT = Tile<DT>::WT;     // workgroup tile, MFMA tiles per wave side
+  constexpr int WT = BM / 32;                              // MFMA tiles per wave side
   constexpr int BK = 32, LD = BK + Mma<DT>::PAD, KS = Mma<DT>::KSTEP;
   constexpr int EPL = (KS == 4) ? 1 : 8;                  // elements per lane per MFMA
   constexpr int LOADS = BM * BK / 256;                    // elements per thread per operand and K tile
@@ -227,7 +233,7 @@ __global__ __launch_bounds__(256) void gemm_tn_kernel(int M, int N, int K, const
   constexpr int VB = 16 / (int)sizeof(elt);   // elements per 16-byte vector
   constexpr int LPR = BK / VB;                // lanes per tile row
   constexpr int RPI = 256 / LPR;              // tile rows per pass
-  constexpr int ITERS = BM / RPI;
+  constexpr int ITERS = (BM + RPI - 1) / RPI;  // (8-bit, BM = 64: one pass over half the threads)
   const bool vec = (M % BM == 0) && (N % BM == 0) && (K % BK == 0);
   const int vrow = tid / LPR, vk = (tid % LPR) * VB;
   uint4 va[ITERS], vb[ITERS];
@@ -239,6 +245,7 @@ __global__ __launch_bounds__(256) void gemm_tn_kernel(int M, int N, int K, const
 #pragma unroll
       for (int it = 0; it < ITERS; ++it) {
         const int row = it * RPI + vrow;
+        if (RPI * ITERS > BM && row >= BM) continue;
         va[it] = *reinterpret_cast<const uint4*>(A + (size_t)(m0 + row) * K + k0 + vk);
         vb[it] = *reinterpret_cast<const uint4*>(B + (size_t)(n0 + row) * K + k0 + vk);
       }
@@ -257,6 +264,7 @@ __global__ __launch_bounds__(256) void gemm_tn_kernel(int M, int N, int K, const
 #pragma unroll
       for (int it = 0; it < ITERS; ++it) {
         const int row = it * RPI + vrow;
+        if (RPI * ITERS > BM && row >= BM) continue;
         const elt* ea = reinterpret_cast<const elt*>(&va[it]);
         const elt* eb = reinterpret_cast<const elt*>(&vb[it]);
 #pragma unroll
@@ -328,8 +336,116 @@ hipError_t launch_unscale(int64_t nout, int64_t elems, int src_is_f32, const voi
   return hipGetLastError();
 }
 
-static size_t elt_bytes(int dt) {
-  return dt == MCTRG_F64 ? 8 : dt == MCTRG_F32 ? 4 : dt == MCTRG_BF16 ? 2 : 1;
+// ---------------------------------------------------------------------------
+// Tile autotuner: the first GEMM of a (dtype, M, N, K, batch) shape on a
+// device times both tile shapes on the call's own operands (best of three
+// launches each, HIP events on the call's stream) and keeps the faster for
+// every later call of that shape.  The environment variable MCTRG_GEMM_TILE
+// (64 or 128) forces a shape (used by the tests to check both).
+// ---------------------------------------------------------------------------
+namespace {
+struct TuneKey {
+  int dev, dt, M, N, K;
+  int64_t batch;
+  bool operator<(const TuneKey& o) const {
+    return std::tie(dev, dt, M, N, K, batch) < std::tie(o.dev, o.dt, o.M, o.N, o.K, o.batch);
+  }
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, int> g_tune;
+
+template <int DT, int BM>
+hipError_t launch_gemm_bm(int M, int N, int K, int64_t nout, const void* A, const void* B, void* C,
+                          hipStream_t stream) {
+  dim3 grid(ceil_div(N, BM), ceil_div(M, BM), (unsigned)nout);
+  hipLaunchKernelGGL((gemm_tn_kernel<DT, BM>), grid, dim3(256), 0, stream, M, N, K, A, B, C);
+  return hipGetLastError();
+}
+
+template <int DT>
+hipError_t launch_gemm_tile(int bm, int M, int N, int K, int64_t nout, const void* A, const void* B, void* C,
+                            hipStream_t stream) {
+  return bm == 128 ? launch_gemm_bm<DT, 128>(M, N, K, nout, A, B, C, stream)
+                   : launch_gemm_bm<DT, 64>(M, N, K, nout, A, B, C, stream);
+}
+
+hipError_t launch_gemm_dt(int dt, int bm, int M, int N, int K, int64_t nout, const void* A, const void* B, void* C,
+                          hipStream_t stream) {
+  switch (dt) {
+    case MCTRG_F64: return launch_gemm_tile<MCTRG_F64>(bm, M, N, K, nout, A, B, C, stream);
+    case MCTRG_F32: return launch_gemm_tile<MCTRG_F32>(bm, M, N, K, nout, A, B, C, stream);
+    case MCTRG_BF16: return launch_gemm_tile<MCTRG_BF16>(bm, M, N, K, nout, A, B, C, stream);
+    case MCTRG_FP8_E4M3: return launch_gemm_tile<MCTRG_FP8_E4M3>(bm, M, N, K, nout, A, B, C, stream);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+// The tile shape for this GEMM: forced, cached, or measured now.
+hipError_t pick_tile(int dt, int M, int N, int K, int64_t nout, const void* A, const void* B, void* C,
+                     hipStream_t stream, int* bm) {
+  if (const char* f = std::getenv("MCTRG_GEMM_TILE")) {
+    const int v = std::atoi(f);
+    if (v == 64 || v == 128) { *bm = v; return hipSuccess; }
+  }
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  const TuneKey key{dev, dt, M, N, K, nout};
+  {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    auto it = g_tune.find(key);
+    if (it != g_tune.end()) { *bm = it->second; return hipSuccess; }
+  }
+  // below one tile of 128 in either dimension the small tile always wins
+  if (M < 128 || N < 128) {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    g_tune[key] = 64;
+    *bm = 64;
+    return hipSuccess;
+  }
+  hipEvent_t ev[2];
+  if ((e = hipEventCreate(&ev[0])) != hipSuccess) return e;
+  if ((e = hipEventCreate(&ev[1])) != hipSuccess) { (void)hipEventDestroy(ev[0]); return e; }
+  float best_ms[2] = {1e30f, 1e30f};
+  const int shapes[2] = {64, 128};
+  for (int rep = 0; rep < 3 && e == hipSuccess; ++rep)
+    for (int t = 0; t < 2 && e == hipSuccess; ++t) {
+      e = hipEventRecord(ev[0], stream);
+      if (e == hipSuccess) e = launch_gemm_dt(dt, shapes[t], M, N, K, nout, A, B, C, stream);
+      if (e == hipSuccess) e = hipEventRecord(ev[1], stream);
+      if (e == hipSuccess) e = hipEventSynchronize(ev[1]);
+      float ms = 0.0f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev[0], ev[1]);
+      if (e == hipSuccess) best_ms[t] = std::min(best_ms[t], ms);
+    }
+  (void)hipEventDestroy(ev[0]);
+  (void)hipEventDestroy(ev[1]);
+  if (e != hipSuccess) return e;
+  *bm = best_ms[1] < best_ms[0] ? 128 : 64;
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  g_tune[key] = *bm;
+  return hipSuccess;
+}
+}  // namespace
+
+int gemm_tile_chosen(int dt, int M, int N, int K, int64_t nout) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  auto it = g_tune.find(TuneKey{dev, dt, M, N, K, nout});
+  return it == g_tune.end() ? 0 : it->second;
+}
+
+static hipError_t run_gemm(int dt, int M, int N, int K, int64_t nout, const void* A, const void* B, void* C,
+                           hipStream_t stream, KernelTimer* gt) {
+  int bm = 64;
+  hipError_t e = pick_tile(dt, M, N, K, nout, A, B, C, stream, &bm);
+  if (e != hipSuccess) return e;
+  if (gt) { e = gt->begin(stream); if (e != hipSuccess) return e; }
+  e = launch_gemm_dt(dt, bm, M, N, K, nout, A, B, C, stream);
+  if (e != hipSuccess) return e;
+  if (gt) { e = gt->end(stream); if (e != hipSuccess) return e; }
+  return hipSuccess;
 }
 
 hipError_t launch_contract(const ContractArgs& a, hipStream_t stream, KernelTimer* gt) {
@@ -342,25 +458,19 @@ hipError_t launch_contract(const ContractArgs& a, hipStream_t stream, KernelTime
   hipLaunchKernelGGL(contract_Y_kernel, dim3(kk, (unsigned)a.nout), dim3(256), sh, stream, D, kk, kcap, a.FA,
                      a.FB, a.f_stride, a.jobs, a.Y);
   const int64_t per = (int64_t)MM * DD;
-  dim3 gg(ceil_div(MM, 64), ceil_div(MM, 64), (unsigned)a.nout);        // FP64 tiles
-  dim3 gn(ceil_div(MM, 128), ceil_div(MM, 128), (unsigned)a.nout);      // narrow tiles
   if (a.dtype == MCTRG_F64) {
     hipLaunchKernelGGL(fill_kernel, dim3(ceil_div(2 * a.nout, 256)), dim3(256), 0, stream, 2 * a.nout, a.scales, 1.0);
-    if (gt) gt->begin(stream);
-    hipLaunchKernelGGL(gemm_tn_kernel<MCTRG_F64>, gg, dim3(256), 0, stream, MM, MM, DD, (const void*)a.X,
-                       (const void*)a.Y, a.Tout);
-    if (gt) gt->end(stream);
+    hipError_t e = run_gemm(MCTRG_F64, MM, MM, DD, a.nout, a.X, a.Y, a.Tout, stream, gt);
+    if (e != hipSuccess) return e;
     return hipGetLastError();
   }
-  // scales: [o*2 + 0] for X, [o*2 + 1] for Yt
+  // scales: the first nout entries for X, the next nout for Yt
   const int target = (a.dtype == MCTRG_FP8_E4M3) ? 8 : 0;
   hipLaunchKernelGGL(fill_kernel, dim3(ceil_div(2 * a.nout, 256)), dim3(256), 0, stream, 2 * a.nout, a.scales, 0.0);
   int gx = (int)((per + 255) / 256);
   if (gx > 256) gx = 256;
-  // absmax writes to scales[o] with a stride of one tensor: run per operand
-  // into a contiguous view (X -> even slots, Yt -> odd slots) via two passes.
-  double* mxX = a.scales;            // first nout entries
-  double* mxY = a.scales + a.nout;   // next nout entries
+  double* mxX = a.scales;
+  double* mxY = a.scales + a.nout;
   hipLaunchKernelGGL(absmax_kernel, dim3(gx, (unsigned)a.nout), dim3(256), 0, stream, per, a.X, mxX);
   hipLaunchKernelGGL(absmax_kernel, dim3(gx, (unsigned)a.nout), dim3(256), 0, stream, per, a.Y, mxY);
   hipLaunchKernelGGL(make_scale_kernel, dim3(ceil_div(2 * a.nout, 256)), dim3(256), 0, stream, 2 * a.nout,
@@ -369,31 +479,20 @@ hipError_t launch_contract(const ContractArgs& a, hipStream_t stream, KernelTime
     case MCTRG_F32:
       hipLaunchKernelGGL(cast_kernel<MCTRG_F32>, dim3(gx, (unsigned)a.nout), dim3(256), 0, stream, per, a.X, mxX, a.Xlp);
       hipLaunchKernelGGL(cast_kernel<MCTRG_F32>, dim3(gx, (unsigned)a.nout), dim3(256), 0, stream, per, a.Y, mxY, a.Ylp);
-      if (gt) gt->begin(stream);
-      hipLaunchKernelGGL(gemm_tn_kernel<MCTRG_F32>, gn, dim3(256), 0, stream, MM, MM, DD, (const void*)a.Xlp,
-                         (const void*)a.Ylp, a.Tout);
-      if (gt) gt->end(stream);
       break;
     case MCTRG_BF16:
       hipLaunchKernelGGL(cast_kernel<MCTRG_BF16>, dim3(gx, (unsigned)a.nout), dim3(256), 0, stream, per, a.X, mxX, a.Xlp);
       hipLaunchKernelGGL(cast_kernel<MCTRG_BF16>, dim3(gx, (unsigned)a.nout), dim3(256), 0, stream, per, a.Y, mxY, a.Ylp);
-      if (gt) gt->begin(stream);
-      hipLaunchKernelGGL(gemm_tn_kernel<MCTRG_BF16>, gn, dim3(256), 0, stream, MM, MM, DD, (const void*)a.Xlp,
-                         (const void*)a.Ylp, a.Tout);
-      if (gt) gt->end(stream);
       break;
     case MCTRG_FP8_E4M3:
       hipLaunchKernelGGL(cast_kernel<MCTRG_FP8_E4M3>, dim3(gx, (unsigned)a.nout), dim3(256), 0, stream, per, a.X, mxX, a.Xlp);
       hipLaunchKernelGGL(cast_kernel<MCTRG_FP8_E4M3>, dim3(gx, (unsigned)a.nout), dim3(256), 0, stream, per, a.Y, mxY, a.Ylp);
-      if (gt) gt->begin(stream);
-      hipLaunchKernelGGL(gemm_tn_kernel<MCTRG_FP8_E4M3>, gn, dim3(256), 0, stream, MM, MM, DD, (const void*)a.Xlp,
-                         (const void*)a.Ylp, a.Tout);
-      if (gt) gt->end(stream);
       break;
     default:
       return hipErrorInvalidValue;
   }
-  (void)elt_bytes;
+  hipError_t e = run_gemm(a.dtype, MM, MM, DD, a.nout, a.Xlp, a.Ylp, a.Tout, stream, gt);
+  if (e != hipSuccess) return e;
   return hipGetLastError();
 }
 

@@ -303,6 +303,9 @@ struct ContractArgs {
   void* Tout;              // nout * kk^4, FP64 (dtype F64) or FP32 (others)
 };
 hipError_t launch_contract(const ContractArgs& a, hipStream_t stream, KernelTimer* gemm_timer = nullptr);
+// The GEMM tile shape (64 or 128) the autotuner chose for this shape on the
+// current device, 0 if none yet.
+int gemm_tile_chosen(int dt, int M, int N, int K, int64_t nout);
 
 // T_out = C / (scale_X * scale_Y) in FP64 (C FP64 or FP32).
 hipError_t launch_unscale(int64_t nout, int64_t elems, int src_is_f32, const void* C, const double* scales,

@@ -269,3 +269,24 @@ def test_chain_parts_profile():
     assert torch.equal(r.sign, r1.sign) and torch.equal(r.ln_abs_Z, r1.ln_abs_Z)
     ch.close()
     one.close()
+
+
+def test_mixed_k_buckets_run_concurrently_with_unchanged_results():
+    """Samples of different k run as concurrent buckets; every sample must be
+    the sample that a call with only that sample gives (draws are addressed
+    by the global sample id, each bucket has its own workspace): the same
+    kept sets, ln c and ln|Z~| per site to rounding (the decomposition's
+    per-part decisions make the rounding depend on the part's other samples)."""
+    torch, m = need_gpu()
+    log("mixed k buckets")
+    ts = m.init_tensor("site", [0.41, 0.46], [0.0, 0.03])
+    ks = [8, 12, 8, 16, 12, 16, 8]
+    groups = [0, 1, 1, 0, 0, 1, 0]
+    a = m.run_samples(ts, len(ks), n_steps=7, k=16, ks=ks, groups=groups, seed=4, want_ln_c=True, record=True)
+    la, lca, ra = a.ln_abs_Z.cpu().numpy(), a.ln_c.cpu().numpy(), a.record.cpu().numpy()
+    for i, (k, g) in enumerate(zip(ks, groups)):
+        b = m.run_samples(ts, 1, n_steps=7, k=16, ks=[k], groups=[g], seed=4, sample_offset=i, want_ln_c=True,
+                          record=True)
+        assert np.array_equal(ra[i], b.record.cpu().numpy()[0]), i
+        assert abs(la[i] - b.ln_abs_Z.cpu().numpy()[0]) / 128 < 1e-13, i
+        assert np.allclose(lca[i], b.ln_c.cpu().numpy()[0], rtol=0, atol=1e-12), i

@@ -109,11 +109,16 @@ def test_sampler_matches_oracle(k, mode):
 
 
 @pytest.mark.parametrize("D,kk,nj", [(2, 2, 3), (4, 4, 2), (4, 8, 2), (8, 8, 3), (8, 16, 2), (16, 16, 2),
-                                     (6, 5, 2)])
+                                     (6, 5, 2), (12, 12, 1)])
 @pytest.mark.parametrize("dtype,tol", [("f64", 1e-13), ("f32", 2e-5), ("bf16", 4e-2), ("fp8", 0.25)])
-def test_contract_matches_oracle(D, kk, nj, dtype, tol):
+@pytest.mark.parametrize("tile", ["64", "128", "auto"])
+def test_contract_matches_oracle(D, kk, nj, dtype, tol, tile, monkeypatch):
+    """Both GEMM tile shapes (forced through the MCTRG_GEMM_TILE hook) and
+    the autotuner's choice; shapes with and without whole 128 tiles."""
     torch, m = need_gpu()
-    log(f"contract D={D} kk={kk} nj={nj} {dtype}")
+    if tile != "auto":
+        monkeypatch.setenv("MCTRG_GEMM_TILE", tile)
+    log(f"contract D={D} kk={kk} nj={nj} {dtype} tile {tile}")
     rng = np.random.default_rng(D * 1000 + kk)
     GA = rng.standard_normal((nj, kk, D, D))
     GB = rng.standard_normal((nj, kk, D, D))
