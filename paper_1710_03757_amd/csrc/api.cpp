@@ -286,7 +286,7 @@ void layout(Chain& c, Arena& ar) {
   c.jw.active = ar.take<int>(jmax);
   c.jw.rotated = ar.take<int>(jmax);
   c.jw.sweeps = ar.take<int>(jmax);
-  c.jw.counter = ar.take<int>(2);
+  c.jw.counter = ar.take<int>(2 * kMaxSweeps);
   c.jw.lastmod = ar.take<int>((size_t)jmax * kJacobiMaxBlocks);
   c.jw.lastchk = ar.take<int>((size_t)jmax * kJacobiMaxBlocks * kJacobiMaxBlocks);
   c.nb_job = ar.take<int>(jmax);
@@ -354,7 +354,7 @@ int chain_start(Chain& c, const mctrg_tensor_set* ts, const std::vector<int32_t>
   ar.counting = false;
   layout(c, ar);
   const int64_t J = c.max_jobs, O = c.max_out;
-  const size_t hb = sizeof(int32_t) * (2 * J + 4 * O) + sizeof(uint64_t) * 3 * J + 2 * sizeof(int) + 64;
+  const size_t hb = sizeof(int32_t) * (2 * J + 4 * O) + sizeof(uint64_t) * 3 * J + 2 * kMaxSweeps * sizeof(int) + 64;
   if (hipHostMalloc(&c.pin.p, hb, hipHostMallocDefault) != hipSuccess) return MCTRG_ENOMEM;
   char* hp = reinterpret_cast<char*>(c.pin.p);
   c.h_rng = reinterpret_cast<uint64_t*>(hp);
@@ -366,6 +366,7 @@ int chain_start(Chain& c, const mctrg_tensor_set* ts, const std::vector<int32_t>
   c.h_cjobs = reinterpret_cast<int32_t*>(hp);
   hp += sizeof(int32_t) * 4 * O;
   c.jw.counter_host = reinterpret_cast<int*>(hp);
+  c.jw.hist_len = kMaxSweeps;
 
   // groups -> device (staged through the cjobs area, int32 per sample)
   int32_t* dgroups = c.cjobs;  // reused before the first step
@@ -514,8 +515,11 @@ int chain_step(Chain& c) {
     CKH(run_deflate(nj, sh.n_pad, c.tau, rows, Wj, c.nb_job, c.dnrm, c.dpos, c.jw.counter, c.jw.counter_host, &nb_max,
                     c.st));
   if (!qr_basis)
+    // the first sweeps run without host round trips: as many as the previous
+    // step needed, less two (a sweep after convergence only launches idle
+    // workgroups)
     CKH(run_jacobi(nj, sh.n_pad, Wj, c.jw, kMaxSweeps, c.st, c.tj.enabled ? &c.tj : nullptr, &c.last_sweeps, c.nb_job,
-                   nb_max, c.sweep_hist, jcols));
+                   nb_max, c.sweep_hist, jcols, c.last_sweeps - 2));
   if (s < 64) c.step_sweeps[s] = c.last_sweeps;
   if (!qr_basis) {
     int64_t rp = 0;

@@ -690,17 +690,29 @@ hipError_t KernelTimer::collect() {
   return hipSuccess;
 }
 
+__global__ void zero_ints_kernel(int n, int* p) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0;
+}
+
 hipError_t run_jacobi(int64_t njobs, int n_pad, double* W, const JacobiWork& wk, int max_sweeps,
                       hipStream_t stream, KernelTimer* timer, int* sweeps_done, const int* nb_job, int nb_max,
-                      int* history, int ncol) {
+                      int* history, int ncol, int blind) {
   if (ncol <= 0 || ncol > n_pad || ncol % 64) ncol = n_pad;
   if (njobs == 0) return hipSuccess;
   const int brows = jacobi_block_rows(n_pad);
   const int nb = nb_job ? nb_max : n_pad / brows;
   const double tol = fmax(32.0, 8.0 * sqrt((double)n_pad)) * 0x1.0p-53;
+  // per-sweep counters (jobs still rotating, block pairs rotated) in their own
+  // slots when the work area has room for every sweep: the first `blind`
+  // sweeps then run without waiting for the host (a sweep of converged jobs
+  // leaves every workgroup idle), and one copy brings all their counters back
+  const bool slots = wk.hist_len >= max_sweeps;
+  if (!slots) blind = 0;
+  blind = blind < 0 ? 0 : (blind > max_sweeps ? max_sweeps : blind);
   int g = ceil_div(njobs, 256);
   hipLaunchKernelGGL(jacobi_init_kernel, dim3(g), dim3(256), 0, stream, njobs, wk.active, wk.rotated,
                      wk.sweeps);
+  if (slots) hipLaunchKernelGGL(zero_ints_kernel, dim3(1), dim3(256), 0, stream, 2 * max_sweeps, wk.counter);
   if (wk.lastmod && brows == 32) {
     hipError_t e = hipMemsetAsync(wk.lastmod, 0, sizeof(int) * njobs * kJacobiMaxBlocks, stream);
     if (e == hipSuccess)
@@ -708,21 +720,25 @@ hipError_t run_jacobi(int64_t njobs, int n_pad, double* W, const JacobiWork& wk,
     if (e != hipSuccess) return e;
   }
   for (int sweep = 0; sweep < max_sweeps; ++sweep) {
-    hipLaunchKernelGGL(zero_int_kernel, dim3(1), dim3(2), 0, stream, wk.counter);
+    int* cnt = slots ? wk.counter + 2 * sweep : wk.counter;
+    if (!slots) hipLaunchKernelGGL(zero_int_kernel, dim3(1), dim3(2), 0, stream, wk.counter);
     for (int r = 0; r < nb - 1; ++r) {
       if (timer) { hipError_t e = timer->begin(stream); if (e != hipSuccess) return e; }
       if (brows == 32)
         hipLaunchKernelGGL(jacobi_round64_kernel, dim3(nb / 2, (unsigned)njobs), dim3(256), 0, stream, W,
-                           n_pad, ncol, nb, nb_job, r, wk.active, wk.rotated, wk.counter + 1, tol, wk.lastmod, wk.lastchk,
+                           n_pad, ncol, nb, nb_job, r, wk.active, wk.rotated, cnt + 1, tol, wk.lastmod, wk.lastchk,
                            1 + sweep * (nb - 1) + r);
       else
         hipLaunchKernelGGL(jacobi_round_kernel, dim3(nb / 2, (unsigned)njobs), dim3(256), 0, stream, W,
-                           n_pad, nb, nb_job, r, wk.active, wk.rotated, wk.counter + 1, tol);
+                           n_pad, nb, nb_job, r, wk.active, wk.rotated, cnt + 1, tol);
       if (timer) { hipError_t e = timer->end(stream); if (e != hipSuccess) return e; }
     }
     hipLaunchKernelGGL(jacobi_sweep_end_kernel, dim3(g), dim3(256), 0, stream, njobs, sweep, wk.active,
-                       wk.rotated, wk.sweeps, wk.counter);
-    hipError_t e = hipMemcpyAsync(wk.counter_host, wk.counter, 2 * sizeof(int), hipMemcpyDeviceToHost, stream);
+                       wk.rotated, wk.sweeps, cnt);
+    if (sweep + 1 < blind) continue;   // no host round trip yet
+    const int nslot = slots ? sweep + 1 : 1;      // counter slots to bring back
+    hipError_t e = hipMemcpyAsync(wk.counter_host, wk.counter, 2 * nslot * sizeof(int), hipMemcpyDeviceToHost,
+                                  stream);
     if (e != hipSuccess) return e;
     e = hipStreamSynchronize(stream);
     if (e != hipSuccess) return e;
@@ -730,9 +746,15 @@ hipError_t run_jacobi(int64_t njobs, int n_pad, double* W, const JacobiWork& wk,
       e = timer->collect();
       if (e != hipSuccess) return e;
     }
-    if (sweeps_done) *sweeps_done = sweep + 1;
-    if (history) { history[2 * sweep] = wk.counter_host[1]; history[2 * sweep + 1] = wk.counter_host[0]; }
-    if (*wk.counter_host == 0) break;
+    // the sweeps covered by this copy, up to the first after which no job rotated
+    int last = sweep;
+    for (int s = (slots ? 0 : sweep); s <= sweep; ++s) {
+      const int* h = wk.counter_host + 2 * (slots ? s : 0);
+      if (history) { history[2 * s] = h[1]; history[2 * s + 1] = h[0]; }
+      if (h[0] == 0) { last = s; break; }
+    }
+    if (sweeps_done) *sweeps_done = last + 1;
+    if (wk.counter_host[2 * (slots ? last : 0)] == 0) break;
   }
   return hipGetLastError();
 }

@@ -117,14 +117,15 @@ struct JacobiWork {
   int* active;      // njobs
   int* rotated;     // njobs
   int* sweeps;      // njobs (-1 until converged)
-  int* counter;      // device 2 ints: jobs still rotating, block pairs rotated in the sweep
-  int* counter_host; // pinned host 2 ints
+  int* counter;      // device 2 ints per slot: jobs still rotating, block pairs rotated in the sweep
+  int* counter_host; // pinned host, as many ints as counter
   // optional (64-row pairs): per job and 32-row block, the round stamp of its
   // last rotation (kJacobiMaxBlocks ints), and per block pair the stamp at
   // which it was last found orthogonal (kJacobiMaxBlocks^2 ints); a pair
   // whose blocks have not changed since then is skipped without reading it
   int* lastmod = nullptr;
   int* lastchk = nullptr;
+  int hist_len = 1;   // counter slots (pairs of ints) in counter / counter_host
 };
 constexpr int kJacobiMaxBlocks = 128;   // n_pad / 32 for n_pad <= 4096
 // Three approximations of the decomposition drop parts of the matrix below
@@ -137,13 +138,16 @@ constexpr int kJacobiMaxBlocks = 128;   // n_pad / 32 for n_pad <= 4096
 // transforms of the dropped parts), a tenth of the cut.
 inline double approx_budget(double tau_null) { return fmax(0x1.0p-48, 0.1 * tau_null) / 3.0; }
 // history (optional, host, max_sweeps x 2): per sweep, the block pairs that
-// rotated (summed over jobs) and the jobs still rotating after it.  ncol
+// rotated (summed over jobs) and the jobs still rotating after it.  blind:
+// sweeps launched before the first host round trip (needs wk.hist_len >=
+// max_sweeps; a sweep after convergence is a launch of idle workgroups).  ncol
 // (0: n_pad; a multiple of 64 for the 64-row pairs): the rows are zero from
 // column ncol on, so the Gram and the update stop there (rotations keep those
 // columns zero).
 hipError_t run_jacobi(int64_t njobs, int n_pad, double* W, const JacobiWork& wk, int max_sweeps,
                       hipStream_t stream, KernelTimer* timer = nullptr, int* sweeps_done = nullptr,
-                      const int* nb_job = nullptr, int nb_max = 0, int* history = nullptr, int ncol = 0);
+                      const int* nb_job = nullptr, int nb_max = 0, int* history = nullptr, int ncol = 0,
+                      int blind = 0);
 // Rank of the rows of W (n_pad x n_pad per job, row-major): *rows_max = the
 // largest over the jobs of the smallest L such that the rows from L on hold
 // at most approx_budget(tau_null)^2 times the largest squared row norm of
