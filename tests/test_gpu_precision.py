@@ -1,0 +1,89 @@
+"""Precision forms of the contraction (SURVEY configurations C4 and C5):
+the coarse-graining GEMM in FP32, BF16 or FP8 (e4m3) with FP32 accumulation
+and one power-of-two scale per operand tensor, everything else FP64.
+
+For each dtype, two comparisons with the FP64 oracle:
+* top-k chains (deterministic TRG, Section II Eq. approxSVD), paired with
+  the oracle's stored chain (tests/golden/topk_refs.json, written by
+  make_topk_refs.py from the oracle alone): |d ln Z| per site;
+* Monte Carlo chains, unpaired (rounding changes the draws' inputs, so
+  chains of different dtypes part after their first flip): the mean of
+  ln|Z~| per site over the samples against the FP64 form's, with its
+  standard error.  The FP64 form itself is held to the oracle by the C4/C5
+  parity tests.
+Also logged: the GEMM time (library HIP-event timers) and the whole chain
+time per dtype, i.e. the kernel-level and end-to-end speedup over FP64.
+
+Bounds per dtype (unit roundoff u: FP32 2^-24, BF16 2^-8, e4m3 2^-4): the
+paired error per site must stay below 100 u (the contraction rounds T' at
+about u per step; ln Z per site weighs step s by 2^-(s+1)); FP64 below
+1e-12 when its per-step ln c equals the oracle's to 1e-10."""
+import json
+import math
+import os
+import time
+
+import numpy as np
+import pytest
+
+from gpu_util import log, need_gpu
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+U = {"f64": 2.0 ** -53, "f32": 2.0 ** -24, "bf16": 2.0 ** -8, "fp8": 2.0 ** -4}
+FORMS = {"k48_betac_h0_24": ("f64", "f32", "bf16"), "k64_b042_h01_20": ("f64", "bf16", "fp8")}
+MC_SAMPLES = {"k48_betac_h0_24": 24, "k64_b042_h01_20": 8}
+
+
+def _refs():
+    with open(os.path.join(HERE, "golden", "topk_refs.json")) as f:
+        return json.load(f)
+
+
+@pytest.mark.parametrize("name", list(FORMS))
+def test_precision_forms(name):
+    torch, m = need_gpu()
+    ref = _refs()[name]
+    k, beta, h, n = ref["k"], ref["beta"], ref["h"], ref["n_steps"]
+    ts = m.init_tensor("site", [beta], [h])
+    tau = 1e-11
+    paired, mc = {}, {}
+    for dt in FORMS[name]:
+        # paired: top-k against the oracle
+        r = m.run_samples(ts, 1, n_steps=n, k=k, mode="topk", dtype=dt, want_ln_c=True, tau_null=tau)
+        lnz = float(r.ln_abs_Z.cpu().numpy()[0]) / 2.0 ** n
+        lnc = r.ln_c.cpu().numpy()[0]
+        d = abs(lnz - ref["ln_abs_Z_per_site"])
+        dc = float(np.max(np.abs(lnc - np.asarray(ref["ln_c"]))))
+        paired[dt] = (d, dc)
+        log(f"{name} {dt}: top-k |d lnZ|/site vs oracle {d:.3e}, max per-step |d ln c| {dc:.3e}")
+        # unpaired: Monte Carlo chains, timed
+        S = MC_SAMPLES[name]
+        ch = m.Chain(ts, S, n_steps=n, k=k, dtype=dt, seed=3, profile=True, tau_null=tau)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ch.step(n)
+        res = ch.finish()
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        p = ch.profile()
+        ch.close()
+        ln = res.ln_abs_Z.cpu().numpy() / 2.0 ** n
+        assert np.all(res.sign.cpu().numpy() != 0)
+        mc[dt] = (ln.mean(), ln.std(ddof=1) / math.sqrt(S), t, p["gemm_ms"], p["gemm_busy_ms"])
+        log(f"{name} {dt}: MC {S} samples x {n} steps in {t:.2f} s (GEMM {p['gemm_ms']:.1f} ms summed, "
+            f"{p['gemm_busy_ms']:.1f} ms busy); mean ln|Z~|/site {mc[dt][0]:.10f} +- {mc[dt][1]:.1e}")
+    m64 = mc["f64"]
+    for dt in FORMS[name]:
+        d, dc = paired[dt]
+        if dt == "f64":
+            if dc < 1e-10:
+                assert d < 1e-12
+        else:
+            assert d < 100 * U[dt], (dt, d)
+            mu, se, t, g, gb = mc[dt]
+            diff = mu - m64[0]
+            log(f"{name} {dt} vs f64: MC mean difference {diff:+.3e} +- {math.hypot(se, m64[1]):.1e}; "
+                f"GEMM speedup {m64[3] / g:.2f}x (summed), {m64[4] / gb:.2f}x (busy); end to end "
+                f"{m64[2] / t:.2f}x; paired top-k error {d:.2e}")
