@@ -298,13 +298,26 @@ const char* mctrg_status_string(int status);
 /* ---- Step-level entry points (the individual steps of one TRG step) ---- */
 
 /* Decomposition step (Section II, Eq. exactSVD): FP64 SVD of n_mats square
- * n x n matrices (device, row-major, n_mats * n * n), n = d1 * d2 with the
- * column index j = i1 * d2 + i2.  sigma_out: device, n_mats * n, descending.
- * V_out: device or NULL, n_mats * n * n, row i = i-th right singular vector,
- * signed so that sum_j V[i][j] / (1 + i1 + phi*i2) > 0 (phi = golden ratio).
+ * n x n matrices (device, row-major, n_mats * n * n), n = d1 * d2 <= 4096 with
+ * the column index j = i1 * d2 + i2, by the same route and with the same
+ * approximations as every chain step: a column-re-ordered QR that stops at
+ * the numerical rank, two or four more QRs over the leading columns, the
+ * deflation of rows below the budget, block one-sided Jacobi on the rest.
+ * tau_null (0 <= tau_null < 1) is the candidate cut of the sampler: the parts
+ * of M the approximations drop total at most max(2^-48, tau_null / 10) * s_1
+ * in Frobenius norm, which bounds the error of every singular value (Weyl's
+ * inequality); tau_null = 0 keeps M to the rounding floor.
+ * sigma_out: device, n_mats * n, descending (values beyond the numerical
+ * rank are 0).
+ * V_out: device or NULL, n_mats * n * n, row i = the i-th right singular
+ * vector, signed so that sum_j V[i][j] / (1 + i1 + phi*i2) > 0 (phi = golden
+ * ratio); rows of zero values are zero, and rows of values below the budget
+ * are accurate only to budget / (their distance to the other values).
  * sweeps_out: device or NULL, n_mats int32 Jacobi sweeps used (-1 = no
- * convergence).  Blocks on hip_stream. */
-int mctrg_svd_batched(int64_t n_mats, int32_t d1, int32_t d2, const double* M,
+ * convergence).  Allocates its workspace (about 4 n_pad^2 doubles per
+ * matrix, n_pad = n rounded up to 32, plus n^2 with V_out).  Blocks on
+ * hip_stream.  Errors: EINVAL, ENOMEM, EDEVICE. */
+int mctrg_svd_batched(int64_t n_mats, int32_t d1, int32_t d2, const double* M, double tau_null,
                       double* sigma_out, double* V_out, int32_t* sweeps_out, void* hip_stream);
 
 /* Sampling and reweighting step (Section II): for each of n_jobs descending

@@ -103,7 +103,7 @@ _lib.mctrg_destroy.argtypes = [_vp]
 _lib.mctrg_destroy.restype = None
 _lib.mctrg_status_string.argtypes = [ctypes.c_int]
 _lib.mctrg_status_string.restype = ctypes.c_char_p
-_lib.mctrg_svd_batched.argtypes = [_i64, _i32, _i32, _vp, _vp, _vp, _vp, _vp]
+_lib.mctrg_svd_batched.argtypes = [_i64, _i32, _i32, _vp, _f64, _vp, _vp, _vp, _vp]
 _lib.mctrg_svd_batched.restype = ctypes.c_int
 _lib.mctrg_sample_batched.argtypes = [_i64, _i32, _i32, _i32, _u64, _f64, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
                                       _vp, _vp]
@@ -324,9 +324,10 @@ def estimate_lnZ(sign, ln_abs_Z, n_sites: float) -> dict:
     return est.as_dict()
 
 
-def svd_batched(M, d1: int, d2: int, want_V: bool = True):
-    """mctrg_svd_batched on a (n_mats, n, n) float64 device tensor.
-    Returns (sigma, V or None, sweeps)."""
+def svd_batched(M, d1: int, d2: int, want_V: bool = True, tau_null: float = 1e-11):
+    """mctrg_svd_batched on a (n_mats, n, n) float64 device tensor: the chain
+    step's decomposition, with the approximation budget of the candidate cut
+    tau_null.  Returns (sigma, V or None, sweeps)."""
     torch = _torch()
     _dev(torch, M, torch.float64, "M")
     nm, n = M.shape[0], d1 * d2
@@ -335,8 +336,8 @@ def svd_batched(M, d1: int, d2: int, want_V: bool = True):
     sig = torch.empty((nm, n), dtype=torch.float64, device=M.device)
     V = torch.empty((nm, n, n), dtype=torch.float64, device=M.device) if want_V else None
     sw = torch.empty(nm, dtype=torch.int32, device=M.device)
-    _check(_lib.mctrg_svd_batched(nm, d1, d2, _ptr(M), _ptr(sig), _ptr(V), _ptr(sw), _stream(torch)),
-           "mctrg_svd_batched")
+    _check(_lib.mctrg_svd_batched(nm, d1, d2, _ptr(M), float(tau_null), _ptr(sig), _ptr(V), _ptr(sw),
+                                  _stream(torch)), "mctrg_svd_batched")
     return sig, V, sw
 
 

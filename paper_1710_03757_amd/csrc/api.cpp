@@ -338,6 +338,126 @@ size_t chain_bytes(Chain& c) {
     if (e_ != hipSuccess) return MCTRG_EDEVICE; \
   } while (0)
 
+// ---------------------------------------------------------------------------
+// The decomposition of a batch of unfoldings (paper Section II, Eq.
+// exactSVD), shared by the chains and the step-level SVD entry point.
+// ---------------------------------------------------------------------------
+struct DecompBufs {
+  double *S, *W, *W2, *W3, *Tscr, *Tws, *Tws2, *colnorm, *dnrm, *sigma;
+  int32_t *perm, *colmap, *dpos, *order;
+  int* nb_job;
+  JacobiWork jw;
+};
+
+DecompBufs decomp_bufs(const Chain& c) {
+  return DecompBufs{c.S,    c.W,     c.W2,   c.W3,     c.Tscr,  c.Tws, c.Tws2, c.colnorm, c.dnrm,
+                    c.sigma, c.perm, c.colmap, c.dpos, c.order, c.nb_job, c.jw};
+}
+
+struct DecompCtl {
+  int dec = MCTRG_DEC_SVD;
+  double tau = 0.0;        // candidate cut: sets the approximation budget
+  int blind = 0;           // Jacobi sweeps launched before the first host round trip
+  KernelTimer* tq = nullptr;
+  double* tq_flops = nullptr;
+  KernelTimer* tj = nullptr;
+  int* sweep_hist = nullptr;   // host, 2 kMaxSweeps ints, or NULL
+};
+
+// Where the result is: the rows Wj whose norms are the singular values
+// (sigma / order hold them sorted), and which orthogonal factors map the
+// normalised rows to the right singular vectors: Q2 (W / Tws2) and Q4 (S /
+// Tws) after five QRs (qr5 && !three), Q2 alone after three (three, or qr
+// without qr5), none on the direct route.
+struct DecompOut {
+  double* Wj = nullptr;
+  bool qr5 = false, qr = false, three = false, qr_basis = false;
+  int jcols = 0;    // the Jacobi rows are zero from this column on (0: none)
+  int sweeps = 0;   // Jacobi sweeps of the slowest job
+};
+
+// Three or five QRs (n_pad <= 1024) or three (n_pad <= 4096), then Jacobi on
+// the rows of the last R; larger unfoldings go straight to the Jacobi.  Rows
+// at the noise floor or below a tenth of the candidate cut move behind the
+// active ones and are not rotated (deflation).  The early stop of the first
+// QR, the rank limit of the later ones and the deflation each drop at most
+// approx_budget(tau) s_1 in Frobenius norm.
+hipError_t decompose(int64_t nj, int n, int D, int n_pad, const double* T, const int32_t* src, const int32_t* split,
+                     const DecompBufs& b, const DecompCtl& ctl, DecompOut& out, hipStream_t st) {
+#define HKE(x)                           \
+  do {                                   \
+    hipError_t e_ = (x);                 \
+    if (e_ != hipSuccess) return e_;     \
+  } while (0)
+  out = DecompOut{};
+  const bool qr5 = n_pad <= 1024;
+  const bool qr = n_pad <= kQrMaxN;
+  out.qr5 = qr5;
+  out.qr = qr;
+  double* rows = b.W2;   // the rows handed to the Jacobi
+  double* Wj = b.W;      // the Jacobi workspace
+  int nb_max = 0;
+  const bool qr_basis = qr5 && ctl.dec != MCTRG_DEC_SVD;
+  out.qr_basis = qr_basis;
+  if (qr5) {
+    // the first QR stops once the columns it has not factored hold at most the
+    // approximation budget in every job (their rows of R1 are then set to zero)
+    QrStop stop;
+    stop.budget = approx_budget(ctl.tau);
+    stop.dev = b.jw.counter;
+    stop.host = b.jw.counter_host;
+    HKE(run_qr1(nj, n, D, n_pad, T, src, split, b.perm, b.dpos, b.S, b.W, b.Tscr, b.colmap, b.colnorm, st, &stop));
+    // The first QR re-orders the columns by norm, so the rows of R1 come in
+    // roughly decreasing norm: the later QRs run over the leading ncols
+    // columns only, where the rows from ncols on hold at most the
+    // approximation budget in total (they are set to zero, which moves the
+    // singular values by at most their Frobenius norm).
+    int rows1 = 0;
+    HKE(run_rank_rows(nj, n_pad, ctl.tau, b.W, b.dnrm, b.nb_job, b.jw.counter, b.jw.counter_host, &rows1, st));
+    const int ncols = std::min(n_pad, std::max(128, 128 * ceil_div(rows1, 128)));
+    HKE(run_qr23(nj, n_pad, ncols, b.W, b.Tws2, b.W2, b.W3, b.Tscr, st, ctl.tq, ctl.tq_flops));
+    if (qr_basis) {
+      // the cheaper decomposition: the basis V = P Q2 (Q4) of three (five) QR
+      // steps, the terms (M v_j) v_j^T weighted by |M v_j| = the column norms
+      // of R3 (R5); no Jacobi
+      if (ctl.dec == MCTRG_DEC_QR5) HKE(run_qr45(nj, n_pad, ncols, b.S, b.W2, b.Tws, b.W3, b.Tscr, st, ctl.tq, ctl.tq_flops));
+      out.three = ctl.dec == MCTRG_DEC_QR3;
+      out.Wj = b.W2;
+      return launch_qr_basis(nj, n, n_pad, ncols, b.W3, b.dnrm, b.W2, b.sigma, b.order, st);
+    }
+    out.jcols = ncols;
+    // The QR iteration stops after three steps when the rows left to rotate
+    // are at most half of the matrix (a cut above the tensor's rounding floor
+    // deflates its noise subspace): the Jacobi on them then costs less than
+    // the fourth and fifth QR would save.  Otherwise those follow.
+    HKE(run_deflate(nj, n_pad, ctl.tau, b.W3, b.S, b.nb_job, b.dnrm, b.dpos, b.jw.counter, b.jw.counter_host, &nb_max,
+                    st));
+    if (2 * nb_max * jacobi_block_rows(n_pad) <= n_pad) {
+      out.three = true;
+      Wj = b.S;          // W / Tws2 keep Q2
+    } else {
+      HKE(run_qr45(nj, n_pad, ncols, b.S, b.W2, b.Tws, b.W3, b.Tscr, st, ctl.tq, ctl.tq_flops));
+      rows = b.W3;       // W / Tws2 keep Q2, S / Tws keep Q4
+      Wj = b.W2;
+    }
+  } else if (qr) {
+    HKE(run_qr3_precondition(nj, n, D, n_pad, T, src, split, b.perm, b.dpos, b.S, b.Tws, b.W, b.Tws2, b.W2, b.colmap,
+                             b.colnorm, &rows, st));
+    Wj = b.W2;           // W keeps Q2
+  } else {
+    HKE(launch_unfold(nj, D, n_pad, T, src, split, b.W2, st));
+    HKE(launch_iota(nj, n_pad, b.perm, st));
+  }
+  if (!out.three)
+    HKE(run_deflate(nj, n_pad, ctl.tau, rows, Wj, b.nb_job, b.dnrm, b.dpos, b.jw.counter, b.jw.counter_host, &nb_max,
+                    st));
+  HKE(run_jacobi(nj, n_pad, Wj, b.jw, kMaxSweeps, st, ctl.tj, &out.sweeps, b.nb_job, nb_max, ctl.sweep_hist,
+                 out.jcols, ctl.blind));
+  out.Wj = Wj;
+  return launch_jacobi_finalize(nj, n, n_pad, Wj, b.sigma, b.order, st, b.dnrm);
+#undef HKE
+}
+
 // Allocates the chain's memory and gathers its starting tensors.
 int chain_start(Chain& c, const mctrg_tensor_set* ts, const std::vector<int32_t>& groups,
                 const std::vector<int64_t>& out_index) {
@@ -438,101 +558,36 @@ int chain_step(Chain& c) {
   CKH(hipMemcpyAsync(c.rng, c.h_rng, 3 * nj * sizeof(uint64_t), hipMemcpyHostToDevice, c.st));
   CKH(hipMemcpyAsync(c.cjobs, c.h_cjobs, 4 * no * sizeof(int32_t), hipMemcpyHostToDevice, c.st));
 
-  // decomposition: three or five QRs (n_pad <= 1024) or three (n_pad <= 4096)
-  // then Jacobi on the rows of the last R; larger unfoldings go straight to
-  // Jacobi.  Rows at the noise floor or below a tenth of the candidate cut
-  // move behind the active ones and are not rotated (deflation).
-  const bool qr5 = sh.n_pad <= 1024;
-  const bool qr = sh.n_pad <= kQrMaxN;
-  bool three = false;    // the n_pad <= 1024 preconditioner stopped after three QRs
-  double* rows = c.W2;   // the rows handed to the Jacobi
-  double* Wj = c.W;      // the Jacobi workspace
-  int nb_max = 0;
-  int jcols = 0;         // the Jacobi rows are zero from this column on (0: none)
-  KernelTimer* tq = c.tq.enabled ? &c.tq : nullptr;
-  const bool qr_basis = qr5 && c.dec != MCTRG_DEC_SVD;
-  if (qr_basis) {
-    // the cheaper decomposition: the basis V = P Q2 (Q4) of three (five) QR
-    // steps, the terms (M v_j) v_j^T weighted by |M v_j| = the column norms
-    // of R3 (R5); no Jacobi
-    QrStop stop;
-    stop.budget = approx_budget(c.tau);
-    stop.dev = c.jw.counter;
-    stop.host = c.jw.counter_host;
-    CKH(run_qr1(nj, sh.n, sh.D, sh.n_pad, c.Ta, c.src, c.split, c.perm, c.dpos, c.S, c.W, c.Tscr, c.colmap, c.colnorm,
-                c.st, &stop));
-    int rows1 = 0;
-    CKH(run_rank_rows(nj, sh.n_pad, c.tau, c.W, c.dnrm, c.nb_job, c.jw.counter, c.jw.counter_host, &rows1, c.st));
-    const int ncols = std::min(sh.n_pad, std::max(128, 128 * ceil_div(rows1, 128)));
-    CKH(run_qr23(nj, sh.n_pad, ncols, c.W, c.Tws2, c.W2, c.W3, c.Tscr, c.st, tq, &c.tq_flops));
-    if (c.dec == MCTRG_DEC_QR5) CKH(run_qr45(nj, sh.n_pad, ncols, c.S, c.W2, c.Tws, c.W3, c.Tscr, c.st, tq, &c.tq_flops));
-    three = c.dec == MCTRG_DEC_QR3;
-    Wj = c.W2;
-    CKH(launch_qr_basis(nj, sh.n, sh.n_pad, ncols, c.W3, c.dnrm, Wj, c.sigma, c.order, c.st));
-    c.last_sweeps = 0;
-  } else if (qr5) {
-    // the first QR stops once the columns it has not factored hold at most the
-    // approximation budget in every job (their rows of R1 are then set to zero)
-    QrStop stop;
-    stop.budget = approx_budget(c.tau);
-    stop.dev = c.jw.counter;
-    stop.host = c.jw.counter_host;
-    CKH(run_qr1(nj, sh.n, sh.D, sh.n_pad, c.Ta, c.src, c.split, c.perm, c.dpos, c.S, c.W, c.Tscr, c.colmap, c.colnorm,
-                c.st, &stop));
-    // The first QR re-orders the columns by norm, so the rows of R1 come in
-    // roughly decreasing norm: the later QRs run over the leading ncols
-    // columns only, where the rows from ncols on hold at most the
-    // approximation budget in total (they are set to zero, which moves the
-    // singular values by at most their Frobenius norm).
-    int rows1 = 0;
-    CKH(run_rank_rows(nj, sh.n_pad, c.tau, c.W, c.dnrm, c.nb_job, c.jw.counter, c.jw.counter_host, &rows1, c.st));
-    const int ncols = std::min(sh.n_pad, std::max(128, 128 * ceil_div(rows1, 128)));
-    CKH(run_qr23(nj, sh.n_pad, ncols, c.W, c.Tws2, c.W2, c.W3, c.Tscr, c.st, tq, &c.tq_flops));
-    jcols = ncols;
-    // The QR iteration stops after three steps when the rows left to rotate
-    // are at most half of the matrix (a cut above the tensor's rounding floor
-    // deflates its noise subspace): the Jacobi on them then costs less than
-    // the fourth and fifth QR would save.  Otherwise those follow.
-    CKH(run_deflate(nj, sh.n_pad, c.tau, c.W3, c.S, c.nb_job, c.dnrm, c.dpos, c.jw.counter, c.jw.counter_host,
-                    &nb_max, c.st));
-    if (2 * nb_max * jacobi_block_rows(sh.n_pad) <= sh.n_pad) {
-      three = true;
-      Wj = c.S;          // c.W / c.Tws2 keep Q2
-    } else {
-      CKH(run_qr45(nj, sh.n_pad, ncols, c.S, c.W2, c.Tws, c.W3, c.Tscr, c.st, tq, &c.tq_flops));
-      rows = c.W3;       // c.W / c.Tws2 keep Q2, c.S / c.Tws keep Q4
-      Wj = c.W2;
-    }
-  } else if (qr) {
-    CKH(run_qr3_precondition(nj, sh.n, sh.D, sh.n_pad, c.Ta, c.src, c.split, c.perm, c.dpos, c.S, c.Tws, c.W, c.Tws2, c.W2,
-                             c.colmap, c.colnorm, &rows, c.st));
-    Wj = c.W2;           // c.W keeps Q2
-  } else {
-    CKH(launch_unfold(nj, sh.D, sh.n_pad, c.Ta, c.src, c.split, c.W2, c.st));
-    CKH(launch_iota(nj, sh.n_pad, c.perm, c.st));
-  }
-  if (!three && !qr_basis)
-    CKH(run_deflate(nj, sh.n_pad, c.tau, rows, Wj, c.nb_job, c.dnrm, c.dpos, c.jw.counter, c.jw.counter_host, &nb_max,
-                    c.st));
-  if (!qr_basis)
+  DecompOut dout;
+  {
+    DecompCtl ctl;
+    ctl.dec = c.dec;
+    ctl.tau = c.tau;
     // the first sweeps run without host round trips: as many as the previous
     // step needed, less two (a sweep after convergence only launches idle
     // workgroups)
-    CKH(run_jacobi(nj, sh.n_pad, Wj, c.jw, kMaxSweeps, c.st, c.tj.enabled ? &c.tj : nullptr, &c.last_sweeps, c.nb_job,
-                   nb_max, c.sweep_hist, jcols, c.last_sweeps - 2));
+    ctl.blind = c.last_sweeps - 2;
+    if (c.tq.enabled) {
+      ctl.tq = &c.tq;
+      ctl.tq_flops = &c.tq_flops;
+    }
+    if (c.tj.enabled) ctl.tj = &c.tj;
+    ctl.sweep_hist = c.sweep_hist;
+    CKH(decompose(nj, sh.n, sh.D, sh.n_pad, c.Ta, c.src, c.split, decomp_bufs(c), ctl, dout, c.st));
+    c.last_sweeps = dout.sweeps;
+  }
+  const bool qr5 = dout.qr5, qr = dout.qr, three = dout.three, qr_basis = dout.qr_basis;
+  double* const Wj = dout.Wj;
   if (s < 64) c.step_sweeps[s] = c.last_sweeps;
   if (!qr_basis) {
     int64_t rp = 0;
     for (int w = 0; w < c.last_sweeps && w < kMaxSweeps; ++w) rp += c.sweep_hist[2 * w];
     // per rotated pair of two row blocks (2 brows rows): the symmetric Gram
     // (2 brows)^2 len and the update W <- Q^T W, 2 (2 brows)^2 len
-    const double rows = 2.0 * jacobi_block_rows(sh.n_pad), len = jcols > 0 ? jcols : sh.n_pad;
+    const double rows = 2.0 * jacobi_block_rows(sh.n_pad), len = dout.jcols > 0 ? dout.jcols : sh.n_pad;
     c.rotated_pairs += rp;
     c.jacobi_flops += (double)rp * 3.0 * rows * rows * len;
-  }
-  if (!qr_basis) {
     CKH(launch_jacobi_fail(nj, sh.jps, c.jw.sweeps, c.failed, c.st));
-    CKH(launch_jacobi_finalize(nj, sh.n, sh.n_pad, Wj, c.sigma, c.order, c.st, c.dnrm));
   }
   SampleArgs sa{};
   sa.njobs = nj; sa.n = sh.n; sa.k = sh.kc; sa.mode = s < c.n_det ? MCTRG_TOPK : c.mode; sa.seed = c.seed;
@@ -1238,61 +1293,88 @@ int mctrg_estimate_lnZ(int64_t n_samples, const int8_t* sign, const double* ln_a
 
 // ---- step-level entry points ----------------------------------------------
 
-int mctrg_svd_batched(int64_t n_mats, int32_t d1, int32_t d2, const double* M, double* sigma_out, double* V_out,
-                      int32_t* sweeps_out, void* hip_stream) {
+int mctrg_svd_batched(int64_t n_mats, int32_t d1, int32_t d2, const double* M, double tau_null, double* sigma_out,
+                      double* V_out, int32_t* sweeps_out, void* hip_stream) {
   if (n_mats < 0 || d1 < 1 || d2 < 1 || (int64_t)d1 * d2 > 4096 || !M || !sigma_out) return MCTRG_EINVAL;
+  if (!(tau_null >= 0.0 && tau_null < 1.0)) return MCTRG_EINVAL;
   if (n_mats == 0) return MCTRG_OK;
   hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
   const int n = d1 * d2, n_pad = std::max(32, round_up32(n));
   const size_t per = (size_t)n_pad * n_pad;
+  const int64_t nm = n_mats;
+  // the chains' buffers at one step's shape, the right vectors' scratch after them
+  DecompBufs b{};
+  double *X = nullptr, *wgt = nullptr;
+  int32_t *ss = nullptr, *kept = nullptr, *sel = nullptr;
+  auto lay = [&](Arena& ar) {
+    b.S = ar.take<double>(nm * per);
+    b.W = ar.take<double>(nm * per);
+    b.W2 = ar.take<double>(nm * per);
+    b.W3 = ar.take<double>(nm * per);
+    b.Tscr = ar.take<double>((size_t)nm * kQrTscr);
+    b.Tws = ar.take<double>((size_t)nm * 32 * 1024);
+    b.Tws2 = ar.take<double>((size_t)nm * 32 * 1024);
+    b.colnorm = ar.take<double>((size_t)nm * n_pad);
+    b.dnrm = ar.take<double>((size_t)nm * n_pad);
+    b.sigma = sigma_out;
+    b.perm = ar.take<int32_t>((size_t)nm * n_pad);
+    b.colmap = ar.take<int32_t>((size_t)nm * n_pad);
+    b.dpos = ar.take<int32_t>((size_t)nm * n_pad);
+    b.order = ar.take<int32_t>((size_t)nm * n);
+    b.nb_job = ar.take<int>(nm);
+    b.jw.active = ar.take<int>(nm);
+    b.jw.rotated = ar.take<int>(nm);
+    b.jw.sweeps = ar.take<int>(nm);
+    b.jw.counter = ar.take<int>(2 * kMaxSweeps);
+    b.jw.lastmod = ar.take<int>((size_t)nm * kJacobiMaxBlocks);
+    b.jw.lastchk = ar.take<int>((size_t)nm * kJacobiMaxBlocks * kJacobiMaxBlocks);
+    b.jw.hist_len = kMaxSweeps;
+    ss = ar.take<int32_t>(2 * nm);
+    if (V_out) {
+      X = ar.take<double>((size_t)nm * n * n);
+      wgt = ar.take<double>((size_t)nm * n);
+      kept = ar.take<int32_t>(nm);
+      sel = ar.take<int32_t>((size_t)nm * n);
+    }
+  };
   Arena ar;
-  for (int pass = 0; pass < 2; ++pass) {
-    ar.off = 0;
-    (void)ar.take<double>(n_mats * per);          // W
-    (void)ar.take<double>(n_mats * per);          // S
-    (void)ar.take<double>((size_t)n_mats * 1024); // Tws
-    (void)ar.take<int32_t>((size_t)n_mats * n);   // order
-    (void)ar.take<int32_t>((size_t)n_mats * n_pad);  // perm
-    (void)ar.take<int32_t>((size_t)n_mats * n_pad);  // inverse of perm
-    (void)ar.take<int32_t>(2 * n_mats);           // src, split
-    (void)ar.take<int>(3 * n_mats + 2);           // jacobi work
-    if (pass == 0) break;
-  }
+  lay(ar);
   char* mem = nullptr;
   if (hipMalloc(&mem, ar.off) != hipSuccess) { (void)hipGetLastError(); return MCTRG_ENOMEM; }
   HostPinned pin;
-  if (hipHostMalloc(&pin.p, 64, hipHostMallocDefault) != hipSuccess) { (void)hipFree(mem); return MCTRG_ENOMEM; }
+  if (hipHostMalloc(&pin.p, 2 * kMaxSweeps * sizeof(int) + 64, hipHostMallocDefault) != hipSuccess) {
+    (void)hipFree(mem);
+    return MCTRG_ENOMEM;
+  }
   Arena a2;
-  a2.base = mem; a2.counting = false;
-  double* W = a2.take<double>(n_mats * per);
-  double* S = a2.take<double>(n_mats * per);
-  double* Tws = a2.take<double>((size_t)n_mats * 1024);
-  int32_t* order = a2.take<int32_t>((size_t)n_mats * n);
-  int32_t* perm = a2.take<int32_t>((size_t)n_mats * n_pad);
-  int32_t* iperm = a2.take<int32_t>((size_t)n_mats * n_pad);
-  int32_t* ss = a2.take<int32_t>(2 * n_mats);
-  int* jws = a2.take<int>(3 * n_mats + 2);
-  std::vector<int32_t> hs(2 * n_mats);
-  for (int64_t i = 0; i < n_mats; ++i) { hs[i] = (int32_t)i; hs[n_mats + i] = 2; }
-  JacobiWork wk{jws, jws + n_mats, jws + 2 * n_mats, jws + 3 * n_mats, reinterpret_cast<int*>(pin.p)};
+  a2.base = mem;
+  a2.counting = false;
+  lay(a2);
+  b.jw.counter_host = reinterpret_cast<int*>(pin.p);
+  // every matrix is its own source, read as a plain row-major n x n matrix (split 2)
+  std::vector<int32_t> hs(2 * nm);
+  for (int64_t i = 0; i < nm; ++i) { hs[i] = (int32_t)i; hs[nm + i] = 2; }
   int rc = MCTRG_OK;
   if (hipMemcpyAsync(ss, hs.data(), hs.size() * sizeof(int32_t), hipMemcpyHostToDevice, st) != hipSuccess)
     rc = MCTRG_EDEVICE;
+  DecompOut out;
   if (rc == MCTRG_OK) {
-    hipError_t e = (n_pad <= kQrMaxN)
-                       ? run_qr_precondition(n_mats, n, 0, n_pad, M, ss, ss + n_mats, perm, iperm, S, Tws, W, st)
-                       : (launch_pad_copy(n_mats, n, n_pad, M, W, st) == hipSuccess ? launch_iota(n_mats, n_pad, perm, st)
-                                                                                    : hipErrorUnknown);
+    DecompCtl ctl;
+    ctl.tau = tau_null;
+    if (decompose(nm, n, 1, n_pad, M, ss, ss + nm, b, ctl, out, st) != hipSuccess) rc = MCTRG_EDEVICE;
+  }
+  if (rc == MCTRG_OK && V_out) {
+    // v = P Q2 (Q4) y for every positive value, the rows of zero values zero
+    const bool five = out.qr5 && !out.three;
+    hipError_t e = launch_select_all(nm, n, sigma_out, kept, sel, wgt, st);
+    if (e == hipSuccess)
+      e = launch_apply_q1(nm, n, n_pad, n, b.W, nullptr, b.Tws2, five ? b.S : nullptr, five ? b.Tws : nullptr, out.Wj,
+                          sigma_out, b.order, kept, sel, wgt, X, st);
+    if (e == hipSuccess) e = launch_scatter_V(nm, n, d2, n_pad, X, b.perm, out.qr5 ? b.colmap : nullptr, kept, V_out, st);
     if (e != hipSuccess) rc = MCTRG_EDEVICE;
   }
-  if (rc == MCTRG_OK && (run_jacobi(n_mats, n_pad, W, wk, kMaxSweeps, st) != hipSuccess ||
-                         launch_jacobi_finalize(n_mats, n, n_pad, W, sigma_out, order, st) != hipSuccess))
-    rc = MCTRG_EDEVICE;
-  if (rc == MCTRG_OK && V_out &&
-      launch_extract_V(n_mats, n, n_pad, d2, W, sigma_out, order, perm, V_out, st) != hipSuccess)
-    rc = MCTRG_EDEVICE;
   if (rc == MCTRG_OK && sweeps_out &&
-      hipMemcpyAsync(sweeps_out, wk.sweeps, n_mats * sizeof(int32_t), hipMemcpyDeviceToDevice, st) != hipSuccess)
+      hipMemcpyAsync(sweeps_out, b.jw.sweeps, nm * sizeof(int32_t), hipMemcpyDeviceToDevice, st) != hipSuccess)
     rc = MCTRG_EDEVICE;
   if (hipStreamSynchronize(st) != hipSuccess) rc = MCTRG_EDEVICE;
   (void)hipFree(mem);

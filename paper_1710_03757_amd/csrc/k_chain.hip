@@ -145,23 +145,4 @@ hipError_t launch_scatter(int64_t nsamp, int n_steps, const int64_t* idx, const 
   return hipGetLastError();
 }
 
-// Square n x n matrices into zero-padded n_pad x n_pad workspaces.
-__global__ void pad_copy_kernel(int n, int n_pad, const double* __restrict__ M, double* __restrict__ W) {
-  const int64_t m = blockIdx.y;
-  const size_t per = (size_t)n_pad * n_pad;
-  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < per; e += (size_t)gridDim.x * blockDim.x) {
-    const int r = (int)(e / n_pad), c = (int)(e % n_pad);
-    W[m * per + e] = (r < n && c < n) ? M[(size_t)m * n * n + (size_t)r * n + c] : 0.0;
-  }
-}
-
-hipError_t launch_pad_copy(int64_t nmats, int n, int n_pad, const double* M, double* W, hipStream_t stream) {
-  if (nmats == 0) return hipSuccess;
-  const size_t per = (size_t)n_pad * n_pad;
-  int gx = (int)((per + 255) / 256);
-  if (gx > 1024) gx = 1024;
-  hipLaunchKernelGGL(pad_copy_kernel, dim3(gx, (unsigned)nmats), dim3(256), 0, stream, n, n_pad, M, W);
-  return hipGetLastError();
-}
-
 }  // namespace mctrg

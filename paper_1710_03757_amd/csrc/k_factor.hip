@@ -205,15 +205,15 @@ hipError_t launch_factor_F(int64_t njobs, int D, int kcap, const double* T, cons
 // w_a z_a[c] is the kept
 // right singular vector of M P (logical column c, c < n: the padding columns
 // sort last), so G[a][perm[colmap[c]]] = X[c][a] (= w_a v_a^T), signed so
-// that sum_e G[a][e] / (1 + e/D + phi (e % D)) > 0.  One workgroup per
-// (a, job).
-__global__ __launch_bounds__(256) void scatter_G_kernel(int D, int n_pad, int kcap, const double* __restrict__ X,
+// that sum_e G[a][e] / (1 + e/d2 + phi (e % d2)) > 0 (the chains: n = D^2,
+// d2 = D).  One workgroup per (a, job).
+__global__ __launch_bounds__(256) void scatter_G_kernel(int n, int d2, int n_pad, int kcap,
+                                                        const double* __restrict__ X,
                                                         const int32_t* __restrict__ perm,
                                                         const int32_t* __restrict__ colmap,
                                                         const int32_t* __restrict__ kept, double* __restrict__ G) {
   const int a = blockIdx.x;
   const int64_t job = blockIdx.y;
-  const int n = D * D;
   double* Ga = G + (size_t)job * kcap * n + (size_t)a * n;
   if (a >= kept[job]) {
     for (int e = threadIdx.x; e < n; e += 256) Ga[e] = 0.0;
@@ -226,7 +226,7 @@ __global__ __launch_bounds__(256) void scatter_G_kernel(int D, int n_pad, int kc
   double g = 0.0;
   for (int c = threadIdx.x; c < n; c += 256) {
     const int e = pj[cm ? cm[c] : c];
-    g += Xj[(size_t)c * kcap + a] / (1.0 + (double)(e / D) + kGolden * (double)(e % D));
+    g += Xj[(size_t)c * kcap + a] / (1.0 + (double)(e / d2) + kGolden * (double)(e % d2));
   }
   for (int o = 32; o > 0; o >>= 1) g += __shfl_xor(g, o);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = g;
@@ -239,45 +239,44 @@ __global__ __launch_bounds__(256) void scatter_G_kernel(int D, int n_pad, int kc
 hipError_t launch_scatter_G(int64_t njobs, int D, int n_pad, int kcap, const double* X, const int32_t* perm,
                             const int32_t* colmap, const int32_t* kept, double* G, hipStream_t stream) {
   if (njobs == 0) return hipSuccess;
-  hipLaunchKernelGGL(scatter_G_kernel, dim3(kcap, (unsigned)njobs), dim3(256), 0, stream, D, n_pad, kcap, X, perm,
-                     colmap, kept, G);
+  hipLaunchKernelGGL(scatter_G_kernel, dim3(kcap, (unsigned)njobs), dim3(256), 0, stream, D * D, D, n_pad, kcap, X,
+                     perm, colmap, kept, G);
   return hipGetLastError();
 }
 
-// V[i][:] = W[order[i]] / sigma_i, signed so that sum_j V[i][j] g_j > 0
-// with g_j = 1 / (1 + j/d2 + phi * (j % d2)).  One workgroup per (i, matrix).
-__global__ __launch_bounds__(256) void extract_V_kernel(int n, int n_pad, int d2, const double* __restrict__ W,
-                                                        const double* __restrict__ sigma,
-                                                        const int32_t* __restrict__ order,
-                                                        const int32_t* __restrict__ perm, double* __restrict__ V) {
-  const int i = blockIdx.x;
-  const int64_t m = blockIdx.y;
-  const double s = sigma[(size_t)m * n + i];
-  const double* v = W + (size_t)m * n_pad * n_pad + (size_t)order[(size_t)m * n + i] * n_pad;
-  double* out = V + ((size_t)m * n + i) * n;
-  const int32_t* pj = perm + m * n_pad;
-  __shared__ double red[4];
-  double g = 0.0;
-  for (int c = threadIdx.x; c < n_pad; c += 256) {
-    const int e = pj[c];
-    if (e < n) g += v[c] / (1.0 + (double)(e / d2) + kGolden * (double)(e % d2));
-  }
-  for (int o = 32; o > 0; o >>= 1) g += __shfl_xor(g, o);
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = g;
-  __syncthreads();
-  g = (red[0] + red[1]) + (red[2] + red[3]);
-  const double f = s > 0.0 ? (g < 0.0 ? -1.0 : 1.0) / s : 0.0;
-  for (int c = threadIdx.x; c < n_pad; c += 256) {
-    const int e = pj[c];
-    if (e < n) out[e] = f * v[c];
-  }
+hipError_t launch_scatter_V(int64_t nmats, int n, int d2, int n_pad, const double* X, const int32_t* perm,
+                            const int32_t* colmap, const int32_t* kept, double* V, hipStream_t stream) {
+  if (nmats == 0) return hipSuccess;
+  hipLaunchKernelGGL(scatter_G_kernel, dim3(n, (unsigned)nmats), dim3(256), 0, stream, n, d2, n_pad, n, X, perm,
+                     colmap, kept, V);
+  return hipGetLastError();
 }
 
-hipError_t launch_extract_V(int64_t nmats, int n, int n_pad, int d2, const double* W, const double* sigma,
-                            const int32_t* order, const int32_t* perm, double* V, hipStream_t stream) {
+// All right vectors of a step-level SVD: kept[j] = the number of positive
+// values in sigma[j] (n, descending), sel[j][a] = a, weight[j][a] = 1.  One
+// workgroup per matrix.
+__global__ __launch_bounds__(256) void select_all_kernel(int n, const double* __restrict__ sigma,
+                                                         int32_t* __restrict__ kept, int32_t* __restrict__ sel,
+                                                         double* __restrict__ weight) {
+  const int64_t j = blockIdx.x;
+  __shared__ int cnt;
+  if (threadIdx.x == 0) cnt = 0;
+  __syncthreads();
+  int mine = 0;
+  for (int a = threadIdx.x; a < n; a += 256) {
+    sel[j * n + a] = a;
+    weight[j * n + a] = 1.0;
+    mine += sigma[j * n + a] > 0.0 ? 1 : 0;
+  }
+  atomicAdd(&cnt, mine);
+  __syncthreads();
+  if (threadIdx.x == 0) kept[j] = cnt;
+}
+
+hipError_t launch_select_all(int64_t nmats, int n, const double* sigma, int32_t* kept, int32_t* sel, double* weight,
+                             hipStream_t stream) {
   if (nmats == 0) return hipSuccess;
-  hipLaunchKernelGGL(extract_V_kernel, dim3(n, (unsigned)nmats), dim3(256), 0, stream, n, n_pad, d2, W, sigma,
-                     order, perm, V);
+  hipLaunchKernelGGL(select_all_kernel, dim3((unsigned)nmats), dim3(256), 0, stream, n, sigma, kept, sel, weight);
   return hipGetLastError();
 }
 

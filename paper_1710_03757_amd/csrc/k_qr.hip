@@ -1586,20 +1586,6 @@ static hipError_t order_and_unfold(int64_t njobs, int n, int D, int n_pad, const
   return hipGetLastError();
 }
 
-hipError_t run_qr_precondition(int64_t njobs, int n, int D, int n_pad, const double* T, const int32_t* src,
-                               const int32_t* split, int32_t* perm, int32_t* iperm, double* S, double* Tws, double* W,
-                               hipStream_t stream) {
-  if (njobs == 0) return hipSuccess;
-  if (n_pad > kQrMaxN) return hipErrorInvalidValue;
-  hipError_t e = order_and_unfold(njobs, n, D, n_pad, T, src, split, perm, iperm, S, stream);
-  if (e != hipSuccess) return e;
-  e = qr_factor(njobs, n_pad, S, Tws, false, nullptr, nullptr, stream);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(r_rows_kernel, dim3(n_pad / 32, n_pad / 32, (unsigned)njobs), dim3(256), 0, stream, n_pad, S, W,
-                     (const int32_t*)nullptr, n_pad, n_pad);
-  return hipGetLastError();
-}
-
 // Three QRs: M P = Q1 R1, R1^T = Q2 R2, R2^T = Q3 R3 (P: the static norm
 // order, refined panel by panel through colmap when n_pad <= 1024).  Each
 // factorisation of the transposed triangle is one step of the unshifted QR

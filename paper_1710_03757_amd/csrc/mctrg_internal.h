@@ -173,9 +173,9 @@ hipError_t run_deflate(int64_t njobs, int n_pad, double tau_null, const double* 
 hipError_t launch_qr_basis(int64_t njobs, int n, int n_pad, int nrows, const double* R, double* nrm, double* W,
                            double* sigma, int32_t* order, hipStream_t stream);
 // QR preconditioning (k_qr.hip): perm[j] (n_pad) orders the columns of the
-// unfolding by decreasing norm, S (n_pad^2 per job) holds M P column-wise
-// and is overwritten by V and R, Tws (1024 per job) is scratch, and W
-// receives the rows of R.  split 2 = plain row-major n x n matrices.
+// unfolding by decreasing norm, the QRs factor M P column-wise.  split 0 / 1:
+// the A / B unfolding of a D^4 tensor; split 2: a plain row-major n x n
+// matrix.
 constexpr int kQrMaxN = 4096;
 // Scratch of the blocked QR path per job: two 64 x 64 T factors and the
 // 128 x 128 T as 144 MFMA fragments of 64 doubles.
@@ -183,9 +183,6 @@ constexpr int64_t kQrBlockScratch = 8192 + 144 * 64;
 // Tscr of the five-QR preconditioning per job: two 32 x 32 panel T slots and
 // the blocked-path scratch.
 constexpr int64_t kQrTscr = 2048 + kQrBlockScratch;
-hipError_t run_qr_precondition(int64_t njobs, int n, int D, int n_pad, const double* T, const int32_t* src,
-                               const int32_t* split, int32_t* perm, int32_t* iperm, double* S, double* Tws, double* W,
-                               hipStream_t stream);
 hipError_t launch_iota(int64_t njobs, int n_pad, int32_t* perm, hipStream_t stream);
 // Three-QR preconditioning (see k_qr.hip): *rows receives the buffer with
 // the rows of R3 (S1); W1 keeps Q2 (V) and Tws2 its panel T factors
@@ -251,6 +248,13 @@ hipError_t launch_apply_q1(int64_t njobs, int n, int n_pad, int kcap, const doub
 // with the gauge of the factor kernels; zero rows for a >= kept.
 hipError_t launch_scatter_G(int64_t njobs, int D, int n_pad, int kcap, const double* X, const int32_t* perm,
                             const int32_t* colmap, const int32_t* kept, double* G, hipStream_t stream);
+// The same for the step-level SVD: V[a][perm[colmap[c]]] = X[c][a] for n x n
+// matrices with columns (i1, i2), gauge over 1 + i1 + phi i2, kcap = n.
+hipError_t launch_scatter_V(int64_t nmats, int n, int d2, int n_pad, const double* X, const int32_t* perm,
+                            const int32_t* colmap, const int32_t* kept, double* V, hipStream_t stream);
+// kept[j] = #{a : sigma[j][a] > 0}, sel[j][a] = a, weight[j][a] = 1 (n per matrix).
+hipError_t launch_select_all(int64_t nmats, int n, const double* sigma, int32_t* kept, int32_t* sel, double* weight,
+                             hipStream_t stream);
 
 // Norms of the rotated rows, sorted descending: sigma[j][0..n), order[j][0..n).
 // nrm (n_pad doubles per job, or NULL): scratch for the squared row norms,
@@ -315,10 +319,6 @@ int gemm_tile_chosen(int dt, int M, int N, int K, int64_t nout);
 hipError_t launch_unscale(int64_t nout, int64_t elems, int src_is_f32, const void* C, const double* scales,
                           double* T_out, hipStream_t stream);
 
-// Right singular vectors of the Jacobi result, gauge-fixed (row i of V).
-hipError_t launch_extract_V(int64_t nmats, int n, int n_pad, int d2, const double* W, const double* sigma,
-                            const int32_t* order, const int32_t* perm, double* V, hipStream_t stream);
-
 // Normalisation: c = max|T'|, T = T'/c, ln c - ln(scales) written to lnc[j].
 hipError_t launch_normalize(int64_t nout, int64_t elems, int src_is_f32, const void* Tp,
                             const double* scales, double* cbuf, double* T, double* lnc,
@@ -349,6 +349,5 @@ hipError_t launch_izero(int64_t n, int* p, hipStream_t stream);
 hipError_t launch_scatter(int64_t nsamp, int n_steps, const int64_t* idx, const int8_t* sign, const double* ln,
                           const double* lnc_steps, int8_t* out_sign, double* out_ln, double* out_lnc,
                           hipStream_t stream);
-hipError_t launch_pad_copy(int64_t nmats, int n, int n_pad, const double* M, double* W, hipStream_t stream);
 
 }  // namespace mctrg

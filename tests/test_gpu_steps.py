@@ -29,46 +29,95 @@ def ising_unfoldings(k, steps, beta=BETA_C, h=0.0, seed=0, sample=0):
     return out
 
 
+def approx_budget(tau):
+    """Total Frobenius norm, relative to s_1, that the decomposition's
+    approximations (early stop of the first QR, rank limit, deflation) may
+    drop for the candidate cut tau (a tenth of the cut, at least 2^-48)."""
+    return max(2.0 ** -48, tau / 10.0)
+
+
+def check_svd(M, cs, sig, V, sw, tau, label):
+    """The step's decomposition against the exact SVD (LAPACK through the
+    oracle): every value within the Weyl bound of the dropped parts plus
+    rounding (1e-13 sqrt(n) s_1); every vector whose value is isolated by a
+    gap g within 4 eps / g of the exact one (the perturbation bound of
+    singular subspaces, eps the same total perturbation), checked where that
+    bound is below 1e-3; the rows of values above the budget orthonormal."""
+    U0, s0, Vt0 = trg.decompose(M, cs)
+    n = M.shape[0]
+    eps = (approx_budget(tau) + 1e-13 * math.sqrt(n)) * s0[0]
+    assert sw >= 1, (label, sw)
+    verr = np.max(np.abs(sig - s0))
+    assert verr <= eps, (label, verr, eps)
+    assert np.all(np.diff(sig) <= 0)
+    if V is None:
+        return verr, 0.0, 0
+    gaps = np.minimum(np.abs(np.diff(np.r_[np.inf, s0])), np.abs(np.diff(np.r_[s0, -np.inf])))
+    bound = 4.0 * eps / np.maximum(gaps, 1e-300)
+    ok = bound < 1e-3
+    assert ok[0], (label, "the leading vector must be checked", gaps[0], eps)
+    errs = np.max(np.abs(V[ok] - Vt0[ok]), axis=1)
+    assert np.all(errs <= bound[ok]), (label, np.max(errs / bound[ok]))
+    # zero values have zero rows; the rows above the budget are orthonormal
+    assert np.all(V[sig == 0.0] == 0.0)
+    top = sig > 10.0 * eps
+    G = V[top] @ V[top].T
+    assert np.max(np.abs(G - np.eye(int(top.sum())))) <= 1e-10 + 4.0 * eps / max(np.min(sig[top]), 1e-300)
+    return verr, float(np.max(errs)), int(ok.sum())
+
+
+@pytest.mark.parametrize("tau", [0.0, 1e-11, 1e-6])
 @pytest.mark.parametrize("d1,d2,nm", [(2, 2, 3), (4, 4, 5), (5, 6, 4), (8, 8, 6), (16, 16, 3), (24, 24, 2),
                                       (33, 34, 2), (36, 36, 1), (48, 48, 1)])
-def test_svd_random(d1, d2, nm):
+def test_svd_random(d1, d2, nm, tau):
+    """Graded spectra (random orthogonal x geometric values x random
+    orthogonal, down to 1e-8 and 1e-16, and one of rank n/2), through every
+    route of the decomposition: five or three QRs with the rank limit and
+    deflation (n_pad <= 1024), three QRs (n_pad <= 4096)."""
     torch, m = need_gpu()
-    log(f"svd_random d1={d1} d2={d2} nm={nm}")
+    log(f"svd_random d1={d1} d2={d2} nm={nm} tau={tau}")
     rng = np.random.default_rng(d1 * 100 + d2)
     n = d1 * d2
-    # graded spectra: random orthogonal * geometric singular values * random orthogonal
     Ms = []
     for i in range(nm):
         U, _ = np.linalg.qr(rng.standard_normal((n, n)))
         V, _ = np.linalg.qr(rng.standard_normal((n, n)))
         s = np.logspace(0, -8 * (i % 2 + 1), n)
+        if i == 2:
+            s[n // 2:] = 0.0
         Ms.append((U * s) @ V.T)
     Ms = np.stack(Ms)
-    sig, V, sw = m.svd_batched(torch.tensor(Ms, device="cuda"), d1, d2)
-    sig, V, sw = sig.cpu().numpy(), V.cpu().numpy(), sw.cpu().numpy()
-    assert np.all(sw > 0)
+    Md = torch.tensor(Ms, device="cuda")
+    sig, V, sw = m.svd_batched(Md, d1, d2, tau_null=tau)
+    sig2, V2, _ = m.svd_batched(Md, d1, d2, want_V=False, tau_null=tau)
+    sig, V, sw, sig2 = sig.cpu().numpy(), V.cpu().numpy(), sw.cpu().numpy(), sig2.cpu().numpy()
+    assert V2 is None
+    # the values do not depend on whether the vectors are asked for
+    assert np.array_equal(sig, sig2)
     for i in range(nm):
-        U0, s0, Vt0 = trg.decompose(Ms[i], (d1, d2))
-        assert np.max(np.abs(sig[i] - s0)) <= 1e-13 * s0[0] * math.sqrt(n)
-        # vectors of well-separated values (relative gap > 1e-3) agree after the gauge
-        gaps = np.minimum(np.abs(np.diff(np.r_[np.inf, s0])), np.abs(np.diff(np.r_[s0, -np.inf])))
-        ok = (gaps > 1e-3 * s0) & (s0 > 1e-6 * s0[0])
-        err = np.max(np.abs(V[i][ok] - Vt0[ok]))
-        assert err < 1e-9, err
+        verr, vecerr, nchk = check_svd(Ms[i], (d1, d2), sig[i], V[i], int(sw[i]), tau, f"{d1}x{d2}#{i}")
+        log(f"  #{i}: |ds| {verr:.2e}  vectors checked {nchk} max err {vecerr:.2e}  sweeps {sw[i]}")
 
 
-def test_svd_ising_unfoldings():
+@pytest.mark.parametrize("tau", [0.0, 1e-11])
+def test_svd_ising_unfoldings(tau):
+    """The unfoldings of the shared chain's tensors at k = 8 (critical Ising,
+    five steps, both splits): the values and the candidate vectors."""
     torch, m = need_gpu()
-    log("svd_ising_unfoldings")
-    for (M, cs) in ising_unfoldings(8, 5):
-        U0, s0, Vt0 = trg.decompose(M, cs)
-        sig, V, sw = m.svd_batched(torch.tensor(M[None], device="cuda"), cs[0], cs[1])
-        sig, V = sig.cpu().numpy()[0], V.cpu().numpy()[0]
-        assert np.max(np.abs(sig - s0)) <= 1e-14 * s0[0] * M.shape[0]
-        c = esp.n_candidates(s0, 1e-11)
-        gaps = np.minimum(np.abs(np.diff(np.r_[np.inf, s0])), np.abs(np.diff(np.r_[s0, -np.inf])))
-        ok = (np.arange(len(s0)) < c) & (gaps > 1e-6 * s0[0])
-        assert np.max(np.abs(V[ok] - Vt0[ok])) < 1e-8
+    log(f"svd_ising_unfoldings tau={tau}")
+    for j, (M, cs) in enumerate(ising_unfoldings(8, 5)):
+        sig, V, sw = m.svd_batched(torch.tensor(M[None], device="cuda"), cs[0], cs[1], tau_null=tau)
+        check_svd(M, cs, sig.cpu().numpy()[0], V.cpu().numpy()[0], int(sw.cpu().numpy()[0]), tau, f"unfolding {j}")
+
+
+def test_svd_rejects_bad_arguments():
+    torch, m = need_gpu()
+    M = torch.zeros((1, 4, 4), dtype=torch.float64, device="cuda")
+    for tau in (-1e-3, 1.0, float("nan")):
+        with pytest.raises(m.MctrgError):
+            m.svd_batched(M, 2, 2, tau_null=tau)
+    with pytest.raises(m.MctrgError):
+        m.svd_batched(torch.zeros((1, 4225, 4225), dtype=torch.float64, device="cuda"), 65, 65)
 
 
 @pytest.mark.parametrize("k,mode", [(4, "shared"), (8, "shared"), (16, "shared"), (8, "topk"), (32, "shared")])
