@@ -128,6 +128,68 @@ def run_form(m, torch, args, dtype, tau, decomposition="svd"):
     return out
 
 
+def run_all_steps(m, torch, args, dtype, tau):
+    """All steps 0..n-1 of a fresh chain of the headline form in one timed
+    region (after the forms above, so that the GEMM tile autotuner has run:
+    one-time setup - library load, autotuning, chain allocation and T0
+    gather - stays outside)."""
+    k, B = args.k, args.batch
+    n_chain = args.warmup + args.steps
+    ts = m.init_tensor("site", [args.beta], [args.h])
+    chain = m.Chain(ts, B, n_steps=n_chain, k=k, dtype=dtype, seed=0, tau_null=tau)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    chain.step(n_chain)
+    chain.finish()
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1)
+    chain.close()
+    ts.close()
+    print(f"[bench] {dtype}: all {n_chain} steps in {ms:.1f} ms", flush=True)
+    return {"value": B * n_chain / (ms / 1e3), "unit": "sample-steps/s", "steps": n_chain, "ms_total": ms,
+            "note": f"steps 0..{n_chain - 1} of a fresh {B}-sample chain of the headline form (the small early "
+                    "steps included); setup and tile autotuning outside the timed region"}
+
+
+def contraction_alone(m, torch, args, dtypes):
+    """The coarse-graining GEMM of each contraction dtype with nothing beside
+    it: a one-part chain of the batch (one stream, so no other kernel runs
+    during the GEMM) is advanced to the steady shape (D = k), and the GEMM of
+    its next step is timed by the library's HIP events."""
+    k, B = args.k, args.batch
+    warm = 1
+    while True:   # steps until the bond dimension reaches k
+        D = 2
+        for _ in range(warm):
+            D = min(k, D * D)
+        if D >= k:
+            break
+        warm += 1
+    out = {}
+    for dt in dtypes:
+        ts = m.init_tensor("site", [args.beta], [args.h])
+        chain = m.Chain(ts, B, n_steps=warm + 2, k=k, dtype=dt, seed=0, profile=True, tau_null=TAU_NULL[dt],
+                        one_stream=True)
+        chain.step(warm + 1)   # the first steady step also runs the tile autotuner for this shape
+        p0 = chain.profile()
+        chain.step(1)
+        p1 = chain.profile()
+        chain.close()
+        ts.close()
+        n = p1["gemm_launches"] - p0["gemm_launches"]
+        ms = (p1["gemm_ms"] - p0["gemm_ms"]) / max(n, 1)
+        ach = gemm_flops(k) * B / (ms / 1e3) / 1e12 if ms > 0 else None
+        out[dt] = {"kernel": f"gemm_tn_kernel<{dt}>", "achieved": ach, "peak": PEAK_TFLOPS[dt], "unit": "TFLOP/s",
+                   "frac": ach / PEAK_TFLOPS[dt] if ach else None, "avg_launch_ms": ms, "launches": n}
+        print(f"[bench] {dt}: GEMM alone {ms:.3f} ms ({ach:.1f} TF/s)", flush=True)
+    return {"per_dtype": out, "batch": B, "shape": f"{k * k} x {k * k} x {k * k} per sample (k^2 x k^2 output, "
+                                                  "inner dimension D^2 = k^2)",
+            "flop_count": "2 k^6 per sample", "note": "one part (one stream): the GEMM dispatch has the GPU to "
+                                                      "itself; in the chains of the headline three parts overlap"}
+
+
 def kernel_records(r, args, dtype, tau):
     """Roofline records of the Jacobi and the 128-column QR update for one
     form (the dominant first)."""
@@ -266,6 +328,10 @@ def main():
                     help="candidate cut of the headline form (default: per contraction dtype, see TAU_NULL)")
     ap.add_argument("--cpu-samples", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-gemm-alone", action="store_true",
+                    help="skip the GEMM of every contraction dtype timed on its own")
+    ap.add_argument("--no-all-steps", action="store_true",
+                    help="skip the all-steps rate (a fresh chain of the headline form timed over every step)")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="after the timed region, copy this many MiB device-to-device (a plain copy kernel of known "
                          "size whose counter readings calibrate FETCH_SIZE / WRITE_SIZE)")
@@ -351,6 +417,10 @@ def main():
             "mean_difference_over_stderr": float((np.mean(phi_q) - np.mean(phi_s)) /
                                                  math.sqrt(sd_q ** 2 / len(phi_q) + sd_s ** 2 / len(phi_s))),
             "note": "same samples and draws addressing as the headline; shared chains (one tensor per level)"}
+    if not args.no_all_steps:
+        out["all_steps"] = run_all_steps(m, torch, args, args.dtype, tau)
+    if not args.no_gemm_alone:
+        out["mfma_contraction_alone"] = contraction_alone(m, torch, args, ("f64", "f32", "bf16", "fp8"))
     if not args.no_cpu_baseline:
         base, ores = cpu_baseline(args)
         out["cpu_baseline"] = base
