@@ -158,21 +158,24 @@ __global__ void cast_kernel(int64_t per, const double* __restrict__ A, const dou
 // K staged through LDS in chunks of 32.
 // ---------------------------------------------------------------------------
 template <int DT> struct Mma;
+// KSTEP: K per MFMA; BK: K per LDS tile (one barrier pair per tile), 32 for
+// the four-element MFMAs and 256 bytes of K per row for the narrow types, so
+// that a wave issues 4 x 4 x 8 (BF16: 4 x 4 x 4) MFMAs between barriers.
 template <> struct Mma<MCTRG_F64> {
   typedef double elt; typedef double acc_t; typedef f64x4 frag_c;
-  static constexpr int KSTEP = 4, PAD = 1;
+  static constexpr int KSTEP = 4, PAD = 1, BK = 32;
 };
 template <> struct Mma<MCTRG_F32> {
   typedef float elt; typedef float acc_t; typedef f32x4 frag_c;
-  static constexpr int KSTEP = 4, PAD = 1;
+  static constexpr int KSTEP = 4, PAD = 1, BK = 32;
 };
 template <> struct Mma<MCTRG_BF16> {
   typedef unsigned short elt; typedef float acc_t; typedef f32x4 frag_c;
-  static constexpr int KSTEP = 32, PAD = 8;
+  static constexpr int KSTEP = 32, PAD = 8, BK = 128;
 };
 template <> struct Mma<MCTRG_FP8_E4M3> {
   typedef unsigned char elt; typedef float acc_t; typedef f32x4 frag_c;
-  static constexpr int KSTEP = 32, PAD = 16;
+  static constexpr int KSTEP = 32, PAD = 16, BK = 256;
 };
 
 template <int DT>
@@ -208,9 +211,8 @@ __global__ __launch_bounds__(256) void gemm_tn_kernel(int M, int N, int K, const
   typedef typename Mma<DT>::acc_t acc_t;
   typedef typename Mma<DT>::frag_c frag_c;
   constexpr int WT = BM / 32;                              // MFMA tiles per wave side
-  constexpr int BK = 32, LD = BK + Mma<DT>::PAD, KS = Mma<DT>::KSTEP;
+  constexpr int BK = Mma<DT>::BK, LD = BK + Mma<DT>::PAD, KS = Mma<DT>::KSTEP;
   constexpr int EPL = (KS == 4) ? 1 : 8;                  // elements per lane per MFMA
-  constexpr int LOADS = BM * BK / 256;                    // elements per thread per operand and K tile
   __shared__ __attribute__((aligned(16))) elt As[BM * LD];
   __shared__ __attribute__((aligned(16))) elt Bs[BM * LD];
   const int64_t o = blockIdx.z;
@@ -237,29 +239,17 @@ __global__ __launch_bounds__(256) void gemm_tn_kernel(int M, int N, int K, const
   const bool vec = (M % BM == 0) && (N % BM == 0) && (K % BK == 0);
   const int vrow = tid / LPR, vk = (tid % LPR) * VB;
   uint4 va[ITERS], vb[ITERS];
-  // thread t loads LOADS consecutive K elements of row (t * LOADS) / BK
-  const int lrow = (tid * LOADS) / BK, lk = (tid * LOADS) % BK;
-  elt ra[LOADS], rb[LOADS];
-  auto gload = [&](int k0) {
-    if (vec) {
+  auto gload = [&](int k0) {   // the next tile into registers (tile-aligned shapes)
+    if (!vec) return;
 #pragma unroll
-      for (int it = 0; it < ITERS; ++it) {
-        const int row = it * RPI + vrow;
-        if (RPI * ITERS > BM && row >= BM) continue;
-        va[it] = *reinterpret_cast<const uint4*>(A + (size_t)(m0 + row) * K + k0 + vk);
-        vb[it] = *reinterpret_cast<const uint4*>(B + (size_t)(n0 + row) * K + k0 + vk);
-      }
-      return;
-    }
-    const int gm = m0 + lrow, gn = n0 + lrow;
-#pragma unroll
-    for (int x = 0; x < LOADS; ++x) {
-      const int gk = k0 + lk + x;
-      ra[x] = (gm < M && gk < K) ? A[(size_t)gm * K + gk] : elt(0);
-      rb[x] = (gn < N && gk < K) ? B[(size_t)gn * K + gk] : elt(0);
+    for (int it = 0; it < ITERS; ++it) {
+      const int row = it * RPI + vrow;
+      if (RPI * ITERS > BM && row >= BM) continue;
+      va[it] = *reinterpret_cast<const uint4*>(A + (size_t)(m0 + row) * K + k0 + vk);
+      vb[it] = *reinterpret_cast<const uint4*>(B + (size_t)(n0 + row) * K + k0 + vk);
     }
   };
-  auto lstore = [&]() {
+  auto lstore = [&](int k0) {
     if (vec) {
 #pragma unroll
       for (int it = 0; it < ITERS; ++it) {
@@ -275,15 +265,17 @@ __global__ __launch_bounds__(256) void gemm_tn_kernel(int M, int N, int K, const
       }
       return;
     }
-#pragma unroll
-    for (int x = 0; x < LOADS; ++x) {
-      As[lrow * LD + lk + x] = ra[x];
-      Bs[lrow * LD + lk + x] = rb[x];
+    // other shapes: element loads straight into LDS, zero outside M x K / N x K
+    for (int e = tid; e < BM * BK; e += 256) {
+      const int row = e / BK, kk = e % BK, gk = k0 + kk;
+      const int gm = m0 + row, gn = n0 + row;
+      As[row * LD + kk] = (gm < M && gk < K) ? A[(size_t)gm * K + gk] : elt(0);
+      Bs[row * LD + kk] = (gn < N && gk < K) ? B[(size_t)gn * K + gk] : elt(0);
     }
   };
   gload(0);
   for (int k0 = 0; k0 < K; k0 += BK) {
-    lstore();
+    lstore(k0);
     __syncthreads();
     if (k0 + BK < K) gload(k0 + BK);    // next K tile in flight during the MFMAs
 #pragma unroll
