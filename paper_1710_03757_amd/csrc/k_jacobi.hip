@@ -288,7 +288,7 @@ __device__ __forceinline__ double unit_cosine(double t) {
 // norm order, the larger half to the lower-numbered block (a few percent
 // fewer outer sweeps on TRG unfoldings).
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256, 3) void jacobi_round64_kernel(double* __restrict__ W, int n_pad, int ncol, int nb_all,
+__global__ __launch_bounds__(256, 4) void jacobi_round64_kernel(double* __restrict__ W, int n_pad, int ncol, int nb_all,
                                                                 const int* __restrict__ nb_job, int round,
                                                                 const int* __restrict__ active,
                                                                 int* __restrict__ rotated, int* __restrict__ pairs,
@@ -327,7 +327,7 @@ __global__ __launch_bounds__(256, 3) void jacobi_round64_kernel(double* __restri
   __shared__ double2 rcs[32];      // (c, s) of the round's rotations, by slot
   __shared__ double dg[2][64];     // diagonal of G by position, by round parity
   __shared__ int rank_s[64];       // output position of each index (decreasing new row norm)
-  __shared__ double xch[2][4][2][64];   // rows of Q^T handed to the neighbouring wave, by round parity
+  __shared__ double xch[4][2][64];      // rows of Q^T handed to the neighbouring wave
   __shared__ double redbuf[4];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -339,35 +339,36 @@ __global__ __launch_bounds__(256, 3) void jacobi_round64_kernel(double* __restri
   f64x4 acc[10];
 #pragma unroll
   for (int t = 0; t < 10; ++t) acc[t] = f64x4{0, 0, 0, 0};
-  double cur[4][4], nxt[4][4];
-  auto load_chunk = [&](int k0, double (&v)[4][4]) {
+  // Each wave takes 16-column chunks k0 = 16 wave + 64 i in two halves of 8
+  // columns: lane (lr, lg) holds columns k0 + 8 h + 2 lg + {0, 1} of row lr
+  // of every sub-block (one 16-byte load each, 64 contiguous bytes per row
+  // and half), which are the K indices of two k-steps.  The next half is
+  // loaded while the current one is multiplied; 48 VGPRs of operands and
+  // the 80 of the ten accumulator tiles keep four waves per SIMD.
+  double2 hc[4], hn[4];
+  const int go = lr * n_pad + 2 * lg;   // the lane's offset from a sub-block's uniform base
+  auto load_half = [&](int c, double2 (&v)[4]) {
 #pragma unroll
-    for (int sb = 0; sb < 4; ++sb) {
-      const double* p = sub[sb] + (size_t)lr * n_pad + k0 + 4 * lg;
-      double2 a01 = *reinterpret_cast<const double2*>(p);
-      double2 a23 = *reinterpret_cast<const double2*>(p + 2);
-      v[sb][0] = a01.x; v[sb][1] = a01.y; v[sb][2] = a23.x; v[sb][3] = a23.y;
-    }
+    for (int sb = 0; sb < 4; ++sb) v[sb] = *reinterpret_cast<const double2*>(sub[sb] + (go + c));
+  };
+  auto mfma_half = [&](const double2 (&v)[4]) {
+    int t = 0;
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+      for (int y = x; y < 4; ++y) {
+        acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(v[x].x, v[y].x, acc[t], 0, 0, 0);
+        acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(v[x].y, v[y].y, acc[t], 0, 0, 0);
+        ++t;
+      }
   };
   int k0 = 16 * wave;
-  if (k0 < ncol) load_chunk(k0, cur);
+  if (k0 < ncol) load_half(k0, hc);
   for (; k0 < ncol; k0 += 64) {
-    if (k0 + 64 < ncol) load_chunk(k0 + 64, nxt);
-#pragma unroll
-    for (int jj = 0; jj < 4; ++jj) {
-      int t = 0;
-#pragma unroll
-      for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = a; b < 4; ++b) {
-          acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(cur[a][jj], cur[b][jj], acc[t], 0, 0, 0);
-          ++t;
-        }
-    }
-#pragma unroll
-    for (int sb = 0; sb < 4; ++sb)
-#pragma unroll
-      for (int jj = 0; jj < 4; ++jj) cur[sb][jj] = nxt[sb][jj];
+    load_half(k0 + 8, hn);
+    mfma_half(hc);
+    if (k0 + 64 < ncol) load_half(k0 + 64, hc);
+    mfma_half(hn);
   }
   // partial tiles: waves 1..3 stage five tiles at a time, wave 0 adds them
   // to its own (same order for every entry), then stores G by position
@@ -456,7 +457,10 @@ __global__ __launch_bounds__(256, 3) void jacobi_round64_kernel(double* __restri
   // Q lives in registers, by position: wave w holds the Q^T rows at
   // positions 8w .. 8w + 7 (qr[0..7]) and 56 - 8w .. 63 - 8w (qr[8..15]),
   // lane = row of Q, so its slots 8w + a pair qr[a] with qr[15 - a]; each
-  // shift moves one row in from each neighbouring wave.
+  // shift moves one row in from each neighbouring wave.  The rows handed
+  // over in round r - 1 are read before the first barrier of round r and
+  // the new ones written after it, so one exchange buffer serves all rounds
+  // (with the G buffers below 40 KB of LDS: four workgroups per CU).
   //
   // The block grid is enumerated as 16 folded rows of 33 (row m and row
   // 31 - m); thread tid owns blocks tid, tid + 256 and (tid < 16) tid + 512.
@@ -496,6 +500,20 @@ __global__ __launch_bounds__(256, 3) void jacobi_round64_kernel(double* __restri
   for (int r = 0; r < 63; ++r) {
     const double* Gc = U + (r & 1) * kGpk;
     double* Gn = U + ((r + 1) & 1) * kGpk;
+    // Q: finish the shift of the previous round (its rows were handed over
+    // before that round's second barrier)
+    if (r > 0) {
+      double nq[16];
+#pragma unroll
+      for (int a = 0; a < 7; ++a) nq[a] = qr[a + 1];
+      nq[7] = ws < 3 ? xch[ws + 1][0][lane] : qr[8];          // position 8w + 8
+#pragma unroll
+      for (int b = 0; b < 7; ++b) nq[8 + b] = qr[9 + b];
+      nq[15] = ws > 0 ? xch[ws - 1][1][lane] : qr[1];         // position 64 - 8w (64 -> 1)
+      if (ws == 0) nq[0] = qr[0];                             // position 0 stays
+#pragma unroll
+      for (int a = 0; a < 16; ++a) qr[a] = nq[a];
+    }
     if (tid < 32) {
       const int x = tid, y = 63 - tid;
       const double gxx = dg[r & 1][x], gyy = dg[r & 1][y], gxy = Gc[own_rd];
@@ -514,20 +532,8 @@ __global__ __launch_bounds__(256, 3) void jacobi_round64_kernel(double* __restri
       Gn[own_wr] = gn;
     }
     __syncthreads();
-    // Q: finish the shift of the previous round, then rotate this round's slots
-    if (r > 0) {
-      const double (*xp)[2][64] = xch[(r - 1) & 1];
-      double nq[16];
-#pragma unroll
-      for (int a = 0; a < 7; ++a) nq[a] = qr[a + 1];
-      nq[7] = ws < 3 ? xp[ws + 1][0][lane] : qr[8];          // position 8w + 8
-#pragma unroll
-      for (int b = 0; b < 7; ++b) nq[8 + b] = qr[9 + b];
-      nq[15] = ws > 0 ? xp[ws - 1][1][lane] : qr[1];          // position 64 - 8w (64 -> 1)
-      if (ws == 0) nq[0] = qr[0];                             // position 0 stays
-#pragma unroll
-      for (int a = 0; a < 16; ++a) qr[a] = nq[a];
-    }
+    // Q: rotate this round's slots (every wave has read the previous
+    // round's hand-over before the barrier above, so it may be overwritten)
 #pragma unroll
     for (int a = 0; a < 8; ++a) {
       const double2 ct = rcs[8 * ws + a];
@@ -535,11 +541,8 @@ __global__ __launch_bounds__(256, 3) void jacobi_round64_kernel(double* __restri
       qr[a] = ct.x * fma(-ct.y, y, x);
       qr[15 - a] = ct.x * fma(ct.y, x, y);
     }
-    {
-      double (*xw)[2][64] = xch[r & 1];
-      xw[ws][0][lane] = qr[0];   // position 8w, wanted by wave w - 1
-      xw[ws][1][lane] = qr[8];   // position 56 - 8w, wanted by wave w + 1
-    }
+    xch[ws][0][lane] = qr[0];   // position 8w, wanted by wave w - 1
+    xch[ws][1][lane] = qr[8];   // position 56 - 8w, wanted by wave w + 1
     // G blocks: read from this round's buffer, store into the other.  With
     // J = c [[1, t], [-t, 1]] acting on the columns (x, y) -> (c (x - t y),
     // c (t x + y)), J_i^T A J_j = c_i c_j (the tangent products below).
@@ -573,14 +576,13 @@ __global__ __launch_bounds__(256, 3) void jacobi_round64_kernel(double* __restri
   }
   __syncthreads();
   {  // last shift (positions back to indices), then Q^T to LDS for the update
-    const double (*xp)[2][64] = xch[62 & 1];
     double nq[16];
 #pragma unroll
     for (int a = 0; a < 7; ++a) nq[a] = qr[a + 1];
-    nq[7] = ws < 3 ? xp[ws + 1][0][lane] : qr[8];
+    nq[7] = ws < 3 ? xch[ws + 1][0][lane] : qr[8];
 #pragma unroll
     for (int b = 0; b < 7; ++b) nq[8 + b] = qr[9 + b];
-    nq[15] = ws > 0 ? xp[ws - 1][1][lane] : qr[1];
+    nq[15] = ws > 0 ? xch[ws - 1][1][lane] : qr[1];
     if (ws == 0) nq[0] = qr[0];
 #pragma unroll
     for (int a = 0; a < 8; ++a) {
@@ -596,18 +598,17 @@ __global__ __launch_bounds__(256, 3) void jacobi_round64_kernel(double* __restri
   // fragments are read from LDS (64 consecutive doubles each, no bank
   // conflicts), which leaves the registers for the next chunk's loads, so
   // every wave keeps one chunk in flight while it multiplies the other.
-  auto row_ptr = [&](int r) -> double* {
+  // Addresses: a uniform row base (rows 0..31 of the pair in block I, 32..63
+  // in J) plus the lane's own offset of lg rows and lr columns, so that no
+  // per-lane 64-bit row pointers stay live across the loop.
+  auto urow = [&](int r) -> double* {
     return r < 32 ? rowI + (size_t)r * n_pad : rowJ + (size_t)(r - 32) * n_pad;
   };
-  auto load_b = [&](int c0, double (&v)[16]) {
+  const int lo = lg * n_pad + lr;
+  double bc[16];
+  for (int c0 = 16 * wave; c0 < ncol; c0 += 64) {
 #pragma unroll
-    for (int s = 0; s < 16; ++s) v[s] = row_ptr(4 * s + lg)[c0 + lr];
-  };
-  double bc[16], bn[16];
-  int c0 = 16 * wave;
-  if (c0 < ncol) load_b(c0, bc);
-  for (; c0 < ncol; c0 += 64) {
-    if (c0 + 64 < ncol) load_b(c0 + 64, bn);
+    for (int s = 0; s < 16; ++s) bc[s] = urow(4 * s)[lo + c0];       // row 4 s + lg
     asm volatile("" ::: "memory");   // keep the fragment reads inside the loop
     f64x4 out[4];
 #pragma unroll
@@ -620,9 +621,7 @@ __global__ __launch_bounds__(256, 3) void jacobi_round64_kernel(double* __restri
 #pragma unroll
     for (int t = 0; t < 4; ++t)
 #pragma unroll
-      for (int i = 0; i < 4; ++i) row_ptr(16 * t + acc_row_f64(lg, i))[c0 + lr] = out[t][i];
-#pragma unroll
-    for (int s = 0; s < 16; ++s) bc[s] = bn[s];
+      for (int i = 0; i < 4; ++i) urow(16 * t + 4 * i)[lo + c0] = out[t][i];   // row 16 t + acc_row_f64(lg, i)
   }
 }
 
