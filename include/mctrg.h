@@ -185,7 +185,8 @@ int32_t mctrg_capacity_dim(int32_t d0, int32_t k, int32_t n_steps);
  * one host thread each, so that the kernels of some parts fill the GPU while
  * another waits on a convergence count or runs latency-bound QR panels.
  * hip_stream waits for all parts before a call returns or completes.
- * Results do not depend on the split; MCTRG_ONE_STREAM keeps one part.
+ * Results do not depend on the split (bit for bit, see below);
+ * MCTRG_ONE_STREAM keeps one part.
  *
  * Run n_samples independent Monte Carlo samples (Section III).
  *   group_of_sample: host, n_samples group indices, or NULL (all group 0)
@@ -197,14 +198,13 @@ int32_t mctrg_capacity_dim(int32_t d0, int32_t k, int32_t n_steps);
  *                    ln of the normalisation (shared: max|T'| of the one
  *                    tensor; independent: sum over the level's tensors)
  * Per-sample results depend only on (seed, global sample id, group, k,
- * n_steps, mode, dtype, tau_null, n_det, decomposition), up to rounding:
- * every random draw is addressed by the global sample id, but the
- * decomposition's early QR stop, rank limit, number of QR steps and
- * deflation take one decision per part of a wave (the largest over its
- * decompositions), so the rounding of a sample - never more than the
- * approximation budget of tau_null / 10 times s_1 - can depend on the
- * samples that share its part.  Samples of different k run as concurrent
- * buckets.
+ * n_steps, mode, dtype, tau_null, n_det, decomposition), bit for bit: every
+ * random draw is addressed by the global sample id, and the decomposition's
+ * early QR stop, rank limit, number of QR steps and deflation are decided
+ * per decomposition (a batch runs its kernels to the largest extent, where
+ * the parts a decomposition has dropped are exact zeros), so neither the
+ * other samples of the batch, nor the waves, parts or buckets change a
+ * sample.  Samples of different k run as concurrent buckets.
  * Returns ENUMERIC if any sample failed (its sign is 0, its ln|Z~| NaN: a
  * non-finite normalisation, a zero trace or a decomposition that did not
  * converge); the other samples are valid.  Blocks until the outputs are

@@ -166,6 +166,9 @@ struct Chain {
          *scales = nullptr, *cbuf = nullptr, *lnc = nullptr, *lnc_steps = nullptr, *lnabs = nullptr;
   void *Xlp = nullptr, *Ylp = nullptr;
   double *S = nullptr, *Tws = nullptr, *W2 = nullptr, *Tws2 = nullptr, *W3 = nullptr, *Tscr = nullptr;
+  double* W4 = nullptr;         // deflated rows of R3 of the jobs that stop after three QRs (n_pad <= 1024)
+  int* three_job = nullptr;     // per job: stopped after three QRs
+  int* nb_first = nullptr;      // per job: active blocks after the first deflation
   int32_t* perm = nullptr;
   int32_t* colmap = nullptr;   // column re-ordering of the first QR (n_pad <= 1024)
   double* colnorm = nullptr;
@@ -220,7 +223,7 @@ struct Chain {
 
 // Lays out (or, when counting, sizes) every device buffer of a chain.
 void layout(Chain& c, Arena& ar) {
-  size_t tmax = 0, wmax = 0, nmax = 0, selmax = 0, sscr = 0, gmax = 0, xmax = 0, tnmax = 0, pmax = 0;
+  size_t tmax = 0, wmax = 0, w4max = 0, nmax = 0, selmax = 0, sscr = 0, gmax = 0, xmax = 0, tnmax = 0, pmax = 0;
   int64_t jmax = 0, omax = 0;
   for (int s = 0; s < c.n_steps; ++s) {
     const StepShape sh = c.shape(s);
@@ -229,6 +232,7 @@ void layout(Chain& c, Arena& ar) {
     tmax = std::max(tmax, (size_t)c.nsamp * sh.P * D4);
     tmax = std::max(tmax, (size_t)no * K4);
     wmax = std::max(wmax, (size_t)nj * sh.n_pad * sh.n_pad);
+    if (sh.n_pad <= 1024) w4max = std::max(w4max, (size_t)nj * sh.n_pad * sh.n_pad);
     nmax = std::max(nmax, (size_t)nj * sh.n);
     pmax = std::max(pmax, (size_t)nj * sh.n_pad);
     selmax = std::max(selmax, (size_t)nj * sh.kc);
@@ -248,6 +252,7 @@ void layout(Chain& c, Arena& ar) {
   c.S = ar.take<double>(wmax);
   c.W2 = ar.take<double>(wmax);
   c.W3 = ar.take<double>(wmax);
+  c.W4 = ar.take<double>(w4max);
   c.Tscr = ar.take<double>((size_t)jmax * kQrTscr);
   c.Tws = ar.take<double>((size_t)jmax * 32 * 1024);
   c.Tws2 = ar.take<double>((size_t)jmax * 32 * 1024);
@@ -290,6 +295,8 @@ void layout(Chain& c, Arena& ar) {
   c.jw.lastmod = ar.take<int>((size_t)jmax * kJacobiMaxBlocks);
   c.jw.lastchk = ar.take<int>((size_t)jmax * kJacobiMaxBlocks * kJacobiMaxBlocks);
   c.nb_job = ar.take<int>(jmax);
+  c.three_job = ar.take<int>(jmax);
+  c.nb_first = ar.take<int>(jmax);
   c.dnrm = ar.take<double>(pmax);
   c.dpos = ar.take<int32_t>(pmax);
 }
@@ -343,15 +350,16 @@ size_t chain_bytes(Chain& c) {
 // exactSVD), shared by the chains and the step-level SVD entry point.
 // ---------------------------------------------------------------------------
 struct DecompBufs {
-  double *S, *W, *W2, *W3, *Tscr, *Tws, *Tws2, *colnorm, *dnrm, *sigma;
+  double *S, *W, *W2, *W3, *W4, *Tscr, *Tws, *Tws2, *colnorm, *dnrm, *sigma;
   int32_t *perm, *colmap, *dpos, *order;
-  int* nb_job;
+  int *nb_job, *three_job, *nb_first;
   JacobiWork jw;
 };
 
 DecompBufs decomp_bufs(const Chain& c) {
-  return DecompBufs{c.S,    c.W,     c.W2,   c.W3,     c.Tscr,  c.Tws, c.Tws2, c.colnorm, c.dnrm,
-                    c.sigma, c.perm, c.colmap, c.dpos, c.order, c.nb_job, c.jw};
+  return DecompBufs{c.S,    c.W,      c.W2,    c.W3,   c.W4,    c.Tscr,   c.Tws,       c.Tws2,     c.colnorm,
+                    c.dnrm, c.sigma,  c.perm,  c.colmap, c.dpos, c.order, c.nb_job, c.three_job, c.nb_first,
+                    c.jw};
 }
 
 struct DecompCtl {
@@ -367,10 +375,12 @@ struct DecompCtl {
 // Where the result is: the rows Wj whose norms are the singular values
 // (sigma / order hold them sorted), and which orthogonal factors map the
 // normalised rows to the right singular vectors: Q2 (W / Tws2) and Q4 (S /
-// Tws) after five QRs (qr5 && !three), Q2 alone after three (three, or qr
-// without qr5), none on the direct route.
+// Tws) after five QRs (qr5 && !three; nob, if not NULL, marks per job those
+// that stopped after three, for which Q4 is not applied), Q2 alone after
+// three (three: every job, or qr without qr5), none on the direct route.
 struct DecompOut {
   double* Wj = nullptr;
+  const int* nob = nullptr;
   bool qr5 = false, qr = false, three = false, qr_basis = false;
   int jcols = 0;    // the Jacobi rows are zero from this column on (0: none)
   int sweeps = 0;   // Jacobi sweeps of the slowest job
@@ -406,16 +416,18 @@ hipError_t decompose(int64_t nj, int n, int D, int n_pad, const double* T, const
     stop.budget = approx_budget(ctl.tau);
     stop.dev = b.jw.counter;
     stop.host = b.jw.counter_host;
+    stop.rows_job = b.nb_job;   // free until the rank rows below
     HKE(run_qr1(nj, n, D, n_pad, T, src, split, b.perm, b.dpos, b.S, b.W, b.Tscr, b.colmap, b.colnorm, st, &stop));
     // The first QR re-orders the columns by norm, so the rows of R1 come in
     // roughly decreasing norm: the later QRs run over the leading ncols
-    // columns only, where the rows from ncols on hold at most the
-    // approximation budget in total (they are set to zero, which moves the
-    // singular values by at most their Frobenius norm).
+    // columns only.  Every job's rows of R1 from its own limit on hold at
+    // most the approximation budget in total and are set to zero (which
+    // moves the singular values by at most their Frobenius norm); ncols is
+    // the largest limit, and a job's zero columns below it are exact no-ops.
     int rows1 = 0;
     HKE(run_rank_rows(nj, n_pad, ctl.tau, b.W, b.dnrm, b.nb_job, b.jw.counter, b.jw.counter_host, &rows1, st));
     const int ncols = std::min(n_pad, std::max(128, 128 * ceil_div(rows1, 128)));
-    HKE(run_qr23(nj, n_pad, ncols, b.W, b.Tws2, b.W2, b.W3, b.Tscr, st, ctl.tq, ctl.tq_flops));
+    HKE(run_qr23(nj, n_pad, ncols, b.W, b.Tws2, b.W2, b.W3, b.Tscr, st, ctl.tq, ctl.tq_flops, b.nb_job));
     if (qr_basis) {
       // the cheaper decomposition: the basis V = P Q2 (Q4) of three (five) QR
       // steps, the terms (M v_j) v_j^T weighted by |M v_j| = the column norms
@@ -426,19 +438,26 @@ hipError_t decompose(int64_t nj, int n, int D, int n_pad, const double* T, const
       return launch_qr_basis(nj, n, n_pad, ncols, b.W3, b.dnrm, b.W2, b.sigma, b.order, st);
     }
     out.jcols = ncols;
-    // The QR iteration stops after three steps when the rows left to rotate
-    // are at most half of the matrix (a cut above the tensor's rounding floor
-    // deflates its noise subspace): the Jacobi on them then costs less than
-    // the fourth and fifth QR would save.  Otherwise those follow.
-    HKE(run_deflate(nj, n_pad, ctl.tau, b.W3, b.S, b.nb_job, b.dnrm, b.dpos, b.jw.counter, b.jw.counter_host, &nb_max,
-                    st));
-    if (2 * nb_max * jacobi_block_rows(n_pad) <= n_pad) {
+    // The QR iteration of a job stops after three steps when its rows left to
+    // rotate are at most half of the matrix (a cut above the tensor's
+    // rounding floor deflates its noise subspace): the Jacobi on them then
+    // costs less than the fourth and fifth QR would save.  Otherwise those
+    // follow.  Decided per job: in a batch of both kinds the fourth and
+    // fifth QR run on all, and the jobs that stop after three take back
+    // their deflated rows of R3 (kept in W4) before the Jacobi.
+    HKE(run_deflate(nj, n_pad, ctl.tau, b.W3, b.W4, b.nb_job, b.dnrm, b.dpos, b.jw.counter, b.jw.counter_host,
+                    &nb_max, st));
+    int n_five = 0;
+    HKE(run_choose_qr_count(nj, n_pad, b.nb_job, b.three_job, b.nb_first, b.jw.counter, b.jw.counter_host, &n_five,
+                            st));
+    if (n_five == 0) {
       out.three = true;
-      Wj = b.S;          // W / Tws2 keep Q2
+      Wj = b.W4;         // W / Tws2 keep Q2
     } else {
       HKE(run_qr45(nj, n_pad, ncols, b.S, b.W2, b.Tws, b.W3, b.Tscr, st, ctl.tq, ctl.tq_flops));
       rows = b.W3;       // W / Tws2 keep Q2, S / Tws keep Q4
       Wj = b.W2;
+      if (n_five < nj) out.nob = b.three_job;
     }
   } else if (qr) {
     HKE(run_qr3_precondition(nj, n, D, n_pad, T, src, split, b.perm, b.dpos, b.S, b.Tws, b.W, b.Tws2, b.W2, b.colmap,
@@ -448,9 +467,17 @@ hipError_t decompose(int64_t nj, int n, int D, int n_pad, const double* T, const
     HKE(launch_unfold(nj, D, n_pad, T, src, split, b.W2, st));
     HKE(launch_iota(nj, n_pad, b.perm, st));
   }
-  if (!out.three)
-    HKE(run_deflate(nj, n_pad, ctl.tau, rows, Wj, b.nb_job, b.dnrm, b.dpos, b.jw.counter, b.jw.counter_host, &nb_max,
+  if (!out.three) {
+    int nb2 = 0;
+    HKE(run_deflate(nj, n_pad, ctl.tau, rows, Wj, b.nb_job, b.dnrm, b.dpos, b.jw.counter, b.jw.counter_host, &nb2,
                     st));
+    if (out.nob) {   // the jobs that stopped after three QRs
+      HKE(launch_keep_three(nj, n_pad, b.three_job, b.W4, Wj, b.nb_first, b.nb_job, st));
+      nb_max = std::max(nb_max, nb2);
+    } else {
+      nb_max = nb2;
+    }
+  }
   HKE(run_jacobi(nj, n_pad, Wj, b.jw, kMaxSweeps, st, ctl.tj, &out.sweeps, b.nb_job, nb_max, ctl.sweep_hist,
                  out.jcols, ctl.blind));
   out.Wj = Wj;
@@ -610,7 +637,7 @@ int chain_step(Chain& c) {
   if (qr5 && !three) {
     // z = Q2 Q4 y (in F as scratch), v = P z into G with the gauge, u = M v / s
     CKH(launch_apply_q1(nj, sh.n, sh.n_pad, sh.kc, c.W, nullptr, c.Tws2, c.S, c.Tws, Wj, c.sigma, c.order, c.kept,
-                        c.sel, c.weight, c.F, c.st));
+                        c.sel, c.weight, c.F, c.st, dout.nob));
     CKH(launch_scatter_G(nj, sh.D, sh.n_pad, sh.kc, c.F, c.perm, c.colmap, c.kept, c.G, c.st));
     CKH(launch_factor_F(nj, sh.D, sh.kc, c.Ta, c.src, c.split, c.sigma, c.kept, c.sel, c.G, c.Gt, c.F, c.st));
   } else if (qr) {
@@ -1311,6 +1338,7 @@ int mctrg_svd_batched(int64_t n_mats, int32_t d1, int32_t d2, const double* M, d
     b.W = ar.take<double>(nm * per);
     b.W2 = ar.take<double>(nm * per);
     b.W3 = ar.take<double>(nm * per);
+    b.W4 = ar.take<double>(n_pad <= 1024 ? nm * per : 0);
     b.Tscr = ar.take<double>((size_t)nm * kQrTscr);
     b.Tws = ar.take<double>((size_t)nm * 32 * 1024);
     b.Tws2 = ar.take<double>((size_t)nm * 32 * 1024);
@@ -1322,6 +1350,8 @@ int mctrg_svd_batched(int64_t n_mats, int32_t d1, int32_t d2, const double* M, d
     b.dpos = ar.take<int32_t>((size_t)nm * n_pad);
     b.order = ar.take<int32_t>((size_t)nm * n);
     b.nb_job = ar.take<int>(nm);
+    b.three_job = ar.take<int>(nm);
+    b.nb_first = ar.take<int>(nm);
     b.jw.active = ar.take<int>(nm);
     b.jw.rotated = ar.take<int>(nm);
     b.jw.sweeps = ar.take<int>(nm);
@@ -1369,7 +1399,7 @@ int mctrg_svd_batched(int64_t n_mats, int32_t d1, int32_t d2, const double* M, d
     hipError_t e = launch_select_all(nm, n, sigma_out, kept, sel, wgt, st);
     if (e == hipSuccess)
       e = launch_apply_q1(nm, n, n_pad, n, b.W, nullptr, b.Tws2, five ? b.S : nullptr, five ? b.Tws : nullptr, out.Wj,
-                          sigma_out, b.order, kept, sel, wgt, X, st);
+                          sigma_out, b.order, kept, sel, wgt, X, st, out.nob);
     if (e == hipSuccess) e = launch_scatter_V(nm, n, d2, n_pad, X, b.perm, out.qr5 ? b.colmap : nullptr, kept, V_out, st);
     if (e != hipSuccess) rc = MCTRG_EDEVICE;
   }

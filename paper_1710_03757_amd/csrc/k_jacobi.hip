@@ -923,6 +923,65 @@ hipError_t run_deflate(int64_t njobs, int n_pad, double tau_null, const double* 
   return hipGetLastError();
 }
 
+// The decomposition of a job stops after three QR steps when its rows left
+// to rotate after the deflation are at most half of the matrix (2 nb brows
+// <= n_pad), else it takes five; decided per job, so that a job's result
+// does not depend on the others in its batch.  three[j] / nb_first[j]: the
+// decision and the active blocks after this first deflation; *count: the
+// jobs that take five.
+__global__ void choose_qr_count_kernel(int64_t njobs, int n_pad, int brows, const int* __restrict__ nb_job,
+                                       int* __restrict__ three, int* __restrict__ nb_first, int* __restrict__ count) {
+  const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  int five = 0;
+  if (j < njobs) {
+    const int nb = nb_job[j];
+    const int t = 2 * nb * brows <= n_pad ? 1 : 0;
+    three[j] = t;
+    nb_first[j] = nb;
+    five = 1 - t;
+  }
+  unsigned long long m = __ballot(five);
+  if ((threadIdx.x & 63) == 0 && m) atomicAdd(count, __popcll(m));
+}
+
+hipError_t run_choose_qr_count(int64_t njobs, int n_pad, const int* nb_job, int* three, int* nb_first,
+                               int* scratch_dev, int* scratch_host, int* n_five, hipStream_t stream) {
+  if (njobs == 0) { *n_five = 0; return hipSuccess; }
+  hipLaunchKernelGGL(zero_ints_kernel, dim3(1), dim3(64), 0, stream, 1, scratch_dev);
+  hipLaunchKernelGGL(choose_qr_count_kernel, dim3((unsigned)ceil_div(njobs, 256)), dim3(256), 0, stream, njobs, n_pad,
+                     jacobi_block_rows(n_pad), nb_job, three, nb_first, scratch_dev);
+  hipError_t e = hipMemcpyAsync(scratch_host, scratch_dev, sizeof(int), hipMemcpyDeviceToHost, stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) return e;
+  *n_five = *scratch_host;
+  return hipGetLastError();
+}
+
+// The jobs that stop after three QRs (three[j]) take back their deflated
+// rows of R3 (Wsrc) as the Jacobi input (Wdst) and their active block count.
+__global__ void keep_three_kernel(int n_pad, const int* __restrict__ three, const double* __restrict__ Wsrc,
+                                  double* __restrict__ Wdst, const int* __restrict__ nb_first, int* __restrict__ nb_job) {
+  const int64_t job = blockIdx.y;
+  if (!three[job]) return;
+  const size_t per = (size_t)n_pad * n_pad;
+  const double2* src = reinterpret_cast<const double2*>(Wsrc + job * per);
+  double2* dst = reinterpret_cast<double2*>(Wdst + job * per);
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < per / 2; e += (size_t)gridDim.x * blockDim.x)
+    dst[e] = src[e];
+  if (blockIdx.x == 0 && threadIdx.x == 0) nb_job[job] = nb_first[job];
+}
+
+hipError_t launch_keep_three(int64_t njobs, int n_pad, const int* three, const double* Wsrc, double* Wdst,
+                             const int* nb_first, int* nb_job, hipStream_t stream) {
+  if (njobs == 0) return hipSuccess;
+  const size_t half = (size_t)n_pad * n_pad / 2;
+  int gx = (int)((half + 255) / 256);
+  if (gx > 512) gx = 512;
+  hipLaunchKernelGGL(keep_three_kernel, dim3(gx, (unsigned)njobs), dim3(256), 0, stream, n_pad, three, Wsrc, Wdst,
+                     nb_first, nb_job);
+  return hipGetLastError();
+}
+
 hipError_t run_rank_rows(int64_t njobs, int n_pad, double tau_null, const double* W, double* nrm, int* last,
                          int* scratch_dev, int* scratch_host, int* rows_max, hipStream_t stream) {
   if (njobs == 0) { *rows_max = 0; return hipSuccess; }

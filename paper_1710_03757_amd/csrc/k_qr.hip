@@ -1308,11 +1308,15 @@ __global__ __launch_bounds__(256, 3) void qr_trailing128_kernel(int64_t njobs, i
 // norms (ties by position), by permuting the column map.  One workgroup per
 // job, bitonic sort in LDS.
 __global__ __launch_bounds__(256) void resort_cols_kernel(int n_pad, int j0, const double* __restrict__ colnorm,
-                                                          int32_t* __restrict__ colmap) {
+                                                          int32_t* __restrict__ colmap,
+                                                          const int* __restrict__ stopped) {
   __shared__ double key[1024];
   __shared__ int idx[1024];
   __shared__ int32_t old[1024];
   const int64_t job = blockIdx.x;
+  // a job whose first QR has stopped keeps its column order (the columns it
+  // did not factor are dropped, whatever the other jobs of the batch do)
+  if (stopped && stopped[job] < n_pad) return;
   const int m = n_pad - j0;
   int P = 1;
   while (P < m) P <<= 1;
@@ -1346,12 +1350,15 @@ __global__ __launch_bounds__(256) void resort_cols_kernel(int n_pad, int j0, con
 
 // W[r][c] = R[r][c] = S[colmap[c]][r] for r <= c, r < rlim and c < clim,
 // else 0 (rows of R for the Jacobi or the next QR; colmap NULL: identity;
-// rlim / clim multiples of 32: the rows and columns of R known to be zero).
+// rlim / clim multiples of 32: the rows and columns of R known to be zero;
+// rlim_job (or NULL): a lower row limit per job, a multiple of 32).
 // One 32 x 32 tile per workgroup, transposed through LDS; tiles wholly below
 // the diagonal or beyond the limits are written as zeros without reading S.
 __global__ void r_rows_kernel(int n_pad, const double* __restrict__ S, double* __restrict__ W,
-                              const int32_t* __restrict__ colmap, int rlim, int clim) {
+                              const int32_t* __restrict__ colmap, int rlim, int clim,
+                              const int* __restrict__ rlim_job = nullptr) {
   const int64_t job = blockIdx.z;
+  if (rlim_job) rlim = min(rlim, rlim_job[job]);
   __shared__ double tile[32][33];
   const size_t per = (size_t)n_pad * n_pad;
   const int bx = blockIdx.x * 32, by = blockIdx.y * 32;   // bx: column c block, by: row r block
@@ -1386,14 +1393,19 @@ __global__ void r_rows_kernel(int n_pad, const double* __restrict__ S, double* _
 // the factored rows) of the columns from logical position j0 on, summed,
 // against budget_sq times the squared leading diagonal entry of R (at most
 // s_1^2): dropping that rest perturbs M P by at most its Frobenius norm, so
-// the singular values move by at most sqrt(budget_sq) s_1; *any becomes 1
-// when some job still exceeds it.
+// the singular values move by at most sqrt(budget_sq) s_1.  A job within it
+// stops here (stopped[job] = j0: its rows of R from j0 on are dropped and
+// its column order is frozen, so that its result does not depend on the
+// other jobs, which the batch keeps factoring); *any becomes 1 while some
+// job has not stopped.
 __global__ __launch_bounds__(256) void trailing_above_kernel(int n_pad, int j0, double budget_sq,
                                                              const double* __restrict__ S,
                                                              const int32_t* __restrict__ colmap,
-                                                             const double* __restrict__ colnorm, int* __restrict__ any) {
+                                                             const double* __restrict__ colnorm, int* __restrict__ any,
+                                                             int* __restrict__ stopped) {
   const int64_t job = blockIdx.x;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  if (stopped[job] < n_pad) return;   // stopped at an earlier check (uniform)
   const int32_t* cm = colmap + job * n_pad;
   __shared__ double red[4];
   double sum = 0.0;
@@ -1404,7 +1416,29 @@ __global__ __launch_bounds__(256) void trailing_above_kernel(int n_pad, int j0, 
   if (tid == 0) {
     const double tot = (red[0] + red[1]) + (red[2] + red[3]);
     const double r00 = S[(size_t)job * n_pad * n_pad + (size_t)cm[0] * n_pad];
-    if (!(tot <= budget_sq * r00 * r00)) atomicMax(any, 1);   // NaN counts as above
+    if (tot <= budget_sq * r00 * r00) stopped[job] = j0;
+    else atomicMax(any, 1);   // NaN counts as above
+  }
+}
+
+__global__ void fill_int_kernel(int64_t n, int* __restrict__ p, int v) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+// Rows of R1 from each job's own rank limit on become zero: rows >= the
+// job's rank rows rounded up to 128 (at least 128, at most n_pad), as a
+// batch of that job alone would set them.  One workgroup per 8 rows and job.
+__global__ void zero_rows_from_kernel(int n_pad, double* __restrict__ W, const int* __restrict__ rows_job) {
+  const int64_t job = blockIdx.y;
+  const int r0 = 8 * blockIdx.x;
+  const int rk = rows_job[job];
+  const int from = min(n_pad, max(128, 128 * ((rk + 127) / 128)));
+  if (r0 + 7 < from) return;
+  double* Wj = W + job * (size_t)n_pad * n_pad;
+  for (int e = threadIdx.x; e < 8 * n_pad; e += 256) {
+    const int r = r0 + e / n_pad;
+    if (r >= from) Wj[(size_t)r * n_pad + e % n_pad] = 0.0;
   }
 }
 
@@ -1485,19 +1519,23 @@ static hipError_t qr_factor_t(int64_t njobs, int n_pad, double* S, double* Tws, 
     // trailing columns per 64 columns instead of six.
     hipError_t e = launch_iota(njobs, n_pad, colmap, stream);
     if (e != hipSuccess) return e;
+    int* const stopped = stop ? stop->rows_job : nullptr;
+    if (stopped)
+      hipLaunchKernelGGL(fill_int_kernel, dim3((unsigned)ceil_div(njobs, 256)), dim3(256), 0, stream, njobs, stopped,
+                         n_pad);
     const int64_t ts = keep_T ? (int64_t)n_pad * 32 : 2048;
     for (int j = 0; j < n_pad; j += 64) {
       const int64_t o1 = keep_T ? (int64_t)(j / 32) * 1024 : 0, o2 = keep_T ? o1 + 1024 : 1024;
       if (j > 0)
         hipLaunchKernelGGL(resort_cols_kernel, dim3((unsigned)njobs), dim3(256), 0, stream, n_pad, j,
-                           (const double*)colnorm, colmap);
+                           (const double*)colnorm, colmap, (const int*)stopped);
       launch_panel32(dim3((unsigned)njobs), dim3(256), 0, stream, n_pad, j, S, Tws, ts, o1, (const int32_t*)colmap);
       const int rest = n_pad - j - 32;
       if (rest <= 0) break;
       hipLaunchKernelGGL(qr_trailing32_kernel, xcd_tile_grid(ceil_div(rest, 64), njobs), dim3(256), 0, stream, njobs,
                          n_pad, j, n_pad, S, (const double*)Tws, ts, o1, (const int32_t*)colmap, colnorm, 1);
       hipLaunchKernelGGL(resort_cols_kernel, dim3((unsigned)njobs), dim3(256), 0, stream, n_pad, j + 32,
-                         (const double*)colnorm, colmap);
+                         (const double*)colnorm, colmap, (const int*)stopped);
       hipLaunchKernelGGL(qr_trailing32_kernel, xcd_tile_grid(1, njobs), dim3(256), 0, stream, njobs, n_pad, j, j + 64,
                          S, (const double*)Tws, ts, o1, (const int32_t*)colmap, (double*)nullptr, 0);
       launch_panel32(dim3((unsigned)njobs), dim3(256), 0, stream, n_pad, j + 32, S, Tws, ts, o2,
@@ -1507,11 +1545,11 @@ static hipError_t qr_factor_t(int64_t njobs, int n_pad, double* S, double* Tws, 
                          (const double*)Tws, ts, o1, o2, T64, (const int32_t*)colmap);
       hipLaunchKernelGGL(qr_trailing64_kernel, xcd_tile_grid(ceil_div(n_pad - j - 64, 64), njobs), dim3(256), 0,
                          stream, njobs, n_pad, j, n_pad, S, (const double*)T64, (const int32_t*)colmap, colnorm);
-      if (stop) {   // the remaining columns within the budget in every job: stop here
+      if (stop) {   // every job within the budget (each stopped at its own check): stop here
         hipLaunchKernelGGL(set_int_kernel, dim3(1), dim3(1), 0, stream, stop->dev, 0);
         hipLaunchKernelGGL(trailing_above_kernel, dim3((unsigned)njobs), dim3(256), 0, stream, n_pad, j + 64,
                            stop->budget * stop->budget, (const double*)S, (const int32_t*)colmap,
-                           (const double*)colnorm, stop->dev);
+                           (const double*)colnorm, stop->dev, stopped);
         hipError_t e = hipMemcpyAsync(stop->host, stop->dev, sizeof(int), hipMemcpyDeviceToHost, stream);
         if (e == hipSuccess) e = hipStreamSynchronize(stream);
         if (e != hipSuccess) return e;
@@ -1547,7 +1585,7 @@ static hipError_t qr_factor_t(int64_t njobs, int n_pad, double* S, double* Tws, 
                            n_pad, j, S, Tws, t_stride, t_off, (const int32_t*)colmap, colmap ? colnorm : nullptr);
       if (colmap)
         hipLaunchKernelGGL(resort_cols_kernel, dim3((unsigned)njobs), dim3(256), 0, stream, n_pad, j + PW,
-                           (const double*)colnorm, colmap);
+                           (const double*)colnorm, colmap, (const int*)nullptr);
     }
   }
   return hipGetLastError();
@@ -1647,18 +1685,24 @@ hipError_t run_qr1(int64_t njobs, int n, int D, int n_pad, const double* T, cons
   const dim3 rg(n_pad / 32, n_pad / 32, (unsigned)njobs);
   // rows from the stop on (the unfactored rest, within the budget) are written as zero
   hipLaunchKernelGGL(r_rows_kernel, rg, dim3(256), 0, stream, n_pad, S1, W1, (const int32_t*)colmap,
-                     stop ? stop->rows : n_pad, n_pad);
+                     stop ? stop->rows : n_pad, n_pad, stop ? (const int*)stop->rows_job : nullptr);
   return hipGetLastError();
 }
 
 hipError_t run_qr23(int64_t njobs, int n_pad, int ncols, double* W1, double* Tws2, double* W2, double* W3,
-                    double* Tscr, hipStream_t stream, KernelTimer* tq, double* tq_flops) {
+                    double* Tscr, hipStream_t stream, KernelTimer* tq, double* tq_flops, const int* rows_job) {
   if (njobs == 0) return hipSuccess;
   if (n_pad > 1024 || ncols <= 0 || ncols > n_pad || (ncols % 128 && ncols != n_pad)) return hipErrorInvalidValue;
   if (tq && !tq_flops) return hipErrorInvalidValue;
   double* T64 = Tscr + (size_t)njobs * 2048;
   const dim3 rg(n_pad / 32, n_pad / 32, (unsigned)njobs);
-  if (ncols < n_pad) {   // the rows of R1 from ncols on (within the budget in total) become zero
+  if (rows_job) {
+    // every job's rows of R1 from its own limit on (within the budget in
+    // total) become zero; the batch factors the leading ncols columns, the
+    // largest limit, where the zero columns of a job are exact no-ops
+    hipLaunchKernelGGL(zero_rows_from_kernel, dim3((unsigned)(n_pad / 8), (unsigned)njobs), dim3(256), 0, stream,
+                       n_pad, W1, rows_job);
+  } else if (ncols < n_pad) {   // the rows of R1 from ncols on (within the budget in total) become zero
     const int64_t nz = (int64_t)(n_pad - ncols) * n_pad;
     hipLaunchKernelGGL(zero_tail_kernel, dim3((unsigned)ceil_div(nz, 256), (unsigned)njobs), dim3(256), 0, stream, nz,
                        W1 + (int64_t)ncols * n_pad, (int64_t)n_pad * n_pad);
@@ -1681,7 +1725,7 @@ hipError_t run_qr5_precondition(int64_t njobs, int n, int D, int n_pad, const do
   hipError_t e = run_qr1(njobs, n, D, n_pad, T, src, split, perm, iperm, S1, W1, Tscr, colmap, colnorm, stream,
                          nullptr);
   if (e != hipSuccess) return e;
-  e = run_qr23(njobs, n_pad, n_pad, W1, Tws2, W2, W3, Tscr, stream, tq, tq_flops);
+  e = run_qr23(njobs, n_pad, n_pad, W1, Tws2, W2, W3, Tscr, stream, tq, tq_flops, nullptr);
   if (e != hipSuccess || nqr == 3) return e;
   return run_qr45(njobs, n_pad, n_pad, S1, W2, Tws4, W3, Tscr, stream, tq, tq_flops);
 }
@@ -1794,7 +1838,8 @@ __global__ __launch_bounds__(256) void apply_q1_mfma_kernel(int n, int n_pad, in
                                                             const int32_t* __restrict__ order,
                                                             const int32_t* __restrict__ kept,
                                                             const int32_t* __restrict__ sel,
-                                                            const double* __restrict__ weight, double* __restrict__ F) {
+                                                            const double* __restrict__ weight, double* __restrict__ F,
+                                                            const int* __restrict__ nob) {
   extern __shared__ unsigned char smem[];
   double* X = reinterpret_cast<double*>(smem);   // [n_pad][16]
   double* Yp = X + (size_t)n_pad * 16;     // [4 waves][2 tiles][256]
@@ -1826,7 +1871,8 @@ __global__ __launch_bounds__(256) void apply_q1_mfma_kernel(int n, int n_pad, in
     X[e] = rowp[v] ? rowp[v][r] / sv[v] : 0.0;
   }
   __syncthreads();
-  for (int set = S1b ? 0 : 1; set < 2; ++set) {   // the second factor (if any) first
+  // the second factor (if any, and not masked off for this job) first
+  for (int set = (S1b && !(nob && nob[job])) ? 0 : 1; set < 2; ++set) {
   const double* Sj = (set == 0 ? S1b : S1) + (size_t)job * n_pad * n_pad;
   const int32_t* cm = (set == 1 && colmap) ? colmap + job * n_pad : nullptr;   // V_d is stored in column cm[d]
   const double* Tj = (set == 0 ? Tws1b : Tws1) + (size_t)job * n_pad * 32;
@@ -1930,7 +1976,8 @@ __global__ __launch_bounds__(512) void apply_q_reg_kernel(int n, int n_pad, int 
                                                           const int32_t* __restrict__ order,
                                                           const int32_t* __restrict__ kept,
                                                           const int32_t* __restrict__ sel,
-                                                          const double* __restrict__ weight, double* __restrict__ F) {
+                                                          const double* __restrict__ weight, double* __restrict__ F,
+                                                            const int* __restrict__ nob) {
   const int64_t job = blockIdx.x;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int lr = lane & 15, lg = lane >> 4;
@@ -1967,7 +2014,8 @@ __global__ __launch_bounds__(512) void apply_q_reg_kernel(int n, int n_pad, int 
         xr[t][vt][i] = (g < ntile && rowp[v]) ? rowp[v][r] / sv[v] : 0.0;
       }
     }
-  for (int set = S1b ? 0 : 1; set < 2; ++set) {   // the second factor (if any) first
+  // the second factor (if any, and not masked off for this job) first
+  for (int set = (S1b && !(nob && nob[job])) ? 0 : 1; set < 2; ++set) {
     const double* Sj = (set == 0 ? S1b : S1) + (size_t)job * n_pad * n_pad;
     const int32_t* cm = (set == 1 && colmap) ? colmap + job * n_pad : nullptr;   // V_d is stored in column cm[d]
     const double* Tj = (set == 0 ? Tws1b : Tws1) + (size_t)job * n_pad * 32;
@@ -2060,19 +2108,19 @@ size_t apply_q1_mfma_lds(int n_pad) { return sizeof(double) * ((size_t)n_pad * 1
 hipError_t launch_apply_q1(int64_t njobs, int n, int n_pad, int kcap, const double* S1, const int32_t* colmap,
                            const double* Tws1, const double* S1b, const double* Tws1b, const double* W2,
                            const double* sigma, const int32_t* order, const int32_t* kept, const int32_t* sel,
-                           const double* weight, double* F, hipStream_t stream) {
+                           const double* weight, double* F, hipStream_t stream, const int* nob) {
   if (njobs == 0) return hipSuccess;
   if (S1b && n_pad > 1024) return hipErrorInvalidValue;   // two factors only with 32-column panels
   if (n_pad <= 1024 && kcap > 16 && kcap <= 32) {
     hipLaunchKernelGGL(apply_q_reg_kernel, dim3((unsigned)njobs), dim3(512), 0, stream, n, n_pad, kcap, S1, colmap,
-                       Tws1, S1b, Tws1b, W2, sigma, order, kept, sel, weight, F);
+                       Tws1, S1b, Tws1b, W2, sigma, order, kept, sel, weight, F, nob);
   } else if (n_pad <= 1024) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&apply_q1_mfma_kernel),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)apply_q1_mfma_lds(n_pad));
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(apply_q1_mfma_kernel, dim3((kcap + 15) / 16, (unsigned)njobs), dim3(256),
                        apply_q1_mfma_lds(n_pad), stream, n, n_pad, kcap, S1, colmap, Tws1, S1b, Tws1b, W2, sigma,
-                       order, kept, sel, weight, F);
+                       order, kept, sel, weight, F, nob);
   } else
     hipLaunchKernelGGL((apply_q1_kernel<16, 8>), dim3(kcap, (unsigned)njobs), dim3(256), 0, stream, n, n_pad, kcap, S1,
                        Tws1, W2, sigma, order, kept, sel, weight, F);

@@ -156,6 +156,15 @@ hipError_t run_jacobi(int64_t njobs, int n_pad, double* W, const JacobiWork& wk,
 // scratch; synchronises the stream.
 hipError_t run_rank_rows(int64_t njobs, int n_pad, double tau_null, const double* W, double* nrm, int* last,
                          int* scratch_dev, int* scratch_host, int* rows_max, hipStream_t stream);
+// Per job after the first deflation of the five-QR route: three[j] = 1 when
+// its active rows are at most half of n_pad (it stops after three QRs),
+// nb_first[j] = its active blocks; *n_five = the jobs that take five
+// (synchronises the stream).  launch_keep_three: for those three[j] jobs,
+// Wdst <- Wsrc (their deflated rows of R3) and nb_job <- nb_first.
+hipError_t run_choose_qr_count(int64_t njobs, int n_pad, const int* nb_job, int* three, int* nb_first,
+                               int* scratch_dev, int* scratch_host, int* n_five, hipStream_t stream);
+hipError_t launch_keep_three(int64_t njobs, int n_pad, const int* three, const double* Wsrc, double* Wdst,
+                             const int* nb_first, int* nb_job, hipStream_t stream);
 // Noise-floor deflation: Wout = rows of Win with the active rows (norm >
 // approx_budget(tau_null) / sqrt(n_pad) times the largest, so that the rows
 // left out hold at most approx_budget^2 times the largest squared norm in
@@ -213,37 +222,45 @@ hipError_t run_qr5_precondition(int64_t njobs, int n, int D, int n_pad, const do
 // the rows of R1 in W1.  run_qr23: the second and third QR over the first
 // ncols columns (a multiple of 128, or n_pad; the rows of R1 from ncols on
 // are set to zero first, so that R2 and R3 are zero outside their leading
-// ncols x ncols block): Q2 in W1 / Tws2 (the T of the panels from column
+// ncols x ncols block; rows_job (or NULL): per job the rank rows of
+// run_rank_rows, whose rows from that count rounded up to 128 (the ncols of
+// a batch of that job alone) are set to zero instead - ncols is then their
+// largest): Q2 in W1 / Tws2 (the T of the panels from column
 // ncols on set to zero), the rows of R3 in W3, W2 holding the factored third
 // QR.  run_qr45: the fourth and fifth after it, the rows of R5 in W3, Q4 in
 // S1 / Tws4.
-// stop (or NULL): after every 64 columns of the first QR, if in every job
-// the columns not yet factored hold (summed squares below the factored rows)
-// at most budget^2 times the squared leading diagonal entry of R, the QR
-// stops there; rows = the factored rows (n_pad if it ran to the end);
-// the rows of R1 from there on are written as zero.  dev / host: one int of
-// device and pinned host scratch; each check synchronises the stream.
+// stop (or NULL): after every 64 columns of the first QR, a job whose
+// columns not yet factored hold (summed squares below the factored rows) at
+// most budget^2 times the squared leading diagonal entry of R stops there
+// (rows_job[job]: its later rows of R1 are written as zero and its column
+// order is frozen; the batch goes on factoring, which leaves its earlier
+// rows as they are); the QR ends once every job has stopped, rows = the
+// rows factored by then (n_pad if it ran to the end).  dev / host: one int
+// of device and pinned host scratch; each check synchronises the stream.
 struct QrStop {
   double budget = 0.0;   // approx_budget(tau_null)
   int* dev = nullptr;
   int* host = nullptr;
-  int rows = 0;
+  int* rows_job = nullptr;   // device, one int per job: the row at which that job stopped (n_pad: none)
+  int rows = 0;              // the batch stopped after this many rows (every job stopped at or before)
 };
 hipError_t run_qr1(int64_t njobs, int n, int D, int n_pad, const double* T, const int32_t* src, const int32_t* split,
                    int32_t* perm, int32_t* iperm, double* S1, double* W1, double* Tscr, int32_t* colmap,
                    double* colnorm, hipStream_t stream, QrStop* stop = nullptr);
 hipError_t run_qr23(int64_t njobs, int n_pad, int ncols, double* W1, double* Tws2, double* W2, double* W3,
-                    double* Tscr, hipStream_t stream, KernelTimer* tq = nullptr, double* tq_flops = nullptr);
+                    double* Tscr, hipStream_t stream, KernelTimer* tq = nullptr, double* tq_flops = nullptr,
+                    const int* rows_job = nullptr);
 hipError_t run_qr45(int64_t njobs, int n_pad, int ncols, double* S1, double* W2, double* Tws4, double* W3,
                     double* Tscr, hipStream_t stream, KernelTimer* tq = nullptr, double* tq_flops = nullptr);
 // X[:, a] = w_a Q Qb (W[order[sel[a]]] / s) with Q the orthogonal factor
 // kept in S1 (V, stored columns via colmap, NULL: identity) and Tws1 (panel
 // T), and Qb (optional: S1b / Tws1b, no column map, applied first; n_pad <=
-// 1024) a second factor in the same format
+// 1024) a second factor in the same format; nob (or NULL): per job, nonzero
+// where Qb is not applied (a job whose decomposition stopped after three QRs)
 hipError_t launch_apply_q1(int64_t njobs, int n, int n_pad, int kcap, const double* S1, const int32_t* colmap,
                            const double* Tws1, const double* S1b, const double* Tws1b, const double* W2,
                            const double* sigma, const int32_t* order, const int32_t* kept, const int32_t* sel,
-                           const double* weight, double* F, hipStream_t stream);
+                           const double* weight, double* F, hipStream_t stream, const int* nob = nullptr);
 // G[a][perm[colmap[c]]] = X[c][a] (c < n; colmap NULL: identity), signed
 // with the gauge of the factor kernels; zero rows for a >= kept.
 hipError_t launch_scatter_G(int64_t njobs, int D, int n_pad, int kcap, const double* X, const int32_t* perm,
