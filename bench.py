@@ -190,6 +190,59 @@ def contraction_alone(m, torch, args, dtypes):
                                                       "itself; in the chains of the headline three parts overlap"}
 
 
+# The other configurations of the batched estimator, at reduced sample counts
+# so that each runs in under a minute (throughput per sample-step; the full
+# counts would only repeat the same waves).  (betas, hs) span the groups,
+# ks are assigned round-robin over blocks of 64 samples.
+CONFIGS = {
+    "c1": dict(workload="Ising h=0 at beta_c, k=8, 16x16 lattice (8 steps), FP64", betas=[BETA_C], hs=[0.0],
+               ks=[8], n_steps=8, samples=1000, full_samples=1000, dtype="f64"),
+    "c2": dict(workload="Ising h=0, k=16, 2^20 sites (20 steps), 16 betas in [0.30, 0.60], FP64",
+               betas=[0.30 + 0.02 * i for i in range(16)], hs=[0.0], ks=[16], n_steps=20, samples=16 * 256,
+               full_samples=16 * 10000, dtype="f64"),
+    "c3": dict(workload="batched: k in {16, 24, 32}, 32 betas in [0.35, 0.55] x h in {0, 0.05}, 30 steps, FP32 "
+                        "contraction", betas=[0.35 + 0.2 * i / 31 for i in range(32)], hs=[0.0, 0.05],
+               ks=[16, 24, 32], n_steps=30, samples=1536, full_samples=65536, dtype="f32"),
+    "c4": dict(workload="Ising h=0 at beta_c, k=48, 24 steps, BF16 contraction", betas=[BETA_C], hs=[0.0], ks=[48],
+               n_steps=24, samples=48, full_samples=8192, dtype="bf16"),
+    "c5": dict(workload="Ising beta=0.42, h=0.1, k=64, 20 steps, FP8 e4m3 contraction", betas=[0.42], hs=[0.1],
+               ks=[64], n_steps=20, samples=16, full_samples=256, dtype="fp8"),
+}
+
+
+def run_configs(m, torch, names):
+    """Sample-steps/s of each named configuration through mctrg_run_samples
+    (one call for the whole batch; a short call of the same shapes before it
+    runs the tile autotuner)."""
+    out = {}
+    for name in names:
+        c = CONFIGS[name]
+        betas = [b for b in c["betas"] for _ in c["hs"]]
+        hs = [h for _ in c["betas"] for h in c["hs"]]
+        ts = m.init_tensor("site", betas, hs)
+        ng, n = len(betas), c["samples"]
+        groups = [i % ng for i in range(n)]
+        ks = [c["ks"][(i // 64) % len(c["ks"])] for i in range(n)]
+        kw = dict(n_steps=c["n_steps"], k=max(c["ks"]), dtype=c["dtype"], tau_null=TAU_NULL[c["dtype"]], seed=0)
+        warm = sorted(set(ks))
+        m.run_samples(ts, len(warm), groups=[0] * len(warm), ks=warm, **kw)
+        torch.cuda.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        r = m.run_samples(ts, n, groups=groups, ks=ks, **kw)
+        ev1.record()
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1)
+        est = m.estimate_lnZ(r.sign, r.ln_abs_Z, 2.0 ** c["n_steps"])
+        ts.close()
+        out[name] = {"workload": c["workload"], "value": n * c["n_steps"] / (ms / 1e3), "unit": "sample-steps/s",
+                     "samples": n, "samples_in_config": c["full_samples"], "n_steps": c["n_steps"], "ks": c["ks"],
+                     "groups": ng, "dtype": c["dtype"], "tau_null": TAU_NULL[c["dtype"]], "ms": ms,
+                     "n_failed": est["n_failed"]}
+        print(f"[bench] config {name}: {n} samples x {c['n_steps']} steps in {ms:.1f} ms", flush=True)
+    return out
+
+
 def kernel_records(r, args, dtype, tau):
     """Roofline records of the Jacobi and the 128-column QR update for one
     form (the dominant first)."""
@@ -328,6 +381,9 @@ def main():
                     help="candidate cut of the headline form (default: per contraction dtype, see TAU_NULL)")
     ap.add_argument("--cpu-samples", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--configs", default="",
+                    help="comma-separated names of other configurations to time after the headline (" +
+                         ", ".join(CONFIGS) + "), reported under 'configs'")
     ap.add_argument("--no-gemm-alone", action="store_true",
                     help="skip the GEMM of every contraction dtype timed on its own")
     ap.add_argument("--no-all-steps", action="store_true",
@@ -419,6 +475,8 @@ def main():
             "note": "same samples and draws addressing as the headline; shared chains (one tensor per level)"}
     if not args.no_all_steps:
         out["all_steps"] = run_all_steps(m, torch, args, args.dtype, tau)
+    if args.configs:
+        out["configs"] = run_configs(m, torch, [c for c in args.configs.split(",") if c])
     if not args.no_gemm_alone:
         out["mfma_contraction_alone"] = contraction_alone(m, torch, args, ("f64", "f32", "bf16", "fp8"))
     if not args.no_cpu_baseline:

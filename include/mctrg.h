@@ -209,9 +209,9 @@ int32_t mctrg_capacity_dim(int32_t d0, int32_t k, int32_t n_steps);
  * non-finite normalisation, a zero trace or a decomposition that did not
  * converge); the other samples are valid.  Blocks until the outputs are
  * written.  Errors: EINVAL, ENOMEM, EDEVICE, EUNSUPPORTED.
- * Test hook: when the environment variable MCTRG_TEST_FAIL_SAMPLE holds a
- * global sample id, that sample's normalisation at the last step is made
- * non-finite (the failure path above, without feeding a non-finite value
+ * Test hook (here and in mctrg_chain_create): when the environment variable
+ * MCTRG_TEST_FAIL_SAMPLE holds a global sample id, that sample's
+ * normalisation at the last step is made non-finite (the failure path above, without feeding a non-finite value
  * through the decomposition kernels). */
 int mctrg_run_samples(mctrg_tensor_set* ts, const mctrg_run_config* cfg, int64_t n_samples,
                       const int32_t* group_of_sample, const int32_t* k_of_sample,
@@ -242,7 +242,8 @@ int mctrg_estimate_lnZ(int64_t n_samples, const int8_t* sign, const double* ln_a
  * cfg->n_steps in total); finish traces the current tensor - after s
  * steps this is the sample of Z for the 2^s-site lattice - and writes
  * sign / ln|Z~| / ln c (device arrays, n_samples and n_samples *
- * cfg->n_steps; out_ln_c may be NULL).  Errors as mctrg_run_samples;
+ * cfg->n_steps; out_ln_c may be NULL).  Errors as mctrg_run_samples (finish
+ * returns ENUMERIC when some sample failed, its sign 0 and ln|Z~| NaN);
  * MCTRG_RECORD writes cfg->record_buf as mctrg_run_samples does (sample i
  * of the chain at index i); out_tensor is ignored here. */
 typedef struct mctrg_chain mctrg_chain;

@@ -433,8 +433,9 @@ class Chain:
         sign = torch.empty(self.n_samples, dtype=torch.int8, device=dev)
         ln = torch.empty(self.n_samples, dtype=torch.float64, device=dev)
         lnc = torch.zeros((self.n_samples, self.n_steps), dtype=torch.float64, device=dev) if want_ln_c else None
-        _check(_lib.mctrg_chain_finish(self._h, _ptr(sign), _ptr(ln), _ptr(lnc)), "mctrg_chain_finish")
-        return SampleResult(sign, ln, lnc, OK)
+        st = _lib.mctrg_chain_finish(self._h, _ptr(sign), _ptr(ln), _ptr(lnc))
+        _check(st, "mctrg_chain_finish", allow=(OK, ENUMERIC))   # ENUMERIC: some samples failed (sign 0)
+        return SampleResult(sign, ln, lnc, st)
 
     def profile(self) -> dict:
         p = ChainProfile()

@@ -32,7 +32,10 @@ struct mctrg_tensor_set {
 
 namespace {
 
-constexpr int kMaxSweeps = 60;
+constexpr int kMaxSweeps = 120;
+// Sweeps after which the Jacobi also accepts pairs at the approximation
+// budget's absolute floor (the FP64 forms converge in at most about a dozen)
+constexpr int kAbsFromSweep = 30;
 
 // ---------------------------------------------------------------------------
 // Independent-mode lattice (TRG geometry on a torus).
@@ -478,8 +481,10 @@ hipError_t decompose(int64_t nj, int n, int D, int n_pad, const double* T, const
       nb_max = nb2;
     }
   }
+  // a job still rotating after kAbsFromSweep sweeps (rows stalled at the
+  // rounding of the larger ones) converges at the budget's absolute floor
   HKE(run_jacobi(nj, n_pad, Wj, b.jw, kMaxSweeps, st, ctl.tj, &out.sweeps, b.nb_job, nb_max, ctl.sweep_hist,
-                 out.jcols, ctl.blind));
+                 out.jcols, ctl.blind, approx_budget(ctl.tau) / std::sqrt((double)n_pad), kAbsFromSweep));
   out.Wj = Wj;
   return launch_jacobi_finalize(nj, n, n_pad, Wj, b.sigma, b.order, st, b.dnrm);
 #undef HKE
@@ -1210,6 +1215,8 @@ int mctrg_chain_create(mctrg_tensor_set* ts, const mctrg_run_config* cfg, int64_
     out_index[i] = i;
     sids[i] = cfg->sample_offset + i;
   }
+  int64_t fail_sid = -1;   // test hook (see mctrg.h), as in run_samples
+  if (const char* e = std::getenv("MCTRG_TEST_FAIL_SAMPLE")) fail_sid = std::strtoll(e, nullptr, 10);
   auto configure = [&](Chain& c) {
     c.mode = cfg->mode; c.dtype = cfg->contract_dtype; c.k = cfg->k; c.n_steps = cfg->n_steps;
     c.tau = cfg->tau_null; c.seed = cfg->seed; c.flags = cfg->flags & (MCTRG_PROFILE | MCTRG_RECORD);
@@ -1217,6 +1224,7 @@ int mctrg_chain_create(mctrg_tensor_set* ts, const mctrg_run_config* cfg, int64_
     c.kmax_rec = cfg->k;
     c.n_det = cfg->n_det;
     c.dec = cfg->decomposition;
+    c.fail_sid = fail_sid;
     c.Dsched = probe.Dsched;
     c.levels = probe.levels;
     c.plaqs = probe.plaqs;
@@ -1241,6 +1249,13 @@ int mctrg_chain_finish(mctrg_chain* ch, int8_t* out_sign, double* out_ln_abs_Z, 
   const int rc = parts_finish(ch->cp, out_sign, out_ln_abs_Z, out_ln_c, nullptr);
   if (rc != MCTRG_OK) return rc;
   if (hipStreamSynchronize(ch->cp.caller) != hipSuccess) return MCTRG_EDEVICE;
+  // a failed sample (sign 0) makes the call return ENUMERIC, as run_samples
+  int64_t n = 0;
+  for (const auto& c : ch->cp.parts) n += c->nsamp;
+  std::vector<int8_t> sg((size_t)n);
+  if (n > 0 && hipMemcpy(sg.data(), out_sign, (size_t)n, hipMemcpyDeviceToHost) != hipSuccess) return MCTRG_EDEVICE;
+  for (int8_t v : sg)
+    if (v == 0) return MCTRG_ENUMERIC;
   return MCTRG_OK;
 }
 

@@ -35,7 +35,7 @@ __global__ __launch_bounds__(256) void jacobi_round_kernel(double* __restrict__ 
                                                            const int* __restrict__ nb_job, int round,
                                                            const int* __restrict__ active,
                                                            int* __restrict__ rotated, int* __restrict__ pairs,
-                                                           double tol) {
+                                                           double tol, double tabs) {
   const int job = blockIdx.y;
   if (!active[job]) return;
   // rows beyond the job's active blocks sit below the noise floor and stay
@@ -102,12 +102,12 @@ __global__ __launch_bounds__(256) void jacobi_round_kernel(double* __restrict__ 
   for (int e = tid; e < 1024; e += 256) Q[e >> 5][e & 31] = ((e >> 5) == (e & 31)) ? 1.0 : 0.0;
 
   // ---- convergence test of this pair ------------------------------------
-  double off = 0.0;
+  double off = 0.0;   // (tabs: as in jacobi_round64_kernel)
   for (int e = tid; e < 1024; e += 256) {
     int i = e >> 5, j = e & 31;
     if (i < j) {
-      double d = G[i][i] * G[j][j];
-      if (d > 0.0) off = fmax(off, fabs(G[i][j]) / sqrt(d));
+      const double gi = G[i][i], gj = G[j][j], d = gi * gj, g = fabs(G[i][j]);
+      if (d > 0.0 && g > tabs * fmax(gi, gj)) off = fmax(off, g / sqrt(d));
     }
   }
   for (int o = 32; o > 0; o >>= 1) off = fmax(off, __shfl_xor(off, o));
@@ -293,7 +293,7 @@ __global__ __launch_bounds__(256, 4) void jacobi_round64_kernel(double* __restri
                                                                 const int* __restrict__ active,
                                                                 int* __restrict__ rotated, int* __restrict__ pairs,
                                                                 double tol, int* __restrict__ lastmod,
-                                                                int* __restrict__ lastchk, int stamp) {
+                                                                int* __restrict__ lastchk, int stamp, double tabs) {
   const int job = blockIdx.y;
   if (!active[job]) return;
   const int nb = nb_job ? nb_job[job] : nb_all;   // 32-row blocks
@@ -413,12 +413,18 @@ __global__ __launch_bounds__(256, 4) void jacobi_round64_kernel(double* __restri
   __syncthreads();
 
   // ---- convergence test of this pair ------------------------------------
+  // An entry needs a rotation when its cosine exceeds tol and (tabs > 0, a
+  // job still rotating after many sweeps) the entry itself exceeds tabs
+  // times the larger squared row norm: below that, rounding of the larger
+  // row keeps the smaller one from becoming more orthogonal, and leaving
+  // the entry moves the singular values by less than the approximation
+  // budget's share (see run_jacobi).
   double off = 0.0;
   for (int e = tid; e < 4096; e += 256) {
     const int i = e >> 6, j = e & 63;
     if (i < j) {
-      const double d = dg[0][i] * dg[0][j];
-      if (d > 0.0) off = fmax(off, fabs(U[gpk_index(i, j)]) / sqrt(d));
+      const double gi = dg[0][i], gj = dg[0][j], d = gi * gj, g = fabs(U[gpk_index(i, j)]);
+      if (d > 0.0 && g > tabs * fmax(gi, gj)) off = fmax(off, g / sqrt(d));
     }
   }
   for (int o = 32; o > 0; o >>= 1) off = fmax(off, __shfl_xor(off, o));
@@ -695,7 +701,7 @@ __global__ void zero_ints_kernel(int n, int* p) {
 
 hipError_t run_jacobi(int64_t njobs, int n_pad, double* W, const JacobiWork& wk, int max_sweeps,
                       hipStream_t stream, KernelTimer* timer, int* sweeps_done, const int* nb_job, int nb_max,
-                      int* history, int ncol, int blind) {
+                      int* history, int ncol, int blind, double tabs, int abs_from) {
   if (ncol <= 0 || ncol > n_pad || ncol % 64) ncol = n_pad;
   if (njobs == 0) return hipSuccess;
   const int brows = jacobi_block_rows(n_pad);
@@ -720,16 +726,17 @@ hipError_t run_jacobi(int64_t njobs, int n_pad, double* W, const JacobiWork& wk,
   }
   for (int sweep = 0; sweep < max_sweeps; ++sweep) {
     int* cnt = slots ? wk.counter + 2 * sweep : wk.counter;
+    const double ta = (abs_from > 0 && sweep >= abs_from) ? tabs : 0.0;
     if (!slots) hipLaunchKernelGGL(zero_int_kernel, dim3(1), dim3(2), 0, stream, wk.counter);
     for (int r = 0; r < nb - 1; ++r) {
       if (timer) { hipError_t e = timer->begin(stream); if (e != hipSuccess) return e; }
       if (brows == 32)
         hipLaunchKernelGGL(jacobi_round64_kernel, dim3(nb / 2, (unsigned)njobs), dim3(256), 0, stream, W,
                            n_pad, ncol, nb, nb_job, r, wk.active, wk.rotated, cnt + 1, tol, wk.lastmod, wk.lastchk,
-                           1 + sweep * (nb - 1) + r);
+                           1 + sweep * (nb - 1) + r, ta);
       else
         hipLaunchKernelGGL(jacobi_round_kernel, dim3(nb / 2, (unsigned)njobs), dim3(256), 0, stream, W,
-                           n_pad, nb, nb_job, r, wk.active, wk.rotated, cnt + 1, tol);
+                           n_pad, nb, nb_job, r, wk.active, wk.rotated, cnt + 1, tol, ta);
       if (timer) { hipError_t e = timer->end(stream); if (e != hipSuccess) return e; }
     }
     hipLaunchKernelGGL(jacobi_sweep_end_kernel, dim3(g), dim3(256), 0, stream, njobs, sweep, wk.active,

@@ -144,10 +144,17 @@ inline double approx_budget(double tau_null) { return fmax(0x1.0p-48, 0.1 * tau_
 // (0: n_pad; a multiple of 64 for the 64-row pairs): the rows are zero from
 // column ncol on, so the Gram and the update stop there (rotations keep those
 // columns zero).
+// tabs / abs_from (abs_from 0: off): from sweep abs_from on, an entry g_ij
+// of a pair's Gram no longer counts as unconverged once |g_ij| <= tabs
+// max(g_ii, g_jj).  Rows far below the largest ones can stall above the
+// relative tolerance: the rounding of the larger rows (about eps times
+// their norm) keeps their cosines from falling.  With tabs =
+// approx_budget(tau_null) / sqrt(n_pad) the entries left move every
+// singular value by at most approx_budget(tau_null) s_1 in all.
 hipError_t run_jacobi(int64_t njobs, int n_pad, double* W, const JacobiWork& wk, int max_sweeps,
                       hipStream_t stream, KernelTimer* timer = nullptr, int* sweeps_done = nullptr,
                       const int* nb_job = nullptr, int nb_max = 0, int* history = nullptr, int ncol = 0,
-                      int blind = 0);
+                      int blind = 0, double tabs = 0.0, int abs_from = 0);
 // Rank of the rows of W (n_pad x n_pad per job, row-major): *rows_max = the
 // largest over the jobs of the smallest L such that the rows from L on hold
 // at most approx_budget(tau_null)^2 times the largest squared row norm of

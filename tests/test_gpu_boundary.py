@@ -39,6 +39,18 @@ def test_enumeric_isolates_the_failed_sample(monkeypatch):
     monkeypatch.setenv("MCTRG_TEST_FAIL_SAMPLE", "7")
     r = m.run_samples(ts, 3, n_steps=5, k=6, seed=4, sample_offset=7)
     assert r.status == m.ENUMERIC and r.sign.cpu().numpy()[0] == 0 and np.all(r.sign.cpu().numpy()[1:] != 0)
+    # the stepping interface reports it the same way at its finish
+    ch = m.Chain(ts, 3, n_steps=5, k=6, seed=4, sample_offset=7)
+    ch.step(5)
+    c = ch.finish()
+    ch.close()
+    assert c.status == m.ENUMERIC
+    assert np.array_equal(c.sign.cpu().numpy(), r.sign.cpu().numpy())
+    monkeypatch.delenv("MCTRG_TEST_FAIL_SAMPLE")
+    ch = m.Chain(ts, 3, n_steps=5, k=6, seed=4, sample_offset=7)
+    ch.step(5)
+    assert ch.finish().status == m.OK
+    ch.close()
 
 
 def test_enomem_under_a_workspace_cap_leaves_outputs():
