@@ -413,8 +413,9 @@ hipError_t decompose(int64_t nj, int n, int D, int n_pad, const double* T, const
   const bool qr_basis = qr5 && ctl.dec != MCTRG_DEC_SVD;
   out.qr_basis = qr_basis;
   if (qr5) {
-    // the first QR stops once the columns it has not factored hold at most the
-    // approximation budget in every job (their rows of R1 are then set to zero)
+    // a job's first QR stops once the columns it has not factored hold at most
+    // the approximation budget (its later rows of R1 are set to zero and its
+    // column order is frozen); the batch factors on until every job has stopped
     QrStop stop;
     stop.budget = approx_budget(ctl.tau);
     stop.dev = b.jw.counter;
