@@ -1477,9 +1477,11 @@ int mctrg_contract_batched(int64_t n_jobs, int32_t D, int32_t kk, int32_t dtype,
   if (!GA || !GB || !FA || !FB || !T_out) return MCTRG_EINVAL;
   hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
   const size_t xe = (size_t)n_jobs * kk * kk * D * D, te = (size_t)n_jobs * kk * kk * kk * kk;
+  const size_t fe = (size_t)n_jobs * D * D * kk;   // each F pool, by kept index
   Arena ar;
   ar.take<double>(xe); ar.take<double>(xe); ar.take<float>(xe); ar.take<float>(xe);
   ar.take<double>(2 * n_jobs); ar.take<double>(te); ar.take<int32_t>(4 * n_jobs);
+  ar.take<double>(fe); ar.take<double>(fe);
   char* mem = nullptr;
   if (hipMalloc(&mem, ar.off) != hipSuccess) { (void)hipGetLastError(); return MCTRG_ENOMEM; }
   Arena a2;
@@ -1489,16 +1491,19 @@ int mctrg_contract_batched(int64_t n_jobs, int32_t D, int32_t kk, int32_t dtype,
   ca.scales = a2.take<double>(2 * n_jobs);
   double* C = a2.take<double>(te);
   int32_t* jobs = a2.take<int32_t>(4 * n_jobs);
+  double* FAk = a2.take<double>(fe);
+  double* FBk = a2.take<double>(fe);
   std::vector<int32_t> hj(4 * n_jobs);
   for (int64_t o = 0; o < n_jobs; ++o)
     for (int t = 0; t < 4; ++t) hj[4 * o + t] = (int32_t)o;
   ca.nout = n_jobs; ca.D = D; ca.kk = kk; ca.dtype = dtype;
-  ca.GA = GA; ca.GB = GB; ca.FA = FA; ca.FB = FB;
+  ca.GA = GA; ca.GB = GB; ca.FA = FAk; ca.FB = FBk;
   ca.g_stride = (int64_t)kk * D * D; ca.f_stride = (int64_t)D * D * kk;
   ca.jobs = jobs; ca.Tout = C;
   int rc = MCTRG_OK;
   if (hipMemcpyAsync(jobs, hj.data(), hj.size() * sizeof(int32_t), hipMemcpyHostToDevice, st) != hipSuccess ||
-      launch_contract(ca, st) != hipSuccess ||
+      launch_f_by_kept(n_jobs, D, kk, FA, FAk, st) != hipSuccess ||
+      launch_f_by_kept(n_jobs, D, kk, FB, FBk, st) != hipSuccess || launch_contract(ca, st) != hipSuccess ||
       launch_unscale(n_jobs, (int64_t)kk * kk * kk * kk, dtype != MCTRG_F64, C, ca.scales, T_out, st) != hipSuccess ||
       hipStreamSynchronize(st) != hipSuccess)
     rc = MCTRG_EDEVICE;

@@ -70,15 +70,17 @@ __global__ __launch_bounds__(256) void contract_Y_kernel(int D, int kk, int kcap
   const int DD = D * D, ld = D + 1;
   double* FAc = sh;               // [s][q]
   double* FBe = sh + D * ld;      // [t][s]
-  const double* FA = FApool + (size_t)jobs[4 * o + 2] * f_stride;
+  // F by kept index: u_c of FA and u_ee of FB are D^2 contiguous doubles each
+  const double* FA = FApool + (size_t)jobs[4 * o + 2] * f_stride + (size_t)c * DD;
   const double* FB = FBpool + (size_t)jobs[4 * o + 3] * f_stride;
-  for (int e = threadIdx.x; e < DD; e += 256) FAc[(e / D) * ld + e % D] = FA[(size_t)e * kcap + c];
+  for (int e = threadIdx.x; e < DD; e += 256) FAc[(e / D) * ld + e % D] = FA[e];
   double* Yo = Yt + (size_t)o * kk * kk * DD;
   const bool stage_b = D <= 45;
   for (int ee = 0; ee < kk; ++ee) {
+    const double* FBee = FB + (size_t)ee * DD;
     __syncthreads();
     if (stage_b)
-      for (int e = threadIdx.x; e < DD; e += 256) FBe[(e / D) * ld + e % D] = FB[(size_t)e * kcap + ee];
+      for (int e = threadIdx.x; e < DD; e += 256) FBe[(e / D) * ld + e % D] = FBee[e];
     __syncthreads();
     for (int e = threadIdx.x; e < DD; e += 256) {
       const int t = e / D, q = e % D;
@@ -86,10 +88,39 @@ __global__ __launch_bounds__(256) void contract_Y_kernel(int D, int kk, int kcap
       if (stage_b)
         for (int ss = 0; ss < D; ++ss) s += FBe[t * ld + ss] * FAc[ss * ld + q];
       else
-        for (int ss = 0; ss < D; ++ss) s += FB[((size_t)t * D + ss) * kcap + ee] * FAc[ss * ld + q];
+        for (int ss = 0; ss < D; ++ss) s += FBee[t * D + ss] * FAc[ss * ld + q];
       Yo[((size_t)c * kk + ee) * DD + e] = s;
     }
   }
+  (void)kcap;
+}
+
+// out[j][c][e] = in[j][e][c]: 32 x 32 tiles transposed through LDS.
+__global__ __launch_bounds__(256) void f_by_kept_kernel(int DD, int kk, const double* __restrict__ in,
+                                                        double* __restrict__ out) {
+  __shared__ double tile[32][33];
+  const int64_t j = blockIdx.z;
+  const int e0 = 32 * blockIdx.x, c0 = 32 * blockIdx.y;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  const double* ij = in + (size_t)j * DD * kk;
+  double* oj = out + (size_t)j * DD * kk;
+  for (int yy = ty; yy < 32; yy += 8) {
+    const int e = e0 + yy, c = c0 + tx;
+    tile[yy][tx] = (e < DD && c < kk) ? ij[(size_t)e * kk + c] : 0.0;
+  }
+  __syncthreads();
+  for (int yy = ty; yy < 32; yy += 8) {
+    const int c = c0 + yy, e = e0 + tx;
+    if (c < kk && e < DD) oj[(size_t)c * DD + e] = tile[tx][yy];
+  }
+}
+
+hipError_t launch_f_by_kept(int64_t njobs, int D, int kk, const double* in, double* out, hipStream_t stream) {
+  if (njobs == 0) return hipSuccess;
+  const int DD = D * D;
+  hipLaunchKernelGGL(f_by_kept_kernel, dim3((unsigned)ceil_div(DD, 32), (unsigned)ceil_div(kk, 32), (unsigned)njobs),
+                     dim3(256), 0, stream, DD, kk, in, out);
+  return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------

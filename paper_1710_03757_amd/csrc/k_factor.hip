@@ -11,7 +11,7 @@
 // S^(e)_ii = S_ii / r(S_ii); the reweighted value is split symmetrically):
 //   G[a][:] = w_a v_{i_a}^T,          v = normalised Jacobi row, signed so
 //                                     that sum_j v_j / (1 + i1 + phi i2) > 0
-//   F[:][a] = w_a u_{i_a} = M G[a]^T / s_{i_a}
+//   F[a][:] = w_a u_{i_a}^T = (M G[a]^T)^T / s_{i_a}  (stored by kept index)
 // with w_a = sqrt(s_{i_a} / r_{i_a}); entries a >= kept are zero
 // (capacity padding).
 #include "mctrg_internal.h"
@@ -115,7 +115,7 @@ __global__ void transpose_G_kernel(int D, int kcap, const int32_t* __restrict__ 
   Gt[base + e] = G[base + (size_t)d * D + l];
 }
 
-// F[job][row][a] = (1/s_a) sum_col M[row][col] G[job][a][col].  One
+// F[job][a][row] = (1/s_a) sum_col M[row][col] G[job][a][col].  One
 // workgroup per (64-row tile, job); column chunks of 32 staged in LDS.  For
 // the B split M_B[(u,r)][(d,l)] = T[l][u][r][d], so the columns are taken in
 // T's order (l, d), contiguous per row, with G from its transposed copy Gt.
@@ -183,7 +183,7 @@ __global__ __launch_bounds__(256) void factor_F_kernel(int D, int kcap, const do
       if (aa < kcap) {
         double v = 0.0;
         if (aa < kk) v = acc[q] / sigma[(size_t)job * n + sel[job * kcap + aa]];
-        F[(size_t)job * n * kcap + (size_t)row * kcap + aa] = v;
+        F[(size_t)job * n * kcap + (size_t)aa * n + row] = v;   // by kept index: rows contiguous
       }
     }
   }

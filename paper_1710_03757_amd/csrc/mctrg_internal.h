@@ -312,7 +312,8 @@ size_t noalloc_scratch_doubles();
 hipError_t noalloc_scratch(double** out);
 size_t sample_scratch_doubles(int64_t njobs, int n, int k);
 
-// Factors.  G[j]: kcap x n (row a = w_a v_a), F[j]: n x kcap (col a = w_a u_a).
+// Factors.  G[j]: kcap x n (row a = w_a v_a), F[j]: kcap x n (row a = w_a u_a,
+// stored by kept index so that the contraction reads each u_a contiguously).
 hipError_t launch_factor_G(int64_t njobs, int D, int n_pad, int kcap, const double* W,
                            const double* sigma, const int32_t* order, const int32_t* kept,
                            const int32_t* sel, const double* weight, const int32_t* perm, double* G,
@@ -326,7 +327,7 @@ struct ContractArgs {
   int64_t nout;            // number of output tensors
   int D, kk, dtype;
   const double* GA; const double* GB;   // factor pools indexed by decomposition job
-  const double* FA; const double* FB;
+  const double* FA; const double* FB;   // F by kept index: [a][s D + q] per job
   int64_t g_stride, f_stride;           // doubles per job in the G and F pools
   const int32_t* jobs;     // nout x 4: (job of GA, job of GB, job of FA, job of FB)
   double* X; double* Y;    // workspace: nout * kk^2 * D^2 each
@@ -335,6 +336,9 @@ struct ContractArgs {
   void* Tout;              // nout * kk^4, FP64 (dtype F64) or FP32 (others)
 };
 hipError_t launch_contract(const ContractArgs& a, hipStream_t stream, KernelTimer* gemm_timer = nullptr);
+// out[j][c][e] = in[j][e][c] for e < D^2, c < kk: the F factors of the
+// step-level contraction entry ([s][q][c] per job) into the kept-index order.
+hipError_t launch_f_by_kept(int64_t njobs, int D, int kk, const double* in, double* out, hipStream_t stream);
 // The GEMM tile shape (64 or 128) the autotuner chose for this shape on the
 // current device, 0 if none yet.
 int gemm_tile_chosen(int dt, int M, int N, int K, int64_t nout);
