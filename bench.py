@@ -25,7 +25,10 @@ over their average duration (HIP events around every dispatch on the
 library's own streams).  The kernel's own executed flops are reported
 separately (``implementation_flops_per_launch``).  HBM traffic per dispatch
 comes from the committed rocprofv3 counter summary when that was taken on
-the same kernel source and workload window.  Also reported: the whole-step
+the same kernel source and workload window; with it, the kernel's HBM rate
+over its busy time is set against a device copy timed live on the same GPU
+(``hbm_probe``: the achievable rate for a read + write stream, well below the
+8 TB/s nominal peak).  Also reported: the whole-step
 roofline fraction, the MFMA rate of the coarse-graining GEMM, the same
 window with the cheaper unbiased decomposition (``cheaper_decomposition``:
 a QR-iteration basis instead of the SVD, its speedup and the spread of its
@@ -272,6 +275,8 @@ def kernel_records(r, args, dtype, tau):
         return {"bound": "mfma", "kernel": name, "achieved": ach, "peak": PEAK_TFLOPS["f64"], "unit": "TFLOP/s",
                 "frac": ach / PEAK_TFLOPS["f64"] if ach else None, "traffic": traffic,
                 "traffic_unit": "HBM bytes per dispatch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                "hbm_rate_over_busy_time_TBps": (traffic * x["launches"] / (x["busy"] / 1e3) / 1e12
+                                                 if traffic and x["busy"] > 0 else None),
                 "algorithmic_flops_per_launch": alg,
                 "flop_count": "the decomposition's (14/3) k^6 FP64 flops per sample-step over the window, divided "
                               "by this kernel's dispatches in the window",
@@ -362,6 +367,34 @@ def accuracy(r, ores, n_chain, dtype, tau):
             "note": f"same Philox draws; GPU contraction {dtype} with tau_null {tau:g}; oracle FP64, tau_null 1e-11"}
 
 
+def hbm_probe(torch, mib=2048, reps=5):
+    """Achievable HBM bandwidth on this GPU, measured live: a device-to-device
+    copy (read + write) of ``mib`` MiB, the best of ``reps`` runs timed with
+    events on the current stream."""
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def best(fn):
+        fn()
+        torch.cuda.synchronize()
+        ms = []
+        for _ in range(reps):
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            ms.append(e0.elapsed_time(e1))
+        return min(ms)
+
+    nbytes = n * 4
+    copy_ms = best(lambda: dst.copy_(src))
+    del src, dst
+    return {"bytes": nbytes, "copy_TBps": 2 * nbytes / (copy_ms / 1e3) / 1e12,
+            "note": "bytes read + written by a device-to-device copy over its time"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -388,6 +421,8 @@ def main():
                     help="skip the GEMM of every contraction dtype timed on its own")
     ap.add_argument("--no-all-steps", action="store_true",
                     help="skip the all-steps rate (a fresh chain of the headline form timed over every step)")
+    ap.add_argument("--no-hbm-probe", action="store_true",
+                    help="skip the live copy bandwidth probe that the dominant kernel's HBM rate is set against")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="after the timed region, copy this many MiB device-to-device (a plain copy kernel of known "
                          "size whose counter readings calibrate FETCH_SIZE / WRITE_SIZE)")
@@ -486,6 +521,12 @@ def main():
         if side is not None:
             out["accuracy"][args.side_dtype] = accuracy(side, ores, n_chain, args.side_dtype,
                                                         TAU_NULL[args.side_dtype])
+    if not args.no_hbm_probe:
+        hb = hbm_probe(torch)
+        out["hbm_probe"] = hb
+        for rec in (out["roofline"], out["second_kernel"]):
+            rate = rec.get("hbm_rate_over_busy_time_TBps")
+            rec["hbm_rate_over_copy_rate"] = rate / hb["copy_TBps"] if rate else None
     if args.copy_probe_mb:
         src = torch.ones(args.copy_probe_mb * (1 << 20) // 4, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
