@@ -277,11 +277,12 @@ __device__ __forceinline__ double unit_cosine(double t) {
 // (every round streams each active row through the Gram and update passes).
 //   1. Gram G (64 x 64): the ten distinct 16 x 16 tiles of the four 16-row
 //      sub-blocks, each wave over a quarter of the row length, partial tiles
-//      summed through LDS in a fixed order;
-//   2. one cyclic Jacobi sweep on G (63 rounds of 32 disjoint rotations,
-//      one barrier per round, see below);
-//   3. W_pair <- Q^T W_pair with v_mfma_f64_16x16x4 (Q^T fragments in
-//      registers).
+//      summed into wave 0's registers through LDS in a fixed order;
+//   2. one cyclic Jacobi sweep on G (63 rounds of 32 disjoint rotations, two
+//      barriers per round: after the rotations are formed and after the
+//      rotated entries are stored, see below);
+//   3. W_pair <- Q^T W_pair with v_mfma_f64_16x16x4 (Q^T fragments read
+//      from LDS).
 // One inner sweep is enough: the outer iteration recomputes the Gram from
 // the rows, and a second inner sweep did not reduce the number of outer
 // sweeps on TRG unfoldings.  The 64 rotated rows are written in decreasing

@@ -99,6 +99,27 @@ def test_svd_random(d1, d2, nm, tau):
         log(f"  #{i}: |ds| {verr:.2e}  vectors checked {nchk} max err {vecerr:.2e}  sweeps {sw[i]}")
 
 
+def test_svd_largest_size():
+    """The largest decomposition the library takes, 64 x 64 = 4096 (the k =
+    64 unfoldings): three QRs with 8-column panels, then 127 rounds per
+    sweep; a graded spectrum down to 1e-12, across the candidate cut."""
+    torch, m = need_gpu()
+    d1 = d2 = 64
+    tau = 1e-11
+    log(f"svd_largest d1={d1} d2={d2} tau={tau}")
+    rng = np.random.default_rng(6464)
+    n = d1 * d2
+    U, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    V, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    Ms = (U * np.logspace(0, -12, n)) @ V.T
+    Ms = Ms[None]
+    sig, V, sw = m.svd_batched(torch.tensor(Ms, device="cuda"), d1, d2, tau_null=tau)
+    sig, V, sw = sig.cpu().numpy(), V.cpu().numpy(), sw.cpu().numpy()
+    for i in range(1):
+        verr, vecerr, nchk = check_svd(Ms[i], (d1, d2), sig[i], V[i], int(sw[i]), tau, f"{d1}x{d2}#{i}")
+        log(f"  #{i}: |ds| {verr:.2e}  vectors checked {nchk} max err {vecerr:.2e}  sweeps {sw[i]}")
+
+
 @pytest.mark.parametrize("tau", [0.0, 1e-11])
 def test_svd_ising_unfoldings(tau):
     """The unfoldings of the shared chain's tensors at k = 8 (critical Ising,
