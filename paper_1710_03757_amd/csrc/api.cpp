@@ -8,8 +8,6 @@
 // In independent mode the batch is (sample x lattice position) and the
 // contraction gathers its four halves from the plaquette's four positions.
 #include <algorithm>
-#include <atomic>
-#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -200,7 +198,6 @@ struct Chain {
   double jacobi_flops = 0.0;              // their Gram + update flops at the row length used
   int step_sweeps[64] = {};               // Jacobi sweeps of every step
   int64_t fail_sid = -1;                  // test hook: global sample id whose last ln c is made non-finite
-  std::atomic<int>* jacobi_entered = nullptr;   // set when a step's Jacobi is about to be launched (parts_step)
 
   ~Chain() {
     if (mem) (void)hipFree(mem);
@@ -376,7 +373,6 @@ struct DecompCtl {
   double* tq_flops = nullptr;
   KernelTimer* tj = nullptr;
   int* sweep_hist = nullptr;   // host, 2 kMaxSweeps ints, or NULL
-  std::atomic<int>* entered = nullptr;   // if set, 1 is stored when the Jacobi is about to be launched
 };
 
 // Where the result is: the rows Wj whose norms are the singular values
@@ -486,7 +482,6 @@ hipError_t decompose(int64_t nj, int n, int D, int n_pad, const double* T, const
       nb_max = nb2;
     }
   }
-  if (ctl.entered) ctl.entered->store(1, std::memory_order_release);
   // a job still rotating after kAbsFromSweep sweeps (rows stalled at the
   // rounding of the larger ones) converges at the budget's absolute floor
   HKE(run_jacobi(nj, n_pad, Wj, b.jw, kMaxSweeps, st, ctl.tj, &out.sweeps, b.nb_job, nb_max, ctl.sweep_hist,
@@ -611,7 +606,6 @@ int chain_step(Chain& c) {
     }
     if (c.tj.enabled) ctl.tj = &c.tj;
     ctl.sweep_hist = c.sweep_hist;
-    ctl.entered = c.jacobi_entered;
     CKH(decompose(nj, sh.n, sh.D, sh.n_pad, c.Ta, c.src, c.split, decomp_bufs(c), ctl, dout, c.st));
     c.last_sweeps = dout.sweeps;
   }
@@ -797,40 +791,19 @@ int parts_join(ChainParts& cp) {
 
 // n TRG steps on every part, part 0 on the calling thread and the others on
 // threads of their own (one after the other if a thread cannot be started).
-//
-// The parts are equal in size, so started together they would run the same
-// phase at the same time: the QR steps of all parts (partly latency-bound,
-// HBM far from busy) and then the Jacobi rounds of all parts (HBM-bound).
-// For several steps in one call, part p > 0 on a thread of its own starts
-// when part p - 1 is about to launch its first Jacobi, so that one part's QR
-// steps run beside the other parts' rounds; the offset then holds for the
-// rest of the call.  Each part's results do not depend on when it runs.
 int parts_step(ChainParts& cp, int n) {
   const int P = (int)cp.parts.size();
   std::vector<int> rcs(P, MCTRG_OK);
-  std::unique_ptr<std::atomic<int>[]> entered(new (std::nothrow) std::atomic<int>[P > 0 ? P : 1]);
-  const bool stagger = entered && P > 1 && n > 1 && cp.parts[0]->dec == MCTRG_DEC_SVD;
-  for (int p = 0; p < P; ++p) {
-    if (entered) entered[p].store(0);
-    cp.parts[p]->jacobi_entered = stagger ? &entered[p] : nullptr;
-  }
-  auto run = [&](int p, bool wait) {   // no exception leaves a part's thread
+  auto run = [&](int p) {   // no exception leaves a part's thread
     try {
       if (p > 0 && hipSetDevice(cp.device) != hipSuccess) {
         rcs[p] = MCTRG_EDEVICE;
-      } else {
-        if (stagger && wait)   // part p - 1 stores 1 at its first Jacobi, after any step and when it stops
-          while (entered[p - 1].load(std::memory_order_acquire) == 0)
-            std::this_thread::sleep_for(std::chrono::microseconds(20));
-        for (int i = 0; i < n && rcs[p] == MCTRG_OK; ++i) {
-          rcs[p] = chain_step(*cp.parts[p]);
-          if (stagger) entered[p].store(1, std::memory_order_release);
-        }
+        return;
       }
+      for (int i = 0; i < n && rcs[p] == MCTRG_OK; ++i) rcs[p] = chain_step(*cp.parts[p]);
     } catch (...) {
       rcs[p] = MCTRG_ENOMEM;
     }
-    if (stagger) entered[p].store(1, std::memory_order_release);
   };
   std::vector<std::thread> th;
   try {
@@ -839,14 +812,13 @@ int parts_step(ChainParts& cp, int n) {
   }
   for (int p = 1; p < P; ++p) {
     try {
-      th.emplace_back(run, p, true);
-    } catch (...) {   // no thread: step this part here, without waiting for part p - 1
-      run(p, false);
+      th.emplace_back(run, p);
+    } catch (...) {   // no thread: step this part here
+      run(p);
     }
   }
-  run(0, false);
+  run(0);
   for (auto& t : th) t.join();
-  for (int p = 0; p < P; ++p) cp.parts[p]->jacobi_entered = nullptr;
   for (int p = 0; p < P; ++p)
     if (rcs[p] != MCTRG_OK) return rcs[p];
   return parts_join(cp);
