@@ -52,6 +52,7 @@ from workloads import BETA_C  # noqa: E402
 METRIC = "TRG sample-steps/s at χ=32 + MFMA util; |Δ ln Z|/site vs FP64 oracle"
 PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0, "fp8": 5000.0}
 PEAK_HBM_TBS = 8.0
+GEMM_ELT_BYTES = {"f64": 8, "f32": 4, "bf16": 2, "fp8": 1}
 JACOBI_KERNEL = "jacobi_round64_kernel"
 QR128_KERNEL = "qr_trailing128_kernel"
 KERNEL_SRC = {JACOBI_KERNEL: os.path.join(ROOT, "paper_1710_03757_amd", "csrc", "k_jacobi.hip"),
@@ -184,13 +185,23 @@ def contraction_alone(m, torch, args, dtypes):
         n = p1["gemm_launches"] - p0["gemm_launches"]
         ms = (p1["gemm_ms"] - p0["gemm_ms"]) / max(n, 1)
         ach = gemm_flops(k) * B / (ms / 1e3) / 1e12 if ms > 0 else None
+        # operands k^2 x k^2 each in the dtype, output k^2 x k^2 in the accumulator type
+        nbytes = B * k ** 4 * (2 * GEMM_ELT_BYTES[dt] + (8 if dt == "f64" else 4))
+        t_mfma = gemm_flops(k) * B / (PEAK_TFLOPS[dt] * 1e12) * 1e3
+        t_hbm = nbytes / (PEAK_HBM_TBS * 1e12) * 1e3
         out[dt] = {"kernel": f"gemm_tn_kernel<{dt}>", "achieved": ach, "peak": PEAK_TFLOPS[dt], "unit": "TFLOP/s",
-                   "frac": ach / PEAK_TFLOPS[dt] if ach else None, "avg_launch_ms": ms, "launches": n}
+                   "frac": ach / PEAK_TFLOPS[dt] if ach else None, "avg_launch_ms": ms, "launches": n,
+                   "hbm_bytes_per_launch": nbytes, "bound": "mfma" if t_mfma >= t_hbm else "hbm",
+                   "floor_ms": max(t_mfma, t_hbm), "frac_of_floor": max(t_mfma, t_hbm) / ms if ms > 0 else None}
         print(f"[bench] {dt}: GEMM alone {ms:.3f} ms ({ach:.1f} TF/s)", flush=True)
     return {"per_dtype": out, "batch": B, "shape": f"{k * k} x {k * k} x {k * k} per sample (k^2 x k^2 output, "
                                                   "inner dimension D^2 = k^2)",
-            "flop_count": "2 k^6 per sample", "note": "one part (one stream): the GEMM dispatch has the GPU to "
-                                                      "itself; in the chains of the headline three parts overlap"}
+            "flop_count": "2 k^6 per sample",
+            "floor": "the larger of the flops at the dtype's MFMA peak and the operand and output bytes at 8 TB/s "
+                     "(the narrow dtypes write a 4-byte accumulator per output element, so at this shape their "
+                     "GEMM is bound by HBM)",
+            "note": "one part (one stream): the GEMM dispatch has the GPU to itself; in the chains of the headline "
+                    "three parts overlap"}
 
 
 # The other configurations of the batched estimator, at reduced sample counts
