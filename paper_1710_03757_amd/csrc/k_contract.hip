@@ -190,8 +190,9 @@ __global__ void cast_kernel(int64_t per, const double* __restrict__ A, const dou
 // ---------------------------------------------------------------------------
 template <int DT> struct Mma;
 // KSTEP: K per MFMA; BK: K per LDS tile (one barrier pair per tile), 32 for
-// the four-element MFMAs and 256 bytes of K per row for the narrow types, so
-// that a wave issues 4 x 4 x 8 (BF16: 4 x 4 x 4) MFMAs between barriers.
+// the four-element MFMAs and 128 for the narrow types (BF16: 256 bytes of K
+// per row; FP8: 128 bytes, which keeps its 128-tile variant within two waves
+// per SIMD), so that a wave issues 4 x 4 x 4 MFMAs between barriers.
 template <> struct Mma<MCTRG_F64> {
   typedef double elt; typedef double acc_t; typedef f64x4 frag_c;
   static constexpr int KSTEP = 4, PAD = 1, BK = 32;
@@ -206,7 +207,7 @@ template <> struct Mma<MCTRG_BF16> {
 };
 template <> struct Mma<MCTRG_FP8_E4M3> {
   typedef unsigned char elt; typedef float acc_t; typedef f32x4 frag_c;
-  static constexpr int KSTEP = 32, PAD = 16, BK = 256;
+  static constexpr int KSTEP = 32, PAD = 16, BK = 128;
 };
 
 template <int DT>
@@ -235,8 +236,11 @@ __device__ __forceinline__ typename Mma<DT>::frag_c mma_step(const typename Mma<
 // accumulator registers (FP64: 128 VGPRs) and twice the LDS (FP64: 67 KB,
 // two workgroups per CU).
 
+// The 128-tile variants of the narrow types are held to two workgroups per
+// CU (256 registers per lane): left to itself the compiler preloads enough
+// LDS operands to drop them to one wave per SIMD.
 template <int DT, int BM>
-__global__ __launch_bounds__(256) void gemm_tn_kernel(int M, int N, int K, const void* __restrict__ Av,
+__global__ __launch_bounds__(256, (BM == 128 && (DT == MCTRG_BF16 || DT == MCTRG_FP8_E4M3)) ? 2 : 1) void gemm_tn_kernel(int M, int N, int K, const void* __restrict__ Av,
                                                       const void* __restrict__ Bv, void* __restrict__ Cv) {
   typedef typename Mma<DT>::elt elt;
   typedef typename Mma<DT>::acc_t acc_t;
