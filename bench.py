@@ -157,6 +157,17 @@ def run_all_steps(m, torch, args, dtype, tau):
                     "steps included); setup and tile autotuning outside the timed region"}
 
 
+def gemm_floor(dt, k, batch):
+    """(HBM bytes, MFMA ms, HBM ms) of one batched coarse-graining GEMM: the
+    two k^2 x k^2 operands in the dtype, the k^2 x k^2 output in its
+    accumulator type (8 bytes for FP64, else 4), the flops at the dtype's
+    dense MFMA peak and the bytes at the nominal HBM peak."""
+    nbytes = batch * k ** 4 * (2 * GEMM_ELT_BYTES[dt] + (8 if dt == "f64" else 4))
+    t_mfma = gemm_flops(k) * batch / (PEAK_TFLOPS[dt] * 1e12) * 1e3
+    t_hbm = nbytes / (PEAK_HBM_TBS * 1e12) * 1e3
+    return nbytes, t_mfma, t_hbm
+
+
 def contraction_alone(m, torch, args, dtypes):
     """The coarse-graining GEMM of each contraction dtype with nothing beside
     it: a one-part chain of the batch (one stream, so no other kernel runs
@@ -185,10 +196,7 @@ def contraction_alone(m, torch, args, dtypes):
         n = p1["gemm_launches"] - p0["gemm_launches"]
         ms = (p1["gemm_ms"] - p0["gemm_ms"]) / max(n, 1)
         ach = gemm_flops(k) * B / (ms / 1e3) / 1e12 if ms > 0 else None
-        # operands k^2 x k^2 each in the dtype, output k^2 x k^2 in the accumulator type
-        nbytes = B * k ** 4 * (2 * GEMM_ELT_BYTES[dt] + (8 if dt == "f64" else 4))
-        t_mfma = gemm_flops(k) * B / (PEAK_TFLOPS[dt] * 1e12) * 1e3
-        t_hbm = nbytes / (PEAK_HBM_TBS * 1e12) * 1e3
+        nbytes, t_mfma, t_hbm = gemm_floor(dt, k, B)
         out[dt] = {"kernel": f"gemm_tn_kernel<{dt}>", "achieved": ach, "peak": PEAK_TFLOPS[dt], "unit": "TFLOP/s",
                    "frac": ach / PEAK_TFLOPS[dt] if ach else None, "avg_launch_ms": ms, "launches": n,
                    "hbm_bytes_per_launch": nbytes, "bound": "mfma" if t_mfma >= t_hbm else "hbm",

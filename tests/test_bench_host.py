@@ -23,6 +23,18 @@ def test_algorithmic_counts():
     assert bench.gemm_flops(32) == 2 * 1024 ** 3
 
 
+def test_gemm_floor():
+    # k = 32, 256 products of 1024^3: FP64 bound by the MFMA pipe (7.0 ms
+    # against 0.8 ms of bytes), BF16 and FP8 by their bytes (8 and 6 MiB per
+    # product: 0.27 and 0.20 ms against 0.22 and 0.11 ms of flops)
+    nb, tm, th = bench.gemm_floor("f64", 32, 256)
+    assert nb == 256 * 1024 ** 2 * (2 * 8 + 8) and tm > th and abs(tm - 6.994) < 0.01
+    nb, tm, th = bench.gemm_floor("bf16", 32, 256)
+    assert nb == 256 * 8 * 2 ** 20 and th > tm and abs(th - 0.2684) < 1e-3
+    nb, tm, th = bench.gemm_floor("fp8", 32, 256)
+    assert nb == 256 * 6 * 2 ** 20 and th > tm and abs(tm - 0.1099) < 1e-3
+
+
 def test_traffic_record_key():
     try:
         rec = json.load(open(bench.TRAFFIC_FILE))
