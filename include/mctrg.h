@@ -296,7 +296,9 @@ void mctrg_chain_destroy(mctrg_chain* ch);
 void mctrg_destroy(mctrg_tensor_set* ts);
 const char* mctrg_status_string(int status);
 
-/* ---- Step-level entry points (the individual steps of one TRG step) ---- */
+/* ---- Step-level entry points (the individual steps of one TRG step) ----
+ * An empty batch (n_mats or n_jobs = 0) with otherwise valid sizes returns
+ * MCTRG_OK without reading or writing anything (its pointers may be NULL). */
 
 /* Decomposition step (Section II, Eq. exactSVD): FP64 SVD of n_mats square
  * n x n matrices (device, row-major, n_mats * n * n), n = d1 * d2 <= 4096 with

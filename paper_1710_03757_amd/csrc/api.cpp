@@ -1338,9 +1338,10 @@ int mctrg_estimate_lnZ(int64_t n_samples, const int8_t* sign, const double* ln_a
 
 int mctrg_svd_batched(int64_t n_mats, int32_t d1, int32_t d2, const double* M, double tau_null, double* sigma_out,
                       double* V_out, int32_t* sweeps_out, void* hip_stream) {
-  if (n_mats < 0 || d1 < 1 || d2 < 1 || (int64_t)d1 * d2 > 4096 || !M || !sigma_out) return MCTRG_EINVAL;
+  if (n_mats < 0 || d1 < 1 || d2 < 1 || (int64_t)d1 * d2 > 4096) return MCTRG_EINVAL;
   if (!(tau_null >= 0.0 && tau_null < 1.0)) return MCTRG_EINVAL;
   if (n_mats == 0) return MCTRG_OK;
+  if (!M || !sigma_out) return MCTRG_EINVAL;
   hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
   const int n = d1 * d2, n_pad = std::max(32, round_up32(n));
   const size_t per = (size_t)n_pad * n_pad;

@@ -141,6 +141,35 @@ def test_svd_rejects_bad_arguments():
         m.svd_batched(torch.zeros((1, 4225, 4225), dtype=torch.float64, device="cuda"), 65, 65)
 
 
+def test_step_entries_empty_batches_and_zero_matrix():
+    """Empty batches return at once through every step entry point (NULL
+    pointers allowed); an all-zero matrix and a rank-one matrix decompose to
+    their exact spectra (zero values with zero vector rows)."""
+    import ctypes
+    torch, m = need_gpu()
+    lib = m._lib
+    assert lib.mctrg_svd_batched(0, 4, 4, None, 1e-11, None, None, None, None) == 0
+    assert lib.mctrg_sample_batched(0, 16, 4, 0, 0, 1e-11, None, None, None, None, None, None, None, None,
+                                    None) == 0
+    assert lib.mctrg_sample_batched_noalloc(0, 16, 4, 0, 0, 1e-11, None, None, None, None, None, None, None,
+                                            None, None) == 0
+    assert lib.mctrg_contract_batched(0, 4, 4, 0, None, None, None, None, None, None) == 0
+    # sizes are still checked on an empty batch
+    assert lib.mctrg_svd_batched(0, 65, 65, None, 1e-11, None, None, None, None) != 0
+    sig, V, sw = m.svd_batched(torch.zeros((0, 16, 16), dtype=torch.float64, device="cuda"), 4, 4)
+    assert sig.shape == (0, 16) and V.shape == (0, 16, 16) and sw.shape == (0,)
+    rng = np.random.default_rng(11)
+    u, v = rng.standard_normal(36), rng.standard_normal(36)
+    Ms = np.stack([np.zeros((36, 36)), 3.0 * np.outer(u, v)])
+    sig, V, sw = m.svd_batched(torch.tensor(Ms, device="cuda"), 6, 6, tau_null=1e-11)
+    sig, V = sig.cpu().numpy(), V.cpu().numpy()
+    assert np.all(sig[0] == 0.0) and np.all(V[0] == 0.0)
+    s1 = 3.0 * np.linalg.norm(u) * np.linalg.norm(v)
+    assert abs(sig[1, 0] - s1) <= 1e-13 * s1 and np.all(np.abs(sig[1, 1:]) <= 1e-13 * s1)
+    vh = v / np.linalg.norm(v)
+    assert abs(abs(V[1, 0] @ vh) - 1.0) <= 1e-12
+
+
 @pytest.mark.parametrize("k,mode", [(4, "shared"), (8, "shared"), (16, "shared"), (8, "topk"), (32, "shared")])
 def test_sampler_matches_oracle(k, mode):
     torch, m = need_gpu()
